@@ -1,0 +1,202 @@
+/*
+ * smg.h -- C ABI of the MI355X spectral-multigrid Poisson solver.
+ *
+ * Solves the finite-volume Poisson equation  lap Phi = 4 pi G rho  on a
+ * spherical (r, theta, phi) or cylindrical (R, phi, z) grid with uniform or
+ * logarithmic radial spacing and vacuum (isolated) boundaries, following
+ * Mandal, Gressel, Ziegler & Mignone, "A fast spectral-multigrid Poisson
+ * solver in non-Cartesian geometries": an azimuthal real FFT (Sec. 2.2)
+ * splits the problem into one 2D Helmholtz problem per Fourier mode
+ * m = 0..n_phi/2 (Eqs. helmholz_sph / helmholz_cyl), each solved by
+ * geometric multigrid (Sec. 3) with the James screening-mass boundary
+ * (Sec. 4), then the inverse FFT returns the potential (Sec. 5.1).
+ *
+ * Conventions shared by every entry point
+ *  - All pointers named *_dev are device (HIP) pointers owned by the caller;
+ *    *_host pointers are host memory owned by the caller.  The library owns
+ *    only the opaque host-side plan object.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *    device work of a call is enqueued on it.  Calls that return host data
+ *    (info structs, *_host outputs) synchronise the stream before returning.
+ *  - Real-space arrays (density, potential) are FP64, interior cells only,
+ *    C order [n_a][n_b][n_phi] with phi fastest.  a = r (spherical) or R
+ *    (cylindrical); b = theta (spherical) or z (cylindrical).  A cylindrical
+ *    caller permutes (R, phi, z) to (R, z, phi).
+ *  - Mode arrays are interleaved complex FP64 (re, im), C order
+ *    [n_phi/2 + 1][n_a][n_b] with b fastest.
+ *  - Every function returns an smg_status; on failure smg_last_error()
+ *    returns a thread-local message.  No exception or abort crosses the ABI.
+ *  - A plan and its workspace may be used by one stream at a time; calls
+ *    that overlap on one plan race.
+ */
+#ifndef SMG_H
+#define SMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SMG_OK = 0,
+  SMG_EINVAL = -1,      /* invalid argument or unsupported grid            */
+  SMG_ENOCONV = -2,     /* a mode missed the tolerance within max_cycles;
+                           outputs hold the last iterate, info says which  */
+  SMG_EHIP = -3,        /* a HIP runtime call failed                       */
+  SMG_EWORKSPACE = -4,  /* workspace missing, too small or misaligned      */
+  SMG_ESTATE = -5       /* call out of order (e.g. solve before setup)     */
+} smg_status;
+
+enum { SMG_SPHERICAL = 0, SMG_CYLINDRICAL = 1 };
+enum { SMG_RADIAL_UNIFORM = 0, SMG_RADIAL_LOG = 1 };
+enum { SMG_FP64 = 0, SMG_MIXED = 1 };
+enum { SMG_DGF_AUTO = 0, SMG_DGF_AUX = 1, SMG_DGF_EXTENDED = 2 };
+enum { SMG_LINE_SOR = 0, SMG_LINE_EXACT = 1 };
+
+/* Grid of Sec. 2.1.  Radial faces: uniform, or geometric
+ * a_min * (a_max/a_min)^(f/n_a) for SMG_RADIAL_LOG.  b faces are uniform;
+ * b_min = 0 (and b_max = pi) are poles for spherical grids.
+ * Constraints (SMG_EINVAL otherwise): n_a, n_b >= 4 and even; n_phi even,
+ * >= 4, of the form 2^p 3^q with n_phi/2 <= 1024; 0 < a_min < a_max;
+ * spherical b range within [0, pi]; the inner radial ghost face
+ * a_min - (a_max - a_min)/n_a > 0 for uniform grids; G > 0. */
+typedef struct {
+  int geometry;          /* SMG_SPHERICAL | SMG_CYLINDRICAL */
+  int radial;            /* SMG_RADIAL_UNIFORM | SMG_RADIAL_LOG */
+  int n_a, n_b, n_phi;
+  double a_min, a_max;
+  double b_min, b_max;
+  double G;
+} smg_grid;
+
+/* Solver options.  Zero-initialised fields take the defaults in brackets. */
+typedef struct {
+  int precision;         /* SMG_FP64 [default] | SMG_MIXED (FP32 smoothing
+                            and transfers, FP64 residual, coarsest solve and
+                            correction accumulation: iterative refinement) */
+  int nu_pre;            /* pre-smoothing steps per level [2] */
+  int nu_post;           /* post-smoothing steps per level [2] */
+  int n_sor;             /* SOR passes per line relaxation [2] (Sec. 3.2) */
+  int max_cycles;        /* V-cycles per mode and solve [60] */
+  int dgf_method;        /* SMG_DGF_AUTO [log radial -> extended domain,
+                            uniform -> auxiliary grid] | _AUX | _EXTENDED */
+  int n_pad;             /* DGF padding cells [16] (Sec. 4.2) */
+  double dgf_tol;        /* relative residual of the DGF solves [1e-13] */
+  int line_solver;       /* SMG_LINE_SOR [default]: each line relaxed by
+                            n_sor even-odd SOR passes with the WKB omega
+                            (Sec. 3.2); SMG_LINE_EXACT: each line solved
+                            exactly (Thomas), the ideal Sec. 3.2 names.  The
+                            DGF extended-domain solves always use exact
+                            lines (their radial cells reach aspect ratios
+                            of 1e3 and more). */
+} smg_opts;
+
+/* Per-solve report.  Arrays are caller-owned host buffers of length
+ * n_modes = n_phi/2 + 1 (any may be NULL). */
+typedef struct {
+  int n_modes;
+  int *cycles1, *cycles2;        /* V-cycles of solve 1 (Psi) and 2 (Phi)   */
+  double *resid1, *resid2;       /* final ||D^m||_V / max(||D^m_0||, floor) */
+  int total_cycles;              /* sum over modes and both solves          */
+  int converged;                 /* 1 if every mode met the tolerance       */
+  double ms_fft, ms_mg1, ms_james, ms_mg2, ms_ifft;  /* component times (ms),
+                                    measured with HIP events on the stream  */
+} smg_info;
+
+/* Flags of smg_solve. */
+#define SMG_WARM_PREV   1u  /* start both solves from the previous call's
+                               Psi^m / Phi^m (Sec. 5.1, last paragraph);
+                               otherwise from zero                         */
+#define SMG_TIMINGS     2u  /* fill the component times of smg_info        */
+
+typedef struct smg_plan smg_plan;
+
+/* Validate the grid and options and build the host tables (geometry,
+ * per-level stencil factors, WKB omegas of Appendix A, transfer weights).
+ * *out receives a new plan on success.  No device work. */
+smg_status smg_plan_create(const smg_grid *grid, const smg_opts *opts, smg_plan **out);
+
+/* Bytes of device workspace the plan needs (DGF tables, mode planes of every
+ * multigrid level, previous-step solutions, tables).  0 on a NULL plan. */
+size_t smg_workspace_bytes(const smg_plan *plan);
+
+/* Bind the caller's workspace (>= smg_workspace_bytes, 256-byte aligned),
+ * upload the tables and compute the discrete Green's function tables of
+ * Sec. 4.2 on the device (one-time, not part of a solve).  Temporary device
+ * memory of the DGF computation is allocated and freed inside this call. */
+smg_status smg_plan_setup(smg_plan *plan, void *workspace_dev, size_t workspace_bytes, void *stream);
+
+/* The seven-step workflow of Sec. 5.1: rho_dev -> phi_dev, both
+ * [n_a][n_b][n_phi] FP64 device arrays (may not alias).  Each mode iterates
+ * until ||D^m||_V <= rel_tol * max(||D^m_0||_V, 1e-6 max_m ||D^m_0||_V)
+ * (D_0: defect of the zero guess with the solve's boundary data).
+ * info_host may be NULL.  Returns SMG_ENOCONV if a mode hits max_cycles. */
+smg_status smg_solve(smg_plan *plan, const double *rho_dev, double *phi_dev, double rel_tol,
+                     unsigned flags, void *stream, smg_info *info_host);
+
+/* Destroy a plan (the workspace stays the caller's).  NULL is a no-op. */
+smg_status smg_plan_destroy(smg_plan *plan);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *smg_last_error(void);
+
+/* ---- geometry query (host, no device work) ------------------------------ */
+/* Cell-centre coordinates: a_host[n_a], b_host[n_b], phi_host[n_phi]
+ * (volume-weighted centroids of Eq. cell_centers_sph and Sec. 2.1.2), and
+ * the cell volumes dv_host[n_a*n_b] (per azimuthal cell, Eqs. vol_sph /
+ * vol_cyl).  Any pointer may be NULL. */
+smg_status smg_plan_geometry(const smg_plan *plan, double *a_host, double *b_host, double *phi_host,
+                             double *dv_host);
+
+/* Number of multigrid levels, number of boundary ghost cells n_g of the
+ * James boundary, and the level sizes (n_a, n_b per level; arrays of 16). */
+smg_status smg_plan_shape(const smg_plan *plan, int *n_levels, int *n_ghost, int *level_na, int *level_nb);
+
+/* ---- the steps of the path, for step-level checks ------------------------
+ * Each runs one step of smg_solve on caller buffers; all arrays are device
+ * arrays in the layouts above.  The plan must be set up. */
+
+/* Step 2 (Sec. 2.2): modes_dev[m] = 4 pi G / n_phi * sum_k rho_k e^{-2 pi i m k/n_phi}. */
+smg_status smg_fft_forward(smg_plan *plan, const double *rho_dev, double *modes_dev, void *stream);
+
+/* Step 7: phi_k = sum_{m=0}^{n_phi-1} X_m e^{+2 pi i m k/n_phi} with the upper
+ * half completed by Hermitian symmetry (imaginary parts of m = 0 and
+ * m = n_phi/2 ignored). */
+smg_status smg_fft_inverse(smg_plan *plan, const double *modes_dev, double *phi_dev, void *stream);
+
+/* Steps 3/6 for given right-hand sides: solve L_m u^m = f^m for every mode
+ * with homogeneous boundary conditions (the boundary data of solve 2 are
+ * already folded into f).  u_dev holds the initial guess on entry and the
+ * solution on exit.  cycles_host / resid_host (length n_modes) may be NULL. */
+smg_status smg_mg_solve(smg_plan *plan, const double *f_dev, double *u_dev, double rel_tol,
+                        void *stream, int *cycles_host, double *resid_host);
+
+/* One V-cycle on every mode (no convergence test). */
+smg_status smg_mg_vcycle(smg_plan *plan, const double *f_dev, double *u_dev, void *stream);
+
+/* One smoothing step (radial-line phase then polar-line phase, Algorithm 1)
+ * on the finest level for every mode. */
+smg_status smg_mg_smooth(smg_plan *plan, const double *f_dev, double *u_dev, void *stream);
+
+/* Residual f - L_m u (finest level, every mode) into r_dev. */
+smg_status smg_mg_residual(smg_plan *plan, const double *f_dev, const double *u_dev, double *r_dev,
+                           void *stream);
+
+/* Steps 4-5 (Eqs. charge_sph / charge_cyl and theta_left..theta_top):
+ * sigma_dev[m][g] = screening masses from psi_dev; theta_dev[m][g] =
+ * sum_s Gt^m(g <- s) sigma^m_s; f2_dev = f_dev with the ghost potential
+ * -Theta folded into the boundary cells.  sigma/theta are complex
+ * [n_modes][n_g]. */
+smg_status smg_james(smg_plan *plan, const double *psi_dev, const double *f_dev, double *sigma_dev,
+                     double *theta_dev, double *f2_dev, void *stream);
+
+/* Copy the DGF table Gt^m(t <- s) of mode m to dgf_host[n_g][n_g] (FP64,
+ * row = field ghost t, column = source ghost s). */
+smg_status smg_dgf_table(smg_plan *plan, int m, double *dgf_host, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMG_H */

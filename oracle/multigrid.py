@@ -113,6 +113,27 @@ class MGLevel:
         tmp = (f[i0::2, j0::2] - nbsum) / c
         U[ii, jj] = (1.0 - w) * U[ii, jj] + w * tmp
 
+    def smooth_exact(self, u, f, m):
+        """One alternating step with exact line relaxation (the tridiagonal
+        solve the paper names as the ideal, Sec. 3.2): zebra radial lines,
+        then zebra polar lines, each line solved by the Thomas algorithm."""
+        c = self.diag(m)
+        U = np.zeros((self.n_a + 2, self.n_b + 2), dtype=np.complex128)
+        U[1:-1, 1:-1] = u
+        R = self.R
+        for lc in (0, 1):                       # radial lines j
+            js = np.arange(lc, self.n_b, 2)
+            rhs = f[:, js] - R[:, None] * (self.ub[None, js] * U[1:-1, js + 2] + self.db[None, js] * U[1:-1, js])
+            U[1:-1, js + 1] = thomas(self.da[:, None] * np.ones((1, len(js))), c[:, js],
+                                     self.ua[:, None] * np.ones((1, len(js))), rhs)
+        for lc in (0, 1):                       # polar lines i
+            is_ = np.arange(lc, self.n_a, 2)
+            rhs = f[is_, :] - (self.ua[is_, None] * U[is_ + 2, 1:-1] + self.da[is_, None] * U[is_, 1:-1])
+            lo = (R[is_, None] * self.db[None, :]).T
+            up = (R[is_, None] * self.ub[None, :]).T
+            U[is_ + 1, 1:-1] = thomas(lo, c[is_, :].T, up, rhs.T).T
+        u[...] = U[1:-1, 1:-1]
+
     def smooth(self, u, f, m, n_sor):
         """One alternating step: radial lines, then polar lines."""
         wr, wb = self.omega_lines(m)
@@ -148,6 +169,25 @@ class MGLevel:
             if np.linalg.norm(f - self.apply(U[1:-1, 1:-1], m)) <= rtol * r0:
                 break
         return U[1:-1, 1:-1].copy(), sweeps
+
+
+def thomas(lower, diag, upper, rhs):
+    """Solve tridiagonal systems along axis 0 (columns are independent
+    systems): lower[k] x[k-1] + diag[k] x[k] + upper[k] x[k+1] = rhs[k]."""
+    n = diag.shape[0]
+    cp = np.zeros(diag.shape)
+    dp = np.zeros(rhs.shape, dtype=np.result_type(rhs, np.float64))
+    cp[0] = upper[0] / diag[0]
+    dp[0] = rhs[0] / diag[0]
+    for k in range(1, n):
+        den = diag[k] - lower[k] * cp[k - 1]
+        cp[k] = upper[k] / den
+        dp[k] = (rhs[k] - lower[k] * dp[k - 1]) / den
+    x = np.zeros_like(dp)
+    x[-1] = dp[-1]
+    for k in range(n - 2, -1, -1):
+        x[k] = dp[k] - cp[k] * x[k + 1]
+    return x
 
 
 def _transfer_coord(geometry, which, x):
@@ -202,9 +242,10 @@ def prolongation_matrix_1d(fine: Axis1D, coarse: Axis1D, geometry, which, k_lo, 
 class Hierarchy:
     """The multigrid hierarchy of the problem grid and its V-cycle."""
 
-    def __init__(self, spec, nu_pre=2, nu_post=2, n_sor=2, restriction="bilinear"):
+    def __init__(self, spec, nu_pre=2, nu_post=2, n_sor=2, restriction="bilinear", line_solver="sor"):
         self.spec = spec
         self.nu_pre, self.nu_post, self.n_sor = nu_pre, nu_post, n_sor
+        self.line_solver = line_solver
         self.sizes = level_sizes(spec)
         self.levels = [MGLevel(spec, l) for l in range(len(self.sizes))]
         lit = restriction == "literal"
@@ -234,20 +275,26 @@ class Hierarchy:
         Pa, Pb = self._pcache[key]
         return Pa @ e @ Pb.T
 
+    def _smooth(self, lev, u, f, m):
+        if self.line_solver == "exact":
+            lev.smooth_exact(u, f, m)
+        else:
+            lev.smooth(u, f, m, self.n_sor)
+
     def vcycle(self, u, f, m, l=0):
         lev = self.levels[l]
         if l == len(self.levels) - 1:
             u[...], _ = lev.coarse_solve(f, m)
             return
         for _ in range(self.nu_pre):
-            lev.smooth(u, f, m, self.n_sor)
+            self._smooth(lev, u, f, m)
         r = f - lev.apply(u, m)
         fc = self.restrict(l, r)
         ec = np.zeros_like(fc)
         self.vcycle(ec, fc, m, l + 1)
         u += self.prolong(l, ec, m)
         for _ in range(self.nu_post):
-            lev.smooth(u, f, m, self.n_sor)
+            self._smooth(lev, u, f, m)
 
     def defect_norm(self, u, f, m):
         lev = self.levels[0]

@@ -1,0 +1,186 @@
+// Azimuthal real FFT (Sec. 2.2 and step 2 / step 7 of Sec. 5.1).
+//
+// Forward: modes[m][line] = scale * sum_k rho[line][k] e^{-2 pi i m k / N},
+// m = 0..N/2, line = i*n_b + j (so mode m's output is the contiguous plane
+// [n_a][n_b]).  Inverse: out[line][k] = sum_{m=0}^{N-1} X_m e^{+2 pi i m k/N}
+// with Hermitian completion.
+//
+// A real line of length N is packed as n = N/2 complex values
+// z_k = x_{2k} + i x_{2k+1}; an n-point complex Stockham FFT (radices 4, 2,
+// 3) runs in LDS, and the two interleaved half-length spectra are separated
+// with the post-twiddles e^{-2 pi i m / N}.  A block handles LPB consecutive
+// lines, which are contiguous in the input and give contiguous segments of
+// every output plane.  Twiddles come from a table built on the host in FP64.
+#include "smg_internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPoints = 2048;  // complex points staged per block (ping-pong)
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+// multiply by -i
+__device__ __forceinline__ double2 cmi(double2 a) { return make_double2(a.y, -a.x); }
+
+// One Stockham pass of radix R over LPB lines of n points: src -> dst.
+template <int R>
+__device__ void stockham_pass(const double2* __restrict__ src, double2* __restrict__ dst, int n, int lines,
+                              int Ns, const double2* __restrict__ tw) {
+  const int nb = n / R;
+  const int total = lines * nb;
+  for (int b = threadIdx.x; b < total; b += blockDim.x) {
+    const int line = b / nb, j = b - line * nb;
+    const double2* s = src + line * n;
+    double2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = s[j + r * nb];
+    const int k = j % Ns;
+    if (Ns > 1) {
+      const int step = n / (Ns * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[(r * k * step) % n]);
+    }
+    if (R == 2) {
+      double2 a = v[0], c = v[1];
+      v[0] = cadd(a, c);
+      v[1] = csub(a, c);
+    } else if (R == 4) {
+      double2 a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+      double2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
+      double2 s13 = cadd(a1, a3), d13 = cmi(csub(a1, a3));
+      v[0] = cadd(s02, s13);
+      v[2] = csub(s02, s13);
+      v[1] = cadd(d02, d13);
+      v[3] = csub(d02, d13);
+    } else {  // R == 3
+      const double h = 0.86602540378443864676372317075294;  // sqrt(3)/2
+      double2 a0 = v[0], a1 = v[1], a2 = v[2];
+      double2 t1 = cadd(a1, a2);
+      double2 t2 = make_double2(a0.x - 0.5 * t1.x, a0.y - 0.5 * t1.y);
+      double2 d = csub(a1, a2);
+      double2 t3 = make_double2(h * d.y, -h * d.x);  // -i sqrt(3)/2 (a1 - a2)
+      v[0] = cadd(a0, t1);
+      v[1] = cadd(t2, t3);
+      v[2] = csub(t2, t3);
+    }
+    double2* d = dst + line * n;
+    const int idxD = (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) d[idxD + r * Ns] = v[r];
+  }
+}
+
+// Full n-point forward complex FFT of `lines` lines in LDS; returns the
+// buffer holding the result.
+__device__ double2* fft_lds(double2* a, double2* b, int n, int lines, const double2* tw) {
+  int Ns = 1;
+  int rem = n;
+  while (rem > 1) {
+    if (rem % 4 == 0) {
+      stockham_pass<4>(a, b, n, lines, Ns, tw);
+      Ns *= 4; rem /= 4;
+    } else if (rem % 2 == 0) {
+      stockham_pass<2>(a, b, n, lines, Ns, tw);
+      Ns *= 2; rem /= 2;
+    } else {
+      stockham_pass<3>(a, b, n, lines, Ns, tw);
+      Ns *= 3; rem /= 3;
+    }
+    __syncthreads();
+    double2* t = a; a = b; b = t;
+  }
+  return a;
+}
+
+__global__ void __launch_bounds__(kThreads) k_fft_r2c(const double* __restrict__ rho, double2* __restrict__ modes,
+                                                     int n_lines, int N, double scale,
+                                                     const double2* __restrict__ tw) {
+  extern __shared__ double2 sh[];
+  const int n = N / 2;
+  const int lpb = kPoints / n;
+  double2* a = sh;
+  double2* b = sh + lpb * n;
+  const int line0 = blockIdx.x * lpb;
+  const int lines = min(lpb, n_lines - line0);
+  const double2* src = reinterpret_cast<const double2*>(rho + (size_t)line0 * N);
+  for (int t = threadIdx.x; t < lines * n; t += blockDim.x) a[t] = src[t];
+  __syncthreads();
+  double2* z = fft_lds(a, b, n, lines, tw);
+  // separate the even/odd half spectra: X_m = E_m + e^{-2 pi i m/N} O_m
+  const double2* post = tw + n;
+  const int total = lines * (n + 1);
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int m = t / lines, line = t - m * lines;
+    const double2* Z = z + line * n;
+    double2 zm = Z[m % n];
+    double2 zc = cconj(Z[(n - m) % n]);
+    double2 E = make_double2(0.5 * (zm.x + zc.x), 0.5 * (zm.y + zc.y));
+    double2 dd = csub(zm, zc);
+    double2 O = make_double2(0.5 * dd.y, -0.5 * dd.x);  // -i/2 (Z_m - conj Z_{n-m})
+    double2 X = cadd(E, cmul(post[m], O));
+    modes[(size_t)m * n_lines + line0 + line] = make_double2(scale * X.x, scale * X.y);
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_fft_c2r(const double2* __restrict__ modes, double* __restrict__ out,
+                                                     int n_lines, int N, const double2* __restrict__ tw) {
+  extern __shared__ double2 sh[];
+  const int n = N / 2;
+  const int lpb = kPoints / n;
+  double2* a = sh;
+  double2* b = sh + lpb * n;
+  const int line0 = blockIdx.x * lpb;
+  const int lines = min(lpb, n_lines - line0);
+  const double2* post = tw + n;
+  // Z_m = (X_m + conj X_{n-m}) + i w^m (X_m - conj X_{n-m}), w = e^{+2 pi i/N};
+  // stored conjugated so that a forward FFT gives conj of the inverse sum.
+  const int total = lines * n;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int m = t / lines, line = t - m * lines;
+    double2 xm = modes[(size_t)m * n_lines + line0 + line];
+    double2 xr = modes[(size_t)(n - m) * n_lines + line0 + line];
+    if (m == 0) { xm.y = 0.0; xr.y = 0.0; }  // m = 0 and m = N/2 are real
+    double2 xc = cconj(xr);
+    double2 S = cadd(xm, xc);
+    double2 D = csub(xm, xc);
+    double2 wm = cconj(post[m]);               // e^{+2 pi i m/N}
+    double2 iwD = cmul(make_double2(-wm.y, wm.x), D);  // i w^m D
+    double2 Z = cadd(S, iwD);
+    a[line * n + m] = cconj(Z);
+  }
+  __syncthreads();
+  double2* z = fft_lds(a, b, n, lines, tw);
+  double2* dst = reinterpret_cast<double2*>(out + (size_t)line0 * N);
+  for (int t = threadIdx.x; t < lines * n; t += blockDim.x) dst[t] = cconj(z[t]);
+}
+
+}  // namespace
+
+namespace smgk {
+
+static size_t fft_lds_bytes() { return 2 * kPoints * sizeof(double2); }
+
+hipError_t fft_r2c(const double* rho, double2* modes, int n_lines, int n_phi, double scale,
+                   const double2* tw, hipStream_t st) {
+  const int lpb = kPoints / (n_phi / 2);
+  const int blocks = (n_lines + lpb - 1) / lpb;
+  hipLaunchKernelGGL(k_fft_r2c, dim3(blocks), dim3(kThreads), fft_lds_bytes(), st, rho, modes, n_lines,
+                     n_phi, scale, tw);
+  return hipGetLastError();
+}
+
+hipError_t fft_c2r(const double2* modes, double* out, int n_lines, int n_phi, const double2* tw,
+                   hipStream_t st) {
+  const int lpb = kPoints / (n_phi / 2);
+  const int blocks = (n_lines + lpb - 1) / lpb;
+  hipLaunchKernelGGL(k_fft_c2r, dim3(blocks), dim3(kThreads), fft_lds_bytes(), st, modes, out, n_lines,
+                     n_phi, tw);
+  return hipGetLastError();
+}
+
+}  // namespace smgk

@@ -1,0 +1,357 @@
+// Host-side plan tables: finite-volume geometry (Sec. 2.1.1, Sec. 2.1.2),
+// per-mode Helmholtz stencil factors (Sec. 2.2), WKB over-relaxation
+// parameters (Appendix A), grid-transfer weights (Sec. 3.1) and the James
+// ghost-cell set (Sec. 4.1).  Everything here is one-time FP64 setup.
+//
+// Conventions (see smg_internal.h): an axis has interior cells 1..n and one
+// ghost cell each side; ghosts continue the face law of their level, a ghost
+// across a pole is the mirror cell, faces on a pole have zero sine.  The
+// operator diagonal is split as c_ij = Ca[m][i] + Rr[i] * Cb[m][j]; ghost
+// couplings are removed from the off-diagonals and ghosts that are a fixed
+// multiple kappa of the adjacent cell (pole parity (-1)^m, Neumann +1) are
+// folded into the diagonal.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+
+#include "smg_internal.h"
+
+namespace smg {
+
+static const double kPi = 3.141592653589793238462643383279502884;
+
+std::string strprintf(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  return std::string(buf);
+}
+
+bool Spec::pole_lo() const { return sph() && b_min == 0.0; }
+bool Spec::pole_hi() const { return sph() && std::fabs(b_max - kPi) < 1e-12; }
+double Spec::dphi() const { return 2.0 * kPi / n_phi; }
+
+double Spec::radial_face(double f) const {
+  if (radial == SMG_RADIAL_UNIFORM) return a_min + f * ((a_max - a_min) / n_a);
+  return a_min * std::pow(a_max / a_min, f / n_a);
+}
+
+bool Spec::b_face_is_pole(long f) const {
+  return (pole_lo() && f == 0) || (pole_hi() && f == n_b);
+}
+
+double Spec::b_face(long f) const {
+  if (pole_lo() && f == 0) return 0.0;
+  if (pole_hi() && f == n_b) return kPi;
+  return b_min + (double)f * ((b_max - b_min) / n_b);
+}
+
+double mode_s2(int n_phi, int m) {
+  double s = std::sin(m * kPi / n_phi) / (kPi / n_phi);
+  return s * s;
+}
+
+double kappa(int kind, int m) {
+  if (kind == EDGE_DIRICHLET) return 0.0;
+  if (kind == EDGE_POLE) return (m % 2) ? -1.0 : 1.0;
+  return 1.0;  // Neumann
+}
+
+Axis make_axis(const Spec& s, char which, long off, long stride, int n) {
+  Axis ax;
+  ax.which = which;
+  ax.n = n;
+  ax.off = off;
+  ax.stride = stride;
+  ax.face.resize(n + 3);
+  ax.sinf.assign(n + 3, 0.0);
+  std::vector<bool> pole(n + 3, false);
+  for (int q = 0; q < n + 3; ++q) {
+    long f = off + (long)(q - 1) * stride;
+    if (which == 'a') {
+      ax.face[q] = s.radial_face((double)f);
+    } else {
+      ax.face[q] = s.b_face(f);
+      pole[q] = s.b_face_is_pole(f);
+      if (s.sph()) ax.sinf[q] = pole[q] ? 0.0 : std::sin(ax.face[q]);
+    }
+  }
+  ax.pole_lo = which == 'b' && pole[1];
+  ax.pole_hi = which == 'b' && pole[n + 1];
+  ax.cent.resize(n + 2);
+  ax.vol.resize(n + 2);
+  for (int k = 0; k < n + 2; ++k) {
+    double lo = ax.face[k], hi = ax.face[k + 1];
+    if (which == 'a') {
+      if (s.sph()) {
+        ax.cent[k] = 0.75 * (hi * hi * hi * hi - lo * lo * lo * lo) / (hi * hi * hi - lo * lo * lo);
+        ax.vol[k] = (hi * hi * hi - lo * lo * lo) / 3.0;
+      } else {
+        ax.cent[k] = (2.0 / 3.0) * (hi * hi * hi - lo * lo * lo) / (hi * hi - lo * lo);
+        ax.vol[k] = 0.5 * (hi * hi - lo * lo);
+      }
+    } else {
+      if (s.sph()) {
+        ax.cent[k] = (std::sin(hi) - std::sin(lo) + lo * std::cos(lo) - hi * std::cos(hi)) /
+                     (std::cos(lo) - std::cos(hi));
+        ax.vol[k] = std::cos(lo) - std::cos(hi);
+      } else {
+        ax.cent[k] = 0.5 * (lo + hi);
+        ax.vol[k] = hi - lo;
+      }
+    }
+  }
+  if (ax.pole_lo) ax.cent[0] = -ax.cent[1];
+  if (ax.pole_hi) ax.cent[n + 1] = 2.0 * kPi - ax.cent[n];
+  ax.up.assign(n + 2, 0.0);
+  ax.dn.assign(n + 2, 0.0);
+  ax.R.assign(n + 2, 1.0);
+  ax.P.assign(n + 2, 1.0);
+  for (int k = 0; k < n + 2; ++k) {
+    double lo = ax.face[k], hi = ax.face[k + 1], x = ax.cent[k];
+    double xp = ax.cent[k + 1 < n + 2 ? k + 1 : k], xm = ax.cent[k > 0 ? k - 1 : k];
+    if (which == 'a') {
+      if (s.sph()) {
+        double den = hi * hi * hi - lo * lo * lo;
+        if (k < n + 1) ax.up[k] = 3.0 * hi * hi / (den * (xp - x));
+        if (k > 0) ax.dn[k] = 3.0 * lo * lo / (den * (x - xm));
+        ax.R[k] = 1.5 / x * (hi * hi - lo * lo) / den;
+        ax.P[k] = ax.R[k];
+      } else {
+        double den = hi * hi - lo * lo;
+        if (k < n + 1) ax.up[k] = 2.0 * hi / (den * (xp - x));
+        if (k > 0) ax.dn[k] = 2.0 * lo / (den * (x - xm));
+        ax.P[k] = 2.0 / (x * (hi + lo));
+      }
+    } else {
+      if (s.sph()) {
+        double den = std::cos(lo) - std::cos(hi);
+        if (k < n + 1) ax.up[k] = ax.sinf[k + 1] / (den * (xp - x));
+        if (k > 0) ax.dn[k] = ax.sinf[k] / (den * (x - xm));
+        ax.P[k] = (hi - lo) / (std::sin(x) * den);
+      } else {
+        double den = hi - lo;
+        if (k < n + 1) ax.up[k] = 1.0 / (den * (xp - x));
+        if (k > 0) ax.dn[k] = 1.0 / (den * (x - xm));
+      }
+    }
+  }
+  return ax;
+}
+
+// WKB Jacobi radius of a tridiagonal line (Appendix A): positions x[0..n+1]
+// (including the two end positions), couplings and diagonal of points 1..n.
+static double wkb_radius(const double* x, int n, const double* lower, const double* upper,
+                         const double* diag, int dstride) {
+  double L = x[n + 1] - x[0];
+  double num = 0.0, den = 0.0;
+  for (int k = 1; k <= n; ++k) {
+    double w = std::sin(kPi * (x[k] - x[0]) / L);
+    w *= w;
+    num += (lower[k - 1] + upper[k - 1]) * std::cos(kPi * (x[k] - x[k - 1]) / L) * w;
+    den += diag[(k - 1) * dstride] * w;
+  }
+  return std::fabs(num / den);
+}
+
+static double omega_of(double rho) {
+  if (rho > 1.0) rho = 1.0;
+  double t = 1.0 - rho * rho;
+  if (t < 0.0) t = 0.0;
+  return 2.0 / (1.0 + std::sqrt(t));
+}
+
+static double transfer_coord(const Spec& s, char which, double x) {
+  return (which == 'a' && s.sph()) ? x * x : x;
+}
+
+Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, const int edge[4],
+                          const std::vector<int>& modes, bool main_grid) {
+  Hierarchy h;
+  h.spec = s;
+  h.M = (int)modes.size();
+  // level sizes: halve while both sides are even, the smaller coarse side
+  // stays >= 2 and (for the problem grid) the coarse inner radial ghost face
+  // stays at r > 0.
+  std::vector<std::pair<int, int>> sizes{{na, nb}};
+  long stride = 1;
+  while (true) {
+    int ca = sizes.back().first, cb = sizes.back().second;
+    if ((ca % 2) || (cb % 2) || std::min(ca, cb) / 2 < 2) break;
+    if (s.radial_face((double)((a_lo - 1) - 2 * stride)) <= 0.0) break;
+    sizes.push_back({ca / 2, cb / 2});
+    stride *= 2;
+  }
+  (void)main_grid;
+  int L = (int)sizes.size();
+  h.lv.resize(L);
+  for (int l = 0; l < L; ++l) {
+    LevelTables& T = h.lv[l];
+    long st = 1L << l;
+    T.na = sizes[l].first;
+    T.nb = sizes[l].second;
+    for (int e = 0; e < 4; ++e) T.edge[e] = edge[e];
+    T.A = make_axis(s, 'a', a_lo - 1, st, T.na);
+    T.B = make_axis(s, 'b', b_lo - 1, st, T.nb);
+    const Axis &A = T.A, &B = T.B;
+    int n1 = T.na, n2 = T.nb;
+    T.ua.resize(n1); T.da.resize(n1); T.Rr.resize(n1);
+    T.ub.resize(n2); T.db.resize(n2);
+    for (int i = 0; i < n1; ++i) {
+      T.ua[i] = (i == n1 - 1) ? 0.0 : A.up[i + 1];
+      T.da[i] = (i == 0) ? 0.0 : A.dn[i + 1];
+      T.Rr[i] = s.sph() ? A.R[i + 1] : 1.0;
+    }
+    for (int j = 0; j < n2; ++j) {
+      T.ub[j] = (j == n2 - 1) ? 0.0 : B.up[j + 1];
+      T.db[j] = (j == 0) ? 0.0 : B.dn[j + 1];
+    }
+    int M = h.M;
+    T.Ca.assign((size_t)M * n1, 0.0);
+    T.Cb.assign((size_t)M * n2, 0.0);
+    T.wr.assign((size_t)M * n2, 1.0);
+    T.wb.assign((size_t)M * n1, 1.0);
+    T.wc.assign(M, 1.0);
+    for (int p = 0; p < M; ++p) {
+      int m = modes[p];
+      double s2 = mode_s2(s.n_phi, m);
+      double* Ca = &T.Ca[(size_t)p * n1];
+      double* Cb = &T.Cb[(size_t)p * n2];
+      for (int i = 0; i < n1; ++i) {
+        double dn = A.dn[i + 1];
+        if (i == 0) dn = (edge[0] == EDGE_NEUMANN) ? 0.0 : dn * (1.0 - kappa(edge[0], m));
+        Ca[i] = -(A.up[i + 1] + dn);
+        if (i == n1 - 1) Ca[i] += kappa(edge[1], m) * A.up[i + 1];
+        if (!s.sph()) Ca[i] -= s2 * A.P[i + 1];
+      }
+      for (int j = 0; j < n2; ++j) {
+        Cb[j] = -(B.up[j + 1] + B.dn[j + 1]);
+        if (j == 0) Cb[j] += kappa(edge[2], m) * B.dn[1];
+        if (j == n2 - 1) Cb[j] += kappa(edge[3], m) * B.up[n2];
+        if (s.sph()) Cb[j] -= s2 * B.P[j + 1];
+      }
+      // WKB omegas: radial line j (points i), polar line i (points j)
+      std::vector<double> diag(n1), lo(n2), hi(n2), dg(n2);
+      for (int j = 0; j < n2; ++j) {
+        for (int i = 0; i < n1; ++i) diag[i] = Ca[i] + T.Rr[i] * Cb[j];
+        T.wr[(size_t)p * n2 + j] = omega_of(wkb_radius(A.cent.data(), n1, T.da.data(), T.ua.data(), diag.data(), 1));
+      }
+      for (int i = 0; i < n1; ++i) {
+        for (int j = 0; j < n2; ++j) {
+          lo[j] = T.Rr[i] * T.db[j];
+          hi[j] = T.Rr[i] * T.ub[j];
+          dg[j] = Ca[i] + T.Rr[i] * Cb[j];
+        }
+        T.wb[(size_t)p * n1 + i] = omega_of(wkb_radius(B.cent.data(), n2, lo.data(), hi.data(), dg.data(), 1));
+      }
+      // 2D estimate (p = q = 1 term of Appendix A's 2D formula)
+      double La = A.cent[n1 + 1] - A.cent[0], Lb = B.cent[n2 + 1] - B.cent[0];
+      double num = 0.0, den = 0.0;
+      for (int i = 0; i < n1; ++i) {
+        double wa = std::sin(kPi * (A.cent[i + 1] - A.cent[0]) / La);
+        wa *= wa;
+        double ca = std::cos(kPi * (A.cent[i + 1] - A.cent[i]) / La);
+        for (int j = 0; j < n2; ++j) {
+          double wbv = std::sin(kPi * (B.cent[j + 1] - B.cent[0]) / Lb);
+          wbv *= wbv;
+          double cbv = std::cos(kPi * (B.cent[j + 1] - B.cent[j]) / Lb);
+          double w = wa * wbv;
+          num += ((T.ua[i] + T.da[i]) * ca + T.Rr[i] * (T.ub[j] + T.db[j]) * cbv) * w;
+          den += (Ca[i] + T.Rr[i] * Cb[j]) * w;
+        }
+      }
+      T.wc[p] = omega_of(std::fabs(num / den));
+    }
+    // normalised volume weights
+    double sa = 0.0, sb = 0.0;
+    T.va.resize(n1);
+    T.vb.resize(n2);
+    for (int i = 0; i < n1; ++i) sa += A.vol[i + 1];
+    for (int j = 0; j < n2; ++j) sb += B.vol[j + 1];
+    for (int i = 0; i < n1; ++i) T.va[i] = A.vol[i + 1] / sa;
+    for (int j = 0; j < n2; ++j) T.vb[j] = B.vol[j + 1] / sb;
+  }
+  // transfers between consecutive levels (bilinear in (r^2, theta) or (R, z);
+  // restriction: the printed area weights read as opposite-corner weights)
+  for (int l = 0; l + 1 < L; ++l) {
+    LevelTables &F = h.lv[l], &C = h.lv[l + 1];
+    for (int ax = 0; ax < 2; ++ax) {
+      const Axis& fa = ax ? F.B : F.A;
+      const Axis& caa = ax ? C.B : C.A;
+      char which = ax ? 'b' : 'a';
+      int nc = caa.n, nf = fa.n;
+      std::vector<double>& rw = ax ? F.rwb : F.rwa;
+      rw.resize(2 * nc);
+      for (int I = 1; I <= nc; ++I) {
+        double xl = transfer_coord(s, which, fa.cent[2 * I - 1]);
+        double xh = transfer_coord(s, which, fa.cent[2 * I]);
+        double X = transfer_coord(s, which, caa.cent[I]);
+        rw[2 * (I - 1) + 0] = std::fabs(xh - X) / std::fabs(xh - xl);
+        rw[2 * (I - 1) + 1] = std::fabs(X - xl) / std::fabs(xh - xl);
+      }
+      for (int par = 0; par < (ax ? 2 : 1); ++par) {
+        double k_lo = kappa(edge[ax ? 2 : 0], par);
+        double k_hi = kappa(edge[ax ? 3 : 1], par);
+        std::vector<int> i0(nf), i1(nf);
+        std::vector<double> w0(nf), w1(nf);
+        for (int k = 1; k <= nf; ++k) {
+          int I = (k + 1) / 2;
+          int c0 = (k % 2) ? I - 1 : I;
+          int c1 = c0 + 1;
+          double x0 = transfer_coord(s, which, caa.cent[c0]);
+          double x1 = transfer_coord(s, which, caa.cent[c1]);
+          double x = transfer_coord(s, which, fa.cent[k]);
+          double a0 = std::fabs(x1 - x) / std::fabs(x1 - x0);
+          double a1 = std::fabs(x - x0) / std::fabs(x1 - x0);
+          int j0 = c0 - 1, j1 = c1 - 1;
+          if (c0 == 0) { j0 = 0; a0 *= k_lo; }
+          if (c1 == nc + 1) { j1 = nc - 1; a1 *= k_hi; }
+          i0[k - 1] = j0; i1[k - 1] = j1; w0[k - 1] = a0; w1[k - 1] = a1;
+        }
+        if (ax == 0) {
+          F.pa_i0 = i0; F.pa_i1 = i1; F.pa_w0 = w0; F.pa_w1 = w1;
+        } else {
+          F.pb_i0[par] = i0; F.pb_i1[par] = i1; F.pb_w0[par] = w0; F.pb_w1[par] = w1;
+        }
+      }
+    }
+  }
+  return h;
+}
+
+GhostSet make_ghosts(const Spec& s) {
+  GhostSet g;
+  Axis A = make_axis(s, 'a', 0, 1, s.n_a);
+  Axis B = make_axis(s, 'b', 0, 1, s.n_b);
+  auto add = [&](int i, int j, int e, double cout, double cin) {
+    g.gi.push_back(i);
+    g.gj.push_back(j);
+    g.edge.push_back(e);
+    g.a.push_back(A.cent[i]);
+    g.b.push_back(B.cent[j]);
+    g.dv3.push_back(A.vol[i] * B.vol[j] * s.dphi());
+    g.coup_out.push_back(cout);
+    g.coup_in.push_back(cin);
+    int ia = std::min(std::max(i, 1), s.n_a) - 1;
+    int jb = std::min(std::max(j, 1), s.n_b) - 1;
+    g.adj.push_back(ia * s.n_b + jb);
+  };
+  for (int j = 1; j <= s.n_b; ++j) add(0, j, 0, A.up[0], A.dn[1]);
+  for (int j = 1; j <= s.n_b; ++j) add(s.n_a + 1, j, 1, A.dn[s.n_a + 1], A.up[s.n_a]);
+  if (!s.pole_lo())
+    for (int i = 1; i <= s.n_a; ++i) {
+      double R = s.sph() ? A.R[i] : 1.0;
+      add(i, 0, 2, R * B.up[0], R * B.dn[1]);
+    }
+  if (!s.pole_hi())
+    for (int i = 1; i <= s.n_a; ++i) {
+      double R = s.sph() ? A.R[i] : 1.0;
+      add(i, s.n_b + 1, 3, R * B.dn[s.n_b + 1], R * B.up[s.n_b]);
+    }
+  g.n = (int)g.gi.size();
+  return g;
+}
+
+}  // namespace smg

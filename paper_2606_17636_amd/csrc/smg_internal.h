@@ -1,0 +1,157 @@
+// Internal declarations of the smg library: host plan tables and the device
+// launchers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/smg.h"
+
+namespace smg {
+
+enum EdgeKind { EDGE_DIRICHLET = 0, EDGE_POLE = 1, EDGE_NEUMANN = 2 };
+
+// Grid description in host form.
+struct Spec {
+  int geometry, radial, n_a, n_b, n_phi;
+  double a_min, a_max, b_min, b_max, G;
+  bool sph() const { return geometry == SMG_SPHERICAL; }
+  bool pole_lo() const;
+  bool pole_hi() const;
+  int n_modes() const { return n_phi / 2 + 1; }
+  double dphi() const;
+  double radial_face(double f) const;  // fine face index -> coordinate
+  double b_face(long f) const;         // fine face index -> coordinate (pole exact)
+  bool b_face_is_pole(long f) const;
+};
+
+// One axis of one level: interior cells 1..n; faces at law(off + (q-1)*stride)
+// for q = 0..n+2 (q = 0 and n+2 are the ghost faces).
+struct Axis {
+  char which;  // 'a' radial, 'b' theta / z
+  int n;
+  long off, stride;
+  bool pole_lo = false, pole_hi = false;
+  std::vector<double> face;  // n+3
+  std::vector<double> sinf;  // n+3, spherical theta only (0 at poles)
+  std::vector<double> cent;  // n+2 (0 and n+1 are ghosts)
+  std::vector<double> vol;   // n+2
+  std::vector<double> up, dn;  // n+2: coupling of local cell k to k+1 / k-1
+  std::vector<double> R;       // n+2: spherical radial metric factor R_k (1 otherwise)
+  std::vector<double> P;       // n+2: factor of -s_m^2 in the azimuthal eigenvalue
+};
+
+Axis make_axis(const Spec& s, char which, long off, long stride, int n);
+
+// Host tables of one multigrid level (main grid or DGF extended box).
+struct LevelTables {
+  int na, nb;
+  int edge[4];  // a_lo, a_hi, b_lo, b_hi
+  Axis A, B;
+  // interior arrays (length na or nb), ghost couplings removed
+  std::vector<double> ua, da, Rr, ub, db;
+  std::vector<double> Ca, Cb;   // [M][na], [M][nb]; diag c = Ca[i] + Rr[i] * Cb[j]
+  std::vector<double> wr, wb;   // [M][nb] radial-line omega, [M][na] polar-line omega
+  std::vector<double> wc;       // [M] coarsest red-black omega
+  std::vector<double> va, vb;   // normalised volume weights (sum_ij va_i vb_j = 1)
+  // restriction to the next coarser level: [nc][2]
+  std::vector<double> rwa, rwb;
+  // prolongation from the next coarser level: per fine index two coarse
+  // indices and weights (ghosts folded with kappa); b tables for even/odd m
+  std::vector<int> pa_i0, pa_i1;
+  std::vector<double> pa_w0, pa_w1;
+  std::vector<int> pb_i0[2], pb_i1[2];
+  std::vector<double> pb_w0[2], pb_w1[2];
+};
+
+struct Hierarchy {
+  Spec spec;
+  int M;  // number of mode indices the tables cover
+  std::vector<LevelTables> lv;
+};
+
+// Build a hierarchy for interior cells a in [a_lo, a_lo + na - 1] and b in
+// [b_lo, b_lo + nb - 1] (global fine indices) with the given edge kinds.
+// `modes` is the list of azimuthal indices tables are built for (index into
+// the per-mode tables = position in the list).
+Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, const int edge[4],
+                          const std::vector<int>& modes, bool main_grid);
+
+double mode_s2(int n_phi, int m);
+double kappa(int kind, int m);
+
+// The Dirichlet ghost cells of the problem grid (order: inner radial j=1..nb,
+// outer radial, lower b i=1..na, upper b; pole edges have none).
+struct GhostSet {
+  int n = 0;
+  std::vector<int> gi, gj;        // global fine indices (0 / n+1 on the ghost side)
+  std::vector<int> edge;          // 0 a_lo, 1 a_hi, 2 b_lo, 3 b_hi
+  std::vector<double> a, b, dv3;  // centroid coordinates, 3D volume
+  std::vector<double> coup_out;   // ghost -> interior coupling (screening mass)
+  std::vector<double> coup_in;    // interior -> ghost coupling (boundary data)
+  std::vector<int> adj;           // interior cell index i*nb + j (0-based)
+};
+GhostSet make_ghosts(const Spec& s);
+
+std::string strprintf(const char* fmt, ...);
+
+}  // namespace smg
+
+// ---------------------------------------------------------------------------
+// Device-side views and launchers (implemented in the .hip files).
+// ---------------------------------------------------------------------------
+struct LevelDev {
+  int na, nb;
+  int M;                     // per-mode table stride
+  const double *ua, *da, *Rr, *ub, *db;
+  const double *Ca, *Cb;     // [M][na], [M][nb]
+  const double *wr, *wb, *wc;
+  const double *va, *vb;
+  const double *rwa, *rwb;   // restriction to the next level
+  const int *pa_i0, *pa_i1;  // prolongation from the next level
+  const double *pa_w0, *pa_w1;
+  const int *pb_i0, *pb_i1;  // [2][nb]
+  const double *pb_w0, *pb_w1;
+};
+
+// A batch of planes: plane p of the batch lives at slot[p] in the level
+// arrays (plane stride na*nb complex) and uses per-mode tables at mode[p].
+struct Batch {
+  int n;
+  const int* slot;
+  const int* mode;
+};
+
+namespace smgk {
+// FFT (fft.hip)
+hipError_t fft_r2c(const double* rho, double2* modes, int n_lines, int n_phi, double scale,
+                   const double2* tw, hipStream_t st);
+hipError_t fft_c2r(const double2* modes, double* out, int n_lines, int n_phi, const double2* tw,
+                   hipStream_t st);
+// multigrid (mg.hip), FP64 fields
+hipError_t mg_smooth(const LevelDev& L, const Batch& b, double2* u, const double2* f, int n_sor, bool exact,
+                     hipStream_t st);
+hipError_t mg_residual(const LevelDev& L, const Batch& b, const double2* u, const double2* f,
+                       double2* r, hipStream_t st);
+hipError_t mg_restrict_residual(const LevelDev& L, const LevelDev& Lc, const Batch& b, const double2* u,
+                                const double2* f, double2* fc, double2* uc, hipStream_t st);
+hipError_t mg_prolong_add(const LevelDev& L, const LevelDev& Lc, const Batch& b, double2* u,
+                          const double2* uc, hipStream_t st);
+hipError_t mg_coarse_solve(const LevelDev& L, const Batch& b, double2* u, const double2* f,
+                           double rtol, int max_sweeps, hipStream_t st);
+hipError_t mg_norms(const LevelDev& L, const Batch& b, const double2* u, const double2* f,
+                    double* partial, double* out, hipStream_t st);
+hipError_t fill_zero(double2* p, size_t n, hipStream_t st);
+// James boundary (james.hip)
+hipError_t james_screen(const int* adj, const double* coup, int n_g, int plane, int M,
+                        const double2* psi, double inv4piG, double2* sigma, hipStream_t st);
+hipError_t james_conv(const double* dgf, const double2* sigma, double2* theta, int n_g, int M,
+                      hipStream_t st);
+hipError_t james_apply(const int* cells, const int* g0, const int* g1, const double* c0,
+                       const double* c1, int n_cells, int plane, int n_g, int M, const double2* theta,
+                       const double2* f, double2* f2, hipStream_t st);
+}  // namespace smgk

@@ -1,0 +1,288 @@
+"""ctypes binding of libsmg.so (include/smg.h): argument marshalling only.
+
+Every step of the solve runs in the HIP library; torch is used for device
+memory (the workspace and the caller's arrays) and for the current stream.
+Loading fails loudly if the library has not been built -- there is no
+fallback path.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsmg.so")
+
+SPHERICAL, CYLINDRICAL = 0, 1
+UNIFORM, LOG = 0, 1
+FP64, MIXED = 0, 1
+DGF_AUTO, DGF_AUX, DGF_EXTENDED = 0, 1, 2
+LINE_SOR, LINE_EXACT = 0, 1
+WARM_PREV = 1
+TIMINGS = 2
+
+STATUS = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOCONV", -3: "SMG_EHIP", -4: "SMG_EWORKSPACE", -5: "SMG_ESTATE"}
+
+
+class SmgError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("geometry", ctypes.c_int), ("radial", ctypes.c_int), ("n_a", ctypes.c_int), ("n_b", ctypes.c_int),
+                ("n_phi", ctypes.c_int), ("a_min", ctypes.c_double), ("a_max", ctypes.c_double),
+                ("b_min", ctypes.c_double), ("b_max", ctypes.c_double), ("G", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
+                ("n_sor", ctypes.c_int), ("max_cycles", ctypes.c_int), ("dgf_method", ctypes.c_int),
+                ("n_pad", ctypes.c_int), ("dgf_tol", ctypes.c_double), ("line_solver", ctypes.c_int)]
+
+
+_PI = ctypes.POINTER(ctypes.c_int)
+_PD = ctypes.POINTER(ctypes.c_double)
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_modes", ctypes.c_int), ("cycles1", _PI), ("cycles2", _PI), ("resid1", _PD), ("resid2", _PD),
+                ("total_cycles", ctypes.c_int), ("converged", ctypes.c_int), ("ms_fft", ctypes.c_double),
+                ("ms_mg1", ctypes.c_double), ("ms_james", ctypes.c_double), ("ms_mg2", ctypes.c_double),
+                ("ms_ifft", ctypes.c_double)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def load():
+    """Load libsmg.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not built: run `python -m paper_2606_17636_amd.build`")
+    # torch brings its own HIP runtime (soname libamdhip64.so.7); importing it
+    # first makes libsmg.so bind to that same runtime instead of loading a
+    # second copy from /opt/rocm, which could not share the device with it.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    P = _VP
+    sig = {
+        "smg_plan_create": ([ctypes.POINTER(Grid), ctypes.POINTER(Opts), ctypes.POINTER(P)], ctypes.c_int),
+        "smg_workspace_bytes": ([P], ctypes.c_size_t),
+        "smg_plan_setup": ([P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "smg_solve": ([P, P, P, ctypes.c_double, ctypes.c_uint, P, ctypes.POINTER(Info)], ctypes.c_int),
+        "smg_plan_destroy": ([P], ctypes.c_int),
+        "smg_last_error": ([], ctypes.c_char_p),
+        "smg_plan_geometry": ([P, _PD, _PD, _PD, _PD], ctypes.c_int),
+        "smg_plan_shape": ([P, _PI, _PI, _PI, _PI], ctypes.c_int),
+        "smg_fft_forward": ([P, P, P, P], ctypes.c_int),
+        "smg_fft_inverse": ([P, P, P, P], ctypes.c_int),
+        "smg_mg_solve": ([P, P, P, ctypes.c_double, P, _PI, _PD], ctypes.c_int),
+        "smg_mg_vcycle": ([P, P, P, P], ctypes.c_int),
+        "smg_mg_smooth": ([P, P, P, P], ctypes.c_int),
+        "smg_mg_residual": ([P, P, P, P, P], ctypes.c_int),
+        "smg_james": ([P, P, P, P, P, P, P], ctypes.c_int),
+        "smg_dgf_table": ([P, ctypes.c_int, _PD, P], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status, ok=(0,)):
+    if status not in ok:
+        raise SmgError(status, load().smg_last_error().decode())
+    return status
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_PD)
+
+
+def _iptr(a):
+    return a.ctypes.data_as(_PI)
+
+
+class Plan:
+    """One grid + options.  Host tables are built at construction; call
+    ``setup()`` to bind a device workspace and build the DGF tables."""
+
+    def __init__(self, geometry, radial, n_a, n_b, n_phi, a_min, a_max, b_min, b_max, G=1.0, precision=FP64,
+                 nu_pre=2, nu_post=2, n_sor=2, max_cycles=60, dgf_method=DGF_AUTO, n_pad=16, dgf_tol=1e-13,
+                 line_solver=LINE_SOR):
+        lib = load()
+        geo = {"spherical": SPHERICAL, "cylindrical": CYLINDRICAL}.get(geometry, geometry)
+        rad = {"uniform": UNIFORM, "log": LOG}.get(radial, radial)
+        prec = {"fp64": FP64, "mixed": MIXED}.get(precision, precision)
+        self.grid = Grid(geo, rad, n_a, n_b, n_phi, a_min, a_max, b_min, b_max, G)
+        ls = {"sor": LINE_SOR, "exact": LINE_EXACT}.get(line_solver, line_solver)
+        self.opts = Opts(prec, nu_pre, nu_post, n_sor, max_cycles, dgf_method, n_pad, dgf_tol, ls)
+        self.line_solver = ls
+        self._h = ctypes.c_void_p()
+        _check(lib.smg_plan_create(ctypes.byref(self.grid), ctypes.byref(self.opts), ctypes.byref(self._h)))
+        self.n_a, self.n_b, self.n_phi = n_a, n_b, n_phi
+        self.n_modes = n_phi // 2 + 1
+        self.workspace_bytes = int(lib.smg_workspace_bytes(self._h))
+        nl, ng = ctypes.c_int(), ctypes.c_int()
+        la = (ctypes.c_int * 16)()
+        lb = (ctypes.c_int * 16)()
+        _check(lib.smg_plan_shape(self._h, ctypes.byref(nl), ctypes.byref(ng), la, lb))
+        self.n_levels, self.n_ghost = nl.value, ng.value
+        self.level_shapes = [(la[i], lb[i]) for i in range(nl.value)]
+        self._ws = None
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.smg_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- host queries -------------------------------------------------------
+    def geometry(self):
+        """Cell centres (a, b, phi) and volumes dv[n_a, n_b] as numpy arrays."""
+        a = np.zeros(self.n_a)
+        b = np.zeros(self.n_b)
+        p = np.zeros(self.n_phi)
+        dv = np.zeros((self.n_a, self.n_b))
+        _check(load().smg_plan_geometry(self._h, _dptr(a), _dptr(b), _dptr(p), _dptr(dv)))
+        return a, b, p, dv
+
+    # -- device -------------------------------------------------------------
+    def setup(self, device="cuda"):
+        import torch
+        self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=device)
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        _check(load().smg_plan_setup(self._h, ctypes.c_void_p(base + off), ctypes.c_size_t(self.workspace_bytes),
+                                     _stream()))
+        return self
+
+    def _f64(self, t, shape):
+        import torch
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+            raise ValueError(f"expected a contiguous cuda float64 tensor of shape {shape}, got "
+                             f"{tuple(t.shape)} {t.dtype} {t.device}")
+        return t
+
+    def _c128(self, t, shape):
+        import torch
+        if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+            raise ValueError(f"expected a contiguous cuda complex128 tensor of shape {shape}")
+        return t
+
+    def solve(self, rho, tol=1e-8, warm=False, out=None, timings=False, allow_noconv=False):
+        """Phi for the density rho (cuda float64 [n_a, n_b, n_phi]); returns
+        (phi, info dict)."""
+        import torch
+        shape = (self.n_a, self.n_b, self.n_phi)
+        self._f64(rho, shape)
+        phi = out if out is not None else torch.empty(shape, dtype=torch.float64, device=rho.device)
+        self._f64(phi, shape)
+        M = self.n_modes
+        c1 = np.zeros(M, dtype=np.int32)
+        c2 = np.zeros(M, dtype=np.int32)
+        r1 = np.zeros(M)
+        r2 = np.zeros(M)
+        info = Info(M, _iptr(c1), _iptr(c2), _dptr(r1), _dptr(r2), 0, 0, 0, 0, 0, 0, 0)
+        flags = (WARM_PREV if warm else 0) | (TIMINGS if timings else 0)
+        st = load().smg_solve(self._h, _ptr(rho), _ptr(phi), ctypes.c_double(tol), ctypes.c_uint(flags), _stream(),
+                              ctypes.byref(info))
+        _check(st, ok=(0, -2) if allow_noconv else (0,))
+        d = dict(cycles1=c1, cycles2=c2, resid1=r1, resid2=r2, total_cycles=info.total_cycles,
+                 converged=bool(info.converged), status=st)
+        if timings:
+            d.update(ms_fft=info.ms_fft, ms_mg1=info.ms_mg1, ms_james=info.ms_james, ms_mg2=info.ms_mg2,
+                     ms_ifft=info.ms_ifft)
+        return phi, d
+
+    def solve_nosync(self, rho, phi, tol=1e-8, warm=False):
+        """smg_solve without the info report (for timing loops)."""
+        _check(load().smg_solve(self._h, _ptr(rho), _ptr(phi), ctypes.c_double(tol),
+                                ctypes.c_uint(WARM_PREV if warm else 0), _stream(), None))
+
+    # -- steps ----------------------------------------------------------------
+    def mode_shape(self):
+        return (self.n_modes, self.n_a, self.n_b)
+
+    def fft_forward(self, rho, out=None):
+        import torch
+        self._f64(rho, (self.n_a, self.n_b, self.n_phi))
+        out = out if out is not None else torch.empty(self.mode_shape(), dtype=torch.complex128, device=rho.device)
+        _check(load().smg_fft_forward(self._h, _ptr(rho), _ptr(self._c128(out, self.mode_shape())), _stream()))
+        return out
+
+    def fft_inverse(self, modes, out=None):
+        import torch
+        self._c128(modes, self.mode_shape())
+        out = out if out is not None else torch.empty((self.n_a, self.n_b, self.n_phi), dtype=torch.float64,
+                                                      device=modes.device)
+        _check(load().smg_fft_inverse(self._h, _ptr(modes), _ptr(out), _stream()))
+        return out
+
+    def mg_solve(self, f, u, tol):
+        self._c128(f, self.mode_shape())
+        self._c128(u, self.mode_shape())
+        cyc = np.zeros(self.n_modes, dtype=np.int32)
+        res = np.zeros(self.n_modes)
+        _check(load().smg_mg_solve(self._h, _ptr(f), _ptr(u), ctypes.c_double(tol), _stream(), _iptr(cyc), _dptr(res)))
+        return cyc, res
+
+    def mg_vcycle(self, f, u):
+        _check(load().smg_mg_vcycle(self._h, _ptr(self._c128(f, self.mode_shape())),
+                                    _ptr(self._c128(u, self.mode_shape())), _stream()))
+
+    def mg_smooth(self, f, u):
+        _check(load().smg_mg_smooth(self._h, _ptr(self._c128(f, self.mode_shape())),
+                                    _ptr(self._c128(u, self.mode_shape())), _stream()))
+
+    def mg_residual(self, f, u, out=None):
+        import torch
+        out = out if out is not None else torch.empty(self.mode_shape(), dtype=torch.complex128, device=f.device)
+        _check(load().smg_mg_residual(self._h, _ptr(self._c128(f, self.mode_shape())),
+                                      _ptr(self._c128(u, self.mode_shape())), _ptr(out), _stream()))
+        return out
+
+    def james(self, psi, f):
+        import torch
+        M, ng = self.n_modes, self.n_ghost
+        sigma = torch.empty((M, ng), dtype=torch.complex128, device=psi.device)
+        theta = torch.empty((M, ng), dtype=torch.complex128, device=psi.device)
+        f2 = torch.empty(self.mode_shape(), dtype=torch.complex128, device=psi.device)
+        _check(load().smg_james(self._h, _ptr(self._c128(psi, self.mode_shape())),
+                                _ptr(self._c128(f, self.mode_shape())), _ptr(sigma), _ptr(theta), _ptr(f2), _stream()))
+        return sigma, theta, f2
+
+    def dgf_table(self, m):
+        out = np.zeros((self.n_ghost, self.n_ghost))
+        _check(load().smg_dgf_table(self._h, int(m), _dptr(out), _stream()))
+        return out
+
+
+def grid_from_spec(spec, **opts):
+    """Plan from any object with the GridSpec attributes (geometry, radial,
+    n_a, n_b, n_phi, a_min, a_max, b_min, b_max, G)."""
+    return Plan(spec.geometry, spec.radial, spec.n_a, spec.n_b, spec.n_phi, spec.a_min, spec.a_max, spec.b_min,
+                spec.b_max, spec.G, **opts)
+
+
+PI = math.pi

@@ -1,0 +1,214 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, step by
+step and end to end, on grids that span several tiles with ragged tails.
+
+Tolerances: the FFT and single kernel applications are compared element by
+element at rounding level (1e-13 relative to the array maximum); full
+multigrid solves at rel_tol 1e-12 are compared with the oracle's exact
+solution at 1e-10 relative L2 (the FP64 tolerance of the method's
+specification)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fourier
+from oracle.geometry import GridSpec, cell_centres, cell_volumes_3d
+from oracle.james import GhostSet, boundary_potential, dgf_tables, screening_mass
+from oracle.multigrid import Hierarchy
+from oracle.solve import OraclePlan
+from workloads.densities import gaussian_blobs, smooth_sphere, uniform_sphere
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SPECS = {
+    "sph-uni": (GridSpec("spherical", "uniform", 32, 16, 32, 0.1, 1.0, 0.0, math.pi), 16),
+    "sph-log": (GridSpec("spherical", "log", 48, 24, 24, 0.05, 5.0, 0.0, math.pi), 16),
+    "cyl-uni": (GridSpec("cylindrical", "uniform", 24, 20, 12, 0.2, 2.0, -0.5, 0.5), 8),
+    "cyl-log": (GridSpec("cylindrical", "log", 40, 12, 12, 0.05, 5.0, -2.5, 2.5), 16),
+    "sph-part": (GridSpec("spherical", "uniform", 16, 24, 8, 1.9, 3.5, 0.34 * math.pi, 0.66 * math.pi), 6),
+}
+
+
+def _density(spec, seed=0):
+    a, b, p = cell_centres(spec)
+    rng = np.random.default_rng(seed)
+    if spec.geometry == "spherical":
+        amid = math.sqrt(spec.a_min * spec.a_max) if spec.radial == "log" else 0.5 * (spec.a_min + spec.a_max)
+        cen = [(amid, 0.5 * (spec.b_min + spec.b_max) + 0.1, 0.3), (amid * 1.2, 0.5 * (spec.b_min + spec.b_max) - 0.2, 2.5)]
+    else:
+        amid = math.sqrt(spec.a_min * spec.a_max) if spec.radial == "log" else 0.5 * (spec.a_min + spec.a_max)
+        cen = [(amid, 0.05, 0.3), (amid * 1.1, -0.1, 2.5)]
+    w = 0.25 * (spec.a_max - spec.a_min) / (3.0 if spec.radial == "log" else 1.0)
+    rho = gaussian_blobs(spec.geometry, a, b, p, cen, [w, 0.7 * w], [1.0, 0.5])
+    return rho + 1e-3 * rng.random(rho.shape)
+
+
+_cache = {}
+
+
+def _plans(key):
+    if key not in _cache:
+        from paper_2606_17636_amd import smg
+        spec, npad = SPECS[key]
+        print(f"[setup] {key} {spec}", flush=True)
+        gp = smg.grid_from_spec(spec, n_pad=npad).setup()
+        op = OraclePlan(spec, n_pad=npad)
+        _cache[key] = (spec, gp, op)
+    return _cache[key]
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("key", list(SPECS))
+def test_fft_forward_inverse(key):
+    spec, gp, op = _plans(key)
+    rho = _density(spec, 1)
+    modes = gp.fft_forward(_dev(rho)).cpu().numpy()
+    ref = 4 * math.pi * spec.G * fourier.forward(rho)
+    assert _rel(modes, ref) < 1e-13
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal(ref.shape) + 1j * rng.standard_normal(ref.shape)
+    out = gp.fft_inverse(_dev(X)).cpu().numpy()
+    assert _rel(out, fourier.inverse(X, spec.n_phi)) < 1e-13
+
+
+@pytest.mark.parametrize("n_phi", [4, 6, 24, 96, 192, 256])
+def test_fft_radices(n_phi):
+    from paper_2606_17636_amd import smg
+    spec = GridSpec("cylindrical", "uniform", 4, 6, n_phi, 0.5, 1.0, -0.5, 0.5)
+    gp = smg.grid_from_spec(spec, n_pad=2).setup()
+    rho = np.random.default_rng(n_phi).standard_normal((4, 6, n_phi))
+    modes = gp.fft_forward(_dev(rho)).cpu().numpy()
+    assert _rel(modes, 4 * math.pi * fourier.forward(rho)) < 1e-13
+    back = gp.fft_inverse(_dev(modes)).cpu().numpy() / (4 * math.pi)
+    assert _rel(back, rho) < 1e-13
+
+
+def _random_modes(spec, seed):
+    rng = np.random.default_rng(seed)
+    shp = (spec.n_modes, spec.n_a, spec.n_b)
+    x = rng.standard_normal(shp) + 1j * rng.standard_normal(shp)
+    x[0].imag = 0.0
+    return x
+
+
+@pytest.mark.parametrize("key", ["sph-log", "cyl-uni", "cyl-log"])
+def test_smoother_exact_one_step(key):
+    from paper_2606_17636_amd import smg
+    spec, npad = SPECS[key]
+    gp = smg.grid_from_spec(spec, n_pad=npad, line_solver="exact").setup()
+    u, f = _random_modes(spec, 15), _random_modes(spec, 16)
+    ud = _dev(u)
+    gp.mg_smooth(_dev(f), ud)
+    h = Hierarchy(spec, line_solver="exact")
+    ref = u.copy()
+    for m in range(spec.n_modes):
+        h.levels[0].smooth_exact(ref[m], f[m], m)
+    assert _rel(ud.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("key", list(SPECS))
+def test_residual_kernel(key):
+    spec, gp, op = _plans(key)
+    u, f = _random_modes(spec, 3), _random_modes(spec, 4)
+    r = gp.mg_residual(_dev(f), _dev(u)).cpu().numpy()
+    ref = np.stack([f[m] - op.op.apply(u[m], m) for m in range(spec.n_modes)])
+    assert _rel(r, ref) < 1e-13
+
+
+@pytest.mark.parametrize("key", list(SPECS))
+def test_smoother_one_step(key):
+    spec, gp, op = _plans(key)
+    u, f = _random_modes(spec, 5), _random_modes(spec, 6)
+    ud = _dev(u)
+    gp.mg_smooth(_dev(f), ud)
+    h = Hierarchy(spec)
+    ref = u.copy()
+    for m in range(spec.n_modes):
+        h.levels[0].smooth(ref[m], f[m], m, 2)
+    assert _rel(ud.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("key", list(SPECS))
+def test_vcycle(key):
+    spec, gp, op = _plans(key)
+    f = _random_modes(spec, 7)
+    u = np.zeros_like(f)
+    ud = _dev(u)
+    gp.mg_vcycle(_dev(f), ud)
+    h = Hierarchy(spec)
+    for m in range(spec.n_modes):
+        h.vcycle(u[m], f[m], m)
+    assert _rel(ud.cpu().numpy(), u) < 1e-9
+
+
+@pytest.mark.parametrize("key", list(SPECS))
+def test_mg_solve_matches_direct(key):
+    spec, gp, op = _plans(key)
+    f = op.source_modes(_density(spec, 8))
+    ud = torch.zeros(f.shape, dtype=torch.complex128, device="cuda")
+    cycles, res = gp.mg_solve(_dev(f), ud, 1e-12)
+    ref = op.solve_modes(f)
+    assert _rel(ud.cpu().numpy(), ref) < 1e-10
+    assert cycles.max() <= 60 and np.all(res <= 1e-12)
+
+
+@pytest.mark.parametrize("key", list(SPECS))
+def test_dgf_tables(key):
+    spec, gp, op = _plans(key)
+    for m in sorted({0, 1, spec.n_modes - 1}):
+        tab = gp.dgf_table(m)
+        assert _rel(tab, op.dgf[m]) < 1e-10, m
+
+
+@pytest.mark.parametrize("key", list(SPECS))
+def test_james_steps(key):
+    spec, gp, op = _plans(key)
+    f = op.source_modes(_density(spec, 9))
+    psi = op.solve_modes(f)
+    sig, th, f2 = gp.james(_dev(psi), _dev(f))
+    gh = GhostSet(spec)
+    sig_ref = screening_mass(spec, gh, psi)
+    th_ref = boundary_potential(op.dgf, sig_ref)
+    assert _rel(sig.cpu().numpy(), sig_ref) < 1e-13
+    assert _rel(th.cpu().numpy(), th_ref) < 1e-10
+    assert _rel(f2.cpu().numpy(), f + op.boundary_rhs(th_ref)) < 1e-10
+
+
+def _l2(spec, x, ref):
+    w = cell_volumes_3d(spec)[:, :, None]
+    return math.sqrt(np.sum((x - ref) ** 2 * w) / np.sum(ref**2 * w))
+
+
+@pytest.mark.parametrize("key", list(SPECS))
+def test_full_solve_fp64(key):
+    spec, gp, op = _plans(key)
+    rho = _density(spec, 10)
+    phi, info = gp.solve(_dev(rho), tol=1e-12)
+    ref = op.solve(rho)
+    assert _l2(spec, phi.cpu().numpy(), ref) < 1e-10
+    assert info["converged"]
+
+
+def test_zero_density_gives_zero():
+    spec, gp, op = _plans("sph-uni")
+    phi, info = gp.solve(torch.zeros((spec.n_a, spec.n_b, spec.n_phi), dtype=torch.float64, device="cuda"), tol=1e-8)
+    assert float(phi.abs().max()) == 0.0
+    assert info["total_cycles"] == 0
+
+
+def test_warm_start_reduces_cycles():
+    spec, gp, op = _plans("sph-log")
+    rho = _density(spec, 11)
+    _, cold = gp.solve(_dev(rho), tol=1e-10)
+    phi, warm = gp.solve(_dev(rho * 1.001), tol=1e-10, warm=True)
+    assert warm["total_cycles"] < cold["total_cycles"]
+    ref = op.solve(rho * 1.001)
+    assert _l2(spec, phi.cpu().numpy(), ref) < 1e-8
