@@ -196,6 +196,27 @@ smg_status smg_james(smg_plan *plan, const double *psi_dev, const double *f_dev,
  * row = field ghost t, column = source ghost s). */
 smg_status smg_dgf_table(smg_plan *plan, int m, double *dgf_host, void *stream);
 
+/* ---- per-launch timing ---------------------------------------------------
+ * Between smg_profile_begin and smg_profile_end every kernel launch of
+ * smg_solve is bracketed by HIP events on the solve's stream.  End
+ * synchronises the device and reports, per kernel class, the number of
+ * launches, the summed launch durations (ms) and the summed algorithmic
+ * bytes (each launch reads its inputs and writes its outputs once: 48 B per
+ * cell for a directional FP64 smoothing pass, 40 B per fine cell for the
+ * fused residual + restriction, 36 B for prolongation + correction, the
+ * real input plus complex output for the FFTs, the FP64 DGF table for the
+ * boundary convolution).  `name` points to a string owned by the library.
+ * Writes at most max_stats entries; *n_stats receives the number of classes. */
+typedef struct {
+  const char *name;
+  int launches;
+  double total_ms;
+  double bytes;
+} smg_kernel_stat;
+
+smg_status smg_profile_begin(smg_plan *plan);
+smg_status smg_profile_end(smg_plan *plan, smg_kernel_stat *stats, int max_stats, int *n_stats);
+
 #ifdef __cplusplus
 }
 #endif

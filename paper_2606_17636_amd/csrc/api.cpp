@@ -136,11 +136,18 @@ struct smg_plan {
   bool have_prev = false;
   double dgf_resid = 0.0;  // worst relative residual of the DGF solves
   MGFields mg;
+  // per-launch event timing (smg_profile_begin / smg_profile_end)
+  struct ProfRec { int cls, ev0, ev1; double bytes; };
+  mutable bool prof_on = false;
+  mutable std::vector<hipEvent_t> prof_pool;
+  mutable size_t prof_used = 0;
+  mutable std::vector<ProfRec> prof_log;
   // pinned host staging
   int* h_slot = nullptr;
   int* h_mode = nullptr;
   double* h_norm = nullptr;
   ~smg_plan() {
+    for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
     if (h_slot) (void)hipHostFree(h_slot);
     if (h_mode) (void)hipHostFree(h_mode);
     if (h_norm) (void)hipHostFree(h_norm);
@@ -326,6 +333,34 @@ extern "C" smg_status smg_plan_shape(const smg_plan* p, int* n_levels, int* n_gh
 }
 
 // ----------------------------------------------------------------------------
+// per-launch timing
+// ----------------------------------------------------------------------------
+enum KernelClass {
+  K_FFT_R2C, K_FFT_C2R, K_SMOOTH_RADIAL0, K_SMOOTH_POLAR0, K_SMOOTH_COARSE, K_RESTRICT, K_PROLONG, K_COARSE,
+  K_NORM, K_SCREEN, K_CONV, K_APPLY, K_COUNT
+};
+static const char* kKernelNames[K_COUNT] = {
+  "fft_r2c", "fft_c2r", "smooth_radial_lines_l0", "smooth_polar_lines_l0", "smooth_coarser_levels",
+  "residual_restrict", "prolong_add", "coarse_rbsor", "defect_norm", "james_screen", "james_conv", "james_apply"};
+
+static int prof_mark(const smg_plan& p, hipStream_t st) {
+  if (!p.prof_on) return -1;
+  if (p.prof_used == p.prof_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    p.prof_pool.push_back(e);
+  }
+  if (hipEventRecord(p.prof_pool[p.prof_used], st) != hipSuccess) return -1;
+  return (int)p.prof_used++;
+}
+
+static void prof_close(const smg_plan& p, int cls, int ev0, double bytes, hipStream_t st) {
+  if (ev0 < 0) return;
+  int ev1 = prof_mark(p, st);
+  if (ev1 >= 0) p.prof_log.push_back({cls, ev0, ev1, bytes});
+}
+
+// ----------------------------------------------------------------------------
 // multigrid driver
 // ----------------------------------------------------------------------------
 static smg_status vcycle(const smg_plan& p, const MGFields& F, const Batch& b, double2* u0, const double2* f0,
@@ -336,14 +371,32 @@ static smg_status vcycle(const smg_plan& p, const MGFields& F, const Batch& b, d
   u[0] = u0;
   f[0] = f0;
   for (int l = 1; l < L; ++l) { u[l] = F.u[l]; f[l] = F.f[l]; }
+  auto cells = [&](int l) { return (double)b.n * F.L[l].na * F.L[l].nb; };
+  auto smooth = [&](int l) -> smg_status {
+    for (int dir = 0; dir < 2; ++dir) {
+      int ev = prof_mark(p, st);
+      HIPCHK(smgk::mg_smooth_dir(F.L[l], b, u[l], f[l], p.opts.n_sor, F.exact, dir, st));
+      prof_close(p, l == 0 ? (dir == 0 ? K_SMOOTH_RADIAL0 : K_SMOOTH_POLAR0) : K_SMOOTH_COARSE, ev,
+                 48.0 * cells(l), st);
+    }
+    return SMG_OK;
+  };
   for (int l = 0; l + 1 < L; ++l) {
-    for (int k = 0; k < p.opts.nu_pre; ++k) HIPCHK(smgk::mg_smooth(F.L[l], b, u[l], f[l], p.opts.n_sor, F.exact, st));
+    for (int k = 0; k < p.opts.nu_pre; ++k) STCHK(smooth(l));
+    int ev = prof_mark(p, st);
     HIPCHK(smgk::mg_restrict_residual(F.L[l], F.L[l + 1], b, u[l], f[l], F.f[l + 1], F.u[l + 1], st));
+    prof_close(p, K_RESTRICT, ev, 40.0 * cells(l), st);
   }
-  HIPCHK(smgk::mg_coarse_solve(F.L[L - 1], b, u[L - 1], f[L - 1], kCoarseRtol, kCoarseSweeps, st));
+  {
+    int ev = prof_mark(p, st);
+    HIPCHK(smgk::mg_coarse_solve(F.L[L - 1], b, u[L - 1], f[L - 1], kCoarseRtol, kCoarseSweeps, st));
+    prof_close(p, K_COARSE, ev, 48.0 * cells(L - 1), st);
+  }
   for (int l = L - 2; l >= 0; --l) {
+    int ev = prof_mark(p, st);
     HIPCHK(smgk::mg_prolong_add(F.L[l], F.L[l + 1], b, u[l], u[l + 1], st));
-    for (int k = 0; k < p.opts.nu_post; ++k) HIPCHK(smgk::mg_smooth(F.L[l], b, u[l], f[l], p.opts.n_sor, F.exact, st));
+    prof_close(p, K_PROLONG, ev, 36.0 * cells(l), st);
+    for (int k = 0; k < p.opts.nu_post; ++k) STCHK(smooth(l));
   }
   return SMG_OK;
 }
@@ -397,7 +450,9 @@ static smg_status mg_solve_planes(const smg_plan& p, const MGFields& F, int n, c
     HIPCHK(hipMemcpyAsync(d_mode, h_mode, sizeof(int) * na, hipMemcpyHostToDevice, st));
     Batch b{na, d_slot, d_mode};
     STCHK(vcycle(p, F, b, u0, f0, st));
+    int ev = prof_mark(p, st);
     HIPCHK(smgk::mg_norms(L0, b, u0, f0, d_partial, d_norm, st));
+    prof_close(p, K_NORM, ev, 32.0 * na * plane, st);
     HIPCHK(hipMemcpyAsync(h_norm, d_norm, sizeof(double) * na, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     std::vector<int> next;
@@ -724,14 +779,21 @@ static smg_status james_steps(smg_plan* p, const double2* psi, const double2* f,
   const Spec& s = p->spec;
   const int plane = s.n_a * s.n_b;
   const char* base = p->ws + p->w_blob;
+  const double M = p->M, ng = p->n_g;
+  int ev = prof_mark(*p, st);
   HIPCHK(smgk::james_screen(reinterpret_cast<const int*>(base + p->o_adj), reinterpret_cast<const double*>(base + p->o_cout),
                             p->n_g, plane, p->M, psi, 1.0 / (4.0 * kPi * s.G), sigma, st));
+  prof_close(*p, K_SCREEN, ev, M * ng * 32.0, st);
+  ev = prof_mark(*p, st);
   HIPCHK(smgk::james_conv(reinterpret_cast<const double*>(p->ws + p->w_dgf), sigma, theta, p->n_g, p->M, st));
+  prof_close(*p, K_CONV, ev, M * ng * ng * 8.0 + M * ng * 32.0, st);
   if (f2 != f) HIPCHK(hipMemcpyAsync(f2, f, sizeof(double2) * (size_t)p->M * plane, hipMemcpyDeviceToDevice, st));
+  ev = prof_mark(*p, st);
   HIPCHK(smgk::james_apply(reinterpret_cast<const int*>(base + p->o_apc), reinterpret_cast<const int*>(base + p->o_apg0),
                            reinterpret_cast<const int*>(base + p->o_apg1), reinterpret_cast<const double*>(base + p->o_apc0),
                            reinterpret_cast<const double*>(base + p->o_apc1), (int)p->ap_cell.size(), plane, p->n_g,
                            p->M, theta, f2, f2, st));
+  prof_close(*p, K_APPLY, ev, M * (double)p->ap_cell.size() * 48.0, st);
   return SMG_OK;
 }
 
@@ -758,7 +820,10 @@ extern "C" smg_status smg_solve(smg_plan* p, const double* rho, double* phi, dou
   const bool warm = (flags & SMG_WARM_PREV) && p->have_prev;
   const int lines = s.n_a * s.n_b;
   if (timings) HIPCHK(hipEventRecord(ev[0], st));
+  const double fft_bytes = (double)lines * (8.0 * s.n_phi + 16.0 * p->M);
+  int pe = prof_mark(*p, st);
   HIPCHK(smgk::fft_r2c(rho, f, lines, s.n_phi, 4.0 * kPi * s.G / s.n_phi, tw, st));
+  prof_close(*p, K_FFT_R2C, pe, fft_bytes, st);
   if (timings) HIPCHK(hipEventRecord(ev[1], st));
   SolveOut s1, s2;
   STCHK(solve_main(p, f, psi, tol, warm, st, s1));
@@ -767,7 +832,9 @@ extern "C" smg_status smg_solve(smg_plan* p, const double* rho, double* phi, dou
   if (timings) HIPCHK(hipEventRecord(ev[3], st));
   STCHK(solve_main(p, f, phim, tol, warm, st, s2));
   if (timings) HIPCHK(hipEventRecord(ev[4], st));
+  pe = prof_mark(*p, st);
   HIPCHK(smgk::fft_c2r(phim, phi, lines, s.n_phi, tw, st));
+  prof_close(*p, K_FFT_C2R, pe, fft_bytes, st);
   if (timings) HIPCHK(hipEventRecord(ev[5], st));
   p->have_prev = true;
   if (info) {
@@ -885,5 +952,46 @@ extern "C" smg_status smg_dgf_table(smg_plan* p, int m, double* host, void* stre
   const size_t n = (size_t)p->n_g * p->n_g;
   HIPCHK(hipMemcpyAsync(host, p->ws + p->w_dgf + sizeof(double) * n * m, sizeof(double) * n, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  return SMG_OK;
+}
+
+// ----------------------------------------------------------------------------
+// per-launch timing entry points
+// ----------------------------------------------------------------------------
+extern "C" smg_status smg_profile_begin(smg_plan* p) {
+  if (!p) return fail(SMG_EINVAL, "NULL plan");
+  p->prof_on = true;
+  p->prof_used = 0;
+  p->prof_log.clear();
+  return SMG_OK;
+}
+
+extern "C" smg_status smg_profile_end(smg_plan* p, smg_kernel_stat* stats, int max_stats, int* n_stats) {
+  if (!p) return fail(SMG_EINVAL, "NULL plan");
+  p->prof_on = false;
+  HIPCHK(hipDeviceSynchronize());
+  std::vector<int> launches(K_COUNT, 0);
+  std::vector<double> ms(K_COUNT, 0.0), bytes(K_COUNT, 0.0);
+  for (const auto& r : p->prof_log) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, p->prof_pool[r.ev0], p->prof_pool[r.ev1]));
+    launches[r.cls] += 1;
+    ms[r.cls] += t;
+    bytes[r.cls] += r.bytes;
+  }
+  int n = 0;
+  for (int c = 0; c < K_COUNT; ++c) {
+    if (!launches[c]) continue;
+    if (stats && n < max_stats) {
+      stats[n].name = kKernelNames[c];
+      stats[n].launches = launches[c];
+      stats[n].total_ms = ms[c];
+      stats[n].bytes = bytes[c];
+    }
+    ++n;
+  }
+  if (n_stats) *n_stats = n;
+  p->prof_log.clear();
+  p->prof_used = 0;
   return SMG_OK;
 }

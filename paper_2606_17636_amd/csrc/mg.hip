@@ -390,11 +390,11 @@ constexpr size_t kSmoothLds = 48 * 1024;
 
 namespace smgk {
 
-hipError_t mg_smooth(const LevelDev& L, const Batch& b, double2* u, const double2* f, int n_sor, bool exact,
-                     hipStream_t st) {
+hipError_t mg_smooth_dir(const LevelDev& L, const Batch& b, double2* u, const double2* f, int n_sor, bool exact,
+                         int dir, hipStream_t st) {
   if (b.n == 0) return hipSuccess;
-  // radial lines: tile of W columns spanning all rows
-  {
+  if (dir == 0) {
+    // radial lines: tile of W columns spanning all rows
     const size_t row = sizeof(double2) * (L.na + 2) + (exact ? sizeof(double) * L.na / 2 : 0);
     int W = (int)((kSmoothLds - (exact ? 2 * sizeof(double) * L.na : 0)) / row) - 4;
     W = W < 2 ? 2 : (W > L.nb ? L.nb : W);
@@ -405,11 +405,8 @@ hipError_t mg_smooth(const LevelDev& L, const Batch& b, double2* u, const double
       hipLaunchKernelGGL((k_smooth<0, true>), dim3((L.nb + W - 1) / W, b.n), dim3(kThreads), lds, st, L, b, u, f, n_sor, W);
     else
       hipLaunchKernelGGL((k_smooth<0, false>), dim3((L.nb + W - 1) / W, b.n), dim3(kThreads), lds, st, L, b, u, f, n_sor, W);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  // polar lines: tile of T rows spanning all columns
-  {
+  } else {
+    // polar lines: tile of T rows spanning all columns
     const size_t row = sizeof(double2) * (L.nb + 2) + (exact ? sizeof(double) * L.nb / 2 : 0);
     int T = (int)((kSmoothLds - (exact ? 2 * sizeof(double) * L.nb : 0)) / row) - 4;
     T = T < 2 ? 2 : (T > L.na ? L.na : T);
@@ -422,6 +419,13 @@ hipError_t mg_smooth(const LevelDev& L, const Batch& b, double2* u, const double
       hipLaunchKernelGGL((k_smooth<1, false>), dim3((L.na + T - 1) / T, b.n), dim3(kThreads), lds, st, L, b, u, f, n_sor, T);
   }
   return hipGetLastError();
+}
+
+hipError_t mg_smooth(const LevelDev& L, const Batch& b, double2* u, const double2* f, int n_sor, bool exact,
+                     hipStream_t st) {
+  hipError_t e = mg_smooth_dir(L, b, u, f, n_sor, exact, 0, st);
+  if (e != hipSuccess) return e;
+  return mg_smooth_dir(L, b, u, f, n_sor, exact, 1, st);
 }
 
 hipError_t mg_residual(const LevelDev& L, const Batch& b, const double2* u, const double2* f, double2* r,

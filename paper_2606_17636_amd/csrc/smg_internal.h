@@ -135,6 +135,8 @@ hipError_t fft_c2r(const double2* modes, double* out, int n_lines, int n_phi, co
 // multigrid (mg.hip), FP64 fields
 hipError_t mg_smooth(const LevelDev& L, const Batch& b, double2* u, const double2* f, int n_sor, bool exact,
                      hipStream_t st);
+hipError_t mg_smooth_dir(const LevelDev& L, const Batch& b, double2* u, const double2* f, int n_sor, bool exact,
+                         int dir, hipStream_t st);
 hipError_t mg_residual(const LevelDev& L, const Batch& b, const double2* u, const double2* f,
                        double2* r, hipStream_t st);
 hipError_t mg_restrict_residual(const LevelDev& L, const LevelDev& Lc, const Batch& b, const double2* u,

@@ -54,6 +54,11 @@ class Info(ctypes.Structure):
                 ("ms_ifft", ctypes.c_double)]
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_int), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
 _lib = None
 _VP = ctypes.c_void_p
 
@@ -88,6 +93,8 @@ def load():
         "smg_mg_residual": ([P, P, P, P, P], ctypes.c_int),
         "smg_james": ([P, P, P, P, P, P, P], ctypes.c_int),
         "smg_dgf_table": ([P, ctypes.c_int, _PD, P], ctypes.c_int),
+        "smg_profile_begin": ([P], ctypes.c_int),
+        "smg_profile_end": ([P, ctypes.POINTER(KernelStat), ctypes.c_int, _PI], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -271,6 +278,17 @@ class Plan:
         _check(load().smg_james(self._h, _ptr(self._c128(psi, self.mode_shape())),
                                 _ptr(self._c128(f, self.mode_shape())), _ptr(sigma), _ptr(theta), _ptr(f2), _stream()))
         return sigma, theta, f2
+
+    def profile_begin(self):
+        _check(load().smg_profile_begin(self._h))
+
+    def profile_end(self):
+        """Per kernel class: launches, total ms, algorithmic bytes."""
+        arr = (KernelStat * 32)()
+        n = ctypes.c_int()
+        _check(load().smg_profile_end(self._h, arr, 32, ctypes.byref(n)))
+        return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms, bytes=arr[i].bytes)
+                for i in range(min(n.value, 32))}
 
     def dgf_table(self, m):
         out = np.zeros((self.n_ghost, self.n_ghost))
