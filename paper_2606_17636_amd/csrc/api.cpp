@@ -109,7 +109,35 @@ struct MGFields {
   std::vector<LevelDev> L;
   std::vector<double2*> u, f;  // index 0 unused
   bool exact = false;          // exact (Thomas) line relaxation
+  int lds_first = 0;           // first level of the in-LDS coarse cycle
+  LdsLevels lds{};
 };
+
+constexpr size_t kLdsCycleMax = 63 * 1024;  // leaves room for the static reduction buffer
+
+// Choose the deepest run of levels (ending at the coarsest) that one block
+// can hold in LDS, starting as fine as possible.
+void plan_lds(MGFields& F) {
+  const int L = (int)F.L.size();
+  for (int first = 0; first < L; ++first) {
+    if (L - first > kMaxLdsLevels) continue;
+    LdsLevels LL{};
+    LL.n = L - first;
+    int words = 0;
+    for (int l = first; l < L; ++l) {
+      LL.L[l - first] = F.L[l];
+      words += (F.L[l].na + 2) * (F.L[l].nb + 2) + F.L[l].na * F.L[l].nb;
+    }
+    LL.words = words;
+    LL.scratch = smgk::lds_cycle_scratch(LL, F.exact);
+    if (smgk::lds_cycle_bytes(LL, F.exact) <= kLdsCycleMax) {
+      F.lds_first = first;
+      F.lds = LL;
+      return;
+    }
+  }
+  F.lds_first = L - 1;
+}
 
 }  // namespace
 
@@ -341,7 +369,7 @@ enum KernelClass {
 };
 static const char* kKernelNames[K_COUNT] = {
   "fft_r2c", "fft_c2r", "smooth_radial_lines_l0", "smooth_polar_lines_l0", "smooth_coarser_levels",
-  "residual_restrict", "prolong_add", "coarse_rbsor", "defect_norm", "james_screen", "james_conv", "james_apply"};
+  "residual_restrict", "prolong_add", "lds_coarse_cycle", "defect_norm", "james_screen", "james_conv", "james_apply"};
 
 static int prof_mark(const smg_plan& p, hipStream_t st) {
   if (!p.prof_on) return -1;
@@ -381,7 +409,8 @@ static smg_status vcycle(const smg_plan& p, const MGFields& F, const Batch& b, d
     }
     return SMG_OK;
   };
-  for (int l = 0; l + 1 < L; ++l) {
+  const int first = F.lds_first;
+  for (int l = 0; l < first; ++l) {
     for (int k = 0; k < p.opts.nu_pre; ++k) STCHK(smooth(l));
     int ev = prof_mark(p, st);
     HIPCHK(smgk::mg_restrict_residual(F.L[l], F.L[l + 1], b, u[l], f[l], F.f[l + 1], F.u[l + 1], st));
@@ -389,10 +418,11 @@ static smg_status vcycle(const smg_plan& p, const MGFields& F, const Batch& b, d
   }
   {
     int ev = prof_mark(p, st);
-    HIPCHK(smgk::mg_coarse_solve(F.L[L - 1], b, u[L - 1], f[L - 1], kCoarseRtol, kCoarseSweeps, st));
-    prof_close(p, K_COARSE, ev, 48.0 * cells(L - 1), st);
+    HIPCHK(smgk::mg_lds_cycle(F.lds, b, f[first], u[first], first == 0, p.opts.nu_pre, p.opts.nu_post, p.opts.n_sor,
+                              F.exact, kCoarseRtol, kCoarseSweeps, st));
+    prof_close(p, K_COARSE, ev, 32.0 * cells(first), st);
   }
-  for (int l = L - 2; l >= 0; --l) {
+  for (int l = first - 1; l >= 0; --l) {
     int ev = prof_mark(p, st);
     HIPCHK(smgk::mg_prolong_add(F.L[l], F.L[l + 1], b, u[l], u[l + 1], st));
     prof_close(p, K_PROLONG, ev, 36.0 * cells(l), st);
@@ -696,6 +726,7 @@ static smg_status dgf_extended(smg_plan& p, hipStream_t st) {
     F.u[l] = static_cast<double2*>(tmp.alloc(sizeof(double2) * cap * pl, herr)); TMPCHK(F.u[l]);
     F.f[l] = static_cast<double2*>(tmp.alloc(sizeof(double2) * cap * pl, herr)); TMPCHK(F.f[l]);
   }
+  plan_lds(F);
   int* d_slot = static_cast<int*>(tmp.alloc(sizeof(int) * cap, herr)); TMPCHK(d_slot);
   int* d_mode = static_cast<int*>(tmp.alloc(sizeof(int) * cap, herr)); TMPCHK(d_mode);
   int* d_pm = tmp.upload(pm, st, herr); TMPCHK(d_pm);
@@ -751,6 +782,7 @@ extern "C" smg_status smg_plan_setup(smg_plan* p, void* workspace, size_t bytes,
     p->mg.u[l] = p->dptr(p->w_u[l]);
     p->mg.f[l] = p->dptr(p->w_fl[l]);
   }
+  plan_lds(p->mg);
   smg_status s = dgf_method_of(*p) == SMG_DGF_EXTENDED ? dgf_extended(*p, st) : dgf_aux(*p, st);
   if (s != SMG_OK) return s;
   HIPCHK(hipStreamSynchronize(st));

@@ -56,7 +56,8 @@ __device__ __forceinline__ double2 resid_at(const LevelDev& L, int m, const doub
 // ---------------------------------------------------------------------------
 template <int DIR, bool EXACT>
 __global__ void __launch_bounds__(kThreads) k_smooth(LevelDev L, Batch bt, double2* __restrict__ U,
-                                                    const double2* __restrict__ F, int n_sor, int tile) {
+                                                    const double2* __restrict__ F, int n_sor, int tile,
+                                                    int scratch_doubles, int stage) {
   extern __shared__ double2 sh[];
   const int p = blockIdx.y;
   const int slot = bt.slot[p], m = bt.mode[p];
@@ -90,6 +91,47 @@ __global__ void __launch_bounds__(kThreads) k_smooth(LevelDev L, Batch bt, doubl
   const int npts = DIR == 1 ? nb : na;                    // points per line
   // scratch for the exact line solve: one row of Thomas factors per line
   double* cp = reinterpret_cast<double*>(sh + nr * nc);
+  // the 1D stencil tables of this tile and mode (per row ua, da, R, Ca,
+  // omega of the polar line; per column ub, db, Cb, omega of the radial
+  // line), staged in LDS when they fit, else read in place; indexed by the
+  // tile-local row rr = i - r0 and column cc = j - c0.
+  const double *trU, *trD, *trR, *trC, *trW, *tcU, *tcD, *tcC, *tcW;
+  if (stage) {
+    double* t0 = cp + scratch_doubles;
+    double* t1 = t0 + nr;
+    double* t2 = t1 + nr;
+    double* t3 = t2 + nr;
+    double* t4 = t3 + nr;
+    double* c1 = t4 + nr;
+    double* c2 = c1 + nc;
+    double* c3 = c2 + nc;
+    double* c4 = c3 + nc;
+    for (int rr = threadIdx.x; rr < nr; rr += blockDim.x) {
+      const int i = r0 + rr;
+      const bool in = i >= 0 && i < na;
+      t0[rr] = in ? L.ua[i] : 0.0;
+      t1[rr] = in ? L.da[i] : 0.0;
+      t2[rr] = in ? L.Rr[i] : 0.0;
+      t3[rr] = in ? L.Ca[(size_t)m * na + i] : 1.0;
+      t4[rr] = in ? L.wb[(size_t)m * na + i] : 0.0;
+    }
+    for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
+      const int j = c0 + cc;
+      const bool in = j >= 0 && j < nb;
+      c1[cc] = in ? L.ub[j] : 0.0;
+      c2[cc] = in ? L.db[j] : 0.0;
+      c3[cc] = in ? L.Cb[(size_t)m * nb + j] : 0.0;
+      c4[cc] = in ? L.wr[(size_t)m * nb + j] : 0.0;
+    }
+    trU = t0; trD = t1; trR = t2; trC = t3; trW = t4;
+    tcU = c1; tcD = c2; tcC = c3; tcW = c4;
+    __syncthreads();
+  } else {
+    // rows and columns outside the plane are never read
+    trU = L.ua + r0; trD = L.da + r0; trR = L.Rr + r0;
+    trC = L.Ca + (size_t)m * na + r0; trW = L.wb + (size_t)m * na + r0;
+    tcU = L.ub + c0; tcD = L.db + c0; tcC = L.Cb + (size_t)m * nb + c0; tcW = L.wr + (size_t)m * nb + c0;
+  }
   for (int lc = 0; lc < 2; ++lc) {
     // colour lc: first colour includes the inner halo lines
     int a = lc == 0 ? lbeg - 1 : lbeg;
@@ -110,19 +152,19 @@ __global__ void __launch_bounds__(kThreads) k_smooth(LevelDev L, Batch bt, doubl
           const int i = DIR == 1 ? line : k;
           const int j = DIR == 1 ? k : line;
           const int rr = i - r0, cc = j - c0;
-          const double R = L.Rr[i];
-          const double c = L.Ca[(size_t)m * na + i] + R * L.Cb[(size_t)m * nb + j];
+          const double R = trR[rr];
+          const double c = trC[rr] + R * tcC[cc];
           double lo, up;
           double2 o1, o2;
           double w1, w2;
           if (DIR == 1) {  // line along j; fixed neighbours i+1, i-1
-            lo = R * L.db[j]; up = R * L.ub[j];
+            lo = R * tcD[cc]; up = R * tcU[cc];
             o1 = sh[(rr + 1) * nc + cc]; o2 = sh[(rr - 1) * nc + cc];
-            w1 = L.ua[i]; w2 = L.da[i];
+            w1 = trU[rr]; w2 = trD[rr];
           } else {         // line along i; fixed neighbours j+1, j-1
-            lo = L.da[i]; up = L.ua[i];
+            lo = trD[rr]; up = trU[rr];
             o1 = sh[rr * nc + cc + 1]; o2 = sh[rr * nc + cc - 1];
-            w1 = R * L.ub[j]; w2 = R * L.db[j];
+            w1 = R * tcU[cc]; w2 = R * tcD[cc];
           }
           const double2 fv = f[(size_t)i * nb + j];
           const double rx = fv.x - (w1 * o1.x + w2 * o2.x);
@@ -166,10 +208,10 @@ __global__ void __launch_bounds__(kThreads) k_smooth(LevelDev L, Batch bt, doubl
           const double2 us = sh[(rr - 1) * nc + cc];
           const double2 ue = sh[rr * nc + cc + 1];
           const double2 uw = sh[rr * nc + cc - 1];
-          const double R = L.Rr[i];
-          const double c = L.Ca[(size_t)m * na + i] + R * L.Cb[(size_t)m * nb + j];
-          const double w = DIR == 1 ? L.wb[(size_t)m * na + i] : L.wr[(size_t)m * nb + j];
-          const double ua = L.ua[i], da = L.da[i], ub = R * L.ub[j], db = R * L.db[j];
+          const double R = trR[rr];
+          const double c = trC[rr] + R * tcC[cc];
+          const double w = DIR == 1 ? trW[rr] : tcW[cc];
+          const double ua = trU[rr], da = trD[rr], ub = R * tcU[cc], db = R * tcD[cc];
           const double2 fv = f[(size_t)i * nb + j];
           double sx = ua * un.x + da * us.x + ub * ue.x + db * uw.x;
           double sy = ua * un.y + da * us.y + ub * ue.y + db * uw.y;
@@ -265,82 +307,6 @@ __global__ void __launch_bounds__(kThreads) k_prolong(LevelDev L, LevelDev C, Ba
   }
 }
 
-// Coarsest level (Sec. 3.3): red-black point SOR with the 2D WKB omega from a
-// zero start, one block per plane, the plane resident in LDS; stops when the
-// residual 2-norm has dropped by rtol or after max_sweeps sweeps.
-__global__ void __launch_bounds__(kThreads) k_coarse(LevelDev L, Batch bt, double2* __restrict__ U,
-                                                    const double2* __restrict__ F, double rtol, int max_sweeps) {
-  extern __shared__ double2 sh[];
-  __shared__ double red[kThreads / 64];
-  const int p = blockIdx.x;
-  const int slot = bt.slot[p], m = bt.mode[p];
-  const int na = L.na, nb = L.nb;
-  const int nc = nb + 2;
-  double2* us = sh;                       // (na+2) x (nb+2), zero border
-  double2* fs = sh + (na + 2) * nc;       // na x nb
-  const size_t off = (size_t)slot * na * nb;
-  for (int t = threadIdx.x; t < (na + 2) * nc; t += blockDim.x) us[t] = make_double2(0.0, 0.0);
-  double f2 = 0.0;
-  for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
-    double2 v = F[off + t];
-    fs[t] = v;
-    f2 += v.x * v.x + v.y * v.y;
-  }
-  auto block_sum = [&](double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double s = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
-    __syncthreads();
-    return s;
-  };
-  const double f2t = block_sum(f2);
-  const double w = L.wc[m];
-  const double* Ca = L.Ca + (size_t)m * na;
-  const double* Cb = L.Cb + (size_t)m * nb;
-  if (f2t > 0.0) {
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-      for (int colour = 0; colour < 2; ++colour) {
-        for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
-          const int i = t / nb, j = t - i * nb;
-          if (((i + j) & 1) != colour) continue;
-          const double R = L.Rr[i];
-          const double c = Ca[i] + R * Cb[j];
-          const int q = (i + 1) * nc + (j + 1);
-          const double2 un = us[q + nc], uS = us[q - nc], ue = us[q + 1], uw = us[q - 1];
-          const double a1 = L.ua[i], a2 = L.da[i], b1 = R * L.ub[j], b2 = R * L.db[j];
-          const double2 fv = fs[t];
-          const double tx = (fv.x - (a1 * un.x + a2 * uS.x + b1 * ue.x + b2 * uw.x)) / c;
-          const double ty = (fv.y - (a1 * un.y + a2 * uS.y + b1 * ue.y + b2 * uw.y)) / c;
-          const double2 old = us[q];
-          us[q] = make_double2(old.x + w * (tx - old.x), old.y + w * (ty - old.y));
-        }
-        __syncthreads();
-      }
-      double r2 = 0.0;
-      for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
-        const int i = t / nb, j = t - i * nb;
-        const double R = L.Rr[i];
-        const double c = Ca[i] + R * Cb[j];
-        const int q = (i + 1) * nc + (j + 1);
-        const double2 un = us[q + nc], uS = us[q - nc], ue = us[q + 1], uw = us[q - 1], uc = us[q];
-        const double a1 = L.ua[i], a2 = L.da[i], b1 = R * L.ub[j], b2 = R * L.db[j];
-        const double2 fv = fs[t];
-        const double rx = fv.x - (c * uc.x + a1 * un.x + a2 * uS.x + b1 * ue.x + b2 * uw.x);
-        const double ry = fv.y - (c * uc.y + a1 * un.y + a2 * uS.y + b1 * ue.y + b2 * uw.y);
-        r2 += rx * rx + ry * ry;
-      }
-      const double r2t = block_sum(r2);
-      if (r2t <= rtol * rtol * f2t) break;
-    }
-  }
-  for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
-    const int i = t / nb, j = t - i * nb;
-    U[off + t] = us[(i + 1) * nc + (j + 1)];
-  }
-}
-
 // Volume-weighted squared defect: partial sums per (plane, block).
 __global__ void __launch_bounds__(kThreads) k_norm_partial(LevelDev L, Batch bt, const double2* __restrict__ U,
                                                           const double2* __restrict__ F, double* __restrict__ partial) {
@@ -384,7 +350,16 @@ int grid_for(int cells) {
   return g < 1 ? 1 : (g > 1024 ? 1024 : g);
 }
 
-constexpr size_t kSmoothLds = 48 * 1024;
+constexpr size_t kSmoothLds = 60 * 1024;     // preferred per-block LDS
+constexpr size_t kSmoothLdsMax = 64 * 1024;  // hard limit of a launch
+
+// Lines per tile so that a launch over n_planes planes has about two blocks
+// per compute unit (512 blocks) when the planes allow it.
+int par_tile(int n_lines, int n_planes) {
+  const int want = (512 + n_planes - 1) / n_planes;  // tiles per plane
+  int t = (n_lines + want - 1) / want;
+  return t < 2 ? 2 : t;
+}
 
 }  // namespace
 
@@ -393,30 +368,36 @@ namespace smgk {
 hipError_t mg_smooth_dir(const LevelDev& L, const Batch& b, double2* u, const double2* f, int n_sor, bool exact,
                          int dir, hipStream_t st) {
   if (b.n == 0) return hipSuccess;
+  // LDS per block: tile (lines + 4 halo) x (points + 2), Thomas scratch for
+  // the exact variant, and the staged 1D tables (5 per row, 4 per column).
+  const int npts = dir == 0 ? L.na : L.nb;       // points per line
+  const int nlines = dir == 0 ? L.nb : L.na;     // lines in the plane
+  auto bytes = [&](int t, bool stage) {
+    const size_t nr = dir == 0 ? (size_t)L.na + 2 : (size_t)t + 4;
+    const size_t nc = dir == 0 ? (size_t)t + 4 : (size_t)L.nb + 2;
+    const size_t scratch = exact ? (size_t)(t / 2 + 2) * npts : 0;
+    return sizeof(double2) * nr * nc + sizeof(double) * (scratch + (stage ? 5 * nr + 4 * nc : 0));
+  };
+  int tile = par_tile(nlines, b.n);
+  if (tile > nlines) tile = nlines;
+  while (tile > 2 && bytes(tile, true) > kSmoothLds) --tile;
+  if (tile > 2 && (tile & 1)) --tile;
+  const bool stage = bytes(tile, true) <= kSmoothLds;
+  const size_t lds = bytes(tile, stage);
+  if (lds > kSmoothLdsMax) return hipErrorInvalidConfiguration;
+  const int scratch = exact ? (tile / 2 + 2) * npts : 0;
+  const dim3 grid((nlines + tile - 1) / tile, b.n);
+  const int sg = stage ? 1 : 0;
   if (dir == 0) {
-    // radial lines: tile of W columns spanning all rows
-    const size_t row = sizeof(double2) * (L.na + 2) + (exact ? sizeof(double) * L.na / 2 : 0);
-    int W = (int)((kSmoothLds - (exact ? 2 * sizeof(double) * L.na : 0)) / row) - 4;
-    W = W < 2 ? 2 : (W > L.nb ? L.nb : W);
-    if (W > 2 && (W & 1)) --W;
-    const size_t lds = sizeof(double2) * (size_t)(L.na + 2) * (W + 4) +
-                       (exact ? sizeof(double) * (size_t)(W / 2 + 2) * L.na : 0);
     if (exact)
-      hipLaunchKernelGGL((k_smooth<0, true>), dim3((L.nb + W - 1) / W, b.n), dim3(kThreads), lds, st, L, b, u, f, n_sor, W);
+      hipLaunchKernelGGL((k_smooth<0, true>), grid, dim3(kThreads), lds, st, L, b, u, f, n_sor, tile, scratch, sg);
     else
-      hipLaunchKernelGGL((k_smooth<0, false>), dim3((L.nb + W - 1) / W, b.n), dim3(kThreads), lds, st, L, b, u, f, n_sor, W);
+      hipLaunchKernelGGL((k_smooth<0, false>), grid, dim3(kThreads), lds, st, L, b, u, f, n_sor, tile, scratch, sg);
   } else {
-    // polar lines: tile of T rows spanning all columns
-    const size_t row = sizeof(double2) * (L.nb + 2) + (exact ? sizeof(double) * L.nb / 2 : 0);
-    int T = (int)((kSmoothLds - (exact ? 2 * sizeof(double) * L.nb : 0)) / row) - 4;
-    T = T < 2 ? 2 : (T > L.na ? L.na : T);
-    if (T > 2 && (T & 1)) --T;
-    const size_t lds = sizeof(double2) * (size_t)(T + 4) * (L.nb + 2) +
-                       (exact ? sizeof(double) * (size_t)(T / 2 + 2) * L.nb : 0);
     if (exact)
-      hipLaunchKernelGGL((k_smooth<1, true>), dim3((L.na + T - 1) / T, b.n), dim3(kThreads), lds, st, L, b, u, f, n_sor, T);
+      hipLaunchKernelGGL((k_smooth<1, true>), grid, dim3(kThreads), lds, st, L, b, u, f, n_sor, tile, scratch, sg);
     else
-      hipLaunchKernelGGL((k_smooth<1, false>), dim3((L.na + T - 1) / T, b.n), dim3(kThreads), lds, st, L, b, u, f, n_sor, T);
+      hipLaunchKernelGGL((k_smooth<1, false>), grid, dim3(kThreads), lds, st, L, b, u, f, n_sor, tile, scratch, sg);
   }
   return hipGetLastError();
 }
@@ -446,14 +427,6 @@ hipError_t mg_prolong_add(const LevelDev& L, const LevelDev& C, const Batch& b, 
                           hipStream_t st) {
   if (b.n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_prolong, dim3(grid_for(L.na * L.nb), b.n), dim3(kThreads), 0, st, L, C, b, u, uc);
-  return hipGetLastError();
-}
-
-hipError_t mg_coarse_solve(const LevelDev& L, const Batch& b, double2* u, const double2* f, double rtol,
-                           int max_sweeps, hipStream_t st) {
-  if (b.n == 0) return hipSuccess;
-  const size_t lds = sizeof(double2) * ((size_t)(L.na + 2) * (L.nb + 2) + (size_t)L.na * L.nb);
-  hipLaunchKernelGGL(k_coarse, dim3(b.n), dim3(kThreads), lds, st, L, b, u, f, rtol, max_sweeps);
   return hipGetLastError();
 }
 

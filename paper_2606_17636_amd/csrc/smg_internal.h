@@ -118,6 +118,16 @@ struct LevelDev {
   const double *pb_w0, *pb_w1;
 };
 
+// The levels that one block per plane processes entirely in LDS (the
+// coarse end of the V-cycle); L[0] is the first fused level.
+constexpr int kMaxLdsLevels = 8;
+struct LdsLevels {
+  int n;
+  int words;    // double2 words of u (padded) and f storage of all fused levels
+  int scratch;  // doubles of exact-line scratch (0 for the SOR smoother)
+  LevelDev L[kMaxLdsLevels];
+};
+
 // A batch of planes: plane p of the batch lives at slot[p] in the level
 // arrays (plane stride na*nb complex) and uses per-mode tables at mode[p].
 struct Batch {
@@ -143,8 +153,10 @@ hipError_t mg_restrict_residual(const LevelDev& L, const LevelDev& Lc, const Bat
                                 const double2* f, double2* fc, double2* uc, hipStream_t st);
 hipError_t mg_prolong_add(const LevelDev& L, const LevelDev& Lc, const Batch& b, double2* u,
                           const double2* uc, hipStream_t st);
-hipError_t mg_coarse_solve(const LevelDev& L, const Batch& b, double2* u, const double2* f,
-                           double rtol, int max_sweeps, hipStream_t st);
+size_t lds_cycle_bytes(const LdsLevels& LL, bool exact);
+int lds_cycle_scratch(const LdsLevels& LL, bool exact);
+hipError_t mg_lds_cycle(const LdsLevels& LL, const Batch& b, const double2* f, double2* u, bool load_u, int nu_pre,
+                        int nu_post, int n_sor, bool exact, double rtol, int max_sweeps, hipStream_t st);
 hipError_t mg_norms(const LevelDev& L, const Batch& b, const double2* u, const double2* f,
                     double* partial, double* out, hipStream_t st);
 hipError_t fill_zero(double2* p, size_t n, hipStream_t st);
