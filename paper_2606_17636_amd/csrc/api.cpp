@@ -68,7 +68,8 @@ struct Blob {
 // Offsets of one level's tables inside the blob.
 struct LevelOff {
   size_t ua, da, Rr, ub, db, Ca, Cb, wr, wb, wc, va, vb, rwa, rwb, pa_i0, pa_i1, pa_w0, pa_w1, pb_i0, pb_i1,
-      pb_w0, pb_w1;
+      pb_w0, pb_w1, cinv;
+  bool has_cinv;
 };
 
 LevelOff pack_level(Blob& B, const LevelTables& T) {
@@ -87,6 +88,8 @@ LevelOff pack_level(Blob& B, const LevelTables& T) {
     w1.insert(w1.end(), T.pb_w1[par].begin(), T.pb_w1[par].end());
   }
   o.pb_i0 = B.add(i0); o.pb_i1 = B.add(i1); o.pb_w0 = B.add(w0); o.pb_w1 = B.add(w1);
+  o.has_cinv = !T.cinv.empty();
+  o.cinv = o.has_cinv ? B.add(T.cinv) : 0;
   return o;
 }
 
@@ -100,6 +103,7 @@ LevelDev level_view(const char* base, const LevelOff& o, const LevelTables& T, i
   L.va = d(o.va); L.vb = d(o.vb); L.rwa = d(o.rwa); L.rwb = d(o.rwb);
   L.pa_i0 = i(o.pa_i0); L.pa_i1 = i(o.pa_i1); L.pa_w0 = d(o.pa_w0); L.pa_w1 = d(o.pa_w1);
   L.pb_i0 = i(o.pb_i0); L.pb_i1 = i(o.pb_i1); L.pb_w0 = d(o.pb_w0); L.pb_w1 = d(o.pb_w1);
+  L.cinv = o.has_cinv ? d(o.cinv) : nullptr;
   return L;
 }
 
@@ -109,6 +113,8 @@ struct MGFields {
   std::vector<LevelDev> L;
   std::vector<double2*> u, f;  // index 0 unused
   bool exact = false;          // exact (Thomas) line relaxation
+  bool fp32 = false;           // mixed form: FP32 correction cycles
+  std::vector<float2*> u32, f32;  // FP32 correction / right-hand side per level (mixed form)
   int lds_first = 0;           // first level of the in-LDS coarse cycle
   LdsLevels lds{};
 };
@@ -130,7 +136,7 @@ void plan_lds(MGFields& F) {
     }
     LL.words = words;
     LL.scratch = smgk::lds_cycle_scratch(LL, F.exact);
-    if (smgk::lds_cycle_bytes(LL, F.exact) <= kLdsCycleMax) {
+    if (smgk::lds_cycle_bytes(LL, F.fp32) <= kLdsCycleMax) {
       F.lds_first = first;
       F.lds = LL;
       return;
@@ -157,7 +163,7 @@ struct smg_plan {
   // workspace layout (byte offsets)
   size_t w_blob = 0, w_dgf = 0, w_psi = 0, w_phi = 0, w_f = 0, w_sigma = 0, w_theta = 0, w_partial = 0,
          w_norm = 0, w_slot = 0, w_mode = 0, w_total = 0;
-  std::vector<size_t> w_u, w_fl;
+  std::vector<size_t> w_u, w_fl, w_u32, w_f32;
   // bound workspace
   char* ws = nullptr;
   bool ready = false;
@@ -321,6 +327,15 @@ extern "C" smg_status smg_plan_create(const smg_grid* grid, const smg_opts* opts
     p->w_u[l] = take(sizeof(double2) * M * pl);
     p->w_fl[l] = take(sizeof(double2) * M * pl);
   }
+  if (o.precision == SMG_MIXED) {
+    p->w_u32.assign(p->H.lv.size(), 0);
+    p->w_f32.assign(p->H.lv.size(), 0);
+    for (size_t l = 0; l < p->H.lv.size(); ++l) {
+      size_t pl = (size_t)p->H.lv[l].na * p->H.lv[l].nb;
+      p->w_u32[l] = take(sizeof(float2) * M * pl);
+      p->w_f32[l] = take(sizeof(float2) * M * pl);
+    }
+  }
   p->w_total = off;
   *out = p.release();
   g_err.clear();
@@ -365,11 +380,12 @@ extern "C" smg_status smg_plan_shape(const smg_plan* p, int* n_levels, int* n_gh
 // ----------------------------------------------------------------------------
 enum KernelClass {
   K_FFT_R2C, K_FFT_C2R, K_SMOOTH_RADIAL0, K_SMOOTH_POLAR0, K_SMOOTH_COARSE, K_RESTRICT, K_PROLONG, K_COARSE,
-  K_NORM, K_SCREEN, K_CONV, K_APPLY, K_COUNT
+  K_NORM, K_SCREEN, K_CONV, K_APPLY, K_ACCUM, K_COUNT
 };
 static const char* kKernelNames[K_COUNT] = {
   "fft_r2c", "fft_c2r", "smooth_radial_lines_l0", "smooth_polar_lines_l0", "smooth_coarser_levels",
-  "residual_restrict", "prolong_add", "lds_coarse_cycle", "defect_norm", "james_screen", "james_conv", "james_apply"};
+  "residual_restrict", "prolong_add", "lds_coarse_cycle", "defect_norm", "james_screen", "james_conv", "james_apply",
+  "accumulate_fp64"};
 
 static int prof_mark(const smg_plan& p, hipStream_t st) {
   if (!p.prof_on) return -1;
@@ -431,6 +447,44 @@ static smg_status vcycle(const smg_plan& p, const MGFields& F, const Batch& b, d
   return SMG_OK;
 }
 
+// One FP32 correction V-cycle of the mixed form: solves L e = r on level 0
+// (F.u32[0] = e, zero on entry; F.f32[0] = r) with FP32 smoothing and
+// transfers and the FP64 coarsest solve.
+static smg_status vcycle32(const smg_plan& p, const MGFields& F, const Batch& b, hipStream_t st) {
+  const int L = (int)F.L.size();
+  auto cells = [&](int l) { return (double)b.n * F.L[l].na * F.L[l].nb; };
+  auto smooth = [&](int l) -> smg_status {
+    for (int dir = 0; dir < 2; ++dir) {
+      int ev = prof_mark(p, st);
+      HIPCHK(smgk::mg_smooth_dir32(F.L[l], b, F.u32[l], F.f32[l], p.opts.n_sor, F.exact, dir, st));
+      prof_close(p, l == 0 ? (dir == 0 ? K_SMOOTH_RADIAL0 : K_SMOOTH_POLAR0) : K_SMOOTH_COARSE, ev,
+                 24.0 * cells(l), st);
+    }
+    return SMG_OK;
+  };
+  const int first = F.lds_first;
+  for (int l = 0; l < first; ++l) {
+    for (int k = 0; k < p.opts.nu_pre; ++k) STCHK(smooth(l));
+    int ev = prof_mark(p, st);
+    HIPCHK(smgk::mg_restrict_residual32(F.L[l], F.L[l + 1], b, F.u32[l], F.f32[l], F.f32[l + 1], F.u32[l + 1], st));
+    prof_close(p, K_RESTRICT, ev, 20.0 * cells(l), st);
+  }
+  {
+    int ev = prof_mark(p, st);
+    HIPCHK(smgk::mg_lds_cycle32(F.lds, b, F.f32[first], F.u32[first], first == 0, p.opts.nu_pre, p.opts.nu_post,
+                                p.opts.n_sor, F.exact, kCoarseRtol, kCoarseSweeps, st));
+    prof_close(p, K_COARSE, ev, 16.0 * cells(first), st);
+  }
+  for (int l = first - 1; l >= 0; --l) {
+    int ev = prof_mark(p, st);
+    HIPCHK(smgk::mg_prolong_add32(F.L[l], F.L[l + 1], b, F.u32[l], F.u32[l + 1], st));
+    prof_close(p, K_PROLONG, ev, 18.0 * cells(l), st);
+    for (int k = 0; k < p.opts.nu_post; ++k) STCHK(smooth(l));
+  }
+  (void)L;
+  return SMG_OK;
+}
+
 // Iterate V-cycles on planes 0..n-1 (slot p, mode modes[p]) until each meets
 // ||D|| <= tol * max(||D_0||, floor_factor * max ||D_0||).  d_slot/d_mode
 // are device int arrays of capacity n; partial/norm device scratch.
@@ -455,7 +509,9 @@ static smg_status mg_solve_planes(const smg_plan& p, const MGFields& F, int n, c
   HIPCHK(hipMemcpyAsync(d_slot, h_slot, sizeof(int) * n, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_mode, h_mode, sizeof(int) * n, hipMemcpyHostToDevice, st));
   Batch all{n, d_slot, d_mode};
-  HIPCHK(smgk::mg_norms(L0, all, nullptr, f0, d_partial, d_norm, st));
+  float2* r32 = F.fp32 ? F.f32[0] : nullptr;
+  float2* e32 = F.fp32 ? F.u32[0] : nullptr;
+  HIPCHK(smgk::mg_norms(L0, all, nullptr, f0, d_partial, d_norm, st, r32, e32));
   HIPCHK(hipMemcpyAsync(h_norm, d_norm, sizeof(double) * n, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   std::vector<double> d0(h_norm, h_norm + n), cur(n), thr(n);
@@ -463,7 +519,7 @@ static smg_status mg_solve_planes(const smg_plan& p, const MGFields& F, int n, c
   for (double v : d0) dmax = std::max(dmax, v);
   for (int q = 0; q < n; ++q) thr[q] = tol * std::max(d0[q], floor_factor * dmax);
   if (warm) {
-    HIPCHK(smgk::mg_norms(L0, all, u0, f0, d_partial, d_norm, st));
+    HIPCHK(smgk::mg_norms(L0, all, u0, f0, d_partial, d_norm, st, r32, e32));
     HIPCHK(hipMemcpyAsync(h_norm, d_norm, sizeof(double) * n, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     cur.assign(h_norm, h_norm + n);
@@ -479,10 +535,19 @@ static smg_status mg_solve_planes(const smg_plan& p, const MGFields& F, int n, c
     HIPCHK(hipMemcpyAsync(d_slot, h_slot, sizeof(int) * na, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d_mode, h_mode, sizeof(int) * na, hipMemcpyHostToDevice, st));
     Batch b{na, d_slot, d_mode};
-    STCHK(vcycle(p, F, b, u0, f0, st));
+    if (F.fp32) {
+      // iterative refinement: FP32 correction cycle, FP64 accumulation, FP64
+      // residual (stored rounded to FP32 for the next correction)
+      STCHK(vcycle32(p, F, b, st));
+      int ev = prof_mark(p, st);
+      HIPCHK(smgk::mg_accumulate(L0, b, u0, e32, st));
+      prof_close(p, K_ACCUM, ev, 40.0 * na * plane, st);
+    } else {
+      STCHK(vcycle(p, F, b, u0, f0, st));
+    }
     int ev = prof_mark(p, st);
-    HIPCHK(smgk::mg_norms(L0, b, u0, f0, d_partial, d_norm, st));
-    prof_close(p, K_NORM, ev, 32.0 * na * plane, st);
+    HIPCHK(smgk::mg_norms(L0, b, u0, f0, d_partial, d_norm, st, r32, e32));
+    prof_close(p, K_NORM, ev, (F.fp32 ? 48.0 : 32.0) * na * plane, st);
     HIPCHK(hipMemcpyAsync(h_norm, d_norm, sizeof(double) * na, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     std::vector<int> next;
@@ -775,12 +840,21 @@ extern "C" smg_status smg_plan_setup(smg_plan* p, void* workspace, size_t bytes,
   HIPCHK(hipMemcpyAsync(p->ws + p->w_blob, p->blob.bytes.data(), p->blob.bytes.size(), hipMemcpyHostToDevice, st));
   p->mg.L.clear();
   p->mg.exact = p->opts.line_solver == SMG_LINE_EXACT;
+  p->mg.fp32 = p->opts.precision == SMG_MIXED;
   for (size_t l = 0; l < p->H.lv.size(); ++l) p->mg.L.push_back(level_view(p->ws + p->w_blob, p->loff[l], p->H.lv[l], p->M));
   p->mg.u.assign(p->H.lv.size(), nullptr);
   p->mg.f.assign(p->H.lv.size(), nullptr);
   for (size_t l = 1; l < p->H.lv.size(); ++l) {
     p->mg.u[l] = p->dptr(p->w_u[l]);
     p->mg.f[l] = p->dptr(p->w_fl[l]);
+  }
+  if (p->mg.fp32) {
+    p->mg.u32.assign(p->H.lv.size(), nullptr);
+    p->mg.f32.assign(p->H.lv.size(), nullptr);
+    for (size_t l = 0; l < p->H.lv.size(); ++l) {
+      p->mg.u32[l] = reinterpret_cast<float2*>(p->ws + p->w_u32[l]);
+      p->mg.f32[l] = reinterpret_cast<float2*>(p->ws + p->w_f32[l]);
+    }
   }
   plan_lds(p->mg);
   smg_status s = dgf_method_of(*p) == SMG_DGF_EXTENDED ? dgf_extended(*p, st) : dgf_aux(*p, st);

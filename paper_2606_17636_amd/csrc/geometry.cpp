@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 
 #include "smg_internal.h"
 
@@ -272,6 +273,57 @@ Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, c
     for (int j = 0; j < n2; ++j) sb += B.vol[j + 1];
     for (int i = 0; i < n1; ++i) T.va[i] = A.vol[i + 1] / sa;
     for (int j = 0; j < n2; ++j) T.vb[j] = B.vol[j + 1] / sb;
+  }
+  // exact inverse of the coarsest operator for every mode (Gauss-Jordan with
+  // partial pivoting on the dense n x n matrix, n = na*nb <= kMaxDirect)
+  {
+    LevelTables& T = h.lv[L - 1];
+    const int n1 = T.na, n2 = T.nb, n = n1 * n2;
+    if (n <= kMaxDirect) {
+      T.cinv.assign((size_t)h.M * n * n, 0.0);
+      std::vector<double> A((size_t)n * n), I((size_t)n * n);
+      for (int p = 0; p < h.M; ++p) {
+        std::fill(A.begin(), A.end(), 0.0);
+        std::fill(I.begin(), I.end(), 0.0);
+        const double* Ca = &T.Ca[(size_t)p * n1];
+        const double* Cb = &T.Cb[(size_t)p * n2];
+        for (int i = 0; i < n1; ++i)
+          for (int j = 0; j < n2; ++j) {
+            const int k = i * n2 + j;
+            A[(size_t)k * n + k] = Ca[i] + T.Rr[i] * Cb[j];
+            if (i + 1 < n1) A[(size_t)k * n + k + n2] += T.ua[i];
+            if (i > 0) A[(size_t)k * n + k - n2] += T.da[i];
+            if (j + 1 < n2) A[(size_t)k * n + k + 1] += T.Rr[i] * T.ub[j];
+            if (j > 0) A[(size_t)k * n + k - 1] += T.Rr[i] * T.db[j];
+            I[(size_t)k * n + k] = 1.0;
+          }
+        for (int c = 0; c < n; ++c) {
+          int piv = c;
+          for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[(size_t)r * n + c]) > std::fabs(A[(size_t)piv * n + c])) piv = r;
+          if (piv != c)
+            for (int k = 0; k < n; ++k) {
+              std::swap(A[(size_t)c * n + k], A[(size_t)piv * n + k]);
+              std::swap(I[(size_t)c * n + k], I[(size_t)piv * n + k]);
+            }
+          const double d = 1.0 / A[(size_t)c * n + c];
+          for (int k = 0; k < n; ++k) {
+            A[(size_t)c * n + k] *= d;
+            I[(size_t)c * n + k] *= d;
+          }
+          for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double fct = A[(size_t)r * n + c];
+            if (fct == 0.0) continue;
+            for (int k = 0; k < n; ++k) {
+              A[(size_t)r * n + k] -= fct * A[(size_t)c * n + k];
+              I[(size_t)r * n + k] -= fct * I[(size_t)c * n + k];
+            }
+          }
+        }
+        std::copy(I.begin(), I.end(), T.cinv.begin() + (size_t)p * n * n);
+      }
+    }
   }
   // transfers between consecutive levels (bilinear in (r^2, theta) or (R, z);
   // restriction: the printed area weights read as opposite-corner weights)

@@ -5,7 +5,10 @@
 // memory between levels.  The arithmetic is that of the per-level kernels in
 // mg.hip (same colour order, same transfer weights, same stopping rule of
 // the coarsest solve); only the memory traffic and the launch count differ.
+// Templated on the real type R of the smoothing levels; the coarsest level
+// is always solved in FP64 (the mixed form keeps the coarsest solve in FP64).
 #include "smg_internal.h"
+#include "vec.h"
 
 namespace {
 
@@ -24,35 +27,39 @@ struct Red {
   }
 };
 
-// 1D stencil tables of one level and mode, staged in LDS.
+// 1D stencil tables of one level and mode, staged in LDS (rounded to R).
+template <typename R>
 struct Tab {
-  const double *ua, *da, *R, *Ca, *wb;  // per row i
-  const double *ub, *db, *Cb, *wr;      // per column j
+  const R *ua, *da, *Rr, *Ca, *wb;  // per row i
+  const R *ub, *db, *Cb, *wr;       // per column j
 };
 
-__device__ Tab stage_tab(const LevelDev& L, int m, double* buf) {
+template <typename R>
+__device__ Tab<R> stage_tab(const LevelDev& L, int m, R* buf) {
   const int na = L.na, nb = L.nb;
-  double* t = buf;
+  R* t = buf;
   for (int i = threadIdx.x; i < na; i += blockDim.x) {
-    t[i] = L.ua[i];
-    t[na + i] = L.da[i];
-    t[2 * na + i] = L.Rr[i];
-    t[3 * na + i] = L.Ca[(size_t)m * na + i];
-    t[4 * na + i] = L.wb[(size_t)m * na + i];
+    t[i] = (R)L.ua[i];
+    t[na + i] = (R)L.da[i];
+    t[2 * na + i] = (R)L.Rr[i];
+    t[3 * na + i] = (R)L.Ca[(size_t)m * na + i];
+    t[4 * na + i] = (R)L.wb[(size_t)m * na + i];
   }
-  double* c = buf + 5 * na;
+  R* c = buf + 5 * na;
   for (int j = threadIdx.x; j < nb; j += blockDim.x) {
-    c[j] = L.ub[j];
-    c[nb + j] = L.db[j];
-    c[2 * nb + j] = L.Cb[(size_t)m * nb + j];
-    c[3 * nb + j] = L.wr[(size_t)m * nb + j];
+    c[j] = (R)L.ub[j];
+    c[nb + j] = (R)L.db[j];
+    c[2 * nb + j] = (R)L.Cb[(size_t)m * nb + j];
+    c[3 * nb + j] = (R)L.wr[(size_t)m * nb + j];
   }
-  return Tab{t, t + na, t + 2 * na, t + 3 * na, t + 4 * na, c, c + nb, c + 2 * nb, c + 3 * nb};
+  return Tab<R>{t, t + na, t + 2 * na, t + 3 * na, t + 4 * na, c, c + nb, c + 2 * nb, c + 3 * nb};
 }
 
 // u: padded (na+2) x (nb+2) plane, f: na x nb.
-template <int DIR>
-__device__ void sor_phase(const LevelDev& L, const Tab& T, double2* u, const double2* f, int n_sor) {
+template <int DIR, typename R>
+__device__ void sor_phase(const LevelDev& L, const Tab<R>& T, typename Vec<R>::T* u, const typename Vec<R>::T* f,
+                          int n_sor) {
+  using V = typename Vec<R>::T;
   const int na = L.na, nb = L.nb, nc = nb + 2;
   for (int lc = 0; lc < 2; ++lc) {
     const int nl = DIR == 0 ? (nb - lc + 1) / 2 : (na - lc + 1) / 2;
@@ -70,17 +77,17 @@ __device__ void sor_phase(const LevelDev& L, const Tab& T, double2* u, const dou
             j = pc + 2 * (t % np);
           }
           const int q = (i + 1) * nc + (j + 1);
-          const double R = T.R[i];
-          const double c = T.Ca[i] + R * T.Cb[j];
-          const double w = DIR == 1 ? T.wb[i] : T.wr[j];
-          const double ua = T.ua[i], da = T.da[i], ub = R * T.ub[j], db = R * T.db[j];
-          const double2 un = u[q + nc], us = u[q - nc], ue = u[q + 1], uw = u[q - 1];
-          const double2 fv = f[i * nb + j];
-          const double sx = ua * un.x + da * us.x + ub * ue.x + db * uw.x;
-          const double sy = ua * un.y + da * us.y + ub * ue.y + db * uw.y;
-          const double2 old = u[q];
-          const double tx = (fv.x - sx) / c, ty = (fv.y - sy) / c;
-          u[q] = make_double2(old.x + w * (tx - old.x), old.y + w * (ty - old.y));
+          const R Rr = T.Rr[i];
+          const R c = T.Ca[i] + Rr * T.Cb[j];
+          const R w = DIR == 1 ? T.wb[i] : T.wr[j];
+          const R ua = T.ua[i], da = T.da[i], ub = Rr * T.ub[j], db = Rr * T.db[j];
+          const V un = u[q + nc], us = u[q - nc], ue = u[q + 1], uw = u[q - 1];
+          const V fv = f[i * nb + j];
+          const R sx = ua * un.x + da * us.x + ub * ue.x + db * uw.x;
+          const R sy = ua * un.y + da * us.y + ub * ue.y + db * uw.y;
+          const V old = u[q];
+          const R tx = (fv.x - sx) / c, ty = (fv.y - sy) / c;
+          u[q] = mkv<R>(old.x + w * (tx - old.x), old.y + w * (ty - old.y));
         }
         __syncthreads();
       }
@@ -88,100 +95,112 @@ __device__ void sor_phase(const LevelDev& L, const Tab& T, double2* u, const dou
   }
 }
 
-template <int DIR>
-__device__ void exact_phase(const LevelDev& L, const Tab& T, double2* u, const double2* f, double* cp) {
+template <int DIR, typename R>
+__device__ void exact_phase(const LevelDev& L, const Tab<R>& T, typename Vec<R>::T* u, const typename Vec<R>::T* f,
+                            R* cp) {
+  using V = typename Vec<R>::T;
   const int na = L.na, nb = L.nb, nc = nb + 2;
   const int npts = DIR == 0 ? na : nb;
   for (int lc = 0; lc < 2; ++lc) {
     const int nl = DIR == 0 ? (nb - lc + 1) / 2 : (na - lc + 1) / 2;
     for (int t = threadIdx.x; t < nl; t += blockDim.x) {
       const int line = lc + 2 * t;
-      double* c1 = cp + t * npts;
-      double2 prev = make_double2(0.0, 0.0);
-      double cprev = 0.0;
+      R* c1 = cp + t * npts;
+      V prev = mkv<R>(0, 0);
+      R cprev = 0;
       for (int k = 0; k < npts; ++k) {
         const int i = DIR == 1 ? line : k, j = DIR == 1 ? k : line;
         const int q = (i + 1) * nc + (j + 1);
-        const double R = T.R[i];
-        const double c = T.Ca[i] + R * T.Cb[j];
-        double lo, up, w1, w2;
-        double2 o1, o2;
+        const R Rr = T.Rr[i];
+        const R c = T.Ca[i] + Rr * T.Cb[j];
+        R lo, up, w1, w2;
+        V o1, o2;
         if (DIR == 1) {
-          lo = R * T.db[j]; up = R * T.ub[j];
+          lo = Rr * T.db[j]; up = Rr * T.ub[j];
           o1 = u[q + nc]; o2 = u[q - nc]; w1 = T.ua[i]; w2 = T.da[i];
         } else {
           lo = T.da[i]; up = T.ua[i];
-          o1 = u[q + 1]; o2 = u[q - 1]; w1 = R * T.ub[j]; w2 = R * T.db[j];
+          o1 = u[q + 1]; o2 = u[q - 1]; w1 = Rr * T.ub[j]; w2 = Rr * T.db[j];
         }
-        const double2 fv = f[i * nb + j];
-        const double rx = fv.x - (w1 * o1.x + w2 * o2.x), ry = fv.y - (w1 * o1.y + w2 * o2.y);
-        const double den = c - lo * cprev;
+        const V fv = f[i * nb + j];
+        const R rx = fv.x - (w1 * o1.x + w2 * o2.x), ry = fv.y - (w1 * o1.y + w2 * o2.y);
+        const R den = c - lo * cprev;
         cprev = up / den;
         c1[k] = cprev;
-        prev = make_double2((rx - lo * prev.x) / den, (ry - lo * prev.y) / den);
+        prev = mkv<R>((rx - lo * prev.x) / den, (ry - lo * prev.y) / den);
         u[q] = prev;
       }
       for (int k = npts - 2; k >= 0; --k) {
         const int i = DIR == 1 ? line : k, j = DIR == 1 ? k : line;
         const int q = (i + 1) * nc + (j + 1);
-        const double2 nx = DIR == 1 ? u[q + 1] : u[q + nc];
-        const double2 d = u[q];
-        u[q] = make_double2(d.x - c1[k] * nx.x, d.y - c1[k] * nx.y);
+        const V nx = DIR == 1 ? u[q + 1] : u[q + nc];
+        const V d = u[q];
+        u[q] = mkv<R>(d.x - c1[k] * nx.x, d.y - c1[k] * nx.y);
       }
     }
     __syncthreads();
   }
 }
 
-__device__ void smooth_step(const LevelDev& L, const Tab& T, double2* u, const double2* f, int n_sor, bool exact,
-                            double* cp) {
+template <typename R>
+__device__ void smooth_step(const LevelDev& L, const Tab<R>& T, typename Vec<R>::T* u, const typename Vec<R>::T* f,
+                            int n_sor, bool exact, R* cp) {
   if (exact) {
-    exact_phase<0>(L, T, u, f, cp);
-    exact_phase<1>(L, T, u, f, cp);
+    exact_phase<0, R>(L, T, u, f, cp);
+    exact_phase<1, R>(L, T, u, f, cp);
   } else {
-    sor_phase<0>(L, T, u, f, n_sor);
-    sor_phase<1>(L, T, u, f, n_sor);
+    sor_phase<0, R>(L, T, u, f, n_sor);
+    sor_phase<1, R>(L, T, u, f, n_sor);
   }
 }
 
-__device__ __forceinline__ double2 resid_lds(const LevelDev& L, const Tab& T, const double2* u, const double2* f,
-                                             int i, int j) {
+template <typename R>
+__device__ __forceinline__ typename Vec<R>::T resid_lds(const LevelDev& L, const Tab<R>& T, const typename Vec<R>::T* u,
+                                                        const typename Vec<R>::T* f, int i, int j) {
   const int nb = L.nb, nc = nb + 2;
   const int q = (i + 1) * nc + (j + 1);
-  const double R = T.R[i];
-  const double c = T.Ca[i] + R * T.Cb[j];
-  const double a1 = T.ua[i], a2 = T.da[i], b1 = R * T.ub[j], b2 = R * T.db[j];
-  const double2 un = u[q + nc], us = u[q - nc], ue = u[q + 1], uw = u[q - 1], uc = u[q];
-  const double2 fv = f[i * nb + j];
-  return make_double2(fv.x - (c * uc.x + a1 * un.x + a2 * us.x + b1 * ue.x + b2 * uw.x),
-                      fv.y - (c * uc.y + a1 * un.y + a2 * us.y + b1 * ue.y + b2 * uw.y));
+  const R Rr = T.Rr[i];
+  const R c = T.Ca[i] + Rr * T.Cb[j];
+  const R a1 = T.ua[i], a2 = T.da[i], b1 = Rr * T.ub[j], b2 = Rr * T.db[j];
+  const auto un = u[q + nc], us = u[q - nc], ue = u[q + 1], uw = u[q - 1], uc = u[q];
+  const auto fv = f[i * nb + j];
+  return mkv<R>(fv.x - (c * uc.x + a1 * un.x + a2 * us.x + b1 * ue.x + b2 * uw.x),
+                fv.y - (c * uc.y + a1 * un.y + a2 * us.y + b1 * ue.y + b2 * uw.y));
 }
 
-__global__ void __launch_bounds__(kThreads) k_lds_cycle(LdsLevels LL, Batch bt, const double2* __restrict__ Fg,
-                                                       double2* __restrict__ Ug, int load_u, int nu_pre, int nu_post,
-                                                       int n_sor, int exact, double rtol, int max_sweeps) {
-  extern __shared__ double2 sh[];
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_lds_cycle(LdsLevels LL, Batch bt, const typename Vec<R>::T* __restrict__ Fg,
+                                                       typename Vec<R>::T* __restrict__ Ug, int load_u, int nu_pre,
+                                                       int nu_post, int n_sor, int exact, double rtol, int max_sweeps) {
+  using V = typename Vec<R>::T;
+  extern __shared__ char smem[];
   __shared__ double redbuf[kThreads / 64];
   Red red{redbuf};
   const int p = blockIdx.x;
   const int slot = bt.slot[p], m = bt.mode[p];
   const int n = LL.n;
-  double2* u[kMaxLdsLevels];
-  double2* f[kMaxLdsLevels];
-  {
-    double2* q = sh;
-    for (int l = 0; l < n; ++l) {
-      u[l] = q; q += (LL.L[l].na + 2) * (LL.L[l].nb + 2);
-      f[l] = q; q += LL.L[l].na * LL.L[l].nb;
-    }
+  const int cl = n - 1;  // coarsest level (FP64 storage)
+  // LDS carve-up: [coarsest u, f (double2)] [levels 0..n-2 u, f (V)] [scratch (R)] [tables]
+  const LevelDev& LC = LL.L[cl];
+  double2* uC = reinterpret_cast<double2*>(smem);
+  double2* fC = uC + (LC.na + 2) * (LC.nb + 2);
+  V* u[kMaxLdsLevels];
+  V* f[kMaxLdsLevels];
+  char* q = reinterpret_cast<char*>(fC + LC.na * LC.nb);
+  for (int l = 0; l < cl; ++l) {
+    u[l] = reinterpret_cast<V*>(q); q += sizeof(V) * (LL.L[l].na + 2) * (LL.L[l].nb + 2);
+    f[l] = reinterpret_cast<V*>(q); q += sizeof(V) * LL.L[l].na * LL.L[l].nb;
   }
-  double* cp = reinterpret_cast<double*>(sh + LL.words);  // exact-line scratch
-  Tab tab[kMaxLdsLevels];
+  R* cp = reinterpret_cast<R*>(q);
+  double* tq = reinterpret_cast<double*>(cp + LL.scratch);
+  Tab<double> tabC = stage_tab<double>(LC, m, tq);
+  tq += 5 * LC.na + 4 * LC.nb;
+  Tab<R> tab[kMaxLdsLevels];
   {
-    double* q = cp + LL.scratch;
-    for (int l = 0; l < n; ++l) {
-      tab[l] = stage_tab(LL.L[l], m, q);
-      q += 5 * LL.L[l].na + 4 * LL.L[l].nb;
+    R* tr = reinterpret_cast<R*>(tq);
+    for (int l = 0; l < cl; ++l) {
+      tab[l] = stage_tab<R>(LL.L[l], m, tr);
+      tr += 5 * LL.L[l].na + 4 * LL.L[l].nb;
     }
   }
   // level 0 of the fused range: load f (and u for a full in-LDS cycle)
@@ -189,80 +208,105 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(LdsLevels LL, Batch bt, 
     const LevelDev& L0 = LL.L[0];
     const int na = L0.na, nb = L0.nb, nc = nb + 2;
     const size_t off = (size_t)slot * na * nb;
-    for (int t = threadIdx.x; t < (na + 2) * nc; t += blockDim.x) {
-      const int i = t / nc - 1, j = t % nc - 1;
-      double2 v = make_double2(0.0, 0.0);
-      if (load_u && i >= 0 && i < na && j >= 0 && j < nb) v = Ug[off + (size_t)i * nb + j];
-      u[0][t] = v;
+    if (n > 1) {
+      for (int t = threadIdx.x; t < (na + 2) * nc; t += blockDim.x) {
+        const int i = t / nc - 1, j = t % nc - 1;
+        V v = mkv<R>(0, 0);
+        if (load_u && i >= 0 && i < na && j >= 0 && j < nb) v = Ug[off + (size_t)i * nb + j];
+        u[0][t] = v;
+      }
+      for (int t = threadIdx.x; t < na * nb; t += blockDim.x) f[0][t] = Fg[off + t];
+    } else {
+      for (int t = threadIdx.x; t < na * nb; t += blockDim.x) fC[t] = make_double2(Fg[off + t].x, Fg[off + t].y);
     }
-    for (int t = threadIdx.x; t < na * nb; t += blockDim.x) f[0][t] = Fg[off + t];
   }
   __syncthreads();
   // descend
-  for (int l = 0; l + 1 < n; ++l) {
+  for (int l = 0; l < cl; ++l) {
     const LevelDev& L = LL.L[l];
     const LevelDev& C = LL.L[l + 1];
-    for (int k = 0; k < nu_pre; ++k) smooth_step(L, tab[l], u[l], f[l], n_sor, exact, cp);
+    for (int k = 0; k < nu_pre; ++k) smooth_step<R>(L, tab[l], u[l], f[l], n_sor, exact, cp);
     const int ncc = C.nb + 2;
-    for (int t = threadIdx.x; t < (C.na + 2) * ncc; t += blockDim.x) u[l + 1][t] = make_double2(0.0, 0.0);
+    for (int t = threadIdx.x; t < (C.na + 2) * ncc; t += blockDim.x) {
+      if (l + 1 == cl) uC[t] = make_double2(0.0, 0.0);
+      else u[l + 1][t] = mkv<R>(0, 0);
+    }
     for (int t = threadIdx.x; t < C.na * C.nb; t += blockDim.x) {
       const int I = t / C.nb, J = t - I * C.nb;
-      double ax = 0.0, ay = 0.0;
+      R ax = 0, ay = 0;
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
-          const double w = L.rwa[2 * I + a] * L.rwb[2 * J + b];
-          const double2 r = resid_lds(L, tab[l], u[l], f[l], 2 * I + a, 2 * J + b);
+          const R w = (R)L.rwa[2 * I + a] * (R)L.rwb[2 * J + b];
+          const V r = resid_lds<R>(L, tab[l], u[l], f[l], 2 * I + a, 2 * J + b);
           ax = fma(w, r.x, ax);
           ay = fma(w, r.y, ay);
         }
-      f[l + 1][t] = make_double2(ax, ay);
+      if (l + 1 == cl) fC[t] = make_double2(ax, ay);
+      else f[l + 1][t] = mkv<R>(ax, ay);
     }
     __syncthreads();
   }
-  // coarsest: red-black SOR from zero (the same rule as k_coarse)
+  // coarsest level in FP64: the precomputed inverse when the level is small
+  // (an exact solve), otherwise red-black SOR from zero until the residual
+  // 2-norm dropped by rtol (Sec. 3.3)
   {
-    const LevelDev& L = LL.L[n - 1];
+    const LevelDev& L = LC;
+    const Tab<double>& T = tabC;
     const int na = L.na, nb = L.nb, nc = nb + 2;
-    double2* uu = u[n - 1];
-    const double2* ff = f[n - 1];
-    double f2 = 0.0;
-    for (int t = threadIdx.x; t < na * nb; t += blockDim.x) f2 += ff[t].x * ff[t].x + ff[t].y * ff[t].y;
-    f2 = red.sum(f2);
-    const double w = L.wc[m];
-    if (f2 > 0.0) {
-      for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        for (int colour = 0; colour < 2; ++colour) {
+    for (int t = threadIdx.x; t < (na + 2) * nc; t += blockDim.x) uC[t] = make_double2(0.0, 0.0);
+    __syncthreads();
+    if (L.cinv) {
+      const int nn = na * nb;
+      const double* A = L.cinv + (size_t)m * nn * nn;
+      for (int k = threadIdx.x; k < nn; k += blockDim.x) {
+        double sx = 0.0, sy = 0.0;
+        for (int l = 0; l < nn; ++l) {
+          const double a = A[(size_t)k * nn + l];
+          sx = fma(a, fC[l].x, sx);
+          sy = fma(a, fC[l].y, sy);
+        }
+        const int i = k / nb, j = k - i * nb;
+        uC[(i + 1) * nc + (j + 1)] = make_double2(sx, sy);
+      }
+    } else {
+      double f2 = 0.0;
+      for (int t = threadIdx.x; t < na * nb; t += blockDim.x) f2 += fC[t].x * fC[t].x + fC[t].y * fC[t].y;
+      f2 = red.sum(f2);
+      const double w = L.wc[m];
+      if (f2 > 0.0) {
+        for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+          for (int colour = 0; colour < 2; ++colour) {
+            for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
+              const int i = t / nb, j = t - i * nb;
+              if (((i + j) & 1) != colour) continue;
+              const int qq = (i + 1) * nc + (j + 1);
+              const double Rr = T.Rr[i];
+              const double c = T.Ca[i] + Rr * T.Cb[j];
+              const double a1 = T.ua[i], a2 = T.da[i], b1 = Rr * T.ub[j], b2 = Rr * T.db[j];
+              const double2 un = uC[qq + nc], us = uC[qq - nc], ue = uC[qq + 1], uw = uC[qq - 1];
+              const double2 fv = fC[t];
+              const double tx = (fv.x - (a1 * un.x + a2 * us.x + b1 * ue.x + b2 * uw.x)) / c;
+              const double ty = (fv.y - (a1 * un.y + a2 * us.y + b1 * ue.y + b2 * uw.y)) / c;
+              const double2 old = uC[qq];
+              uC[qq] = make_double2(old.x + w * (tx - old.x), old.y + w * (ty - old.y));
+            }
+            __syncthreads();
+          }
+          double r2 = 0.0;
           for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
             const int i = t / nb, j = t - i * nb;
-            if (((i + j) & 1) != colour) continue;
-            const int q = (i + 1) * nc + (j + 1);
-            const Tab& T = tab[n - 1];
-            const double R = T.R[i];
-            const double c = T.Ca[i] + R * T.Cb[j];
-            const double a1 = T.ua[i], a2 = T.da[i], b1 = R * T.ub[j], b2 = R * T.db[j];
-            const double2 un = uu[q + nc], us = uu[q - nc], ue = uu[q + 1], uw = uu[q - 1];
-            const double2 fv = ff[t];
-            const double tx = (fv.x - (a1 * un.x + a2 * us.x + b1 * ue.x + b2 * uw.x)) / c;
-            const double ty = (fv.y - (a1 * un.y + a2 * us.y + b1 * ue.y + b2 * uw.y)) / c;
-            const double2 old = uu[q];
-            uu[q] = make_double2(old.x + w * (tx - old.x), old.y + w * (ty - old.y));
+            const double2 r = resid_lds<double>(L, T, uC, fC, i, j);
+            r2 += r.x * r.x + r.y * r.y;
           }
-          __syncthreads();
+          r2 = red.sum(r2);
+          if (r2 <= rtol * rtol * f2) break;
         }
-        double r2 = 0.0;
-        for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
-          const int i = t / nb, j = t - i * nb;
-          const double2 r = resid_lds(L, tab[n - 1], uu, ff, i, j);
-          r2 += r.x * r.x + r.y * r.y;
-        }
-        r2 = red.sum(r2);
-        if (r2 <= rtol * rtol * f2) break;
       }
     }
     __syncthreads();
   }
   // ascend
-  for (int l = n - 2; l >= 0; --l) {
+  for (int l = cl - 1; l >= 0; --l) {
     const LevelDev& L = LL.L[l];
     const LevelDev& C = LL.L[l + 1];
     const int nb = L.nb, nc = nb + 2, ncc = C.nb + 2;
@@ -271,21 +315,30 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(LdsLevels LL, Batch bt, 
       const int i = t / nb, j = t - i * nb;
       const int a0 = L.pa_i0[i], a1 = L.pa_i1[i];
       const int b0 = L.pb_i0[par * nb + j], b1 = L.pb_i1[par * nb + j];
-      const double wa0 = L.pa_w0[i], wa1 = L.pa_w1[i];
-      const double wb0 = L.pb_w0[par * nb + j], wb1 = L.pb_w1[par * nb + j];
-      const double2* uc = u[l + 1];
-      const double2 e00 = uc[(a0 + 1) * ncc + b0 + 1], e01 = uc[(a0 + 1) * ncc + b1 + 1];
-      const double2 e10 = uc[(a1 + 1) * ncc + b0 + 1], e11 = uc[(a1 + 1) * ncc + b1 + 1];
-      double ex = 0.0, ey = 0.0;
-      ex = fma(wa0 * wb0, e00.x, ex); ey = fma(wa0 * wb0, e00.y, ey);
-      ex = fma(wa0 * wb1, e01.x, ex); ey = fma(wa0 * wb1, e01.y, ey);
-      ex = fma(wa1 * wb0, e10.x, ex); ey = fma(wa1 * wb0, e10.y, ey);
-      ex = fma(wa1 * wb1, e11.x, ex); ey = fma(wa1 * wb1, e11.y, ey);
-      const int q = (i + 1) * nc + (j + 1);
-      u[l][q] = make_double2(u[l][q].x + ex, u[l][q].y + ey);
+      const R wa0 = (R)L.pa_w0[i], wa1 = (R)L.pa_w1[i];
+      const R wb0 = (R)L.pb_w0[par * nb + j], wb1 = (R)L.pb_w1[par * nb + j];
+      R e00x, e00y, e01x, e01y, e10x, e10y, e11x, e11y;
+      if (l + 1 == cl) {
+        const double2 a = uC[(a0 + 1) * ncc + b0 + 1], b = uC[(a0 + 1) * ncc + b1 + 1];
+        const double2 c = uC[(a1 + 1) * ncc + b0 + 1], d = uC[(a1 + 1) * ncc + b1 + 1];
+        e00x = (R)a.x; e00y = (R)a.y; e01x = (R)b.x; e01y = (R)b.y;
+        e10x = (R)c.x; e10y = (R)c.y; e11x = (R)d.x; e11y = (R)d.y;
+      } else {
+        const V* uc = u[l + 1];
+        const V a = uc[(a0 + 1) * ncc + b0 + 1], b = uc[(a0 + 1) * ncc + b1 + 1];
+        const V c = uc[(a1 + 1) * ncc + b0 + 1], d = uc[(a1 + 1) * ncc + b1 + 1];
+        e00x = a.x; e00y = a.y; e01x = b.x; e01y = b.y; e10x = c.x; e10y = c.y; e11x = d.x; e11y = d.y;
+      }
+      R ex = 0, ey = 0;
+      ex = fma(wa0 * wb0, e00x, ex); ey = fma(wa0 * wb0, e00y, ey);
+      ex = fma(wa0 * wb1, e01x, ex); ey = fma(wa0 * wb1, e01y, ey);
+      ex = fma(wa1 * wb0, e10x, ex); ey = fma(wa1 * wb0, e10y, ey);
+      ex = fma(wa1 * wb1, e11x, ex); ey = fma(wa1 * wb1, e11y, ey);
+      const int qq = (i + 1) * nc + (j + 1);
+      u[l][qq] = mkv<R>(u[l][qq].x + ex, u[l][qq].y + ey);
     }
     __syncthreads();
-    for (int k = 0; k < nu_post; ++k) smooth_step(L, tab[l], u[l], f[l], n_sor, exact, cp);
+    for (int k = 0; k < nu_post; ++k) smooth_step<R>(L, tab[l], u[l], f[l], n_sor, exact, cp);
   }
   {
     const LevelDev& L0 = LL.L[0];
@@ -293,49 +346,68 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(LdsLevels LL, Batch bt, 
     const size_t off = (size_t)slot * na * nb;
     for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
       const int i = t / nb, j = t - i * nb;
-      Ug[off + t] = u[0][(i + 1) * nc + (j + 1)];
+      if (n > 1) {
+        Ug[off + t] = u[0][(i + 1) * nc + (j + 1)];
+      } else {
+        const double2 v = uC[(i + 1) * nc + (j + 1)];
+        Ug[off + t] = mkv<R>((R)v.x, (R)v.y);
+      }
     }
   }
+}
+
+template <typename R>
+size_t cycle_bytes(const LdsLevels& LL) {
+  using V = typename Vec<R>::T;
+  const int cl = LL.n - 1;
+  size_t b = sizeof(double2) * ((size_t)(LL.L[cl].na + 2) * (LL.L[cl].nb + 2) + (size_t)LL.L[cl].na * LL.L[cl].nb);
+  b += sizeof(double) * (5 * (size_t)LL.L[cl].na + 4 * (size_t)LL.L[cl].nb);
+  for (int l = 0; l < cl; ++l) {
+    b += sizeof(V) * ((size_t)(LL.L[l].na + 2) * (LL.L[l].nb + 2) + (size_t)LL.L[l].na * LL.L[l].nb);
+    b += sizeof(R) * (5 * (size_t)LL.L[l].na + 4 * (size_t)LL.L[l].nb);
+  }
+  b += sizeof(R) * (size_t)LL.scratch;
+  return b;
+}
+
+int cycle_threads(const LdsLevels& LL) {
+  // the fused levels are small: few threads make the colour-step barriers cheap
+  const int cells = LL.L[0].na * LL.L[0].nb;
+  return cells >= 2048 ? 256 : (cells >= 512 ? 128 : 64);
 }
 
 }  // namespace
 
 namespace smgk {
 
-size_t lds_cycle_bytes(const LdsLevels& LL, bool exact) {
-  size_t words = 0, scratch = 0, tabs = 0;
-  for (int l = 0; l < LL.n; ++l) {
-    words += (size_t)(LL.L[l].na + 2) * (LL.L[l].nb + 2) + (size_t)LL.L[l].na * LL.L[l].nb;
-    tabs += 5 * (size_t)LL.L[l].na + 4 * (size_t)LL.L[l].nb;
-    if (exact) {
-      const size_t a = (size_t)((LL.L[l].nb + 1) / 2) * LL.L[l].na;
-      const size_t b = (size_t)((LL.L[l].na + 1) / 2) * LL.L[l].nb;
-      scratch = scratch > a ? scratch : a;
-      scratch = scratch > b ? scratch : b;
-    }
-  }
-  return words * sizeof(double2) + (scratch + tabs) * sizeof(double);
-}
-
 int lds_cycle_scratch(const LdsLevels& LL, bool exact) {
   size_t scratch = 0;
   if (exact)
-    for (int l = 0; l < LL.n; ++l) {
+    for (int l = 0; l + 1 < LL.n; ++l) {
       const size_t a = (size_t)((LL.L[l].nb + 1) / 2) * LL.L[l].na;
       const size_t b = (size_t)((LL.L[l].na + 1) / 2) * LL.L[l].nb;
       scratch = scratch > a ? scratch : a;
       scratch = scratch > b ? scratch : b;
     }
-  return (int)scratch;
+  return (int)((scratch + 1) / 2 * 2);  // even: keeps the FP64 tables that follow 8-byte aligned
+}
+
+size_t lds_cycle_bytes(const LdsLevels& LL, bool fp32) {
+  return fp32 ? cycle_bytes<float>(LL) : cycle_bytes<double>(LL);
 }
 
 hipError_t mg_lds_cycle(const LdsLevels& LL, const Batch& b, const double2* f, double2* u, bool load_u, int nu_pre,
                         int nu_post, int n_sor, bool exact, double rtol, int max_sweeps, hipStream_t st) {
   if (b.n == 0) return hipSuccess;
-  // the fused levels are small: a single wavefront per plane makes every
-  // colour-step barrier nearly free
-  const int threads = LL.L[0].na * LL.L[0].nb >= 2048 ? 256 : (LL.L[0].na * LL.L[0].nb >= 512 ? 128 : 64);
-  hipLaunchKernelGGL(k_lds_cycle, dim3(b.n), dim3(threads), lds_cycle_bytes(LL, exact), st, LL, b, f, u,
+  hipLaunchKernelGGL(k_lds_cycle<double>, dim3(b.n), dim3(cycle_threads(LL)), cycle_bytes<double>(LL), st, LL, b, f, u,
+                     load_u ? 1 : 0, nu_pre, nu_post, n_sor, exact ? 1 : 0, rtol, max_sweeps);
+  return hipGetLastError();
+}
+
+hipError_t mg_lds_cycle32(const LdsLevels& LL, const Batch& b, const float2* f, float2* u, bool load_u, int nu_pre,
+                          int nu_post, int n_sor, bool exact, double rtol, int max_sweeps, hipStream_t st) {
+  if (b.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lds_cycle<float>, dim3(b.n), dim3(cycle_threads(LL)), cycle_bytes<float>(LL), st, LL, b, f, u,
                      load_u ? 1 : 0, nu_pre, nu_post, n_sor, exact ? 1 : 0, rtol, max_sweeps);
   return hipGetLastError();
 }

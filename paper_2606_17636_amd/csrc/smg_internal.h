@@ -57,6 +57,7 @@ struct LevelTables {
   std::vector<double> Ca, Cb;   // [M][na], [M][nb]; diag c = Ca[i] + Rr[i] * Cb[j]
   std::vector<double> wr, wb;   // [M][nb] radial-line omega, [M][na] polar-line omega
   std::vector<double> wc;       // [M] coarsest red-black omega
+  std::vector<double> cinv;     // [M][n][n] inverse of the coarsest operator (n = na*nb <= kMaxDirect), else empty
   std::vector<double> va, vb;   // normalised volume weights (sum_ij va_i vb_j = 1)
   // restriction to the next coarser level: [nc][2]
   std::vector<double> rwa, rwb;
@@ -80,6 +81,10 @@ struct Hierarchy {
 // the per-mode tables = position in the list).
 Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, const int edge[4],
                           const std::vector<int>& modes, bool main_grid);
+
+// Coarsest levels up to this many cells are solved with a precomputed
+// inverse instead of red-black SOR.
+constexpr int kMaxDirect = 128;
 
 double mode_s2(int n_phi, int m);
 double kappa(int kind, int m);
@@ -116,6 +121,7 @@ struct LevelDev {
   const double *pa_w0, *pa_w1;
   const int *pb_i0, *pb_i1;  // [2][nb]
   const double *pb_w0, *pb_w1;
+  const double* cinv;        // [M][na*nb][na*nb] coarsest inverse, or nullptr
 };
 
 // The levels that one block per plane processes entirely in LDS (the
@@ -147,18 +153,31 @@ hipError_t mg_smooth(const LevelDev& L, const Batch& b, double2* u, const double
                      hipStream_t st);
 hipError_t mg_smooth_dir(const LevelDev& L, const Batch& b, double2* u, const double2* f, int n_sor, bool exact,
                          int dir, hipStream_t st);
+hipError_t mg_smooth_dir32(const LevelDev& L, const Batch& b, float2* u, const float2* f, int n_sor, bool exact,
+                           int dir, hipStream_t st);
+hipError_t mg_restrict_residual32(const LevelDev& L, const LevelDev& C, const Batch& b, const float2* u,
+                                  const float2* f, float2* fc, float2* uc, hipStream_t st);
+hipError_t mg_prolong_add32(const LevelDev& L, const LevelDev& C, const Batch& b, float2* u, const float2* uc,
+                            hipStream_t st);
+hipError_t mg_accumulate(const LevelDev& L, const Batch& b, double2* u, const float2* e, hipStream_t st);
+hipError_t mg_lds_cycle32(const LdsLevels& LL, const Batch& b, const float2* f, float2* u, bool load_u, int nu_pre,
+                          int nu_post, int n_sor, bool exact, double rtol, int max_sweeps, hipStream_t st);
 hipError_t mg_residual(const LevelDev& L, const Batch& b, const double2* u, const double2* f,
                        double2* r, hipStream_t st);
 hipError_t mg_restrict_residual(const LevelDev& L, const LevelDev& Lc, const Batch& b, const double2* u,
                                 const double2* f, double2* fc, double2* uc, hipStream_t st);
 hipError_t mg_prolong_add(const LevelDev& L, const LevelDev& Lc, const Batch& b, double2* u,
                           const double2* uc, hipStream_t st);
-size_t lds_cycle_bytes(const LdsLevels& LL, bool exact);
+size_t lds_cycle_bytes(const LdsLevels& LL, bool fp32);
 int lds_cycle_scratch(const LdsLevels& LL, bool exact);
 hipError_t mg_lds_cycle(const LdsLevels& LL, const Batch& b, const double2* f, double2* u, bool load_u, int nu_pre,
                         int nu_post, int n_sor, bool exact, double rtol, int max_sweeps, hipStream_t st);
+// Volume-weighted defect norms; with r32 != nullptr the FP64 residual is
+// also stored rounded to FP32 (the mixed form's correction right-hand side)
+// and the FP32 correction e32 is zeroed.
 hipError_t mg_norms(const LevelDev& L, const Batch& b, const double2* u, const double2* f,
-                    double* partial, double* out, hipStream_t st);
+                    double* partial, double* out, hipStream_t st, float2* r32 = nullptr,
+                    float2* e32 = nullptr);
 hipError_t fill_zero(double2* p, size_t n, hipStream_t st);
 // James boundary (james.hip)
 hipError_t james_screen(const int* adj, const double* coup, int n_g, int plane, int M,
