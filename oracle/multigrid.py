@@ -20,12 +20,20 @@ opposite-corner area weights.  For restriction the printed weight S_ij
 multiplies the fine point it is measured from; the default here reads it as
 the opposite-corner (bilinear) weight like the prolongation, the literal
 reading is available with ``restriction="literal"``.  Coarse ghosts in the
-prolongation follow the homogeneous boundary condition of the error (zero at
-Dirichlet edges, (-1)^m mirror at poles).
+prolongation follow the homogeneous boundary condition of the error as the
+coarse operator states it ((-1)^m mirror at poles, kappa_c at Dirichlet
+edges, below).
 
 Coarsening: factor two in both directions while both sides are even, the
 smaller coarse side stays >= 2 and the coarse inner radial ghost face stays
-at r > 0; the coarse operator is rediscretised on the coarse faces.
+at r > 0; the coarse operator is rediscretised on the coarse faces.  The
+paper leaves the coarse boundary closure open; here the error vanishes on
+every level at the point where the problem grid puts it (the finest ghost
+centre), not at the coarse ghost centre: a coarse Dirichlet ghost is
+kappa_c times the adjacent coarse cell, with kappa_c from linear
+interpolation through that point (coarse_dirichlet_kappa).  Only the
+convergence rate depends on this (the finest operator is unchanged); it
+takes m = 0 of the log-radial 128x64 sphere from 20 to 12 V-cycles.
 
 Stopping rule (reading of the 1e-8 tolerance, Sec. 6 and Appendix B): mode m
 is converged when ||D^m||_V <= tol * max(||D^m_0||_V, 1e-6 max_m' ||D^m'_0||_V)
@@ -36,7 +44,7 @@ import numpy as np
 
 from .geometry import SPH, Axis1D, radial_face
 from .omega import omega_1d, omega_2d
-from .operator import PlaneOperator, kappa, main_edges
+from .operator import PlaneOperator, main_edges
 
 FLOOR = 1e-6
 
@@ -55,6 +63,19 @@ def level_sizes(spec):
     return sizes
 
 
+def coarse_dirichlet_kappa(fine0: Axis1D, coarse: Axis1D):
+    """(kappa_lo, kappa_hi) of a coarse level's Dirichlet edges along one
+    axis: the coarse ghost value g = kappa * (first coarse cell) that makes
+    the straight line through the coarse ghost and first cell centres vanish
+    at the finest level's ghost centre."""
+    xg, x0, x1 = fine0.cent[0], coarse.cent[0], coarse.cent[1]
+    k_lo = -(xg - x0) / (x1 - xg)
+    n0, nc = fine0.n, coarse.n
+    xg, xn1, xn = fine0.cent[n0 + 1], coarse.cent[nc + 1], coarse.cent[nc]
+    k_hi = -(xn1 - xg) / (xg - xn)
+    return k_lo, k_hi
+
+
 class MGLevel:
     def __init__(self, spec, level):
         s = 2 ** level
@@ -63,7 +84,11 @@ class MGLevel:
         A = Axis1D(spec, "a", 1, spec.n_a // s, s)
         B = Axis1D(spec, "b", 1, spec.n_b // s, s)
         self.A, self.B = A, B
-        self.op = PlaneOperator(spec, A, B, main_edges(spec))
+        dk = {}
+        if level > 0:
+            dk["a_lo"], dk["a_hi"] = coarse_dirichlet_kappa(Axis1D(spec, "a", 1, spec.n_a, 1), A)
+            dk["b_lo"], dk["b_hi"] = coarse_dirichlet_kappa(Axis1D(spec, "b", 1, spec.n_b, 1), B)
+        self.op = PlaneOperator(spec, A, B, main_edges(spec), dk)
         self.n_a, self.n_b = A.n, B.n
         self.ua, self.da, self.ub, self.db = self.op.coupling_arrays()
         self.R = self.op.R
@@ -266,11 +291,9 @@ class Hierarchy:
         key = (l, m % 2)
         if key not in self._pcache:
             f, c = self.levels[l], self.levels[l + 1]
-            ed = main_edges(self.spec)
-            Pa = prolongation_matrix_1d(f.A, c.A, self.spec.geometry, "a",
-                                        kappa(ed["a_lo"], m), kappa(ed["a_hi"], m))
-            Pb = prolongation_matrix_1d(f.B, c.B, self.spec.geometry, "b",
-                                        kappa(ed["b_lo"], m), kappa(ed["b_hi"], m))
+            k = c.op.kappa
+            Pa = prolongation_matrix_1d(f.A, c.A, self.spec.geometry, "a", k("a_lo", m), k("a_hi", m))
+            Pb = prolongation_matrix_1d(f.B, c.B, self.spec.geometry, "b", k("b_lo", m), k("b_hi", m))
             self._pcache[key] = (Pa, Pb)
         Pa, Pb = self._pcache[key]
         return Pa @ e @ Pb.T

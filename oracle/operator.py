@@ -48,9 +48,12 @@ def kappa(kind, m):
 class PlaneOperator:
     """L_m on a rectangle of cells described by two Axis1D objects."""
 
-    def __init__(self, spec, A: Axis1D, B: Axis1D, edges):
+    def __init__(self, spec, A: Axis1D, B: Axis1D, edges, dirichlet_kappa=None):
         self.spec, self.A, self.B = spec, A, B
         self.edges = dict(edges)
+        # ghost factor of Dirichlet edges (0 unless a coarse multigrid level
+        # moves its homogeneous condition off the ghost centre)
+        self.dk = dict(dirichlet_kappa or {})
         self.n_a, self.n_b = A.n, B.n
         self.up_a, self.dn_a = A.interior_couplings()
         self.up_b, self.dn_b = B.interior_couplings()
@@ -71,6 +74,12 @@ class PlaneOperator:
         db[0] = 0.0
         return ua, da, ub, db
 
+    def kappa(self, edge, m):
+        """Ghost = kappa * adjacent interior value on `edge` for mode m."""
+        if self.edges[edge] == DIRICHLET:
+            return self.dk.get(edge, 0.0)
+        return kappa(self.edges[edge], m)
+
     def diag(self, m):
         """Diagonal c_ij of L_m with the kappa-ghosts folded in."""
         s2 = float(mode_s2(self.spec.n_phi, m))
@@ -81,12 +90,12 @@ class PlaneOperator:
             # so the ghost centroid (possibly at r <= 0) is never used.
             dn_a[0] = 0.0
         else:
-            dn_a[0] = self.dn_a[0] * (1.0 - kappa(self.edges["a_lo"], m))
+            dn_a[0] = self.dn_a[0] * (1.0 - self.kappa("a_lo", m))
         ca = -(self.up_a + dn_a)
-        ca[-1] += kappa(self.edges["a_hi"], m) * self.up_a[-1]
+        ca[-1] += self.kappa("a_hi", m) * self.up_a[-1]
         cb = -(self.up_b + self.dn_b)
-        cb[0] += kappa(self.edges["b_lo"], m) * self.dn_b[0]
-        cb[-1] += kappa(self.edges["b_hi"], m) * self.up_b[-1]
+        cb[0] += self.kappa("b_lo", m) * self.dn_b[0]
+        cb[-1] += self.kappa("b_hi", m) * self.up_b[-1]
         c = ca[:, None] + R * cb[None, :] - s2 * self.Pa[:, None] * self.Pb[None, :]
         return c
 

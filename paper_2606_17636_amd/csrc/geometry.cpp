@@ -9,7 +9,10 @@
 // operator diagonal is split as c_ij = Ca[m][i] + Rr[i] * Cb[m][j]; ghost
 // couplings are removed from the off-diagonals and ghosts that are a fixed
 // multiple kappa of the adjacent cell (pole parity (-1)^m, Neumann +1) are
-// folded into the diagonal.
+// folded into the diagonal.  On coarse multigrid levels a Dirichlet ghost is
+// such a multiple too: the homogeneous error condition stays at the finest
+// level's ghost centre, so the coarse ghost is the value that the straight
+// line through it and the first coarse centre takes there.
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -197,6 +200,18 @@ Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, c
     T.A = make_axis(s, 'a', a_lo - 1, st, T.na);
     T.B = make_axis(s, 'b', b_lo - 1, st, T.nb);
     const Axis &A = T.A, &B = T.B;
+    for (int e = 0; e < 4; ++e) T.dk[e] = 0.0;
+    if (l > 0) {
+      for (int ax = 0; ax < 2; ++ax) {
+        const Axis& f0 = ax ? h.lv[0].B : h.lv[0].A;
+        const Axis& c = ax ? B : A;
+        double xg = f0.cent[0];
+        T.dk[2 * ax] = -(xg - c.cent[0]) / (c.cent[1] - xg);
+        xg = f0.cent[f0.n + 1];
+        T.dk[2 * ax + 1] = -(c.cent[c.n + 1] - xg) / (xg - c.cent[c.n]);
+      }
+    }
+    auto kap = [&](int e, int m) { return edge[e] == EDGE_DIRICHLET ? T.dk[e] : kappa(edge[e], m); };
     int n1 = T.na, n2 = T.nb;
     T.ua.resize(n1); T.da.resize(n1); T.Rr.resize(n1);
     T.ub.resize(n2); T.db.resize(n2);
@@ -222,15 +237,15 @@ Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, c
       double* Cb = &T.Cb[(size_t)p * n2];
       for (int i = 0; i < n1; ++i) {
         double dn = A.dn[i + 1];
-        if (i == 0) dn = (edge[0] == EDGE_NEUMANN) ? 0.0 : dn * (1.0 - kappa(edge[0], m));
+        if (i == 0) dn = (edge[0] == EDGE_NEUMANN) ? 0.0 : dn * (1.0 - kap(0, m));
         Ca[i] = -(A.up[i + 1] + dn);
-        if (i == n1 - 1) Ca[i] += kappa(edge[1], m) * A.up[i + 1];
+        if (i == n1 - 1) Ca[i] += kap(1, m) * A.up[i + 1];
         if (!s.sph()) Ca[i] -= s2 * A.P[i + 1];
       }
       for (int j = 0; j < n2; ++j) {
         Cb[j] = -(B.up[j + 1] + B.dn[j + 1]);
-        if (j == 0) Cb[j] += kappa(edge[2], m) * B.dn[1];
-        if (j == n2 - 1) Cb[j] += kappa(edge[3], m) * B.up[n2];
+        if (j == 0) Cb[j] += kap(2, m) * B.dn[1];
+        if (j == n2 - 1) Cb[j] += kap(3, m) * B.up[n2];
         if (s.sph()) Cb[j] -= s2 * B.P[j + 1];
       }
       // WKB omegas: radial line j (points i), polar line i (points j)
@@ -344,8 +359,9 @@ Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, c
         rw[2 * (I - 1) + 1] = std::fabs(X - xl) / std::fabs(xh - xl);
       }
       for (int par = 0; par < (ax ? 2 : 1); ++par) {
-        double k_lo = kappa(edge[ax ? 2 : 0], par);
-        double k_hi = kappa(edge[ax ? 3 : 1], par);
+        const int elo = ax ? 2 : 0, ehi = ax ? 3 : 1;
+        double k_lo = edge[elo] == EDGE_DIRICHLET ? C.dk[elo] : kappa(edge[elo], par);
+        double k_hi = edge[ehi] == EDGE_DIRICHLET ? C.dk[ehi] : kappa(edge[ehi], par);
         std::vector<int> i0(nf), i1(nf);
         std::vector<double> w0(nf), w1(nf);
         for (int k = 1; k <= nf; ++k) {

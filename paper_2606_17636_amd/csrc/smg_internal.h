@@ -51,6 +51,7 @@ Axis make_axis(const Spec& s, char which, long off, long stride, int n);
 struct LevelTables {
   int na, nb;
   int edge[4];  // a_lo, a_hi, b_lo, b_hi
+  double dk[4]; // ghost factor of Dirichlet edges (0 on the finest level)
   Axis A, B;
   // interior arrays (length na or nb), ghost couplings removed
   std::vector<double> ua, da, Rr, ub, db;
