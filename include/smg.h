@@ -91,7 +91,23 @@ typedef struct {
                             DGF extended-domain solves always use exact
                             lines (their radial cells reach aspect ratios
                             of 1e3 and more). */
+  int launch;            /* SMG_LAUNCH_GRAPH [default]: after the first solve
+                            of a kind (zero or warm start) every V-cycle of a
+                            solve is scheduled from the previous solve's
+                            per-mode cycle counts, the whole body (both
+                            multigrid solves and the boundary steps) replays
+                            as one captured HIP graph, and the host
+                            synchronises once per solve; modes that still
+                            miss the tolerance are finished afterwards.
+                            SMG_LAUNCH_DYNAMIC: the host reads the number of
+                            unconverged modes after every V-cycle (no graph). */
+  int autotune;          /* 1: at setup, time V-cycles under candidate launch
+                            shapes (where the in-LDS coarse cycle starts,
+                            smoother blocks per launch) for 2, 8, 32 and all
+                            planes, and keep the fastest [0: built-in rule] */
 } smg_opts;
+
+enum { SMG_LAUNCH_GRAPH = 0, SMG_LAUNCH_DYNAMIC = 1 };
 
 /* Per-solve report.  Arrays are caller-owned host buffers of length
  * n_modes = n_phi/2 + 1 (any may be NULL). */
@@ -125,7 +141,9 @@ size_t smg_workspace_bytes(const smg_plan *plan);
 /* Bind the caller's workspace (>= smg_workspace_bytes, 256-byte aligned),
  * upload the tables and compute the discrete Green's function tables of
  * Sec. 4.2 on the device (one-time, not part of a solve).  Temporary device
- * memory of the DGF computation is allocated and freed inside this call. */
+ * memory of the DGF computation is allocated and freed inside this call;
+ * with opts.autotune the launch shapes are tuned here.  The plan owns the
+ * HIP graphs of later solves and a private stream they are captured on. */
 smg_status smg_plan_setup(smg_plan *plan, void *workspace_dev, size_t workspace_bytes, void *stream);
 
 /* The seven-step workflow of Sec. 5.1: rho_dev -> phi_dev, both
@@ -173,7 +191,10 @@ smg_status smg_fft_inverse(smg_plan *plan, const double *modes_dev, double *phi_
 smg_status smg_mg_solve(smg_plan *plan, const double *f_dev, double *u_dev, double rel_tol,
                         void *stream, int *cycles_host, double *resid_host);
 
-/* One V-cycle on every mode (no convergence test). */
+/* One V-cycle on every mode (no convergence test).  This and the next two
+ * entry points need an FP64 plan (SMG_EINVAL otherwise).  The step entry
+ * points work on copies in the plan's own arrays, so the next smg_solve does
+ * not warm-start. */
 smg_status smg_mg_vcycle(smg_plan *plan, const double *f_dev, double *u_dev, void *stream);
 
 /* One smoothing step (radial-line phase then polar-line phase, Algorithm 1)
@@ -216,6 +237,11 @@ typedef struct {
 
 smg_status smg_profile_begin(smg_plan *plan);
 smg_status smg_profile_end(smg_plan *plan, smg_kernel_stat *stats, int max_stats, int *n_stats);
+
+/* Text report of the setup-time autotuner (opts.autotune = 1): the timed
+ * candidates and the configuration kept per planes bucket.  Owned by the
+ * plan; empty when the autotuner did not run. */
+const char *smg_tune_report(const smg_plan *plan);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "dgf_dev.h"
+#include "engine.h"
 #include "smg_internal.h"
 
 using namespace smg;
@@ -41,7 +42,6 @@ namespace {
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr size_t kAlign = 256;
-constexpr int kNormBlocks = 64;
 constexpr double kFloor = 1e-6;          // stopping-rule floor factor
 constexpr double kCoarseRtol = 1e-10;    // coarsest red-black SOR
 constexpr int kCoarseSweeps = 1000;
@@ -107,44 +107,26 @@ LevelDev level_view(const char* base, const LevelOff& o, const LevelTables& T, i
   return L;
 }
 
-// Fields of one multigrid run: level 0 is supplied per call, coarser levels
-// hold `cap` planes each.
-struct MGFields {
-  std::vector<LevelDev> L;
-  std::vector<double2*> u, f;  // index 0 unused
-  bool exact = false;          // exact (Thomas) line relaxation
-  bool fp32 = false;           // mixed form: FP32 correction cycles
-  std::vector<float2*> u32, f32;  // FP32 correction / right-hand side per level (mixed form)
-  int lds_first = 0;           // first level of the in-LDS coarse cycle
-  LdsLevels lds{};
+}  // namespace
+
+struct smg_plan;
+
+namespace {
+// Routes the engine's per-launch timing marks to the plan's event pool.
+struct PlanProf : ProfSink {
+  const smg_plan* p = nullptr;
+  int mark(hipStream_t st) override;
+  void close(int cls, int ev, double bytes, hipStream_t st) override;
 };
 
-constexpr size_t kLdsCycleMax = 63 * 1024;  // leaves room for the static reduction buffer
-
-// Choose the deepest run of levels (ending at the coarsest) that one block
-// can hold in LDS, starting as fine as possible.
-void plan_lds(MGFields& F) {
-  const int L = (int)F.L.size();
-  for (int first = 0; first < L; ++first) {
-    if (L - first > kMaxLdsLevels) continue;
-    LdsLevels LL{};
-    LL.n = L - first;
-    int words = 0;
-    for (int l = first; l < L; ++l) {
-      LL.L[l - first] = F.L[l];
-      words += (F.L[l].na + 2) * (F.L[l].nb + 2) + F.L[l].na * F.L[l].nb;
-    }
-    LL.words = words;
-    LL.scratch = smgk::lds_cycle_scratch(LL, F.exact);
-    if (smgk::lds_cycle_bytes(LL, F.fp32) <= kLdsCycleMax) {
-      F.lds_first = first;
-      F.lds = LL;
-      return;
-    }
-  }
-  F.lds_first = L - 1;
-}
-
+// A captured solve body (both multigrid solves and the boundary steps) for
+// one per-cycle schedule.
+struct GraphEnt {
+  std::vector<int> key;
+  hipGraphExec_t exec = nullptr;
+  unsigned long long used = 0;
+};
+constexpr int kMaxGraphs = 8;
 }  // namespace
 
 struct smg_plan {
@@ -161,30 +143,40 @@ struct smg_plan {
   std::vector<LevelOff> loff;
   size_t o_tw = 0, o_adj = 0, o_cout = 0, o_apc = 0, o_apg0 = 0, o_apg1 = 0, o_apc0 = 0, o_apc1 = 0;
   // workspace layout (byte offsets)
-  size_t w_blob = 0, w_dgf = 0, w_psi = 0, w_phi = 0, w_f = 0, w_sigma = 0, w_theta = 0, w_partial = 0,
-         w_norm = 0, w_slot = 0, w_mode = 0, w_total = 0;
+  size_t w_blob = 0, w_dgf = 0, w_psi = 0, w_phi = 0, w_f = 0, w_f2 = 0, w_sigma = 0, w_theta = 0, w_eng = 0, w_eng_bytes = 0,
+         w_total = 0;
   std::vector<size_t> w_u, w_fl, w_u32, w_f32;
   // bound workspace
   char* ws = nullptr;
   bool ready = false;
   bool have_prev = false;
   double dgf_resid = 0.0;  // worst relative residual of the DGF solves
-  MGFields mg;
+  std::vector<LevelDev> levels;
+  Engine eng;               // targets: 0 = Psi (solve 1), 1 = Phi (solve 2)
+  std::string tune_report;
+  // per-mode cycle counts of the last solve, per initial-guess kind
+  // (0 zero, 1 warm) and target: the schedule of the next solve
+  std::vector<int> hist[2][2];
+  bool hist_ok[2] = {false, false};
+  std::vector<GraphEnt> graphs;
+  unsigned long long graph_clock = 0;
+  hipStream_t cap_stream = nullptr;  // private stream the solve graphs are captured on
   // per-launch event timing (smg_profile_begin / smg_profile_end)
   struct ProfRec { int cls, ev0, ev1; double bytes; };
   mutable bool prof_on = false;
   mutable std::vector<hipEvent_t> prof_pool;
   mutable size_t prof_used = 0;
   mutable std::vector<ProfRec> prof_log;
-  // pinned host staging
-  int* h_slot = nullptr;
-  int* h_mode = nullptr;
-  double* h_norm = nullptr;
+  PlanProf prof_sink;
+  void drop_graphs() {
+    for (GraphEnt& g : graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  }
   ~smg_plan() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
-    if (h_slot) (void)hipHostFree(h_slot);
-    if (h_mode) (void)hipHostFree(h_mode);
-    if (h_norm) (void)hipHostFree(h_norm);
   }
   double2* dptr(size_t off) const { return reinterpret_cast<double2*>(ws + off); }
 };
@@ -314,12 +306,11 @@ extern "C" smg_status smg_plan_create(const smg_grid* grid, const smg_opts* opts
   p->w_psi = take(sizeof(double2) * M * plane);
   p->w_phi = take(sizeof(double2) * M * plane);
   p->w_f = take(sizeof(double2) * M * plane);
+  p->w_f2 = take(sizeof(double2) * M * plane);
   p->w_sigma = take(sizeof(double2) * (size_t)M * p->n_g);
   p->w_theta = take(sizeof(double2) * (size_t)M * p->n_g);
-  p->w_partial = take(sizeof(double) * (size_t)M * kNormBlocks);
-  p->w_norm = take(sizeof(double) * M);
-  p->w_slot = take(sizeof(int) * M);
-  p->w_mode = take(sizeof(int) * M);
+  p->w_eng_bytes = Engine::region_bytes(2, 1, (int)p->H.lv.size(), M);
+  p->w_eng = take(p->w_eng_bytes);
   p->w_u.assign(p->H.lv.size(), 0);
   p->w_fl.assign(p->H.lv.size(), 0);
   for (size_t l = 1; l < p->H.lv.size(); ++l) {
@@ -404,167 +395,12 @@ static void prof_close(const smg_plan& p, int cls, int ev0, double bytes, hipStr
   if (ev1 >= 0) p.prof_log.push_back({cls, ev0, ev1, bytes});
 }
 
-// ----------------------------------------------------------------------------
-// multigrid driver
-// ----------------------------------------------------------------------------
-static smg_status vcycle(const smg_plan& p, const MGFields& F, const Batch& b, double2* u0, const double2* f0,
-                         hipStream_t st) {
-  const int L = (int)F.L.size();
-  std::vector<double2*> u(L);
-  std::vector<const double2*> f(L);
-  u[0] = u0;
-  f[0] = f0;
-  for (int l = 1; l < L; ++l) { u[l] = F.u[l]; f[l] = F.f[l]; }
-  auto cells = [&](int l) { return (double)b.n * F.L[l].na * F.L[l].nb; };
-  auto smooth = [&](int l) -> smg_status {
-    for (int dir = 0; dir < 2; ++dir) {
-      int ev = prof_mark(p, st);
-      HIPCHK(smgk::mg_smooth_dir(F.L[l], b, u[l], f[l], p.opts.n_sor, F.exact, dir, st));
-      prof_close(p, l == 0 ? (dir == 0 ? K_SMOOTH_RADIAL0 : K_SMOOTH_POLAR0) : K_SMOOTH_COARSE, ev,
-                 48.0 * cells(l), st);
-    }
-    return SMG_OK;
-  };
-  const int first = F.lds_first;
-  for (int l = 0; l < first; ++l) {
-    for (int k = 0; k < p.opts.nu_pre; ++k) STCHK(smooth(l));
-    int ev = prof_mark(p, st);
-    HIPCHK(smgk::mg_restrict_residual(F.L[l], F.L[l + 1], b, u[l], f[l], F.f[l + 1], F.u[l + 1], st));
-    prof_close(p, K_RESTRICT, ev, 40.0 * cells(l), st);
-  }
-  {
-    int ev = prof_mark(p, st);
-    HIPCHK(smgk::mg_lds_cycle(F.lds, b, f[first], u[first], first == 0, p.opts.nu_pre, p.opts.nu_post, p.opts.n_sor,
-                              F.exact, kCoarseRtol, kCoarseSweeps, st));
-    prof_close(p, K_COARSE, ev, 32.0 * cells(first), st);
-  }
-  for (int l = first - 1; l >= 0; --l) {
-    int ev = prof_mark(p, st);
-    HIPCHK(smgk::mg_prolong_add(F.L[l], F.L[l + 1], b, u[l], u[l + 1], st));
-    prof_close(p, K_PROLONG, ev, 36.0 * cells(l), st);
-    for (int k = 0; k < p.opts.nu_post; ++k) STCHK(smooth(l));
-  }
-  return SMG_OK;
-}
+int PlanProf::mark(hipStream_t st) { return prof_mark(*p, st); }
 
-// One FP32 correction V-cycle of the mixed form: solves L e = r on level 0
-// (F.u32[0] = e, zero on entry; F.f32[0] = r) with FP32 smoothing and
-// transfers and the FP64 coarsest solve.
-static smg_status vcycle32(const smg_plan& p, const MGFields& F, const Batch& b, hipStream_t st) {
-  const int L = (int)F.L.size();
-  auto cells = [&](int l) { return (double)b.n * F.L[l].na * F.L[l].nb; };
-  auto smooth = [&](int l) -> smg_status {
-    for (int dir = 0; dir < 2; ++dir) {
-      int ev = prof_mark(p, st);
-      HIPCHK(smgk::mg_smooth_dir32(F.L[l], b, F.u32[l], F.f32[l], p.opts.n_sor, F.exact, dir, st));
-      prof_close(p, l == 0 ? (dir == 0 ? K_SMOOTH_RADIAL0 : K_SMOOTH_POLAR0) : K_SMOOTH_COARSE, ev,
-                 24.0 * cells(l), st);
-    }
-    return SMG_OK;
-  };
-  const int first = F.lds_first;
-  for (int l = 0; l < first; ++l) {
-    for (int k = 0; k < p.opts.nu_pre; ++k) STCHK(smooth(l));
-    int ev = prof_mark(p, st);
-    HIPCHK(smgk::mg_restrict_residual32(F.L[l], F.L[l + 1], b, F.u32[l], F.f32[l], F.f32[l + 1], F.u32[l + 1], st));
-    prof_close(p, K_RESTRICT, ev, 20.0 * cells(l), st);
-  }
-  {
-    int ev = prof_mark(p, st);
-    HIPCHK(smgk::mg_lds_cycle32(F.lds, b, F.f32[first], F.u32[first], first == 0, p.opts.nu_pre, p.opts.nu_post,
-                                p.opts.n_sor, F.exact, kCoarseRtol, kCoarseSweeps, st));
-    prof_close(p, K_COARSE, ev, 16.0 * cells(first), st);
-  }
-  for (int l = first - 1; l >= 0; --l) {
-    int ev = prof_mark(p, st);
-    HIPCHK(smgk::mg_prolong_add32(F.L[l], F.L[l + 1], b, F.u32[l], F.u32[l + 1], st));
-    prof_close(p, K_PROLONG, ev, 18.0 * cells(l), st);
-    for (int k = 0; k < p.opts.nu_post; ++k) STCHK(smooth(l));
-  }
-  (void)L;
-  return SMG_OK;
-}
-
-// Iterate V-cycles on planes 0..n-1 (slot p, mode modes[p]) until each meets
-// ||D|| <= tol * max(||D_0||, floor_factor * max ||D_0||).  d_slot/d_mode
-// are device int arrays of capacity n; partial/norm device scratch.
-struct SolveOut {
-  std::vector<int> cycles;
-  std::vector<double> resid;
-  bool converged = true;
-};
-
-static smg_status mg_solve_planes(const smg_plan& p, const MGFields& F, int n, const int* modes, double2* u0,
-                                  const double2* f0, double tol, double floor_factor, bool warm, int max_cycles,
-                                  int* d_slot, int* d_mode, int* h_slot, int* h_mode, double* d_partial,
-                                  double* d_norm, double* h_norm, hipStream_t st, SolveOut& out) {
-  const LevelDev& L0 = F.L[0];
-  const size_t plane = (size_t)L0.na * L0.nb;
-  out.cycles.assign(n, 0);
-  out.resid.assign(n, 0.0);
-  out.converged = true;
-  if (n == 0) return SMG_OK;
-  if (!warm) HIPCHK(smgk::fill_zero(u0, (size_t)n * plane, st));
-  for (int q = 0; q < n; ++q) { h_slot[q] = q; h_mode[q] = modes[q]; }
-  HIPCHK(hipMemcpyAsync(d_slot, h_slot, sizeof(int) * n, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d_mode, h_mode, sizeof(int) * n, hipMemcpyHostToDevice, st));
-  Batch all{n, d_slot, d_mode};
-  float2* r32 = F.fp32 ? F.f32[0] : nullptr;
-  float2* e32 = F.fp32 ? F.u32[0] : nullptr;
-  HIPCHK(smgk::mg_norms(L0, all, nullptr, f0, d_partial, d_norm, st, r32, e32));
-  HIPCHK(hipMemcpyAsync(h_norm, d_norm, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  std::vector<double> d0(h_norm, h_norm + n), cur(n), thr(n);
-  double dmax = 0.0;
-  for (double v : d0) dmax = std::max(dmax, v);
-  for (int q = 0; q < n; ++q) thr[q] = tol * std::max(d0[q], floor_factor * dmax);
-  if (warm) {
-    HIPCHK(smgk::mg_norms(L0, all, u0, f0, d_partial, d_norm, st, r32, e32));
-    HIPCHK(hipMemcpyAsync(h_norm, d_norm, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    cur.assign(h_norm, h_norm + n);
-  } else {
-    cur = d0;
-  }
-  std::vector<int> active;
-  for (int q = 0; q < n; ++q)
-    if (cur[q] > thr[q]) active.push_back(q);
-  while (!active.empty()) {
-    const int na = (int)active.size();
-    for (int k = 0; k < na; ++k) { h_slot[k] = active[k]; h_mode[k] = modes[active[k]]; }
-    HIPCHK(hipMemcpyAsync(d_slot, h_slot, sizeof(int) * na, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_mode, h_mode, sizeof(int) * na, hipMemcpyHostToDevice, st));
-    Batch b{na, d_slot, d_mode};
-    if (F.fp32) {
-      // iterative refinement: FP32 correction cycle, FP64 accumulation, FP64
-      // residual (stored rounded to FP32 for the next correction)
-      STCHK(vcycle32(p, F, b, st));
-      int ev = prof_mark(p, st);
-      HIPCHK(smgk::mg_accumulate(L0, b, u0, e32, st));
-      prof_close(p, K_ACCUM, ev, 40.0 * na * plane, st);
-    } else {
-      STCHK(vcycle(p, F, b, u0, f0, st));
-    }
-    int ev = prof_mark(p, st);
-    HIPCHK(smgk::mg_norms(L0, b, u0, f0, d_partial, d_norm, st, r32, e32));
-    prof_close(p, K_NORM, ev, (F.fp32 ? 48.0 : 32.0) * na * plane, st);
-    HIPCHK(hipMemcpyAsync(h_norm, d_norm, sizeof(double) * na, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    std::vector<int> next;
-    for (int k = 0; k < na; ++k) {
-      const int q = active[k];
-      cur[q] = h_norm[k];
-      out.cycles[q] += 1;
-      if (!(cur[q] <= thr[q]) && out.cycles[q] < max_cycles) next.push_back(q);
-    }
-    active.swap(next);
-  }
-  for (int q = 0; q < n; ++q) {
-    const double den = std::max(d0[q], floor_factor * dmax);
-    out.resid[q] = den > 0.0 ? cur[q] / den : 0.0;
-    if (!(cur[q] <= thr[q])) out.converged = false;
-  }
-  return SMG_OK;
+void PlanProf::close(int cls, int ev, double bytes, hipStream_t st) {
+  static const int map[] = {K_SMOOTH_RADIAL0, K_SMOOTH_POLAR0, K_SMOOTH_COARSE, K_RESTRICT, K_PROLONG,
+                            K_COARSE,         K_NORM,          K_ACCUM,         K_NORM};
+  prof_close(*p, map[cls], ev, bytes, st);
 }
 
 // ----------------------------------------------------------------------------
@@ -741,9 +577,8 @@ static smg_status dgf_extended(smg_plan& p, hipStream_t st) {
   for (const LevelTables& T : HE.lv) lo.push_back(pack_level(B, T));
   char* tb = static_cast<char*>(tmp.alloc(B.bytes.size(), herr)); TMPCHK(tb);
   HIPCHK(hipMemcpyAsync(tb, B.bytes.data(), B.bytes.size(), hipMemcpyHostToDevice, st));
-  MGFields F;
-  F.exact = true;
-  for (size_t l = 0; l < HE.lv.size(); ++l) F.L.push_back(level_view(tb, lo[l], HE.lv[l], p.M));
+  std::vector<LevelDev> LV;
+  for (size_t l = 0; l < HE.lv.size(); ++l) LV.push_back(level_view(tb, lo[l], HE.lv[l], p.M));
   // box geometry for the right-hand sides
   const LevelTables& T0 = HE.lv[0];
   ExtBox E{};
@@ -780,41 +615,61 @@ static smg_status dgf_extended(smg_plan& p, hipStream_t st) {
   size_t per_plane = 0;
   for (const LevelTables& T : HE.lv) per_plane += 2 * sizeof(double2) * (size_t)T.na * T.nb;
   size_t budget = (size_t)4 << 30;
-  int cap = (int)std::max<size_t>(1, std::min<size_t>(budget / per_plane, 4096));
+  int cap = (int)std::max<size_t>(1, std::min<size_t>(budget / per_plane, (size_t)Engine::kMaxPlanes));
   cap = std::min(cap, total);
-  double2* u0 = static_cast<double2*>(tmp.alloc(sizeof(double2) * (size_t)cap * na * nb, herr)); TMPCHK(u0);
-  double2* f0 = static_cast<double2*>(tmp.alloc(sizeof(double2) * (size_t)cap * na * nb, herr)); TMPCHK(f0);
-  F.u.assign(HE.lv.size(), nullptr);
-  F.f.assign(HE.lv.size(), nullptr);
-  for (size_t l = 1; l < HE.lv.size(); ++l) {
-    size_t pl = (size_t)HE.lv[l].na * HE.lv[l].nb;
-    F.u[l] = static_cast<double2*>(tmp.alloc(sizeof(double2) * cap * pl, herr)); TMPCHK(F.u[l]);
-    F.f[l] = static_cast<double2*>(tmp.alloc(sizeof(double2) * cap * pl, herr)); TMPCHK(F.f[l]);
-  }
-  plan_lds(F);
-  int* d_slot = static_cast<int*>(tmp.alloc(sizeof(int) * cap, herr)); TMPCHK(d_slot);
-  int* d_mode = static_cast<int*>(tmp.alloc(sizeof(int) * cap, herr)); TMPCHK(d_mode);
+  // the list is padded to whole chunks; padding planes get a zero source and
+  // drop out at once (zero defect)
+  const int chunks = (total + cap - 1) / cap;
+  pm.resize((size_t)chunks * cap, 0);
+  ps0.resize((size_t)chunks * cap, -1);
+  ps1.resize((size_t)chunks * cap, -1);
+  const size_t box = (size_t)na * nb;
+  double2* u0 = static_cast<double2*>(tmp.alloc(sizeof(double2) * (size_t)cap * box, herr)); TMPCHK(u0);
+  double2* f0 = static_cast<double2*>(tmp.alloc(sizeof(double2) * (size_t)cap * box, herr)); TMPCHK(f0);
   int* d_pm = tmp.upload(pm, st, herr); TMPCHK(d_pm);
   int* d_s0 = tmp.upload(ps0, st, herr); TMPCHK(d_s0);
   int* d_s1 = tmp.upload(ps1, st, herr); TMPCHK(d_s1);
-  double* d_partial = static_cast<double*>(tmp.alloc(sizeof(double) * cap * kNormBlocks, herr)); TMPCHK(d_partial);
-  double* d_norm = static_cast<double*>(tmp.alloc(sizeof(double) * cap, herr)); TMPCHK(d_norm);
-  int *h_slot = nullptr, *h_mode = nullptr;
-  double* h_norm = nullptr;
-  HIPCHK(hipHostMalloc((void**)&h_slot, sizeof(int) * cap));
-  std::unique_ptr<int, void (*)(int*)> g1(h_slot, [](int* q) { (void)hipHostFree(q); });
-  HIPCHK(hipHostMalloc((void**)&h_mode, sizeof(int) * cap));
-  std::unique_ptr<int, void (*)(int*)> g2(h_mode, [](int* q) { (void)hipHostFree(q); });
-  HIPCHK(hipHostMalloc((void**)&h_norm, sizeof(double) * cap));
-  std::unique_ptr<double, void (*)(double*)> g3(h_norm, [](double* q) { (void)hipHostFree(q); });
+  int* d_mode = static_cast<int*>(tmp.alloc(sizeof(int) * cap, herr)); TMPCHK(d_mode);
+  MGProblem pr;
+  pr.L = LV;
+  pr.u.assign(HE.lv.size(), nullptr);
+  pr.f.assign(HE.lv.size(), nullptr);
+  for (size_t l = 1; l < HE.lv.size(); ++l) {
+    size_t pl = (size_t)HE.lv[l].na * HE.lv[l].nb;
+    pr.u[l] = tmp.alloc(sizeof(double2) * cap * pl, herr); TMPCHK(pr.u[l]);
+    pr.f[l] = tmp.alloc(sizeof(double2) * cap * pl, herr); TMPCHK(pr.f[l]);
+  }
+  pr.u0 = {u0};
+  pr.f0 = {f0};
+  pr.mode = d_mode;
+  pr.n = cap;
+  MGParams prm;
+  prm.nu_pre = p.opts.nu_pre;
+  prm.nu_post = p.opts.nu_post;
+  prm.n_sor = p.opts.n_sor;
+  prm.exact = true;
+  prm.fp32 = false;
+  prm.coarse_rtol = kCoarseRtol;
+  prm.coarse_sweeps = kCoarseSweeps;
+  const size_t eb = Engine::region_bytes(1, 1, (int)HE.lv.size(), cap);
+  char* er = static_cast<char*>(tmp.alloc(eb, herr)); TMPCHK(er);
+  Engine eng;
+  std::string emsg;
+  smg_status es = eng.init({pr}, 1, prm, er, eb, st, &emsg);
+  if (es != SMG_OK) return fail(es, "extended DGF engine: " + emsg);
   double* out = reinterpret_cast<double*>(p.ws + p.w_dgf);
+  std::vector<int> cyc;
+  std::vector<double> cur, thr, d0;
   for (int q0 = 0; q0 < total; q0 += cap) {
     const int n = std::min(cap, total - q0);
+    HIPCHK(hipMemcpyAsync(d_mode, d_pm + q0, sizeof(int) * cap, hipMemcpyDeviceToDevice, st));
+    HIPCHK(smgk::fill_zero(f0, (size_t)cap * box, st));
     HIPCHK(smgk::dgf_ext_rhs(K, E, d_pm + q0, d_s0 + q0, d_s1 + q0, n, f0, st));
-    SolveOut so;
-    STCHK(mg_solve_planes(p, F, n, &pm[q0], u0, f0, p.opts.dgf_tol, 0.0, false, 100, d_slot, d_mode, h_slot, h_mode,
-                          d_partial, d_norm, h_norm, st, so));
-    for (double v : so.resid) p.dgf_resid = std::max(p.dgf_resid, v);
+    STCHK(eng.start(0, p.opts.dgf_tol, 0.0, false, 100, st));
+    STCHK(eng.finish_dynamic(0, st, nullptr));
+    STCHK(eng.read_state(0, st, cyc, cur, thr, d0));
+    for (int k = 0; k < n; ++k)
+      if (d0[k] > 0.0) p.dgf_resid = std::max(p.dgf_resid, cur[k] / d0[k]);
     if (!(p.dgf_resid <= 1e3 * p.opts.dgf_tol))
       return fail(SMG_ENOCONV, strprintf("extended-domain DGF solve stalled at relative residual %.3e", p.dgf_resid));
     HIPCHK(smgk::dgf_ext_extract(E, p.n_g, d_pm + q0, d_s0 + q0, d_s1 + q0, n, u0, out, st));
@@ -834,31 +689,59 @@ extern "C" smg_status smg_plan_setup(smg_plan* p, void* workspace, size_t bytes,
   p->ws = static_cast<char*>(workspace);
   p->ready = false;
   p->have_prev = false;
-  if (!p->h_slot) HIPCHK(hipHostMalloc((void**)&p->h_slot, sizeof(int) * p->M));
-  if (!p->h_mode) HIPCHK(hipHostMalloc((void**)&p->h_mode, sizeof(int) * p->M));
-  if (!p->h_norm) HIPCHK(hipHostMalloc((void**)&p->h_norm, sizeof(double) * p->M));
+  p->hist_ok[0] = p->hist_ok[1] = false;
+  p->drop_graphs();
   HIPCHK(hipMemcpyAsync(p->ws + p->w_blob, p->blob.bytes.data(), p->blob.bytes.size(), hipMemcpyHostToDevice, st));
-  p->mg.L.clear();
-  p->mg.exact = p->opts.line_solver == SMG_LINE_EXACT;
-  p->mg.fp32 = p->opts.precision == SMG_MIXED;
-  for (size_t l = 0; l < p->H.lv.size(); ++l) p->mg.L.push_back(level_view(p->ws + p->w_blob, p->loff[l], p->H.lv[l], p->M));
-  p->mg.u.assign(p->H.lv.size(), nullptr);
-  p->mg.f.assign(p->H.lv.size(), nullptr);
-  for (size_t l = 1; l < p->H.lv.size(); ++l) {
-    p->mg.u[l] = p->dptr(p->w_u[l]);
-    p->mg.f[l] = p->dptr(p->w_fl[l]);
-  }
-  if (p->mg.fp32) {
-    p->mg.u32.assign(p->H.lv.size(), nullptr);
-    p->mg.f32.assign(p->H.lv.size(), nullptr);
-    for (size_t l = 0; l < p->H.lv.size(); ++l) {
-      p->mg.u32[l] = reinterpret_cast<float2*>(p->ws + p->w_u32[l]);
-      p->mg.f32[l] = reinterpret_cast<float2*>(p->ws + p->w_f32[l]);
+  const bool fp32 = p->opts.precision == SMG_MIXED;
+  const int L = (int)p->H.lv.size();
+  p->levels.clear();
+  for (int l = 0; l < L; ++l) p->levels.push_back(level_view(p->ws + p->w_blob, p->loff[l], p->H.lv[l], p->M));
+  MGProblem pr;
+  pr.L = p->levels;
+  pr.u.assign(L, nullptr);
+  pr.f.assign(L, nullptr);
+  for (int l = 0; l < L; ++l) {
+    if (fp32) {
+      pr.u[l] = p->ws + p->w_u32[l];
+      pr.f[l] = p->ws + p->w_f32[l];
+    } else if (l > 0) {
+      pr.u[l] = p->dptr(p->w_u[l]);
+      pr.f[l] = p->dptr(p->w_fl[l]);
     }
   }
-  plan_lds(p->mg);
+  pr.u0 = {p->dptr(p->w_psi), p->dptr(p->w_phi)};
+  pr.f0 = {p->dptr(p->w_f), p->dptr(p->w_f2)};
+  if (fp32) {
+    pr.r32 = reinterpret_cast<float2*>(p->ws + p->w_f32[0]);
+    pr.e32 = reinterpret_cast<float2*>(p->ws + p->w_u32[0]);
+  }
+  pr.n = p->M;
+  MGParams prm;
+  prm.nu_pre = p->opts.nu_pre;
+  prm.nu_post = p->opts.nu_post;
+  prm.n_sor = p->opts.n_sor;
+  prm.exact = p->opts.line_solver == SMG_LINE_EXACT;
+  prm.fp32 = fp32;
+  prm.coarse_rtol = kCoarseRtol;
+  prm.coarse_sweeps = kCoarseSweeps;
+  std::string emsg;
+  smg_status es = p->eng.init({pr}, 2, prm, p->ws + p->w_eng, p->w_eng_bytes, st, &emsg);
+  if (es != SMG_OK) return fail(es, "multigrid engine: " + emsg);
+  p->prof_sink.p = p;
+  p->eng.set_prof(&p->prof_sink);
   smg_status s = dgf_method_of(*p) == SMG_DGF_EXTENDED ? dgf_extended(*p, st) : dgf_aux(*p, st);
   if (s != SMG_OK) return s;
+  if (p->opts.autotune) {
+    // the tuning cycles run on a zero right-hand side (launch times do not
+    // depend on the values)
+    HIPCHK(smgk::fill_zero(p->dptr(p->w_f), (size_t)p->M * p->spec.n_a * p->spec.n_b, st));
+    STCHK(p->eng.start(0, 1e-8, kFloor, false, 1, st));
+    const bool was = p->prof_on;
+    p->prof_on = false;
+    es = p->eng.autotune(0, st, &p->tune_report);
+    p->prof_on = was;
+    if (es != SMG_OK) return fail(es, "autotune: " + p->tune_report);
+  }
   HIPCHK(hipStreamSynchronize(st));
   p->ready = true;
   return SMG_OK;
@@ -868,16 +751,6 @@ static smg_status need_ready(const smg_plan* p) {
   if (!p) return fail(SMG_EINVAL, "NULL plan");
   if (!p->ready) return fail(SMG_ESTATE, "plan is not set up (call smg_plan_setup first)");
   return SMG_OK;
-}
-
-static smg_status solve_main(smg_plan* p, const double2* f, double2* u, double tol, bool warm, hipStream_t st,
-                             SolveOut& so) {
-  std::vector<int> modes(p->M);
-  for (int m = 0; m < p->M; ++m) modes[m] = m;
-  return mg_solve_planes(*p, p->mg, p->M, modes.data(), u, f, tol, kFloor, warm, p->opts.max_cycles,
-                         reinterpret_cast<int*>(p->ws + p->w_slot), reinterpret_cast<int*>(p->ws + p->w_mode),
-                         p->h_slot, p->h_mode, reinterpret_cast<double*>(p->ws + p->w_partial),
-                         reinterpret_cast<double*>(p->ws + p->w_norm), p->h_norm, st, so);
 }
 
 static smg_status james_steps(smg_plan* p, const double2* psi, const double2* f, double2* sigma, double2* theta,
@@ -893,13 +766,96 @@ static smg_status james_steps(smg_plan* p, const double2* psi, const double2* f,
   ev = prof_mark(*p, st);
   HIPCHK(smgk::james_conv(reinterpret_cast<const double*>(p->ws + p->w_dgf), sigma, theta, p->n_g, p->M, st));
   prof_close(*p, K_CONV, ev, M * ng * ng * 8.0 + M * ng * 32.0, st);
-  if (f2 != f) HIPCHK(hipMemcpyAsync(f2, f, sizeof(double2) * (size_t)p->M * plane, hipMemcpyDeviceToDevice, st));
+  if (f2 != f) HIPCHK(smgk::copy_planes(f2, f, (size_t)p->M * plane, st));
   ev = prof_mark(*p, st);
   HIPCHK(smgk::james_apply(reinterpret_cast<const int*>(base + p->o_apc), reinterpret_cast<const int*>(base + p->o_apg0),
                            reinterpret_cast<const int*>(base + p->o_apg1), reinterpret_cast<const double*>(base + p->o_apc0),
                            reinterpret_cast<const double*>(base + p->o_apc1), (int)p->ap_cell.size(), plane, p->n_g,
                            p->M, theta, f2, f2, st));
   prof_close(*p, K_APPLY, ev, M * (double)p->ap_cell.size() * 48.0, st);
+  return SMG_OK;
+}
+
+// Per-cycle plane counts of a solve from the per-mode cycle counts of the
+// previous one: cycle k runs on the modes that needed more than k cycles.
+static std::vector<int> schedule_of(const std::vector<int>& cyc) {
+  int mx = 0;
+  for (int c : cyc) mx = std::max(mx, c);
+  std::vector<int> caps(mx, 0);
+  for (int c : cyc)
+    for (int k = 0; k < c; ++k) caps[k] += 1;
+  return caps;
+}
+
+// The body of a solve between the two FFTs: solve 1 into Psi, the James
+// steps, solve 2 into Phi^m.  With schedules, every cycle is enqueued up
+// front (no host synchronisation); otherwise each solve reads its list
+// length after every cycle.  ev (optional) records 4 component boundaries.
+static smg_status solve_body(smg_plan* p, double tol, bool warm, const std::vector<int>* sched0,
+                             const std::vector<int>* sched1, hipStream_t st, hipEvent_t* ev) {
+  const int maxc = p->opts.max_cycles;
+  STCHK(p->eng.start(0, tol, kFloor, warm, maxc, st));
+  if (sched0) {
+    for (int cap : *sched0) STCHK(p->eng.cycle(0, cap, st));
+  } else {
+    STCHK(p->eng.finish_dynamic(0, st, nullptr));
+  }
+  if (ev) HIPCHK(hipEventRecord(ev[0], st));
+  STCHK(james_steps(p, p->dptr(p->w_psi), p->dptr(p->w_f), p->dptr(p->w_sigma), p->dptr(p->w_theta), p->dptr(p->w_f2), st));
+  if (ev) HIPCHK(hipEventRecord(ev[1], st));
+  STCHK(p->eng.start(1, tol, kFloor, warm, maxc, st));
+  if (sched1) {
+    for (int cap : *sched1) STCHK(p->eng.cycle(1, cap, st));
+  } else {
+    STCHK(p->eng.finish_dynamic(1, st, nullptr));
+  }
+  if (ev) HIPCHK(hipEventRecord(ev[2], st));
+  return SMG_OK;
+}
+
+// Captured graph of solve_body for the two schedules (cached).
+static smg_status body_graph(smg_plan* p, double tol, bool warm, const std::vector<int>& s0, const std::vector<int>& s1,
+                             hipStream_t st, hipGraphExec_t* out) {
+  std::vector<int> key;
+  key.push_back(warm ? 1 : 0);
+  long long tb;
+  std::memcpy(&tb, &tol, sizeof(tb));
+  key.push_back((int)(tb & 0xffffffff));
+  key.push_back((int)(tb >> 32));
+  key.push_back((int)s0.size());
+  key.insert(key.end(), s0.begin(), s0.end());
+  key.insert(key.end(), s1.begin(), s1.end());
+  for (GraphEnt& g : p->graphs)
+    if (g.key == key) {
+      g.used = ++p->graph_clock;
+      *out = g.exec;
+      return SMG_OK;
+    }
+  // captured on the plan's own stream (the caller's may be the null
+  // stream, which cannot capture) and launched on the caller's
+  (void)st;
+  if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+  smg_status sb = solve_body(p, tol, warm, &s0, &s1, p->cap_stream, nullptr);
+  hipError_t ce = hipStreamEndCapture(p->cap_stream, &graph);
+  if (sb != SMG_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return sb;
+  }
+  HIPCHK(ce);
+  hipGraphExec_t exec = nullptr;
+  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIPCHK(ie);
+  if ((int)p->graphs.size() >= kMaxGraphs) {
+    auto lru = std::min_element(p->graphs.begin(), p->graphs.end(),
+                                [](const GraphEnt& a, const GraphEnt& b) { return a.used < b.used; });
+    (void)hipGraphExecDestroy(lru->exec);
+    p->graphs.erase(lru);
+  }
+  p->graphs.push_back(GraphEnt{key, exec, ++p->graph_clock});
+  *out = exec;
   return SMG_OK;
 }
 
@@ -920,48 +876,86 @@ extern "C" smg_status smg_solve(smg_plan* p, const double* rho, double* phi, dou
   } guard{ev, timings};
   const char* base = p->ws + p->w_blob;
   const double2* tw = reinterpret_cast<const double2*>(base + p->o_tw);
-  double2* f = p->dptr(p->w_f);
-  double2* psi = p->dptr(p->w_psi);
-  double2* phim = p->dptr(p->w_phi);
   const bool warm = (flags & SMG_WARM_PREV) && p->have_prev;
+  const int wk = warm ? 1 : 0;
   const int lines = s.n_a * s.n_b;
+  // scheduled launches (one host synchronisation per solve) once a previous
+  // solve of the same kind gave the per-mode cycle counts; per-cycle host
+  // reads for the first solve, for profiling and with SMG_LAUNCH_DYNAMIC
+  const bool sched = p->opts.launch == SMG_LAUNCH_GRAPH && p->hist_ok[wk] && !p->prof_on;
+  const bool graph = sched && !timings;
   if (timings) HIPCHK(hipEventRecord(ev[0], st));
   const double fft_bytes = (double)lines * (8.0 * s.n_phi + 16.0 * p->M);
   int pe = prof_mark(*p, st);
-  HIPCHK(smgk::fft_r2c(rho, f, lines, s.n_phi, 4.0 * kPi * s.G / s.n_phi, tw, st));
+  HIPCHK(smgk::fft_r2c(rho, p->dptr(p->w_f), lines, s.n_phi, 4.0 * kPi * s.G / s.n_phi, tw, st));
   prof_close(*p, K_FFT_R2C, pe, fft_bytes, st);
   if (timings) HIPCHK(hipEventRecord(ev[1], st));
-  SolveOut s1, s2;
-  STCHK(solve_main(p, f, psi, tol, warm, st, s1));
-  if (timings) HIPCHK(hipEventRecord(ev[2], st));
-  STCHK(james_steps(p, psi, f, p->dptr(p->w_sigma), p->dptr(p->w_theta), f, st));
-  if (timings) HIPCHK(hipEventRecord(ev[3], st));
-  STCHK(solve_main(p, f, phim, tol, warm, st, s2));
-  if (timings) HIPCHK(hipEventRecord(ev[4], st));
+  std::vector<int> s0, s1;
+  if (sched) {
+    s0 = schedule_of(p->hist[wk][0]);
+    s1 = schedule_of(p->hist[wk][1]);
+  }
+  if (graph) {
+    hipGraphExec_t exec = nullptr;
+    STCHK(body_graph(p, tol, warm, s0, s1, st, &exec));
+    HIPCHK(hipGraphLaunch(exec, st));
+  } else {
+    STCHK(solve_body(p, tol, warm, sched ? &s0 : nullptr, sched ? &s1 : nullptr, st, timings ? ev + 2 : nullptr));
+  }
   pe = prof_mark(*p, st);
-  HIPCHK(smgk::fft_c2r(phim, phi, lines, s.n_phi, tw, st));
+  HIPCHK(smgk::fft_c2r(p->dptr(p->w_phi), phi, lines, s.n_phi, tw, st));
   prof_close(*p, K_FFT_C2R, pe, fft_bytes, st);
   if (timings) HIPCHK(hipEventRecord(ev[5], st));
   p->have_prev = true;
+  // per-mode state of both solves (one synchronisation); modes that needed
+  // more cycles than the schedule gave them are finished here and the
+  // inverse transform is repeated
+  Engine::State es;
+  STCHK(p->eng.read_all(st, &es));
+  if (es.count[0] > 0 || es.count[1] > 0) {
+    if (es.count[0] > 0) {
+      STCHK(p->eng.finish_dynamic(0, st, nullptr));
+      STCHK(james_steps(p, p->dptr(p->w_psi), p->dptr(p->w_f), p->dptr(p->w_sigma), p->dptr(p->w_theta),
+                        p->dptr(p->w_f2), st));
+      // Phi^m holds the result for the old boundary data: a good guess
+      STCHK(p->eng.start(1, tol, kFloor, true, p->opts.max_cycles, st));
+    }
+    STCHK(p->eng.finish_dynamic(1, st, nullptr));
+    HIPCHK(smgk::fft_c2r(p->dptr(p->w_phi), phi, lines, s.n_phi, tw, st));
+    STCHK(p->eng.read_all(st, &es));
+  }
+  std::vector<int>* cyc = es.cyc.data();
+  std::vector<double>* cur = es.cur.data();
+  std::vector<double>* thr = es.thr.data();
+  bool converged = true;
+  for (int t = 0; t < 2; ++t)
+    for (int m = 0; m < p->M; ++m)
+      if (!(cur[t][m] <= thr[t][m])) converged = false;
+  if (converged && p->opts.launch == SMG_LAUNCH_GRAPH) {
+    // a mode that took one cycle more than scheduled keeps its new count
+    p->hist[wk][0] = cyc[0];
+    p->hist[wk][1] = cyc[1];
+    p->hist_ok[wk] = true;
+  }
   if (info) {
-    HIPCHK(hipStreamSynchronize(st));
     info->n_modes = p->M;
     info->total_cycles = 0;
     for (int m = 0; m < p->M; ++m) {
-      if (info->cycles1) info->cycles1[m] = s1.cycles[m];
-      if (info->cycles2) info->cycles2[m] = s2.cycles[m];
-      if (info->resid1) info->resid1[m] = s1.resid[m];
-      if (info->resid2) info->resid2[m] = s2.resid[m];
-      info->total_cycles += s1.cycles[m] + s2.cycles[m];
+      const double den0 = thr[0][m] / tol, den1 = thr[1][m] / tol;
+      if (info->cycles1) info->cycles1[m] = cyc[0][m];
+      if (info->cycles2) info->cycles2[m] = cyc[1][m];
+      if (info->resid1) info->resid1[m] = den0 > 0.0 ? cur[0][m] / den0 : 0.0;
+      if (info->resid2) info->resid2[m] = den1 > 0.0 ? cur[1][m] / den1 : 0.0;
+      info->total_cycles += cyc[0][m] + cyc[1][m];
     }
-    info->converged = (s1.converged && s2.converged) ? 1 : 0;
+    info->converged = converged ? 1 : 0;
     if (timings) {
       float t[5];
       for (int k = 0; k < 5; ++k) HIPCHK(hipEventElapsedTime(&t[k], ev[k], ev[k + 1]));
       info->ms_fft = t[0]; info->ms_mg1 = t[1]; info->ms_james = t[2]; info->ms_mg2 = t[3]; info->ms_ifft = t[4];
     }
   }
-  if (!(s1.converged && s2.converged)) return fail(SMG_ENOCONV, "a mode did not reach the tolerance within max_cycles");
+  if (!converged) return fail(SMG_ENOCONV, "a mode did not reach the tolerance within max_cycles");
   return SMG_OK;
 }
 
@@ -986,60 +980,81 @@ extern "C" smg_status smg_fft_inverse(smg_plan* p, const double* modes, double* 
   return SMG_OK;
 }
 
-extern "C" smg_status smg_mg_solve(smg_plan* p, const double* f, double* u, double tol, void* stream, int* cycles,
-                                   double* resid) {
-  STCHK(need_ready(p));
-  if (!(tol > 0.0)) return fail(SMG_EINVAL, "rel_tol must be > 0");
-  SolveOut so;
-  STCHK(solve_main(p, reinterpret_cast<const double2*>(f), reinterpret_cast<double2*>(u), tol, true,
-                   static_cast<hipStream_t>(stream), so));
-  for (int m = 0; m < p->M; ++m) {
-    if (cycles) cycles[m] = so.cycles[m];
-    if (resid) resid[m] = so.resid[m];
-  }
-  if (!so.converged) return fail(SMG_ENOCONV, "a mode did not reach the tolerance within max_cycles");
+// The step entry points work on copies in the plan's solve-1 arrays (the
+// next smg_solve does not warm-start from them).
+static smg_status stage_in(smg_plan* p, const double* f, const double* u, hipStream_t st) {
+  const size_t n = (size_t)p->M * p->spec.n_a * p->spec.n_b;
+  if (f) HIPCHK(smgk::copy_planes(p->dptr(p->w_f), reinterpret_cast<const double2*>(f), n, st));
+  if (u) HIPCHK(smgk::copy_planes(p->dptr(p->w_psi), reinterpret_cast<const double2*>(u), n, st));
+  p->have_prev = false;
   return SMG_OK;
 }
 
-static Batch all_modes(smg_plan* p, hipStream_t st, hipError_t& e) {
-  for (int m = 0; m < p->M; ++m) { p->h_slot[m] = m; p->h_mode[m] = m; }
-  int* ds = reinterpret_cast<int*>(p->ws + p->w_slot);
-  int* dm = reinterpret_cast<int*>(p->ws + p->w_mode);
-  e = hipMemcpyAsync(ds, p->h_slot, sizeof(int) * p->M, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(dm, p->h_mode, sizeof(int) * p->M, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  return Batch{p->M, ds, dm};
+static smg_status stage_out(smg_plan* p, double* u, hipStream_t st) {
+  const size_t n = (size_t)p->M * p->spec.n_a * p->spec.n_b;
+  HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(u), p->dptr(p->w_psi), n, st));
+  return SMG_OK;
+}
+
+extern "C" smg_status smg_mg_solve(smg_plan* p, const double* f, double* u, double tol, void* stream, int* cycles,
+                                   double* resid) {
+  STCHK(need_ready(p));
+  if (!f || !u) return fail(SMG_EINVAL, "f and u must not be NULL");
+  if (!(tol > 0.0)) return fail(SMG_EINVAL, "rel_tol must be > 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  STCHK(stage_in(p, f, u, st));
+  STCHK(p->eng.start(0, tol, kFloor, true, p->opts.max_cycles, st));
+  STCHK(p->eng.finish_dynamic(0, st, nullptr));
+  std::vector<int> cyc;
+  std::vector<double> cur, thr, d0;
+  STCHK(p->eng.read_state(0, st, cyc, cur, thr, d0));
+  STCHK(stage_out(p, u, st));
+  bool ok = true;
+  for (int m = 0; m < p->M; ++m) {
+    const double den = thr[m] / tol;
+    if (cycles) cycles[m] = cyc[m];
+    if (resid) resid[m] = den > 0.0 ? cur[m] / den : 0.0;
+    if (!(cur[m] <= thr[m])) ok = false;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  if (!ok) return fail(SMG_ENOCONV, "a mode did not reach the tolerance within max_cycles");
+  return SMG_OK;
+}
+
+static smg_status need_fp64(const smg_plan* p) {
+  if (p->opts.precision != SMG_FP64) return fail(SMG_EINVAL, "this step entry point needs an FP64 plan");
+  return SMG_OK;
 }
 
 extern "C" smg_status smg_mg_vcycle(smg_plan* p, const double* f, double* u, void* stream) {
   STCHK(need_ready(p));
+  STCHK(need_fp64(p));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e;
-  Batch b = all_modes(p, st, e);
-  HIPCHK(e);
-  STCHK(vcycle(*p, p->mg, b, reinterpret_cast<double2*>(u), reinterpret_cast<const double2*>(f), st));
+  STCHK(stage_in(p, f, u, st));
+  STCHK(p->eng.vcycle_all(0, p->M, (int)p->eng.configs().size() - 1, st));
+  STCHK(stage_out(p, u, st));
+  HIPCHK(hipStreamSynchronize(st));
   return SMG_OK;
 }
 
 extern "C" smg_status smg_mg_smooth(smg_plan* p, const double* f, double* u, void* stream) {
   STCHK(need_ready(p));
+  STCHK(need_fp64(p));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e;
-  Batch b = all_modes(p, st, e);
-  HIPCHK(e);
-  HIPCHK(smgk::mg_smooth(p->mg.L[0], b, reinterpret_cast<double2*>(u), reinterpret_cast<const double2*>(f), p->opts.n_sor,
-                         p->mg.exact, st));
+  STCHK(stage_in(p, f, u, st));
+  STCHK(p->eng.smooth_all(0, st));
+  STCHK(stage_out(p, u, st));
+  HIPCHK(hipStreamSynchronize(st));
   return SMG_OK;
 }
 
 extern "C" smg_status smg_mg_residual(smg_plan* p, const double* f, const double* u, double* r, void* stream) {
   STCHK(need_ready(p));
+  STCHK(need_fp64(p));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e;
-  Batch b = all_modes(p, st, e);
-  HIPCHK(e);
-  HIPCHK(smgk::mg_residual(p->mg.L[0], b, reinterpret_cast<const double2*>(u), reinterpret_cast<const double2*>(f),
-                           reinterpret_cast<double2*>(r), st));
+  STCHK(stage_in(p, f, u, st));
+  STCHK(p->eng.residual_all(0, reinterpret_cast<double2*>(r), st));
+  HIPCHK(hipStreamSynchronize(st));
   return SMG_OK;
 }
 
@@ -1060,6 +1075,8 @@ extern "C" smg_status smg_dgf_table(smg_plan* p, int m, double* host, void* stre
   HIPCHK(hipStreamSynchronize(st));
   return SMG_OK;
 }
+
+extern "C" const char* smg_tune_report(const smg_plan* p) { return p ? p->tune_report.c_str() : ""; }
 
 // ----------------------------------------------------------------------------
 // per-launch timing entry points

@@ -1,4 +1,8 @@
-// Per-mode geometric multigrid kernels (Sec. 3), batched over planes.
+// Per-mode geometric multigrid kernels (Sec. 3), batched over planes of one
+// or several problems.  Block (x, y) works on list entry y (a plane of one
+// problem) and tile x of it; the problem's level tables, arrays and launch
+// shape come from its LvJob.  Entries beyond the device list length and
+// tiles beyond the problem's own tile count return at once.
 //
 // A level stores each plane as an interleaved complex array [na][nb] (b
 // fastest), FP64 (double2) or, for the smoothing and transfers of the mixed
@@ -19,6 +23,8 @@
 // neighbours without another pass over memory.  Inside a colour the n_sor
 // even-odd SOR passes of every line run as point updates in LDS, or (exact
 // variant) each line is solved by the Thomas algorithm.
+#include <algorithm>
+
 #include "smg_internal.h"
 #include "vec.h"
 
@@ -54,17 +60,22 @@ __device__ __forceinline__ typename Vec<R>::T resid_at(const LevelDev& L, int m,
 // with one zero column/row of padding at the ends of the lines.
 // ---------------------------------------------------------------------------
 template <int DIR, bool EXACT, typename R>
-__global__ void __launch_bounds__(kThreads) k_smooth(LevelDev L, Batch bt, typename Vec<R>::T* __restrict__ U,
-                                                    const typename Vec<R>::T* __restrict__ F, int n_sor, int tile,
-                                                    int scratch_words, int stage) {
+__global__ void __launch_bounds__(kThreads) k_smooth(const LvJob* __restrict__ jobs, BatchRef bt, int n_sor) {
   using V = typename Vec<R>::T;
   extern __shared__ char smem[];
   V* sh = reinterpret_cast<V*>(smem);
   const int p = blockIdx.y;
-  const int slot = bt.slot[p], m = bt.mode[p];
+  if (bt.count && p >= *bt.count) return;
+  const int e = bt.ent[p];
+  const LvJob& J = jobs[ent_prob(e)];
+  if (!J.active || (int)blockIdx.x >= J.ntile[DIR]) return;
+  const int slot = ent_slot(e);
+  const int m = J.mode ? J.mode[slot] : slot;
+  const LevelDev L = J.L;
+  const int tile = J.tile[DIR], scratch_words = J.scratch[DIR], stage = J.stage[DIR];
   const int na = L.na, nb = L.nb;
-  V* u = U + (size_t)slot * na * nb;
-  const V* f = F + (size_t)slot * na * nb;
+  V* u = static_cast<V*>(J.u) + (size_t)slot * na * nb;
+  const V* f = static_cast<const V*>(J.f) + (size_t)slot * na * nb;
   // tile geometry in (row, col) = (i, j) coordinates
   int r0, nr, c0, nc;  // first global row/col held in LDS and counts (incl. halo/pad)
   if (DIR == 1) {
@@ -234,58 +245,71 @@ __global__ void __launch_bounds__(kThreads) k_smooth(LevelDev L, Batch bt, typen
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_residual(LevelDev L, Batch bt, const double2* __restrict__ U,
-                                                      const double2* __restrict__ F, double2* __restrict__ Rout) {
-  const int p = blockIdx.y;
-  const int slot = bt.slot[p], m = bt.mode[p];
+// Common prologue of the per-cell kernels: resolve list entry blockIdx.y.
+#define SMG_ENTRY(JOBS, BT)                                  \
+  const int p = blockIdx.y;                                  \
+  if ((BT).count && p >= *(BT).count) return;                \
+  const int e = (BT).ent[p];                                 \
+  const auto& J = (JOBS)[ent_prob(e)];                       \
+  const int slot = ent_slot(e);                              \
+  const int m = J.mode ? J.mode[slot] : slot;                \
+  (void)m
+
+__global__ void __launch_bounds__(kThreads) k_residual(const LvJob* __restrict__ jobs, BatchRef bt,
+                                                      double2* __restrict__ Rout) {
+  SMG_ENTRY(jobs, bt);
+  const LevelDev L = J.L;
   const size_t off = (size_t)slot * L.na * L.nb;
+  const double2* U = static_cast<const double2*>(J.u) + off;
+  const double2* F = static_cast<const double2*>(J.f) + off;
   const int cells = L.na * L.nb;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += gridDim.x * blockDim.x) {
     const int i = t / L.nb, j = t - i * L.nb;
-    Rout[off + t] = resid_at<double>(L, m, U + off, F + off, i, j);
+    Rout[off + t] = resid_at<double>(L, m, U, F, i, j);
   }
 }
 
 // Coarse right-hand side = bilinear restriction of the fine residual; the
 // coarse correction starts from zero.
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_restrict(LevelDev L, LevelDev C, Batch bt,
-                                                      const typename Vec<R>::T* __restrict__ U,
-                                                      const typename Vec<R>::T* __restrict__ F,
-                                                      typename Vec<R>::T* __restrict__ FC,
-                                                      typename Vec<R>::T* __restrict__ UC) {
+__global__ void __launch_bounds__(kThreads) k_restrict(const LvJob* __restrict__ jobs, BatchRef bt) {
   using V = typename Vec<R>::T;
-  const int p = blockIdx.y;
-  const int slot = bt.slot[p], m = bt.mode[p];
+  SMG_ENTRY(jobs, bt);
+  if (!J.active) return;
+  const LevelDev L = J.L, C = J.C;
   const size_t off = (size_t)slot * L.na * L.nb;
   const size_t offc = (size_t)slot * C.na * C.nb;
+  const V* U = static_cast<const V*>(J.u) + off;
+  const V* F = static_cast<const V*>(J.f) + off;
+  V* FC = static_cast<V*>(J.fc) + offc;
+  V* UC = static_cast<V*>(J.uc) + offc;
   const int cells = C.na * C.nb;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += gridDim.x * blockDim.x) {
-    const int I = t / C.nb, J = t - I * C.nb;
+    const int I = t / C.nb, Jc = t - I * C.nb;
     V acc = mkv<R>(0, 0);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const R wa = (R)L.rwa[2 * I + a];
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const R w = wa * (R)L.rwb[2 * J + b];
-        const V r = resid_at<R>(L, m, U + off, F + off, 2 * I + a, 2 * J + b);
+        const R w = wa * (R)L.rwb[2 * Jc + b];
+        const V r = resid_at<R>(L, m, U, F, 2 * I + a, 2 * Jc + b);
         acc = axpy<R>(w, r, acc);
       }
     }
-    FC[offc + t] = acc;
-    UC[offc + t] = mkv<R>(0, 0);
+    FC[t] = acc;
+    UC[t] = mkv<R>(0, 0);
   }
 }
 
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_prolong(LevelDev L, LevelDev C, Batch bt, typename Vec<R>::T* __restrict__ U,
-                                                     const typename Vec<R>::T* __restrict__ UC) {
+__global__ void __launch_bounds__(kThreads) k_prolong(const LvJob* __restrict__ jobs, BatchRef bt) {
   using V = typename Vec<R>::T;
-  const int p = blockIdx.y;
-  const int slot = bt.slot[p], m = bt.mode[p];
-  const size_t off = (size_t)slot * L.na * L.nb;
-  const size_t offc = (size_t)slot * C.na * C.nb;
+  SMG_ENTRY(jobs, bt);
+  if (!J.active) return;
+  const LevelDev L = J.L, C = J.C;
+  V* U = static_cast<V*>(J.u) + (size_t)slot * L.na * L.nb;
+  const V* uc = static_cast<const V*>(J.uc) + (size_t)slot * C.na * C.nb;
   const int par = m & 1;
   const int cells = L.na * L.nb;
   const int* pbi0 = L.pb_i0 + par * L.nb;
@@ -298,37 +322,38 @@ __global__ void __launch_bounds__(kThreads) k_prolong(LevelDev L, LevelDev C, Ba
     const int b0 = pbi0[j], b1 = pbi1[j];
     const R wa0 = (R)L.pa_w0[i], wa1 = (R)L.pa_w1[i];
     const R wb0 = (R)pbw0[j], wb1 = (R)pbw1[j];
-    const V* uc = UC + offc;
-    V e = mkv<R>(0, 0);
-    e = axpy<R>(wa0 * wb0, uc[(size_t)a0 * C.nb + b0], e);
-    e = axpy<R>(wa0 * wb1, uc[(size_t)a0 * C.nb + b1], e);
-    e = axpy<R>(wa1 * wb0, uc[(size_t)a1 * C.nb + b0], e);
-    e = axpy<R>(wa1 * wb1, uc[(size_t)a1 * C.nb + b1], e);
-    const V v = U[off + t];
-    U[off + t] = mkv<R>(v.x + e.x, v.y + e.y);
+    V ev = mkv<R>(0, 0);
+    ev = axpy<R>(wa0 * wb0, uc[(size_t)a0 * C.nb + b0], ev);
+    ev = axpy<R>(wa0 * wb1, uc[(size_t)a0 * C.nb + b1], ev);
+    ev = axpy<R>(wa1 * wb0, uc[(size_t)a1 * C.nb + b0], ev);
+    ev = axpy<R>(wa1 * wb1, uc[(size_t)a1 * C.nb + b1], ev);
+    const V v = U[t];
+    U[t] = mkv<R>(v.x + ev.x, v.y + ev.y);
   }
 }
 
-// Volume-weighted squared defect (FP64): partial sums per (plane, block).
-// U == nullptr: norm of F itself (defect of the zero guess).  When R32 is
-// non-null the FP64 residual is also stored rounded to FP32 (the right-hand
-// side of the next FP32 correction cycle of the mixed form) and the FP32
-// correction E32 is reset to zero.
-__global__ void __launch_bounds__(kThreads) k_norm_partial(LevelDev L, Batch bt, const double2* __restrict__ U,
-                                                          const double2* __restrict__ F, double* __restrict__ partial,
-                                                          float2* __restrict__ R32, float2* __restrict__ E32) {
+// Volume-weighted squared defect (FP64): partial sums per (list position,
+// block).  use_u = 0: the defect of the zero guess (f itself).  With the
+// mixed form the FP64 residual is also stored rounded to FP32 (the right-hand
+// side of the next FP32 correction cycle) and the FP32 correction is zeroed.
+__global__ void __launch_bounds__(kThreads) k_norm_partial(const NormJob* __restrict__ jobs, BatchRef bt, int use_u,
+                                                          double* __restrict__ partial) {
   __shared__ double red[kThreads / 64];
-  const int p = blockIdx.y;
-  const int slot = bt.slot[p], m = bt.mode[p];
+  SMG_ENTRY(jobs, bt);
+  const LevelDev L = J.L;
   const size_t off = (size_t)slot * L.na * L.nb;
+  const double2* U = J.u + off;
+  const double2* F = J.f + off;
+  float2* R32 = J.r32 ? J.r32 + off : nullptr;
+  float2* E32 = J.e32 ? J.e32 + off : nullptr;
   const int cells = L.na * L.nb;
   double acc = 0.0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += gridDim.x * blockDim.x) {
     const int i = t / L.nb, j = t - i * L.nb;
-    const double2 r = U ? resid_at<double>(L, m, U + off, F + off, i, j) : F[off + t];
+    const double2 r = use_u ? resid_at<double>(L, m, U, F, i, j) : F[t];
     if (R32) {
-      R32[off + t] = make_float2((float)r.x, (float)r.y);
-      E32[off + t] = make_float2(0.f, 0.f);
+      R32[t] = make_float2((float)r.x, (float)r.y);
+      E32[t] = make_float2(0.f, 0.f);
     }
     acc += (r.x * r.x + r.y * r.y) * (L.va[i] * L.vb[j]);
   }
@@ -336,35 +361,33 @@ __global__ void __launch_bounds__(kThreads) k_norm_partial(LevelDev L, Batch bt,
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
-    partial[(size_t)p * gridDim.x + blockIdx.x] = s;
+    double sum = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += red[w];
+    partial[(size_t)p * gridDim.x + blockIdx.x] = sum;
   }
 }
 
-__global__ void k_norm_final(const double* __restrict__ partial, int nblk, int n, double* __restrict__ out) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[(size_t)p * nblk + b];
-  out[p] = sqrt(s);
-}
-
 // u (FP64) += e (FP32): the correction step of the mixed form.
-__global__ void __launch_bounds__(kThreads) k_accumulate(int cells, Batch bt, double2* __restrict__ U,
-                                                        const float2* __restrict__ E) {
-  const int p = blockIdx.y;
-  const size_t off = (size_t)bt.slot[p] * cells;
+__global__ void __launch_bounds__(kThreads) k_accumulate(const NormJob* __restrict__ jobs, BatchRef bt) {
+  SMG_ENTRY(jobs, bt);
+  const int cells = J.L.na * J.L.nb;
+  const size_t off = (size_t)slot * cells;
+  double2* U = J.u + off;
+  const float2* E = J.e32 + off;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += gridDim.x * blockDim.x) {
-    const float2 e = E[off + t];
-    const double2 v = U[off + t];
-    U[off + t] = make_double2(v.x + (double)e.x, v.y + (double)e.y);
+    const float2 ev = E[t];
+    const double2 v = U[t];
+    U[t] = make_double2(v.x + (double)ev.x, v.y + (double)ev.y);
   }
 }
 
 __global__ void k_fill_zero(double2* p, size_t n) {
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
     p[t] = make_double2(0.0, 0.0);
+}
+
+__global__ void k_copy(double2* __restrict__ d, const double2* __restrict__ s, size_t n) {
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) d[t] = s[t];
 }
 
 int grid_for(int cells) {
@@ -375,121 +398,129 @@ int grid_for(int cells) {
 constexpr size_t kSmoothLds = 60 * 1024;     // preferred per-block LDS
 constexpr size_t kSmoothLdsMax = 64 * 1024;  // hard limit of a launch
 
-// Lines per tile so that a launch over n_planes planes has about two blocks
-// per compute unit (512 blocks) when the planes allow it.
-int par_tile(int n_lines, int n_planes) {
-  const int want = (512 + n_planes - 1) / n_planes;  // tiles per plane
-  int t = (n_lines + want - 1) / want;
-  return t < 2 ? 2 : t;
-}
-
-template <typename R>
-hipError_t smooth_dir(const LevelDev& L, const Batch& b, typename Vec<R>::T* u, const typename Vec<R>::T* f, int n_sor,
-                      bool exact, int dir, hipStream_t st) {
-  using V = typename Vec<R>::T;
-  if (b.n == 0) return hipSuccess;
-  // LDS per block: tile (lines + 4 halo) x (points + 2), Thomas scratch for
-  // the exact variant, and the staged 1D tables (5 per row, 4 per column).
-  const int npts = dir == 0 ? L.na : L.nb;       // points per line
-  const int nlines = dir == 0 ? L.nb : L.na;     // lines in the plane
-  auto bytes = [&](int t, bool stage) {
-    const size_t nr = dir == 0 ? (size_t)L.na + 2 : (size_t)t + 4;
-    const size_t nc = dir == 0 ? (size_t)t + 4 : (size_t)L.nb + 2;
-    const size_t scratch = exact ? (size_t)(t / 2 + 2) * npts : 0;
-    return sizeof(V) * nr * nc + sizeof(R) * (scratch + (stage ? 5 * nr + 4 * nc : 0));
-  };
-  int tile = par_tile(nlines, b.n);
-  if (tile > nlines) tile = nlines;
-  while (tile > 2 && bytes(tile, true) > kSmoothLds) --tile;
-  if (tile > 2 && (tile & 1)) --tile;
-  const bool stage = bytes(tile, true) <= kSmoothLds;
-  const size_t lds = bytes(tile, stage);
-  if (lds > kSmoothLdsMax) return hipErrorInvalidConfiguration;
-  const int scratch = exact ? (tile / 2 + 2) * npts : 0;
-  const dim3 grid((nlines + tile - 1) / tile, b.n);
-  const int sg = stage ? 1 : 0;
-  if (dir == 0) {
-    if (exact)
-      hipLaunchKernelGGL((k_smooth<0, true, R>), grid, dim3(kThreads), lds, st, L, b, u, f, n_sor, tile, scratch, sg);
-    else
-      hipLaunchKernelGGL((k_smooth<0, false, R>), grid, dim3(kThreads), lds, st, L, b, u, f, n_sor, tile, scratch, sg);
-  } else {
-    if (exact)
-      hipLaunchKernelGGL((k_smooth<1, true, R>), grid, dim3(kThreads), lds, st, L, b, u, f, n_sor, tile, scratch, sg);
-    else
-      hipLaunchKernelGGL((k_smooth<1, false, R>), grid, dim3(kThreads), lds, st, L, b, u, f, n_sor, tile, scratch, sg);
-  }
-  return hipGetLastError();
-}
-
 }  // namespace
 
 namespace smgk {
 
-hipError_t mg_smooth_dir(const LevelDev& L, const Batch& b, double2* u, const double2* f, int n_sor, bool exact,
-                         int dir, hipStream_t st) {
-  return smooth_dir<double>(L, b, u, f, n_sor, exact, dir, st);
+// Lines per tile so that a launch over `planes` planes has about
+// target_blocks blocks, within the LDS budget; tables are staged in LDS when
+// they fit.
+bool smooth_shape(const LevelDev& L, int dir, bool exact, bool fp32, int target_blocks, int planes, SmoothShape* out) {
+  const size_t vb = fp32 ? sizeof(float2) : sizeof(double2), rb = fp32 ? sizeof(float) : sizeof(double);
+  const int npts = dir == 0 ? L.na : L.nb;    // points per line
+  const int nlines = dir == 0 ? L.nb : L.na;  // lines in the plane
+  auto bytes = [&](int t, bool stage) {
+    const size_t nr = dir == 0 ? (size_t)L.na + 2 : (size_t)t + 4;
+    const size_t nc = dir == 0 ? (size_t)t + 4 : (size_t)L.nb + 2;
+    const size_t scratch = exact ? (size_t)(t / 2 + 2) * npts : 0;
+    return vb * nr * nc + rb * (scratch + (stage ? 5 * nr + 4 * nc : 0));
+  };
+  if (planes < 1) planes = 1;
+  const int want = (target_blocks + planes - 1) / planes;  // tiles per plane
+  int tile = (nlines + want - 1) / want;
+  if (tile < 2) tile = 2;
+  if (tile > nlines) tile = nlines;
+  while (tile > 2 && bytes(tile, true) > kSmoothLds) --tile;
+  if (tile > 2 && (tile & 1)) --tile;
+  const bool stage = bytes(tile, true) <= kSmoothLds;
+  out->tile = tile;
+  out->ntile = (nlines + tile - 1) / tile;
+  out->stage = stage ? 1 : 0;
+  out->scratch = exact ? (tile / 2 + 2) * npts : 0;
+  out->lds = bytes(tile, stage);
+  return out->lds <= kSmoothLdsMax;
 }
 
-hipError_t mg_smooth_dir32(const LevelDev& L, const Batch& b, float2* u, const float2* f, int n_sor, bool exact,
-                           int dir, hipStream_t st) {
-  return smooth_dir<float>(L, b, u, f, n_sor, exact, dir, st);
-}
-
-hipError_t mg_smooth(const LevelDev& L, const Batch& b, double2* u, const double2* f, int n_sor, bool exact,
-                     hipStream_t st) {
-  hipError_t e = mg_smooth_dir(L, b, u, f, n_sor, exact, 0, st);
-  if (e != hipSuccess) return e;
-  return mg_smooth_dir(L, b, u, f, n_sor, exact, 1, st);
-}
-
-hipError_t mg_residual(const LevelDev& L, const Batch& b, const double2* u, const double2* f, double2* r,
-                       hipStream_t st) {
-  if (b.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_residual, dim3(grid_for(L.na * L.nb), b.n), dim3(kThreads), 0, st, L, b, u, f, r);
+template <typename R>
+static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, int n_sor,
+                                bool exact, int dir, hipStream_t st) {
+  int gx = 0;
+  size_t lds = 0;
+  for (int q = 0; q < n_prob; ++q) {
+    if (!hj[q].active) continue;
+    const LevelDev& L = hj[q].L;
+    const size_t vb = sizeof(typename Vec<R>::T), rb = sizeof(R);
+    const int t = hj[q].tile[dir], npts = dir == 0 ? L.na : L.nb;
+    const size_t nr = dir == 0 ? (size_t)L.na + 2 : (size_t)t + 4;
+    const size_t nc = dir == 0 ? (size_t)t + 4 : (size_t)L.nb + 2;
+    size_t bytes = vb * nr * nc + rb * ((size_t)hj[q].scratch[dir] + (hj[q].stage[dir] ? 5 * nr + 4 * nc : 0));
+    (void)npts;
+    if (bytes > lds) lds = bytes;
+    if (hj[q].ntile[dir] > gx) gx = hj[q].ntile[dir];
+  }
+  if (gx == 0 || b.cap == 0) return hipSuccess;
+  if (lds > kSmoothLdsMax) return hipErrorInvalidConfiguration;
+  const dim3 grid(gx, b.cap);
+  if (dir == 0) {
+    if (exact) hipLaunchKernelGGL((k_smooth<0, true, R>), grid, dim3(kThreads), lds, st, jobs, b, n_sor);
+    else hipLaunchKernelGGL((k_smooth<0, false, R>), grid, dim3(kThreads), lds, st, jobs, b, n_sor);
+  } else {
+    if (exact) hipLaunchKernelGGL((k_smooth<1, true, R>), grid, dim3(kThreads), lds, st, jobs, b, n_sor);
+    else hipLaunchKernelGGL((k_smooth<1, false, R>), grid, dim3(kThreads), lds, st, jobs, b, n_sor);
+  }
   return hipGetLastError();
 }
 
-hipError_t mg_restrict_residual(const LevelDev& L, const LevelDev& C, const Batch& b, const double2* u,
-                                const double2* f, double2* fc, double2* uc, hipStream_t st) {
-  if (b.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_restrict<double>, dim3(grid_for(C.na * C.nb), b.n), dim3(kThreads), 0, st, L, C, b, u, f, fc, uc);
+hipError_t mg_smooth_dir(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, int n_sor, bool exact,
+                         int dir, bool fp32, hipStream_t st) {
+  return fp32 ? smooth_launch<float>(jobs, hj, n_prob, b, n_sor, exact, dir, st)
+              : smooth_launch<double>(jobs, hj, n_prob, b, n_sor, exact, dir, st);
+}
+
+// blocks per plane of a per-cell launch: enough for the largest problem
+static int cell_grid(const LvJob* hj, int n_prob, bool coarse, bool need_active) {
+  int cells = 0;
+  for (int q = 0; q < n_prob; ++q) {
+    if (need_active && !hj[q].active) continue;
+    const LevelDev& L = coarse ? hj[q].C : hj[q].L;
+    cells = std::max(cells, L.na * L.nb);
+  }
+  return cells ? grid_for(cells) : 0;
+}
+
+hipError_t mg_residual(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, double2* r, hipStream_t st) {
+  const int g = cell_grid(hj, n_prob, false, false);
+  if (!g || !b.cap) return hipSuccess;
+  hipLaunchKernelGGL(k_residual, dim3(g, b.cap), dim3(kThreads), 0, st, jobs, b, r);
   return hipGetLastError();
 }
 
-hipError_t mg_restrict_residual32(const LevelDev& L, const LevelDev& C, const Batch& b, const float2* u,
-                                  const float2* f, float2* fc, float2* uc, hipStream_t st) {
-  if (b.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_restrict<float>, dim3(grid_for(C.na * C.nb), b.n), dim3(kThreads), 0, st, L, C, b, u, f, fc, uc);
+hipError_t mg_restrict(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, bool fp32, hipStream_t st) {
+  const int g = cell_grid(hj, n_prob, true, true);
+  if (!g || !b.cap) return hipSuccess;
+  if (fp32) hipLaunchKernelGGL(k_restrict<float>, dim3(g, b.cap), dim3(kThreads), 0, st, jobs, b);
+  else hipLaunchKernelGGL(k_restrict<double>, dim3(g, b.cap), dim3(kThreads), 0, st, jobs, b);
   return hipGetLastError();
 }
 
-hipError_t mg_prolong_add(const LevelDev& L, const LevelDev& C, const Batch& b, double2* u, const double2* uc,
-                          hipStream_t st) {
-  if (b.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prolong<double>, dim3(grid_for(L.na * L.nb), b.n), dim3(kThreads), 0, st, L, C, b, u, uc);
+hipError_t mg_prolong(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, bool fp32, hipStream_t st) {
+  const int g = cell_grid(hj, n_prob, false, true);
+  if (!g || !b.cap) return hipSuccess;
+  if (fp32) hipLaunchKernelGGL(k_prolong<float>, dim3(g, b.cap), dim3(kThreads), 0, st, jobs, b);
+  else hipLaunchKernelGGL(k_prolong<double>, dim3(g, b.cap), dim3(kThreads), 0, st, jobs, b);
   return hipGetLastError();
 }
 
-hipError_t mg_prolong_add32(const LevelDev& L, const LevelDev& C, const Batch& b, float2* u, const float2* uc,
-                            hipStream_t st) {
-  if (b.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prolong<float>, dim3(grid_for(L.na * L.nb), b.n), dim3(kThreads), 0, st, L, C, b, u, uc);
+int norm_blocks(const NormJob* hj, int n_prob) {
+  int cells = 0;
+  for (int q = 0; q < n_prob; ++q) cells = std::max(cells, hj[q].L.na * hj[q].L.nb);
+  const int g = grid_for(cells);
+  return g > 64 ? 64 : g;
+}
+
+hipError_t mg_norm_partial(const NormJob* jobs, const NormJob* hj, int n_prob, const BatchRef& b, bool use_u,
+                           double* partial, int nblk, hipStream_t st) {
+  (void)hj; (void)n_prob;
+  if (!b.cap) return hipSuccess;
+  hipLaunchKernelGGL(k_norm_partial, dim3(nblk, b.cap), dim3(kThreads), 0, st, jobs, b, use_u ? 1 : 0, partial);
   return hipGetLastError();
 }
 
-hipError_t mg_norms(const LevelDev& L, const Batch& b, const double2* u, const double2* f, double* partial,
-                    double* out, hipStream_t st, float2* r32, float2* e32) {
-  if (b.n == 0) return hipSuccess;
-  const int g = grid_for(L.na * L.nb) > 64 ? 64 : grid_for(L.na * L.nb);
-  hipLaunchKernelGGL(k_norm_partial, dim3(g, b.n), dim3(kThreads), 0, st, L, b, u, f, partial, r32, e32);
-  hipLaunchKernelGGL(k_norm_final, dim3((b.n + 255) / 256), dim3(256), 0, st, partial, g, b.n, out);
-  return hipGetLastError();
-}
-
-hipError_t mg_accumulate(const LevelDev& L, const Batch& b, double2* u, const float2* e, hipStream_t st) {
-  if (b.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_accumulate, dim3(grid_for(L.na * L.nb), b.n), dim3(kThreads), 0, st, L.na * L.nb, b, u, e);
+hipError_t mg_accumulate(const NormJob* jobs, const NormJob* hj, int n_prob, const BatchRef& b, hipStream_t st) {
+  int cells = 0;
+  for (int q = 0; q < n_prob; ++q) cells = std::max(cells, hj[q].L.na * hj[q].L.nb);
+  if (!cells || !b.cap) return hipSuccess;
+  hipLaunchKernelGGL(k_accumulate, dim3(grid_for(cells), b.cap), dim3(kThreads), 0, st, jobs, b);
   return hipGetLastError();
 }
 
@@ -498,6 +529,14 @@ hipError_t fill_zero(double2* p, size_t n, hipStream_t st) {
   size_t g = (n + kThreads - 1) / kThreads;
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)g), dim3(kThreads), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t copy_planes(double2* dst, const double2* src, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  size_t g = (n + kThreads - 1) / kThreads;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)g), dim3(kThreads), 0, st, dst, src, n);
   return hipGetLastError();
 }
 

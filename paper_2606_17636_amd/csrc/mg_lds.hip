@@ -7,6 +7,8 @@
 // the coarsest solve); only the memory traffic and the launch count differ.
 // Templated on the real type R of the smoothing levels; the coarsest level
 // is always solved in FP64 (the mixed form keeps the coarsest solve in FP64).
+#include <algorithm>
+
 #include "smg_internal.h"
 #include "vec.h"
 
@@ -169,15 +171,22 @@ __device__ __forceinline__ typename Vec<R>::T resid_lds(const LevelDev& L, const
 }
 
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_lds_cycle(LdsLevels LL, Batch bt, const typename Vec<R>::T* __restrict__ Fg,
-                                                       typename Vec<R>::T* __restrict__ Ug, int load_u, int nu_pre,
+__global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict__ jobs, BatchRef bt, int nu_pre,
                                                        int nu_post, int n_sor, int exact, double rtol, int max_sweeps) {
   using V = typename Vec<R>::T;
   extern __shared__ char smem[];
   __shared__ double redbuf[kThreads / 64];
   Red red{redbuf};
   const int p = blockIdx.x;
-  const int slot = bt.slot[p], m = bt.mode[p];
+  if (bt.count && p >= *bt.count) return;
+  const int e = bt.ent[p];
+  const LdsJob& J = jobs[ent_prob(e)];
+  const LdsLevels& LL = J.LL;
+  const int slot = ent_slot(e);
+  const int m = J.mode ? J.mode[slot] : slot;
+  const V* __restrict__ Fg = static_cast<const V*>(J.f);
+  V* __restrict__ Ug = static_cast<V*>(J.u);
+  const int load_u = J.load_u;
   const int n = LL.n;
   const int cl = n - 1;  // coarsest level (FP64 storage)
   // LDS carve-up: [coarsest u, f (double2)] [levels 0..n-2 u, f (V)] [scratch (R)] [tables]
@@ -396,19 +405,24 @@ size_t lds_cycle_bytes(const LdsLevels& LL, bool fp32) {
   return fp32 ? cycle_bytes<float>(LL) : cycle_bytes<double>(LL);
 }
 
-hipError_t mg_lds_cycle(const LdsLevels& LL, const Batch& b, const double2* f, double2* u, bool load_u, int nu_pre,
-                        int nu_post, int n_sor, bool exact, double rtol, int max_sweeps, hipStream_t st) {
-  if (b.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lds_cycle<double>, dim3(b.n), dim3(cycle_threads(LL)), cycle_bytes<double>(LL), st, LL, b, f, u,
-                     load_u ? 1 : 0, nu_pre, nu_post, n_sor, exact ? 1 : 0, rtol, max_sweeps);
-  return hipGetLastError();
-}
+int lds_cycle_threads(const LdsLevels& LL) { return cycle_threads(LL); }
 
-hipError_t mg_lds_cycle32(const LdsLevels& LL, const Batch& b, const float2* f, float2* u, bool load_u, int nu_pre,
-                          int nu_post, int n_sor, bool exact, double rtol, int max_sweeps, hipStream_t st) {
-  if (b.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lds_cycle<float>, dim3(b.n), dim3(cycle_threads(LL)), cycle_bytes<float>(LL), st, LL, b, f, u,
-                     load_u ? 1 : 0, nu_pre, nu_post, n_sor, exact ? 1 : 0, rtol, max_sweeps);
+hipError_t mg_lds_cycle(const LdsJob* jobs, const LdsJob* hj, int n_prob, const BatchRef& b, int nu_pre, int nu_post,
+                        int n_sor, bool exact, bool fp32, double rtol, int max_sweeps, hipStream_t st) {
+  if (!b.cap) return hipSuccess;
+  size_t lds = 0;
+  int threads = 64;
+  for (int q = 0; q < n_prob; ++q) {
+    lds = std::max(lds, lds_cycle_bytes(hj[q].LL, fp32));
+    threads = std::max(threads, cycle_threads(hj[q].LL));
+  }
+  if (lds > 64 * 1024) return hipErrorInvalidConfiguration;
+  if (fp32)
+    hipLaunchKernelGGL(k_lds_cycle<float>, dim3(b.cap), dim3(threads), lds, st, jobs, b, nu_pre, nu_post, n_sor,
+                       exact ? 1 : 0, rtol, max_sweeps);
+  else
+    hipLaunchKernelGGL(k_lds_cycle<double>, dim3(b.cap), dim3(threads), lds, st, jobs, b, nu_pre, nu_post, n_sor,
+                       exact ? 1 : 0, rtol, max_sweeps);
   return hipGetLastError();
 }
 

@@ -1,0 +1,134 @@
+// Device-side convergence bookkeeping of the batched V-cycles: the stopping
+// rule of the per-mode solves (defect relative to the zero-guess defect,
+// with a floor relative to the largest mode of the same problem) and the
+// list of planes that still need cycles, kept on the device so that the
+// host does not have to read norms back between V-cycles.
+#include "smg_internal.h"
+
+namespace {
+
+constexpr int kConvThreads = 1024;
+constexpr int kPerThread = 4;      // list capacity kConvThreads * kPerThread
+constexpr int kMaxProblems = 256;  // problems one batch can hold
+
+// Exclusive prefix sum over the block of one int per thread; returns the
+// thread's offset and writes the total to *total.
+__device__ int block_scan(int v, int* buf, int* total) {
+  const int t = threadIdx.x;
+  buf[t] = v;
+  __syncthreads();
+  for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+    const int add = t >= o ? buf[t - o] : 0;
+    __syncthreads();
+    buf[t] += add;
+    __syncthreads();
+  }
+  const int incl = buf[t];
+  if (t == (int)blockDim.x - 1) *total = incl;
+  __syncthreads();
+  return incl - v;
+}
+
+__device__ double sum_partial(const double* partial, int p, int nblk) {
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[(size_t)p * nblk + b];
+  return sqrt(s);
+}
+
+__global__ void __launch_bounds__(kConvThreads) k_conv_init(const NormJob* __restrict__ jobs, const int* __restrict__ all,
+                                                           int n, int n_prob, const double* __restrict__ partial,
+                                                           int nblk, double tol, double floor_factor, ConvState cs,
+                                                           int* __restrict__ list, int* __restrict__ count) {
+  __shared__ unsigned long long dmax[kMaxProblems];
+  __shared__ int buf[kConvThreads];
+  __shared__ int total;
+  for (int q = threadIdx.x; q < n_prob; q += blockDim.x) dmax[q] = 0ull;
+  __syncthreads();
+  int e[kPerThread], g[kPerThread];
+  double d[kPerThread];
+  for (int k = 0; k < kPerThread; ++k) {
+    const int p = threadIdx.x * kPerThread + k;
+    e[k] = -1;
+    if (p >= n) continue;
+    e[k] = all[p];
+    const int q = ent_prob(e[k]);
+    g[k] = jobs[q].base + ent_slot(e[k]);
+    d[k] = sum_partial(partial, p, nblk);
+    cs.d0[g[k]] = d[k];
+    cs.cur[g[k]] = d[k];
+    cs.cyc[g[k]] = 0;
+    // non-negative doubles order like their bit patterns
+    atomicMax(&dmax[q], (unsigned long long)__double_as_longlong(d[k]));
+  }
+  __syncthreads();
+  int keep = 0;
+  bool kk[kPerThread];
+  for (int k = 0; k < kPerThread; ++k) {
+    kk[k] = false;
+    if (e[k] < 0) continue;
+    const double mx = __longlong_as_double((long long)dmax[ent_prob(e[k])]);
+    const double thr = tol * fmax(d[k], floor_factor * mx);
+    cs.thr[g[k]] = thr;
+    kk[k] = d[k] > thr;
+    keep += kk[k] ? 1 : 0;
+  }
+  int off = block_scan(keep, buf, &total);
+  for (int k = 0; k < kPerThread; ++k)
+    if (kk[k]) list[off++] = e[k];
+  if (threadIdx.x == 0) *count = total;
+}
+
+__global__ void __launch_bounds__(kConvThreads) k_converge(const NormJob* __restrict__ jobs, int cap,
+                                                          const double* __restrict__ partial, int nblk, ConvState cs,
+                                                          int max_cycles, int count_cycle, int* __restrict__ list,
+                                                          int* __restrict__ count) {
+  __shared__ int buf[kConvThreads];
+  __shared__ int total;
+  const int n = *count;  // every thread reads it before the block writes it
+  int e[kPerThread];
+  bool kk[kPerThread];
+  int keep = 0;
+  for (int k = 0; k < kPerThread; ++k) {
+    const int p = threadIdx.x * kPerThread + k;
+    e[k] = -1;
+    kk[k] = false;
+    if (p >= n) continue;
+    e[k] = list[p];
+    if (p < cap) {
+      const int g = jobs[ent_prob(e[k])].base + ent_slot(e[k]);
+      const double nrm = sum_partial(partial, p, nblk);
+      cs.cur[g] = nrm;
+      const int c = cs.cyc[g] + count_cycle;
+      cs.cyc[g] = c;
+      kk[k] = !(nrm <= cs.thr[g]) && c < max_cycles;
+    } else {
+      kk[k] = true;  // not cycled this time
+    }
+    keep += kk[k] ? 1 : 0;
+  }
+  int off = block_scan(keep, buf, &total);  // contains barriers: all list reads are done
+  for (int k = 0; k < kPerThread; ++k)
+    if (kk[k]) list[off++] = e[k];
+  if (threadIdx.x == 0) *count = total;
+}
+
+}  // namespace
+
+namespace smgk {
+
+hipError_t mg_conv_init(const NormJob* jobs, const int* all, int n, int n_prob, const double* partial, int nblk,
+                        double tol, double floor_factor, ConvState cs, int* list, int* count, hipStream_t st) {
+  if (n > kConvThreads * kPerThread || n_prob > kMaxProblems || n_prob < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_conv_init, dim3(1), dim3(kConvThreads), 0, st, jobs, all, n, n_prob, partial, nblk, tol,
+                     floor_factor, cs, list, count);
+  return hipGetLastError();
+}
+
+hipError_t mg_converge(const NormJob* jobs, int cap, const double* partial, int nblk, ConvState cs, int max_cycles,
+                       int count_cycle, int* list, int* count, hipStream_t st) {
+  hipLaunchKernelGGL(k_converge, dim3(1), dim3(kConvThreads), 0, st, jobs, cap, partial, nblk, cs, max_cycles,
+                     count_cycle, list, count);
+  return hipGetLastError();
+}
+
+}  // namespace smgk

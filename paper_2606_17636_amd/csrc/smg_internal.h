@@ -135,12 +135,63 @@ struct LdsLevels {
   LevelDev L[kMaxLdsLevels];
 };
 
-// A batch of planes: plane p of the batch lives at slot[p] in the level
-// arrays (plane stride na*nb complex) and uses per-mode tables at mode[p].
-struct Batch {
-  int n;
-  const int* slot;
+// ---------------------------------------------------------------------------
+// Batched launches.  A launch covers a list of planes of one or several
+// problems (plans).  Entry e of the list packs (problem << kSlotBits | slot);
+// the list and, optionally, its length live in device memory so that the
+// convergence test can shrink it on the device between V-cycles.  The grid
+// is sized for `cap` planes; blocks beyond the device count return at once.
+// ---------------------------------------------------------------------------
+constexpr int kSlotBits = 20;
+__host__ __device__ inline int ent_prob(int e) { return e >> kSlotBits; }
+__host__ __device__ inline int ent_slot(int e) { return e & ((1 << kSlotBits) - 1); }
+__host__ __device__ inline int ent_make(int prob, int slot) { return (prob << kSlotBits) | slot; }
+
+struct BatchRef {
+  int cap;           // planes the grid is sized for
+  const int* count;  // device list length (nullptr: cap)
+  const int* ent;    // device list
+};
+
+// One problem's view of one multigrid depth: the tables of this level and of
+// the next coarser one, the level arrays (double2 or float2, as the kernel's
+// real type says) and the smoother's launch shape per line direction
+// (0 radial lines, 1 polar lines).
+struct LvJob {
+  LevelDev L, C;
+  void *u, *f, *uc, *fc;
+  const int* mode;   // azimuthal index of each slot (nullptr: the slot itself)
+  int active;        // 0: this problem's V-cycle is fused in LDS from this depth on
+  int tile[2];       // lines per block
+  int ntile[2];      // blocks per plane
+  int stage[2];      // 1: 1D tables staged in LDS
+  int scratch[2];    // exact-line scratch words
+};
+
+// One problem's fused coarse end of the V-cycle (mg_lds.hip).
+struct LdsJob {
+  LdsLevels LL;
+  void* u;           // first fused level arrays (R typed; the coarsest is FP64)
+  const void* f;
   const int* mode;
+  int load_u;        // the first fused level is the finest: u holds the iterate
+};
+
+// One problem's finest level for the defect norms, the FP64 accumulation of
+// the mixed form and the convergence state.
+struct NormJob {
+  LevelDev L;
+  double2* u;        // FP64 iterate
+  const double2* f;  // FP64 right-hand side
+  float2 *r32, *e32; // mixed form: FP32 residual and correction (else nullptr)
+  const int* mode;
+  int base;          // global index of slot 0 in the convergence state arrays
+};
+
+// Per-plane convergence state, indexed by global plane index.
+struct ConvState {
+  double *d0, *thr, *cur;
+  int* cyc;
 };
 
 namespace smgk {
@@ -149,37 +200,43 @@ hipError_t fft_r2c(const double* rho, double2* modes, int n_lines, int n_phi, do
                    const double2* tw, hipStream_t st);
 hipError_t fft_c2r(const double2* modes, double* out, int n_lines, int n_phi, const double2* tw,
                    hipStream_t st);
-// multigrid (mg.hip), FP64 fields
-hipError_t mg_smooth(const LevelDev& L, const Batch& b, double2* u, const double2* f, int n_sor, bool exact,
-                     hipStream_t st);
-hipError_t mg_smooth_dir(const LevelDev& L, const Batch& b, double2* u, const double2* f, int n_sor, bool exact,
-                         int dir, hipStream_t st);
-hipError_t mg_smooth_dir32(const LevelDev& L, const Batch& b, float2* u, const float2* f, int n_sor, bool exact,
-                           int dir, hipStream_t st);
-hipError_t mg_restrict_residual32(const LevelDev& L, const LevelDev& C, const Batch& b, const float2* u,
-                                  const float2* f, float2* fc, float2* uc, hipStream_t st);
-hipError_t mg_prolong_add32(const LevelDev& L, const LevelDev& C, const Batch& b, float2* u, const float2* uc,
-                            hipStream_t st);
-hipError_t mg_accumulate(const LevelDev& L, const Batch& b, double2* u, const float2* e, hipStream_t st);
-hipError_t mg_lds_cycle32(const LdsLevels& LL, const Batch& b, const float2* f, float2* u, bool load_u, int nu_pre,
-                          int nu_post, int n_sor, bool exact, double rtol, int max_sweeps, hipStream_t st);
-hipError_t mg_residual(const LevelDev& L, const Batch& b, const double2* u, const double2* f,
-                       double2* r, hipStream_t st);
-hipError_t mg_restrict_residual(const LevelDev& L, const LevelDev& Lc, const Batch& b, const double2* u,
-                                const double2* f, double2* fc, double2* uc, hipStream_t st);
-hipError_t mg_prolong_add(const LevelDev& L, const LevelDev& Lc, const Batch& b, double2* u,
-                          const double2* uc, hipStream_t st);
+// Multigrid (mg.hip).  `jobs` is the device array of one depth's LvJob per
+// problem, `hj` its host mirror (used only to size the grid and LDS).
+hipError_t mg_smooth_dir(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, int n_sor, bool exact,
+                         int dir, bool fp32, hipStream_t st);
+hipError_t mg_restrict(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, bool fp32, hipStream_t st);
+hipError_t mg_prolong(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, bool fp32, hipStream_t st);
+hipError_t mg_residual(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, double2* r, hipStream_t st);
+// Launch shape of the smoother for a level seen by `planes` planes at once.
+struct SmoothShape { int tile, ntile, stage, scratch; size_t lds; };
+bool smooth_shape(const LevelDev& L, int dir, bool exact, bool fp32, int target_blocks, int planes, SmoothShape* out);
+// fused coarse cycle (mg_lds.hip)
 size_t lds_cycle_bytes(const LdsLevels& LL, bool fp32);
 int lds_cycle_scratch(const LdsLevels& LL, bool exact);
-hipError_t mg_lds_cycle(const LdsLevels& LL, const Batch& b, const double2* f, double2* u, bool load_u, int nu_pre,
-                        int nu_post, int n_sor, bool exact, double rtol, int max_sweeps, hipStream_t st);
-// Volume-weighted defect norms; with r32 != nullptr the FP64 residual is
-// also stored rounded to FP32 (the mixed form's correction right-hand side)
-// and the FP32 correction e32 is zeroed.
-hipError_t mg_norms(const LevelDev& L, const Batch& b, const double2* u, const double2* f,
-                    double* partial, double* out, hipStream_t st, float2* r32 = nullptr,
-                    float2* e32 = nullptr);
+int lds_cycle_threads(const LdsLevels& LL);
+hipError_t mg_lds_cycle(const LdsJob* jobs, const LdsJob* hj, int n_prob, const BatchRef& b, int nu_pre, int nu_post,
+                        int n_sor, bool exact, bool fp32, double rtol, int max_sweeps, hipStream_t st);
+// Norms and convergence (sched.hip).  mg_norm_partial: volume-weighted
+// squared defect per (list position, block); use_u = 0 takes the zero guess
+// (defect = f).  With the mixed form the FP64 residual is also stored
+// rounded to FP32 and the FP32 correction zeroed.
+int norm_blocks(const NormJob* hj, int n_prob);
+hipError_t mg_norm_partial(const NormJob* jobs, const NormJob* hj, int n_prob, const BatchRef& b, bool use_u,
+                           double* partial, int nblk, hipStream_t st);
+// Thresholds from the zero-guess defects: thr = tol * max(d0, floor * max
+// over the problem's planes of d0); cyc = 0; the list keeps the planes
+// whose d0 exceeds thr.  The full list of n planes is `all` (n <= 4096).
+hipError_t mg_conv_init(const NormJob* jobs, const int* all, int n, int n_prob, const double* partial, int nblk,
+                        double tol, double floor_factor, ConvState cs, int* list, int* count, hipStream_t st);
+// After a V-cycle on the first `cap` planes of the list: record their
+// defect norm, count the cycle (count_cycle), and keep the planes whose norm
+// is above thr and whose cycle count is below max_cycles.  Planes at list
+// positions >= cap were not cycled and stay.  Compacts the list in place.
+hipError_t mg_converge(const NormJob* jobs, int cap, const double* partial, int nblk, ConvState cs, int max_cycles,
+                       int count_cycle, int* list, int* count, hipStream_t st);
+hipError_t mg_accumulate(const NormJob* jobs, const NormJob* hj, int n_prob, const BatchRef& b, hipStream_t st);
 hipError_t fill_zero(double2* p, size_t n, hipStream_t st);
+hipError_t copy_planes(double2* dst, const double2* src, size_t n, hipStream_t st);
 // James boundary (james.hip)
 hipError_t james_screen(const int* adj, const double* coup, int n_g, int plane, int M,
                         const double2* psi, double inv4piG, double2* sigma, hipStream_t st);

@@ -19,6 +19,7 @@ UNIFORM, LOG = 0, 1
 FP64, MIXED = 0, 1
 DGF_AUTO, DGF_AUX, DGF_EXTENDED = 0, 1, 2
 LINE_SOR, LINE_EXACT = 0, 1
+LAUNCH_GRAPH, LAUNCH_DYNAMIC = 0, 1
 WARM_PREV = 1
 TIMINGS = 2
 
@@ -40,7 +41,8 @@ class Grid(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
                 ("n_sor", ctypes.c_int), ("max_cycles", ctypes.c_int), ("dgf_method", ctypes.c_int),
-                ("n_pad", ctypes.c_int), ("dgf_tol", ctypes.c_double), ("line_solver", ctypes.c_int)]
+                ("n_pad", ctypes.c_int), ("dgf_tol", ctypes.c_double), ("line_solver", ctypes.c_int),
+                ("launch", ctypes.c_int), ("autotune", ctypes.c_int)]
 
 
 _PI = ctypes.POINTER(ctypes.c_int)
@@ -95,6 +97,7 @@ def load():
         "smg_dgf_table": ([P, ctypes.c_int, _PD, P], ctypes.c_int),
         "smg_profile_begin": ([P], ctypes.c_int),
         "smg_profile_end": ([P, ctypes.POINTER(KernelStat), ctypes.c_int, _PI], ctypes.c_int),
+        "smg_tune_report": ([P], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -133,14 +136,16 @@ class Plan:
 
     def __init__(self, geometry, radial, n_a, n_b, n_phi, a_min, a_max, b_min, b_max, G=1.0, precision=FP64,
                  nu_pre=2, nu_post=2, n_sor=2, max_cycles=60, dgf_method=DGF_AUTO, n_pad=16, dgf_tol=1e-13,
-                 line_solver=LINE_SOR):
+                 line_solver=LINE_SOR, launch=LAUNCH_GRAPH, autotune=False):
         lib = load()
         geo = {"spherical": SPHERICAL, "cylindrical": CYLINDRICAL}.get(geometry, geometry)
         rad = {"uniform": UNIFORM, "log": LOG}.get(radial, radial)
         prec = {"fp64": FP64, "mixed": MIXED}.get(precision, precision)
         self.grid = Grid(geo, rad, n_a, n_b, n_phi, a_min, a_max, b_min, b_max, G)
         ls = {"sor": LINE_SOR, "exact": LINE_EXACT}.get(line_solver, line_solver)
-        self.opts = Opts(prec, nu_pre, nu_post, n_sor, max_cycles, dgf_method, n_pad, dgf_tol, ls)
+        lc = {"graph": LAUNCH_GRAPH, "dynamic": LAUNCH_DYNAMIC}.get(launch, launch)
+        self.opts = Opts(prec, nu_pre, nu_post, n_sor, max_cycles, dgf_method, n_pad, dgf_tol, ls, lc,
+                         1 if autotune else 0)
         self.line_solver = ls
         self._h = ctypes.c_void_p()
         _check(lib.smg_plan_create(ctypes.byref(self.grid), ctypes.byref(self.opts), ctypes.byref(self._h)))
@@ -289,6 +294,9 @@ class Plan:
         _check(load().smg_profile_end(self._h, arr, 32, ctypes.byref(n)))
         return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms, bytes=arr[i].bytes)
                 for i in range(min(n.value, 32))}
+
+    def tune_report(self):
+        return load().smg_tune_report(self._h).decode()
 
     def dgf_table(self, m):
         out = np.zeros((self.n_ghost, self.n_ghost))
