@@ -4,10 +4,14 @@
 One step = one full solve (azimuthal FFT -> multigrid solve 1 -> screening
 mass + DGF convolution -> multigrid solve 2 -> inverse FFT) of the workload's
 density from a zero initial guess, to relative residual --tol (default 1e-8)
-on every mode.  The DGF tables and plan setup are built before the timed
-region (one-time, as in the paper).  Prints one JSON line.
+on every mode.  The DGF tables, the launch-shape tuning and the plan setup
+are done before the timed region (one-time, as in the paper).  The timed
+form is the chosen one (FP32/FP64 iterative refinement, per-mode cycle
+schedules replayed as HIP graphs, autotuned launch shapes); the plain GPU
+form (FP64, host reads after every V-cycle) is timed next to it.  Prints one
+JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2] [--form chosen|plain]
 """
 import argparse
 import json
@@ -61,18 +65,48 @@ def cpu_baseline(workload, tol, budget_s):
                        f"first solve incl. factorisation {t_first:.2f}s; DGF zeros, setup excluded)")
 
 
+def _plan(smg, g, form, line_solver):
+    """The chosen form (mixed precision, scheduled graph replay, autotuned
+    launch shapes) or the plain GPU form (FP64, host reads after every
+    V-cycle, built-in launch shapes)."""
+    if form == "chosen":
+        return smg.Plan(**g, precision="mixed", launch="graph", autotune=True, line_solver=line_solver)
+    return smg.Plan(**g, precision="fp64", launch="dynamic", autotune=False, line_solver=line_solver)
+
+
+def _timed(plan, rho, phi, steps, tol, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.solve_nosync(rho, phi, tol=tol)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2")
-    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
+    ap.add_argument("--form", default="chosen", choices=["chosen", "plain"])
     ap.add_argument("--line-solver", default="sor", choices=["sor", "exact"])
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-GPU comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy 5 times (the HBM-counter calibration kernel)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the path would shard "
               "by Fourier mode across GPUs, which is not built here.", file=sys.stderr)
@@ -86,33 +120,34 @@ def main():
 
     g = configs.GRIDS[args.workload]
     log(f"workload {args.workload}: {configs.DESCRIPTION[args.workload]}")
-    plan = smg.Plan(**g, precision=args.precision, line_solver=args.line_solver)
+    plan = _plan(smg, g, args.form, args.line_solver)
     t0 = time.perf_counter()
     plan.setup("cuda:0")
     torch.cuda.synchronize()
-    log(f"setup (tables + DGF) {time.perf_counter() - t0:.2f}s, levels {plan.level_shapes}, ghosts {plan.n_ghost}")
+    log(f"setup (tables + DGF + tuning) {time.perf_counter() - t0:.2f}s, levels {plan.level_shapes}, "
+        f"ghosts {plan.n_ghost}")
+    if plan.tune_report():
+        log("autotune: " + " | ".join(l for l in plan.tune_report().splitlines() if l.startswith("planes <=")))
     a, b, p, _ = plan.geometry()
     rho = torch.from_numpy(configs.density(args.workload, a, b, p)).to("cuda:0")
     phi = torch.empty_like(rho)
-    for _ in range(args.warmup):
+    for _ in range(max(args.warmup, 2)):   # the first solve of a kind runs the host loop and fixes the schedule
         plan.solve_nosync(rho, phi, tol=args.tol)
     torch.cuda.synchronize()
-    log(f"warmup {args.warmup} done")
+    log(f"warmup {max(args.warmup, 2)} done")
 
-    plan.profile_begin()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.solve_nosync(rho, phi, tol=args.tol)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    stats = plan.profile_end()
+    dt = _timed(plan, rho, phi, args.steps, args.tol, torch)
     value = args.steps / dt
-    log(f"timed {args.steps} solves in {dt:.3f}s -> {value:.2f} solves/s")
+    log(f"timed {args.steps} solves in {dt:.3f}s -> {value:.2f} solves/s ({args.form})")
 
+    # per-kernel launch durations: the same solves with every launch
+    # bracketed by HIP events on the solve stream (host loop launches, the
+    # same kernels and launch shapes as the timed replay)
+    plan.profile_begin()
+    _timed(plan, rho, phi, args.steps, args.tol, torch)
+    stats = plan.profile_end()
     _, info = plan.solve(rho, tol=args.tol, timings=True)
     cyc = info["total_cycles"]
-    # dominant kernel by summed launch time
     name, st = max(stats.items(), key=lambda kv: kv[1]["total_ms"])
     achieved = st["bytes"] / (st["total_ms"] * 1e-3) / 1e9
     roofline = dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -132,15 +167,26 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f32+f64" if args.form == "chosen" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {configs.DESCRIPTION[args.workload]}", "tol": args.tol,
-                   "precision": args.precision, "line_solver": args.line_solver, "initial_guess": "zero",
+                   "form": args.form, "line_solver": args.line_solver, "initial_guess": "zero",
                    "v_cycles_per_solve": cyc,
+                   "v_cycles_m0": [int(info["cycles1"][0]), int(info["cycles2"][0])],
                    "component_ms": {k: round(info[k], 3) for k in ("ms_fft", "ms_mg1", "ms_james", "ms_mg2", "ms_ifft")}},
         "roofline": roofline,
         "kernels_per_step": kern,
     }
+    if args.form == "chosen" and not args.no_plain:
+        pl = _plan(smg, g, "plain", args.line_solver).setup("cuda:0")
+        for _ in range(max(args.warmup, 2)):
+            pl.solve_nosync(rho, phi, tol=args.tol)
+        dtp = _timed(pl, rho, phi, args.steps, args.tol, torch)
+        out["plain_gpu"] = dict(value=round(args.steps / dtp, 3), unit="solves/s",
+                                ms_per_step=round(1e3 * dtp / args.steps, 3),
+                                form="FP64, host reads after every V-cycle, built-in launch shapes, no graph")
+        out["speedup_vs_plain"] = round(dtp / dt, 3)
+        log(f"plain GPU form: {args.steps / dtp:.2f} solves/s")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.tol, args.cpu_budget)
