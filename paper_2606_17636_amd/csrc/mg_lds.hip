@@ -37,7 +37,13 @@ struct Tab {
 };
 
 template <typename R>
-__device__ Tab<R> stage_tab(const LevelDev& L, int m, R* buf) {
+__device__ __forceinline__ Tab<R> tab_at(R* t, int na, int nb) {
+  R* c = t + 5 * na;
+  return Tab<R>{t, t + na, t + 2 * na, t + 3 * na, t + 4 * na, c, c + nb, c + 2 * nb, c + 3 * nb};
+}
+
+template <typename R>
+__device__ __forceinline__ Tab<R> stage_tab(const LevelDev& L, int m, R* buf) {
   const int na = L.na, nb = L.nb;
   R* t = buf;
   for (int i = threadIdx.x; i < na; i += blockDim.x) {
@@ -54,12 +60,12 @@ __device__ Tab<R> stage_tab(const LevelDev& L, int m, R* buf) {
     c[2 * nb + j] = (R)L.Cb[(size_t)m * nb + j];
     c[3 * nb + j] = (R)L.wr[(size_t)m * nb + j];
   }
-  return Tab<R>{t, t + na, t + 2 * na, t + 3 * na, t + 4 * na, c, c + nb, c + 2 * nb, c + 3 * nb};
+  return tab_at<R>(buf, na, nb);
 }
 
 // u: padded (na+2) x (nb+2) plane, f: na x nb.
 template <int DIR, typename R>
-__device__ void sor_phase(const LevelDev& L, const Tab<R>& T, typename Vec<R>::T* u, const typename Vec<R>::T* f,
+__device__ __forceinline__ void sor_phase(const LevelDev& L, const Tab<R>& T, typename Vec<R>::T* u, const typename Vec<R>::T* f,
                           int n_sor) {
   using V = typename Vec<R>::T;
   const int na = L.na, nb = L.nb, nc = nb + 2;
@@ -98,7 +104,7 @@ __device__ void sor_phase(const LevelDev& L, const Tab<R>& T, typename Vec<R>::T
 }
 
 template <int DIR, typename R>
-__device__ void exact_phase(const LevelDev& L, const Tab<R>& T, typename Vec<R>::T* u, const typename Vec<R>::T* f,
+__device__ __forceinline__ void exact_phase(const LevelDev& L, const Tab<R>& T, typename Vec<R>::T* u, const typename Vec<R>::T* f,
                             R* cp) {
   using V = typename Vec<R>::T;
   const int na = L.na, nb = L.nb, nc = nb + 2;
@@ -145,7 +151,7 @@ __device__ void exact_phase(const LevelDev& L, const Tab<R>& T, typename Vec<R>:
 }
 
 template <typename R>
-__device__ void smooth_step(const LevelDev& L, const Tab<R>& T, typename Vec<R>::T* u, const typename Vec<R>::T* f,
+__device__ __forceinline__ void smooth_step(const LevelDev& L, const Tab<R>& T, typename Vec<R>::T* u, const typename Vec<R>::T* f,
                             int n_sor, bool exact, R* cp) {
   if (exact) {
     exact_phase<0, R>(L, T, u, f, cp);
@@ -193,25 +199,36 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict
   const LevelDev& LC = LL.L[cl];
   double2* uC = reinterpret_cast<double2*>(smem);
   double2* fC = uC + (LC.na + 2) * (LC.nb + 2);
-  V* u[kMaxLdsLevels];
-  V* f[kMaxLdsLevels];
-  char* q = reinterpret_cast<char*>(fC + LC.na * LC.nb);
-  for (int l = 0; l < cl; ++l) {
-    u[l] = reinterpret_cast<V*>(q); q += sizeof(V) * (LL.L[l].na + 2) * (LL.L[l].nb + 2);
-    f[l] = reinterpret_cast<V*>(q); q += sizeof(V) * LL.L[l].na * LL.L[l].nb;
-  }
-  R* cp = reinterpret_cast<R*>(q);
-  double* tq = reinterpret_cast<double*>(cp + LL.scratch);
-  Tab<double> tabC = stage_tab<double>(LC, m, tq);
-  tq += 5 * LC.na + 4 * LC.nb;
-  Tab<R> tab[kMaxLdsLevels];
-  {
-    R* tr = reinterpret_cast<R*>(tq);
+  // per-level byte offsets into LDS of u, f and the staged tables (kept in
+  // LDS and turned into pointers at each use, so that the pointers stay
+  // known as LDS addresses and no per-thread array is indexed dynamically)
+  __shared__ int s_off[3 * kMaxLdsLevels];
+  if (threadIdx.x == 0) {
+    int q = (int)(sizeof(double2) * ((LC.na + 2) * (LC.nb + 2) + LC.na * LC.nb));
     for (int l = 0; l < cl; ++l) {
-      tab[l] = stage_tab<R>(LL.L[l], m, tr);
-      tr += 5 * LL.L[l].na + 4 * LL.L[l].nb;
+      s_off[l] = q;
+      q += (int)sizeof(V) * (LL.L[l].na + 2) * (LL.L[l].nb + 2);
+      s_off[kMaxLdsLevels + l] = q;
+      q += (int)sizeof(V) * LL.L[l].na * LL.L[l].nb;
+    }
+    q += (int)sizeof(R) * LL.scratch;
+    s_off[2 * kMaxLdsLevels + cl] = q;  // coarsest tables (double)
+    q += (int)sizeof(double) * (5 * LC.na + 4 * LC.nb);
+    for (int l = 0; l < cl; ++l) {
+      s_off[2 * kMaxLdsLevels + l] = q;
+      q += (int)sizeof(R) * (5 * LL.L[l].na + 4 * LL.L[l].nb);
     }
   }
+  __syncthreads();
+  auto Ul = [&](int l) { return reinterpret_cast<V*>(smem + s_off[l]); };
+  auto Fl = [&](int l) { return reinterpret_cast<V*>(smem + s_off[kMaxLdsLevels + l]); };
+  auto Tl = [&](int l) {
+    return tab_at<R>(reinterpret_cast<R*>(smem + s_off[2 * kMaxLdsLevels + l]), LL.L[l].na, LL.L[l].nb);
+  };
+  R* cp = reinterpret_cast<R*>(smem + (cl > 0 ? s_off[kMaxLdsLevels + cl - 1] + (int)sizeof(V) * LL.L[cl - 1].na * LL.L[cl - 1].nb
+                                               : (int)(sizeof(double2) * ((LC.na + 2) * (LC.nb + 2) + LC.na * LC.nb))));
+  Tab<double> tabC = stage_tab<double>(LC, m, reinterpret_cast<double*>(smem + s_off[2 * kMaxLdsLevels + cl]));
+  for (int l = 0; l < cl; ++l) (void)stage_tab<R>(LL.L[l], m, reinterpret_cast<R*>(smem + s_off[2 * kMaxLdsLevels + l]));
   // level 0 of the fused range: load f (and u for a full in-LDS cycle)
   {
     const LevelDev& L0 = LL.L[0];
@@ -222,9 +239,9 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict
         const int i = t / nc - 1, j = t % nc - 1;
         V v = mkv<R>(0, 0);
         if (load_u && i >= 0 && i < na && j >= 0 && j < nb) v = Ug[off + (size_t)i * nb + j];
-        u[0][t] = v;
+        Ul(0)[t] = v;
       }
-      for (int t = threadIdx.x; t < na * nb; t += blockDim.x) f[0][t] = Fg[off + t];
+      for (int t = threadIdx.x; t < na * nb; t += blockDim.x) Fl(0)[t] = Fg[off + t];
     } else {
       for (int t = threadIdx.x; t < na * nb; t += blockDim.x) fC[t] = make_double2(Fg[off + t].x, Fg[off + t].y);
     }
@@ -234,11 +251,14 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict
   for (int l = 0; l < cl; ++l) {
     const LevelDev& L = LL.L[l];
     const LevelDev& C = LL.L[l + 1];
-    for (int k = 0; k < nu_pre; ++k) smooth_step<R>(L, tab[l], u[l], f[l], n_sor, exact, cp);
+    const Tab<R> T = Tl(l);
+    V* ul = Ul(l);
+    const V* fl = Fl(l);
+    for (int k = 0; k < nu_pre; ++k) smooth_step<R>(L, T, ul, fl, n_sor, exact, cp);
     const int ncc = C.nb + 2;
     for (int t = threadIdx.x; t < (C.na + 2) * ncc; t += blockDim.x) {
       if (l + 1 == cl) uC[t] = make_double2(0.0, 0.0);
-      else u[l + 1][t] = mkv<R>(0, 0);
+      else Ul(l + 1)[t] = mkv<R>(0, 0);
     }
     for (int t = threadIdx.x; t < C.na * C.nb; t += blockDim.x) {
       const int I = t / C.nb, J = t - I * C.nb;
@@ -246,12 +266,12 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
           const R w = (R)L.rwa[2 * I + a] * (R)L.rwb[2 * J + b];
-          const V r = resid_lds<R>(L, tab[l], u[l], f[l], 2 * I + a, 2 * J + b);
+          const V r = resid_lds<R>(L, T, ul, fl, 2 * I + a, 2 * J + b);
           ax = fma(w, r.x, ax);
           ay = fma(w, r.y, ay);
         }
       if (l + 1 == cl) fC[t] = make_double2(ax, ay);
-      else f[l + 1][t] = mkv<R>(ax, ay);
+      else Fl(l + 1)[t] = mkv<R>(ax, ay);
     }
     __syncthreads();
   }
@@ -320,6 +340,9 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict
     const LevelDev& C = LL.L[l + 1];
     const int nb = L.nb, nc = nb + 2, ncc = C.nb + 2;
     const int par = m & 1;
+    const Tab<R> T = Tl(l);
+    V* ul = Ul(l);
+    const V* fl = Fl(l);
     for (int t = threadIdx.x; t < L.na * nb; t += blockDim.x) {
       const int i = t / nb, j = t - i * nb;
       const int a0 = L.pa_i0[i], a1 = L.pa_i1[i];
@@ -333,7 +356,7 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict
         e00x = (R)a.x; e00y = (R)a.y; e01x = (R)b.x; e01y = (R)b.y;
         e10x = (R)c.x; e10y = (R)c.y; e11x = (R)d.x; e11y = (R)d.y;
       } else {
-        const V* uc = u[l + 1];
+        const V* uc = Ul(l + 1);
         const V a = uc[(a0 + 1) * ncc + b0 + 1], b = uc[(a0 + 1) * ncc + b1 + 1];
         const V c = uc[(a1 + 1) * ncc + b0 + 1], d = uc[(a1 + 1) * ncc + b1 + 1];
         e00x = a.x; e00y = a.y; e01x = b.x; e01y = b.y; e10x = c.x; e10y = c.y; e11x = d.x; e11y = d.y;
@@ -344,10 +367,10 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict
       ex = fma(wa1 * wb0, e10x, ex); ey = fma(wa1 * wb0, e10y, ey);
       ex = fma(wa1 * wb1, e11x, ex); ey = fma(wa1 * wb1, e11y, ey);
       const int qq = (i + 1) * nc + (j + 1);
-      u[l][qq] = mkv<R>(u[l][qq].x + ex, u[l][qq].y + ey);
+      ul[qq] = mkv<R>(ul[qq].x + ex, ul[qq].y + ey);
     }
     __syncthreads();
-    for (int k = 0; k < nu_post; ++k) smooth_step<R>(L, tab[l], u[l], f[l], n_sor, exact, cp);
+    for (int k = 0; k < nu_post; ++k) smooth_step<R>(L, T, ul, fl, n_sor, exact, cp);
   }
   {
     const LevelDev& L0 = LL.L[0];
@@ -356,7 +379,7 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict
     for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
       const int i = t / nb, j = t - i * nb;
       if (n > 1) {
-        Ug[off + t] = u[0][(i + 1) * nc + (j + 1)];
+        Ug[off + t] = Ul(0)[(i + 1) * nc + (j + 1)];
       } else {
         const double2 v = uC[(i + 1) * nc + (j + 1)];
         Ug[off + t] = mkv<R>((R)v.x, (R)v.y);

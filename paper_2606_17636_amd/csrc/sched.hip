@@ -7,26 +7,28 @@
 
 namespace {
 
-constexpr int kConvThreads = 1024;
-constexpr int kPerThread = 4;      // list capacity kConvThreads * kPerThread
+constexpr int kConvThreads = 256;
+constexpr int kPerThread = 16;     // list capacity kConvThreads * kPerThread
 constexpr int kMaxProblems = 256;  // problems one batch can hold
 
-// Exclusive prefix sum over the block of one int per thread; returns the
-// thread's offset and writes the total to *total.
-__device__ int block_scan(int v, int* buf, int* total) {
-  const int t = threadIdx.x;
-  buf[t] = v;
-  __syncthreads();
-  for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-    const int add = t >= o ? buf[t - o] : 0;
-    __syncthreads();
-    buf[t] += add;
-    __syncthreads();
+// Exclusive prefix sum over the block of one int per thread (wave shuffles,
+// then the wave totals); returns the thread's offset and the block total.
+__device__ int block_scan(int v, int* wsum, int* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
   }
-  const int incl = buf[t];
-  if (t == (int)blockDim.x - 1) *total = incl;
+  if (lane == 63) wsum[w] = x;
   __syncthreads();
-  return incl - v;
+  int before = 0, all = 0;
+  for (int k = 0; k < nw; ++k) {
+    before += k < w ? wsum[k] : 0;
+    all += wsum[k];
+  }
+  *total = all;
+  return before + x - v;
 }
 
 __device__ double sum_partial(const double* partial, int p, int nblk) {
@@ -40,12 +42,13 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_init(const NormJob* __res
                                                            int nblk, double tol, double floor_factor, ConvState cs,
                                                            int* __restrict__ list, int* __restrict__ count) {
   __shared__ unsigned long long dmax[kMaxProblems];
-  __shared__ int buf[kConvThreads];
-  __shared__ int total;
+  __shared__ int buf[kConvThreads / 64];
+  int total;
   for (int q = threadIdx.x; q < n_prob; q += blockDim.x) dmax[q] = 0ull;
   __syncthreads();
   int e[kPerThread], g[kPerThread];
   double d[kPerThread];
+#pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
     const int p = threadIdx.x * kPerThread + k;
     e[k] = -1;
@@ -63,6 +66,7 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_init(const NormJob* __res
   __syncthreads();
   int keep = 0;
   bool kk[kPerThread];
+#pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
     kk[k] = false;
     if (e[k] < 0) continue;
@@ -73,6 +77,7 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_init(const NormJob* __res
     keep += kk[k] ? 1 : 0;
   }
   int off = block_scan(keep, buf, &total);
+#pragma unroll
   for (int k = 0; k < kPerThread; ++k)
     if (kk[k]) list[off++] = e[k];
   if (threadIdx.x == 0) *count = total;
@@ -82,12 +87,13 @@ __global__ void __launch_bounds__(kConvThreads) k_converge(const NormJob* __rest
                                                           const double* __restrict__ partial, int nblk, ConvState cs,
                                                           int max_cycles, int count_cycle, int* __restrict__ list,
                                                           int* __restrict__ count) {
-  __shared__ int buf[kConvThreads];
-  __shared__ int total;
+  __shared__ int buf[kConvThreads / 64];
+  int total;
   const int n = *count;  // every thread reads it before the block writes it
   int e[kPerThread];
   bool kk[kPerThread];
   int keep = 0;
+#pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
     const int p = threadIdx.x * kPerThread + k;
     e[k] = -1;
@@ -106,7 +112,8 @@ __global__ void __launch_bounds__(kConvThreads) k_converge(const NormJob* __rest
     }
     keep += kk[k] ? 1 : 0;
   }
-  int off = block_scan(keep, buf, &total);  // contains barriers: all list reads are done
+  int off = block_scan(keep, buf, &total);  // contains a barrier: all list reads are done
+#pragma unroll
   for (int k = 0; k < kPerThread; ++k)
     if (kk[k]) list[off++] = e[k];
   if (threadIdx.x == 0) *count = total;
