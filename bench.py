@@ -65,13 +65,14 @@ def cpu_baseline(workload, tol, budget_s):
                        f"first solve incl. factorisation {t_first:.2f}s; DGF zeros, setup excluded)")
 
 
-def _plan(smg, g, form, line_solver):
+def _plan(smg, g, form, line_solver, max_cycles=60):
     """The chosen form (mixed precision, scheduled graph replay, autotuned
     launch shapes) or the plain GPU form (FP64, host reads after every
-    V-cycle, built-in launch shapes)."""
+    V-cycle, built-in launch shapes, the paper's SOR line smoother)."""
     if form == "chosen":
-        return smg.Plan(**g, precision="mixed", launch="graph", autotune=True, line_solver=line_solver)
-    return smg.Plan(**g, precision="fp64", launch="dynamic", autotune=False, line_solver=line_solver)
+        return smg.Plan(**g, precision="mixed", launch="graph", autotune=True, line_solver=line_solver,
+                        max_cycles=max_cycles)
+    return smg.Plan(**g, precision="fp64", launch="dynamic", autotune=False, line_solver="sor", max_cycles=max_cycles)
 
 
 def _timed(plan, rho, phi, steps, tol, torch):
@@ -81,6 +82,74 @@ def _timed(plan, rho, phi, steps, tol, torch):
         plan.solve_nosync(rho, phi, tol=tol)
     torch.cuda.synchronize()
     return time.perf_counter() - t0
+
+
+def bench_batch(args, smg, configs, torch):
+    """The 16-problem batch: one batched solve of all problems per step
+    (chosen form) against the plain GPU form solving them one by one."""
+    grids = configs.c4_grids()
+    log(f"workload c4: {configs.DESCRIPTION['c4']}")
+    t0 = time.perf_counter()
+    plans = [_plan(smg, g, "chosen", args.line_solver, 200).setup("cuda:0") for g in grids]
+    batch = smg.Batch(plans).setup("cuda:0")
+    torch.cuda.synchronize()
+    log(f"setup of {len(plans)} plans + batch {time.perf_counter() - t0:.1f}s; "
+        f"{sum(p.n_modes for p in plans)} mode planes")
+    rhos, phis = [], []
+    for q, (g, p) in enumerate(zip(grids, plans)):
+        a, b, ph, _ = p.geometry()
+        rhos.append(torch.from_numpy(configs.c4_density(q, g, a, b, ph)).to("cuda:0"))
+        phis.append(torch.empty_like(rhos[-1]))
+    for _ in range(max(args.warmup, 2)):
+        batch.solve(rhos, tol=args.tol, outs=phis, info=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.solve(rhos, tol=args.tol, outs=phis, info=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = len(plans)
+    value = n * args.steps / dt
+    _, infos = batch.solve(rhos, tol=args.tol, outs=phis, timings=True)
+    log(f"batched: {value:.2f} solves/s ({1e3 * dt / args.steps:.2f} ms per batch of {n})")
+    out = {
+        "metric": "Poisson solves/s at rel. residual 1e-8",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"c4: {configs.DESCRIPTION['c4']}", "tol": args.tol, "form": "chosen, one batch",
+                   "line_solver": args.line_solver,
+                   "problems": n, "step": "one batched solve of all problems",
+                   "v_cycles_per_step": int(sum(i["total_cycles"] for i in infos)),
+                   "converged": all(i["converged"] for i in infos)},
+        "roofline": None,
+    }
+    if not args.no_plain:
+        plain = [_plan(smg, g, "plain", args.line_solver, 200).setup("cuda:0") for g in grids]
+        for _ in range(max(args.warmup, 2)):
+            for p, r, o in zip(plain, rhos, phis):
+                p.solve_nosync(r, o, tol=args.tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for p, r, o in zip(plain, rhos, phis):
+                p.solve_nosync(r, o, tol=args.tol)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t0
+        out["plain_gpu"] = dict(value=round(n * args.steps / dtp, 3), unit="solves/s",
+                                ms_per_step=round(1e3 * dtp / args.steps, 3),
+                                form="FP64, problems one after another, host reads after every V-cycle")
+        out["speedup_vs_plain"] = round(dtp / dt, 3)
+        log(f"plain GPU form: {n * args.steps / dtp:.2f} solves/s")
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -118,6 +187,8 @@ def main():
     from paper_2606_17636_amd import smg
     from workloads import configs
 
+    if args.workload == "c4":
+        return bench_batch(args, smg, configs, torch)
     g = configs.GRIDS[args.workload]
     log(f"workload {args.workload}: {configs.DESCRIPTION[args.workload]}")
     plan = _plan(smg, g, args.form, args.line_solver)

@@ -160,6 +160,31 @@ smg_status smg_plan_destroy(smg_plan *plan);
 /* Thread-local message of the last failing call ("" if none). */
 const char *smg_last_error(void);
 
+/* ---- batches: several problems in every launch ---------------------------
+ * The multigrid solves of several set-up plans run together: every kernel
+ * launch of a V-cycle covers the unconverged mode planes of all plans (each
+ * with its own grid, tables and launch shape), the convergence lists span
+ * the batch, and the per-mode cycle schedule and graph replay of the
+ * SMG_LAUNCH_GRAPH form apply to the batch as a whole.  The plans must share
+ * precision, line solver, nu_pre, nu_post and n_sor (SMG_EINVAL), hold at
+ * most 4096 mode planes together, and stay set up while the batch is used.
+ * Each plan keeps its own workspace (its mode arrays are the ones solved);
+ * the batch needs a small workspace of its own for its tables and lists.
+ * A batch solve and a solve of one of its plans must not overlap in time;
+ * SMG_WARM_PREV starts from the plans' last Psi^m / Phi^m. */
+typedef struct smg_batch smg_batch;
+smg_status smg_batch_create(smg_plan *const *plans, int n_plans, smg_batch **out);
+size_t smg_batch_workspace_bytes(const smg_batch *batch);
+/* Bind the batch workspace (256-byte aligned); tunes the launch shapes of
+ * the batch when plans[0] was created with opts.autotune. */
+smg_status smg_batch_setup(smg_batch *batch, void *workspace_dev, size_t workspace_bytes, void *stream);
+/* rho_dev[q] -> phi_dev[q] for plan q as smg_solve does; infos_host: NULL or
+ * n_plans reports (component times are those of the whole batch). */
+smg_status smg_batch_solve(smg_batch *batch, const double *const *rho_dev, double *const *phi_dev, double rel_tol,
+                           unsigned flags, void *stream, smg_info *infos_host);
+const char *smg_batch_tune_report(const smg_batch *batch);
+smg_status smg_batch_destroy(smg_batch *batch);
+
 /* ---- geometry query (host, no device work) ------------------------------ */
 /* Cell-centre coordinates: a_host[n_a], b_host[n_b], phi_host[n_phi]
  * (volume-weighted centroids of Eq. cell_centers_sph and Sec. 2.1.2), and

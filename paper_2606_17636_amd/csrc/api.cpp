@@ -129,6 +129,40 @@ struct GraphEnt {
 constexpr int kMaxGraphs = 8;
 }  // namespace
 
+// Plans whose multigrid solves share one engine (a plan alone, or a batch):
+// per-mode cycle history, solve graphs and their capture stream.
+struct Group {
+  std::vector<smg_plan*> plans;
+  Engine* eng = nullptr;
+  int launch = SMG_LAUNCH_GRAPH;
+  int max_cycles = 60;
+  bool have_prev = false;
+  // per-mode cycle counts of the last solve, per initial-guess kind (0 zero,
+  // 1 warm) and target: the schedule of the next solve of that kind
+  std::vector<int> hist[2][2];
+  bool hist_ok[2] = {false, false};
+  std::vector<GraphEnt> graphs;
+  unsigned long long clock = 0;
+  hipStream_t cap_stream = nullptr;  // private stream the solve graphs are captured on
+  void drop_graphs() {
+    for (GraphEnt& g : graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  }
+  void reset() {
+    have_prev = false;
+    hist_ok[0] = hist_ok[1] = false;
+    drop_graphs();
+  }
+  Group() = default;
+  Group(const Group&) = delete;
+  Group& operator=(const Group&) = delete;
+  ~Group() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+};
+
 struct smg_plan {
   Spec spec{};
   smg_opts opts{};
@@ -149,18 +183,11 @@ struct smg_plan {
   // bound workspace
   char* ws = nullptr;
   bool ready = false;
-  bool have_prev = false;
   double dgf_resid = 0.0;  // worst relative residual of the DGF solves
   std::vector<LevelDev> levels;
   Engine eng;               // targets: 0 = Psi (solve 1), 1 = Phi (solve 2)
+  Group grp;                // this plan alone
   std::string tune_report;
-  // per-mode cycle counts of the last solve, per initial-guess kind
-  // (0 zero, 1 warm) and target: the schedule of the next solve
-  std::vector<int> hist[2][2];
-  bool hist_ok[2] = {false, false};
-  std::vector<GraphEnt> graphs;
-  unsigned long long graph_clock = 0;
-  hipStream_t cap_stream = nullptr;  // private stream the solve graphs are captured on
   // per-launch event timing (smg_profile_begin / smg_profile_end)
   struct ProfRec { int cls, ev0, ev1; double bytes; };
   mutable bool prof_on = false;
@@ -168,14 +195,7 @@ struct smg_plan {
   mutable size_t prof_used = 0;
   mutable std::vector<ProfRec> prof_log;
   PlanProf prof_sink;
-  void drop_graphs() {
-    for (GraphEnt& g : graphs)
-      if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    graphs.clear();
-  }
   ~smg_plan() {
-    drop_graphs();
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
   }
   double2* dptr(size_t off) const { return reinterpret_cast<double2*>(ws + off); }
@@ -681,21 +701,11 @@ static smg_status dgf_extended(smg_plan& p, hipStream_t st) {
 // ----------------------------------------------------------------------------
 // setup and solve
 // ----------------------------------------------------------------------------
-extern "C" smg_status smg_plan_setup(smg_plan* p, void* workspace, size_t bytes, void* stream) {
-  if (!p) return fail(SMG_EINVAL, "NULL plan");
-  if (!workspace || bytes < p->w_total) return fail(SMG_EWORKSPACE, strprintf("workspace of %zu bytes needed", p->w_total));
-  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SMG_EWORKSPACE, "workspace must be 256-byte aligned");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  p->ws = static_cast<char*>(workspace);
-  p->ready = false;
-  p->have_prev = false;
-  p->hist_ok[0] = p->hist_ok[1] = false;
-  p->drop_graphs();
-  HIPCHK(hipMemcpyAsync(p->ws + p->w_blob, p->blob.bytes.data(), p->blob.bytes.size(), hipMemcpyHostToDevice, st));
+// The plan's multigrid as the engine sees it: targets 0 (Psi, right-hand
+// side f) and 1 (Phi^m, right-hand side f2).
+static MGProblem plan_problem(smg_plan* p) {
   const bool fp32 = p->opts.precision == SMG_MIXED;
   const int L = (int)p->H.lv.size();
-  p->levels.clear();
-  for (int l = 0; l < L; ++l) p->levels.push_back(level_view(p->ws + p->w_blob, p->loff[l], p->H.lv[l], p->M));
   MGProblem pr;
   pr.L = p->levels;
   pr.u.assign(L, nullptr);
@@ -716,19 +726,44 @@ extern "C" smg_status smg_plan_setup(smg_plan* p, void* workspace, size_t bytes,
     pr.e32 = reinterpret_cast<float2*>(p->ws + p->w_u32[0]);
   }
   pr.n = p->M;
+  return pr;
+}
+
+static MGParams plan_params(const smg_plan* p) {
   MGParams prm;
   prm.nu_pre = p->opts.nu_pre;
   prm.nu_post = p->opts.nu_post;
   prm.n_sor = p->opts.n_sor;
   prm.exact = p->opts.line_solver == SMG_LINE_EXACT;
-  prm.fp32 = fp32;
+  prm.fp32 = p->opts.precision == SMG_MIXED;
   prm.coarse_rtol = kCoarseRtol;
   prm.coarse_sweeps = kCoarseSweeps;
+  return prm;
+}
+
+extern "C" smg_status smg_plan_setup(smg_plan* p, void* workspace, size_t bytes, void* stream) {
+  if (!p) return fail(SMG_EINVAL, "NULL plan");
+  if (!workspace || bytes < p->w_total) return fail(SMG_EWORKSPACE, strprintf("workspace of %zu bytes needed", p->w_total));
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SMG_EWORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  p->ws = static_cast<char*>(workspace);
+  p->ready = false;
+  p->grp.reset();
+  HIPCHK(hipMemcpyAsync(p->ws + p->w_blob, p->blob.bytes.data(), p->blob.bytes.size(), hipMemcpyHostToDevice, st));
+  p->levels.clear();
+  for (size_t l = 0; l < p->H.lv.size(); ++l)
+    p->levels.push_back(level_view(p->ws + p->w_blob, p->loff[l], p->H.lv[l], p->M));
+  MGProblem pr = plan_problem(p);
+  MGParams prm = plan_params(p);
   std::string emsg;
   smg_status es = p->eng.init({pr}, 2, prm, p->ws + p->w_eng, p->w_eng_bytes, st, &emsg);
   if (es != SMG_OK) return fail(es, "multigrid engine: " + emsg);
   p->prof_sink.p = p;
   p->eng.set_prof(&p->prof_sink);
+  p->grp.plans = {p};
+  p->grp.eng = &p->eng;
+  p->grp.launch = p->opts.launch;
+  p->grp.max_cycles = p->opts.max_cycles;
   smg_status s = dgf_method_of(*p) == SMG_DGF_EXTENDED ? dgf_extended(*p, st) : dgf_aux(*p, st);
   if (s != SMG_OK) return s;
   if (p->opts.autotune) {
@@ -787,35 +822,43 @@ static std::vector<int> schedule_of(const std::vector<int>& cyc) {
   return caps;
 }
 
+static smg_status james_all(Group& g, hipStream_t st) {
+  for (smg_plan* p : g.plans)
+    STCHK(james_steps(p, p->dptr(p->w_psi), p->dptr(p->w_f), p->dptr(p->w_sigma), p->dptr(p->w_theta),
+                      p->dptr(p->w_f2), st));
+  return SMG_OK;
+}
+
 // The body of a solve between the two FFTs: solve 1 into Psi, the James
-// steps, solve 2 into Phi^m.  With schedules, every cycle is enqueued up
-// front (no host synchronisation); otherwise each solve reads its list
-// length after every cycle.  ev (optional) records 4 component boundaries.
-static smg_status solve_body(smg_plan* p, double tol, bool warm, const std::vector<int>* sched0,
+// steps, solve 2 into Phi^m, for every plan of the group.  With schedules,
+// every cycle is enqueued up front (no host synchronisation); otherwise
+// each solve reads its list length after every cycle.  ev (optional)
+// records 3 component boundaries.
+static smg_status group_body(Group& g, double tol, bool warm, const std::vector<int>* sched0,
                              const std::vector<int>* sched1, hipStream_t st, hipEvent_t* ev) {
-  const int maxc = p->opts.max_cycles;
-  STCHK(p->eng.start(0, tol, kFloor, warm, maxc, st));
+  Engine& e = *g.eng;
+  STCHK(e.start(0, tol, kFloor, warm, g.max_cycles, st));
   if (sched0) {
-    for (int cap : *sched0) STCHK(p->eng.cycle(0, cap, st));
+    for (int cap : *sched0) STCHK(e.cycle(0, cap, st));
   } else {
-    STCHK(p->eng.finish_dynamic(0, st, nullptr));
+    STCHK(e.finish_dynamic(0, st, nullptr));
   }
   if (ev) HIPCHK(hipEventRecord(ev[0], st));
-  STCHK(james_steps(p, p->dptr(p->w_psi), p->dptr(p->w_f), p->dptr(p->w_sigma), p->dptr(p->w_theta), p->dptr(p->w_f2), st));
+  STCHK(james_all(g, st));
   if (ev) HIPCHK(hipEventRecord(ev[1], st));
-  STCHK(p->eng.start(1, tol, kFloor, warm, maxc, st));
+  STCHK(e.start(1, tol, kFloor, warm, g.max_cycles, st));
   if (sched1) {
-    for (int cap : *sched1) STCHK(p->eng.cycle(1, cap, st));
+    for (int cap : *sched1) STCHK(e.cycle(1, cap, st));
   } else {
-    STCHK(p->eng.finish_dynamic(1, st, nullptr));
+    STCHK(e.finish_dynamic(1, st, nullptr));
   }
   if (ev) HIPCHK(hipEventRecord(ev[2], st));
   return SMG_OK;
 }
 
-// Captured graph of solve_body for the two schedules (cached).
-static smg_status body_graph(smg_plan* p, double tol, bool warm, const std::vector<int>& s0, const std::vector<int>& s1,
-                             hipStream_t st, hipGraphExec_t* out) {
+// Captured graph of group_body for the two schedules (cached).
+static smg_status group_graph(Group& g, double tol, bool warm, const std::vector<int>& s0, const std::vector<int>& s1,
+                              hipGraphExec_t* out) {
   std::vector<int> key;
   key.push_back(warm ? 1 : 0);
   long long tb;
@@ -825,20 +868,19 @@ static smg_status body_graph(smg_plan* p, double tol, bool warm, const std::vect
   key.push_back((int)s0.size());
   key.insert(key.end(), s0.begin(), s0.end());
   key.insert(key.end(), s1.begin(), s1.end());
-  for (GraphEnt& g : p->graphs)
-    if (g.key == key) {
-      g.used = ++p->graph_clock;
-      *out = g.exec;
+  for (GraphEnt& ge : g.graphs)
+    if (ge.key == key) {
+      ge.used = ++g.clock;
+      *out = ge.exec;
       return SMG_OK;
     }
-  // captured on the plan's own stream (the caller's may be the null
+  // captured on the group's own stream (the caller's may be the null
   // stream, which cannot capture) and launched on the caller's
-  (void)st;
-  if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  if (!g.cap_stream) HIPCHK(hipStreamCreateWithFlags(&g.cap_stream, hipStreamNonBlocking));
   hipGraph_t graph = nullptr;
-  HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-  smg_status sb = solve_body(p, tol, warm, &s0, &s1, p->cap_stream, nullptr);
-  hipError_t ce = hipStreamEndCapture(p->cap_stream, &graph);
+  HIPCHK(hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeThreadLocal));
+  smg_status sb = group_body(g, tol, warm, &s0, &s1, g.cap_stream, nullptr);
+  hipError_t ce = hipStreamEndCapture(g.cap_stream, &graph);
   if (sb != SMG_OK) {
     if (graph) (void)hipGraphDestroy(graph);
     return sb;
@@ -848,25 +890,51 @@ static smg_status body_graph(smg_plan* p, double tol, bool warm, const std::vect
   hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   HIPCHK(ie);
-  if ((int)p->graphs.size() >= kMaxGraphs) {
-    auto lru = std::min_element(p->graphs.begin(), p->graphs.end(),
+  if ((int)g.graphs.size() >= kMaxGraphs) {
+    auto lru = std::min_element(g.graphs.begin(), g.graphs.end(),
                                 [](const GraphEnt& a, const GraphEnt& b) { return a.used < b.used; });
     (void)hipGraphExecDestroy(lru->exec);
-    p->graphs.erase(lru);
+    g.graphs.erase(lru);
   }
-  p->graphs.push_back(GraphEnt{key, exec, ++p->graph_clock});
+  g.graphs.push_back(GraphEnt{key, exec, ++g.clock});
   *out = exec;
   return SMG_OK;
 }
 
-extern "C" smg_status smg_solve(smg_plan* p, const double* rho, double* phi, double tol, unsigned flags, void* stream,
-                                smg_info* info) {
-  STCHK(need_ready(p));
-  if (!rho || !phi) return fail(SMG_EINVAL, "rho and phi must not be NULL");
+static smg_status fft_forward_all(Group& g, const double* const* rho, hipStream_t st) {
+  for (size_t q = 0; q < g.plans.size(); ++q) {
+    smg_plan* p = g.plans[q];
+    const Spec& s = p->spec;
+    const int lines = s.n_a * s.n_b;
+    const double2* tw = reinterpret_cast<const double2*>(p->ws + p->w_blob + p->o_tw);
+    int pe = prof_mark(*p, st);
+    HIPCHK(smgk::fft_r2c(rho[q], p->dptr(p->w_f), lines, s.n_phi, 4.0 * kPi * s.G / s.n_phi, tw, st));
+    prof_close(*p, K_FFT_R2C, pe, (double)lines * (8.0 * s.n_phi + 16.0 * p->M), st);
+  }
+  return SMG_OK;
+}
+
+static smg_status fft_inverse_all(Group& g, double* const* phi, hipStream_t st) {
+  for (size_t q = 0; q < g.plans.size(); ++q) {
+    smg_plan* p = g.plans[q];
+    const Spec& s = p->spec;
+    const int lines = s.n_a * s.n_b;
+    const double2* tw = reinterpret_cast<const double2*>(p->ws + p->w_blob + p->o_tw);
+    int pe = prof_mark(*p, st);
+    HIPCHK(smgk::fft_c2r(p->dptr(p->w_phi), phi[q], lines, s.n_phi, tw, st));
+    prof_close(*p, K_FFT_C2R, pe, (double)lines * (8.0 * s.n_phi + 16.0 * p->M), st);
+  }
+  return SMG_OK;
+}
+
+// The seven steps for every plan of the group.  infos: one per plan or NULL.
+static smg_status group_solve(Group& g, const double* const* rho, double* const* phi, double tol, unsigned flags,
+                              hipStream_t st, smg_info* infos, bool profiling) {
+  const int P = (int)g.plans.size();
+  for (int q = 0; q < P; ++q)
+    if (!rho[q] || !phi[q]) return fail(SMG_EINVAL, "rho and phi must not be NULL");
   if (!(tol > 0.0)) return fail(SMG_EINVAL, "rel_tol must be > 0");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const Spec& s = p->spec;
-  const bool timings = (flags & SMG_TIMINGS) && info;
+  const bool timings = (flags & SMG_TIMINGS) && infos;
   hipEvent_t ev[6] = {};
   if (timings)
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
@@ -874,88 +942,181 @@ extern "C" smg_status smg_solve(smg_plan* p, const double* rho, double* phi, dou
     hipEvent_t* e; bool on;
     ~EvGuard() { if (on) for (int k = 0; k < 6; ++k) (void)hipEventDestroy(e[k]); }
   } guard{ev, timings};
-  const char* base = p->ws + p->w_blob;
-  const double2* tw = reinterpret_cast<const double2*>(base + p->o_tw);
-  const bool warm = (flags & SMG_WARM_PREV) && p->have_prev;
+  const bool warm = (flags & SMG_WARM_PREV) && g.have_prev;
   const int wk = warm ? 1 : 0;
-  const int lines = s.n_a * s.n_b;
   // scheduled launches (one host synchronisation per solve) once a previous
   // solve of the same kind gave the per-mode cycle counts; per-cycle host
   // reads for the first solve, for profiling and with SMG_LAUNCH_DYNAMIC
-  const bool sched = p->opts.launch == SMG_LAUNCH_GRAPH && p->hist_ok[wk] && !p->prof_on;
+  const bool sched = g.launch == SMG_LAUNCH_GRAPH && g.hist_ok[wk] && !profiling;
   const bool graph = sched && !timings;
   if (timings) HIPCHK(hipEventRecord(ev[0], st));
-  const double fft_bytes = (double)lines * (8.0 * s.n_phi + 16.0 * p->M);
-  int pe = prof_mark(*p, st);
-  HIPCHK(smgk::fft_r2c(rho, p->dptr(p->w_f), lines, s.n_phi, 4.0 * kPi * s.G / s.n_phi, tw, st));
-  prof_close(*p, K_FFT_R2C, pe, fft_bytes, st);
+  STCHK(fft_forward_all(g, rho, st));
   if (timings) HIPCHK(hipEventRecord(ev[1], st));
   std::vector<int> s0, s1;
   if (sched) {
-    s0 = schedule_of(p->hist[wk][0]);
-    s1 = schedule_of(p->hist[wk][1]);
+    s0 = schedule_of(g.hist[wk][0]);
+    s1 = schedule_of(g.hist[wk][1]);
   }
   if (graph) {
     hipGraphExec_t exec = nullptr;
-    STCHK(body_graph(p, tol, warm, s0, s1, st, &exec));
+    STCHK(group_graph(g, tol, warm, s0, s1, &exec));
     HIPCHK(hipGraphLaunch(exec, st));
   } else {
-    STCHK(solve_body(p, tol, warm, sched ? &s0 : nullptr, sched ? &s1 : nullptr, st, timings ? ev + 2 : nullptr));
+    STCHK(group_body(g, tol, warm, sched ? &s0 : nullptr, sched ? &s1 : nullptr, st, timings ? ev + 2 : nullptr));
   }
-  pe = prof_mark(*p, st);
-  HIPCHK(smgk::fft_c2r(p->dptr(p->w_phi), phi, lines, s.n_phi, tw, st));
-  prof_close(*p, K_FFT_C2R, pe, fft_bytes, st);
+  STCHK(fft_inverse_all(g, phi, st));
   if (timings) HIPCHK(hipEventRecord(ev[5], st));
-  p->have_prev = true;
+  g.have_prev = true;
   // per-mode state of both solves (one synchronisation); modes that needed
   // more cycles than the schedule gave them are finished here and the
-  // inverse transform is repeated
+  // inverse transforms are repeated
+  Engine& e = *g.eng;
   Engine::State es;
-  STCHK(p->eng.read_all(st, &es));
+  STCHK(e.read_all(st, &es));
   if (es.count[0] > 0 || es.count[1] > 0) {
     if (es.count[0] > 0) {
-      STCHK(p->eng.finish_dynamic(0, st, nullptr));
-      STCHK(james_steps(p, p->dptr(p->w_psi), p->dptr(p->w_f), p->dptr(p->w_sigma), p->dptr(p->w_theta),
-                        p->dptr(p->w_f2), st));
+      STCHK(e.finish_dynamic(0, st, nullptr));
+      STCHK(james_all(g, st));
       // Phi^m holds the result for the old boundary data: a good guess
-      STCHK(p->eng.start(1, tol, kFloor, true, p->opts.max_cycles, st));
+      STCHK(e.start(1, tol, kFloor, true, g.max_cycles, st));
     }
-    STCHK(p->eng.finish_dynamic(1, st, nullptr));
-    HIPCHK(smgk::fft_c2r(p->dptr(p->w_phi), phi, lines, s.n_phi, tw, st));
-    STCHK(p->eng.read_all(st, &es));
+    STCHK(e.finish_dynamic(1, st, nullptr));
+    STCHK(fft_inverse_all(g, phi, st));
+    STCHK(e.read_all(st, &es));
   }
-  std::vector<int>* cyc = es.cyc.data();
-  std::vector<double>* cur = es.cur.data();
-  std::vector<double>* thr = es.thr.data();
   bool converged = true;
   for (int t = 0; t < 2; ++t)
-    for (int m = 0; m < p->M; ++m)
-      if (!(cur[t][m] <= thr[t][m])) converged = false;
-  if (converged && p->opts.launch == SMG_LAUNCH_GRAPH) {
-    // a mode that took one cycle more than scheduled keeps its new count
-    p->hist[wk][0] = cyc[0];
-    p->hist[wk][1] = cyc[1];
-    p->hist_ok[wk] = true;
+    for (int k = 0; k < e.n_planes(); ++k)
+      if (!(es.cur[t][k] <= es.thr[t][k])) converged = false;
+  if (converged && g.launch == SMG_LAUNCH_GRAPH) {
+    // a mode that took more cycles than scheduled keeps its new count
+    g.hist[wk][0] = es.cyc[0];
+    g.hist[wk][1] = es.cyc[1];
+    g.hist_ok[wk] = true;
   }
-  if (info) {
-    info->n_modes = p->M;
-    info->total_cycles = 0;
-    for (int m = 0; m < p->M; ++m) {
-      const double den0 = thr[0][m] / tol, den1 = thr[1][m] / tol;
-      if (info->cycles1) info->cycles1[m] = cyc[0][m];
-      if (info->cycles2) info->cycles2[m] = cyc[1][m];
-      if (info->resid1) info->resid1[m] = den0 > 0.0 ? cur[0][m] / den0 : 0.0;
-      if (info->resid2) info->resid2[m] = den1 > 0.0 ? cur[1][m] / den1 : 0.0;
-      info->total_cycles += cyc[0][m] + cyc[1][m];
-    }
-    info->converged = converged ? 1 : 0;
-    if (timings) {
-      float t[5];
+  if (infos) {
+    float t[5] = {0, 0, 0, 0, 0};
+    if (timings)
       for (int k = 0; k < 5; ++k) HIPCHK(hipEventElapsedTime(&t[k], ev[k], ev[k + 1]));
-      info->ms_fft = t[0]; info->ms_mg1 = t[1]; info->ms_james = t[2]; info->ms_mg2 = t[3]; info->ms_ifft = t[4];
+    for (int q = 0; q < P; ++q) {
+      smg_info* info = infos + q;
+      const int M = g.plans[q]->M, b0 = e.base(q);
+      info->n_modes = M;
+      info->total_cycles = 0;
+      bool ok = true;
+      for (int m = 0; m < M; ++m) {
+        const int k = b0 + m;
+        const double den0 = es.thr[0][k] / tol, den1 = es.thr[1][k] / tol;
+        if (info->cycles1) info->cycles1[m] = es.cyc[0][k];
+        if (info->cycles2) info->cycles2[m] = es.cyc[1][k];
+        if (info->resid1) info->resid1[m] = den0 > 0.0 ? es.cur[0][k] / den0 : 0.0;
+        if (info->resid2) info->resid2[m] = den1 > 0.0 ? es.cur[1][k] / den1 : 0.0;
+        info->total_cycles += es.cyc[0][k] + es.cyc[1][k];
+        if (!(es.cur[0][k] <= es.thr[0][k]) || !(es.cur[1][k] <= es.thr[1][k])) ok = false;
+      }
+      info->converged = ok ? 1 : 0;
+      if (timings) {
+        info->ms_fft = t[0]; info->ms_mg1 = t[1]; info->ms_james = t[2]; info->ms_mg2 = t[3]; info->ms_ifft = t[4];
+      }
     }
   }
   if (!converged) return fail(SMG_ENOCONV, "a mode did not reach the tolerance within max_cycles");
+  return SMG_OK;
+}
+
+extern "C" smg_status smg_solve(smg_plan* p, const double* rho, double* phi, double tol, unsigned flags, void* stream,
+                                smg_info* info) {
+  STCHK(need_ready(p));
+  return group_solve(p->grp, &rho, &phi, tol, flags, static_cast<hipStream_t>(stream), info, p->prof_on);
+}
+
+// ----------------------------------------------------------------------------
+// batches of plans: one engine over every plan's planes
+// ----------------------------------------------------------------------------
+struct smg_batch {
+  std::vector<smg_plan*> plans;
+  Engine eng;
+  Group grp;
+  int n_total = 0, max_levels = 0;
+  size_t w_total = 0;
+  bool ready = false;
+  std::string tune_report;
+};
+
+extern "C" smg_status smg_batch_create(smg_plan* const* plans, int n_plans, smg_batch** out) {
+  if (!plans || !out) return fail(SMG_EINVAL, "plans and out must not be NULL");
+  *out = nullptr;
+  if (n_plans < 1 || n_plans > 256) return fail(SMG_EINVAL, "a batch holds 1 to 256 plans");
+  std::unique_ptr<smg_batch> b(new (std::nothrow) smg_batch());
+  if (!b) return fail(SMG_EINVAL, "out of host memory");
+  const smg_opts& o0 = plans[0] ? plans[0]->opts : smg_opts{};
+  for (int q = 0; q < n_plans; ++q) {
+    smg_plan* p = plans[q];
+    if (!p) return fail(SMG_EINVAL, "NULL plan in batch");
+    for (int r = 0; r < q; ++r)
+      if (plans[r] == p) return fail(SMG_EINVAL, "a plan appears twice in the batch");
+    const smg_opts& o = p->opts;
+    if (o.precision != o0.precision || o.line_solver != o0.line_solver || o.nu_pre != o0.nu_pre ||
+        o.nu_post != o0.nu_post || o.n_sor != o0.n_sor)
+      return fail(SMG_EINVAL, "plans of a batch must share precision, line solver, nu_pre, nu_post and n_sor");
+    b->plans.push_back(p);
+    b->n_total += p->M;
+    b->max_levels = std::max(b->max_levels, (int)p->H.lv.size());
+  }
+  if (b->n_total > Engine::kMaxPlanes) return fail(SMG_EINVAL, strprintf("a batch holds at most %d mode planes", Engine::kMaxPlanes));
+  b->w_total = Engine::region_bytes(2, n_plans, b->max_levels, b->n_total);
+  *out = b.release();
+  return SMG_OK;
+}
+
+extern "C" size_t smg_batch_workspace_bytes(const smg_batch* b) { return b ? b->w_total : 0; }
+
+extern "C" smg_status smg_batch_setup(smg_batch* b, void* workspace, size_t bytes, void* stream) {
+  if (!b) return fail(SMG_EINVAL, "NULL batch");
+  if (!workspace || bytes < b->w_total) return fail(SMG_EWORKSPACE, strprintf("workspace of %zu bytes needed", b->w_total));
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SMG_EWORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  b->ready = false;
+  b->grp.reset();
+  std::vector<MGProblem> probs;
+  for (smg_plan* p : b->plans) {
+    if (!p->ready) return fail(SMG_ESTATE, "every plan of a batch must be set up first");
+    probs.push_back(plan_problem(p));
+  }
+  std::string emsg;
+  smg_status es = b->eng.init(probs, 2, plan_params(b->plans[0]), static_cast<char*>(workspace), bytes, st, &emsg);
+  if (es != SMG_OK) return fail(es, "batch engine: " + emsg);
+  b->grp.plans = b->plans;
+  b->grp.eng = &b->eng;
+  b->grp.launch = b->plans[0]->opts.launch;
+  b->grp.max_cycles = 0;
+  for (smg_plan* p : b->plans) b->grp.max_cycles = std::max(b->grp.max_cycles, p->opts.max_cycles);
+  if (b->plans[0]->opts.autotune) {
+    for (smg_plan* p : b->plans)
+      HIPCHK(smgk::fill_zero(p->dptr(p->w_f), (size_t)p->M * p->spec.n_a * p->spec.n_b, st));
+    STCHK(b->eng.start(0, 1e-8, kFloor, false, 1, st));
+    es = b->eng.autotune(0, st, &b->tune_report);
+    if (es != SMG_OK) return fail(es, "autotune: " + b->tune_report);
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  b->ready = true;
+  return SMG_OK;
+}
+
+extern "C" smg_status smg_batch_solve(smg_batch* b, const double* const* rho, double* const* phi, double tol,
+                                      unsigned flags, void* stream, smg_info* infos) {
+  if (!b) return fail(SMG_EINVAL, "NULL batch");
+  if (!b->ready) return fail(SMG_ESTATE, "batch is not set up (call smg_batch_setup first)");
+  if (!rho || !phi) return fail(SMG_EINVAL, "rho and phi must not be NULL");
+  for (smg_plan* p : b->plans)
+    if (!p->ready) return fail(SMG_ESTATE, "a plan of the batch is no longer set up");
+  return group_solve(b->grp, rho, phi, tol, flags, static_cast<hipStream_t>(stream), infos, false);
+}
+
+extern "C" const char* smg_batch_tune_report(const smg_batch* b) { return b ? b->tune_report.c_str() : ""; }
+
+extern "C" smg_status smg_batch_destroy(smg_batch* b) {
+  delete b;
   return SMG_OK;
 }
 
@@ -986,7 +1147,7 @@ static smg_status stage_in(smg_plan* p, const double* f, const double* u, hipStr
   const size_t n = (size_t)p->M * p->spec.n_a * p->spec.n_b;
   if (f) HIPCHK(smgk::copy_planes(p->dptr(p->w_f), reinterpret_cast<const double2*>(f), n, st));
   if (u) HIPCHK(smgk::copy_planes(p->dptr(p->w_psi), reinterpret_cast<const double2*>(u), n, st));
-  p->have_prev = false;
+  p->grp.have_prev = false;
   return SMG_OK;
 }
 

@@ -65,6 +65,7 @@ class Engine {
 
   int n_planes() const { return n_total_; }
   int n_prob() const { return (int)P_.size(); }
+  int base(int q) const { return base_[q]; }  // global index of problem q's first plane
   const MGParams& params() const { return prm_; }
   const std::vector<MGConfig>& configs() const { return cfg_; }
   // Replace the configurations (the last one must cover every plane).

@@ -98,6 +98,13 @@ def load():
         "smg_profile_begin": ([P], ctypes.c_int),
         "smg_profile_end": ([P, ctypes.POINTER(KernelStat), ctypes.c_int, _PI], ctypes.c_int),
         "smg_tune_report": ([P], ctypes.c_char_p),
+        "smg_batch_create": ([ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(P)], ctypes.c_int),
+        "smg_batch_workspace_bytes": ([P], ctypes.c_size_t),
+        "smg_batch_setup": ([P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "smg_batch_solve": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.c_double, ctypes.c_uint, P,
+                             ctypes.POINTER(Info)], ctypes.c_int),
+        "smg_batch_tune_report": ([P], ctypes.c_char_p),
+        "smg_batch_destroy": ([P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -302,6 +309,68 @@ class Plan:
         out = np.zeros((self.n_ghost, self.n_ghost))
         _check(load().smg_dgf_table(self._h, int(m), _dptr(out), _stream()))
         return out
+
+
+class Batch:
+    """Several set-up plans solved together (every multigrid launch covers
+    the mode planes of all of them)."""
+
+    def __init__(self, plans):
+        lib = load()
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        self._h = ctypes.c_void_p()
+        _check(lib.smg_batch_create(arr, len(self.plans), ctypes.byref(self._h)))
+        self.workspace_bytes = int(lib.smg_batch_workspace_bytes(self._h))
+        self._ws = None
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.smg_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def setup(self, device="cuda"):
+        import torch
+        self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=device)
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        _check(load().smg_batch_setup(self._h, ctypes.c_void_p(base + off), ctypes.c_size_t(self.workspace_bytes),
+                                      _stream()))
+        return self
+
+    def tune_report(self):
+        return load().smg_batch_tune_report(self._h).decode()
+
+    def solve(self, rhos, tol=1e-8, warm=False, outs=None, timings=False, info=True):
+        """phi for every plan's density; returns (phis, infos or None)."""
+        import torch
+        n = len(self.plans)
+        outs = outs if outs is not None else [torch.empty_like(r) for r in rhos]
+        for p, r, o in zip(self.plans, rhos, outs):
+            shape = (p.n_a, p.n_b, p.n_phi)
+            p._f64(r, shape)
+            p._f64(o, shape)
+        rp = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
+        op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        flags = (WARM_PREV if warm else 0) | (TIMINGS if timings else 0)
+        infos = None
+        keep = []
+        if info:
+            infos = (Info * n)()
+            for q, p in enumerate(self.plans):
+                M = p.n_modes
+                arrs = [np.zeros(M, dtype=np.int32), np.zeros(M, dtype=np.int32), np.zeros(M), np.zeros(M)]
+                keep.append(arrs)
+                infos[q] = Info(M, _iptr(arrs[0]), _iptr(arrs[1]), _dptr(arrs[2]), _dptr(arrs[3]), 0, 0, 0, 0, 0, 0, 0)
+        _check(load().smg_batch_solve(self._h, rp, op, ctypes.c_double(tol), ctypes.c_uint(flags), _stream(), infos))
+        if not info:
+            return outs, None
+        res = []
+        for q in range(n):
+            c1, c2, r1, r2 = keep[q]
+            res.append(dict(cycles1=c1, cycles2=c2, resid1=r1, resid2=r2, total_cycles=infos[q].total_cycles,
+                            converged=bool(infos[q].converged)))
+        return outs, res
 
 
 def grid_from_spec(spec, **opts):

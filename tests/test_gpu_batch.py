@@ -1,0 +1,86 @@
+"""Several problems in one batch: every multigrid launch covers the planes
+of all of them.  A plane's V-cycles do not depend on which planes share a
+launch, so the batch gives the same bits as solving each plan alone (same
+launch configuration), and meets the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.geometry import GridSpec, cell_centres, cell_volumes_3d
+from oracle.solve import OraclePlan
+from workloads.densities import draw_blobs, gaussian_blobs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SPECS = [
+    (GridSpec("spherical", "uniform", 32, 16, 32, 0.1, 1.0, 0.0, math.pi), 16),
+    (GridSpec("spherical", "log", 48, 24, 24, 0.05, 5.0, 0.0, math.pi), 16),
+    (GridSpec("cylindrical", "uniform", 24, 20, 12, 0.2, 2.0, -0.5, 0.5), 8),
+    (GridSpec("cylindrical", "log", 40, 12, 12, 0.05, 5.0, -2.5, 2.5), 16),
+]
+
+
+def _rho(spec, seed):
+    a, b, p = cell_centres(spec)
+    rng = np.random.default_rng(seed)
+    cen, w, amp = draw_blobs(rng, spec.geometry, spec.radial, spec.a_min, spec.a_max, spec.b_min, spec.b_max, 4)
+    return gaussian_blobs(spec.geometry, a, b, p, cen, np.asarray(w) * (spec.a_max - spec.a_min), amp)
+
+
+def _plans(**kw):
+    from paper_2606_17636_amd import smg
+    out = []
+    for spec, npad in SPECS:
+        print(f"[setup] {spec} {kw}", flush=True)
+        out.append(smg.grid_from_spec(spec, n_pad=npad, **kw).setup())
+    return out
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _l2(spec, x, ref):
+    w = cell_volumes_3d(spec)[:, :, None]
+    return math.sqrt(np.sum((x - ref) ** 2 * w) / np.sum(ref**2 * w))
+
+
+_ref = {}
+
+
+def _oracle(k, seed):
+    if (k, seed) not in _ref:
+        spec, npad = SPECS[k]
+        _ref[(k, seed)] = OraclePlan(spec, n_pad=npad).solve(_rho(spec, seed))
+    return _ref[(k, seed)]
+
+
+def test_batch_matches_single_plans_bitwise():
+    from paper_2606_17636_amd import smg
+    plans = _plans(launch="dynamic")
+    rhos = [_dev(_rho(spec, 20 + k)) for k, (spec, _) in enumerate(SPECS)]
+    singles = [p.solve(r, tol=1e-10) for p, r in zip(plans, rhos)]
+    batch = smg.Batch(plans).setup()
+    phis, infos = batch.solve(rhos, tol=1e-10)
+    for k, ((phi1, i1), phi, i) in enumerate(zip(singles, phis, infos)):
+        assert i["converged"], k
+        assert np.array_equal(i["cycles1"], i1["cycles1"]), k
+        assert np.array_equal(i["cycles2"], i1["cycles2"]), k
+        assert torch.equal(phi, phi1), k
+
+
+@pytest.mark.parametrize("precision,tol,bound", [("fp64", 1e-12, 1e-10), ("mixed", 1e-8, 1e-6), ("mixed", 1e-12, 1e-10)])
+def test_batch_graph_matches_oracle(precision, tol, bound):
+    from paper_2606_17636_amd import smg
+    plans = _plans(precision=precision, launch="graph", autotune=True)
+    batch = smg.Batch(plans).setup()
+    assert "planes <=" in batch.tune_report()
+    rhos_h = [_rho(spec, 30 + k) for k, (spec, _) in enumerate(SPECS)]
+    rhos = [_dev(r) for r in rhos_h]
+    for rep in range(3):  # host loop, then scheduled graph replays
+        phis, infos = batch.solve(rhos, tol=tol)
+        for k, (spec, _) in enumerate(SPECS):
+            assert infos[k]["converged"], (rep, k)
+            assert _l2(spec, phis[k].cpu().numpy(), _oracle(k, 30 + k)) < bound, (rep, k)

@@ -62,3 +62,16 @@ def test_plan_geometry_matches_oracle(spec):
     assert plan.level_shapes == level_sizes(spec)
     assert plan.n_ghost == GhostSet(spec).n
     assert plan.workspace_bytes > 0
+
+
+def test_batch_create_validates_plans():
+    from paper_2606_17636_amd import smg
+    a = smg.Plan("spherical", "uniform", 16, 8, 8, 0.2, 1.0, 0.0, math.pi)
+    b = smg.Plan("spherical", "log", 32, 8, 8, 0.05, 5.0, 0.0, math.pi)
+    c = smg.Plan("spherical", "log", 32, 8, 8, 0.05, 5.0, 0.0, math.pi, precision="mixed")
+    bt = smg.Batch([a, b])
+    assert bt.workspace_bytes > 0
+    with pytest.raises(smg.SmgError, match="share precision"):
+        smg.Batch([a, c])
+    with pytest.raises(smg.SmgError, match="twice"):
+        smg.Batch([a, a])

@@ -9,6 +9,13 @@ c2  spherical log 128x64x128, r in [0.05, 5], full theta: 8 Gaussian blobs
 c3  cylindrical uniform N_R x N_phi x N_z = 256x256x128, R in [0.2, 2],
     z in [-0.5, 0.5]: exponential disk (scale 0.5) with Gaussian vertical
     profile (scale height 0.05) and a two-armed spiral.
+c4  16 independent problems solved as one batch (seed 4): 4 each of
+    {spherical, cylindrical} x {uniform, log radial}, N drawn from
+    {64, 96, 128, 192}; spherical (N_r, N_theta, N_phi) = (N, N/2, N),
+    cylindrical (N_R, N_z, N_phi) = (N, N/2, N); domains as c1 (spherical
+    uniform), c2 (spherical log), c3 (cylindrical uniform) and R in
+    [0.05, 5], z in [-2.5, 2.5] (cylindrical log); 8 Gaussian blobs each as
+    c2 with per-problem seed 4000 + p.
 c5  spherical log 256x128x256, r in [0.05, 5]: 12 blobs on Keplerian
     orbits; snapshot t of the sequence (seed 5).
 """
@@ -35,8 +42,37 @@ DESCRIPTION = {
     "c1": "spherical uniform 32x16x32, r in [0.1,1], uniform sphere R=0.3 at (0.5, pi/2, 0)",
     "c2": "spherical log-r 128x64x128, r in [0.05,5], 8 Gaussian blobs (seed 2), all 65 modes batched",
     "c3": "cylindrical uniform 256x256x128 (R,phi,z), R in [0.2,2], z in [-0.5,0.5], spiral exponential disk",
+    "c4": "16-problem batch (seed 4): sph/cyl x uniform/log, N in {64,96,128,192}, 8 Gaussian blobs each",
     "c5": "spherical log-r 256x128x256, r in [0.05,5], 12 Keplerian Gaussian blobs (seed 5)",
 }
+
+C4_DOMAINS = {
+    ("spherical", "uniform"): (0.1, 1.0, 0.0, PI),
+    ("spherical", "log"): (0.05, 5.0, 0.0, PI),
+    ("cylindrical", "uniform"): (0.2, 2.0, -0.5, 0.5),
+    ("cylindrical", "log"): (0.05, 5.0, -2.5, 2.5),
+}
+
+
+def c4_grids(seed=4):
+    """Grids of the 16-problem batch, in problem order."""
+    rng = np.random.default_rng(seed)
+    kinds = [(g, r) for g in ("spherical", "cylindrical") for r in ("uniform", "log") for _ in range(4)]
+    sizes = rng.choice([64, 96, 128, 192], size=len(kinds))
+    out = []
+    for (geo, rad), n in zip(kinds, sizes):
+        a0, a1, b0, b1 = C4_DOMAINS[(geo, rad)]
+        out.append(dict(geometry=geo, radial=rad, n_a=int(n), n_b=int(n) // 2, n_phi=int(n), a_min=a0, a_max=a1,
+                        b_min=b0, b_max=b1))
+    return out
+
+
+def c4_density(p, grid, a, b, phi):
+    """Density of problem p of the batch: 8 blobs drawn as in c2 (seed 4000 + p)."""
+    rng = np.random.default_rng(4000 + p)
+    cen, w, amp = D.draw_blobs(rng, grid["geometry"], grid["radial"], grid["a_min"], grid["a_max"], grid["b_min"],
+                               grid["b_max"], 8)
+    return D.gaussian_blobs(grid["geometry"], a, b, phi, cen, w, amp)
 
 
 def density(name, a, b, phi, t=0.0):
