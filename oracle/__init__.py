@@ -21,6 +21,8 @@ multigrid  the paper's V-cycle: zebra-line even-odd SOR smoother,
 james      screening masses, discrete Green's functions, boundary
            convolution (Sec. 4)
 solve      the seven-step workflow (Sec. 5.1)
+net        the learned initial guess of the low-m planes (a U-Net with BF16
+           weights and activations), forward and backward
 
 Parity status of every function is stated in its docstring; the DGF tables
 (``james.dgf_tables``) are "parity unpinned" beyond the physics checks listed

@@ -1,0 +1,230 @@
+"""The learned initial guess -- oracle side (test infrastructure only).
+
+A small per-mode 2D convolutional network predicts how a low-m mode plane
+of the potential changes from one time step to the next.  The input is one
+real plane (the real or imaginary part of a mode) with four channels,
+  0: f_t / s_f              (this step's right-hand side)
+  1: (f_t - f_{t-1}) / s_f  (its change since the previous step)
+  2: u_{t-1} / s_u          (the previous step's solution)
+  3: m / 4                  (the azimuthal index),
+and the output is (u_t - u_{t-1}) / s_u, so that the guess is
+u_{t-1} + s_u * net(x).  s_f and s_u are per-plane RMS scales.  The output
+layer starts at zero: the untrained network reproduces the previous-step
+warm start exactly.
+
+Architecture (a U-Net with 4 levels and 32 channels): at each encoder level
+two 3x3 convolutions with ReLU (zero padding), 2x2 average pooling between
+levels; in the decoder nearest-neighbour upsampling by 2, concatenation
+[upsampled, encoder output] (64 channels), two 3x3 convolutions with ReLU;
+a final 1x1 convolution to one channel without activation.
+
+Arithmetic convention (shared with the HIP kernels): weights and every
+stored activation and activation gradient are BF16 (round to nearest even,
+from the FP32 value the accumulator holds); sums accumulate in FP32 on the
+GPU and in FP64 here; weight gradients, biases, the output and the loss are
+FP32/FP64.  Rounding points (``rounding=True``):
+  conv output (after bias and ReLU) -> BF16; pooling output -> BF16;
+  upsampling copies BF16; the network output stays unrounded;
+  backward: the gradient entering a layer's input -> BF16 (after the ReLU
+  mask of that input, and after summing the skip and pooling paths).
+With ``rounding=False`` everything is FP64 (used by the finite-difference
+pins of the backward pass).
+
+Layout: activations are NHWC arrays (N, H, W, C); a 3x3 weight tensor is
+(C_out, 9, C_in) with tap t = 3 (dy + 1) + (dx + 1) reading input pixel
+(y + dy, x + dx); the parameter vector concatenates, layer by layer, the
+weights then the biases.
+"""
+import numpy as np
+
+LEVELS = 4
+CH = 32
+IN_CH = 4
+
+
+def layer_shapes(levels=LEVELS, ch=CH, in_ch=IN_CH):
+    """(kind, c_in, c_out) of every layer in parameter order."""
+    shapes = []
+    cin = in_ch
+    for _ in range(levels):            # encoder (the last level is the bottom)
+        shapes += [("conv3", cin, ch), ("conv3", ch, ch)]
+        cin = ch
+    for _ in range(levels - 1):        # decoder
+        shapes += [("conv3", 2 * ch, ch), ("conv3", ch, ch)]
+    shapes.append(("conv1", ch, 1))
+    return shapes
+
+
+def n_params(levels=LEVELS, ch=CH, in_ch=IN_CH):
+    n = 0
+    for kind, ci, co in layer_shapes(levels, ch, in_ch):
+        n += co * ci * (9 if kind == "conv3" else 1) + co
+    return n
+
+
+def unpack(params, levels=LEVELS, ch=CH, in_ch=IN_CH):
+    """List of (W, b) per layer; W is (c_out, 9, c_in) or (c_out, c_in)."""
+    out, k = [], 0
+    for kind, ci, co in layer_shapes(levels, ch, in_ch):
+        nw = co * ci * (9 if kind == "conv3" else 1)
+        W = params[k:k + nw].reshape((co, 9, ci) if kind == "conv3" else (co, ci))
+        k += nw
+        b = params[k:k + co]
+        k += co
+        out.append((W, b))
+    return out
+
+
+def pack(layers):
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in layers])
+
+
+# -- BF16 ---------------------------------------------------------------------
+def bf16(x):
+    """Round to the nearest BF16 value (ties to even) via the FP32 value."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float64).astype(np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    nan = np.isnan(f)
+    out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+    out[nan] = np.nan
+    return out
+
+
+def _q(x, rounding):
+    return bf16(x) if rounding else x
+
+
+# -- layers --------------------------------------------------------------------
+def _shift(x, dy, dx):
+    """y[n, i, j] = x[n, i + dy, j + dx] with zeros outside."""
+    N, H, W, C = x.shape
+    y = np.zeros_like(x)
+    i0, i1 = max(0, -dy), min(H, H - dy)
+    j0, j1 = max(0, -dx), min(W, W - dx)
+    y[:, i0:i1, j0:j1] = x[:, i0 + dy:i1 + dy, j0 + dx:j1 + dx]
+    return y
+
+
+TAPS = [(dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+
+
+def conv3(x, W, b):
+    """3x3 'same' correlation: out[.., o] = b[o] + sum_{t, c} W[o, t, c] x[.. + tap t, c]."""
+    out = np.zeros(x.shape[:3] + (W.shape[0],))
+    for t, (dy, dx) in enumerate(TAPS):
+        out += np.tensordot(_shift(x, dy, dx), W[:, t, :], axes=([3], [1]))
+    return out + b
+
+
+def conv3_backward(x, W, g):
+    """Gradients of sum(g * conv3(x, W, b)) w.r.t. x, W, b."""
+    gx = np.zeros_like(x)
+    gW = np.zeros_like(W)
+    for t, (dy, dx) in enumerate(TAPS):
+        xs = _shift(x, dy, dx)
+        gW[:, t, :] = np.tensordot(g, xs, axes=([0, 1, 2], [0, 1, 2]))
+        gx += _shift(np.tensordot(g, W[:, t, :], axes=([3], [0])), -dy, -dx)
+    gb = g.sum(axis=(0, 1, 2))
+    return gx, gW, gb
+
+
+def pool2(x):
+    N, H, W, C = x.shape
+    return x.reshape(N, H // 2, 2, W // 2, 2, C).mean(axis=(2, 4))
+
+
+def pool2_backward(g):
+    return np.repeat(np.repeat(g, 2, axis=1), 2, axis=2) / 4.0
+
+
+def up2(x):
+    return np.repeat(np.repeat(x, 2, axis=1), 2, axis=2)
+
+
+def up2_backward(g):
+    N, H, W, C = g.shape
+    return g.reshape(N, H // 2, 2, W // 2, 2, C).sum(axis=(2, 4))
+
+
+# -- network -------------------------------------------------------------------
+def forward(params, x, rounding=True, levels=LEVELS, ch=CH):
+    """Network output (N, H, W) and the cache of the backward pass."""
+    L = unpack(params, levels, ch, x.shape[3])
+    q = lambda v: _q(v, rounding)
+    Lq = [(q(W), b) for W, b in L] if rounding else L
+    cache = {"x": x, "L": Lq, "enc": [], "dec": [], "rounding": rounding}
+    h = q(x)
+    k = 0
+    enc_out = []
+    for lev in range(levels):
+        if lev > 0:
+            h = q(pool2(enc_out[-1]))
+        a = q(np.maximum(conv3(h, *Lq[k]), 0.0))
+        e = q(np.maximum(conv3(a, *Lq[k + 1]), 0.0))
+        cache["enc"].append((h, a, e))
+        enc_out.append(e)
+        k += 2
+    d = enc_out[-1]
+    for lev in range(levels - 2, -1, -1):
+        cat = np.concatenate([up2(d), enc_out[lev]], axis=3)
+        a = q(np.maximum(conv3(cat, *Lq[k]), 0.0))
+        d = q(np.maximum(conv3(a, *Lq[k + 1]), 0.0))
+        cache["dec"].append((cat, a, d))
+        k += 2
+    W1, b1 = Lq[k]
+    out = np.tensordot(d, W1, axes=([3], [1]))[..., 0] + b1[0]
+    cache["d0"] = d
+    return out, cache
+
+
+def backward(params, cache, g_out, levels=LEVELS, ch=CH):
+    """Gradient of sum(g_out * out) w.r.t. the parameters (packed vector)."""
+    rounding = cache["rounding"]
+    q = lambda v: _q(v, rounding)
+    Lq = cache["L"]
+    grads = [None] * len(Lq)
+    k = len(Lq) - 1
+    W1, _ = Lq[k]
+    d = cache["d0"]
+    g = g_out[..., None]
+    grads[k] = (np.tensordot(g, d, axes=([0, 1, 2], [0, 1, 2])), g.sum(axis=(0, 1, 2)))
+    gd = q(np.tensordot(g, W1, axes=([3], [0])) * (d > 0))
+    k -= 1
+    skip_g = [None] * levels
+    for idx in range(len(cache["dec"]) - 1, -1, -1):   # from the output back
+        lev = levels - 2 - idx                          # encoder level of the skip input
+        cat, a, dd = cache["dec"][idx]
+        gx, gW, gb = conv3_backward(a, Lq[k][0], gd)
+        grads[k] = (gW, gb)
+        ga = q(gx * (a > 0))
+        gx, gW, gb = conv3_backward(cat, Lq[k - 1][0], ga)
+        grads[k - 1] = (gW, gb)
+        k -= 2
+        gcat = q(gx)
+        skip_g[lev] = gcat[..., ch:]
+        gup = gcat[..., :ch]
+        below = cache["dec"][idx - 1][2] if idx > 0 else cache["enc"][levels - 1][2]
+        gd = q(up2_backward(gup) * (below > 0))
+    # encoder, bottom up: gd is the gradient at the bottom encoder output
+    ge = gd
+    for lev in range(levels - 1, -1, -1):
+        h, a, e = cache["enc"][lev]
+        gx, gW, gb = conv3_backward(a, Lq[k][0], ge)
+        grads[k] = (gW, gb)
+        ga = q(gx * (a > 0))
+        gx, gW, gb = conv3_backward(h, Lq[k - 1][0], ga)
+        grads[k - 1] = (gW, gb)
+        k -= 2
+        if lev > 0:
+            eprev = cache["enc"][lev - 1][2]
+            ge = q((q(pool2_backward(q(gx))) + skip_g[lev - 1]) * (eprev > 0))
+    return pack(grads)
+
+
+def loss(out, target):
+    """Mean squared error and its gradient w.r.t. the output."""
+    diff = out - target
+    n = diff.size
+    return float(np.sum(diff * diff) / n), 2.0 * diff / n
