@@ -185,6 +185,55 @@ smg_status smg_batch_solve(smg_batch *batch, const double *const *rho_dev, doubl
 const char *smg_batch_tune_report(const smg_batch *batch);
 smg_status smg_batch_destroy(smg_batch *batch);
 
+/* ---- the learned initial guess --------------------------------------------
+ * A U-Net on real mode planes (one image per real or imaginary part of a
+ * low-m mode), 4 input channels (f_t / s_f, (f_t - f_{t-1}) / s_f,
+ * u_{t-1} / s_u, m / 4) and one output channel, the change
+ * (u_t - u_{t-1}) / s_u of the plane since the previous time step.  At each
+ * of `levels` resolutions two 3x3 convolutions with ReLU (32 channels),
+ * 2x2 average pooling down, nearest upsampling and concatenation with the
+ * encoder output up, a 1x1 output layer.  Weights and activations are BF16,
+ * products accumulate in FP32 on the matrix cores; the master parameters,
+ * their gradients and the Adam moments are FP32.
+ *
+ * Parameter vector (FP32, n = smg_net_param_count): per layer in the order
+ * encoder levels 0..levels-1 (two 3x3 layers each), decoder levels
+ * levels-2..0 (two 3x3 layers each, the first reading 64 channels), the
+ * 1x1 output layer; per layer the weights [c_out][9][c_in] (tap 3(dy+1) +
+ * (dx+1) reads pixel (y+dy, x+dx)) or [c_out][c_in], then the biases.
+ * Images are NHWC FP32 arrays [n][h][w][4] in, [n][h][w] out; h and w are
+ * multiples of 2^(levels-1).  The caller owns all device memory: the
+ * state buffer (parameters, gradients, Adam moments, BF16 copy) and the
+ * work buffer of one batch shape (activations and their gradients). */
+typedef struct smg_net smg_net;
+smg_status smg_net_create(int levels, int channels /* 32 */, smg_net **out);
+smg_status smg_net_destroy(smg_net *net);
+long long smg_net_param_count(const smg_net *net);
+size_t smg_net_state_bytes(const smg_net *net);
+/* Bind the state buffer (256-byte aligned); parameters start at zero. */
+smg_status smg_net_bind(smg_net *net, void *state_dev, size_t state_bytes, void *stream);
+/* Copy FP32 parameters in (device array; Adam moments reset) or out. */
+smg_status smg_net_set_params(smg_net *net, const float *params_dev, void *stream);
+smg_status smg_net_get_params(const smg_net *net, float *params_dev, void *stream);
+/* Gradients of the last smg_net_backward / smg_net_train_step. */
+smg_status smg_net_get_grads(const smg_net *net, float *grads_dev, void *stream);
+/* Bytes of the work buffer for n images of h x w (0 if the shape is invalid). */
+size_t smg_net_work_bytes(const smg_net *net, int n, int h, int w);
+/* y = net(x); y_dev may be NULL (the output stays in the work buffer). */
+smg_status smg_net_forward(smg_net *net, const float *x_dev, float *y_dev, int n, int h, int w, void *work_dev,
+                           size_t work_bytes, void *stream);
+/* After smg_net_forward on the same work buffer: gradients of
+ * sum(dy * y) with respect to the parameters (readable with
+ * smg_net_get_grads). */
+smg_status smg_net_backward(smg_net *net, const float *dy_dev, int n, int h, int w, void *work_dev, size_t work_bytes,
+                            void *stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean squared error of
+ * n samples picked by idx_host (each in [0, n_samples)) from samples_dev
+ * (each sample: x [h][w][4] then the target [h][w], FP32).  loss_host (may
+ * be NULL) receives the batch loss before the step (synchronises). */
+smg_status smg_net_train_step(smg_net *net, const float *samples_dev, int n_samples, const int *idx_host, int n, int h,
+                              int w, float lr, void *work_dev, size_t work_bytes, void *stream, float *loss_host);
+
 /* ---- geometry query (host, no device work) ------------------------------ */
 /* Cell-centre coordinates: a_host[n_a], b_host[n_b], phi_host[n_phi]
  * (volume-weighted centroids of Eq. cell_centers_sph and Sec. 2.1.2), and

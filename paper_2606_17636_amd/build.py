@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsmg.so")
-SOURCES = ["geometry.cpp", "api.cpp", "engine.cpp", "fft.hip", "mg.hip", "mg_lds.hip", "sched.hip", "james.hip", "dgf.hip"]
+SOURCES = ["geometry.cpp", "api.cpp", "engine.cpp", "fft.hip", "mg.hip", "mg_lds.hip", "sched.hip", "james.hip", "dgf.hip", "net.hip", "net.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SMG_ARCH", "gfx950")
@@ -27,7 +27,7 @@ FLAGS = [
 
 
 def _compile(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    obj = os.path.join(BUILD, src + ".o")
     cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

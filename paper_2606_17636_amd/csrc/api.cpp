@@ -24,6 +24,10 @@ static smg_status fail(smg_status s, const std::string& msg) {
   return s;
 }
 
+namespace smg {
+void set_error(const std::string& msg) { g_err = msg; }
+}  // namespace smg
+
 #define HIPCHK(expr)                                                                        \
   do {                                                                                      \
     hipError_t e_ = (expr);                                                                 \

@@ -105,6 +105,19 @@ def load():
                              ctypes.POINTER(Info)], ctypes.c_int),
         "smg_batch_tune_report": ([P], ctypes.c_char_p),
         "smg_batch_destroy": ([P], ctypes.c_int),
+        "smg_net_create": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(P)], ctypes.c_int),
+        "smg_net_destroy": ([P], ctypes.c_int),
+        "smg_net_param_count": ([P], ctypes.c_longlong),
+        "smg_net_state_bytes": ([P], ctypes.c_size_t),
+        "smg_net_bind": ([P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "smg_net_set_params": ([P, P, P], ctypes.c_int),
+        "smg_net_get_params": ([P, P, P], ctypes.c_int),
+        "smg_net_get_grads": ([P, P, P], ctypes.c_int),
+        "smg_net_work_bytes": ([P, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
+        "smg_net_forward": ([P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_size_t, P], ctypes.c_int),
+        "smg_net_backward": ([P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_size_t, P], ctypes.c_int),
+        "smg_net_train_step": ([P, P, ctypes.c_int, _PI, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_float, P,
+                                ctypes.c_size_t, P, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -371,6 +384,91 @@ class Batch:
             res.append(dict(cycles1=c1, cycles2=c2, resid1=r1, resid2=r2, total_cycles=infos[q].total_cycles,
                             converged=bool(infos[q].converged)))
         return outs, res
+
+
+def _aligned(nbytes, device):
+    import torch
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + off
+
+
+class Net:
+    """The learned-guess U-Net (state and work buffers are torch tensors)."""
+
+    def __init__(self, levels=4, channels=32, device="cuda"):
+        lib = load()
+        self._h = ctypes.c_void_p()
+        _check(lib.smg_net_create(levels, channels, ctypes.byref(self._h)))
+        self.levels = levels
+        self.device = device
+        self.n_params = int(lib.smg_net_param_count(self._h))
+        nb = int(lib.smg_net_state_bytes(self._h))
+        self._state, ptr = _aligned(nb, device)
+        _check(lib.smg_net_bind(self._h, ctypes.c_void_p(ptr), ctypes.c_size_t(nb), _stream()))
+        self._work = {}
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.smg_net_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_params(self, params):
+        import torch
+        t = torch.as_tensor(np.asarray(params, dtype=np.float32) if not hasattr(params, "data_ptr") else params,
+                            dtype=torch.float32, device=self.device).contiguous()
+        assert t.numel() == self.n_params
+        _check(load().smg_net_set_params(self._h, _ptr(t), _stream()))
+
+    def params(self):
+        import torch
+        t = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _check(load().smg_net_get_params(self._h, _ptr(t), _stream()))
+        return t
+
+    def grads(self):
+        import torch
+        t = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _check(load().smg_net_get_grads(self._h, _ptr(t), _stream()))
+        return t
+
+    def work(self, n, h, w):
+        key = (n, h, w)
+        if key not in self._work:
+            nb = int(load().smg_net_work_bytes(self._h, n, h, w))
+            if nb == 0:
+                raise ValueError(f"invalid image batch shape {key}")
+            self._work[key] = (nb,) + _aligned(nb, self.device)
+        nb, _, ptr = self._work[key]
+        return ctypes.c_void_p(ptr), ctypes.c_size_t(nb)
+
+    def forward(self, x):
+        import torch
+        n, h, w, c = x.shape
+        y = torch.empty((n, h, w), dtype=torch.float32, device=x.device)
+        wp, wb = self.work(n, h, w)
+        _check(load().smg_net_forward(self._h, _ptr(x.contiguous()), _ptr(y), n, h, w, wp, wb, _stream()))
+        return y
+
+    def backward(self, dy):
+        n, h, w = dy.shape
+        wp, wb = self.work(n, h, w)
+        _check(load().smg_net_backward(self._h, _ptr(dy.contiguous()), n, h, w, wp, wb, _stream()))
+        return self.grads()
+
+    def train_step(self, samples, idx, h, w, lr):
+        n = len(idx)
+        ia = np.ascontiguousarray(np.asarray(idx, dtype=np.int32))
+        wp, wb = self.work(n, h, w)
+        loss = ctypes.c_float()
+        n_samples = samples.numel() // (h * w * 5)
+        _check(load().smg_net_train_step(self._h, _ptr(samples), n_samples, _iptr(ia), n, h, w, ctypes.c_float(lr), wp,
+                                         wb, _stream(), ctypes.byref(loss)))
+        return loss.value
 
 
 def grid_from_spec(spec, **opts):
