@@ -126,6 +126,12 @@ typedef struct {
                                Psi^m / Phi^m (Sec. 5.1, last paragraph);
                                otherwise from zero                         */
 #define SMG_TIMINGS     2u  /* fill the component times of smg_info        */
+#define SMG_NET_GUESS   4u  /* with SMG_WARM_PREV and an attached network:
+                               modes 0..m_max start from the network's
+                               prediction wherever, after one smoothing step
+                               of each, its defect norm is below that of the
+                               previous step's solution (the multigrid then
+                               runs to the same tolerance)                 */
 
 typedef struct smg_plan smg_plan;
 
@@ -233,6 +239,32 @@ smg_status smg_net_backward(smg_net *net, const float *dy_dev, int n, int h, int
  * be NULL) receives the batch loss before the step (synchronises). */
 smg_status smg_net_train_step(smg_net *net, const float *samples_dev, int n_samples, const int *idx_host, int n, int h,
                               int w, float lr, void *work_dev, size_t work_bytes, void *stream, float *loss_host);
+
+/* ---- the learned guess in a plan's solves ---------------------------------
+ * Attach a bound network as the initial-guess model of modes 0..m_max
+ * (m_max <= 8; n_a and n_b divisible by 2^(levels-1)) using a caller-owned
+ * work buffer of smg_plan_net_work_bytes bytes (256-byte aligned).  From
+ * then on every solve keeps its right-hand sides of those modes for the next
+ * step; a warm-started solve with SMG_NET_GUESS builds the network inputs
+ * (per real image: f_t / s_f, (f_t - f_{t-1}) / s_f, u_{t-1} / s_u, m / 4,
+ * with s_f, s_u the plane RMS values) before each of its two multigrid
+ * solves and starts every mode from the better of the network's guess and
+ * the previous solution (defect norms after one smoothing step of each).
+ * A NULL net detaches. */
+size_t smg_plan_net_work_bytes(const smg_plan *plan, const smg_net *net, int m_max);
+smg_status smg_plan_attach_net(smg_plan *plan, smg_net *net, int m_max, void *work_dev, size_t work_bytes,
+                               void *stream);
+/* Record training samples: every later warm-started solve appends, for each
+ * of its two multigrid solves and each real image of modes 0..m_max, the
+ * sample (network input [n_a][n_b][4], target (u_t - u_{t-1}) / s_u
+ * [n_a][n_b], FP32) to samples_dev while fewer than `capacity` are stored
+ * (the layout smg_net_train_step reads).  Resets the count; capacity 0 stops
+ * recording.  smg_plan_recorded returns the count (synchronises). */
+smg_status smg_plan_record(smg_plan *plan, float *samples_dev, int capacity, void *stream);
+int smg_plan_recorded(const smg_plan *plan, void *stream);
+/* Which modes took the network's guess in the last SMG_NET_GUESS solve:
+ * used_host[t * (m_max + 1) + m] for solve t = 0 (Psi), 1 (Phi). */
+smg_status smg_plan_net_used(const smg_plan *plan, int *used_host, void *stream);
 
 /* ---- geometry query (host, no device work) ------------------------------ */
 /* Cell-centre coordinates: a_host[n_a], b_host[n_b], phi_host[n_phi]

@@ -13,6 +13,8 @@
 
 #include "dgf_dev.h"
 #include "engine.h"
+#include "netdef.h"
+#include "netguess.h"
 #include "smg_internal.h"
 
 using namespace smg;
@@ -167,6 +169,22 @@ struct Group {
   }
 };
 
+// The learned guess attached to a plan: network, caller-owned work buffer
+// and the offsets of its parts.
+struct PlanNet {
+  smg_net* net = nullptr;
+  int m_max = 0, n_img = 0, nblk = 1;
+  char* work = nullptr;
+  NetWork wl{};
+  size_t o_fprev[2] = {0, 0}, o_uprev = 0, o_cand = 0, o_cs = 0, o_us = 0, o_sc = 0, o_part = 0, o_used = 0,
+         o_jobs = 0, o_lv = 0, o_list = 0, o_rec = 0, bytes = 0;
+  std::vector<NormJob> hjobs;  // [target][smoothed candidate, smoothed previous solution]
+  std::vector<LvJob> hlv;      // [target][the same two arrays]: one smoothing step
+  bool prev_ok[2] = {false, false};
+  float* samples = nullptr;
+  int capacity = 0;
+};
+
 struct smg_plan {
   Spec spec{};
   smg_opts opts{};
@@ -192,6 +210,7 @@ struct smg_plan {
   Engine eng;               // targets: 0 = Psi (solve 1), 1 = Phi (solve 2)
   Group grp;                // this plan alone
   std::string tune_report;
+  PlanNet pn;
   // per-launch event timing (smg_profile_begin / smg_profile_end)
   struct ProfRec { int cls, ev0, ev1; double bytes; };
   mutable bool prof_on = false;
@@ -833,38 +852,109 @@ static smg_status james_all(Group& g, hipStream_t st) {
   return SMG_OK;
 }
 
+// ---- the learned guess inside a solve --------------------------------------
+static const double2* target_f(const smg_plan* p, int t) { return p->dptr(t == 0 ? p->w_f : p->w_f2); }
+static double2* target_u(const smg_plan* p, int t) { return p->dptr(t == 0 ? p->w_psi : p->w_phi); }
+
+// Before solve t of a warm start: the network inputs of modes 0..m_max;
+// with `guess`, the candidate u_prev + s_u net(x) replaces the previous
+// step's solution in every mode where, after one smoothing step of each,
+// its defect norm is the smaller one.
+static smg_status net_before(smg_plan* p, int t, bool warm, bool guess, hipStream_t st) {
+  PlanNet& pn = p->pn;
+  if (!pn.net || !warm || !pn.prev_ok[t]) return SMG_OK;
+  const int plane = p->spec.n_a * p->spec.n_b;
+  const size_t np = (size_t)(pn.m_max + 1) * plane;
+  double2* uprev = reinterpret_cast<double2*>(pn.work + pn.o_uprev);
+  double* sc = reinterpret_cast<double*>(pn.work + pn.o_sc);
+  const double2* fprev = reinterpret_cast<const double2*>(pn.work + pn.o_fprev[t]);
+  HIPCHK(smgk::copy_planes(uprev, target_u(p, t), np, st));
+  HIPCHK(smgg::scales(target_f(p, t), uprev, plane, pn.n_img, sc, st));
+  HIPCHK(smgg::assemble(target_f(p, t), fprev, uprev, sc, plane, pn.n_img, reinterpret_cast<float*>(pn.work + pn.wl.x32),
+                        st));
+  if (!guess) return SMG_OK;
+  STCHK(pn.net->def.forward(pn.work, pn.wl, st));
+  double2* cand = reinterpret_cast<double2*>(pn.work + pn.o_cand);
+  HIPCHK(smgg::candidate(uprev, reinterpret_cast<const float*>(pn.work + pn.wl.y), sc, plane, pn.m_max, cand, st));
+  // judge: defect norms after one smoothing step of each candidate (the
+  // smoothing removes the rough part of an error, which the multigrid
+  // removes in its first sweep anyway; what is left decides the cycles)
+  HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_cs), cand, np, st));
+  HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_us), uprev, np, st));
+  BatchRef b{pn.m_max + 1, nullptr, reinterpret_cast<const int*>(pn.work + pn.o_list)};
+  const LvJob* dl = reinterpret_cast<const LvJob*>(pn.work + pn.o_lv) + 2 * t;
+  const bool exact = p->opts.line_solver == SMG_LINE_EXACT;
+  for (int k = 0; k < 2; ++k)
+    for (int dir = 0; dir < 2; ++dir)
+      HIPCHK(smgk::mg_smooth_dir(dl + k, &pn.hlv[2 * t + k], 1, b, p->opts.n_sor, exact, dir, false, st));
+  const NormJob* dj = reinterpret_cast<const NormJob*>(pn.work + pn.o_jobs) + 2 * t;
+  double* pc = reinterpret_cast<double*>(pn.work + pn.o_part);
+  double* pu = pc + (size_t)(pn.m_max + 1) * pn.nblk;
+  HIPCHK(smgk::mg_norm_partial(dj, &pn.hjobs[2 * t], 1, b, true, pc, pn.nblk, st));
+  HIPCHK(smgk::mg_norm_partial(dj + 1, &pn.hjobs[2 * t + 1], 1, b, true, pu, pn.nblk, st));
+  HIPCHK(smgg::select(pc, pu, pn.nblk, cand, target_u(p, t), plane, pn.m_max,
+                      reinterpret_cast<int*>(pn.work + pn.o_used) + t * (pn.m_max + 1), st));
+  return SMG_OK;
+}
+
+// After solve t: a training sample per image when recording, and this
+// step's right-hand side kept for the next step's inputs.
+static smg_status net_after(smg_plan* p, int t, bool warm, hipStream_t st) {
+  PlanNet& pn = p->pn;
+  if (!pn.net) return SMG_OK;
+  const int plane = p->spec.n_a * p->spec.n_b;
+  if (warm && pn.prev_ok[t] && pn.samples)
+    HIPCHK(smgg::record(reinterpret_cast<const float*>(pn.work + pn.wl.x32), target_u(p, t),
+                        reinterpret_cast<const double2*>(pn.work + pn.o_uprev),
+                        reinterpret_cast<const double*>(pn.work + pn.o_sc), plane, pn.n_img,
+                        reinterpret_cast<int*>(pn.work + pn.o_rec), pn.capacity, pn.samples, st));
+  HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_fprev[t]), target_f(p, t),
+                           (size_t)(pn.m_max + 1) * plane, st));
+  pn.prev_ok[t] = true;
+  return SMG_OK;
+}
+
 // The body of a solve between the two FFTs: solve 1 into Psi, the James
-// steps, solve 2 into Phi^m, for every plan of the group.  With schedules,
-// every cycle is enqueued up front (no host synchronisation); otherwise
-// each solve reads its list length after every cycle.  ev (optional)
-// records 3 component boundaries.
-static smg_status group_body(Group& g, double tol, bool warm, const std::vector<int>* sched0,
+// steps, solve 2 into Phi^m, for every plan of the group (with the learned
+// guess of plans that carry a network).  With schedules, every cycle is
+// enqueued up front (no host synchronisation); otherwise each solve reads
+// its list length after every cycle.  ev (optional) records 3 component
+// boundaries.
+static smg_status group_body(Group& g, double tol, bool warm, unsigned flags, const std::vector<int>* sched0,
                              const std::vector<int>* sched1, hipStream_t st, hipEvent_t* ev) {
   Engine& e = *g.eng;
+  const bool guess = (flags & SMG_NET_GUESS) != 0;
+  for (smg_plan* p : g.plans) STCHK(net_before(p, 0, warm, guess, st));
   STCHK(e.start(0, tol, kFloor, warm, g.max_cycles, st));
   if (sched0) {
     for (int cap : *sched0) STCHK(e.cycle(0, cap, st));
   } else {
     STCHK(e.finish_dynamic(0, st, nullptr));
   }
+  for (smg_plan* p : g.plans) STCHK(net_after(p, 0, warm, st));
   if (ev) HIPCHK(hipEventRecord(ev[0], st));
   STCHK(james_all(g, st));
   if (ev) HIPCHK(hipEventRecord(ev[1], st));
+  for (smg_plan* p : g.plans) STCHK(net_before(p, 1, warm, guess, st));
   STCHK(e.start(1, tol, kFloor, warm, g.max_cycles, st));
   if (sched1) {
     for (int cap : *sched1) STCHK(e.cycle(1, cap, st));
   } else {
     STCHK(e.finish_dynamic(1, st, nullptr));
   }
+  for (smg_plan* p : g.plans) STCHK(net_after(p, 1, warm, st));
   if (ev) HIPCHK(hipEventRecord(ev[2], st));
   return SMG_OK;
 }
 
 // Captured graph of group_body for the two schedules (cached).
-static smg_status group_graph(Group& g, double tol, bool warm, const std::vector<int>& s0, const std::vector<int>& s1,
-                              hipGraphExec_t* out) {
+static smg_status group_graph(Group& g, double tol, bool warm, unsigned flags, const std::vector<int>& s0,
+                              const std::vector<int>& s1, hipGraphExec_t* out) {
   std::vector<int> key;
   key.push_back(warm ? 1 : 0);
+  key.push_back((int)(flags & SMG_NET_GUESS));
+  for (const smg_plan* p : g.plans)  // the learned-guess steps the body holds
+    key.push_back(p->pn.net ? 1 + 2 * p->pn.prev_ok[0] + 4 * p->pn.prev_ok[1] + 8 * (p->pn.samples != nullptr) : 0);
   long long tb;
   std::memcpy(&tb, &tol, sizeof(tb));
   key.push_back((int)(tb & 0xffffffff));
@@ -883,7 +973,7 @@ static smg_status group_graph(Group& g, double tol, bool warm, const std::vector
   if (!g.cap_stream) HIPCHK(hipStreamCreateWithFlags(&g.cap_stream, hipStreamNonBlocking));
   hipGraph_t graph = nullptr;
   HIPCHK(hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeThreadLocal));
-  smg_status sb = group_body(g, tol, warm, &s0, &s1, g.cap_stream, nullptr);
+  smg_status sb = group_body(g, tol, warm, flags, &s0, &s1, g.cap_stream, nullptr);
   hipError_t ce = hipStreamEndCapture(g.cap_stream, &graph);
   if (sb != SMG_OK) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -963,10 +1053,10 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
   }
   if (graph) {
     hipGraphExec_t exec = nullptr;
-    STCHK(group_graph(g, tol, warm, s0, s1, &exec));
+    STCHK(group_graph(g, tol, warm, flags, s0, s1, &exec));
     HIPCHK(hipGraphLaunch(exec, st));
   } else {
-    STCHK(group_body(g, tol, warm, sched ? &s0 : nullptr, sched ? &s1 : nullptr, st, timings ? ev + 2 : nullptr));
+    STCHK(group_body(g, tol, warm, flags, sched ? &s0 : nullptr, sched ? &s1 : nullptr, st, timings ? ev + 2 : nullptr));
   }
   STCHK(fft_inverse_all(g, phi, st));
   if (timings) HIPCHK(hipEventRecord(ev[5], st));
@@ -1032,6 +1122,132 @@ extern "C" smg_status smg_solve(smg_plan* p, const double* rho, double* phi, dou
                                 smg_info* info) {
   STCHK(need_ready(p));
   return group_solve(p->grp, &rho, &phi, tol, flags, static_cast<hipStream_t>(stream), info, p->prof_on);
+}
+
+// ----------------------------------------------------------------------------
+// the learned guess: attach a network, record training samples
+// ----------------------------------------------------------------------------
+static smg_status net_layout(const smg_plan* p, const smg_net* net, int m_max, PlanNet& pn) {
+  if (!net) return fail(SMG_EINVAL, "NULL net");
+  const int q = 1 << (net->def.levels - 1);
+  if (m_max < 0 || m_max > 8 || m_max >= p->M) return fail(SMG_EINVAL, "m_max must be in [0, min(8, n_phi/2)]");
+  if (p->spec.n_a % q || p->spec.n_b % q)
+    return fail(SMG_EINVAL, strprintf("the network needs n_a and n_b divisible by %d", q));
+  pn.m_max = m_max;
+  pn.n_img = 2 * m_max + 1;
+  pn.wl = net->def.work_layout(pn.n_img, p->spec.n_a, p->spec.n_b);
+  const size_t plane = (size_t)p->spec.n_a * p->spec.n_b, np = (size_t)(m_max + 1) * plane;
+  size_t off = align_up(pn.wl.bytes);
+  auto take = [&](size_t b) { size_t o = off; off = align_up(off + b); return o; };
+  pn.o_fprev[0] = take(sizeof(double2) * np);
+  pn.o_fprev[1] = take(sizeof(double2) * np);
+  pn.o_uprev = take(sizeof(double2) * np);
+  pn.o_cand = take(sizeof(double2) * np);
+  pn.o_cs = take(sizeof(double2) * np);
+  pn.o_us = take(sizeof(double2) * np);
+  pn.o_sc = take(sizeof(double) * 2 * pn.n_img);
+  NormJob hj{};
+  hj.L = p->levels.empty() ? LevelDev{} : p->levels[0];
+  pn.nblk = smgk::norm_blocks(&hj, 1);
+  pn.o_part = take(sizeof(double) * 2 * (m_max + 1) * pn.nblk);
+  pn.o_used = take(sizeof(int) * 2 * (m_max + 1));
+  pn.o_jobs = take(sizeof(NormJob) * 4);
+  pn.o_lv = take(sizeof(LvJob) * 4);
+  pn.o_list = take(sizeof(int) * (m_max + 1));
+  pn.o_rec = take(sizeof(int));
+  pn.bytes = off;
+  return SMG_OK;
+}
+
+extern "C" size_t smg_plan_net_work_bytes(const smg_plan* p, const smg_net* net, int m_max) {
+  if (!p || !net) return 0;
+  PlanNet pn;
+  if (net_layout(p, net, m_max, pn) != SMG_OK) return 0;
+  return pn.bytes;
+}
+
+extern "C" smg_status smg_plan_attach_net(smg_plan* p, smg_net* net, int m_max, void* work, size_t bytes, void* stream) {
+  STCHK(need_ready(p));
+  p->grp.drop_graphs();
+  if (!net) {
+    p->pn = PlanNet{};
+    return SMG_OK;
+  }
+  if (!net->state) return fail(SMG_ESTATE, "net state not bound");
+  PlanNet pn;
+  STCHK(net_layout(p, net, m_max, pn));
+  if (!work || bytes < pn.bytes) return fail(SMG_EWORKSPACE, strprintf("net work buffer of %zu bytes needed", pn.bytes));
+  if (reinterpret_cast<uintptr_t>(work) % kAlign) return fail(SMG_EWORKSPACE, "net work buffer must be 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  pn.net = net;
+  pn.work = static_cast<char*>(work);
+  const bool exact = p->opts.line_solver == SMG_LINE_EXACT;
+  for (int t = 0; t < 2; ++t) {
+    for (size_t arr : {pn.o_cs, pn.o_us}) {
+      NormJob c{};
+      c.L = p->levels[0];
+      c.u = reinterpret_cast<double2*>(pn.work + arr);
+      c.f = target_f(p, t);
+      pn.hjobs.push_back(c);
+      LvJob J{};
+      J.L = p->levels[0];
+      J.C = p->levels[0];
+      J.u = c.u;
+      J.f = const_cast<double2*>(c.f);
+      J.active = 1;
+      for (int dir = 0; dir < 2; ++dir) {
+        smgk::SmoothShape sh{};
+        if (!smgk::smooth_shape(p->levels[0], dir, exact, false, 512, m_max + 1, &sh))
+          return fail(SMG_EINVAL, "smoothing step of the guess does not fit in LDS");
+        J.tile[dir] = sh.tile;
+        J.ntile[dir] = sh.ntile;
+        J.stage[dir] = sh.stage;
+        J.scratch[dir] = sh.scratch;
+      }
+      pn.hlv.push_back(J);
+    }
+  }
+  std::vector<int> list(m_max + 1);
+  for (int m = 0; m <= m_max; ++m) list[m] = ent_make(0, m);
+  std::vector<int> zeros(2 * (m_max + 1) + 1, 0);
+  HIPCHK(hipMemcpyAsync(pn.work + pn.o_jobs, pn.hjobs.data(), sizeof(NormJob) * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pn.work + pn.o_lv, pn.hlv.data(), sizeof(LvJob) * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pn.work + pn.o_list, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pn.work + pn.o_used, zeros.data(), sizeof(int) * 2 * (m_max + 1), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pn.work + pn.o_rec, zeros.data(), sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  p->pn = pn;
+  return SMG_OK;
+}
+
+extern "C" smg_status smg_plan_record(smg_plan* p, float* samples, int capacity, void* stream) {
+  STCHK(need_ready(p));
+  if (!p->pn.net) return fail(SMG_ESTATE, "no network attached (smg_plan_attach_net)");
+  p->grp.drop_graphs();
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int zero = 0;
+  HIPCHK(hipMemcpyAsync(p->pn.work + p->pn.o_rec, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  p->pn.samples = capacity > 0 ? samples : nullptr;
+  p->pn.capacity = capacity > 0 && samples ? capacity : 0;
+  return SMG_OK;
+}
+
+extern "C" int smg_plan_recorded(const smg_plan* p, void* stream) {
+  if (!p || !p->pn.net) return 0;
+  int n = 0;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipMemcpyAsync(&n, p->pn.work + p->pn.o_rec, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return -1;
+  if (hipStreamSynchronize(st) != hipSuccess) return -1;
+  return n;
+}
+
+extern "C" smg_status smg_plan_net_used(const smg_plan* p, int* used, void* stream) {
+  if (!p || !p->pn.net || !used) return fail(SMG_EINVAL, "no network attached or NULL buffer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIPCHK(hipMemcpyAsync(used, p->pn.work + p->pn.o_used, sizeof(int) * 2 * (p->pn.m_max + 1), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return SMG_OK;
 }
 
 // ----------------------------------------------------------------------------

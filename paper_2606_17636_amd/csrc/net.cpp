@@ -219,13 +219,6 @@ smg_status NetDef::backward(char* base, const NetWork& w, hipStream_t st) const 
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
-struct smg_net {
-  NetDef def;
-  char* state = nullptr;
-  int step = 0;
-  smg_net(int l, int c, int i) : def(l, c, i) {}
-};
-
 static smg_status need_net(const smg_net* n) {
   if (!n) return nfail(SMG_EINVAL, "NULL net");
   if (!n->state) return nfail(SMG_ESTATE, "net state not bound (call smg_net_bind first)");

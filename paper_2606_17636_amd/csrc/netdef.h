@@ -47,3 +47,10 @@ struct NetDef {
 };
 
 }  // namespace smg
+
+struct smg_net {
+  smg::NetDef def;
+  char* state = nullptr;
+  int step = 0;
+  smg_net(int l, int c, int i) : def(l, c, i) {}
+};

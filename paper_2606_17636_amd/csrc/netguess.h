@@ -1,0 +1,17 @@
+// Launchers of the learned-guess steps inside a solve (netguess.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace smgg {
+// images: 0 = re(m=0); 2m-1 = re(m), 2m = im(m) for m = 1..m_max (n_img = 2 m_max + 1)
+hipError_t scales(const double2* f, const double2* uprev, int plane, int n_img, double* sc, hipStream_t st);
+hipError_t assemble(const double2* f, const double2* fprev, const double2* uprev, const double* sc, int plane, int n_img,
+                    float* x, hipStream_t st);
+hipError_t candidate(const double2* uprev, const float* y, const double* sc, int plane, int m_max, double2* cand,
+                     hipStream_t st);
+hipError_t select(const double* pc, const double* pu, int nblk, const double2* cand, double2* u, int plane, int m_max,
+                  int* used, hipStream_t st);
+hipError_t record(const float* x, const double2* u, const double2* uprev, const double* sc, int plane, int n_img,
+                  int* count, int capacity, float* samples, hipStream_t st);
+}  // namespace smgg

@@ -22,6 +22,7 @@ LINE_SOR, LINE_EXACT = 0, 1
 LAUNCH_GRAPH, LAUNCH_DYNAMIC = 0, 1
 WARM_PREV = 1
 TIMINGS = 2
+NET_GUESS = 4
 
 STATUS = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOCONV", -3: "SMG_EHIP", -4: "SMG_EWORKSPACE", -5: "SMG_ESTATE"}
 
@@ -105,6 +106,11 @@ def load():
                              ctypes.POINTER(Info)], ctypes.c_int),
         "smg_batch_tune_report": ([P], ctypes.c_char_p),
         "smg_batch_destroy": ([P], ctypes.c_int),
+        "smg_plan_net_work_bytes": ([P, P, ctypes.c_int], ctypes.c_size_t),
+        "smg_plan_attach_net": ([P, P, ctypes.c_int, P, ctypes.c_size_t, P], ctypes.c_int),
+        "smg_plan_record": ([P, P, ctypes.c_int, P], ctypes.c_int),
+        "smg_plan_recorded": ([P, P], ctypes.c_int),
+        "smg_plan_net_used": ([P, _PI, P], ctypes.c_int),
         "smg_net_create": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(P)], ctypes.c_int),
         "smg_net_destroy": ([P], ctypes.c_int),
         "smg_net_param_count": ([P], ctypes.c_longlong),
@@ -222,7 +228,36 @@ class Plan:
             raise ValueError(f"expected a contiguous cuda complex128 tensor of shape {shape}")
         return t
 
-    def solve(self, rho, tol=1e-8, warm=False, out=None, timings=False, allow_noconv=False):
+    # -- learned guess ---------------------------------------------------------
+    def attach_net(self, net, m_max=4):
+        """Use `net` (an smg.Net) for the guess of modes 0..m_max (None detaches)."""
+        lib = load()
+        if net is None:
+            _check(lib.smg_plan_attach_net(self._h, None, 0, None, ctypes.c_size_t(0), _stream()))
+            self._net = None
+            return self
+        nb = int(lib.smg_plan_net_work_bytes(self._h, net.handle, m_max))
+        if nb == 0:
+            raise SmgError(-1, "network does not fit this grid")
+        self._net_work, ptr = _aligned(nb, net.device)
+        _check(lib.smg_plan_attach_net(self._h, net.handle, m_max, ctypes.c_void_p(ptr), ctypes.c_size_t(nb), _stream()))
+        self._net = net
+        self.m_max = m_max
+        return self
+
+    def record(self, samples, capacity):
+        """Append training samples of later warm solves to `samples` (float32 cuda)."""
+        _check(load().smg_plan_record(self._h, _ptr(samples) if samples is not None else None, int(capacity), _stream()))
+
+    def recorded(self):
+        return int(load().smg_plan_recorded(self._h, _stream()))
+
+    def net_used(self):
+        used = np.zeros(2 * (self.m_max + 1), dtype=np.int32)
+        _check(load().smg_plan_net_used(self._h, _iptr(used), _stream()))
+        return used.reshape(2, self.m_max + 1)
+
+    def solve(self, rho, tol=1e-8, warm=False, out=None, timings=False, allow_noconv=False, net=False):
         """Phi for the density rho (cuda float64 [n_a, n_b, n_phi]); returns
         (phi, info dict)."""
         import torch
@@ -236,7 +271,7 @@ class Plan:
         r1 = np.zeros(M)
         r2 = np.zeros(M)
         info = Info(M, _iptr(c1), _iptr(c2), _dptr(r1), _dptr(r2), 0, 0, 0, 0, 0, 0, 0)
-        flags = (WARM_PREV if warm else 0) | (TIMINGS if timings else 0)
+        flags = (WARM_PREV if warm else 0) | (TIMINGS if timings else 0) | (NET_GUESS if net else 0)
         st = load().smg_solve(self._h, _ptr(rho), _ptr(phi), ctypes.c_double(tol), ctypes.c_uint(flags), _stream(),
                               ctypes.byref(info))
         _check(st, ok=(0, -2) if allow_noconv else (0,))
@@ -247,10 +282,10 @@ class Plan:
                      ms_ifft=info.ms_ifft)
         return phi, d
 
-    def solve_nosync(self, rho, phi, tol=1e-8, warm=False):
+    def solve_nosync(self, rho, phi, tol=1e-8, warm=False, net=False):
         """smg_solve without the info report (for timing loops)."""
         _check(load().smg_solve(self._h, _ptr(rho), _ptr(phi), ctypes.c_double(tol),
-                                ctypes.c_uint(WARM_PREV if warm else 0), _stream(), None))
+                                ctypes.c_uint((WARM_PREV if warm else 0) | (NET_GUESS if net else 0)), _stream(), None))
 
     # -- steps ----------------------------------------------------------------
     def mode_shape(self):

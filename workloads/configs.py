@@ -93,6 +93,13 @@ def density(name, a, b, phi, t=0.0):
     raise KeyError(name)
 
 
+def c5_blobs(seed=5, name="c5"):
+    """Blob set of an orbiting trajectory (seed 5: the measured one; 50-57:
+    the training trajectories of the learned guess)."""
+    g = GRIDS[name]
+    return D.keplerian_blobs(np.random.default_rng(seed), 12, g["a_min"], g["a_max"])
+
+
 def keplerian_dt(name="c5"):
     """Snapshot cadence of the orbiting workload: the fastest blob moves half
     an azimuthal cell per step."""

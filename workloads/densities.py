@@ -121,3 +121,23 @@ def smooth_sphere(geometry, a, b, phi, centre, radius, rho0=1.0):
     cx, cy, cz = point_cartesian(geometry, *centre)
     q = ((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2) / (radius * radius)
     return np.where(q < 1.0, rho0 * (1.0 - q) ** 3, 0.0)
+
+
+def keplerian_snapshot_device(a, b, phi, blobs, t, device="cuda"):
+    """keplerian_snapshot evaluated with torch on `device` (same formula, for
+    generating long trajectories of large grids quickly); returns a float64
+    tensor of shape (n_a, n_b, n_phi)."""
+    import torch
+    r, th, ph0, widths, amps = blobs
+    A = torch.as_tensor(np.asarray(a), dtype=torch.float64, device=device)[:, None, None]
+    B = torch.as_tensor(np.asarray(b), dtype=torch.float64, device=device)[None, :, None]
+    P = torch.as_tensor(np.asarray(phi), dtype=torch.float64, device=device)[None, None, :]
+    x = A * torch.sin(B) * torch.cos(P)
+    y = A * torch.sin(B) * torch.sin(P)
+    z = (A * torch.cos(B)).expand(-1, -1, P.shape[2])
+    out = torch.zeros(x.shape, dtype=torch.float64, device=device)
+    for i in range(len(r)):
+        cx, cy, cz = point_cartesian(SPH, r[i], th[i], ph0[i] + r[i] ** -1.5 * t)
+        d2 = (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2
+        out += amps[i] * torch.exp(-d2 / (2.0 * widths[i] * widths[i]))
+    return out
