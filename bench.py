@@ -152,6 +152,115 @@ def bench_batch(args, smg, configs, torch):
     print(json.dumps(out), flush=True)
 
 
+def bench_learned(args, smg, configs, torch):
+    """The orbiting-blob trajectory (64 snapshots, 256x128x256 log sphere):
+    warm-started solves with the learned guess of modes 0..4 (the network
+    trained at setup on 8 method-generated trajectories, seeds 50-57) vs
+    the previous step's solution as the guess, and the plain GPU form."""
+    import numpy as np
+
+    from paper_2606_17636_amd import learn
+    from workloads.densities import keplerian_snapshot_device
+    from workloads.netinit import init_params
+
+    g = configs.GRIDS["c5"]
+    m_max, n_snap = 4, 64
+    log(f"workload c5: {configs.DESCRIPTION['c5']}")
+    dt = configs.keplerian_dt()
+    t0 = time.perf_counter()
+    plan = _plan(smg, g, "chosen", args.line_solver).setup("cuda:0")
+    a, b, ph, _ = plan.geometry()
+    net = smg.Net()
+    net.set_params(init_params(0))
+    plan.attach_net(net, m_max)
+    log(f"setup (tables + DGF + tuning) {time.perf_counter() - t0:.1f}s")
+
+    def traj(seed, steps):
+        blobs = configs.c5_blobs(seed)
+        return (keplerian_snapshot_device(a, b, ph, blobs, k * dt) for k in range(steps))
+
+    t0 = time.perf_counter()
+    seeds = list(range(50, 50 + args.train_traj))
+    cap = len(seeds) * (n_snap - 1) * learn.samples_per_step(m_max)
+    buf = learn.sample_buffer(plan, cap)
+    n, _ = learn.record_trajectories(plan, [traj(s, n_snap) for s in seeds], args.tol, buf, cap)
+    log(f"recorded {n} samples from {len(seeds)} trajectories in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    losses = learn.train(net, buf, n, g["n_a"], g["n_b"], steps=args.train_steps, batch=16, lr=1e-3, seed=1,
+                         log_every=max(1, args.train_steps // 5), log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"trained {args.train_steps} steps in {t_train:.1f}s")
+    del buf
+    torch.cuda.empty_cache()
+
+    rhos = list(traj(5, n_snap))
+    phi = torch.empty_like(rhos[0])
+
+    taken = [0]
+
+    def run(pl, use_net, with_info):
+        cyc = []
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k, r in enumerate(rhos):
+            if with_info:
+                _, info = pl.solve(r, tol=args.tol, warm=k > 0, out=phi, net=use_net)
+                cyc.append(learn.low_mode_cycles(info, m_max) if k >= 2 else 0)
+                if use_net and k >= 2:
+                    taken[0] += int(pl.net_used().sum())
+            else:
+                pl.solve_nosync(r, phi, tol=args.tol, warm=k > 0, net=use_net)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, cyc
+
+    # cycle counts (info pass), then the timed passes
+    _, cyc_net = run(plan, True, True)
+    _, cyc_prev = run(plan, False, True)
+    for _ in range(max(args.warmup, 1)):
+        run(plan, True, False)
+    dt_net, _ = run(plan, True, False)
+    dt_prev, _ = run(plan, False, False)
+    zero = []
+    for r in rhos[:8]:
+        _, info = plan.solve(r, tol=args.tol, out=phi)
+        zero.append(learn.low_mode_cycles(info, m_max))
+    value = n_snap / dt_net
+    out = {
+        "metric": "Poisson solves/s at rel. residual 1e-8",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": n_snap,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt_net / n_snap, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"c5: {configs.DESCRIPTION['c5']}", "tol": args.tol,
+                   "form": "chosen + learned guess of modes 0..4", "step": "one warm-started solve of the 64-snapshot trajectory",
+                   "train": {"trajectories": len(seeds), "samples": n, "steps": args.train_steps,
+                             "loss_first": float(np.mean(losses[:10])), "loss_last": float(np.mean(losses[-20:])),
+                             "seconds": round(t_train, 1)},
+                   "low_mode_v_cycles_per_step": {"zero_guess": round(float(np.mean(zero)), 2),
+                                                  "previous_step": round(float(np.sum(cyc_prev)) / (n_snap - 2), 2),
+                                                  "network": round(float(np.sum(cyc_net)) / (n_snap - 2), 2)},
+                   "network_guess_taken": f"{taken[0]} of {2 * (m_max + 1) * (n_snap - 2)} mode solves",
+                   "previous_step_guess_solves_per_s": round(n_snap / dt_prev, 3)},
+        "roofline": None,
+    }
+    if not args.no_plain:
+        pl = _plan(smg, g, "plain", args.line_solver).setup("cuda:0")
+        run(pl, False, False)
+        dtp, _ = run(pl, False, False)
+        out["plain_gpu"] = dict(value=round(n_snap / dtp, 3), unit="solves/s", ms_per_step=round(1e3 * dtp / n_snap, 3),
+                                form="FP64, previous-step warm start, host reads after every V-cycle, no graph, no network")
+        out["speedup_vs_plain"] = round(dtp / dt_net, 3)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +273,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-GPU comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--train-traj", type=int, default=8, help="c5: training trajectories")
+    ap.add_argument("--train-steps", type=int, default=2000, help="c5: Adam steps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (the HBM-counter calibration kernel)")
     args = ap.parse_args()
@@ -189,6 +300,8 @@ def main():
 
     if args.workload == "c4":
         return bench_batch(args, smg, configs, torch)
+    if args.workload == "c5":
+        return bench_learned(args, smg, configs, torch)
     g = configs.GRIDS[args.workload]
     log(f"workload {args.workload}: {configs.DESCRIPTION[args.workload]}")
     plan = _plan(smg, g, args.form, args.line_solver)

@@ -193,9 +193,11 @@ smg_status smg_batch_destroy(smg_batch *batch);
 
 /* ---- the learned initial guess --------------------------------------------
  * A U-Net on real mode planes (one image per real or imaginary part of a
- * low-m mode), 4 input channels (f_t / s_f, (f_t - f_{t-1}) / s_f,
- * u_{t-1} / s_u, m / 4) and one output channel, the change
- * (u_t - u_{t-1}) / s_u of the plane since the previous time step.  At each
+ * low-m mode), 8 input channels (f_t / s_f, (f_t - f_{t-1}) / s_d,
+ * u_{t-1} / s_u, m / 4, (i + 1/2) / n_a - 1/2, (j + 1/2) / n_b - 1/2, 0, 0;
+ * s_f, s_d, s_u the plane RMS of f_t, f_t - f_{t-1} and u_{t-1}) and one
+ * output channel, the change (u_t - u_{t-1}) / s_o of
+ * the plane since the previous time step, s_o = s_u s_d / s_f.  At each
  * of `levels` resolutions two 3x3 convolutions with ReLU (32 channels),
  * 2x2 average pooling down, nearest upsampling and concatenation with the
  * encoder output up, a 1x1 output layer.  Weights and activations are BF16,
@@ -207,7 +209,7 @@ smg_status smg_batch_destroy(smg_batch *batch);
  * levels-2..0 (two 3x3 layers each, the first reading 64 channels), the
  * 1x1 output layer; per layer the weights [c_out][9][c_in] (tap 3(dy+1) +
  * (dx+1) reads pixel (y+dy, x+dx)) or [c_out][c_in], then the biases.
- * Images are NHWC FP32 arrays [n][h][w][4] in, [n][h][w] out; h and w are
+ * Images are NHWC FP32 arrays [n][h][w][8] in, [n][h][w] out; h and w are
  * multiples of 2^(levels-1).  The caller owns all device memory: the
  * state buffer (parameters, gradients, Adam moments, BF16 copy) and the
  * work buffer of one batch shape (activations and their gradients). */
@@ -235,7 +237,7 @@ smg_status smg_net_backward(smg_net *net, const float *dy_dev, int n, int h, int
                             void *stream);
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean squared error of
  * n samples picked by idx_host (each in [0, n_samples)) from samples_dev
- * (each sample: x [h][w][4] then the target [h][w], FP32).  loss_host (may
+ * (each sample: x [h][w][8] then the target [h][w], FP32).  loss_host (may
  * be NULL) receives the batch loss before the step (synchronises). */
 smg_status smg_net_train_step(smg_net *net, const float *samples_dev, int n_samples, const int *idx_host, int n, int h,
                               int w, float lr, void *work_dev, size_t work_bytes, void *stream, float *loss_host);
@@ -256,7 +258,7 @@ smg_status smg_plan_attach_net(smg_plan *plan, smg_net *net, int m_max, void *wo
                                void *stream);
 /* Record training samples: every later warm-started solve appends, for each
  * of its two multigrid solves and each real image of modes 0..m_max, the
- * sample (network input [n_a][n_b][4], target (u_t - u_{t-1}) / s_u
+ * sample (network input [n_a][n_b][8], target (u_t - u_{t-1}) / s_o
  * [n_a][n_b], FP32) to samples_dev while fewer than `capacity` are stored
  * (the layout smg_net_train_step reads).  Resets the count; capacity 0 stops
  * recording.  smg_plan_recorded returns the count (synchronises). */

@@ -2,13 +2,16 @@
 
 A small per-mode 2D convolutional network predicts how a low-m mode plane
 of the potential changes from one time step to the next.  The input is one
-real plane (the real or imaginary part of a mode) with four channels,
+real plane (the real or imaginary part of a mode) with eight channels,
   0: f_t / s_f              (this step's right-hand side)
-  1: (f_t - f_{t-1}) / s_f  (its change since the previous step)
+  1: (f_t - f_{t-1}) / s_d  (its change since the previous step)
   2: u_{t-1} / s_u          (the previous step's solution)
   3: m / 4                  (the azimuthal index),
-and the output is (u_t - u_{t-1}) / s_u, so that the guess is
-u_{t-1} + s_u * net(x).  s_f and s_u are per-plane RMS scales.  The output
+  4, 5: (i + 1/2) / n_a - 1/2, (j + 1/2) / n_b - 1/2  (the position on the grid),
+  6, 7: zero,
+and the output is (u_t - u_{t-1}) / s_o, so that the guess is
+u_{t-1} + s_o * net(x).  s_f, s_d and s_u are the per-plane RMS values of
+f_t, f_t - f_{t-1} and u_{t-1}, and s_o = s_u s_d / s_f.  The output
 layer starts at zero: the untrained network reproduces the previous-step
 warm start exactly.
 
@@ -39,7 +42,7 @@ import numpy as np
 
 LEVELS = 4
 CH = 32
-IN_CH = 4
+IN_CH = 8
 
 
 def layer_shapes(levels=LEVELS, ch=CH, in_ch=IN_CH):

@@ -857,7 +857,7 @@ static const double2* target_f(const smg_plan* p, int t) { return p->dptr(t == 0
 static double2* target_u(const smg_plan* p, int t) { return p->dptr(t == 0 ? p->w_psi : p->w_phi); }
 
 // Before solve t of a warm start: the network inputs of modes 0..m_max;
-// with `guess`, the candidate u_prev + s_u net(x) replaces the previous
+// with `guess`, the candidate u_prev + s_o net(x) replaces the previous
 // step's solution in every mode where, after one smoothing step of each,
 // its defect norm is the smaller one.
 static smg_status net_before(smg_plan* p, int t, bool warm, bool guess, hipStream_t st) {
@@ -869,9 +869,9 @@ static smg_status net_before(smg_plan* p, int t, bool warm, bool guess, hipStrea
   double* sc = reinterpret_cast<double*>(pn.work + pn.o_sc);
   const double2* fprev = reinterpret_cast<const double2*>(pn.work + pn.o_fprev[t]);
   HIPCHK(smgk::copy_planes(uprev, target_u(p, t), np, st));
-  HIPCHK(smgg::scales(target_f(p, t), uprev, plane, pn.n_img, sc, st));
-  HIPCHK(smgg::assemble(target_f(p, t), fprev, uprev, sc, plane, pn.n_img, reinterpret_cast<float*>(pn.work + pn.wl.x32),
-                        st));
+  HIPCHK(smgg::scales(target_f(p, t), fprev, uprev, plane, pn.n_img, sc, st));
+  HIPCHK(smgg::assemble(target_f(p, t), fprev, uprev, sc, p->spec.n_a, p->spec.n_b, pn.n_img,
+                        reinterpret_cast<float*>(pn.work + pn.wl.x32), st));
   if (!guess) return SMG_OK;
   STCHK(pn.net->def.forward(pn.work, pn.wl, st));
   double2* cand = reinterpret_cast<double2*>(pn.work + pn.o_cand);
@@ -1145,7 +1145,7 @@ static smg_status net_layout(const smg_plan* p, const smg_net* net, int m_max, P
   pn.o_cand = take(sizeof(double2) * np);
   pn.o_cs = take(sizeof(double2) * np);
   pn.o_us = take(sizeof(double2) * np);
-  pn.o_sc = take(sizeof(double) * 2 * pn.n_img);
+  pn.o_sc = take(sizeof(double) * 4 * pn.n_img);
   NormJob hj{};
   hj.L = p->levels.empty() ? LevelDev{} : p->levels[0];
   pn.nblk = smgk::norm_blocks(&hj, 1);

@@ -237,7 +237,7 @@ extern "C" smg_status smg_net_create(int levels, int channels, smg_net** out) {
   *out = nullptr;
   if (levels < 1 || levels > kNetMaxLevels) return nfail(SMG_EINVAL, "levels must be in [1, 6]");
   if (channels != 32) return nfail(SMG_EINVAL, "channels must be 32");
-  smg_net* n = new (std::nothrow) smg_net(levels, channels, 4);
+  smg_net* n = new (std::nothrow) smg_net(levels, channels, 8);
   if (!n) return nfail(SMG_EINVAL, "out of host memory");
   *out = n;
   return SMG_OK;

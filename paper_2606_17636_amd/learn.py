@@ -21,7 +21,7 @@ def samples_per_step(m_max):
 
 def sample_buffer(plan, capacity, device="cuda"):
     import torch
-    return torch.empty(capacity * plan.n_a * plan.n_b * 5, dtype=torch.float32, device=device)
+    return torch.empty(capacity * plan.n_a * plan.n_b * 9, dtype=torch.float32, device=device)
 
 
 def record_trajectories(plan, trajectories, tol, samples, capacity):

@@ -500,7 +500,7 @@ class Net:
         ia = np.ascontiguousarray(np.asarray(idx, dtype=np.int32))
         wp, wb = self.work(n, h, w)
         loss = ctypes.c_float()
-        n_samples = samples.numel() // (h * w * 5)
+        n_samples = samples.numel() // (h * w * 9)
         _check(load().smg_net_train_step(self._h, _ptr(samples), n_samples, _iptr(ia), n, h, w, ctypes.c_float(lr), wp,
                                          wb, _stream(), ctypes.byref(loss)))
         return loss.value

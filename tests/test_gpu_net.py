@@ -35,7 +35,7 @@ def test_forward_matches_oracle(gnet, shape, tol):
     n, h, w = shape
     rng = np.random.default_rng(10 + h)
     p = init_params(11, zero_output=False)
-    x = rng.normal(size=(n, h, w, 4))
+    x = rng.normal(size=(n, h, w, 8))
     gnet.set_params(p)
     y = gnet.forward(torch.from_numpy(x.astype(np.float32)).cuda()).cpu().numpy()
     ref, _ = onet.forward(p.astype(np.float32).astype(np.float64), x.astype(np.float32).astype(np.float64))
@@ -48,7 +48,7 @@ def test_backward_matches_oracle(gnet, shape):
     n, h, w = shape
     rng = np.random.default_rng(20 + h)
     p = init_params(12, zero_output=False)
-    x = rng.normal(size=(n, h, w, 4)).astype(np.float32)
+    x = rng.normal(size=(n, h, w, 8)).astype(np.float32)
     t = rng.normal(size=(n, h, w)).astype(np.float32)
     pp = p.astype(np.float32).astype(np.float64)
     ref_out, cache = onet.forward(pp, x.astype(np.float64))
@@ -71,7 +71,7 @@ def test_training_lowers_loss(gnet):
     through smg_net_train_step lower the loss by an order of magnitude."""
     rng = np.random.default_rng(30)
     n, h, w = 64, 16, 16
-    x = rng.normal(size=(n, h, w, 4)).astype(np.float32)
+    x = rng.normal(size=(n, h, w, 8)).astype(np.float32)
     t = 0.5 * x[..., 1] + 0.25 * np.roll(x[..., 1], 1, axis=1)
     samples = np.concatenate([x.reshape(n, -1), t.reshape(n, -1)], axis=1).astype(np.float32)
     st = torch.from_numpy(samples).cuda().contiguous()

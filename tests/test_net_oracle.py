@@ -54,7 +54,7 @@ def test_backward_matches_finite_differences(levels, ch):
     rng = np.random.default_rng(4)
     P = net.n_params(levels, ch)
     params = rng.normal(0, 0.5, P)
-    x = rng.normal(0, 1, (2, 8, 8, 4))
+    x = rng.normal(0, 1, (2, 8, 8, 8))
     t = rng.normal(0, 1, (2, 8, 8))
 
     def L(p):
@@ -70,7 +70,7 @@ def test_backward_matches_finite_differences(levels, ch):
 
 
 def test_zero_output_layer_gives_zero_change():
-    x = np.random.default_rng(5).normal(size=(1, 16, 16, 4))
+    x = np.random.default_rng(5).normal(size=(1, 16, 16, 8))
     out, _ = net.forward(init_params(7), x)
     assert np.all(out == 0.0)
 
@@ -78,7 +78,7 @@ def test_zero_output_layer_gives_zero_change():
 def test_rounded_forward_is_close_to_exact():
     rng = np.random.default_rng(6)
     p = init_params(8, zero_output=False)
-    x = rng.normal(size=(1, 16, 16, 4))
+    x = rng.normal(size=(1, 16, 16, 8))
     a, _ = net.forward(p, x, rounding=True)
     b, _ = net.forward(p, x, rounding=False)
     assert np.linalg.norm(a - b) < 0.05 * np.linalg.norm(b)

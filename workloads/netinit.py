@@ -8,7 +8,7 @@ import math
 import numpy as np
 
 
-def layer_shapes(levels=4, ch=32, in_ch=4):
+def layer_shapes(levels=4, ch=32, in_ch=8):
     shapes = []
     cin = in_ch
     for _ in range(levels):
@@ -20,7 +20,7 @@ def layer_shapes(levels=4, ch=32, in_ch=4):
     return shapes
 
 
-def init_params(seed, levels=4, ch=32, in_ch=4, zero_output=True):
+def init_params(seed, levels=4, ch=32, in_ch=8, zero_output=True):
     rng = np.random.default_rng(seed)
     parts = []
     for kind, ci, co in layer_shapes(levels, ch, in_ch):
