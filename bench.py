@@ -302,8 +302,11 @@ def main():
         return bench_batch(args, smg, configs, torch)
     if args.workload == "c5":
         return bench_learned(args, smg, configs, torch)
-    g = configs.GRIDS[args.workload]
-    log(f"workload {args.workload}: {configs.DESCRIPTION[args.workload]}")
+    # c5-snapshot: one snapshot (t = 0) of the orbiting workload, cold solves
+    wl = "c5" if args.workload == "c5-snapshot" else args.workload
+    desc = configs.DESCRIPTION[wl] + (", snapshot t=0, zero initial guess" if wl != args.workload else "")
+    g = configs.GRIDS[wl]
+    log(f"workload {args.workload}: {desc}")
     plan = _plan(smg, g, args.form, args.line_solver)
     t0 = time.perf_counter()
     plan.setup("cuda:0")
@@ -313,7 +316,7 @@ def main():
     if plan.tune_report():
         log("autotune: " + " | ".join(l for l in plan.tune_report().splitlines() if l.startswith("planes <=")))
     a, b, p, _ = plan.geometry()
-    rho = torch.from_numpy(configs.density(args.workload, a, b, p)).to("cuda:0")
+    rho = torch.from_numpy(configs.density(wl, a, b, p)).to("cuda:0")
     phi = torch.empty_like(rho)
     for _ in range(max(args.warmup, 2)):   # the first solve of a kind runs the host loop and fixes the schedule
         plan.solve_nosync(rho, phi, tol=args.tol)
@@ -353,7 +356,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if args.form == "chosen" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {configs.DESCRIPTION[args.workload]}", "tol": args.tol,
+        "config": {"workload": f"{args.workload}: {desc}", "tol": args.tol,
                    "form": args.form, "line_solver": args.line_solver, "initial_guess": "zero",
                    "v_cycles_per_solve": cyc,
                    "v_cycles_m0": [int(info["cycles1"][0]), int(info["cycles2"][0])],
@@ -373,7 +376,7 @@ def main():
         log(f"plain GPU form: {args.steps / dtp:.2f} solves/s")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.tol, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(wl, args.tol, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 
