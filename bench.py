@@ -27,6 +27,27 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
+def measured_traffic(workload, kernel_class):
+    """HBM bytes per launch of `kernel_class` from the committed PMC
+    summary (profiles/hbm_traffic.txt), or None when there is none or the
+    kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        w, k, src, h, val = line.split()[:5]
+        if w != workload or k != kernel_class:
+            continue
+        with open(os.path.join(ROOT, src), "rb") as f:
+            if hashlib.sha1(f.read()).hexdigest()[:12] != h:
+                return None
+        return float(val)
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -338,7 +359,7 @@ def main():
     name, st = max(stats.items(), key=lambda kv: kv[1]["total_ms"])
     achieved = st["bytes"] / (st["total_ms"] * 1e-3) / 1e9
     roofline = dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(args.workload, name),
                     avg_launch_us=round(1e3 * st["total_ms"] / st["launches"], 3),
                     bytes_per_launch=round(st["bytes"] / st["launches"]))
     kern = {k: dict(launches=v["launches"] // args.steps, ms=round(v["total_ms"] / args.steps, 4),
