@@ -7,8 +7,8 @@
 
 namespace {
 
-constexpr int kConvThreads = 256;
-constexpr int kPerThread = 16;     // list capacity kConvThreads * kPerThread
+constexpr int kConvThreads = 1024;
+constexpr int kPerThread = 4;      // list capacity kConvThreads * kPerThread
 constexpr int kMaxProblems = 256;  // problems one batch can hold
 
 // Exclusive prefix sum over the block of one int per thread (wave shuffles,
@@ -37,15 +37,23 @@ __device__ double sum_partial(const double* partial, int p, int nblk) {
   return sqrt(s);
 }
 
+// s_nrm[p] = sqrt(sum of the partials of list position p) for p < n: one
+// position per thread, strided over the block (independent loads in flight)
+__device__ void norms_to_lds(const double* partial, int n, int nblk, double* s_nrm) {
+  for (int p = threadIdx.x; p < n; p += blockDim.x) s_nrm[p] = sum_partial(partial, p, nblk);
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(kConvThreads) k_conv_init(const NormJob* __restrict__ jobs, const int* __restrict__ all,
                                                            int n, int n_prob, const double* __restrict__ partial,
                                                            int nblk, double tol, double floor_factor, ConvState cs,
                                                            int* __restrict__ list, int* __restrict__ count) {
   __shared__ unsigned long long dmax[kMaxProblems];
   __shared__ int buf[kConvThreads / 64];
+  __shared__ double s_nrm[kConvThreads * kPerThread];
   int total;
   for (int q = threadIdx.x; q < n_prob; q += blockDim.x) dmax[q] = 0ull;
-  __syncthreads();
+  norms_to_lds(partial, n, nblk, s_nrm);
   int e[kPerThread], g[kPerThread];
   double d[kPerThread];
 #pragma unroll
@@ -56,7 +64,7 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_init(const NormJob* __res
     e[k] = all[p];
     const int q = ent_prob(e[k]);
     g[k] = jobs[q].base + ent_slot(e[k]);
-    d[k] = sum_partial(partial, p, nblk);
+    d[k] = s_nrm[p];
     cs.d0[g[k]] = d[k];
     cs.cur[g[k]] = d[k];
     cs.cyc[g[k]] = 0;
@@ -88,8 +96,10 @@ __global__ void __launch_bounds__(kConvThreads) k_converge(const NormJob* __rest
                                                           int max_cycles, int count_cycle, int* __restrict__ list,
                                                           int* __restrict__ count) {
   __shared__ int buf[kConvThreads / 64];
+  __shared__ double s_nrm[kConvThreads * kPerThread];
   int total;
   const int n = *count;  // every thread reads it before the block writes it
+  norms_to_lds(partial, min(n, cap), nblk, s_nrm);
   int e[kPerThread];
   bool kk[kPerThread];
   int keep = 0;
@@ -102,7 +112,7 @@ __global__ void __launch_bounds__(kConvThreads) k_converge(const NormJob* __rest
     e[k] = list[p];
     if (p < cap) {
       const int g = jobs[ent_prob(e[k])].base + ent_slot(e[k]);
-      const double nrm = sum_partial(partial, p, nblk);
+      const double nrm = s_nrm[p];
       cs.cur[g] = nrm;
       const int c = cs.cyc[g] + count_cycle;
       cs.cyc[g] = c;
