@@ -63,43 +63,108 @@ __device__ __forceinline__ Tab<R> stage_tab(const LevelDev& L, int m, R* buf) {
   return tab_at<R>(buf, na, nb);
 }
 
+// Ordering of LDS accesses between the even-odd passes of one line: every
+// line is relaxed by a single wave, whose LDS operations complete in issue
+// order, so only the compiler must keep the passes apart.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One zebra phase in direction DIR (0: radial lines, fixed j, points along
+// i; 1: polar lines, fixed i, points along j): the lines of colour 0, then
+// those of colour 1, each line relaxed by n_sor even-odd SOR passes.  A
+// wave takes G lines at a time (lane -> line g, point index k of the
+// current parity), keeps the stencil coefficients of its two cells (one per
+// parity) in registers, and needs no block barrier between the passes of a
+// line; one barrier separates the colours.
 // u: padded (na+2) x (nb+2) plane, f: na x nb.
 template <int DIR, typename R>
 __device__ __forceinline__ void sor_phase(const LevelDev& L, const Tab<R>& T, typename Vec<R>::T* u, const typename Vec<R>::T* f,
                           int n_sor) {
   using V = typename Vec<R>::T;
   const int na = L.na, nb = L.nb, nc = nb + 2;
+  const int npts = DIR == 0 ? na : nb;
+  const int nlines = DIR == 0 ? nb : na;
+  const int half = (npts + 1) / 2;                 // points of parity 0
+  const int G = half >= 64 ? 1 : 64 / half;        // lines per wave step
+  const int cpl = (half + 63) / 64;                // cells per lane and parity
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  const int g = G > 1 ? lane / half : 0, k0 = G > 1 ? lane - g * half : lane;
   for (int lc = 0; lc < 2; ++lc) {
-    const int nl = DIR == 0 ? (nb - lc + 1) / 2 : (na - lc + 1) / 2;
-    for (int it = 0; it < n_sor; ++it) {
-      for (int pc = 0; pc < 2; ++pc) {
-        const int np = DIR == 0 ? (na - pc + 1) / 2 : (nb - pc + 1) / 2;
-        const int total = nl * np;
-        for (int t = threadIdx.x; t < total; t += blockDim.x) {
-          int i, j;
-          if (DIR == 0) {
-            i = pc + 2 * (t / nl);
-            j = lc + 2 * (t % nl);
-          } else {
-            i = lc + 2 * (t / np);
-            j = pc + 2 * (t % np);
+    const int nlc = (nlines - lc + 1) / 2;          // lines of this colour
+    for (int base = wave * G; base < nlc; base += nwave * G) {
+      const int li = base + g;                     // this lane's line (colour index)
+      const bool lane_ok = (G == 1 || g < G) && li < nlc;
+      const int line = lc + 2 * li;
+      if (cpl > 1) {
+        // lines longer than 128 points: each pass sweeps the lane's cells of
+        // that parity, coefficients read as needed
+        for (int it = 0; it < n_sor; ++it) {
+          for (int pc = 0; pc < 2; ++pc) {
+            for (int c = 0; c < cpl && lane_ok; ++c) {
+              const int pt = pc + 2 * (k0 + 64 * c);
+              if (pt >= npts) break;
+              const int i = DIR == 1 ? line : pt, j = DIR == 1 ? pt : line;
+              const int qq = (i + 1) * nc + (j + 1);
+              const R Rr = T.Rr[i];
+              const R cv = T.Ca[i] + Rr * T.Cb[j];
+              const R wv = DIR == 1 ? T.wb[i] : T.wr[j];
+              const R ua = T.ua[i], da = T.da[i], ub = Rr * T.ub[j], db = Rr * T.db[j];
+              const V un = u[qq + nc], us = u[qq - nc], ue = u[qq + 1], uw = u[qq - 1];
+              const V fq = f[i * nb + j];
+              const R sx = ua * un.x + da * us.x + ub * ue.x + db * uw.x;
+              const R sy = ua * un.y + da * us.y + ub * ue.y + db * uw.y;
+              const V old = u[qq];
+              const R tx = (fq.x - sx) / cv, ty = (fq.y - sy) / cv;
+              u[qq] = mkv<R>(old.x + wv * (tx - old.x), old.y + wv * (ty - old.y));
+            }
+            wave_sync();
           }
-          const int q = (i + 1) * nc + (j + 1);
-          const R Rr = T.Rr[i];
-          const R c = T.Ca[i] + Rr * T.Cb[j];
-          const R w = DIR == 1 ? T.wb[i] : T.wr[j];
-          const R ua = T.ua[i], da = T.da[i], ub = Rr * T.ub[j], db = Rr * T.db[j];
-          const V un = u[q + nc], us = u[q - nc], ue = u[q + 1], uw = u[q - 1];
-          const V fv = f[i * nb + j];
-          const R sx = ua * un.x + da * us.x + ub * ue.x + db * uw.x;
-          const R sy = ua * un.y + da * us.y + ub * ue.y + db * uw.y;
-          const V old = u[q];
-          const R tx = (fv.x - sx) / c, ty = (fv.y - sy) / c;
-          u[q] = mkv<R>(old.x + w * (tx - old.x), old.y + w * (ty - old.y));
         }
-        __syncthreads();
+        continue;
+      }
+      {
+        const int k = k0;
+        // the lane's cell of each parity and its coefficients
+        int q[2];
+        R cc[2], w[2], a1[2], a2[2], b1[2], b2[2];
+        V fv[2];
+        bool ok[2];
+        for (int pc = 0; pc < 2; ++pc) {
+          const int pt = pc + 2 * k;
+          ok[pc] = lane_ok && pt < npts;
+          const int i = DIR == 1 ? line : pt, j = DIR == 1 ? pt : line;
+          q[pc] = (i + 1) * nc + (j + 1);
+          if (ok[pc]) {
+            const R Rr = T.Rr[i];
+            cc[pc] = T.Ca[i] + Rr * T.Cb[j];
+            w[pc] = DIR == 1 ? T.wb[i] : T.wr[j];
+            a1[pc] = T.ua[i];
+            a2[pc] = T.da[i];
+            b1[pc] = Rr * T.ub[j];
+            b2[pc] = Rr * T.db[j];
+            fv[pc] = f[i * nb + j];
+          }
+        }
+        for (int it = 0; it < n_sor; ++it) {
+          for (int pc = 0; pc < 2; ++pc) {
+            if (ok[pc]) {
+              const int qq = q[pc];
+              const V un = u[qq + nc], us = u[qq - nc], ue = u[qq + 1], uw = u[qq - 1];
+              const R sx = a1[pc] * un.x + a2[pc] * us.x + b1[pc] * ue.x + b2[pc] * uw.x;
+              const R sy = a1[pc] * un.y + a2[pc] * us.y + b1[pc] * ue.y + b2[pc] * uw.y;
+              const V old = u[qq];
+              const R tx = (fv[pc].x - sx) / cc[pc], ty = (fv[pc].y - sy) / cc[pc];
+              u[qq] = mkv<R>(old.x + w[pc] * (tx - old.x), old.y + w[pc] * (ty - old.y));
+            }
+            wave_sync();
+          }
+        }
       }
     }
+    __syncthreads();
   }
 }
 
