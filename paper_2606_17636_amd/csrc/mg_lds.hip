@@ -14,7 +14,7 @@
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;  // most threads of a fused-cycle block
 
 struct Red {
   double* buf;
@@ -468,9 +468,10 @@ size_t cycle_bytes(const LdsLevels& LL) {
 }
 
 int cycle_threads(const LdsLevels& LL) {
-  // the fused levels are small: few threads make the colour-step barriers cheap
+  // enough waves that each takes about one line group per colour on the
+  // first fused level; few threads keep the barriers of small levels cheap
   const int cells = LL.L[0].na * LL.L[0].nb;
-  return cells >= 2048 ? 256 : (cells >= 512 ? 128 : 64);
+  return cells >= 2048 ? 512 : (cells >= 512 ? 256 : 64);
 }
 
 }  // namespace
