@@ -25,8 +25,10 @@ coarse operator states it ((-1)^m mirror at poles, kappa_c at Dirichlet
 edges, below).
 
 Coarsening: factor two in both directions while both sides are even, the
-smaller coarse side stays >= 2 and the coarse inner radial ghost face stays
-at r > 0; the coarse operator is rediscretised on the coarse faces.  The
+smaller coarse side stays >= 2, the coarse inner radial ghost face stays at
+r > 0 and the level has more than 128 cells (the paper does not fix the
+coarsest size; a level that small is solved to convergence); the coarse
+operator is rediscretised on the coarse faces.  The
 paper leaves the coarse boundary closure open; here the error vanishes on
 every level at the point where the problem grid puts it (the finest ghost
 centre), not at the coarse ghost centre: a coarse Dirichlet ghost is
@@ -47,6 +49,9 @@ from .omega import omega_1d, omega_2d
 from .operator import PlaneOperator, main_edges
 
 FLOOR = 1e-6
+# a level of at most this many cells is the coarsest (it is solved to
+# convergence; coarser levels would only add smoothing latency)
+MAX_COARSEST = 128
 
 
 def level_sizes(spec):
@@ -54,6 +59,8 @@ def level_sizes(spec):
     s = 1
     while True:
         na, nb = sizes[-1]
+        if na * nb <= MAX_COARSEST:
+            break
         if na % 2 or nb % 2 or min(na, nb) // 2 < 2:
             break
         if radial_face(spec, -2 * s) <= 0.0:     # coarse inner ghost face

@@ -176,13 +176,15 @@ Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, c
   Hierarchy h;
   h.spec = s;
   h.M = (int)modes.size();
-  // level sizes: halve while both sides are even, the smaller coarse side
-  // stays >= 2 and (for the problem grid) the coarse inner radial ghost face
-  // stays at r > 0.
+  // level sizes: halve while the level has more than kMaxDirect cells (a
+  // level that small is the coarsest and is solved exactly), both sides are
+  // even, the smaller coarse side stays >= 2 and the coarse inner radial
+  // ghost face stays at r > 0.
   std::vector<std::pair<int, int>> sizes{{na, nb}};
   long stride = 1;
   while (true) {
     int ca = sizes.back().first, cb = sizes.back().second;
+    if (ca * cb <= kMaxDirect) break;
     if ((ca % 2) || (cb % 2) || std::min(ca, cb) / 2 < 2) break;
     if (s.radial_face((double)((a_lo - 1) - 2 * stride)) <= 0.0) break;
     sizes.push_back({ca / 2, cb / 2});

@@ -265,12 +265,14 @@ def test_multigrid_mode_dependence_and_rate():
     assert 10 <= cycles[0] <= 25
 
 
-def test_literal_restriction_reading_diverges_on_log_grid():
+def test_literal_restriction_reading_converges_slowly_on_log_grid():
     """The literal reading of the restriction weights (S_ij multiplying the
-    fine point it is measured from) does not converge on a logarithmic grid;
-    the opposite-corner reading does.  Pins the reading documented in the
-    multigrid module."""
-    spec = _spec(SPH, "log", 64, 32, 8)
+    fine point it is measured from) gives a much slower V-cycle on a
+    logarithmic grid than the opposite-corner (bilinear) reading: over three
+    times the per-cycle defect reduction factor on 128x64 (with a hierarchy
+    that coarsens further, to 4x2, it diverges).  Pins the reading
+    documented in the multigrid module."""
+    spec = _spec(SPH, "log", 128, 64, 8)
     rng = np.random.default_rng(3)
     f = rng.standard_normal((spec.n_a, spec.n_b)) + 0j
     ratios = {}
@@ -282,8 +284,8 @@ def test_literal_restriction_reading_diverges_on_log_grid():
         for _ in range(4):
             h.vcycle(u, f, 0)
         ratios[mode] = (h.defect_norm(u, f, 0) / d1) ** 0.25
-    assert ratios["bilinear"] < 0.6
-    assert ratios["literal"] > 1.0
+    assert ratios["bilinear"] < 0.25
+    assert ratios["literal"] > 3.0 * ratios["bilinear"]
 
 
 # -- James boundary and the full pipeline (Secs. 4, 5.1) -------------------------------
