@@ -1201,7 +1201,6 @@ extern "C" smg_status smg_plan_attach_net(smg_plan* p, smg_net* net, int m_max, 
           return fail(SMG_EINVAL, "smoothing step of the guess does not fit in LDS");
         J.tile[dir] = sh.tile;
         J.ntile[dir] = sh.ntile;
-        J.stage[dir] = sh.stage;
         J.scratch[dir] = sh.scratch;
       }
       pn.hlv.push_back(J);

@@ -11,20 +11,26 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// One-block-per-plane fused levels of problem `P` from level `first` down.
-LdsLevels lds_levels(const MGProblem& P, int first, bool exact) {
+// One-block-per-plane fused levels of problem `P` from level `first` down:
+// the plain LDS layout when it fits in 64 KiB, else the aliased one (the
+// coarser levels reuse the first level's f storage).
+LdsLevels lds_levels(const MGProblem& P, int first, bool exact, bool fp32) {
   LdsLevels LL{};
   const int L = (int)P.L.size();
   LL.n = L - first;
-  int words = 0;
-  for (int l = first; l < L; ++l) {
-    LL.L[l - first] = P.L[l];
-    words += (P.L[l].na + 2) * (P.L[l].nb + 2) + P.L[l].na * P.L[l].nb;
-  }
-  LL.words = words;
+  for (int l = first; l < L; ++l) LL.L[l - first] = P.L[l];
   LL.scratch = smgk::lds_cycle_scratch(LL, exact);
+  LL.alias = 0;
+  if (LL.n > 1 && smgk::lds_cycle_bytes(LL, fp32) > 64 * 1024) {
+    LL.alias = 1;
+    if (!smgk::lds_cycle_alias_ok(LL)) LL.alias = 0;
+  }
   return LL;
 }
+
+// LDS a fused-cycle block may use (the device limit less the kernel's own
+// static arrays).
+size_t lds_cycle_max() { return smgk::lds_limit() - 1024; }
 
 }  // namespace
 
@@ -81,12 +87,12 @@ smg_status Engine::init(std::vector<MGProblem> probs, int n_targets, const MGPar
     int fm = L - 1;
     for (int first = 0; first < L; ++first) {
       if (L - first > kMaxLdsLevels) continue;
-      LdsLevels LL = lds_levels(pr, first, prm_.exact);
-      if (smgk::lds_cycle_bytes(LL, prm_.fp32) <= kLdsCycleMax) { fm = first; break; }
+      LdsLevels LL = lds_levels(pr, first, prm_.exact, prm_.fp32);
+      if (smgk::lds_cycle_bytes(LL, prm_.fp32) <= lds_cycle_max()) { fm = first; break; }
     }
     if (L - fm > kMaxLdsLevels) EFAIL(SMG_EINVAL, "engine: too many fused levels");
-    LdsLevels LL = lds_levels(pr, fm, prm_.exact);
-    if (smgk::lds_cycle_bytes(LL, prm_.fp32) > kLdsCycleMax) EFAIL(SMG_EINVAL, "engine: coarsest level does not fit in LDS");
+    LdsLevels LL = lds_levels(pr, fm, prm_.exact, prm_.fp32);
+    if (smgk::lds_cycle_bytes(LL, prm_.fp32) > lds_cycle_max()) EFAIL(SMG_EINVAL, "engine: coarsest level does not fit in LDS");
     first_min_[q] = fm;
   }
   if (n_total_ > kMaxPlanes) EFAIL(SMG_EINVAL, strprintf("a batch holds at most %d planes", kMaxPlanes));
@@ -191,14 +197,13 @@ smg_status Engine::build_jobs(int target, const MGConfig& c, std::vector<LvJob>&
         }
         J.tile[dir] = sh.tile;
         J.ntile[dir] = sh.ntile;
-        J.stage[dir] = sh.stage;
         J.scratch[dir] = sh.scratch;
       }
     }
     if (first < L) {
       LdsJob& J = lds[q];
-      J.LL = lds_levels(pr, first, prm_.exact);
-      if (smgk::lds_cycle_bytes(J.LL, prm_.fp32) > kLdsCycleMax) return SMG_EINVAL;
+      J.LL = lds_levels(pr, first, prm_.exact, prm_.fp32);
+      if (smgk::lds_cycle_bytes(J.LL, prm_.fp32) > lds_cycle_max()) return SMG_EINVAL;
       J.u = first == 0 && !prm_.fp32 ? (void*)pr.u0[target] : pr.u[first];
       J.f = first == 0 && !prm_.fp32 ? (const void*)pr.f0[target] : pr.f[first];
       J.mode = pr.mode;
@@ -534,7 +539,7 @@ smg_status Engine::autotune(int target, hipStream_t st, std::string* report) {
       }
     }
     if (bt >= 1e30f) EFAIL(SMG_EINVAL, "autotune: no configuration fits");
-    rep += strprintf("planes <= %d: fused from +%d, %d blocks\n", cap, bc.lds_first[0] - first_min_[0], bc.target_blocks);
+    rep += strprintf("planes <= %d: fused from level %d (+%d), %d blocks\n", cap, bc.lds_first[0], bc.lds_first[0] - first_min_[0], bc.target_blocks);
     best.push_back(bc);
   }
   cfg_.resize(std::min(cfg_.size(), (size_t)scratch));

@@ -53,7 +53,6 @@ class Engine {
   static constexpr int kMaxConfigs = 6;
   static constexpr int kNormBlocks = 64;
   static constexpr int kMaxPlanes = 4096;
-  static constexpr size_t kLdsCycleMax = 63 * 1024;
 
   // Device bytes the engine carves from its region.
   static size_t region_bytes(int n_targets, int n_prob, int max_levels, int n_planes);

@@ -338,7 +338,10 @@ Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, c
             }
           }
         }
-        std::copy(I.begin(), I.end(), T.cinv.begin() + (size_t)p * n * n);
+        // stored transposed: cinv[p][l][k] = (A^-1)[k][l]
+        double* out = T.cinv.data() + (size_t)p * n * n;
+        for (int k = 0; k < n; ++k)
+          for (int l = 0; l < n; ++l) out[(size_t)l * n + k] = I[(size_t)k * n + l];
       }
     }
   }

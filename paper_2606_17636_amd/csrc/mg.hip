@@ -25,6 +25,7 @@
 // variant) each line is solved by the Thomas algorithm.
 #include <algorithm>
 
+#include "relax_dev.h"
 #include "smg_internal.h"
 #include "vec.h"
 
@@ -38,28 +39,43 @@ __device__ __forceinline__ typename Vec<R>::T resid_at(const LevelDev& L, int m,
                                                        const typename Vec<R>::T* __restrict__ f, int i, int j) {
   using V = typename Vec<R>::T;
   const int na = L.na, nb = L.nb;
+  const auto ug = gbl(u);
   const size_t row = (size_t)i * nb;
   const int ip = min(i + 1, na - 1), im = max(i - 1, 0);
   const int jp = min(j + 1, nb - 1), jm = max(j - 1, 0);
-  const R Rr = (R)L.Rr[i];
-  const R c = (R)L.Ca[(size_t)m * na + i] + Rr * (R)L.Cb[(size_t)m * nb + j];
-  const V uc = u[row + j];
+  const R Rr = (R)gbl(L.Rr)[i];
+  const R c = (R)gbl(L.Ca)[(size_t)m * na + i] + Rr * (R)gbl(L.Cb)[(size_t)m * nb + j];
+  const V uc = ug[row + j];
   V acc = mkv<R>(c * uc.x, c * uc.y);
-  acc = axpy<R>((R)L.ua[i], u[(size_t)ip * nb + j], acc);
-  acc = axpy<R>((R)L.da[i], u[(size_t)im * nb + j], acc);
-  acc = axpy<R>(Rr * (R)L.ub[j], u[row + jp], acc);
-  acc = axpy<R>(Rr * (R)L.db[j], u[row + jm], acc);
-  const V fv = f[row + j];
+  acc = axpy<R>((R)gbl(L.ua)[i], ug[(size_t)ip * nb + j], acc);
+  acc = axpy<R>((R)gbl(L.da)[i], ug[(size_t)im * nb + j], acc);
+  acc = axpy<R>(Rr * (R)gbl(L.ub)[j], ug[row + jp], acc);
+  acc = axpy<R>(Rr * (R)gbl(L.db)[j], ug[row + jm], acc);
+  const V fv = gbl(f)[row + j];
   return mkv<R>(fv.x - acc.x, fv.y - acc.y);
 }
 
 // ---------------------------------------------------------------------------
 // Smoother.  DIR = 1: polar lines (rows i, points along j); tile = rows
 // [i0-2, i0+T+2) x all columns.  DIR = 0: radial lines (columns j, points
-// along i); tile = all rows x columns [j0-2, j0+W+2).  LDS holds the tile
-// with one zero column/row of padding at the ends of the lines.
+// along i); tile = all rows x columns [j0-2, j0+W+2).  LDS holds the u tile
+// with one zero column/row of padding at the ends of the lines, f of the
+// lines the block relaxes (owned lines and the inner halo line on each side)
+// in the same layout, and the 1D stencil tables of the tile rounded to R.
+// All global reads are issued before the first barrier; the colours then
+// run out of LDS and registers.
 // ---------------------------------------------------------------------------
-template <int DIR, bool EXACT, typename R>
+// LDS bytes of a smoother block: u tile, f tile (the SOR variant; the exact
+// variant reads each f value once, from global memory), exact-line scratch
+// and tables.
+template <typename R>
+__host__ __device__ inline size_t smooth_lds_bytes(int dir, int na, int nb, int tile, bool exact, int scratch) {
+  const size_t nr = dir == 0 ? (size_t)na + 2 : (size_t)tile + 4;
+  const size_t nc = dir == 0 ? (size_t)tile + 4 : (size_t)nb + 2;
+  return (exact ? 1 : 2) * sizeof(typename Vec<R>::T) * nr * nc + sizeof(R) * ((size_t)scratch + 5 * nr + 4 * nc);
+}
+
+template <int DIR, bool EXACT, int PMAX, typename R>
 __global__ void __launch_bounds__(kThreads) k_smooth(const LvJob* __restrict__ jobs, BatchRef bt, int n_sor) {
   using V = typename Vec<R>::T;
   extern __shared__ char smem[];
@@ -72,10 +88,10 @@ __global__ void __launch_bounds__(kThreads) k_smooth(const LvJob* __restrict__ j
   const int slot = ent_slot(e);
   const int m = J.mode ? J.mode[slot] : slot;
   const LevelDev L = J.L;
-  const int tile = J.tile[DIR], scratch_words = J.scratch[DIR], stage = J.stage[DIR];
+  const int tile = J.tile[DIR], scratch_words = J.scratch[DIR];
   const int na = L.na, nb = L.nb;
-  V* u = static_cast<V*>(J.u) + (size_t)slot * na * nb;
-  const V* f = static_cast<const V*>(J.f) + (size_t)slot * na * nb;
+  const auto u = gbl(static_cast<V*>(J.u) + (size_t)slot * na * nb);
+  const auto f = gbl(static_cast<const V*>(J.f) + (size_t)slot * na * nb);
   // tile geometry in (row, col) = (i, j) coordinates
   int r0, nr, c0, nc;  // first global row/col held in LDS and counts (incl. halo/pad)
   if (DIR == 1) {
@@ -87,7 +103,16 @@ __global__ void __launch_bounds__(kThreads) k_smooth(const LvJob* __restrict__ j
     r0 = -1; nr = na + 2;
     c0 = j0 - 2; nc = tile + 4;
   }
-  // load the tile (zeros outside the plane)
+  V* fs = sh + nr * nc;  // staged f (SOR variant only)
+  // line range of this tile (the coordinate across the lines)
+  const int lbeg = blockIdx.x * tile;                     // first owned line
+  const int nlines_total = DIR == 1 ? na : nb;
+  const int lend = min(lbeg + tile, nlines_total);        // one past the last owned line
+  const int npts = DIR == 1 ? nb : na;                    // points per line
+  const int fbeg = max(lbeg - 1, 0), fend = min(lend + 1, nlines_total);
+  // u tile (zeros outside the plane) and f of the relaxed lines, four loads
+  // in flight per thread
+#pragma unroll 4
   for (int t = threadIdx.x; t < nr * nc; t += blockDim.x) {
     const int rr = t / nc, cc = t - rr * nc;
     const int i = r0 + rr, j = c0 + cc;
@@ -95,140 +120,102 @@ __global__ void __launch_bounds__(kThreads) k_smooth(const LvJob* __restrict__ j
     if (i >= 0 && i < na && j >= 0 && j < nb) v = u[(size_t)i * nb + j];
     sh[t] = v;
   }
-  // line range of this tile (the coordinate across the lines)
-  const int lbeg = blockIdx.x * tile;                     // first owned line
-  const int lend = min(lbeg + tile, DIR == 1 ? na : nb);  // one past the last owned line
-  const int nlines_total = DIR == 1 ? na : nb;
-  const int npts = DIR == 1 ? nb : na;                    // points per line
-  // scratch for the exact line solve: one row of Thomas factors per line
-  R* cp = reinterpret_cast<R*>(sh + nr * nc);
-  // the 1D stencil tables of this tile and mode (per row ua, da, R, Ca,
-  // omega of the polar line; per column ub, db, Cb, omega of the radial
-  // line), staged in LDS (rounded to R); indexed by the tile-local row
-  // rr = i - r0 and column cc = j - c0.
+  if (EXACT) {
+  } else if (DIR == 1) {
+#pragma unroll 4
+    for (int t = threadIdx.x; t < (fend - fbeg) * nb; t += blockDim.x) {
+      const int i = fbeg + t / nb, j = t % nb;
+      fs[(i - r0) * nc + (j - c0)] = f[(size_t)i * nb + j];
+    }
+  } else {
+    const int w = fend - fbeg;
+#pragma unroll 4
+    for (int t = threadIdx.x; t < na * w; t += blockDim.x) {
+      const int i = t / w, j = fbeg + t % w;
+      fs[(i - r0) * nc + (j - c0)] = f[(size_t)i * nb + j];
+    }
+  }
+  // scratch for the exact line solve (one row of Thomas factors per line),
+  // then the 1D tables per tile row rr = i - r0 (ua, da, R, Ca, omega of the
+  // polar line) and per tile column cc = j - c0 (ub, db, Cb, omega of the
+  // radial line)
+  R* cp = reinterpret_cast<R*>(EXACT ? fs : fs + nr * nc);
   R* t0 = cp + scratch_words;
   R *t1 = t0 + nr, *t2 = t1 + nr, *t3 = t2 + nr, *t4 = t3 + nr;
   R *c1 = t4 + nr, *c2 = c1 + nc, *c3 = c2 + nc, *c4 = c3 + nc;
-  if (stage) {
-    for (int rr = threadIdx.x; rr < nr; rr += blockDim.x) {
-      const int i = r0 + rr;
-      const bool in = i >= 0 && i < na;
-      t0[rr] = in ? (R)L.ua[i] : (R)0;
-      t1[rr] = in ? (R)L.da[i] : (R)0;
-      t2[rr] = in ? (R)L.Rr[i] : (R)0;
-      t3[rr] = in ? (R)L.Ca[(size_t)m * na + i] : (R)1;
-      t4[rr] = in ? (R)L.wb[(size_t)m * na + i] : (R)0;
-    }
-    for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
-      const int j = c0 + cc;
-      const bool in = j >= 0 && j < nb;
-      c1[cc] = in ? (R)L.ub[j] : (R)0;
-      c2[cc] = in ? (R)L.db[j] : (R)0;
-      c3[cc] = in ? (R)L.Cb[(size_t)m * nb + j] : (R)0;
-      c4[cc] = in ? (R)L.wr[(size_t)m * nb + j] : (R)0;
-    }
+  for (int rr = threadIdx.x; rr < nr; rr += blockDim.x) {
+    const int i = r0 + rr;
+    const bool in = i >= 0 && i < na;
+    t0[rr] = in ? (R)gbl(L.ua)[i] : (R)0;
+    t1[rr] = in ? (R)gbl(L.da)[i] : (R)0;
+    t2[rr] = in ? (R)gbl(L.Rr)[i] : (R)0;
+    t3[rr] = in ? (R)gbl(L.Ca)[(size_t)m * na + i] : (R)1;
+    t4[rr] = in ? (R)gbl(L.wb)[(size_t)m * na + i] : (R)0;
+  }
+  for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
+    const int j = c0 + cc;
+    const bool in = j >= 0 && j < nb;
+    c1[cc] = in ? (R)gbl(L.ub)[j] : (R)0;
+    c2[cc] = in ? (R)gbl(L.db)[j] : (R)0;
+    c3[cc] = in ? (R)gbl(L.Cb)[(size_t)m * nb + j] : (R)0;
+    c4[cc] = in ? (R)gbl(L.wr)[(size_t)m * nb + j] : (R)0;
   }
   __syncthreads();
-  // table access: staged copy or the FP64 tables in place (rows and
-  // columns outside the plane are never read)
-  auto tU = [&](int rr) { return stage ? t0[rr] : (R)L.ua[r0 + rr]; };
-  auto tD = [&](int rr) { return stage ? t1[rr] : (R)L.da[r0 + rr]; };
-  auto tR = [&](int rr) { return stage ? t2[rr] : (R)L.Rr[r0 + rr]; };
-  auto tC = [&](int rr) { return stage ? t3[rr] : (R)L.Ca[(size_t)m * na + r0 + rr]; };
-  auto tW = [&](int rr) { return stage ? t4[rr] : (R)L.wb[(size_t)m * na + r0 + rr]; };
-  auto cU = [&](int cc) { return stage ? c1[cc] : (R)L.ub[c0 + cc]; };
-  auto cD = [&](int cc) { return stage ? c2[cc] : (R)L.db[c0 + cc]; };
-  auto cC = [&](int cc) { return stage ? c3[cc] : (R)L.Cb[(size_t)m * nb + c0 + cc]; };
-  auto cW = [&](int cc) { return stage ? c4[cc] : (R)L.wr[(size_t)m * nb + c0 + cc]; };
+  const LineView<R> view{sh, nc, -r0, -c0, fs, nc, -r0, -c0, t0, t1, t2, t3, t4, -r0, c1, c2, c3, c4, -c0};
   for (int lc = 0; lc < 2; ++lc) {
-    // colour lc: first colour includes the inner halo lines
-    int a = lc == 0 ? lbeg - 1 : lbeg;
-    int b = lc == 0 ? lend + 1 : lend;  // exclusive
-    a = max(a, 0);
-    b = min(b, nlines_total);
+    // colour lc: the first colour includes the inner halo lines
+    int a = lc == 0 ? fbeg : lbeg;
+    const int b = lc == 0 ? fend : lend;  // exclusive
     if ((a & 1) != lc) ++a;
-    const int nl = a < b ? (b - a + 1) / 2 : 0;  // lines a, a+2, ... < b
-    if (EXACT) {
-      // Thomas algorithm along each line of the colour; the couplings to the
-      // neighbouring lines (the other colour) are fixed right-hand-side terms.
-      for (int t = threadIdx.x; t < nl; t += blockDim.x) {
-        const int line = a + 2 * t;
-        R* cpl = cp + t * npts;
-        V prev = mkv<R>(0, 0);
-        R cprev = 0;
-        for (int k = 0; k < npts; ++k) {
-          const int i = DIR == 1 ? line : k;
-          const int j = DIR == 1 ? k : line;
-          const int rr = i - r0, cc = j - c0;
-          const R Rr = tR(rr);
-          const R c = tC(rr) + Rr * cC(cc);
-          R lo, up, w1, w2;
-          V o1, o2;
-          if (DIR == 1) {  // line along j; fixed neighbours i+1, i-1
-            lo = Rr * cD(cc); up = Rr * cU(cc);
-            o1 = sh[(rr + 1) * nc + cc]; o2 = sh[(rr - 1) * nc + cc];
-            w1 = tU(rr); w2 = tD(rr);
-          } else {         // line along i; fixed neighbours j+1, j-1
-            lo = tD(rr); up = tU(rr);
-            o1 = sh[rr * nc + cc + 1]; o2 = sh[rr * nc + cc - 1];
-            w1 = Rr * cU(cc); w2 = Rr * cD(cc);
-          }
-          const V fv = f[(size_t)i * nb + j];
-          const R rx = fv.x - (w1 * o1.x + w2 * o2.x);
-          const R ry = fv.y - (w1 * o1.y + w2 * o2.y);
-          const R den = c - lo * cprev;
-          cprev = up / den;
-          cpl[k] = cprev;
-          prev = mkv<R>((rx - lo * prev.x) / den, (ry - lo * prev.y) / den);
-          sh[rr * nc + cc] = prev;
-        }
-        for (int k = npts - 2; k >= 0; --k) {
-          const int i = DIR == 1 ? line : k;
-          const int j = DIR == 1 ? k : line;
-          const int rr = i - r0, cc = j - c0;
-          const V nx = DIR == 1 ? sh[rr * nc + cc + 1] : sh[(rr + 1) * nc + cc];
-          const V d = sh[rr * nc + cc];
-          sh[rr * nc + cc] = mkv<R>(d.x - cpl[k] * nx.x, d.y - cpl[k] * nx.y);
-        }
-      }
+    if (!EXACT) {
+      relax_colour<DIR, PMAX, R>(view, a, b, npts, n_sor);
       __syncthreads();
       continue;
     }
-    for (int it = 0; it < n_sor; ++it) {
-      for (int pc = 0; pc < 2; ++pc) {
-        const int np = (npts - pc + 1) / 2;  // points pc, pc+2, ... < npts
-        const int total = nl * np;
-        for (int t = threadIdx.x; t < total; t += blockDim.x) {
-          int line, pt;
-          if (DIR == 1) {
-            line = a + 2 * (t / np);
-            pt = pc + 2 * (t % np);
-          } else {
-            pt = pc + 2 * (t / nl);
-            line = a + 2 * (t % nl);
-          }
-          const int i = DIR == 1 ? line : pt;
-          const int j = DIR == 1 ? pt : line;
-          const int rr = i - r0, cc = j - c0;
-          V* me = &sh[rr * nc + cc];
-          const V un = sh[(rr + 1) * nc + cc];
-          const V us = sh[(rr - 1) * nc + cc];
-          const V ue = sh[rr * nc + cc + 1];
-          const V uw = sh[rr * nc + cc - 1];
-          const R Rr = tR(rr);
-          const R c = tC(rr) + Rr * cC(cc);
-          const R w = DIR == 1 ? tW(rr) : cW(cc);
-          const R ua = tU(rr), da = tD(rr), ub = Rr * cU(cc), db = Rr * cD(cc);
-          const V fv = f[(size_t)i * nb + j];
-          const R sx = ua * un.x + da * us.x + ub * ue.x + db * uw.x;
-          const R sy = ua * un.y + da * us.y + ub * ue.y + db * uw.y;
-          const V old = *me;
-          const R tx = (fv.x - sx) / c, ty = (fv.y - sy) / c;
-          *me = mkv<R>(old.x + w * (tx - old.x), old.y + w * (ty - old.y));
+    // Thomas algorithm along each line of the colour; the couplings to the
+    // neighbouring lines (the other colour) are fixed right-hand-side terms.
+    const int nl = a < b ? (b - a + 1) / 2 : 0;  // lines a, a+2, ... < b
+    for (int t = threadIdx.x; t < nl; t += blockDim.x) {
+      const int line = a + 2 * t;
+      R* cpl = cp + t * npts;
+      V prev = mkv<R>(0, 0);
+      R cprev = 0;
+      for (int k = 0; k < npts; ++k) {
+        const int i = DIR == 1 ? line : k;
+        const int j = DIR == 1 ? k : line;
+        const int rr = i - r0, cc = j - c0;
+        const R Rr = t2[rr];
+        const R c = t3[rr] + Rr * c3[cc];
+        R lo, up, w1, w2;
+        V o1, o2;
+        if (DIR == 1) {  // line along j; fixed neighbours i+1, i-1
+          lo = Rr * c2[cc]; up = Rr * c1[cc];
+          o1 = sh[(rr + 1) * nc + cc]; o2 = sh[(rr - 1) * nc + cc];
+          w1 = t0[rr]; w2 = t1[rr];
+        } else {         // line along i; fixed neighbours j+1, j-1
+          lo = t1[rr]; up = t0[rr];
+          o1 = sh[rr * nc + cc + 1]; o2 = sh[rr * nc + cc - 1];
+          w1 = Rr * c1[cc]; w2 = Rr * c2[cc];
         }
-        __syncthreads();
+        const V fv = f[(size_t)i * nb + j];
+        const R rx = fv.x - (w1 * o1.x + w2 * o2.x);
+        const R ry = fv.y - (w1 * o1.y + w2 * o2.y);
+        const R den = c - lo * cprev;
+        cprev = up / den;
+        cpl[k] = cprev;
+        prev = mkv<R>((rx - lo * prev.x) / den, (ry - lo * prev.y) / den);
+        sh[rr * nc + cc] = prev;
+      }
+      for (int k = npts - 2; k >= 0; --k) {
+        const int i = DIR == 1 ? line : k;
+        const int j = DIR == 1 ? k : line;
+        const int rr = i - r0, cc = j - c0;
+        const V nx = DIR == 1 ? sh[rr * nc + cc + 1] : sh[(rr + 1) * nc + cc];
+        const V d = sh[rr * nc + cc];
+        sh[rr * nc + cc] = mkv<R>(d.x - cpl[k] * nx.x, d.y - cpl[k] * nx.y);
       }
     }
+    __syncthreads();
   }
   // write back the owned lines
   if (DIR == 1) {
@@ -281,18 +268,18 @@ __global__ void __launch_bounds__(kThreads) k_restrict(const LvJob* __restrict__
   const size_t offc = (size_t)slot * C.na * C.nb;
   const V* U = static_cast<const V*>(J.u) + off;
   const V* F = static_cast<const V*>(J.f) + off;
-  V* FC = static_cast<V*>(J.fc) + offc;
-  V* UC = static_cast<V*>(J.uc) + offc;
+  const auto FC = gbl(static_cast<V*>(J.fc) + offc);
+  const auto UC = gbl(static_cast<V*>(J.uc) + offc);
   const int cells = C.na * C.nb;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += gridDim.x * blockDim.x) {
     const int I = t / C.nb, Jc = t - I * C.nb;
     V acc = mkv<R>(0, 0);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      const R wa = (R)L.rwa[2 * I + a];
+      const R wa = (R)gbl(L.rwa)[2 * I + a];
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const R w = wa * (R)L.rwb[2 * Jc + b];
+        const R w = wa * (R)gbl(L.rwb)[2 * Jc + b];
         const V r = resid_at<R>(L, m, U, F, 2 * I + a, 2 * Jc + b);
         acc = axpy<R>(w, r, acc);
       }
@@ -308,19 +295,19 @@ __global__ void __launch_bounds__(kThreads) k_prolong(const LvJob* __restrict__ 
   SMG_ENTRY(jobs, bt);
   if (!J.active) return;
   const LevelDev L = J.L, C = J.C;
-  V* U = static_cast<V*>(J.u) + (size_t)slot * L.na * L.nb;
-  const V* uc = static_cast<const V*>(J.uc) + (size_t)slot * C.na * C.nb;
+  const auto U = gbl(static_cast<V*>(J.u) + (size_t)slot * L.na * L.nb);
+  const auto uc = gbl(static_cast<const V*>(J.uc) + (size_t)slot * C.na * C.nb);
   const int par = m & 1;
   const int cells = L.na * L.nb;
-  const int* pbi0 = L.pb_i0 + par * L.nb;
-  const int* pbi1 = L.pb_i1 + par * L.nb;
-  const double* pbw0 = L.pb_w0 + par * L.nb;
-  const double* pbw1 = L.pb_w1 + par * L.nb;
+  const auto pbi0 = gbl(L.pb_i0 + par * L.nb);
+  const auto pbi1 = gbl(L.pb_i1 + par * L.nb);
+  const auto pbw0 = gbl(L.pb_w0 + par * L.nb);
+  const auto pbw1 = gbl(L.pb_w1 + par * L.nb);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += gridDim.x * blockDim.x) {
     const int i = t / L.nb, j = t - i * L.nb;
-    const int a0 = L.pa_i0[i], a1 = L.pa_i1[i];
+    const int a0 = gbl(L.pa_i0)[i], a1 = gbl(L.pa_i1)[i];
     const int b0 = pbi0[j], b1 = pbi1[j];
-    const R wa0 = (R)L.pa_w0[i], wa1 = (R)L.pa_w1[i];
+    const R wa0 = (R)gbl(L.pa_w0)[i], wa1 = (R)gbl(L.pa_w1)[i];
     const R wb0 = (R)pbw0[j], wb1 = (R)pbw1[j];
     V ev = mkv<R>(0, 0);
     ev = axpy<R>(wa0 * wb0, uc[(size_t)a0 * C.nb + b0], ev);
@@ -344,18 +331,18 @@ __global__ void __launch_bounds__(kThreads) k_norm_partial(const NormJob* __rest
   const size_t off = (size_t)slot * L.na * L.nb;
   const double2* U = J.u + off;
   const double2* F = J.f + off;
-  float2* R32 = J.r32 ? J.r32 + off : nullptr;
-  float2* E32 = J.e32 ? J.e32 + off : nullptr;
+  const auto R32 = gbl(J.r32 ? J.r32 + off : nullptr);
+  const auto E32 = gbl(J.e32 ? J.e32 + off : nullptr);
   const int cells = L.na * L.nb;
   double acc = 0.0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += gridDim.x * blockDim.x) {
     const int i = t / L.nb, j = t - i * L.nb;
-    const double2 r = use_u ? resid_at<double>(L, m, U, F, i, j) : F[t];
+    const double2 r = use_u ? resid_at<double>(L, m, U, F, i, j) : (double2)gbl(F)[t];
     if (R32) {
       R32[t] = make_float2((float)r.x, (float)r.y);
       E32[t] = make_float2(0.f, 0.f);
     }
-    acc += (r.x * r.x + r.y * r.y) * (L.va[i] * L.vb[j]);
+    acc += (r.x * r.x + r.y * r.y) * (gbl(L.va)[i] * gbl(L.vb)[j]);
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -372,8 +359,8 @@ __global__ void __launch_bounds__(kThreads) k_accumulate(const NormJob* __restri
   SMG_ENTRY(jobs, bt);
   const int cells = J.L.na * J.L.nb;
   const size_t off = (size_t)slot * cells;
-  double2* U = J.u + off;
-  const float2* E = J.e32 + off;
+  const auto U = gbl(J.u + off);
+  const auto E = gbl(J.e32 + off);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += gridDim.x * blockDim.x) {
     const float2 ev = E[t];
     const double2 v = U[t];
@@ -395,40 +382,48 @@ int grid_for(int cells) {
   return g < 1 ? 1 : (g > 1024 ? 1024 : g);
 }
 
-constexpr size_t kSmoothLds = 60 * 1024;     // preferred per-block LDS
-constexpr size_t kSmoothLdsMax = 64 * 1024;  // hard limit of a launch
+constexpr size_t kSmoothLds = 60 * 1024;  // preferred per-block LDS
 
 }  // namespace
 
 namespace smgk {
 
+size_t lds_limit() {
+  static size_t cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 64 * 1024;
+  if (!cached[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v < 64 * 1024)
+      v = 64 * 1024;
+    cached[dev] = (size_t)v;
+  }
+  return cached[dev];
+}
+
 // Lines per tile so that a launch over `planes` planes has about
-// target_blocks blocks, within the LDS budget; tables are staged in LDS when
-// they fit.
+// target_blocks blocks, within the LDS budget.
 bool smooth_shape(const LevelDev& L, int dir, bool exact, bool fp32, int target_blocks, int planes, SmoothShape* out) {
-  const size_t vb = fp32 ? sizeof(float2) : sizeof(double2), rb = fp32 ? sizeof(float) : sizeof(double);
   const int npts = dir == 0 ? L.na : L.nb;    // points per line
   const int nlines = dir == 0 ? L.nb : L.na;  // lines in the plane
-  auto bytes = [&](int t, bool stage) {
-    const size_t nr = dir == 0 ? (size_t)L.na + 2 : (size_t)t + 4;
-    const size_t nc = dir == 0 ? (size_t)t + 4 : (size_t)L.nb + 2;
-    const size_t scratch = exact ? (size_t)(t / 2 + 2) * npts : 0;
-    return vb * nr * nc + rb * (scratch + (stage ? 5 * nr + 4 * nc : 0));
+  if (npts > kRelaxMaxPoints) return false;
+  auto bytes = [&](int t) {
+    const int scratch = exact ? (t / 2 + 2) * npts : 0;
+    return fp32 ? smooth_lds_bytes<float>(dir, L.na, L.nb, t, exact, scratch)
+                : smooth_lds_bytes<double>(dir, L.na, L.nb, t, exact, scratch);
   };
   if (planes < 1) planes = 1;
   const int want = (target_blocks + planes - 1) / planes;  // tiles per plane
   int tile = (nlines + want - 1) / want;
   if (tile < 2) tile = 2;
   if (tile > nlines) tile = nlines;
-  while (tile > 2 && bytes(tile, true) > kSmoothLds) --tile;
+  while (tile > 2 && bytes(tile) > kSmoothLds) --tile;
   if (tile > 2 && (tile & 1)) --tile;
-  const bool stage = bytes(tile, true) <= kSmoothLds;
   out->tile = tile;
   out->ntile = (nlines + tile - 1) / tile;
-  out->stage = stage ? 1 : 0;
   out->scratch = exact ? (tile / 2 + 2) * npts : 0;
-  out->lds = bytes(tile, stage);
-  return out->lds <= kSmoothLdsMax;
+  out->lds = bytes(tile);
+  return out->lds <= lds_limit();
 }
 
 template <typename R>
@@ -439,24 +434,30 @@ static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, 
   for (int q = 0; q < n_prob; ++q) {
     if (!hj[q].active) continue;
     const LevelDev& L = hj[q].L;
-    const size_t vb = sizeof(typename Vec<R>::T), rb = sizeof(R);
-    const int t = hj[q].tile[dir], npts = dir == 0 ? L.na : L.nb;
-    const size_t nr = dir == 0 ? (size_t)L.na + 2 : (size_t)t + 4;
-    const size_t nc = dir == 0 ? (size_t)t + 4 : (size_t)L.nb + 2;
-    size_t bytes = vb * nr * nc + rb * ((size_t)hj[q].scratch[dir] + (hj[q].stage[dir] ? 5 * nr + 4 * nc : 0));
-    (void)npts;
-    if (bytes > lds) lds = bytes;
+    if ((dir == 0 ? L.na : L.nb) > kRelaxMaxPoints) return hipErrorInvalidConfiguration;
+    lds = std::max(lds, smooth_lds_bytes<R>(dir, L.na, L.nb, hj[q].tile[dir], exact, hj[q].scratch[dir]));
     if (hj[q].ntile[dir] > gx) gx = hj[q].ntile[dir];
   }
   if (gx == 0 || b.cap == 0) return hipSuccess;
-  if (lds > kSmoothLdsMax) return hipErrorInvalidConfiguration;
+  if (lds > lds_limit()) return hipErrorInvalidConfiguration;
   const dim3 grid(gx, b.cap);
-  if (dir == 0) {
-    if (exact) hipLaunchKernelGGL((k_smooth<0, true, R>), grid, dim3(kThreads), lds, st, jobs, b, n_sor);
-    else hipLaunchKernelGGL((k_smooth<0, false, R>), grid, dim3(kThreads), lds, st, jobs, b, n_sor);
+  int pmax = 2;  // points per lane the longest relaxed line needs
+  for (int q = 0; q < n_prob; ++q)
+    if (hj[q].active) pmax = std::max(pmax, relax_points_per_lane(dir == 0 ? hj[q].L.na : hj[q].L.nb));
+  auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, st, jobs, b, n_sor); };
+  if (exact) {
+    if (dir == 0) go(k_smooth<0, true, 2, R>);
+    else go(k_smooth<1, true, 2, R>);
+  } else if (dir == 0) {
+    if (pmax <= 2) go(k_smooth<0, false, 2, R>);
+    else if (pmax <= 4) go(k_smooth<0, false, 4, R>);
+    else if (pmax <= 8) go(k_smooth<0, false, 8, R>);
+    else go(k_smooth<0, false, 16, R>);
   } else {
-    if (exact) hipLaunchKernelGGL((k_smooth<1, true, R>), grid, dim3(kThreads), lds, st, jobs, b, n_sor);
-    else hipLaunchKernelGGL((k_smooth<1, false, R>), grid, dim3(kThreads), lds, st, jobs, b, n_sor);
+    if (pmax <= 2) go(k_smooth<1, false, 2, R>);
+    else if (pmax <= 4) go(k_smooth<1, false, 4, R>);
+    else if (pmax <= 8) go(k_smooth<1, false, 8, R>);
+    else go(k_smooth<1, false, 16, R>);
   }
   return hipGetLastError();
 }

@@ -9,12 +9,13 @@
 // is always solved in FP64 (the mixed form keeps the coarsest solve in FP64).
 #include <algorithm>
 
+#include "relax_dev.h"
 #include "smg_internal.h"
 #include "vec.h"
 
 namespace {
 
-constexpr int kThreads = 512;  // most threads of a fused-cycle block
+constexpr int kAliasCells = 4;  // coarse cells per thread of the aliased restriction
 
 struct Red {
   double* buf;
@@ -47,123 +48,35 @@ __device__ __forceinline__ Tab<R> stage_tab(const LevelDev& L, int m, R* buf) {
   const int na = L.na, nb = L.nb;
   R* t = buf;
   for (int i = threadIdx.x; i < na; i += blockDim.x) {
-    t[i] = (R)L.ua[i];
-    t[na + i] = (R)L.da[i];
-    t[2 * na + i] = (R)L.Rr[i];
-    t[3 * na + i] = (R)L.Ca[(size_t)m * na + i];
-    t[4 * na + i] = (R)L.wb[(size_t)m * na + i];
+    t[i] = (R)gbl(L.ua)[i];
+    t[na + i] = (R)gbl(L.da)[i];
+    t[2 * na + i] = (R)gbl(L.Rr)[i];
+    t[3 * na + i] = (R)gbl(L.Ca)[(size_t)m * na + i];
+    t[4 * na + i] = (R)gbl(L.wb)[(size_t)m * na + i];
   }
   R* c = buf + 5 * na;
   for (int j = threadIdx.x; j < nb; j += blockDim.x) {
-    c[j] = (R)L.ub[j];
-    c[nb + j] = (R)L.db[j];
-    c[2 * nb + j] = (R)L.Cb[(size_t)m * nb + j];
-    c[3 * nb + j] = (R)L.wr[(size_t)m * nb + j];
+    c[j] = (R)gbl(L.ub)[j];
+    c[nb + j] = (R)gbl(L.db)[j];
+    c[2 * nb + j] = (R)gbl(L.Cb)[(size_t)m * nb + j];
+    c[3 * nb + j] = (R)gbl(L.wr)[(size_t)m * nb + j];
   }
   return tab_at<R>(buf, na, nb);
 }
 
-// Ordering of LDS accesses between the even-odd passes of one line: every
-// line is relaxed by a single wave, whose LDS operations complete in issue
-// order, so only the compiler must keep the passes apart.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // One zebra phase in direction DIR (0: radial lines, fixed j, points along
 // i; 1: polar lines, fixed i, points along j): the lines of colour 0, then
-// those of colour 1, each line relaxed by n_sor even-odd SOR passes.  A
-// wave takes G lines at a time (lane -> line g, point index k of the
-// current parity), keeps the stencil coefficients of its two cells (one per
-// parity) in registers, and needs no block barrier between the passes of a
-// line; one barrier separates the colours.
+// those of colour 1, each line relaxed by n_sor even-odd SOR passes in
+// registers; one barrier separates the colours.
 // u: padded (na+2) x (nb+2) plane, f: na x nb.
-template <int DIR, typename R>
+template <int DIR, int PMAX, typename R>
 __device__ __forceinline__ void sor_phase(const LevelDev& L, const Tab<R>& T, typename Vec<R>::T* u, const typename Vec<R>::T* f,
                           int n_sor) {
-  using V = typename Vec<R>::T;
-  const int na = L.na, nb = L.nb, nc = nb + 2;
-  const int npts = DIR == 0 ? na : nb;
-  const int nlines = DIR == 0 ? nb : na;
-  const int half = (npts + 1) / 2;                 // points of parity 0
-  const int G = half >= 64 ? 1 : 64 / half;        // lines per wave step
-  const int cpl = (half + 63) / 64;                // cells per lane and parity
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-  const int g = G > 1 ? lane / half : 0, k0 = G > 1 ? lane - g * half : lane;
+  const int na = L.na, nb = L.nb;
+  const LineView<R> v{u, nb + 2, 1, 1, f, nb, 0, 0, T.ua, T.da, T.Rr, T.Ca, T.wb, 0, T.ub, T.db, T.Cb, T.wr, 0};
+  const int npts = DIR == 0 ? na : nb, nlines = DIR == 0 ? nb : na;
   for (int lc = 0; lc < 2; ++lc) {
-    const int nlc = (nlines - lc + 1) / 2;          // lines of this colour
-    for (int base = wave * G; base < nlc; base += nwave * G) {
-      const int li = base + g;                     // this lane's line (colour index)
-      const bool lane_ok = (G == 1 || g < G) && li < nlc;
-      const int line = lc + 2 * li;
-      if (cpl > 1) {
-        // lines longer than 128 points: each pass sweeps the lane's cells of
-        // that parity, coefficients read as needed
-        for (int it = 0; it < n_sor; ++it) {
-          for (int pc = 0; pc < 2; ++pc) {
-            for (int c = 0; c < cpl && lane_ok; ++c) {
-              const int pt = pc + 2 * (k0 + 64 * c);
-              if (pt >= npts) break;
-              const int i = DIR == 1 ? line : pt, j = DIR == 1 ? pt : line;
-              const int qq = (i + 1) * nc + (j + 1);
-              const R Rr = T.Rr[i];
-              const R cv = T.Ca[i] + Rr * T.Cb[j];
-              const R wv = DIR == 1 ? T.wb[i] : T.wr[j];
-              const R ua = T.ua[i], da = T.da[i], ub = Rr * T.ub[j], db = Rr * T.db[j];
-              const V un = u[qq + nc], us = u[qq - nc], ue = u[qq + 1], uw = u[qq - 1];
-              const V fq = f[i * nb + j];
-              const R sx = ua * un.x + da * us.x + ub * ue.x + db * uw.x;
-              const R sy = ua * un.y + da * us.y + ub * ue.y + db * uw.y;
-              const V old = u[qq];
-              const R tx = (fq.x - sx) / cv, ty = (fq.y - sy) / cv;
-              u[qq] = mkv<R>(old.x + wv * (tx - old.x), old.y + wv * (ty - old.y));
-            }
-            wave_sync();
-          }
-        }
-        continue;
-      }
-      {
-        const int k = k0;
-        // the lane's cell of each parity and its coefficients
-        int q[2];
-        R cc[2], w[2], a1[2], a2[2], b1[2], b2[2];
-        V fv[2];
-        bool ok[2];
-        for (int pc = 0; pc < 2; ++pc) {
-          const int pt = pc + 2 * k;
-          ok[pc] = lane_ok && pt < npts;
-          const int i = DIR == 1 ? line : pt, j = DIR == 1 ? pt : line;
-          q[pc] = (i + 1) * nc + (j + 1);
-          if (ok[pc]) {
-            const R Rr = T.Rr[i];
-            cc[pc] = T.Ca[i] + Rr * T.Cb[j];
-            w[pc] = DIR == 1 ? T.wb[i] : T.wr[j];
-            a1[pc] = T.ua[i];
-            a2[pc] = T.da[i];
-            b1[pc] = Rr * T.ub[j];
-            b2[pc] = Rr * T.db[j];
-            fv[pc] = f[i * nb + j];
-          }
-        }
-        for (int it = 0; it < n_sor; ++it) {
-          for (int pc = 0; pc < 2; ++pc) {
-            if (ok[pc]) {
-              const int qq = q[pc];
-              const V un = u[qq + nc], us = u[qq - nc], ue = u[qq + 1], uw = u[qq - 1];
-              const R sx = a1[pc] * un.x + a2[pc] * us.x + b1[pc] * ue.x + b2[pc] * uw.x;
-              const R sy = a1[pc] * un.y + a2[pc] * us.y + b1[pc] * ue.y + b2[pc] * uw.y;
-              const V old = u[qq];
-              const R tx = (fv[pc].x - sx) / cc[pc], ty = (fv[pc].y - sy) / cc[pc];
-              u[qq] = mkv<R>(old.x + w[pc] * (tx - old.x), old.y + w[pc] * (ty - old.y));
-            }
-            wave_sync();
-          }
-        }
-      }
-    }
+    relax_colour<DIR, PMAX, R>(v, lc, nlines, npts, n_sor);
     __syncthreads();
   }
 }
@@ -215,15 +128,15 @@ __device__ __forceinline__ void exact_phase(const LevelDev& L, const Tab<R>& T, 
   }
 }
 
-template <typename R>
+template <int PMAX, typename R>
 __device__ __forceinline__ void smooth_step(const LevelDev& L, const Tab<R>& T, typename Vec<R>::T* u, const typename Vec<R>::T* f,
                             int n_sor, bool exact, R* cp) {
   if (exact) {
     exact_phase<0, R>(L, T, u, f, cp);
     exact_phase<1, R>(L, T, u, f, cp);
   } else {
-    sor_phase<0, R>(L, T, u, f, n_sor);
-    sor_phase<1, R>(L, T, u, f, n_sor);
+    sor_phase<0, PMAX, R>(L, T, u, f, n_sor);
+    sor_phase<1, PMAX, R>(L, T, u, f, n_sor);
   }
 }
 
@@ -241,12 +154,66 @@ __device__ __forceinline__ typename Vec<R>::T resid_lds(const LevelDev& L, const
                 fv.y - (c * uc.y + a1 * un.y + a2 * us.y + b1 * ue.y + b2 * uw.y));
 }
 
+// Byte offsets of the fused cycle's LDS arrays: o[l] u of level l and
+// o[K + l] its f (l < cl, K = kMaxLdsLevels), o[2K + l] the tables of level
+// l (l <= cl), o[3K] the coarsest u (its f follows), o[3K + 1] the
+// exact-line scratch, o[3K + 2] the total.  Plain layout: [coarsest u, f]
+// [levels 0..cl-1: u, f] [scratch] [tables].  Aliased layout: [level 0 u]
+// [region A] [scratch] [tables], where region A holds level 0's f while
+// level 0 is smoothed and [coarsest u, f] [levels 1..cl-1: u, f] between
+// the restriction from level 0 and the prolongation to it.
+constexpr int kLayoutSlots = 3 * kMaxLdsLevels + 3;
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict__ jobs, BatchRef bt, int nu_pre,
+__host__ __device__ inline void lds_layout(const LdsLevels& LL, int* o) {
+  using V = typename Vec<R>::T;
+  constexpr int K = kMaxLdsLevels;
+  const int cl = LL.n - 1;
+  auto al = [](int x) { return (x + 15) & ~15; };
+  auto ub = [&](int l) { return (int)sizeof(V) * (LL.L[l].na + 2) * (LL.L[l].nb + 2); };
+  auto fb = [&](int l) { return (int)sizeof(V) * LL.L[l].na * LL.L[l].nb; };
+  const int cb = (int)sizeof(double2) * ((LL.L[cl].na + 2) * (LL.L[cl].nb + 2) + LL.L[cl].na * LL.L[cl].nb);
+  int q = 0;
+  if (LL.alias && cl > 0) {
+    o[0] = 0;
+    const int a = al(ub(0));
+    o[K] = a;
+    int c = a;
+    o[3 * K] = c;
+    c = al(c + cb);
+    for (int l = 1; l < cl; ++l) {
+      o[l] = c;
+      c = al(c + ub(l));
+      o[K + l] = c;
+      c = al(c + fb(l));
+    }
+    q = al(a + fb(0)) > c ? al(a + fb(0)) : c;
+  } else {
+    o[3 * K] = 0;
+    q = al(cb);
+    for (int l = 0; l < cl; ++l) {
+      o[l] = q;
+      q = al(q + ub(l));
+      o[K + l] = q;
+      q = al(q + fb(l));
+    }
+  }
+  o[3 * K + 1] = q;
+  q = al(q + (int)sizeof(R) * LL.scratch);
+  o[2 * K + cl] = q;  // coarsest tables (double)
+  q = al(q + (int)sizeof(double) * (5 * LL.L[cl].na + 4 * LL.L[cl].nb));
+  for (int l = 0; l < cl; ++l) {
+    o[2 * K + l] = q;
+    q = al(q + (int)sizeof(R) * (5 * LL.L[l].na + 4 * LL.L[l].nb));
+  }
+  o[3 * K + 2] = q;
+}
+
+template <int PMAX, int NT, typename R>
+__global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ jobs, BatchRef bt, int nu_pre,
                                                        int nu_post, int n_sor, int exact, double rtol, int max_sweeps) {
   using V = typename Vec<R>::T;
   extern __shared__ char smem[];
-  __shared__ double redbuf[kThreads / 64];
+  __shared__ double redbuf[NT / 64];
   Red red{redbuf};
   const int p = blockIdx.x;
   if (bt.count && p >= *bt.count) return;
@@ -255,43 +222,27 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict
   const LdsLevels& LL = J.LL;
   const int slot = ent_slot(e);
   const int m = J.mode ? J.mode[slot] : slot;
-  const V* __restrict__ Fg = static_cast<const V*>(J.f);
-  V* __restrict__ Ug = static_cast<V*>(J.u);
+  const auto Fg = gbl(static_cast<const V*>(J.f));
+  const auto Ug = gbl(static_cast<V*>(J.u));
   const int load_u = J.load_u;
   const int n = LL.n;
   const int cl = n - 1;  // coarsest level (FP64 storage)
-  // LDS carve-up: [coarsest u, f (double2)] [levels 0..n-2 u, f (V)] [scratch (R)] [tables]
+  const int alias = LL.alias;
   const LevelDev& LC = LL.L[cl];
-  double2* uC = reinterpret_cast<double2*>(smem);
-  double2* fC = uC + (LC.na + 2) * (LC.nb + 2);
   // per-level byte offsets into LDS of u, f and the staged tables (kept in
   // LDS and turned into pointers at each use, so that the pointers stay
   // known as LDS addresses and no per-thread array is indexed dynamically)
-  __shared__ int s_off[3 * kMaxLdsLevels];
-  if (threadIdx.x == 0) {
-    int q = (int)(sizeof(double2) * ((LC.na + 2) * (LC.nb + 2) + LC.na * LC.nb));
-    for (int l = 0; l < cl; ++l) {
-      s_off[l] = q;
-      q += (int)sizeof(V) * (LL.L[l].na + 2) * (LL.L[l].nb + 2);
-      s_off[kMaxLdsLevels + l] = q;
-      q += (int)sizeof(V) * LL.L[l].na * LL.L[l].nb;
-    }
-    q += (int)sizeof(R) * LL.scratch;
-    s_off[2 * kMaxLdsLevels + cl] = q;  // coarsest tables (double)
-    q += (int)sizeof(double) * (5 * LC.na + 4 * LC.nb);
-    for (int l = 0; l < cl; ++l) {
-      s_off[2 * kMaxLdsLevels + l] = q;
-      q += (int)sizeof(R) * (5 * LL.L[l].na + 4 * LL.L[l].nb);
-    }
-  }
+  __shared__ int s_off[kLayoutSlots];
+  if (threadIdx.x == 0) lds_layout<R>(LL, s_off);
   __syncthreads();
+  double2* uC = reinterpret_cast<double2*>(smem + s_off[3 * kMaxLdsLevels]);
+  double2* fC = uC + (LC.na + 2) * (LC.nb + 2);
   auto Ul = [&](int l) { return reinterpret_cast<V*>(smem + s_off[l]); };
   auto Fl = [&](int l) { return reinterpret_cast<V*>(smem + s_off[kMaxLdsLevels + l]); };
   auto Tl = [&](int l) {
     return tab_at<R>(reinterpret_cast<R*>(smem + s_off[2 * kMaxLdsLevels + l]), LL.L[l].na, LL.L[l].nb);
   };
-  R* cp = reinterpret_cast<R*>(smem + (cl > 0 ? s_off[kMaxLdsLevels + cl - 1] + (int)sizeof(V) * LL.L[cl - 1].na * LL.L[cl - 1].nb
-                                               : (int)(sizeof(double2) * ((LC.na + 2) * (LC.nb + 2) + LC.na * LC.nb))));
+  R* cp = reinterpret_cast<R*>(smem + s_off[3 * kMaxLdsLevels + 1]);
   Tab<double> tabC = stage_tab<double>(LC, m, reinterpret_cast<double*>(smem + s_off[2 * kMaxLdsLevels + cl]));
   for (int l = 0; l < cl; ++l) (void)stage_tab<R>(LL.L[l], m, reinterpret_cast<R*>(smem + s_off[2 * kMaxLdsLevels + l]));
   // level 0 of the fused range: load f (and u for a full in-LDS cycle)
@@ -300,12 +251,14 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict
     const int na = L0.na, nb = L0.nb, nc = nb + 2;
     const size_t off = (size_t)slot * na * nb;
     if (n > 1) {
+#pragma unroll 4
       for (int t = threadIdx.x; t < (na + 2) * nc; t += blockDim.x) {
         const int i = t / nc - 1, j = t % nc - 1;
         V v = mkv<R>(0, 0);
         if (load_u && i >= 0 && i < na && j >= 0 && j < nb) v = Ug[off + (size_t)i * nb + j];
         Ul(0)[t] = v;
       }
+#pragma unroll 4
       for (int t = threadIdx.x; t < na * nb; t += blockDim.x) Fl(0)[t] = Fg[off + t];
     } else {
       for (int t = threadIdx.x; t < na * nb; t += blockDim.x) fC[t] = make_double2(Fg[off + t].x, Fg[off + t].y);
@@ -319,24 +272,50 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict
     const Tab<R> T = Tl(l);
     V* ul = Ul(l);
     const V* fl = Fl(l);
-    for (int k = 0; k < nu_pre; ++k) smooth_step<R>(L, T, ul, fl, n_sor, exact, cp);
+    for (int k = 0; k < nu_pre; ++k) smooth_step<PMAX, R>(L, T, ul, fl, n_sor, exact, cp);
     const int ncc = C.nb + 2;
-    for (int t = threadIdx.x; t < (C.na + 2) * ncc; t += blockDim.x) {
-      if (l + 1 == cl) uC[t] = make_double2(0.0, 0.0);
-      else Ul(l + 1)[t] = mkv<R>(0, 0);
-    }
-    for (int t = threadIdx.x; t < C.na * C.nb; t += blockDim.x) {
+    // coarse right-hand side = area-weighted restriction of the residual
+    auto restrict_at = [&](int t) {
       const int I = t / C.nb, J = t - I * C.nb;
       R ax = 0, ay = 0;
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
-          const R w = (R)L.rwa[2 * I + a] * (R)L.rwb[2 * J + b];
+          const R w = (R)gbl(L.rwa)[2 * I + a] * (R)gbl(L.rwb)[2 * J + b];
           const V r = resid_lds<R>(L, T, ul, fl, 2 * I + a, 2 * J + b);
           ax = fma(w, r.x, ax);
           ay = fma(w, r.y, ay);
         }
-      if (l + 1 == cl) fC[t] = make_double2(ax, ay);
-      else Fl(l + 1)[t] = mkv<R>(ax, ay);
+      return mkv<R>(ax, ay);
+    };
+    auto put_f = [&](int t, V v) {
+      if (l + 1 == cl) fC[t] = make_double2(v.x, v.y);
+      else Fl(l + 1)[t] = v;
+    };
+    if (alias && l == 0) {
+      // the coarse arrays overlay this level's f: restrict into registers
+      // (at most kAliasCells per thread), then clear and store
+      V acc[kAliasCells];
+#pragma unroll
+      for (int k = 0; k < kAliasCells; ++k) {
+        const int t = threadIdx.x + k * blockDim.x;
+        acc[k] = t < C.na * C.nb ? restrict_at(t) : mkv<R>(0, 0);
+      }
+      __syncthreads();
+      for (int t = threadIdx.x; t < (C.na + 2) * ncc; t += blockDim.x) {
+        if (l + 1 == cl) uC[t] = make_double2(0.0, 0.0);
+        else Ul(l + 1)[t] = mkv<R>(0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < kAliasCells; ++k) {
+        const int t = threadIdx.x + k * blockDim.x;
+        if (t < C.na * C.nb) put_f(t, acc[k]);
+      }
+    } else {
+      for (int t = threadIdx.x; t < (C.na + 2) * ncc; t += blockDim.x) {
+        if (l + 1 == cl) uC[t] = make_double2(0.0, 0.0);
+        else Ul(l + 1)[t] = mkv<R>(0, 0);
+      }
+      for (int t = threadIdx.x; t < C.na * C.nb; t += blockDim.x) put_f(t, restrict_at(t));
     }
     __syncthreads();
   }
@@ -350,23 +329,37 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict
     for (int t = threadIdx.x; t < (na + 2) * nc; t += blockDim.x) uC[t] = make_double2(0.0, 0.0);
     __syncthreads();
     if (L.cinv) {
+      // u = A^-1 f with the inverse stored transposed ([l][k], k fastest):
+      // a wave takes 16 rows k at a time, lane (kk, l4) sums the columns
+      // l = l4 (mod 4) of row kb + kk, so each load instruction reads four
+      // runs of 16 consecutive doubles; two shuffles add the four parts.
       const int nn = na * nb;
-      const double* A = L.cinv + (size_t)m * nn * nn;
-      for (int k = threadIdx.x; k < nn; k += blockDim.x) {
+      const auto At = gbl(L.cinv + (size_t)m * nn * nn);
+      const int lane = threadIdx.x & 63, kk = lane >> 2, l4 = lane & 3;
+      for (int kb = (threadIdx.x >> 6) * 16; kb < nn; kb += (blockDim.x >> 6) * 16) {
+        const int k = kb + kk;
         double sx = 0.0, sy = 0.0;
-        for (int l = 0; l < nn; ++l) {
-          const double a = A[(size_t)k * nn + l];
-          sx = fma(a, fC[l].x, sx);
-          sy = fma(a, fC[l].y, sy);
+        if (k < nn)
+#pragma unroll 8
+          for (int l = l4; l < nn; l += 4) {
+            const double a = At[(size_t)l * nn + k];
+            sx = fma(a, fC[l].x, sx);
+            sy = fma(a, fC[l].y, sy);
+          }
+        sx += __shfl_xor(sx, 1);
+        sy += __shfl_xor(sy, 1);
+        sx += __shfl_xor(sx, 2);
+        sy += __shfl_xor(sy, 2);
+        if (k < nn && l4 == 0) {
+          const int i = k / nb, j = k - i * nb;
+          uC[(i + 1) * nc + (j + 1)] = make_double2(sx, sy);
         }
-        const int i = k / nb, j = k - i * nb;
-        uC[(i + 1) * nc + (j + 1)] = make_double2(sx, sy);
       }
     } else {
       double f2 = 0.0;
       for (int t = threadIdx.x; t < na * nb; t += blockDim.x) f2 += fC[t].x * fC[t].x + fC[t].y * fC[t].y;
       f2 = red.sum(f2);
-      const double w = L.wc[m];
+      const double w = gbl(L.wc)[m];
       if (f2 > 0.0) {
         for (int sweep = 0; sweep < max_sweeps; ++sweep) {
           for (int colour = 0; colour < 2; ++colour) {
@@ -408,12 +401,13 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict
     const Tab<R> T = Tl(l);
     V* ul = Ul(l);
     const V* fl = Fl(l);
+#pragma unroll 4
     for (int t = threadIdx.x; t < L.na * nb; t += blockDim.x) {
       const int i = t / nb, j = t - i * nb;
-      const int a0 = L.pa_i0[i], a1 = L.pa_i1[i];
-      const int b0 = L.pb_i0[par * nb + j], b1 = L.pb_i1[par * nb + j];
-      const R wa0 = (R)L.pa_w0[i], wa1 = (R)L.pa_w1[i];
-      const R wb0 = (R)L.pb_w0[par * nb + j], wb1 = (R)L.pb_w1[par * nb + j];
+      const int a0 = gbl(L.pa_i0)[i], a1 = gbl(L.pa_i1)[i];
+      const int b0 = gbl(L.pb_i0)[par * nb + j], b1 = gbl(L.pb_i1)[par * nb + j];
+      const R wa0 = (R)gbl(L.pa_w0)[i], wa1 = (R)gbl(L.pa_w1)[i];
+      const R wb0 = (R)gbl(L.pb_w0)[par * nb + j], wb1 = (R)gbl(L.pb_w1)[par * nb + j];
       R e00x, e00y, e01x, e01y, e10x, e10y, e11x, e11y;
       if (l + 1 == cl) {
         const double2 a = uC[(a0 + 1) * ncc + b0 + 1], b = uC[(a0 + 1) * ncc + b1 + 1];
@@ -435,7 +429,14 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict
       ul[qq] = mkv<R>(ul[qq].x + ex, ul[qq].y + ey);
     }
     __syncthreads();
-    for (int k = 0; k < nu_post; ++k) smooth_step<R>(L, T, ul, fl, n_sor, exact, cp);
+    if (alias && l == 0) {
+      // the coarse levels are done with region A: level 0's f again
+      const size_t off = (size_t)slot * L.na * nb;
+#pragma unroll 4
+      for (int t = threadIdx.x; t < L.na * nb; t += blockDim.x) Fl(0)[t] = Fg[off + t];
+      __syncthreads();
+    }
+    for (int k = 0; k < nu_post; ++k) smooth_step<PMAX, R>(L, T, ul, fl, n_sor, exact, cp);
   }
   {
     const LevelDev& L0 = LL.L[0];
@@ -455,23 +456,16 @@ __global__ void __launch_bounds__(kThreads) k_lds_cycle(const LdsJob* __restrict
 
 template <typename R>
 size_t cycle_bytes(const LdsLevels& LL) {
-  using V = typename Vec<R>::T;
-  const int cl = LL.n - 1;
-  size_t b = sizeof(double2) * ((size_t)(LL.L[cl].na + 2) * (LL.L[cl].nb + 2) + (size_t)LL.L[cl].na * LL.L[cl].nb);
-  b += sizeof(double) * (5 * (size_t)LL.L[cl].na + 4 * (size_t)LL.L[cl].nb);
-  for (int l = 0; l < cl; ++l) {
-    b += sizeof(V) * ((size_t)(LL.L[l].na + 2) * (LL.L[l].nb + 2) + (size_t)LL.L[l].na * LL.L[l].nb);
-    b += sizeof(R) * (5 * (size_t)LL.L[l].na + 4 * (size_t)LL.L[l].nb);
-  }
-  b += sizeof(R) * (size_t)LL.scratch;
-  return b;
+  int o[kLayoutSlots];
+  lds_layout<R>(LL, o);
+  return (size_t)o[3 * kMaxLdsLevels + 2];
 }
 
 int cycle_threads(const LdsLevels& LL) {
   // enough waves that each takes about one line group per colour on the
   // first fused level; few threads keep the barriers of small levels cheap
   const int cells = LL.L[0].na * LL.L[0].nb;
-  return cells >= 2048 ? 512 : (cells >= 512 ? 256 : 64);
+  return cells >= 8192 ? 1024 : (cells >= 2048 ? 512 : (cells >= 512 ? 256 : 64));
 }
 
 }  // namespace
@@ -494,6 +488,11 @@ size_t lds_cycle_bytes(const LdsLevels& LL, bool fp32) {
   return fp32 ? cycle_bytes<float>(LL) : cycle_bytes<double>(LL);
 }
 
+bool lds_cycle_alias_ok(const LdsLevels& LL) {
+  // every launch has at least min(cycle_threads, 512) threads
+  return LL.n > 1 && LL.L[1].na * LL.L[1].nb <= kAliasCells * std::min(cycle_threads(LL), 512);
+}
+
 int lds_cycle_threads(const LdsLevels& LL) { return cycle_threads(LL); }
 
 hipError_t mg_lds_cycle(const LdsJob* jobs, const LdsJob* hj, int n_prob, const BatchRef& b, int nu_pre, int nu_post,
@@ -505,13 +504,36 @@ hipError_t mg_lds_cycle(const LdsJob* jobs, const LdsJob* hj, int n_prob, const 
     lds = std::max(lds, lds_cycle_bytes(hj[q].LL, fp32));
     threads = std::max(threads, cycle_threads(hj[q].LL));
   }
-  if (lds > 64 * 1024) return hipErrorInvalidConfiguration;
-  if (fp32)
-    hipLaunchKernelGGL(k_lds_cycle<float>, dim3(b.cap), dim3(threads), lds, st, jobs, b, nu_pre, nu_post, n_sor,
-                       exact ? 1 : 0, rtol, max_sweeps);
-  else
-    hipLaunchKernelGGL(k_lds_cycle<double>, dim3(b.cap), dim3(threads), lds, st, jobs, b, nu_pre, nu_post, n_sor,
-                       exact ? 1 : 0, rtol, max_sweeps);
+  if (lds > lds_limit() - 1024) return hipErrorInvalidConfiguration;
+  int pmax = 2;  // points per lane the longest relaxed line needs
+  for (int q = 0; q < n_prob; ++q) {
+    for (int l = 0; l + 1 < hj[q].LL.n; ++l) {
+      if (hj[q].LL.L[l].na > kRelaxMaxPoints || hj[q].LL.L[l].nb > kRelaxMaxPoints) return hipErrorInvalidConfiguration;
+      pmax = std::max(pmax, relax_points_per_lane(std::max(hj[q].LL.L[l].na, hj[q].LL.L[l].nb)));
+    }
+    if (hj[q].LL.alias && !lds_cycle_alias_ok(hj[q].LL)) return hipErrorInvalidConfiguration;
+  }
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(b.cap), dim3(threads), lds, st, jobs, b, nu_pre, nu_post, n_sor, exact ? 1 : 0, rtol,
+                       max_sweeps);
+  };
+  // 1024-thread blocks exist for the FP32 short-line variant only (the
+  // others would spill at 128 registers per lane)
+  if (!fp32 || pmax > 2) threads = std::min(threads, 512);
+  for (int q = 0; q < n_prob; ++q)
+    if (hj[q].LL.alias && hj[q].LL.L[1].na * hj[q].LL.L[1].nb > kAliasCells * threads) return hipErrorInvalidConfiguration;
+  const bool big = threads > 512;
+  if (fp32) {
+    if (pmax <= 2) big ? go(k_lds_cycle<2, 1024, float>) : go(k_lds_cycle<2, 512, float>);
+    else if (pmax <= 4) go(k_lds_cycle<4, 512, float>);
+    else if (pmax <= 8) go(k_lds_cycle<8, 512, float>);
+    else go(k_lds_cycle<16, 512, float>);
+  } else {
+    if (pmax <= 2) go(k_lds_cycle<2, 512, double>);
+    else if (pmax <= 4) go(k_lds_cycle<4, 512, double>);
+    else if (pmax <= 8) go(k_lds_cycle<8, 512, double>);
+    else go(k_lds_cycle<16, 512, double>);
+  }
   return hipGetLastError();
 }
 

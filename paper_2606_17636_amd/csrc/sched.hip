@@ -4,6 +4,7 @@
 // list of planes that still need cycles, kept on the device so that the
 // host does not have to read norms back between V-cycles.
 #include "smg_internal.h"
+#include "vec.h"
 
 namespace {
 
@@ -32,8 +33,10 @@ __device__ int block_scan(int v, int* wsum, int* total) {
 }
 
 __device__ double sum_partial(const double* partial, int p, int nblk) {
+  const auto pp = gbl(partial + (size_t)p * nblk);
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[(size_t)p * nblk + b];
+#pragma unroll 8
+  for (int b = 0; b < nblk; ++b) s += pp[b];
   return sqrt(s);
 }
 
@@ -65,9 +68,9 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_init(const NormJob* __res
     const int q = ent_prob(e[k]);
     g[k] = jobs[q].base + ent_slot(e[k]);
     d[k] = s_nrm[p];
-    cs.d0[g[k]] = d[k];
-    cs.cur[g[k]] = d[k];
-    cs.cyc[g[k]] = 0;
+    gbl(cs.d0)[g[k]] = d[k];
+    gbl(cs.cur)[g[k]] = d[k];
+    gbl(cs.cyc)[g[k]] = 0;
     // non-negative doubles order like their bit patterns
     atomicMax(&dmax[q], (unsigned long long)__double_as_longlong(d[k]));
   }
@@ -80,7 +83,7 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_init(const NormJob* __res
     if (e[k] < 0) continue;
     const double mx = __longlong_as_double((long long)dmax[ent_prob(e[k])]);
     const double thr = tol * fmax(d[k], floor_factor * mx);
-    cs.thr[g[k]] = thr;
+    gbl(cs.thr)[g[k]] = thr;
     kk[k] = d[k] > thr;
     keep += kk[k] ? 1 : 0;
   }
@@ -113,10 +116,10 @@ __global__ void __launch_bounds__(kConvThreads) k_converge(const NormJob* __rest
     if (p < cap) {
       const int g = jobs[ent_prob(e[k])].base + ent_slot(e[k]);
       const double nrm = s_nrm[p];
-      cs.cur[g] = nrm;
-      const int c = cs.cyc[g] + count_cycle;
-      cs.cyc[g] = c;
-      kk[k] = !(nrm <= cs.thr[g]) && c < max_cycles;
+      gbl(cs.cur)[g] = nrm;
+      const int c = gbl(cs.cyc)[g] + count_cycle;
+      gbl(cs.cyc)[g] = c;
+      kk[k] = !(nrm <= gbl(cs.thr)[g]) && c < max_cycles;
     } else {
       kk[k] = true;  // not cycled this time
     }

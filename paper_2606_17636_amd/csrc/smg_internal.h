@@ -58,7 +58,7 @@ struct LevelTables {
   std::vector<double> Ca, Cb;   // [M][na], [M][nb]; diag c = Ca[i] + Rr[i] * Cb[j]
   std::vector<double> wr, wb;   // [M][nb] radial-line omega, [M][na] polar-line omega
   std::vector<double> wc;       // [M] coarsest red-black omega
-  std::vector<double> cinv;     // [M][n][n] inverse of the coarsest operator (n = na*nb <= kMaxDirect), else empty
+  std::vector<double> cinv;     // [M][n][n] inverse of the coarsest operator, transposed ([l][k]; n = na*nb <= kMaxDirect), else empty
   std::vector<double> va, vb;   // normalised volume weights (sum_ij va_i vb_j = 1)
   // restriction to the next coarser level: [nc][2]
   std::vector<double> rwa, rwb;
@@ -122,7 +122,7 @@ struct LevelDev {
   const double *pa_w0, *pa_w1;
   const int *pb_i0, *pb_i1;  // [2][nb]
   const double *pb_w0, *pb_w1;
-  const double* cinv;        // [M][na*nb][na*nb] coarsest inverse, or nullptr
+  const double* cinv;        // [M][na*nb][na*nb] coarsest inverse, transposed, or nullptr
 };
 
 // The levels that one block per plane processes entirely in LDS (the
@@ -130,8 +130,8 @@ struct LevelDev {
 constexpr int kMaxLdsLevels = 8;
 struct LdsLevels {
   int n;
-  int words;    // double2 words of u (padded) and f storage of all fused levels
-  int scratch;  // doubles of exact-line scratch (0 for the SOR smoother)
+  int alias;    // 1: the coarser levels share LDS with the first level's f (reloaded after them)
+  int scratch;  // words of exact-line scratch (0 for the SOR smoother)
   LevelDev L[kMaxLdsLevels];
 };
 
@@ -164,7 +164,6 @@ struct LvJob {
   int active;        // 0: this problem's V-cycle is fused in LDS from this depth on
   int tile[2];       // lines per block
   int ntile[2];      // blocks per plane
-  int stage[2];      // 1: 1D tables staged in LDS
   int scratch[2];    // exact-line scratch words
 };
 
@@ -207,11 +206,15 @@ hipError_t mg_smooth_dir(const LvJob* jobs, const LvJob* hj, int n_prob, const B
 hipError_t mg_restrict(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, bool fp32, hipStream_t st);
 hipError_t mg_prolong(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, bool fp32, hipStream_t st);
 hipError_t mg_residual(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, double2* r, hipStream_t st);
+// Largest dynamic LDS allocation of one block on the current device.
+size_t lds_limit();
 // Launch shape of the smoother for a level seen by `planes` planes at once.
-struct SmoothShape { int tile, ntile, stage, scratch; size_t lds; };
+struct SmoothShape { int tile, ntile, scratch; size_t lds; };
 bool smooth_shape(const LevelDev& L, int dir, bool exact, bool fp32, int target_blocks, int planes, SmoothShape* out);
 // fused coarse cycle (mg_lds.hip)
 size_t lds_cycle_bytes(const LdsLevels& LL, bool fp32);
+// Largest first-level f the aliased layout can restrict through registers.
+bool lds_cycle_alias_ok(const LdsLevels& LL);
 int lds_cycle_scratch(const LdsLevels& LL, bool exact);
 int lds_cycle_threads(const LdsLevels& LL);
 hipError_t mg_lds_cycle(const LdsJob* jobs, const LdsJob* hj, int n_prob, const BatchRef& b, int nu_pre, int nu_post,

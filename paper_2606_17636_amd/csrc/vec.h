@@ -30,3 +30,21 @@ template <typename R>
 __device__ __forceinline__ typename Vec<R>::T axpy(R a, typename Vec<R>::T x, typename Vec<R>::T y) {
   return mkv<R>(fma(a, x.x, y.x), fma(a, x.y, y.y));
 }
+
+// A device-memory pointer seen as a global-address-space pointer.  Accesses
+// through it compile to global_load/global_store, which the compiler keeps
+// in flight across LDS accesses; accesses through a generic pointer might
+// alias LDS, so each one waits for the LDS traffic before it.
+// (The host pass, which only checks the kernels' source, sees the plain
+// pointer: address spaces are a device-side notion.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gbl(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+#else
+template <typename T>
+__device__ __forceinline__ T* gbl(T* p) {
+  return p;
+}
+#endif
