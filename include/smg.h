@@ -321,6 +321,30 @@ smg_status smg_mg_residual(smg_plan *plan, const double *f_dev, const double *u_
 smg_status smg_james(smg_plan *plan, const double *psi_dev, const double *f_dev, double *sigma_dev,
                      double *theta_dev, double *f2_dev, void *stream);
 
+/* Gravitational acceleration g = -grad Phi on every cell face (Sec. 2.1,
+ * Eq. gradient): the potential difference of the two cells sharing a face
+ * over the distance of their centroids projected on the face normal --
+ * radial faces a_{i+1} - a_i; theta faces r_i (theta_{j+1} - theta_j) or z
+ * faces z_{j+1} - z_j; azimuthal faces r_i sin(theta_j) dphi (spherical) or
+ * R_i dphi (cylindrical).  Boundary faces use the ghost potential -Theta of
+ * the second solve (Sec. 4) transformed back to phi; faces lying on a pole
+ * carry 0.
+ *   phi_dev    [n_r][n_b][n_phi] FP64 potential (as returned by smg_solve)
+ *   theta_dev  complex [n_modes][n_g] screening potential Theta^m (as from
+ *              smg_james), or NULL for the Theta of the plan's most recent
+ *              solve, alone or in a batch (SMG_ESTATE if there is none);
+ *              that Theta is read when the work runs, so enqueue this on the
+ *              solve's stream or after it has finished
+ *   g_a_dev    [n_r + 1][n_b][n_phi] radial faces (index i: face i - 1/2)
+ *   g_b_dev    [n_r][n_b + 1][n_phi] theta / z faces (index j: face j - 1/2)
+ *   g_phi_dev  [n_r][n_b][n_phi] azimuthal faces (index k: face k + 1/2,
+ *              periodic)
+ * Components point along the increasing coordinate.  All device buffers are
+ * caller-owned; the work is enqueued on `stream` (uses the plan's ghost
+ * scratch, so calls on one plan must not overlap). */
+smg_status smg_acceleration(smg_plan *plan, const double *phi_dev, const double *theta_dev, double *g_a_dev,
+                            double *g_b_dev, double *g_phi_dev, void *stream);
+
 /* Copy the DGF table Gt^m(t <- s) of mode m to dgf_host[n_g][n_g] (FP64,
  * row = field ghost t, column = source ghost s). */
 smg_status smg_dgf_table(smg_plan *plan, int m, double *dgf_host, void *stream);

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsmg.so")
-SOURCES = ["geometry.cpp", "api.cpp", "engine.cpp", "fft.hip", "mg.hip", "mg_lds.hip", "sched.hip", "james.hip", "dgf.hip", "net.hip", "net.cpp", "netguess.hip"]
+SOURCES = ["geometry.cpp", "api.cpp", "engine.cpp", "accel.hip", "fft.hip", "mg.hip", "mg_lds.hip", "sched.hip", "james.hip", "dgf.hip", "net.hip", "net.cpp", "netguess.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SMG_ARCH", "gfx950")

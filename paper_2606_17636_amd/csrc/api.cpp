@@ -198,9 +198,13 @@ struct smg_plan {
   Blob blob;
   std::vector<LevelOff> loff;
   size_t o_tw = 0, o_adj = 0, o_cout = 0, o_apc = 0, o_apg0 = 0, o_apg1 = 0, o_apc0 = 0, o_apc1 = 0;
+  // face acceleration: inverse centroid distances and metric factors, ghost offsets
+  size_t o_acc_da = 0, o_acc_db = 0, o_acc_ra = 0, o_acc_sb = 0;
+  int acc_g_ahi = 0, acc_g_blo = -1, acc_g_bhi = -1;
+  bool have_theta = false;  // w_theta holds the Theta of an enqueued solve
   // workspace layout (byte offsets)
-  size_t w_blob = 0, w_dgf = 0, w_psi = 0, w_phi = 0, w_f = 0, w_f2 = 0, w_sigma = 0, w_theta = 0, w_eng = 0, w_eng_bytes = 0,
-         w_total = 0;
+  size_t w_blob = 0, w_dgf = 0, w_psi = 0, w_phi = 0, w_f = 0, w_f2 = 0, w_sigma = 0, w_theta = 0, w_gpot = 0, w_eng = 0,
+         w_eng_bytes = 0, w_total = 0;
   std::vector<size_t> w_u, w_fl, w_u32, w_f32;
   // bound workspace
   char* ws = nullptr;
@@ -339,6 +343,28 @@ extern "C" smg_status smg_plan_create(const smg_grid* grid, const smg_opts* opts
   p->o_apg1 = p->blob.add(p->ap_g1);
   p->o_apc0 = p->blob.add(p->ap_c0);
   p->o_apc1 = p->blob.add(p->ap_c1);
+  // face acceleration tables (Eq. gradient): projected centroid distances
+  // across the radial and theta/z faces (ghost centroids at the ends; a face
+  // lying on a pole gets 0, i.e. g = 0), radial centroids and sin(theta)
+  {
+    const Axis A = make_axis(s, 'a', 0, 1, s.n_a), B = make_axis(s, 'b', 0, 1, s.n_b);
+    std::vector<double> ida(s.n_a + 1), idb(s.n_b + 1), ira(s.n_a), isb(s.n_b);
+    for (int f = 0; f <= s.n_a; ++f) ida[f] = 1.0 / (A.cent[f + 1] - A.cent[f]);
+    for (int f = 0; f <= s.n_b; ++f) {
+      const bool pole = (f == 0 && s.pole_lo()) || (f == s.n_b && s.pole_hi());
+      idb[f] = pole ? 0.0 : 1.0 / (B.cent[f + 1] - B.cent[f]);
+    }
+    for (int i = 0; i < s.n_a; ++i) ira[i] = 1.0 / A.cent[i + 1];
+    for (int j = 0; j < s.n_b; ++j) isb[j] = s.sph() ? 1.0 / std::sin(B.cent[j + 1]) : 1.0;
+    p->o_acc_da = p->blob.add(ida);
+    p->o_acc_db = p->blob.add(idb);
+    p->o_acc_ra = p->blob.add(ira);
+    p->o_acc_sb = p->blob.add(isb);
+    // ghost order: inner radial (n_b), outer radial (n_b), lower b, upper b (n_a each, Dirichlet edges only)
+    p->acc_g_ahi = s.n_b;
+    p->acc_g_blo = s.pole_lo() ? -1 : 2 * s.n_b;
+    p->acc_g_bhi = s.pole_hi() ? -1 : 2 * s.n_b + (s.pole_lo() ? 0 : s.n_a);
+  }
   // workspace layout
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o2 = off; off = align_up(off + bytes); return o2; };
@@ -352,6 +378,7 @@ extern "C" smg_status smg_plan_create(const smg_grid* grid, const smg_opts* opts
   p->w_f2 = take(sizeof(double2) * M * plane);
   p->w_sigma = take(sizeof(double2) * (size_t)M * p->n_g);
   p->w_theta = take(sizeof(double2) * (size_t)M * p->n_g);
+  p->w_gpot = take(sizeof(double) * (size_t)p->n_g * s.n_phi);
   p->w_eng_bytes = Engine::region_bytes(2, 1, (int)p->H.lv.size(), M);
   p->w_eng = take(p->w_eng_bytes);
   p->w_u.assign(p->H.lv.size(), 0);
@@ -846,9 +873,11 @@ static std::vector<int> schedule_of(const std::vector<int>& cyc) {
 }
 
 static smg_status james_all(Group& g, hipStream_t st) {
-  for (smg_plan* p : g.plans)
+  for (smg_plan* p : g.plans) {
     STCHK(james_steps(p, p->dptr(p->w_psi), p->dptr(p->w_f), p->dptr(p->w_sigma), p->dptr(p->w_theta),
                       p->dptr(p->w_f2), st));
+    p->have_theta = true;
+  }
   return SMG_OK;
 }
 
@@ -1444,6 +1473,40 @@ extern "C" smg_status smg_james(smg_plan* p, const double* psi, const double* f,
   return james_steps(p, reinterpret_cast<const double2*>(psi), reinterpret_cast<const double2*>(f),
                      reinterpret_cast<double2*>(sigma), reinterpret_cast<double2*>(theta), reinterpret_cast<double2*>(f2),
                      static_cast<hipStream_t>(stream));
+}
+
+extern "C" smg_status smg_acceleration(smg_plan* p, const double* phi, const double* theta, double* g_a, double* g_b,
+                                       double* g_phi, void* stream) {
+  STCHK(need_ready(p));
+  if (!phi || !g_a || !g_b || !g_phi) return fail(SMG_EINVAL, "phi and the three face arrays must not be NULL");
+  const double2* th = theta ? reinterpret_cast<const double2*>(theta) : (p->have_theta ? p->dptr(p->w_theta) : nullptr);
+  if (!th) return fail(SMG_ESTATE, "no ghost potential yet: pass theta or call smg_solve first");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Spec& s = p->spec;
+  const char* base = p->ws + p->w_blob;
+  double* gpot = reinterpret_cast<double*>(p->ws + p->w_gpot);
+  const double2* tw = reinterpret_cast<const double2*>(base + p->o_tw);
+  HIPCHK(smgk::fft_c2r(th, gpot, p->n_g, s.n_phi, tw, st));
+  AccelArgs a{};
+  a.phi = phi;
+  a.gpot = gpot;
+  a.inv_da = reinterpret_cast<const double*>(base + p->o_acc_da);
+  a.inv_db = reinterpret_cast<const double*>(base + p->o_acc_db);
+  a.inv_ra = reinterpret_cast<const double*>(base + p->o_acc_ra);
+  a.inv_sb = reinterpret_cast<const double*>(base + p->o_acc_sb);
+  a.ga = g_a;
+  a.gb = g_b;
+  a.gp = g_phi;
+  a.na = s.n_a;
+  a.nb = s.n_b;
+  a.nphi = s.n_phi;
+  a.inv_dphi = 1.0 / s.dphi();
+  a.sph = s.sph() ? 1 : 0;
+  a.g_ahi = p->acc_g_ahi;
+  a.g_blo = p->acc_g_blo;
+  a.g_bhi = p->acc_g_bhi;
+  HIPCHK(smgk::accel(a, st));
+  return SMG_OK;
 }
 
 extern "C" smg_status smg_dgf_table(smg_plan* p, int m, double* host, void* stream) {

@@ -71,7 +71,7 @@ __device__ __forceinline__ typename Vec<R>::T resid_at(const LevelDev& L, int m,
 template <typename R>
 __host__ __device__ inline size_t smooth_lds_bytes(int dir, int na, int nb, int tile, bool exact, int scratch) {
   const size_t nr = dir == 0 ? (size_t)na + 2 : (size_t)tile + 4;
-  const size_t nc = dir == 0 ? (size_t)tile + 4 : (size_t)nb + 2;
+  const size_t nc = dir == 0 ? (size_t)odd_stride(tile + 4) : (size_t)nb + 2;
   return (exact ? 1 : 2) * sizeof(typename Vec<R>::T) * nr * nc + sizeof(R) * ((size_t)scratch + 5 * nr + 4 * nc);
 }
 
@@ -99,10 +99,13 @@ __global__ void __launch_bounds__(kThreads) k_smooth(const LvJob* __restrict__ j
     r0 = i0 - 2; nr = tile + 4;
     c0 = -1; nc = nb + 2;
   } else {
+    // row stride odd (one unused column when tile + 4 is even): the lanes
+    // walk down the columns
     const int j0 = blockIdx.x * tile;
     r0 = -1; nr = na + 2;
-    c0 = j0 - 2; nc = tile + 4;
+    c0 = j0 - 2; nc = odd_stride(tile + 4);
   }
+  const int ncu = DIR == 0 ? tile + 4 : nc;  // columns holding plane data
   V* fs = sh + nr * nc;  // staged f (SOR variant only)
   // line range of this tile (the coordinate across the lines)
   const int lbeg = blockIdx.x * tile;                     // first owned line
@@ -117,7 +120,7 @@ __global__ void __launch_bounds__(kThreads) k_smooth(const LvJob* __restrict__ j
     const int rr = t / nc, cc = t - rr * nc;
     const int i = r0 + rr, j = c0 + cc;
     V v = mkv<R>(0, 0);
-    if (i >= 0 && i < na && j >= 0 && j < nb) v = u[(size_t)i * nb + j];
+    if (cc < ncu && i >= 0 && i < na && j >= 0 && j < nb) v = u[(size_t)i * nb + j];
     sh[t] = v;
   }
   if (EXACT) {

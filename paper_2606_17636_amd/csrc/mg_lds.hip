@@ -17,6 +17,11 @@ namespace {
 
 constexpr int kAliasCells = 4;  // coarse cells per thread of the aliased restriction
 
+// Row strides of a smoothed level's padded u and of its f (odd: see
+// odd_stride); the coarsest level keeps nb + 2 and nb.
+__host__ __device__ __forceinline__ int lvl_us(int nb) { return odd_stride(nb + 2); }
+__host__ __device__ __forceinline__ int lvl_fs(int nb) { return odd_stride(nb); }
+
 struct Red {
   double* buf;
   __device__ double sum(double v) {
@@ -73,7 +78,7 @@ template <int DIR, int PMAX, typename R>
 __device__ __forceinline__ void sor_phase(const LevelDev& L, const Tab<R>& T, typename Vec<R>::T* u, const typename Vec<R>::T* f,
                           int n_sor) {
   const int na = L.na, nb = L.nb;
-  const LineView<R> v{u, nb + 2, 1, 1, f, nb, 0, 0, T.ua, T.da, T.Rr, T.Ca, T.wb, 0, T.ub, T.db, T.Cb, T.wr, 0};
+  const LineView<R> v{u, lvl_us(nb), 1, 1, f, lvl_fs(nb), 0, 0, T.ua, T.da, T.Rr, T.Ca, T.wb, 0, T.ub, T.db, T.Cb, T.wr, 0};
   const int npts = DIR == 0 ? na : nb, nlines = DIR == 0 ? nb : na;
   for (int lc = 0; lc < 2; ++lc) {
     relax_colour<DIR, PMAX, R>(v, lc, nlines, npts, n_sor);
@@ -85,7 +90,7 @@ template <int DIR, typename R>
 __device__ __forceinline__ void exact_phase(const LevelDev& L, const Tab<R>& T, typename Vec<R>::T* u, const typename Vec<R>::T* f,
                             R* cp) {
   using V = typename Vec<R>::T;
-  const int na = L.na, nb = L.nb, nc = nb + 2;
+  const int na = L.na, nb = L.nb, nc = lvl_us(nb), fs = lvl_fs(nb);
   const int npts = DIR == 0 ? na : nb;
   for (int lc = 0; lc < 2; ++lc) {
     const int nl = DIR == 0 ? (nb - lc + 1) / 2 : (na - lc + 1) / 2;
@@ -108,7 +113,7 @@ __device__ __forceinline__ void exact_phase(const LevelDev& L, const Tab<R>& T, 
           lo = T.da[i]; up = T.ua[i];
           o1 = u[q + 1]; o2 = u[q - 1]; w1 = Rr * T.ub[j]; w2 = Rr * T.db[j];
         }
-        const V fv = f[i * nb + j];
+        const V fv = f[i * fs + j];
         const R rx = fv.x - (w1 * o1.x + w2 * o2.x), ry = fv.y - (w1 * o1.y + w2 * o2.y);
         const R den = c - lo * cprev;
         cprev = up / den;
@@ -140,16 +145,16 @@ __device__ __forceinline__ void smooth_step(const LevelDev& L, const Tab<R>& T, 
   }
 }
 
+// nc, fs: row strides of u (padded) and f
 template <typename R>
 __device__ __forceinline__ typename Vec<R>::T resid_lds(const LevelDev& L, const Tab<R>& T, const typename Vec<R>::T* u,
-                                                        const typename Vec<R>::T* f, int i, int j) {
-  const int nb = L.nb, nc = nb + 2;
+                                                        const typename Vec<R>::T* f, int i, int j, int nc, int fs) {
   const int q = (i + 1) * nc + (j + 1);
   const R Rr = T.Rr[i];
   const R c = T.Ca[i] + Rr * T.Cb[j];
   const R a1 = T.ua[i], a2 = T.da[i], b1 = Rr * T.ub[j], b2 = Rr * T.db[j];
   const auto un = u[q + nc], us = u[q - nc], ue = u[q + 1], uw = u[q - 1], uc = u[q];
-  const auto fv = f[i * nb + j];
+  const auto fv = f[i * fs + j];
   return mkv<R>(fv.x - (c * uc.x + a1 * un.x + a2 * us.x + b1 * ue.x + b2 * uw.x),
                 fv.y - (c * uc.y + a1 * un.y + a2 * us.y + b1 * ue.y + b2 * uw.y));
 }
@@ -169,8 +174,8 @@ __host__ __device__ inline void lds_layout(const LdsLevels& LL, int* o) {
   constexpr int K = kMaxLdsLevels;
   const int cl = LL.n - 1;
   auto al = [](int x) { return (x + 15) & ~15; };
-  auto ub = [&](int l) { return (int)sizeof(V) * (LL.L[l].na + 2) * (LL.L[l].nb + 2); };
-  auto fb = [&](int l) { return (int)sizeof(V) * LL.L[l].na * LL.L[l].nb; };
+  auto ub = [&](int l) { return (int)sizeof(V) * (LL.L[l].na + 2) * lvl_us(LL.L[l].nb); };
+  auto fb = [&](int l) { return (int)sizeof(V) * LL.L[l].na * lvl_fs(LL.L[l].nb); };
   const int cb = (int)sizeof(double2) * ((LL.L[cl].na + 2) * (LL.L[cl].nb + 2) + LL.L[cl].na * LL.L[cl].nb);
   int q = 0;
   if (LL.alias && cl > 0) {
@@ -248,9 +253,10 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
   // level 0 of the fused range: load f (and u for a full in-LDS cycle)
   {
     const LevelDev& L0 = LL.L[0];
-    const int na = L0.na, nb = L0.nb, nc = nb + 2;
+    const int na = L0.na, nb = L0.nb;
     const size_t off = (size_t)slot * na * nb;
     if (n > 1) {
+      const int nc = lvl_us(nb), fs = lvl_fs(nb);
 #pragma unroll 4
       for (int t = threadIdx.x; t < (na + 2) * nc; t += blockDim.x) {
         const int i = t / nc - 1, j = t % nc - 1;
@@ -259,7 +265,10 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
         Ul(0)[t] = v;
       }
 #pragma unroll 4
-      for (int t = threadIdx.x; t < na * nb; t += blockDim.x) Fl(0)[t] = Fg[off + t];
+      for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
+        const int i = t / nb, j = t - i * nb;
+        Fl(0)[i * fs + j] = Fg[off + t];
+      }
     } else {
       for (int t = threadIdx.x; t < na * nb; t += blockDim.x) fC[t] = make_double2(Fg[off + t].x, Fg[off + t].y);
     }
@@ -273,7 +282,10 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
     V* ul = Ul(l);
     const V* fl = Fl(l);
     for (int k = 0; k < nu_pre; ++k) smooth_step<PMAX, R>(L, T, ul, fl, n_sor, exact, cp);
-    const int ncc = C.nb + 2;
+    // coarse u is cleared over its padded extent (row stride ncc), coarse f
+    // is stored with row stride fcs
+    const int ncc = l + 1 == cl ? C.nb + 2 : lvl_us(C.nb);
+    const int fcs = l + 1 == cl ? C.nb : lvl_fs(C.nb);
     // coarse right-hand side = area-weighted restriction of the residual
     auto restrict_at = [&](int t) {
       const int I = t / C.nb, J = t - I * C.nb;
@@ -281,15 +293,16 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
           const R w = (R)gbl(L.rwa)[2 * I + a] * (R)gbl(L.rwb)[2 * J + b];
-          const V r = resid_lds<R>(L, T, ul, fl, 2 * I + a, 2 * J + b);
+          const V r = resid_lds<R>(L, T, ul, fl, 2 * I + a, 2 * J + b, lvl_us(L.nb), lvl_fs(L.nb));
           ax = fma(w, r.x, ax);
           ay = fma(w, r.y, ay);
         }
       return mkv<R>(ax, ay);
     };
     auto put_f = [&](int t, V v) {
+      const int I = t / C.nb, J = t - I * C.nb;
       if (l + 1 == cl) fC[t] = make_double2(v.x, v.y);
-      else Fl(l + 1)[t] = v;
+      else Fl(l + 1)[I * fcs + J] = v;
     };
     if (alias && l == 0) {
       // the coarse arrays overlay this level's f: restrict into registers
@@ -382,7 +395,7 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
           double r2 = 0.0;
           for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
             const int i = t / nb, j = t - i * nb;
-            const double2 r = resid_lds<double>(L, T, uC, fC, i, j);
+            const double2 r = resid_lds<double>(L, T, uC, fC, i, j, nb + 2, nb);
             r2 += r.x * r.x + r.y * r.y;
           }
           r2 = red.sum(r2);
@@ -396,7 +409,7 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
   for (int l = cl - 1; l >= 0; --l) {
     const LevelDev& L = LL.L[l];
     const LevelDev& C = LL.L[l + 1];
-    const int nb = L.nb, nc = nb + 2, ncc = C.nb + 2;
+    const int nb = L.nb, nc = lvl_us(nb), ncc = l + 1 == cl ? C.nb + 2 : lvl_us(C.nb);
     const int par = m & 1;
     const Tab<R> T = Tl(l);
     V* ul = Ul(l);
@@ -432,15 +445,19 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
     if (alias && l == 0) {
       // the coarse levels are done with region A: level 0's f again
       const size_t off = (size_t)slot * L.na * nb;
+      const int fs = lvl_fs(nb);
 #pragma unroll 4
-      for (int t = threadIdx.x; t < L.na * nb; t += blockDim.x) Fl(0)[t] = Fg[off + t];
+      for (int t = threadIdx.x; t < L.na * nb; t += blockDim.x) {
+        const int i = t / nb, j = t - i * nb;
+        Fl(0)[i * fs + j] = Fg[off + t];
+      }
       __syncthreads();
     }
     for (int k = 0; k < nu_post; ++k) smooth_step<PMAX, R>(L, T, ul, fl, n_sor, exact, cp);
   }
   {
     const LevelDev& L0 = LL.L[0];
-    const int na = L0.na, nb = L0.nb, nc = nb + 2;
+    const int na = L0.na, nb = L0.nb, nc = n > 1 ? lvl_us(nb) : nb + 2;
     const size_t off = (size_t)slot * na * nb;
     for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
       const int i = t / nb, j = t - i * nb;

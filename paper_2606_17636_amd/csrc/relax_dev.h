@@ -17,7 +17,7 @@
 // which is the over-relaxed Gauss-Seidel step u_p + omega (t_p - u_p) with
 // t_p the point's exact solve.  Couplings that leave the plane are zero in
 // the tables (boundary data live in f), and points past the end of a line
-// hold zero with a zero weight.
+// are never stored.
 #pragma once
 
 #include "vec.h"
@@ -58,6 +58,10 @@ __device__ __forceinline__ double lane_next(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Row strides of the LDS planes that the line kernels use: odd, so that the
+// lanes of a wave walking down a column (radial lines) hit distinct banks.
+__host__ __device__ __forceinline__ int odd_stride(int n) { return n | 1; }
+
 // Points per lane for lines of npts points: the smallest of 2, 4, 8, 16
 // with npts <= 64 P, so that a line fits in one wave (lines longer than
 // kRelaxMaxPoints are rejected when a plan is made).
@@ -66,9 +70,18 @@ __host__ __device__ __forceinline__ int relax_points_per_lane(int npts) {
   return npts <= 128 ? 2 : (npts <= 256 ? 4 : (npts <= 512 ? 8 : 16));
 }
 
+// omega / c: exact in FP64; in the FP32 smoothing of the mixed form the
+// hardware reciprocal (within 1 ulp), which changes the smoother's weights
+// by about one FP32 rounding.
+__device__ __forceinline__ float omega_over(float om, float c) { return om * __builtin_amdgcn_rcpf(c); }
+__device__ __forceinline__ double omega_over(double om, double c) { return om / c; }
+
 // DIR = 1: polar lines (fixed row i, points j); DIR = 0: radial lines (fixed
 // column j, points i).  Every thread of the block calls this; waves take
-// groups of lines in turn.
+// groups of lines in turn.  Lanes past the last line or point load a valid
+// cell instead (clamped indices) and store nothing: their values never
+// reach a stored point, since the couplings across a line's ends are zero
+// and the segment ends are masked in the shifts.
 template <int DIR, int P, typename R>
 __device__ __forceinline__ void relax_colour_p(const LineView<R>& v, int a, int b, int npts, int n_sor) {
   using V = typename Vec<R>::T;
@@ -78,64 +91,51 @@ __device__ __forceinline__ void relax_colour_p(const LineView<R>& v, int a, int 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   const int g = lane / lpl, k = lane - g * lpl;
   const int nl = a < b ? (b - a + 1) / 2 : 0;
+  const bool first = k == 0, last = k == lpl - 1;
   for (int base = wave * G; base < nl; base += nwave * G) {  // uniform in the wave
     const int li = base + g;
     const bool act = g < G && li < nl;
-    const int line = a + 2 * li;
+    const int line = a + 2 * (act ? li : 0);
     R ux[P], uy[P], rx[P], ry[P], wc[P], lo[P], up[P];
-    R omc = 0;
-    if (act) {
-      if (DIR == 1) {
-        const int i = line, ti = i + v.ti;
-        const R om = v.wb[ti], a1 = v.ua[ti], a2 = v.da[ti], rr = v.Rr[ti], ca = v.Ca[ti];
-        omc = (R)1 - om;
-        const V* ur = v.u + (size_t)(i + v.ui) * v.us + v.uj;
-        const V* fr = v.f + (size_t)(i + v.fi) * v.fs + v.fj;
+    R omc;
+    if (DIR == 1) {
+      const int ti = line + v.ti;
+      const R om = v.wb[ti], a1 = v.ua[ti], a2 = v.da[ti], rr = v.Rr[ti], ca = v.Ca[ti];
+      omc = (R)1 - om;
+      const V* ur = v.u + (line + v.ui) * v.us + v.uj;
+      const V* fr = v.f + (line + v.fi) * v.fs + v.fj;
 #pragma unroll
-        for (int s = 0; s < P; ++s) {
-          const int j = P * k + s;
-          if (j < npts) {
-            const int tj = j + v.tj;
-            lo[s] = rr * v.db[tj];
-            up[s] = rr * v.ub[tj];
-            wc[s] = om / (ca + rr * v.Cb[tj]);
-            const V uc = ur[j], un = ur[j + v.us], us = ur[j - v.us], fv = fr[j];
-            ux[s] = uc.x; uy[s] = uc.y;
-            rx[s] = fv.x - (a1 * un.x + a2 * us.x);
-            ry[s] = fv.y - (a1 * un.y + a2 * us.y);
-          } else {
-            ux[s] = uy[s] = rx[s] = ry[s] = wc[s] = lo[s] = up[s] = 0;
-          }
-        }
-      } else {
-        const int j = line, tj = j + v.tj;
-        const R om = v.wr[tj], b1 = v.ub[tj], b2 = v.db[tj], cb = v.Cb[tj];
-        omc = (R)1 - om;
-#pragma unroll
-        for (int s = 0; s < P; ++s) {
-          const int i = P * k + s;
-          if (i < npts) {
-            const int ti = i + v.ti;
-            const R rr = v.Rr[ti];
-            lo[s] = v.da[ti];
-            up[s] = v.ua[ti];
-            wc[s] = om / (v.Ca[ti] + rr * cb);
-            const V* uq = v.u + (size_t)(i + v.ui) * v.us + j + v.uj;
-            const V uc = uq[0], ue = uq[1], uw = uq[-1];
-            const V fv = v.f[(size_t)(i + v.fi) * v.fs + j + v.fj];
-            ux[s] = uc.x; uy[s] = uc.y;
-            rx[s] = fv.x - rr * (b1 * ue.x + b2 * uw.x);
-            ry[s] = fv.y - rr * (b1 * ue.y + b2 * uw.y);
-          } else {
-            ux[s] = uy[s] = rx[s] = ry[s] = wc[s] = lo[s] = up[s] = 0;
-          }
-        }
+      for (int s = 0; s < P; ++s) {
+        const int j = min(P * k + s, npts - 1);
+        const int tj = j + v.tj;
+        lo[s] = rr * v.db[tj];
+        up[s] = rr * v.ub[tj];
+        wc[s] = omega_over(om, ca + rr * v.Cb[tj]);
+        const V uc = ur[j], un = ur[j + v.us], us = ur[j - v.us], fv = fr[j];
+        ux[s] = uc.x; uy[s] = uc.y;
+        rx[s] = fv.x - (a1 * un.x + a2 * us.x);
+        ry[s] = fv.y - (a1 * un.y + a2 * us.y);
       }
     } else {
+      const int j = line, tj = j + v.tj;
+      const R om = v.wr[tj], b1 = v.ub[tj], b2 = v.db[tj], cb = v.Cb[tj];
+      omc = (R)1 - om;
 #pragma unroll
-      for (int s = 0; s < P; ++s) ux[s] = uy[s] = rx[s] = ry[s] = wc[s] = lo[s] = up[s] = 0;
+      for (int s = 0; s < P; ++s) {
+        const int i = min(P * k + s, npts - 1);
+        const int ti = i + v.ti;
+        const R rr = v.Rr[ti];
+        lo[s] = v.da[ti];
+        up[s] = v.ua[ti];
+        wc[s] = omega_over(om, v.Ca[ti] + rr * cb);
+        const V* uq = v.u + (i + v.ui) * v.us + j + v.uj;
+        const V uc = uq[0], ue = uq[1], uw = uq[-1];
+        const V fv = v.f[(i + v.fi) * v.fs + j + v.fj];
+        ux[s] = uc.x; uy[s] = uc.y;
+        rx[s] = fv.x - rr * (b1 * ue.x + b2 * uw.x);
+        ry[s] = fv.y - rr * (b1 * ue.y + b2 * uw.y);
+      }
     }
-    const bool first = k == 0, last = k == lpl - 1;
     for (int it = 0; it < n_sor; ++it) {
       // even points: the left neighbour of point 0 is the last point of lane k-1
       {
@@ -168,7 +168,7 @@ __device__ __forceinline__ void relax_colour_p(const LineView<R>& v, int a, int 
         const int pt = P * k + s;
         if (pt < npts) {
           const int i = DIR == 1 ? line : pt, j = DIR == 1 ? pt : line;
-          v.u[(size_t)(i + v.ui) * v.us + j + v.uj] = mkv<R>(ux[s], uy[s]);
+          v.u[(i + v.ui) * v.us + j + v.uj] = mkv<R>(ux[s], uy[s]);
         }
       }
     }

@@ -193,7 +193,25 @@ struct ConvState {
   int* cyc;
 };
 
+// Face acceleration (accel.hip): g = -grad Phi on every cell face of the
+// real potential, the boundary faces from the ghost potential.
+struct AccelArgs {
+  const double* phi;     // [na][nb][nphi] potential
+  const double* gpot;    // [n_g][nphi] minus the ghost potential (the c2r transform of Theta)
+  const double* inv_da;  // [na + 1] 1 / (centroid distance) across the radial faces 0..na
+  const double* inv_db;  // [nb + 1] the same across the theta / z faces (0 on a face lying on a pole)
+  const double* inv_ra;  // [na] 1 / radial centroid (theta-face and phi-face metric)
+  const double* inv_sb;  // [nb] 1 / sin(theta centroid) (1 for cylindrical grids)
+  double *ga, *gb, *gp;  // [na + 1][nb][nphi], [na][nb + 1][nphi], [na][nb][nphi]
+  int na, nb, nphi;
+  double inv_dphi;
+  int sph;               // theta-face distance carries the radial centroid
+  int g_ahi, g_blo, g_bhi;  // first ghost of the outer radial / lower b / upper b edge (-1: none)
+};
+
 namespace smgk {
+// Face acceleration (accel.hip)
+hipError_t accel(const AccelArgs& a, hipStream_t st);
 // FFT (fft.hip)
 hipError_t fft_r2c(const double* rho, double2* modes, int n_lines, int n_phi, double scale,
                    const double2* tw, hipStream_t st);

@@ -95,6 +95,7 @@ def load():
         "smg_mg_smooth": ([P, P, P, P], ctypes.c_int),
         "smg_mg_residual": ([P, P, P, P, P], ctypes.c_int),
         "smg_james": ([P, P, P, P, P, P, P], ctypes.c_int),
+        "smg_acceleration": ([P, P, P, P, P, P, P], ctypes.c_int),
         "smg_dgf_table": ([P, ctypes.c_int, _PD, P], ctypes.c_int),
         "smg_profile_begin": ([P], ctypes.c_int),
         "smg_profile_end": ([P, ctypes.POINTER(KernelStat), ctypes.c_int, _PI], ctypes.c_int),
@@ -338,6 +339,27 @@ class Plan:
         _check(load().smg_james(self._h, _ptr(self._c128(psi, self.mode_shape())),
                                 _ptr(self._c128(f, self.mode_shape())), _ptr(sigma), _ptr(theta), _ptr(f2), _stream()))
         return sigma, theta, f2
+
+    def acceleration(self, phi, theta=None, out=None):
+        """g = -grad Phi on the faces: (g_a, g_b, g_phi) of shapes
+        (n_a+1, n_b, n_phi), (n_a, n_b+1, n_phi), (n_a, n_b, n_phi).  theta:
+        complex (n_modes, n_ghost) screening potential, or None for that of
+        the last solve."""
+        import torch
+        na, nb, npf = self.grid.n_a, self.grid.n_b, self.grid.n_phi
+        self._f64(phi, (na, nb, npf))
+        if theta is not None:
+            self._c128(theta, (self.n_modes, self.n_ghost))
+        if out is None:
+            kw = dict(dtype=torch.float64, device=phi.device)
+            out = (torch.empty((na + 1, nb, npf), **kw), torch.empty((na, nb + 1, npf), **kw),
+                   torch.empty((na, nb, npf), **kw))
+        g_a, g_b, g_p = out
+        self._f64(g_a, (na + 1, nb, npf))
+        self._f64(g_b, (na, nb + 1, npf))
+        self._f64(g_p, (na, nb, npf))
+        _check(load().smg_acceleration(self._h, _ptr(phi), _ptr(theta), _ptr(g_a), _ptr(g_b), _ptr(g_p), _stream()))
+        return g_a, g_b, g_p
 
     def profile_begin(self):
         _check(load().smg_profile_begin(self._h))
