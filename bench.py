@@ -105,6 +105,48 @@ def _timed(plan, rho, phi, steps, tol, torch):
     return time.perf_counter() - t0
 
 
+def bench_accel(args, smg, configs, torch):
+    """The step after the solve: g = -grad Phi on every face of the workload's
+    grid (one smg_acceleration call per step, the potential and Theta of one
+    chosen-form solve resident in HBM)."""
+    wl = "c5" if args.workload == "c5-snapshot" else args.workload
+    g = configs.GRIDS[wl]
+    log(f"face acceleration on the {args.workload} grid")
+    plan = _plan(smg, g, "chosen", args.line_solver).setup("cuda:0")
+    a, b, p, _ = plan.geometry()
+    rho = torch.from_numpy(configs.density(wl, a, b, p)).to("cuda:0")
+    phi, info = plan.solve(rho, tol=args.tol)
+    out = plan.acceleration(phi)
+    for _ in range(args.warmup):
+        plan.acceleration(phi, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        plan.acceleration(phi, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    ms = e0.elapsed_time(e1) / args.steps
+    na, nb, nph = g["n_a"], g["n_b"], g["n_phi"]
+    cells = na * nb * nph
+    # read phi once, write the three face arrays once, read the ghost potential
+    algo = 8.0 * (cells + (na + 1) * nb * nph + na * (nb + 1) * nph + cells + plan.n_ghost * nph)
+    achieved = algo / (ms * 1e-3) / 1e9
+    print(json.dumps({
+        "metric": "face acceleration fields/s", "value": round(args.steps / dt, 2), "unit": "fields/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: g = -grad Phi on all faces of the solved potential",
+                   "cells": cells, "ghosts": plan.n_ghost},
+        "roofline": {"bound": "hbm", "kernel": "face_acceleration (ghost c2r + face kernel)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "avg_launch_us": round(1e3 * ms, 3), "bytes_per_launch": round(algo)},
+    }), flush=True)
+
+
 def bench_batch(args, smg, configs, torch):
     """The 16-problem batch: one batched solve of all problems per step
     (chosen form) against the plain GPU form solving them one by one."""
@@ -296,6 +338,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--train-traj", type=int, default=8, help="c5: training trajectories")
     ap.add_argument("--train-steps", type=int, default=2000, help="c5: Adam steps")
+    ap.add_argument("--part", default="solve", choices=["solve", "accel"],
+                    help="accel: time the face acceleration of the solved potential instead of the solve")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (the HBM-counter calibration kernel)")
     args = ap.parse_args()
@@ -319,6 +363,8 @@ def main():
     from paper_2606_17636_amd import smg
     from workloads import configs
 
+    if args.part == "accel":
+        return bench_accel(args, smg, configs, torch)
     if args.workload == "c4":
         return bench_batch(args, smg, configs, torch)
     if args.workload == "c5":

@@ -75,8 +75,8 @@ __host__ __device__ inline size_t smooth_lds_bytes(int dir, int na, int nb, int 
   return (exact ? 1 : 2) * sizeof(typename Vec<R>::T) * nr * nc + sizeof(R) * ((size_t)scratch + 5 * nr + 4 * nc);
 }
 
-template <int DIR, bool EXACT, int PMAX, typename R>
-__global__ void __launch_bounds__(kThreads) k_smooth(const LvJob* __restrict__ jobs, BatchRef bt, int n_sor) {
+template <int DIR, bool EXACT, int PMAX, typename R, int NT>
+__global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, BatchRef bt, int n_sor) {
   using V = typename Vec<R>::T;
   extern __shared__ char smem[];
   V* sh = reinterpret_cast<V*>(smem);
@@ -385,7 +385,6 @@ int grid_for(int cells) {
   return g < 1 ? 1 : (g > 1024 ? 1024 : g);
 }
 
-constexpr size_t kSmoothLds = 60 * 1024;  // preferred per-block LDS
 
 }  // namespace
 
@@ -420,7 +419,7 @@ bool smooth_shape(const LevelDev& L, int dir, bool exact, bool fp32, int target_
   int tile = (nlines + want - 1) / want;
   if (tile < 2) tile = 2;
   if (tile > nlines) tile = nlines;
-  while (tile > 2 && bytes(tile) > kSmoothLds) --tile;
+  while (tile > 2 && bytes(tile) > lds_limit() - 1024) --tile;
   if (tile > 2 && (tile & 1)) --tile;
   out->tile = tile;
   out->ntile = (nlines + tile - 1) / tile;
@@ -444,23 +443,37 @@ static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, 
   if (gx == 0 || b.cap == 0) return hipSuccess;
   if (lds > lds_limit()) return hipErrorInvalidConfiguration;
   const dim3 grid(gx, b.cap);
-  int pmax = 2;  // points per lane the longest relaxed line needs
+  int pmax = 2, tmax = 0;  // points per lane of the longest relaxed line; widest tile
   for (int q = 0; q < n_prob; ++q)
-    if (hj[q].active) pmax = std::max(pmax, relax_points_per_lane(dir == 0 ? hj[q].L.na : hj[q].L.nb));
-  auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, st, jobs, b, n_sor); };
+    if (hj[q].active) {
+      pmax = std::max(pmax, relax_points_per_lane(dir == 0 ? hj[q].L.na : hj[q].L.nb));
+      tmax = std::max(tmax, hj[q].tile[dir]);
+    }
+  // wide tiles (more lines per colour than four waves take in one step)
+  // run with 1024 threads where the variant stays within 128 registers
+  const bool big = !exact && tmax >= 16 && pmax <= 4;
+  auto go = [&](auto kern, int nt) { hipLaunchKernelGGL(kern, grid, dim3(nt), lds, st, jobs, b, n_sor); };
   if (exact) {
-    if (dir == 0) go(k_smooth<0, true, 2, R>);
-    else go(k_smooth<1, true, 2, R>);
+    if (dir == 0) go(k_smooth<0, true, 2, R, kThreads>, kThreads);
+    else go(k_smooth<1, true, 2, R, kThreads>, kThreads);
+  } else if (big) {
+    if (dir == 0) {
+      if (pmax <= 2) go(k_smooth<0, false, 2, R, 1024>, 1024);
+      else go(k_smooth<0, false, 4, R, 1024>, 1024);
+    } else {
+      if (pmax <= 2) go(k_smooth<1, false, 2, R, 1024>, 1024);
+      else go(k_smooth<1, false, 4, R, 1024>, 1024);
+    }
   } else if (dir == 0) {
-    if (pmax <= 2) go(k_smooth<0, false, 2, R>);
-    else if (pmax <= 4) go(k_smooth<0, false, 4, R>);
-    else if (pmax <= 8) go(k_smooth<0, false, 8, R>);
-    else go(k_smooth<0, false, 16, R>);
+    if (pmax <= 2) go(k_smooth<0, false, 2, R, kThreads>, kThreads);
+    else if (pmax <= 4) go(k_smooth<0, false, 4, R, kThreads>, kThreads);
+    else if (pmax <= 8) go(k_smooth<0, false, 8, R, kThreads>, kThreads);
+    else go(k_smooth<0, false, 16, R, kThreads>, kThreads);
   } else {
-    if (pmax <= 2) go(k_smooth<1, false, 2, R>);
-    else if (pmax <= 4) go(k_smooth<1, false, 4, R>);
-    else if (pmax <= 8) go(k_smooth<1, false, 8, R>);
-    else go(k_smooth<1, false, 16, R>);
+    if (pmax <= 2) go(k_smooth<1, false, 2, R, kThreads>, kThreads);
+    else if (pmax <= 4) go(k_smooth<1, false, 4, R, kThreads>, kThreads);
+    else if (pmax <= 8) go(k_smooth<1, false, 8, R, kThreads>, kThreads);
+    else go(k_smooth<1, false, 16, R, kThreads>, kThreads);
   }
   return hipGetLastError();
 }
