@@ -105,6 +105,11 @@ typedef struct {
                             shapes (where the in-LDS coarse cycle starts,
                             smoother blocks per launch) for 2, 8, 32 and all
                             planes, and keep the fastest [0: built-in rule] */
+  int coarse_cells;      /* coarsening stops at the first level with at most
+                            this many cells, after at least one halving (the
+                            paper leaves the depth open, Sec. 3.3); that level
+                            is solved exactly by fast diagonalisation
+                            [0: 128] */
 } smg_opts;
 
 enum { SMG_LAUNCH_GRAPH = 0, SMG_LAUNCH_DYNAMIC = 1 };

@@ -49,17 +49,21 @@ from .omega import omega_1d, omega_2d
 from .operator import PlaneOperator, main_edges
 
 FLOOR = 1e-6
-# a level of at most this many cells is the coarsest (it is solved to
-# convergence; coarser levels would only add smoothing latency)
+# by default a level of at most this many cells is the coarsest (it is
+# solved to convergence; coarser levels would only add smoothing latency);
+# the depth is a parameter of the hierarchy (the paper leaves it open)
 MAX_COARSEST = 128
 
 
-def level_sizes(spec):
+def level_sizes(spec, max_coarsest=MAX_COARSEST):
+    """Level shapes: halve until a level has at most max_coarsest cells
+    (after at least one halving), both sides stay even, the smaller coarse
+    side stays >= 2 and the coarse inner ghost face stays at r > 0."""
     sizes = [(spec.n_a, spec.n_b)]
     s = 1
     while True:
         na, nb = sizes[-1]
-        if na * nb <= MAX_COARSEST:
+        if na * nb <= max_coarsest and len(sizes) > 1:
             break
         if na % 2 or nb % 2 or min(na, nb) // 2 < 2:
             break
@@ -183,7 +187,7 @@ class MGLevel:
                     self._update(U, f, m, lc, pc, w)
         u[...] = U[1:-1, 1:-1]
 
-    def coarse_solve(self, f, m, rtol=1e-10, max_sweeps=500):
+    def coarse_solve(self, f, m, rtol=1e-10, max_sweeps=20000):
         """Red-black point SOR from a zero start until the residual 2-norm
         drops by rtol (or max_sweeps)."""
         w = self.omega_coarse(m)
@@ -274,11 +278,12 @@ def prolongation_matrix_1d(fine: Axis1D, coarse: Axis1D, geometry, which, k_lo, 
 class Hierarchy:
     """The multigrid hierarchy of the problem grid and its V-cycle."""
 
-    def __init__(self, spec, nu_pre=2, nu_post=2, n_sor=2, restriction="bilinear", line_solver="sor"):
+    def __init__(self, spec, nu_pre=2, nu_post=2, n_sor=2, restriction="bilinear", line_solver="sor",
+                 max_coarsest=MAX_COARSEST):
         self.spec = spec
         self.nu_pre, self.nu_post, self.n_sor = nu_pre, nu_post, n_sor
         self.line_solver = line_solver
-        self.sizes = level_sizes(spec)
+        self.sizes = level_sizes(spec, max_coarsest)
         self.levels = [MGLevel(spec, l) for l in range(len(self.sizes))]
         lit = restriction == "literal"
         self.rw = []

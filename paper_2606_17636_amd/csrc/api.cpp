@@ -74,8 +74,8 @@ struct Blob {
 // Offsets of one level's tables inside the blob.
 struct LevelOff {
   size_t ua, da, Rr, ub, db, Ca, Cb, wr, wb, wc, va, vb, rwa, rwb, pa_i0, pa_i1, pa_w0, pa_w1, pb_i0, pb_i1,
-      pb_w0, pb_w1, cinv;
-  bool has_cinv;
+      pb_w0, pb_w1, sep_v, sep_vi, sep_cp, sep_id;
+  bool has_sep;
 };
 
 LevelOff pack_level(Blob& B, const LevelTables& T) {
@@ -94,8 +94,11 @@ LevelOff pack_level(Blob& B, const LevelTables& T) {
     w1.insert(w1.end(), T.pb_w1[par].begin(), T.pb_w1[par].end());
   }
   o.pb_i0 = B.add(i0); o.pb_i1 = B.add(i1); o.pb_w0 = B.add(w0); o.pb_w1 = B.add(w1);
-  o.has_cinv = !T.cinv.empty();
-  o.cinv = o.has_cinv ? B.add(T.cinv) : 0;
+  o.has_sep = !T.sep_v.empty();
+  o.sep_v = o.has_sep ? B.add(T.sep_v) : 0;
+  o.sep_vi = o.has_sep ? B.add(T.sep_vi) : 0;
+  o.sep_cp = o.has_sep ? B.add(T.sep_cp) : 0;
+  o.sep_id = o.has_sep ? B.add(T.sep_id) : 0;
   return o;
 }
 
@@ -109,7 +112,10 @@ LevelDev level_view(const char* base, const LevelOff& o, const LevelTables& T, i
   L.va = d(o.va); L.vb = d(o.vb); L.rwa = d(o.rwa); L.rwb = d(o.rwb);
   L.pa_i0 = i(o.pa_i0); L.pa_i1 = i(o.pa_i1); L.pa_w0 = d(o.pa_w0); L.pa_w1 = d(o.pa_w1);
   L.pb_i0 = i(o.pb_i0); L.pb_i1 = i(o.pb_i1); L.pb_w0 = d(o.pb_w0); L.pb_w1 = d(o.pb_w1);
-  L.cinv = o.has_cinv ? d(o.cinv) : nullptr;
+  L.sep_v = o.has_sep ? d(o.sep_v) : nullptr;
+  L.sep_vi = o.has_sep ? d(o.sep_vi) : nullptr;
+  L.sep_cp = o.has_sep ? d(o.sep_cp) : nullptr;
+  L.sep_id = o.has_sep ? d(o.sep_id) : nullptr;
   return L;
 }
 
@@ -257,6 +263,8 @@ static smg_status validate(const smg_grid& g, const smg_opts& o) {
   if (o.n_pad < 2 || o.n_pad > 24) return fail(SMG_EINVAL, "n_pad must be in [2, 24]");
   if (o.dgf_method < SMG_DGF_AUTO || o.dgf_method > SMG_DGF_EXTENDED) return fail(SMG_EINVAL, "bad dgf_method");
   if (o.line_solver != SMG_LINE_SOR && o.line_solver != SMG_LINE_EXACT) return fail(SMG_EINVAL, "bad line_solver");
+  if (o.coarse_cells != 0 && (o.coarse_cells < 16 || o.coarse_cells > 8192))
+    return fail(SMG_EINVAL, "coarse_cells must be 0 or in [16, 8192]");
   return SMG_OK;
 }
 
@@ -288,9 +296,11 @@ extern "C" smg_status smg_plan_create(const smg_grid* grid, const smg_opts* opts
                  s.pole_hi() ? EDGE_POLE : EDGE_DIRICHLET};
   std::vector<int> modes(p->M);
   for (int m = 0; m < p->M; ++m) modes[m] = m;
-  p->H = build_hierarchy(s, 1, s.n_a, 1, s.n_b, edge, modes, true);
+  p->H = build_hierarchy(s, 1, s.n_a, 1, s.n_b, edge, modes, true, o.coarse_cells);
   const LevelTables& Lc = p->H.lv.back();
-  if (Lc.na * Lc.nb > kMaxCoarseCells)
+  if (Lc.na * Lc.nb > kMaxCoarseCells && Lc.sep_v.empty())
+    return fail(SMG_EINVAL, strprintf("the %dx%d coarsest level has no exact solver", Lc.na, Lc.nb));
+  if (Lc.na * Lc.nb > std::max(kMaxCoarseCells, o.coarse_cells))
     return fail(SMG_EINVAL, strprintf("grid coarsens only to %dx%d (> %d cells): the radial ghost face reaches r <= 0",
                                       Lc.na, Lc.nb, kMaxCoarseCells));
   p->gh = make_ghosts(s);

@@ -167,24 +167,163 @@ static double omega_of(double rho) {
   return 2.0 / (1.0 + std::sqrt(t));
 }
 
+// Eigen-decomposition of a symmetric n x n matrix (row-major) by cyclic
+// Jacobi rotations: on return a is diagonal (the eigenvalues) and the
+// columns of q are the eigenvectors.
+static void jacobi_eigen(std::vector<double>& a, std::vector<double>& q, int n) {
+  q.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) q[(size_t)i * n + i] = 1.0;
+  double scale = 0.0;
+  for (double v : a) scale += v * v;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int r = p + 1; r < n; ++r) off += a[(size_t)p * n + r] * a[(size_t)p * n + r];
+    if (off <= 1e-32 * scale) break;
+    for (int p = 0; p < n; ++p)
+      for (int r = p + 1; r < n; ++r) {
+        const double apr = a[(size_t)p * n + r];
+        if (apr == 0.0) continue;
+        const double th = (a[(size_t)r * n + r] - a[(size_t)p * n + p]) / (2.0 * apr);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, r
+          const double x = a[(size_t)k * n + p], y = a[(size_t)k * n + r];
+          a[(size_t)k * n + p] = c * x - sn * y;
+          a[(size_t)k * n + r] = sn * x + c * y;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, r
+          const double x = a[(size_t)p * n + k], y = a[(size_t)r * n + k];
+          a[(size_t)p * n + k] = c * x - sn * y;
+          a[(size_t)r * n + k] = sn * x + c * y;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double x = q[(size_t)k * n + p], y = q[(size_t)k * n + r];
+          q[(size_t)k * n + p] = c * x - sn * y;
+          q[(size_t)k * n + r] = sn * x + c * y;
+        }
+      }
+  }
+}
+
+// Fast diagonalisation of the level operator of every mode.  The operator
+// is L = A (x) I + diag(Rr) (x) B with A = tridiag(da, Ca, ua) along a and
+// B = tridiag(db, Cb, ub) along b.  B = D^-1 S D with D diagonal and S
+// symmetric; S = Q Lambda Q^T gives B = V Lambda V^-1 with V = D^-1 Q and
+// V^-1 = Q^T D, so L u = f becomes, with w = f V^-T row by row, the
+// tridiagonal systems (A + lambda_q diag(Rr)) x_q = w_q along a, one per
+// eigenvalue, and u = x V^T.  Stores V, V^-1 and the Thomas factors of
+// every (mode, q); checks the factors against the operator on random
+// right-hand sides and leaves the tables empty if they miss 1e-10 (the
+// coarsest level then falls back to red-black SOR).
+void separable_factors(LevelTables& T, int M) {
+  const int n1 = T.na, n2 = T.nb;
+  T.sep_v.clear(); T.sep_vi.clear(); T.sep_cp.clear(); T.sep_id.clear();
+  if (n2 > 128) return;  // the device row transforms take at most 128 columns
+  for (int j = 0; j + 1 < n2; ++j)
+    if (!(T.ub[j] > 0.0) || !(T.db[j + 1] > 0.0)) return;
+  std::vector<double> V((size_t)M * n2 * n2), Vi((size_t)M * n2 * n2), CP((size_t)M * n1 * n2), ID((size_t)M * n1 * n2);
+  std::vector<double> d(n2), S, Q, lam(n2);
+  for (int p = 0; p < M; ++p) {
+    const double* Ca = &T.Ca[(size_t)p * n1];
+    const double* Cb = &T.Cb[(size_t)p * n2];
+    d[0] = 1.0;
+    for (int j = 0; j + 1 < n2; ++j) d[j + 1] = d[j] * std::sqrt(T.ub[j] / T.db[j + 1]);
+    S.assign((size_t)n2 * n2, 0.0);
+    for (int j = 0; j < n2; ++j) {
+      S[(size_t)j * n2 + j] = Cb[j];
+      if (j + 1 < n2) S[(size_t)j * n2 + j + 1] = S[(size_t)(j + 1) * n2 + j] = std::sqrt(T.ub[j] * T.db[j + 1]);
+    }
+    jacobi_eigen(S, Q, n2);
+    for (int q = 0; q < n2; ++q) lam[q] = S[(size_t)q * n2 + q];
+    // stored transposed, so that consecutive outputs of a row transform read
+    // consecutive table entries: v[q][j] = V[j][q], vi[j][q] = V^-1[q][j]
+    double* v = &V[(size_t)p * n2 * n2];
+    double* vi = &Vi[(size_t)p * n2 * n2];
+    for (int j = 0; j < n2; ++j)
+      for (int q = 0; q < n2; ++q) {
+        v[(size_t)q * n2 + j] = Q[(size_t)j * n2 + q] / d[j];
+        vi[(size_t)j * n2 + q] = Q[(size_t)j * n2 + q] * d[j];
+      }
+    double* cp = &CP[(size_t)p * n1 * n2];
+    double* id = &ID[(size_t)p * n1 * n2];
+    for (int q = 0; q < n2; ++q) {
+      double prev = 0.0;
+      for (int i = 0; i < n1; ++i) {
+        const double den = Ca[i] + lam[q] * T.Rr[i] - (i > 0 ? T.da[i] * prev : 0.0);
+        if (!(std::fabs(den) > 0.0)) return;
+        id[(size_t)i * n2 + q] = 1.0 / den;
+        prev = T.ua[i] / den;
+        cp[(size_t)i * n2 + q] = prev;
+      }
+    }
+    // check: a random right-hand side solved and multiplied back
+    std::vector<double> f((size_t)n1 * n2), w((size_t)n1 * n2), u((size_t)n1 * n2);
+    unsigned long long st = 0x9E3779B97F4A7C15ull * (unsigned long long)(p + 1);
+    for (double& x : f) {
+      st = st * 6364136223846793005ull + 1442695040888963407ull;
+      x = (double)(st >> 11) / 9007199254740992.0 - 0.5;
+    }
+    for (int i = 0; i < n1; ++i)
+      for (int q = 0; q < n2; ++q) {
+        double acc = 0.0;
+        for (int j = 0; j < n2; ++j) acc += vi[(size_t)j * n2 + q] * f[(size_t)i * n2 + j];
+        w[(size_t)i * n2 + q] = acc;
+      }
+    for (int q = 0; q < n2; ++q) {
+      double prev = 0.0;
+      for (int i = 0; i < n1; ++i) {
+        prev = (w[(size_t)i * n2 + q] - (i > 0 ? T.da[i] * prev : 0.0)) * id[(size_t)i * n2 + q];
+        w[(size_t)i * n2 + q] = prev;
+      }
+      for (int i = n1 - 2; i >= 0; --i) w[(size_t)i * n2 + q] -= cp[(size_t)i * n2 + q] * w[(size_t)(i + 1) * n2 + q];
+    }
+    for (int i = 0; i < n1; ++i)
+      for (int j = 0; j < n2; ++j) {
+        double acc = 0.0;
+        for (int q = 0; q < n2; ++q) acc += v[(size_t)q * n2 + j] * w[(size_t)i * n2 + q];
+        u[(size_t)i * n2 + j] = acc;
+      }
+    double r2 = 0.0, f2 = 0.0;
+    for (int i = 0; i < n1; ++i)
+      for (int j = 0; j < n2; ++j) {
+        double Lu = (Ca[i] + T.Rr[i] * Cb[j]) * u[(size_t)i * n2 + j];
+        if (i + 1 < n1) Lu += T.ua[i] * u[(size_t)(i + 1) * n2 + j];
+        if (i > 0) Lu += T.da[i] * u[(size_t)(i - 1) * n2 + j];
+        if (j + 1 < n2) Lu += T.Rr[i] * T.ub[j] * u[(size_t)i * n2 + j + 1];
+        if (j > 0) Lu += T.Rr[i] * T.db[j] * u[(size_t)i * n2 + j - 1];
+        const double r = Lu - f[(size_t)i * n2 + j];
+        r2 += r * r;
+        f2 += f[(size_t)i * n2 + j] * f[(size_t)i * n2 + j];
+      }
+    if (!(r2 <= 1e-20 * f2)) return;
+  }
+  T.sep_v.swap(V);
+  T.sep_vi.swap(Vi);
+  T.sep_cp.swap(CP);
+  T.sep_id.swap(ID);
+}
+
 static double transfer_coord(const Spec& s, char which, double x) {
   return (which == 'a' && s.sph()) ? x * x : x;
 }
 
 Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, const int edge[4],
-                          const std::vector<int>& modes, bool main_grid) {
+                          const std::vector<int>& modes, bool main_grid, int max_coarse) {
   Hierarchy h;
   h.spec = s;
   h.M = (int)modes.size();
-  // level sizes: halve while the level has more than kMaxDirect cells (a
-  // level that small is the coarsest and is solved exactly), both sides are
+  // level sizes: halve while the level has more than max_coarse cells (a
+  // level that small is the coarsest and is solved exactly) -- but at least
+  // once, so that there is a coarse-grid correction -- while both sides are
   // even, the smaller coarse side stays >= 2 and the coarse inner radial
   // ghost face stays at r > 0.
+  if (max_coarse < 1) max_coarse = kMaxDirect;
   std::vector<std::pair<int, int>> sizes{{na, nb}};
   long stride = 1;
   while (true) {
     int ca = sizes.back().first, cb = sizes.back().second;
-    if (ca * cb <= kMaxDirect) break;
+    if (ca * cb <= max_coarse && sizes.size() > 1) break;
     if ((ca % 2) || (cb % 2) || std::min(ca, cb) / 2 < 2) break;
     if (s.radial_face((double)((a_lo - 1) - 2 * stride)) <= 0.0) break;
     sizes.push_back({ca / 2, cb / 2});
@@ -291,59 +430,10 @@ Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, c
     for (int i = 0; i < n1; ++i) T.va[i] = A.vol[i + 1] / sa;
     for (int j = 0; j < n2; ++j) T.vb[j] = B.vol[j + 1] / sb;
   }
-  // exact inverse of the coarsest operator for every mode (Gauss-Jordan with
-  // partial pivoting on the dense n x n matrix, n = na*nb <= kMaxDirect)
+  // exact solve of the coarsest level by fast diagonalisation
   {
     LevelTables& T = h.lv[L - 1];
-    const int n1 = T.na, n2 = T.nb, n = n1 * n2;
-    if (n <= kMaxDirect) {
-      T.cinv.assign((size_t)h.M * n * n, 0.0);
-      std::vector<double> A((size_t)n * n), I((size_t)n * n);
-      for (int p = 0; p < h.M; ++p) {
-        std::fill(A.begin(), A.end(), 0.0);
-        std::fill(I.begin(), I.end(), 0.0);
-        const double* Ca = &T.Ca[(size_t)p * n1];
-        const double* Cb = &T.Cb[(size_t)p * n2];
-        for (int i = 0; i < n1; ++i)
-          for (int j = 0; j < n2; ++j) {
-            const int k = i * n2 + j;
-            A[(size_t)k * n + k] = Ca[i] + T.Rr[i] * Cb[j];
-            if (i + 1 < n1) A[(size_t)k * n + k + n2] += T.ua[i];
-            if (i > 0) A[(size_t)k * n + k - n2] += T.da[i];
-            if (j + 1 < n2) A[(size_t)k * n + k + 1] += T.Rr[i] * T.ub[j];
-            if (j > 0) A[(size_t)k * n + k - 1] += T.Rr[i] * T.db[j];
-            I[(size_t)k * n + k] = 1.0;
-          }
-        for (int c = 0; c < n; ++c) {
-          int piv = c;
-          for (int r = c + 1; r < n; ++r)
-            if (std::fabs(A[(size_t)r * n + c]) > std::fabs(A[(size_t)piv * n + c])) piv = r;
-          if (piv != c)
-            for (int k = 0; k < n; ++k) {
-              std::swap(A[(size_t)c * n + k], A[(size_t)piv * n + k]);
-              std::swap(I[(size_t)c * n + k], I[(size_t)piv * n + k]);
-            }
-          const double d = 1.0 / A[(size_t)c * n + c];
-          for (int k = 0; k < n; ++k) {
-            A[(size_t)c * n + k] *= d;
-            I[(size_t)c * n + k] *= d;
-          }
-          for (int r = 0; r < n; ++r) {
-            if (r == c) continue;
-            const double fct = A[(size_t)r * n + c];
-            if (fct == 0.0) continue;
-            for (int k = 0; k < n; ++k) {
-              A[(size_t)r * n + k] -= fct * A[(size_t)c * n + k];
-              I[(size_t)r * n + k] -= fct * I[(size_t)c * n + k];
-            }
-          }
-        }
-        // stored transposed: cinv[p][l][k] = (A^-1)[k][l]
-        double* out = T.cinv.data() + (size_t)p * n * n;
-        for (int k = 0; k < n; ++k)
-          for (int l = 0; l < n; ++l) out[(size_t)l * n + k] = I[(size_t)k * n + l];
-      }
-    }
+    separable_factors(T, h.M);
   }
   // transfers between consecutive levels (bilinear in (r^2, theta) or (R, z);
   // restriction: the printed area weights read as opposite-corner weights)

@@ -159,6 +159,104 @@ __device__ __forceinline__ typename Vec<R>::T resid_lds(const LevelDev& L, const
                 fv.y - (c * uc.y + a1 * un.y + a2 * us.y + b1 * ue.y + b2 * uw.y));
 }
 
+// Exact solve of the coarsest level by fast diagonalisation, in place on f
+// ([na][nb] FP64 complex in LDS): rows w = f V^-T, then for every
+// eigenvalue q the tridiagonal system along a by the Thomas factors (one
+// lane per (q, real/imaginary part), the column held in registers in
+// chunks), then rows u = w V^T.  The eigenvector tables sit in LDS from the
+// start of the kernel (vt: V^T at [q][j], V^-T at [j][q] after it); the
+// Thomas factors are staged into LDS (fac) here, all loads in flight at once.
+constexpr int kSepChunk = 16;
+
+__device__ __forceinline__ void sep_rows(double2* x, int na, int nb, const double* M) {
+  // x[i][c] <- sum_r M[r][c] x[i][r] for every row i: a wave per row, lane c
+  // (c and c + 64 when nb > 64); the wave reads the whole row before it
+  // writes, so no other wave touches the row
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  const int c0 = min(lane, nb - 1), c1 = min(lane + 64, nb - 1);
+  for (int i = wave; i < na; i += nwave) {
+    double2* row = x + i * nb;
+    double ax0 = 0.0, ay0 = 0.0, ax1 = 0.0, ay1 = 0.0;
+#pragma unroll 8
+    for (int r = 0; r < nb; ++r) {
+      const double2 v = row[r];
+      const double m0 = M[r * nb + c0], m1 = M[r * nb + c1];
+      ax0 = fma(m0, v.x, ax0);
+      ay0 = fma(m0, v.y, ay0);
+      ax1 = fma(m1, v.x, ax1);
+      ay1 = fma(m1, v.y, ay1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < nb) row[lane] = make_double2(ax0, ay0);
+    if (lane + 64 < nb) row[lane + 64] = make_double2(ax1, ay1);
+  }
+}
+
+__device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<double>& T, int m, double2* f,
+                                                 const double* vt, double* fac) {
+  const int na = L.na, nb = L.nb, nn = na * nb;
+  {
+    const auto gcp = gbl(L.sep_cp + (size_t)m * nn), gid = gbl(L.sep_id + (size_t)m * nn);
+#pragma unroll 4
+    for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+      fac[t] = gcp[t];
+      fac[nn + t] = gid[t];
+    }
+  }
+  sep_rows(f, na, nb, vt + nb * nb);
+  __syncthreads();
+  // tridiagonal solves along a, one per (q, component)
+  const double* cp = fac;
+  const double* id = fac + nn;
+  double* w = reinterpret_cast<double*>(f);
+  for (int t = threadIdx.x; t < 2 * nb; t += blockDim.x) {
+    const int q = t % nb, comp = t / nb;
+    double prev = 0.0;
+    for (int i0 = 0; i0 < na; i0 += kSepChunk) {
+      double v[kSepChunk], pv[kSepChunk], dv[kSepChunk];
+#pragma unroll
+      for (int k = 0; k < kSepChunk; ++k) {
+        const int i = min(i0 + k, na - 1);
+        v[k] = w[2 * (i * nb + q) + comp];
+        pv[k] = id[i * nb + q];
+        dv[k] = T.da[i];
+      }
+#pragma unroll
+      for (int k = 0; k < kSepChunk; ++k) {
+        prev = (v[k] - (i0 + k > 0 ? dv[k] * prev : 0.0)) * pv[k];
+        v[k] = prev;
+      }
+#pragma unroll
+      for (int k = 0; k < kSepChunk; ++k)
+        if (i0 + k < na) w[2 * ((i0 + k) * nb + q) + comp] = v[k];
+    }
+    double next = 0.0;
+    for (int i1 = na - 1; i1 >= 0; i1 -= kSepChunk) {
+      double v[kSepChunk], cv[kSepChunk];
+#pragma unroll
+      for (int k = 0; k < kSepChunk; ++k) {
+        const int i = max(i1 - k, 0);
+        v[k] = w[2 * (i * nb + q) + comp];
+        cv[k] = cp[i * nb + q];
+      }
+#pragma unroll
+      for (int k = 0; k < kSepChunk; ++k) {
+        if (i1 - k < 0) break;
+        if (i1 - k < na - 1) v[k] -= cv[k] * next;
+        next = v[k];
+      }
+#pragma unroll
+      for (int k = 0; k < kSepChunk; ++k)
+        if (i1 - k >= 0) w[2 * ((i1 - k) * nb + q) + comp] = v[k];
+    }
+  }
+  __syncthreads();
+  sep_rows(f, na, nb, vt);
+  __syncthreads();
+}
+
 // Byte offsets of the fused cycle's LDS arrays: o[l] u of level l and
 // o[K + l] its f (l < cl, K = kMaxLdsLevels), o[2K + l] the tables of level
 // l (l <= cl), o[3K] the coarsest u (its f follows), o[3K + 1] the
@@ -167,7 +265,7 @@ __device__ __forceinline__ typename Vec<R>::T resid_lds(const LevelDev& L, const
 // [region A] [scratch] [tables], where region A holds level 0's f while
 // level 0 is smoothed and [coarsest u, f] [levels 1..cl-1: u, f] between
 // the restriction from level 0 and the prolongation to it.
-constexpr int kLayoutSlots = 3 * kMaxLdsLevels + 3;
+constexpr int kLayoutSlots = 3 * kMaxLdsLevels + 5;
 template <typename R>
 __host__ __device__ inline void lds_layout(const LdsLevels& LL, int* o) {
   using V = typename Vec<R>::T;
@@ -176,7 +274,12 @@ __host__ __device__ inline void lds_layout(const LdsLevels& LL, int* o) {
   auto al = [](int x) { return (x + 15) & ~15; };
   auto ub = [&](int l) { return (int)sizeof(V) * (LL.L[l].na + 2) * lvl_us(LL.L[l].nb); };
   auto fb = [&](int l) { return (int)sizeof(V) * LL.L[l].na * lvl_fs(LL.L[l].nb); };
-  const int cb = (int)sizeof(double2) * ((LL.L[cl].na + 2) * (LL.L[cl].nb + 2) + LL.L[cl].na * LL.L[cl].nb);
+  const bool sep = LL.L[cl].sep_v != nullptr;
+  const int nac = LL.L[cl].na, nbc = LL.L[cl].nb;
+  // coarsest block: [u padded (SOR fallback)] f, then (exact solve) the
+  // staged Thomas factors of the level, 2 na nb doubles
+  const int cbf = al((int)sizeof(double2) * ((sep ? 0 : (nac + 2) * (nbc + 2)) + nac * nbc));
+  const int cb = cbf + (sep ? al((int)sizeof(double) * 2 * nac * nbc) : 0);
   int q = 0;
   if (LL.alias && cl > 0) {
     o[0] = 0;
@@ -202,10 +305,13 @@ __host__ __device__ inline void lds_layout(const LdsLevels& LL, int* o) {
       q = al(q + fb(l));
     }
   }
+  o[3 * K + 4] = o[3 * K] + cbf;  // staged Thomas factors of the exact coarse solve
   o[3 * K + 1] = q;
   q = al(q + (int)sizeof(R) * LL.scratch);
   o[2 * K + cl] = q;  // coarsest tables (double)
   q = al(q + (int)sizeof(double) * (5 * LL.L[cl].na + 4 * LL.L[cl].nb));
+  o[3 * K + 3] = q;   // staged eigenvector tables (V^T, V^-T) of the exact coarse solve
+  q = al(q + (sep ? (int)sizeof(double) * 2 * nbc * nbc : 0));
   for (int l = 0; l < cl; ++l) {
     o[2 * K + l] = q;
     q = al(q + (int)sizeof(R) * (5 * LL.L[l].na + 4 * LL.L[l].nb));
@@ -240,8 +346,10 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
   __shared__ int s_off[kLayoutSlots];
   if (threadIdx.x == 0) lds_layout<R>(LL, s_off);
   __syncthreads();
+  // coarsest arrays: f (and, for the SOR fallback, the padded u before it)
+  const bool sep = LC.sep_v != nullptr;
   double2* uC = reinterpret_cast<double2*>(smem + s_off[3 * kMaxLdsLevels]);
-  double2* fC = uC + (LC.na + 2) * (LC.nb + 2);
+  double2* fC = sep ? uC : uC + (LC.na + 2) * (LC.nb + 2);
   auto Ul = [&](int l) { return reinterpret_cast<V*>(smem + s_off[l]); };
   auto Fl = [&](int l) { return reinterpret_cast<V*>(smem + s_off[kMaxLdsLevels + l]); };
   auto Tl = [&](int l) {
@@ -249,6 +357,16 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
   };
   R* cp = reinterpret_cast<R*>(smem + s_off[3 * kMaxLdsLevels + 1]);
   Tab<double> tabC = stage_tab<double>(LC, m, reinterpret_cast<double*>(smem + s_off[2 * kMaxLdsLevels + cl]));
+  double* sepV = reinterpret_cast<double*>(smem + s_off[3 * kMaxLdsLevels + 3]);
+  if (sep) {
+    const int nn = LC.nb * LC.nb;
+    const auto gv = gbl(LC.sep_v + (size_t)m * nn), gvi = gbl(LC.sep_vi + (size_t)m * nn);
+#pragma unroll 4
+    for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+      sepV[t] = gv[t];
+      sepV[nn + t] = gvi[t];
+    }
+  }
   for (int l = 0; l < cl; ++l) (void)stage_tab<R>(LL.L[l], m, reinterpret_cast<R*>(smem + s_off[2 * kMaxLdsLevels + l]));
   // level 0 of the fused range: load f (and u for a full in-LDS cycle)
   {
@@ -314,93 +432,62 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
         acc[k] = t < C.na * C.nb ? restrict_at(t) : mkv<R>(0, 0);
       }
       __syncthreads();
-      for (int t = threadIdx.x; t < (C.na + 2) * ncc; t += blockDim.x) {
-        if (l + 1 == cl) uC[t] = make_double2(0.0, 0.0);
-        else Ul(l + 1)[t] = mkv<R>(0, 0);
-      }
+      if (l + 1 < cl)
+        for (int t = threadIdx.x; t < (C.na + 2) * ncc; t += blockDim.x) Ul(l + 1)[t] = mkv<R>(0, 0);
 #pragma unroll
       for (int k = 0; k < kAliasCells; ++k) {
         const int t = threadIdx.x + k * blockDim.x;
         if (t < C.na * C.nb) put_f(t, acc[k]);
       }
     } else {
-      for (int t = threadIdx.x; t < (C.na + 2) * ncc; t += blockDim.x) {
-        if (l + 1 == cl) uC[t] = make_double2(0.0, 0.0);
-        else Ul(l + 1)[t] = mkv<R>(0, 0);
-      }
+      if (l + 1 < cl)
+        for (int t = threadIdx.x; t < (C.na + 2) * ncc; t += blockDim.x) Ul(l + 1)[t] = mkv<R>(0, 0);
       for (int t = threadIdx.x; t < C.na * C.nb; t += blockDim.x) put_f(t, restrict_at(t));
     }
     __syncthreads();
   }
-  // coarsest level in FP64: the precomputed inverse when the level is small
-  // (an exact solve), otherwise red-black SOR from zero until the residual
-  // 2-norm dropped by rtol (Sec. 3.3)
-  {
+  // coarsest level in FP64, solved exactly by fast diagonalisation when its
+  // factors exist (the solution replaces f in place), otherwise by red-black
+  // SOR from zero until the residual 2-norm dropped by rtol (Sec. 3.3)
+  if (sep) {
+    coarse_separable(LC, tabC, m, fC, sepV, reinterpret_cast<double*>(smem + s_off[3 * kMaxLdsLevels + 4]));
+  } else {
     const LevelDev& L = LC;
     const Tab<double>& T = tabC;
     const int na = L.na, nb = L.nb, nc = nb + 2;
     for (int t = threadIdx.x; t < (na + 2) * nc; t += blockDim.x) uC[t] = make_double2(0.0, 0.0);
     __syncthreads();
-    if (L.cinv) {
-      // u = A^-1 f with the inverse stored transposed ([l][k], k fastest):
-      // a wave takes 16 rows k at a time, lane (kk, l4) sums the columns
-      // l = l4 (mod 4) of row kb + kk, so each load instruction reads four
-      // runs of 16 consecutive doubles; two shuffles add the four parts.
-      const int nn = na * nb;
-      const auto At = gbl(L.cinv + (size_t)m * nn * nn);
-      const int lane = threadIdx.x & 63, kk = lane >> 2, l4 = lane & 3;
-      for (int kb = (threadIdx.x >> 6) * 16; kb < nn; kb += (blockDim.x >> 6) * 16) {
-        const int k = kb + kk;
-        double sx = 0.0, sy = 0.0;
-        if (k < nn)
-#pragma unroll 8
-          for (int l = l4; l < nn; l += 4) {
-            const double a = At[(size_t)l * nn + k];
-            sx = fma(a, fC[l].x, sx);
-            sy = fma(a, fC[l].y, sy);
-          }
-        sx += __shfl_xor(sx, 1);
-        sy += __shfl_xor(sy, 1);
-        sx += __shfl_xor(sx, 2);
-        sy += __shfl_xor(sy, 2);
-        if (k < nn && l4 == 0) {
-          const int i = k / nb, j = k - i * nb;
-          uC[(i + 1) * nc + (j + 1)] = make_double2(sx, sy);
-        }
-      }
-    } else {
-      double f2 = 0.0;
-      for (int t = threadIdx.x; t < na * nb; t += blockDim.x) f2 += fC[t].x * fC[t].x + fC[t].y * fC[t].y;
-      f2 = red.sum(f2);
-      const double w = gbl(L.wc)[m];
-      if (f2 > 0.0) {
-        for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-          for (int colour = 0; colour < 2; ++colour) {
-            for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
-              const int i = t / nb, j = t - i * nb;
-              if (((i + j) & 1) != colour) continue;
-              const int qq = (i + 1) * nc + (j + 1);
-              const double Rr = T.Rr[i];
-              const double c = T.Ca[i] + Rr * T.Cb[j];
-              const double a1 = T.ua[i], a2 = T.da[i], b1 = Rr * T.ub[j], b2 = Rr * T.db[j];
-              const double2 un = uC[qq + nc], us = uC[qq - nc], ue = uC[qq + 1], uw = uC[qq - 1];
-              const double2 fv = fC[t];
-              const double tx = (fv.x - (a1 * un.x + a2 * us.x + b1 * ue.x + b2 * uw.x)) / c;
-              const double ty = (fv.y - (a1 * un.y + a2 * us.y + b1 * ue.y + b2 * uw.y)) / c;
-              const double2 old = uC[qq];
-              uC[qq] = make_double2(old.x + w * (tx - old.x), old.y + w * (ty - old.y));
-            }
-            __syncthreads();
-          }
-          double r2 = 0.0;
+    double f2 = 0.0;
+    for (int t = threadIdx.x; t < na * nb; t += blockDim.x) f2 += fC[t].x * fC[t].x + fC[t].y * fC[t].y;
+    f2 = red.sum(f2);
+    const double w = gbl(L.wc)[m];
+    if (f2 > 0.0) {
+      for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        for (int colour = 0; colour < 2; ++colour) {
           for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
             const int i = t / nb, j = t - i * nb;
-            const double2 r = resid_lds<double>(L, T, uC, fC, i, j, nb + 2, nb);
-            r2 += r.x * r.x + r.y * r.y;
+            if (((i + j) & 1) != colour) continue;
+            const int qq = (i + 1) * nc + (j + 1);
+            const double Rr = T.Rr[i];
+            const double c = T.Ca[i] + Rr * T.Cb[j];
+            const double a1 = T.ua[i], a2 = T.da[i], b1 = Rr * T.ub[j], b2 = Rr * T.db[j];
+            const double2 un = uC[qq + nc], us = uC[qq - nc], ue = uC[qq + 1], uw = uC[qq - 1];
+            const double2 fv = fC[t];
+            const double tx = (fv.x - (a1 * un.x + a2 * us.x + b1 * ue.x + b2 * uw.x)) / c;
+            const double ty = (fv.y - (a1 * un.y + a2 * us.y + b1 * ue.y + b2 * uw.y)) / c;
+            const double2 old = uC[qq];
+            uC[qq] = make_double2(old.x + w * (tx - old.x), old.y + w * (ty - old.y));
           }
-          r2 = red.sum(r2);
-          if (r2 <= rtol * rtol * f2) break;
+          __syncthreads();
         }
+        double r2 = 0.0;
+        for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
+          const int i = t / nb, j = t - i * nb;
+          const double2 r = resid_lds<double>(L, T, uC, fC, i, j, nb + 2, nb);
+          r2 += r.x * r.x + r.y * r.y;
+        }
+        r2 = red.sum(r2);
+        if (r2 <= rtol * rtol * f2) break;
       }
     }
     __syncthreads();
@@ -423,8 +510,13 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
       const R wb0 = (R)gbl(L.pb_w0)[par * nb + j], wb1 = (R)gbl(L.pb_w1)[par * nb + j];
       R e00x, e00y, e01x, e01y, e10x, e10y, e11x, e11y;
       if (l + 1 == cl) {
-        const double2 a = uC[(a0 + 1) * ncc + b0 + 1], b = uC[(a0 + 1) * ncc + b1 + 1];
-        const double2 c = uC[(a1 + 1) * ncc + b0 + 1], d = uC[(a1 + 1) * ncc + b1 + 1];
+        // the coarsest solution: padded u (SOR) or, unpadded, in f (exact
+        // solve; ghost neighbours read as zero)
+        auto cv = [&](int ia, int jb) {
+          if (!sep) return uC[(ia + 1) * ncc + jb + 1];
+          return (ia >= 0 && ia < C.na && jb >= 0 && jb < C.nb) ? fC[ia * C.nb + jb] : make_double2(0.0, 0.0);
+        };
+        const double2 a = cv(a0, b0), b = cv(a0, b1), c = cv(a1, b0), d = cv(a1, b1);
         e00x = (R)a.x; e00y = (R)a.y; e01x = (R)b.x; e01y = (R)b.y;
         e10x = (R)c.x; e10y = (R)c.y; e11x = (R)d.x; e11y = (R)d.y;
       } else {
@@ -464,7 +556,7 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
       if (n > 1) {
         Ug[off + t] = Ul(0)[(i + 1) * nc + (j + 1)];
       } else {
-        const double2 v = uC[(i + 1) * nc + (j + 1)];
+        const double2 v = sep ? fC[t] : uC[(i + 1) * nc + (j + 1)];
         Ug[off + t] = mkv<R>((R)v.x, (R)v.y);
       }
     }

@@ -58,7 +58,11 @@ struct LevelTables {
   std::vector<double> Ca, Cb;   // [M][na], [M][nb]; diag c = Ca[i] + Rr[i] * Cb[j]
   std::vector<double> wr, wb;   // [M][nb] radial-line omega, [M][na] polar-line omega
   std::vector<double> wc;       // [M] coarsest red-black omega
-  std::vector<double> cinv;     // [M][n][n] inverse of the coarsest operator, transposed ([l][k]; n = na*nb <= kMaxDirect), else empty
+  // coarsest level: fast-diagonalisation factors per mode (else empty)
+  std::vector<double> sep_v;    // [M][nb][nb] at [q][j]: V[j][q], eigenvectors of the b operator
+  std::vector<double> sep_vi;   // [M][nb][nb] at [j][q]: V^-1[q][j]
+  std::vector<double> sep_cp;   // [M][na][nb] Thomas upper factor of (A + lambda_q Rr) at [i][q]
+  std::vector<double> sep_id;   // [M][na][nb] inverse pivots, [i][q]
   std::vector<double> va, vb;   // normalised volume weights (sum_ij va_i vb_j = 1)
   // restriction to the next coarser level: [nc][2]
   std::vector<double> rwa, rwb;
@@ -80,8 +84,11 @@ struct Hierarchy {
 // [b_lo, b_lo + nb - 1] (global fine indices) with the given edge kinds.
 // `modes` is the list of azimuthal indices tables are built for (index into
 // the per-mode tables = position in the list).
+void separable_factors(LevelTables& T, int M);
+// max_coarse: coarsening stops at the first level with at most this many
+// cells (after at least one halving); 0 takes kMaxDirect.
 Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, const int edge[4],
-                          const std::vector<int>& modes, bool main_grid);
+                          const std::vector<int>& modes, bool main_grid, int max_coarse = 0);
 
 // Coarsest levels up to this many cells are solved with a precomputed
 // inverse instead of red-black SOR.
@@ -122,7 +129,7 @@ struct LevelDev {
   const double *pa_w0, *pa_w1;
   const int *pb_i0, *pb_i1;  // [2][nb]
   const double *pb_w0, *pb_w1;
-  const double* cinv;        // [M][na*nb][na*nb] coarsest inverse, transposed, or nullptr
+  const double *sep_v, *sep_vi, *sep_cp, *sep_id;  // coarsest fast-diagonalisation factors, or nullptr
 };
 
 // The levels that one block per plane processes entirely in LDS (the

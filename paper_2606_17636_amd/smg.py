@@ -43,7 +43,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
                 ("n_sor", ctypes.c_int), ("max_cycles", ctypes.c_int), ("dgf_method", ctypes.c_int),
                 ("n_pad", ctypes.c_int), ("dgf_tol", ctypes.c_double), ("line_solver", ctypes.c_int),
-                ("launch", ctypes.c_int), ("autotune", ctypes.c_int)]
+                ("launch", ctypes.c_int), ("autotune", ctypes.c_int), ("coarse_cells", ctypes.c_int)]
 
 
 _PI = ctypes.POINTER(ctypes.c_int)
@@ -163,7 +163,7 @@ class Plan:
 
     def __init__(self, geometry, radial, n_a, n_b, n_phi, a_min, a_max, b_min, b_max, G=1.0, precision=FP64,
                  nu_pre=2, nu_post=2, n_sor=2, max_cycles=60, dgf_method=DGF_AUTO, n_pad=16, dgf_tol=1e-13,
-                 line_solver=LINE_SOR, launch=LAUNCH_GRAPH, autotune=False):
+                 line_solver=LINE_SOR, launch=LAUNCH_GRAPH, autotune=False, coarse_cells=0):
         lib = load()
         geo = {"spherical": SPHERICAL, "cylindrical": CYLINDRICAL}.get(geometry, geometry)
         rad = {"uniform": UNIFORM, "log": LOG}.get(radial, radial)
@@ -172,7 +172,7 @@ class Plan:
         ls = {"sor": LINE_SOR, "exact": LINE_EXACT}.get(line_solver, line_solver)
         lc = {"graph": LAUNCH_GRAPH, "dynamic": LAUNCH_DYNAMIC}.get(launch, launch)
         self.opts = Opts(prec, nu_pre, nu_post, n_sor, max_cycles, dgf_method, n_pad, dgf_tol, ls, lc,
-                         1 if autotune else 0)
+                         1 if autotune else 0, coarse_cells)
         self.line_solver = ls
         self._h = ctypes.c_void_p()
         _check(lib.smg_plan_create(ctypes.byref(self.grid), ctypes.byref(self.opts), ctypes.byref(self._h)))

@@ -240,3 +240,22 @@ def test_full_solve_mixed(key):
     phi, info = gp.solve(_dev(rho), tol=1e-12)
     assert info["converged"]
     assert _l2(spec, phi.cpu().numpy(), ref) < 1e-10
+
+
+@pytest.mark.parametrize("key", ["sph-log", "cyl-uni", "cyl-log"])
+def test_vcycle_exact_coarse_level(key):
+    """A deeper coarsest level (at most 512 cells), solved exactly by fast
+    diagonalisation on the GPU and to convergence by red-black SOR in the
+    oracle of the same hierarchy."""
+    from paper_2606_17636_amd import smg
+    spec, npad = SPECS[key]
+    gp = smg.grid_from_spec(spec, n_pad=npad, coarse_cells=512).setup()
+    h = Hierarchy(spec, max_coarsest=512)
+    assert gp.level_shapes == h.sizes
+    f = _random_modes(spec, 17)
+    u = np.zeros_like(f)
+    ud = _dev(u)
+    gp.mg_vcycle(_dev(f), ud)
+    for m in range(spec.n_modes):
+        h.vcycle(u[m], f[m], m)
+    assert _rel(ud.cpu().numpy(), u) < 1e-9

@@ -75,3 +75,16 @@ def test_batch_create_validates_plans():
         smg.Batch([a, c])
     with pytest.raises(smg.SmgError, match="twice"):
         smg.Batch([a, a])
+
+
+@pytest.mark.parametrize("cells", [16, 512, 2048])
+def test_coarsening_depth_matches_oracle(cells):
+    spec = SPECS[0]
+    plan = smg.grid_from_spec(spec, n_pad=8, coarse_cells=cells)
+    assert plan.level_shapes == level_sizes(spec, cells)
+    assert len(plan.level_shapes) >= 2
+
+
+def test_coarse_cells_is_validated():
+    with pytest.raises(smg.SmgError, match="coarse_cells"):
+        smg.grid_from_spec(SPECS[0], n_pad=8, coarse_cells=5)
