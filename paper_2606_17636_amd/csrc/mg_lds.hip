@@ -166,31 +166,43 @@ __device__ __forceinline__ typename Vec<R>::T resid_lds(const LevelDev& L, const
 // chunks), then rows u = w V^T.  The eigenvector tables sit in LDS from the
 // start of the kernel (vt: V^T at [q][j], V^-T at [j][q] after it); the
 // Thomas factors are staged into LDS (fac) here, all loads in flight at once.
-constexpr int kSepChunk = 16;
+constexpr int kSepChunk = 8;
+// Segments per tridiagonal system in the exact coarse solve: a function of
+// the level's width only (not of the block size), so that every launch shape
+// rounds alike; about 512 (system, segment) pairs, at most 16 segments.
+__host__ __device__ constexpr int sep_seg_max(int nb) { return nb >= 256 ? 1 : (nb >= 16 ? 256 / nb : 16); }
 
 __device__ __forceinline__ void sep_rows(double2* x, int na, int nb, const double* M) {
-  // x[i][c] <- sum_r M[r][c] x[i][r] for every row i: a wave per row, lane c
-  // (c and c + 64 when nb > 64); the wave reads the whole row before it
-  // writes, so no other wave touches the row
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-  const int c0 = min(lane, nb - 1), c1 = min(lane + 64, nb - 1);
-  for (int i = wave; i < na; i += nwave) {
+  // x[i][c] <- sum_r M[r][c] x[i][r] for every row i.  ng threads share a
+  // row (ng a power of two with 4 ng >= nb, so a row's threads sit in one
+  // wave), thread g computing the columns c = g + ng k, k < 4; the wave reads
+  // the whole row before it writes, so no other wave touches the row.
+  int ng = 1;
+  while (4 * ng < nb) ng *= 2;
+  for (int t = threadIdx.x; t < na * ng; t += blockDim.x) {
+    const int i = t / ng, g = t - i * ng;
     double2* row = x + i * nb;
-    double ax0 = 0.0, ay0 = 0.0, ax1 = 0.0, ay1 = 0.0;
-#pragma unroll 8
+    int c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = min(g + ng * k, nb - 1);
+    double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
     for (int r = 0; r < nb; ++r) {
       const double2 v = row[r];
-      const double m0 = M[r * nb + c0], m1 = M[r * nb + c1];
-      ax0 = fma(m0, v.x, ax0);
-      ay0 = fma(m0, v.y, ay0);
-      ax1 = fma(m1, v.x, ax1);
-      ay1 = fma(m1, v.y, ay1);
+      const double* mr = M + r * nb;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double mv = mr[c[k]];
+        ax[k] = fma(mv, v.x, ax[k]);
+        ay[k] = fma(mv, v.y, ay[k]);
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane < nb) row[lane] = make_double2(ax0, ay0);
-    if (lane + 64 < nb) row[lane + 64] = make_double2(ax1, ay1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (g + ng * k < nb) row[g + ng * k] = make_double2(ax[k], ay[k]);
   }
 }
 
@@ -207,49 +219,142 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
   }
   sep_rows(f, na, nb, vt + nb * nb);
   __syncthreads();
-  // tridiagonal solves along a, one per (q, component)
+  // Tridiagonal solves along a, one per (q, component): the forward sweep
+  // y_i = id_i w_i - id_i da_i y_{i-1} and the back substitution
+  // x_i = y_i - cp_i x_{i+1} are first-order linear recurrences.  Each
+  // system's rows are cut into S segments; a thread solves its segment from
+  // a zero carry while it multiplies up the recurrence coefficients, then,
+  // after a barrier, takes the true value entering its segment from the
+  // segment ends before it and adds carry * (coefficient product) to its
+  // rows.  Lanes run over l = 2 q + component, so row i of every system is
+  // the contiguous run w[2 i nb + l].
   const double* cp = fac;
   const double* id = fac + nn;
   double* w = reinterpret_cast<double*>(f);
-  for (int t = threadIdx.x; t < 2 * nb; t += blockDim.x) {
-    const int q = t % nb, comp = t / nb;
-    double prev = 0.0;
-    for (int i0 = 0; i0 < na; i0 += kSepChunk) {
+  const int nsys = 2 * nb;
+  int S = min(sep_seg_max(nb), na);
+  const int len = (na + S - 1) / S;
+  S = (na + len - 1) / len;
+  double* pend = fac + 2 * nn;     // [S][nb] coefficient product of a segment
+  double* eend = pend + S * nb;    // [S][2 nb] local value at the segment's far end
+  // forward sweep, local part
+  for (int t = threadIdx.x; t < nsys * S; t += blockDim.x) {
+    const int l = t % nsys, sg = t / nsys, q = l >> 1;
+    const int beg = sg * len, end = min(na, beg + len);
+    double y = 0.0, P = 1.0;
+    for (int i0 = beg; i0 < end; i0 += kSepChunk) {
       double v[kSepChunk], pv[kSepChunk], dv[kSepChunk];
 #pragma unroll
       for (int k = 0; k < kSepChunk; ++k) {
-        const int i = min(i0 + k, na - 1);
-        v[k] = w[2 * (i * nb + q) + comp];
+        const int i = min(i0 + k, end - 1);
+        v[k] = w[2 * i * nb + l];
         pv[k] = id[i * nb + q];
-        dv[k] = T.da[i];
+        dv[k] = i > 0 ? T.da[i] : 0.0;
       }
 #pragma unroll
       for (int k = 0; k < kSepChunk; ++k) {
-        prev = (v[k] - (i0 + k > 0 ? dv[k] * prev : 0.0)) * pv[k];
-        v[k] = prev;
+        const double a = v[k] * pv[k], b = -dv[k] * pv[k];
+        if (i0 + k < end) {
+          y = fma(b, y, a);
+          P *= b;
+        }
+        v[k] = y;
       }
 #pragma unroll
       for (int k = 0; k < kSepChunk; ++k)
-        if (i0 + k < na) w[2 * ((i0 + k) * nb + q) + comp] = v[k];
+        if (i0 + k < end) w[2 * (i0 + k) * nb + l] = v[k];
     }
-    double next = 0.0;
-    for (int i1 = na - 1; i1 >= 0; i1 -= kSepChunk) {
+    if (S > 1) {
+      if ((l & 1) == 0) pend[sg * nb + q] = P;
+      eend[sg * nsys + l] = y;
+    }
+  }
+  if (S > 1) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < nsys * S; t += blockDim.x) {
+      const int l = t % nsys, sg = t / nsys, q = l >> 1;
+      if (sg == 0) continue;
+      double c = 0.0;
+      for (int s2 = 0; s2 < sg; ++s2) c = fma(pend[s2 * nb + q], c, eend[s2 * nsys + l]);
+      const int beg = sg * len, end = min(na, beg + len);
+      double P = 1.0;
+      for (int i0 = beg; i0 < end; i0 += kSepChunk) {
+        double v[kSepChunk], pv[kSepChunk], dv[kSepChunk];
+#pragma unroll
+        for (int k = 0; k < kSepChunk; ++k) {
+          const int i = min(i0 + k, end - 1);
+          v[k] = w[2 * i * nb + l];
+          pv[k] = id[i * nb + q];
+          dv[k] = T.da[i];
+        }
+#pragma unroll
+        for (int k = 0; k < kSepChunk; ++k) {
+          P *= -dv[k] * pv[k];
+          v[k] = fma(P, c, v[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < kSepChunk; ++k)
+          if (i0 + k < end) w[2 * (i0 + k) * nb + l] = v[k];
+      }
+    }
+  }
+  __syncthreads();
+  // back substitution, local part
+  for (int t = threadIdx.x; t < nsys * S; t += blockDim.x) {
+    const int l = t % nsys, sg = t / nsys, q = l >> 1;
+    const int beg = sg * len, end = min(na, beg + len);
+    double x = 0.0, Q = 1.0;
+    for (int i1 = end - 1; i1 >= beg; i1 -= kSepChunk) {
       double v[kSepChunk], cv[kSepChunk];
 #pragma unroll
       for (int k = 0; k < kSepChunk; ++k) {
-        const int i = max(i1 - k, 0);
-        v[k] = w[2 * (i * nb + q) + comp];
-        cv[k] = cp[i * nb + q];
+        const int i = max(i1 - k, beg);
+        v[k] = w[2 * i * nb + l];
+        cv[k] = i < na - 1 ? cp[i * nb + q] : 0.0;
       }
 #pragma unroll
       for (int k = 0; k < kSepChunk; ++k) {
-        if (i1 - k < 0) break;
-        if (i1 - k < na - 1) v[k] -= cv[k] * next;
-        next = v[k];
+        if (i1 - k >= beg) {
+          x = fma(-cv[k], x, v[k]);
+          Q *= -cv[k];
+        }
+        v[k] = x;
       }
 #pragma unroll
       for (int k = 0; k < kSepChunk; ++k)
-        if (i1 - k >= 0) w[2 * ((i1 - k) * nb + q) + comp] = v[k];
+        if (i1 - k >= beg) w[2 * (i1 - k) * nb + l] = v[k];
+    }
+    if (S > 1) {
+      if ((l & 1) == 0) pend[sg * nb + q] = Q;
+      eend[sg * nsys + l] = x;
+    }
+  }
+  if (S > 1) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < nsys * S; t += blockDim.x) {
+      const int l = t % nsys, sg = t / nsys, q = l >> 1;
+      if (sg == S - 1) continue;
+      double c = 0.0;
+      for (int s2 = S - 1; s2 > sg; --s2) c = fma(pend[s2 * nb + q], c, eend[s2 * nsys + l]);
+      const int beg = sg * len, end = min(na, beg + len);
+      double Q = 1.0;
+      for (int i1 = end - 1; i1 >= beg; i1 -= kSepChunk) {
+        double v[kSepChunk], cv[kSepChunk];
+#pragma unroll
+        for (int k = 0; k < kSepChunk; ++k) {
+          const int i = max(i1 - k, beg);
+          v[k] = w[2 * i * nb + l];
+          cv[k] = cp[i * nb + q];
+        }
+#pragma unroll
+        for (int k = 0; k < kSepChunk; ++k) {
+          Q *= -cv[k];
+          v[k] = fma(Q, c, v[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < kSepChunk; ++k)
+          if (i1 - k >= beg) w[2 * (i1 - k) * nb + l] = v[k];
+      }
     }
   }
   __syncthreads();
@@ -277,9 +382,10 @@ __host__ __device__ inline void lds_layout(const LdsLevels& LL, int* o) {
   const bool sep = LL.L[cl].sep_v != nullptr;
   const int nac = LL.L[cl].na, nbc = LL.L[cl].nb;
   // coarsest block: [u padded (SOR fallback)] f, then (exact solve) the
-  // staged Thomas factors of the level, 2 na nb doubles
+  // staged Thomas factors of the level, 2 na nb doubles, and the segment-end
+  // scratch of the tridiagonal solves
   const int cbf = al((int)sizeof(double2) * ((sep ? 0 : (nac + 2) * (nbc + 2)) + nac * nbc));
-  const int cb = cbf + (sep ? al((int)sizeof(double) * 2 * nac * nbc) : 0);
+  const int cb = cbf + (sep ? al((int)sizeof(double) * (2 * nac * nbc + 3 * sep_seg_max(nbc) * nbc)) : 0);
   int q = 0;
   if (LL.alias && cl > 0) {
     o[0] = 0;
@@ -388,7 +494,11 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
         Fl(0)[i * fs + j] = Fg[off + t];
       }
     } else {
-      for (int t = threadIdx.x; t < na * nb; t += blockDim.x) fC[t] = make_double2(Fg[off + t].x, Fg[off + t].y);
+#pragma unroll 4
+      for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
+        const V v = Fg[off + t];
+        fC[t] = make_double2(v.x, v.y);
+      }
     }
   }
   __syncthreads();
