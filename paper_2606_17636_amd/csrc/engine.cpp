@@ -271,19 +271,25 @@ smg_status Engine::vcycle(int target, int c, const BatchRef& b, hipStream_t st) 
     }
     return s;
   };
-  auto smooth = [&](int d) -> hipError_t {
+  // one smoothing step at depth d; with prolong set its first launch also
+  // applies the coarse-grid correction (reads the coarse correction too)
+  auto smooth = [&](int d, bool prolong) -> hipError_t {
     for (int dir = 0; dir < 2; ++dir) {
+      const bool pr = prolong && dir == 0;
       const int ev = prof_ ? prof_->mark(st) : -1;
-      hipError_t e = smgk::mg_smooth_dir(dl + (size_t)d * P, hl + (size_t)d * P, P, b, prm_.n_sor, prm_.exact, dir, f32, st);
+      hipError_t e =
+          smgk::mg_smooth_dir(dl + (size_t)d * P, hl + (size_t)d * P, P, b, prm_.n_sor, prm_.exact, dir, f32, st, pr);
       if (e != hipSuccess) return e;
-      if (prof_) prof_->close(d == 0 ? (dir == 0 ? EC_SMOOTH_R0 : EC_SMOOTH_P0) : EC_SMOOTH_C, ev, 3.0 * vb * cells(d, false), st);
+      if (prof_)
+        prof_->close(d == 0 ? (dir == 0 ? EC_SMOOTH_R0 : EC_SMOOTH_P0) : EC_SMOOTH_C, ev,
+                     (pr ? 3.25 : 3.0) * vb * cells(d, false), st);
     }
     return hipSuccess;
   };
   hipError_t e = hipSuccess;
   for (int d = 0; d < D; ++d) {
     for (int k = 0; k < prm_.nu_pre; ++k)
-      if ((e = smooth(d)) != hipSuccess) return SMG_EHIP;
+      if ((e = smooth(d, false)) != hipSuccess) return SMG_EHIP;
     const int ev = prof_ ? prof_->mark(st) : -1;
     if ((e = smgk::mg_restrict(dl + (size_t)d * P, hl + (size_t)d * P, P, b, f32, st)) != hipSuccess) return SMG_EHIP;
     if (prof_) prof_->close(EC_RESTRICT, ev, (2.0 * vb + 0.5 * vb) * cells(d, false), st);
@@ -300,11 +306,21 @@ smg_status Engine::vcycle(int target, int c, const BatchRef& b, hipStream_t st) 
     }
   }
   for (int d = D - 1; d >= 0; --d) {
-    const int ev = prof_ ? prof_->mark(st) : -1;
-    if ((e = smgk::mg_prolong(dl + (size_t)d * P, hl + (size_t)d * P, P, b, f32, st)) != hipSuccess) return SMG_EHIP;
-    if (prof_) prof_->close(EC_PROLONG, ev, (2.0 * vb + 0.25 * vb) * cells(d, false), st);
+    // the first post-smoothing launch applies the coarse correction itself
+    // where its tiles own at least 8 lines (so that the halo lines, which it
+    // interpolates too, are at most half the tile); else a prolongation pass
+    bool fuse = prm_.nu_post > 0;
+    for (int q = 0; q < P; ++q) {
+      const LvJob& J = hl[(size_t)d * P + q];
+      if (J.active && J.tile[0] < 8) fuse = false;
+    }
+    if (!fuse) {
+      const int ev = prof_ ? prof_->mark(st) : -1;
+      if ((e = smgk::mg_prolong(dl + (size_t)d * P, hl + (size_t)d * P, P, b, f32, st)) != hipSuccess) return SMG_EHIP;
+      if (prof_) prof_->close(EC_PROLONG, ev, (2.0 * vb + 0.25 * vb) * cells(d, false), st);
+    }
     for (int k = 0; k < prm_.nu_post; ++k)
-      if ((e = smooth(d)) != hipSuccess) return SMG_EHIP;
+      if ((e = smooth(d, fuse && k == 0)) != hipSuccess) return SMG_EHIP;
   }
   return SMG_OK;
 }

@@ -24,6 +24,7 @@
 // even-odd SOR passes of every line run as point updates in LDS, or (exact
 // variant) each line is solved by the Thomas algorithm.
 #include <algorithm>
+#include <type_traits>
 
 #include "relax_dev.h"
 #include "smg_internal.h"
@@ -55,6 +56,24 @@ __device__ __forceinline__ typename Vec<R>::T resid_at(const LevelDev& L, int m,
   return mkv<R>(fv.x - acc.x, fv.y - acc.y);
 }
 
+// Bilinear interpolation of the coarse correction uc (one plane, C.nb
+// columns) at fine cell (i, j); the b-direction weights depend on the parity
+// of the mode (par).
+template <typename R, typename P>
+__device__ __forceinline__ typename Vec<R>::T coarse_corr(const LevelDev& L, int cnb, P uc, int par, int i, int j) {
+  using V = typename Vec<R>::T;
+  const int a0 = gbl(L.pa_i0)[i], a1 = gbl(L.pa_i1)[i];
+  const int b0 = gbl(L.pb_i0)[par * L.nb + j], b1 = gbl(L.pb_i1)[par * L.nb + j];
+  const R wa0 = (R)gbl(L.pa_w0)[i], wa1 = (R)gbl(L.pa_w1)[i];
+  const R wb0 = (R)gbl(L.pb_w0)[par * L.nb + j], wb1 = (R)gbl(L.pb_w1)[par * L.nb + j];
+  V ev = mkv<R>(0, 0);
+  ev = axpy<R>(wa0 * wb0, (V)uc[(size_t)a0 * cnb + b0], ev);
+  ev = axpy<R>(wa0 * wb1, (V)uc[(size_t)a0 * cnb + b1], ev);
+  ev = axpy<R>(wa1 * wb0, (V)uc[(size_t)a1 * cnb + b0], ev);
+  ev = axpy<R>(wa1 * wb1, (V)uc[(size_t)a1 * cnb + b1], ev);
+  return ev;
+}
+
 // ---------------------------------------------------------------------------
 // Smoother.  DIR = 1: polar lines (rows i, points along j); tile = rows
 // [i0-2, i0+T+2) x all columns.  DIR = 0: radial lines (columns j, points
@@ -63,19 +82,26 @@ __device__ __forceinline__ typename Vec<R>::T resid_at(const LevelDev& L, int m,
 // lines the block relaxes (owned lines and the inner halo line on each side)
 // in the same layout, and the 1D stencil tables of the tile rounded to R.
 // All global reads are issued before the first barrier; the colours then
-// run out of LDS and registers.
+// run out of LDS and registers.  With PROLONG the launch first applies
+// the coarse-grid correction: every u value entering the tile (halo lines
+// included) gets the interpolated coarse correction added, so the owned
+// lines written back carry it and no separate prolongation pass is needed.
 // ---------------------------------------------------------------------------
 // LDS bytes of a smoother block: u tile, f tile (the SOR variant; the exact
 // variant reads each f value once, from global memory), exact-line scratch
 // and tables.
+// A launch that applies the coarse correction (prolong) also holds the
+// prolongation indices and weights of the tile's rows and columns.
 template <typename R>
-__host__ __device__ inline size_t smooth_lds_bytes(int dir, int na, int nb, int tile, bool exact, int scratch) {
+__host__ __device__ inline size_t smooth_lds_bytes(int dir, int na, int nb, int tile, bool exact, int scratch,
+                                                   bool prolong = false) {
   const size_t nr = dir == 0 ? (size_t)na + 2 : (size_t)tile + 4;
   const size_t nc = dir == 0 ? (size_t)odd_stride(tile + 4) : (size_t)nb + 2;
-  return (exact ? 1 : 2) * sizeof(typename Vec<R>::T) * nr * nc + sizeof(R) * ((size_t)scratch + 5 * nr + 4 * nc);
+  return (exact ? 1 : 2) * sizeof(typename Vec<R>::T) * nr * nc + sizeof(R) * ((size_t)scratch + 5 * nr + 4 * nc) +
+         (prolong ? (nr + nc) * (2 * sizeof(int) + 2 * sizeof(R)) : 0);
 }
 
-template <int DIR, bool EXACT, int PMAX, typename R, int NT>
+template <int DIR, bool EXACT, int PMAX, typename R, int NT, bool PROLONG>
 __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, BatchRef bt, int n_sor) {
   using V = typename Vec<R>::T;
   extern __shared__ char smem[];
@@ -115,13 +141,64 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
   const int fbeg = max(lbeg - 1, 0), fend = min(lend + 1, nlines_total);
   // u tile (zeros outside the plane) and f of the relaxed lines, four loads
   // in flight per thread
+  // LDS arrays after the tiles: exact-line scratch, then the 1D tables per
+  // tile row rr = i - r0 (ua, da, R, Ca, omega of the polar line) and per
+  // tile column cc = j - c0 (ub, db, Cb, omega of the radial line), then the
+  // prolongation indices and weights per tile row and column
+  R* cp = reinterpret_cast<R*>(EXACT ? fs : fs + nr * nc);
+  R* t0 = cp + scratch_words;
+  R *t1 = t0 + nr, *t2 = t1 + nr, *t3 = t2 + nr, *t4 = t3 + nr;
+  R *c1 = t4 + nr, *c2 = c1 + nc, *c3 = c2 + nc, *c4 = c3 + nc;
+  if constexpr (PROLONG) {
+    int* pix = reinterpret_cast<int*>(c4 + nc);          // a0, a1 per row; b0, b1 per column
+    R* pwt = reinterpret_cast<R*>(pix + 2 * (nr + nc));  // the matching weights
+    const int par = m & 1;
+    for (int rr = threadIdx.x; rr < nr; rr += blockDim.x) {
+      const int i = min(max(r0 + rr, 0), na - 1);
+      pix[rr] = gbl(L.pa_i0)[i];
+      pix[nr + rr] = gbl(L.pa_i1)[i];
+      pwt[rr] = (R)gbl(L.pa_w0)[i];
+      pwt[nr + rr] = (R)gbl(L.pa_w1)[i];
+    }
+    for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
+      const int j = min(max(c0 + cc, 0), nb - 1);
+      pix[2 * nr + cc] = gbl(L.pb_i0)[par * nb + j];
+      pix[2 * nr + nc + cc] = gbl(L.pb_i1)[par * nb + j];
+      pwt[2 * nr + cc] = (R)gbl(L.pb_w0)[par * nb + j];
+      pwt[2 * nr + nc + cc] = (R)gbl(L.pb_w1)[par * nb + j];
+    }
+    __syncthreads();
+    const int cnb = J.C.nb;
+    const auto uc = gbl(static_cast<const V*>(J.uc) + (size_t)slot * J.C.na * cnb);
 #pragma unroll 4
-  for (int t = threadIdx.x; t < nr * nc; t += blockDim.x) {
-    const int rr = t / nc, cc = t - rr * nc;
-    const int i = r0 + rr, j = c0 + cc;
-    V v = mkv<R>(0, 0);
-    if (cc < ncu && i >= 0 && i < na && j >= 0 && j < nb) v = u[(size_t)i * nb + j];
-    sh[t] = v;
+    for (int t = threadIdx.x; t < nr * nc; t += blockDim.x) {
+      const int rr = t / nc, cc = t - rr * nc;
+      const int i = r0 + rr, j = c0 + cc;
+      V v = mkv<R>(0, 0);
+      if (cc < ncu && i >= 0 && i < na && j >= 0 && j < nb) {
+        const int a0 = pix[rr], a1 = pix[nr + rr], b0 = pix[2 * nr + cc], b1 = pix[2 * nr + nc + cc];
+        const R wa0 = pwt[rr], wa1 = pwt[nr + rr], wb0 = pwt[2 * nr + cc], wb1 = pwt[2 * nr + nc + cc];
+        // same operations in the same order as coarse_corr + add (k_prolong),
+        // so a fused launch rounds exactly like the separate pass
+        V ev = mkv<R>(0, 0);
+        ev = axpy<R>(wa0 * wb0, (V)uc[(size_t)a0 * cnb + b0], ev);
+        ev = axpy<R>(wa0 * wb1, (V)uc[(size_t)a0 * cnb + b1], ev);
+        ev = axpy<R>(wa1 * wb0, (V)uc[(size_t)a1 * cnb + b0], ev);
+        ev = axpy<R>(wa1 * wb1, (V)uc[(size_t)a1 * cnb + b1], ev);
+        const V w = u[(size_t)i * nb + j];
+        v = mkv<R>(w.x + ev.x, w.y + ev.y);
+      }
+      sh[t] = v;
+    }
+  } else {
+#pragma unroll 4
+    for (int t = threadIdx.x; t < nr * nc; t += blockDim.x) {
+      const int rr = t / nc, cc = t - rr * nc;
+      const int i = r0 + rr, j = c0 + cc;
+      V v = mkv<R>(0, 0);
+      if (cc < ncu && i >= 0 && i < na && j >= 0 && j < nb) v = u[(size_t)i * nb + j];
+      sh[t] = v;
+    }
   }
   if (EXACT) {
   } else if (DIR == 1) {
@@ -138,14 +215,6 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
       fs[(i - r0) * nc + (j - c0)] = f[(size_t)i * nb + j];
     }
   }
-  // scratch for the exact line solve (one row of Thomas factors per line),
-  // then the 1D tables per tile row rr = i - r0 (ua, da, R, Ca, omega of the
-  // polar line) and per tile column cc = j - c0 (ub, db, Cb, omega of the
-  // radial line)
-  R* cp = reinterpret_cast<R*>(EXACT ? fs : fs + nr * nc);
-  R* t0 = cp + scratch_words;
-  R *t1 = t0 + nr, *t2 = t1 + nr, *t3 = t2 + nr, *t4 = t3 + nr;
-  R *c1 = t4 + nr, *c2 = c1 + nc, *c3 = c2 + nc, *c4 = c3 + nc;
   for (int rr = threadIdx.x; rr < nr; rr += blockDim.x) {
     const int i = r0 + rr;
     const bool in = i >= 0 && i < na;
@@ -302,21 +371,9 @@ __global__ void __launch_bounds__(kThreads) k_prolong(const LvJob* __restrict__ 
   const auto uc = gbl(static_cast<const V*>(J.uc) + (size_t)slot * C.na * C.nb);
   const int par = m & 1;
   const int cells = L.na * L.nb;
-  const auto pbi0 = gbl(L.pb_i0 + par * L.nb);
-  const auto pbi1 = gbl(L.pb_i1 + par * L.nb);
-  const auto pbw0 = gbl(L.pb_w0 + par * L.nb);
-  const auto pbw1 = gbl(L.pb_w1 + par * L.nb);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += gridDim.x * blockDim.x) {
     const int i = t / L.nb, j = t - i * L.nb;
-    const int a0 = gbl(L.pa_i0)[i], a1 = gbl(L.pa_i1)[i];
-    const int b0 = pbi0[j], b1 = pbi1[j];
-    const R wa0 = (R)gbl(L.pa_w0)[i], wa1 = (R)gbl(L.pa_w1)[i];
-    const R wb0 = (R)pbw0[j], wb1 = (R)pbw1[j];
-    V ev = mkv<R>(0, 0);
-    ev = axpy<R>(wa0 * wb0, uc[(size_t)a0 * C.nb + b0], ev);
-    ev = axpy<R>(wa0 * wb1, uc[(size_t)a0 * C.nb + b1], ev);
-    ev = axpy<R>(wa1 * wb0, uc[(size_t)a1 * C.nb + b0], ev);
-    ev = axpy<R>(wa1 * wb1, uc[(size_t)a1 * C.nb + b1], ev);
+    const V ev = coarse_corr<R>(L, C.nb, uc, par, i, j);
     const V v = U[t];
     U[t] = mkv<R>(v.x + ev.x, v.y + ev.y);
   }
@@ -430,17 +487,23 @@ bool smooth_shape(const LevelDev& L, int dir, bool exact, bool fp32, int target_
 
 template <typename R>
 static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, int n_sor,
-                                bool exact, int dir, hipStream_t st) {
+                                bool exact, int dir, bool prolong, hipStream_t st) {
   int gx = 0;
   size_t lds = 0;
   for (int q = 0; q < n_prob; ++q) {
     if (!hj[q].active) continue;
     const LevelDev& L = hj[q].L;
     if ((dir == 0 ? L.na : L.nb) > kRelaxMaxPoints) return hipErrorInvalidConfiguration;
-    lds = std::max(lds, smooth_lds_bytes<R>(dir, L.na, L.nb, hj[q].tile[dir], exact, hj[q].scratch[dir]));
+    lds = std::max(lds, smooth_lds_bytes<R>(dir, L.na, L.nb, hj[q].tile[dir], exact, hj[q].scratch[dir], prolong));
     if (hj[q].ntile[dir] > gx) gx = hj[q].ntile[dir];
   }
   if (gx == 0 || b.cap == 0) return hipSuccess;
+  if (prolong && lds > lds_limit()) {
+    // the tables do not fit beside the widest tile: separate prolongation
+    hipError_t e = mg_prolong(jobs, hj, n_prob, b, std::is_same<R, float>::value, st);
+    if (e != hipSuccess) return e;
+    return smooth_launch<R>(jobs, hj, n_prob, b, n_sor, exact, dir, false, st);
+  }
   if (lds > lds_limit()) return hipErrorInvalidConfiguration;
   const dim3 grid(gx, b.cap);
   int pmax = 2, tmax = 0;  // points per lane of the longest relaxed line; widest tile
@@ -452,36 +515,40 @@ static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, 
   // wide tiles (more lines per colour than four waves take in one step)
   // run with 1024 threads where the variant stays within 128 registers
   const bool big = !exact && tmax >= 16 && pmax <= 4;
+  // the coarse correction is applied by radial-line launches only
+  if (prolong && dir != 0) return hipErrorInvalidValue;
   auto go = [&](auto kern, int nt) { hipLaunchKernelGGL(kern, grid, dim3(nt), lds, st, jobs, b, n_sor); };
+  // radial launch with or without the coarse correction
+  auto go0 = [&](auto kern_plain, auto kern_prolong, int nt) { prolong ? go(kern_prolong, nt) : go(kern_plain, nt); };
   if (exact) {
-    if (dir == 0) go(k_smooth<0, true, 2, R, kThreads>, kThreads);
-    else go(k_smooth<1, true, 2, R, kThreads>, kThreads);
+    if (dir == 0) go0(k_smooth<0, true, 2, R, kThreads, false>, k_smooth<0, true, 2, R, kThreads, true>, kThreads);
+    else go(k_smooth<1, true, 2, R, kThreads, false>, kThreads);
   } else if (big) {
     if (dir == 0) {
-      if (pmax <= 2) go(k_smooth<0, false, 2, R, 1024>, 1024);
-      else go(k_smooth<0, false, 4, R, 1024>, 1024);
+      if (pmax <= 2) go0(k_smooth<0, false, 2, R, 1024, false>, k_smooth<0, false, 2, R, 1024, true>, 1024);
+      else go0(k_smooth<0, false, 4, R, 1024, false>, k_smooth<0, false, 4, R, 1024, true>, 1024);
     } else {
-      if (pmax <= 2) go(k_smooth<1, false, 2, R, 1024>, 1024);
-      else go(k_smooth<1, false, 4, R, 1024>, 1024);
+      if (pmax <= 2) go(k_smooth<1, false, 2, R, 1024, false>, 1024);
+      else go(k_smooth<1, false, 4, R, 1024, false>, 1024);
     }
   } else if (dir == 0) {
-    if (pmax <= 2) go(k_smooth<0, false, 2, R, kThreads>, kThreads);
-    else if (pmax <= 4) go(k_smooth<0, false, 4, R, kThreads>, kThreads);
-    else if (pmax <= 8) go(k_smooth<0, false, 8, R, kThreads>, kThreads);
-    else go(k_smooth<0, false, 16, R, kThreads>, kThreads);
+    if (pmax <= 2) go0(k_smooth<0, false, 2, R, kThreads, false>, k_smooth<0, false, 2, R, kThreads, true>, kThreads);
+    else if (pmax <= 4) go0(k_smooth<0, false, 4, R, kThreads, false>, k_smooth<0, false, 4, R, kThreads, true>, kThreads);
+    else if (pmax <= 8) go0(k_smooth<0, false, 8, R, kThreads, false>, k_smooth<0, false, 8, R, kThreads, true>, kThreads);
+    else go0(k_smooth<0, false, 16, R, kThreads, false>, k_smooth<0, false, 16, R, kThreads, true>, kThreads);
   } else {
-    if (pmax <= 2) go(k_smooth<1, false, 2, R, kThreads>, kThreads);
-    else if (pmax <= 4) go(k_smooth<1, false, 4, R, kThreads>, kThreads);
-    else if (pmax <= 8) go(k_smooth<1, false, 8, R, kThreads>, kThreads);
-    else go(k_smooth<1, false, 16, R, kThreads>, kThreads);
+    if (pmax <= 2) go(k_smooth<1, false, 2, R, kThreads, false>, kThreads);
+    else if (pmax <= 4) go(k_smooth<1, false, 4, R, kThreads, false>, kThreads);
+    else if (pmax <= 8) go(k_smooth<1, false, 8, R, kThreads, false>, kThreads);
+    else go(k_smooth<1, false, 16, R, kThreads, false>, kThreads);
   }
   return hipGetLastError();
 }
 
 hipError_t mg_smooth_dir(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, int n_sor, bool exact,
-                         int dir, bool fp32, hipStream_t st) {
-  return fp32 ? smooth_launch<float>(jobs, hj, n_prob, b, n_sor, exact, dir, st)
-              : smooth_launch<double>(jobs, hj, n_prob, b, n_sor, exact, dir, st);
+                         int dir, bool fp32, hipStream_t st, bool prolong) {
+  return fp32 ? smooth_launch<float>(jobs, hj, n_prob, b, n_sor, exact, dir, prolong, st)
+              : smooth_launch<double>(jobs, hj, n_prob, b, n_sor, exact, dir, prolong, st);
 }
 
 // blocks per plane of a per-cell launch: enough for the largest problem

@@ -226,8 +226,11 @@ hipError_t fft_c2r(const double2* modes, double* out, int n_lines, int n_phi, co
                    hipStream_t st);
 // Multigrid (mg.hip).  `jobs` is the device array of one depth's LvJob per
 // problem, `hj` its host mirror (used only to size the grid and LDS).
+// With prolong set (radial lines, dir 0, only) the launch first adds the
+// prolonged coarse correction (the job's uc) to u, in place of an
+// mg_prolong launch.
 hipError_t mg_smooth_dir(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, int n_sor, bool exact,
-                         int dir, bool fp32, hipStream_t st);
+                         int dir, bool fp32, hipStream_t st, bool prolong = false);
 hipError_t mg_restrict(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, bool fp32, hipStream_t st);
 hipError_t mg_prolong(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, bool fp32, hipStream_t st);
 hipError_t mg_residual(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, double2* r, hipStream_t st);
