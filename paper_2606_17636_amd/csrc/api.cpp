@@ -182,7 +182,7 @@ struct PlanNet {
   int m_max = 0, n_img = 0, nblk = 1;
   char* work = nullptr;
   NetWork wl{};
-  size_t o_fprev[2] = {0, 0}, o_uprev = 0, o_cand = 0, o_cs = 0, o_us = 0, o_sc = 0, o_part = 0, o_used = 0,
+  size_t o_fprev[2] = {0, 0}, o_uprev = 0, o_cand = 0, o_cs = 0, o_us = 0, o_u2 = 0, o_sc = 0, o_part = 0, o_used = 0,
          o_jobs = 0, o_lv = 0, o_list = 0, o_rec = 0, bytes = 0;
   std::vector<NormJob> hjobs;  // [target][smoothed candidate, smoothed previous solution]
   std::vector<LvJob> hlv;      // [target][the same two arrays]: one smoothing step
@@ -211,7 +211,7 @@ struct smg_plan {
   // workspace layout (byte offsets)
   size_t w_blob = 0, w_dgf = 0, w_psi = 0, w_phi = 0, w_f = 0, w_f2 = 0, w_sigma = 0, w_theta = 0, w_gpot = 0, w_eng = 0,
          w_eng_bytes = 0, w_total = 0;
-  std::vector<size_t> w_u, w_fl, w_u32, w_f32;
+  std::vector<size_t> w_u, w_fl, w_u32, w_f32, w_u2;
   // bound workspace
   char* ws = nullptr;
   bool ready = false;
@@ -406,6 +406,12 @@ extern "C" smg_status smg_plan_create(const smg_grid* grid, const smg_opts* opts
       p->w_u32[l] = take(sizeof(float2) * M * pl);
       p->w_f32[l] = take(sizeof(float2) * M * pl);
     }
+  }
+  // second iterate array of the smoother per level (the cycle's type)
+  p->w_u2.assign(p->H.lv.size(), 0);
+  for (size_t l = 0; l < p->H.lv.size(); ++l) {
+    size_t pl = (size_t)p->H.lv[l].na * p->H.lv[l].nb;
+    p->w_u2[l] = take((o.precision == SMG_MIXED ? sizeof(float2) : sizeof(double2)) * M * pl);
   }
   p->w_total = off;
   *out = p.release();
@@ -714,8 +720,11 @@ static smg_status dgf_extended(smg_plan& p, hipStream_t st) {
   pr.L = LV;
   pr.u.assign(HE.lv.size(), nullptr);
   pr.f.assign(HE.lv.size(), nullptr);
-  for (size_t l = 1; l < HE.lv.size(); ++l) {
+  pr.u2.assign(HE.lv.size(), nullptr);
+  for (size_t l = 0; l < HE.lv.size(); ++l) {
     size_t pl = (size_t)HE.lv[l].na * HE.lv[l].nb;
+    pr.u2[l] = tmp.alloc(sizeof(double2) * cap * pl, herr); TMPCHK(pr.u2[l]);
+    if (l == 0) continue;
     pr.u[l] = tmp.alloc(sizeof(double2) * cap * pl, herr); TMPCHK(pr.u[l]);
     pr.f[l] = tmp.alloc(sizeof(double2) * cap * pl, herr); TMPCHK(pr.f[l]);
   }
@@ -779,6 +788,8 @@ static MGProblem plan_problem(smg_plan* p) {
       pr.f[l] = p->dptr(p->w_fl[l]);
     }
   }
+  pr.u2.assign(L, nullptr);
+  for (int l = 0; l < L; ++l) pr.u2[l] = p->ws + p->w_u2[l];
   pr.u0 = {p->dptr(p->w_psi), p->dptr(p->w_phi)};
   pr.f0 = {p->dptr(p->w_f), p->dptr(p->w_f2)};
   if (fp32) {
@@ -1184,6 +1195,7 @@ static smg_status net_layout(const smg_plan* p, const smg_net* net, int m_max, P
   pn.o_cand = take(sizeof(double2) * np);
   pn.o_cs = take(sizeof(double2) * np);
   pn.o_us = take(sizeof(double2) * np);
+  pn.o_u2 = take(sizeof(double2) * np);  // the smoother's second array (steps run one after another)
   pn.o_sc = take(sizeof(double) * 4 * pn.n_img);
   NormJob hj{};
   hj.L = p->levels.empty() ? LevelDev{} : p->levels[0];
@@ -1232,6 +1244,7 @@ extern "C" smg_status smg_plan_attach_net(smg_plan* p, smg_net* net, int m_max, 
       J.L = p->levels[0];
       J.C = p->levels[0];
       J.u = c.u;
+      J.u2 = pn.work + pn.o_u2;
       J.f = const_cast<double2*>(c.f);
       J.active = 1;
       for (int dir = 0; dir < 2; ++dir) {

@@ -78,7 +78,9 @@ smg_status Engine::init(std::vector<MGProblem> probs, int n_targets, const MGPar
   for (int q = 0; q < P; ++q) {
     const MGProblem& pr = P_[q];
     if (pr.L.empty() || (int)pr.u0.size() != T_ || (int)pr.f0.size() != T_ || pr.n < 1) EFAIL(SMG_EINVAL, "engine: malformed problem");
-    if ((int)pr.u.size() != (int)pr.L.size() || (int)pr.f.size() != (int)pr.L.size()) EFAIL(SMG_EINVAL, "engine: level arrays");
+    if ((int)pr.u.size() != (int)pr.L.size() || (int)pr.f.size() != (int)pr.L.size() ||
+        (int)pr.u2.size() != (int)pr.L.size())
+      EFAIL(SMG_EINVAL, "engine: level arrays");
     if (prm_.fp32 && (!pr.r32 || !pr.e32)) EFAIL(SMG_EINVAL, "engine: mixed form needs FP32 residual/correction arrays");
     base_[q] = n_total_;
     n_total_ += pr.n;
@@ -186,6 +188,8 @@ smg_status Engine::build_jobs(int target, const MGConfig& c, std::vector<LvJob>&
       J.u = d == 0 && !prm_.fp32 ? (void*)pr.u0[target] : pr.u[d];
       J.f = d == 0 && !prm_.fp32 ? (void*)pr.f0[target] : pr.f[d];
       J.uc = d + 1 < L ? pr.u[d + 1] : nullptr;
+      J.acc = d == 0 && prm_.fp32 ? pr.u0[target] : nullptr;
+      J.u2 = pr.u2[d];
       J.fc = d + 1 < L ? pr.f[d + 1] : nullptr;
       J.mode = pr.mode;
       J.active = d < first ? 1 : 0;
@@ -249,7 +253,7 @@ int Engine::depth_of(const MGConfig& c) const {
   return D;
 }
 
-smg_status Engine::vcycle(int target, int c, const BatchRef& b, hipStream_t st) {
+smg_status Engine::vcycle(int target, int c, const BatchRef& b, hipStream_t st, bool* accumulated) {
   const int P = (int)P_.size();
   const MGConfig& cf = cfg_[c];
   const size_t base = ((size_t)target * kMaxConfigs + c) * Dmax_ * P;
@@ -272,24 +276,32 @@ smg_status Engine::vcycle(int target, int c, const BatchRef& b, hipStream_t st) 
     return s;
   };
   // one smoothing step at depth d; with prolong set its first launch also
-  // applies the coarse-grid correction (reads the coarse correction too)
-  auto smooth = [&](int d, bool prolong) -> hipError_t {
+  // applies the coarse-grid correction (reads the coarse correction too);
+  // with acc set its last launch adds the FP32 correction to the FP64
+  // iterate (reads and writes the FP64 iterate instead of storing FP32)
+  auto smooth = [&](int d, bool prolong, bool acc) -> hipError_t {
     for (int dir = 0; dir < 2; ++dir) {
-      const bool pr = prolong && dir == 0;
+      const bool pr = prolong && dir == 0, ac = acc && dir == 1;
       const int ev = prof_ ? prof_->mark(st) : -1;
-      hipError_t e =
-          smgk::mg_smooth_dir(dl + (size_t)d * P, hl + (size_t)d * P, P, b, prm_.n_sor, prm_.exact, dir, f32, st, pr);
+      hipError_t e = smgk::mg_smooth_dir(dl + (size_t)d * P, hl + (size_t)d * P, P, b, prm_.n_sor, prm_.exact, dir,
+                                         f32, st, pr, ac);
       if (e != hipSuccess) return e;
       if (prof_)
         prof_->close(d == 0 ? (dir == 0 ? EC_SMOOTH_R0 : EC_SMOOTH_P0) : EC_SMOOTH_C, ev,
-                     (pr ? 3.25 : 3.0) * vb * cells(d, false), st);
+                     ((pr ? 3.25 : 3.0) * vb + (ac ? 32.0 - vb : 0.0)) * cells(d, false), st);
     }
     return hipSuccess;
   };
+  // the mixed form's correction step u += e goes into the last launch of the
+  // cycle when every problem smooths its finest level in separate launches
+  bool acc_last = accumulated && f32 && D > 0 && prm_.nu_post > 0;
+  for (int q = 0; q < P; ++q)
+    if (!hl[q].active) acc_last = false;
+  if (accumulated) *accumulated = acc_last;
   hipError_t e = hipSuccess;
   for (int d = 0; d < D; ++d) {
     for (int k = 0; k < prm_.nu_pre; ++k)
-      if ((e = smooth(d, false)) != hipSuccess) return SMG_EHIP;
+      if ((e = smooth(d, false, false)) != hipSuccess) return SMG_EHIP;
     const int ev = prof_ ? prof_->mark(st) : -1;
     if ((e = smgk::mg_restrict(dl + (size_t)d * P, hl + (size_t)d * P, P, b, f32, st)) != hipSuccess) return SMG_EHIP;
     if (prof_) prof_->close(EC_RESTRICT, ev, (2.0 * vb + 0.5 * vb) * cells(d, false), st);
@@ -320,7 +332,7 @@ smg_status Engine::vcycle(int target, int c, const BatchRef& b, hipStream_t st) 
       if (prof_) prof_->close(EC_PROLONG, ev, (2.0 * vb + 0.25 * vb) * cells(d, false), st);
     }
     for (int k = 0; k < prm_.nu_post; ++k)
-      if ((e = smooth(d, fuse && k == 0)) != hipSuccess) return SMG_EHIP;
+      if ((e = smooth(d, fuse && k == 0, acc_last && d == 0 && k == prm_.nu_post - 1)) != hipSuccess) return SMG_EHIP;
   }
   return SMG_OK;
 }
@@ -373,11 +385,12 @@ smg_status Engine::cycle(int target, int cap, hipStream_t st) {
       return SMG_EHIP;
     fp32_owner_ = target;
   }
-  smg_status s = vcycle(target, config_for(cap), b, st);
+  bool accumulated = false;
+  smg_status s = vcycle(target, config_for(cap), b, st, &accumulated);
   if (s != SMG_OK) return s;
   double cells = 0.0;
   for (int q = 0; q < P; ++q) cells += (double)std::min(P_[q].n, cap) * P_[q].L[0].na * P_[q].L[0].nb;
-  if (prm_.fp32) {
+  if (prm_.fp32 && !accumulated) {
     const int ev = prof_ ? prof_->mark(st) : -1;
     if (smgk::mg_accumulate(dn, hn, P, b, st) != hipSuccess) return SMG_EHIP;
     if (prof_) prof_->close(EC_ACCUM, ev, 40.0 * cells, st);

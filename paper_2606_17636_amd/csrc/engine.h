@@ -18,6 +18,8 @@ namespace smg {
 struct MGProblem {
   std::vector<LevelDev> L;         // level views (device tables)
   std::vector<void*> u, f;         // per-level cycle arrays; level 0 only for the mixed form (FP32)
+  std::vector<void*> u2;           // per-level second iterate array of the smoother (level 0: the
+                                   // cycle's type, shared by the targets)
   // a target is one solve: its FP64 iterate and right-hand side arrays
   std::vector<double2*> u0;
   std::vector<const double2*> f0;
@@ -111,7 +113,9 @@ class Engine {
 
  private:
   smg_status build_jobs(int target, const MGConfig& c, std::vector<LvJob>& lv, std::vector<LdsJob>& lds);
-  smg_status vcycle(int target, int c, const BatchRef& b, hipStream_t st);
+  // accumulated: mixed form only; when non-null the cycle may end by adding
+  // its correction to the FP64 iterate and reports whether it did
+  smg_status vcycle(int target, int c, const BatchRef& b, hipStream_t st, bool* accumulated = nullptr);
   int config_for(int cap) const;
   int depth_of(const MGConfig& c) const;
 

@@ -86,6 +86,9 @@ __device__ __forceinline__ typename Vec<R>::T coarse_corr(const LevelDev& L, int
 // the coarse-grid correction: every u value entering the tile (halo lines
 // included) gets the interpolated coarse correction added, so the owned
 // lines written back carry it and no separate prolongation pass is needed.
+// With ACC (polar lines, FP32 correction of the mixed form) the owned lines
+// are added to the FP64 iterate instead of being stored, which is the
+// correction step of the mixed form done by the V-cycle's last launch.
 // ---------------------------------------------------------------------------
 // LDS bytes of a smoother block: u tile, f tile (the SOR variant; the exact
 // variant reads each f value once, from global memory), exact-line scratch
@@ -101,7 +104,7 @@ __host__ __device__ inline size_t smooth_lds_bytes(int dir, int na, int nb, int 
          (prolong ? (nr + nc) * (2 * sizeof(int) + 2 * sizeof(R)) : 0);
 }
 
-template <int DIR, bool EXACT, int PMAX, typename R, int NT, bool PROLONG>
+template <int DIR, bool EXACT, int PMAX, typename R, int NT, bool PROLONG, bool ACC = false>
 __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, BatchRef bt, int n_sor) {
   using V = typename Vec<R>::T;
   extern __shared__ char smem[];
@@ -116,7 +119,10 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
   const LevelDev L = J.L;
   const int tile = J.tile[DIR], scratch_words = J.scratch[DIR];
   const int na = L.na, nb = L.nb;
-  const auto u = gbl(static_cast<V*>(J.u) + (size_t)slot * na * nb);
+  // radial lines: u -> u2; polar lines: u2 -> u (a launch never reads what
+  // another of its blocks writes)
+  const auto u = gbl(static_cast<const V*>(DIR == 0 ? J.u : J.u2) + (size_t)slot * na * nb);
+  const auto uo = gbl(static_cast<V*>(DIR == 0 ? J.u2 : J.u) + (size_t)slot * na * nb);
   const auto f = gbl(static_cast<const V*>(J.f) + (size_t)slot * na * nb);
   // tile geometry in (row, col) = (i, j) coordinates
   int r0, nr, c0, nc;  // first global row/col held in LDS and counts (incl. halo/pad)
@@ -289,17 +295,26 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
     }
     __syncthreads();
   }
-  // write back the owned lines
-  if (DIR == 1) {
+  // write back the owned lines (ACC: add them to the FP64 iterate instead)
+  if constexpr (ACC) {
+    const auto a = gbl(J.acc + (size_t)slot * na * nb);
+#pragma unroll 4
     for (int t = threadIdx.x; t < (lend - lbeg) * nb; t += blockDim.x) {
       const int i = lbeg + t / nb, j = t % nb;
-      u[(size_t)i * nb + j] = sh[(i - r0) * nc + (j - c0)];
+      const V ev = sh[(i - r0) * nc + (j - c0)];
+      const double2 v = a[(size_t)i * nb + j];
+      a[(size_t)i * nb + j] = make_double2(v.x + (double)ev.x, v.y + (double)ev.y);
+    }
+  } else if (DIR == 1) {
+    for (int t = threadIdx.x; t < (lend - lbeg) * nb; t += blockDim.x) {
+      const int i = lbeg + t / nb, j = t % nb;
+      uo[(size_t)i * nb + j] = sh[(i - r0) * nc + (j - c0)];
     }
   } else {
     const int w = lend - lbeg;
     for (int t = threadIdx.x; t < na * w; t += blockDim.x) {
       const int i = t / w, j = lbeg + t % w;
-      u[(size_t)i * nb + j] = sh[(i - r0) * nc + (j - c0)];
+      uo[(size_t)i * nb + j] = sh[(i - r0) * nc + (j - c0)];
     }
   }
 }
@@ -487,7 +502,7 @@ bool smooth_shape(const LevelDev& L, int dir, bool exact, bool fp32, int target_
 
 template <typename R>
 static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, int n_sor,
-                                bool exact, int dir, bool prolong, hipStream_t st) {
+                                bool exact, int dir, bool prolong, bool acc, hipStream_t st) {
   int gx = 0;
   size_t lds = 0;
   for (int q = 0; q < n_prob; ++q) {
@@ -502,7 +517,7 @@ static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, 
     // the tables do not fit beside the widest tile: separate prolongation
     hipError_t e = mg_prolong(jobs, hj, n_prob, b, std::is_same<R, float>::value, st);
     if (e != hipSuccess) return e;
-    return smooth_launch<R>(jobs, hj, n_prob, b, n_sor, exact, dir, false, st);
+    return smooth_launch<R>(jobs, hj, n_prob, b, n_sor, exact, dir, false, acc, st);
   }
   if (lds > lds_limit()) return hipErrorInvalidConfiguration;
   const dim3 grid(gx, b.cap);
@@ -515,21 +530,29 @@ static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, 
   // wide tiles (more lines per colour than four waves take in one step)
   // run with 1024 threads where the variant stays within 128 registers
   const bool big = !exact && tmax >= 16 && pmax <= 4;
-  // the coarse correction is applied by radial-line launches only
+  // the coarse correction is applied by radial-line launches only, the
+  // accumulation into the FP64 iterate by FP32 polar-line launches only
   if (prolong && dir != 0) return hipErrorInvalidValue;
+  if (acc && (dir != 1 || !std::is_same<R, float>::value)) return hipErrorInvalidValue;
+  for (int q = 0; q < n_prob; ++q) {
+    if (acc && hj[q].active && !hj[q].acc) return hipErrorInvalidValue;
+    if (hj[q].active && (!hj[q].u || !hj[q].u2)) return hipErrorInvalidValue;
+  }
   auto go = [&](auto kern, int nt) { hipLaunchKernelGGL(kern, grid, dim3(nt), lds, st, jobs, b, n_sor); };
-  // radial launch with or without the coarse correction
+  // radial launch with or without the coarse correction; polar launch
+  // storing the lines or adding them to the FP64 iterate
   auto go0 = [&](auto kern_plain, auto kern_prolong, int nt) { prolong ? go(kern_prolong, nt) : go(kern_plain, nt); };
+  auto go1 = [&](auto kern_plain, auto kern_acc, int nt) { acc ? go(kern_acc, nt) : go(kern_plain, nt); };
   if (exact) {
     if (dir == 0) go0(k_smooth<0, true, 2, R, kThreads, false>, k_smooth<0, true, 2, R, kThreads, true>, kThreads);
-    else go(k_smooth<1, true, 2, R, kThreads, false>, kThreads);
+    else go1(k_smooth<1, true, 2, R, kThreads, false>, k_smooth<1, true, 2, R, kThreads, false, true>, kThreads);
   } else if (big) {
     if (dir == 0) {
       if (pmax <= 2) go0(k_smooth<0, false, 2, R, 1024, false>, k_smooth<0, false, 2, R, 1024, true>, 1024);
       else go0(k_smooth<0, false, 4, R, 1024, false>, k_smooth<0, false, 4, R, 1024, true>, 1024);
     } else {
-      if (pmax <= 2) go(k_smooth<1, false, 2, R, 1024, false>, 1024);
-      else go(k_smooth<1, false, 4, R, 1024, false>, 1024);
+      if (pmax <= 2) go1(k_smooth<1, false, 2, R, 1024, false>, k_smooth<1, false, 2, R, 1024, false, true>, 1024);
+      else go1(k_smooth<1, false, 4, R, 1024, false>, k_smooth<1, false, 4, R, 1024, false, true>, 1024);
     }
   } else if (dir == 0) {
     if (pmax <= 2) go0(k_smooth<0, false, 2, R, kThreads, false>, k_smooth<0, false, 2, R, kThreads, true>, kThreads);
@@ -537,18 +560,18 @@ static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, 
     else if (pmax <= 8) go0(k_smooth<0, false, 8, R, kThreads, false>, k_smooth<0, false, 8, R, kThreads, true>, kThreads);
     else go0(k_smooth<0, false, 16, R, kThreads, false>, k_smooth<0, false, 16, R, kThreads, true>, kThreads);
   } else {
-    if (pmax <= 2) go(k_smooth<1, false, 2, R, kThreads, false>, kThreads);
-    else if (pmax <= 4) go(k_smooth<1, false, 4, R, kThreads, false>, kThreads);
-    else if (pmax <= 8) go(k_smooth<1, false, 8, R, kThreads, false>, kThreads);
-    else go(k_smooth<1, false, 16, R, kThreads, false>, kThreads);
+    if (pmax <= 2) go1(k_smooth<1, false, 2, R, kThreads, false>, k_smooth<1, false, 2, R, kThreads, false, true>, kThreads);
+    else if (pmax <= 4) go1(k_smooth<1, false, 4, R, kThreads, false>, k_smooth<1, false, 4, R, kThreads, false, true>, kThreads);
+    else if (pmax <= 8) go1(k_smooth<1, false, 8, R, kThreads, false>, k_smooth<1, false, 8, R, kThreads, false, true>, kThreads);
+    else go1(k_smooth<1, false, 16, R, kThreads, false>, k_smooth<1, false, 16, R, kThreads, false, true>, kThreads);
   }
   return hipGetLastError();
 }
 
 hipError_t mg_smooth_dir(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, int n_sor, bool exact,
-                         int dir, bool fp32, hipStream_t st, bool prolong) {
-  return fp32 ? smooth_launch<float>(jobs, hj, n_prob, b, n_sor, exact, dir, prolong, st)
-              : smooth_launch<double>(jobs, hj, n_prob, b, n_sor, exact, dir, prolong, st);
+                         int dir, bool fp32, hipStream_t st, bool prolong, bool accumulate) {
+  return fp32 ? smooth_launch<float>(jobs, hj, n_prob, b, n_sor, exact, dir, prolong, accumulate, st)
+              : smooth_launch<double>(jobs, hj, n_prob, b, n_sor, exact, dir, prolong, accumulate, st);
 }
 
 // blocks per plane of a per-cell launch: enough for the largest problem

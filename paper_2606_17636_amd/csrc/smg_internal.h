@@ -167,6 +167,11 @@ struct BatchRef {
 struct LvJob {
   LevelDev L, C;
   void *u, *f, *uc, *fc;
+  void* u2;          // second iterate array of the level: radial-line launches
+                     // read u and write u2, polar-line launches read u2 and
+                     // write u, so no block reads lines another block of the
+                     // same launch writes
+  double2* acc;      // mixed form, finest level: the FP64 iterate (else nullptr)
   const int* mode;   // azimuthal index of each slot (nullptr: the slot itself)
   int active;        // 0: this problem's V-cycle is fused in LDS from this depth on
   int tile[2];       // lines per block
@@ -228,9 +233,12 @@ hipError_t fft_c2r(const double2* modes, double* out, int n_lines, int n_phi, co
 // problem, `hj` its host mirror (used only to size the grid and LDS).
 // With prolong set (radial lines, dir 0, only) the launch first adds the
 // prolonged coarse correction (the job's uc) to u, in place of an
-// mg_prolong launch.
+// mg_prolong launch.  With accumulate set (polar lines, dir 1, FP32 only)
+// the relaxed correction of the owned lines is added to the job's FP64
+// iterate (acc) instead of being stored to u, in place of an mg_accumulate
+// launch.
 hipError_t mg_smooth_dir(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, int n_sor, bool exact,
-                         int dir, bool fp32, hipStream_t st, bool prolong = false);
+                         int dir, bool fp32, hipStream_t st, bool prolong = false, bool accumulate = false);
 hipError_t mg_restrict(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, bool fp32, hipStream_t st);
 hipError_t mg_prolong(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, bool fp32, hipStream_t st);
 hipError_t mg_residual(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, double2* r, hipStream_t st);
