@@ -145,43 +145,173 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
   const int lend = min(lbeg + tile, nlines_total);        // one past the last owned line
   const int npts = DIR == 1 ? nb : na;                    // points per line
   const int fbeg = max(lbeg - 1, 0), fend = min(lend + 1, nlines_total);
-  // u tile (zeros outside the plane) and f of the relaxed lines, four loads
-  // in flight per thread
   // LDS arrays after the tiles: exact-line scratch, then the 1D tables per
   // tile row rr = i - r0 (ua, da, R, Ca, omega of the polar line) and per
-  // tile column cc = j - c0 (ub, db, Cb, omega of the radial line), then the
-  // prolongation indices and weights per tile row and column
+  // tile column cc = j - c0 (ub, db, Cb, omega of the radial line), then
+  // (PROLONG) the prolongation indices and weights per tile row and column
   R* cp = reinterpret_cast<R*>(EXACT ? fs : fs + nr * nc);
   R* t0 = cp + scratch_words;
   R *t1 = t0 + nr, *t2 = t1 + nr, *t3 = t2 + nr, *t4 = t3 + nr;
   R *c1 = t4 + nr, *c2 = c1 + nc, *c3 = c2 + nc, *c4 = c3 + nc;
+  int* pix = reinterpret_cast<int*>(c4 + nc);          // a0, a1 per row; b0, b1 per column
+  R* pwt = reinterpret_cast<R*>(pix + 2 * (nr + nc));  // the matching weights
+  const int par = m & 1;
+  // Load phase.  The first batch (up to KB values of the u tile and of f per
+  // thread, the thread's table row and column, and the prolongation tables)
+  // is read into registers before anything is stored to LDS, so the block
+  // waits for one round of memory latency rather than one per array; larger
+  // tiles continue in strided loops.  The u tile is zero outside the plane.
+  constexpr int KB = 4;
+  const int n_u = nr * nc;
+  const int fw = fend - fbeg;  // lines whose f is staged
+  const int n_f = EXACT ? 0 : (DIR == 1 ? fw * nb : na * fw);
+  auto u_pos = [&](int t, int& i, int& j) {
+    const int rr = t / nc, cc = t - rr * nc;
+    i = r0 + rr;
+    j = c0 + cc;
+    return cc < ncu && i >= 0 && i < na && j >= 0 && j < nb;
+  };
+  auto f_pos = [&](int t, int& i, int& j) {
+    if (DIR == 1) {
+      i = fbeg + t / nb;
+      j = t % nb;
+    } else {
+      i = t / fw;
+      j = fbeg + t % fw;
+    }
+  };
+  V ub[KB], fb[KB];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int t = threadIdx.x + k * NT;
+    int i, j;
+    ub[k] = mkv<R>(0, 0);
+    if (!PROLONG && t < n_u && u_pos(t, i, j)) ub[k] = u[(size_t)i * nb + j];
+  }
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int t = threadIdx.x + k * NT;
+    fb[k] = mkv<R>(0, 0);
+    if (t < n_f) {
+      int i, j;
+      f_pos(t, i, j);
+      fb[k] = f[(size_t)i * nb + j];
+    }
+  }
+  auto row_tables = [&](int rr, R* tr) {
+    const int i = r0 + rr;
+    const bool in = i >= 0 && i < na;
+    tr[0] = in ? (R)gbl(L.ua)[i] : (R)0;
+    tr[1] = in ? (R)gbl(L.da)[i] : (R)0;
+    tr[2] = in ? (R)gbl(L.Rr)[i] : (R)0;
+    tr[3] = in ? (R)gbl(L.Ca)[(size_t)m * na + i] : (R)1;
+    tr[4] = in ? (R)gbl(L.wb)[(size_t)m * na + i] : (R)0;
+  };
+  auto col_tables = [&](int cc, R* tc) {
+    const int j = c0 + cc;
+    const bool in = j >= 0 && j < nb;
+    tc[0] = in ? (R)gbl(L.ub)[j] : (R)0;
+    tc[1] = in ? (R)gbl(L.db)[j] : (R)0;
+    tc[2] = in ? (R)gbl(L.Cb)[(size_t)m * nb + j] : (R)0;
+    tc[3] = in ? (R)gbl(L.wr)[(size_t)m * nb + j] : (R)0;
+  };
+  auto row_prolong = [&](int rr, int* ix, R* w) {
+    const int i = min(max(r0 + rr, 0), na - 1);
+    ix[0] = gbl(L.pa_i0)[i];
+    ix[1] = gbl(L.pa_i1)[i];
+    w[0] = (R)gbl(L.pa_w0)[i];
+    w[1] = (R)gbl(L.pa_w1)[i];
+  };
+  auto col_prolong = [&](int cc, int* ix, R* w) {
+    const int j = min(max(c0 + cc, 0), nb - 1);
+    ix[0] = gbl(L.pb_i0)[par * nb + j];
+    ix[1] = gbl(L.pb_i1)[par * nb + j];
+    w[0] = (R)gbl(L.pb_w0)[par * nb + j];
+    w[1] = (R)gbl(L.pb_w1)[par * nb + j];
+  };
+  auto store_row = [&](int rr, const R* tr, const int* ix, const R* w) {
+    t0[rr] = tr[0]; t1[rr] = tr[1]; t2[rr] = tr[2]; t3[rr] = tr[3]; t4[rr] = tr[4];
+    if (PROLONG) {
+      pix[rr] = ix[0]; pix[nr + rr] = ix[1];
+      pwt[rr] = w[0]; pwt[nr + rr] = w[1];
+    }
+  };
+  auto store_col = [&](int cc, const R* tc, const int* ix, const R* w) {
+    c1[cc] = tc[0]; c2[cc] = tc[1]; c3[cc] = tc[2]; c4[cc] = tc[3];
+    if (PROLONG) {
+      pix[2 * nr + cc] = ix[0]; pix[2 * nr + nc + cc] = ix[1];
+      pwt[2 * nr + cc] = w[0]; pwt[2 * nr + nc + cc] = w[1];
+    }
+  };
+  const int me = threadIdx.x;
+  R tr[5], tc[4], wr[2] = {0, 0}, wc[2] = {0, 0};
+  int ir[2] = {0, 0}, ic[2] = {0, 0};
+  if (me < nr) {
+    row_tables(me, tr);
+    if (PROLONG) row_prolong(me, ir, wr);
+  }
+  if (me < nc) {
+    col_tables(me, tc);
+    if (PROLONG) col_prolong(me, ic, wc);
+  }
+  // stores of the first batch
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int t = threadIdx.x + k * NT;
+    if (!PROLONG && t < n_u) sh[t] = ub[k];
+  }
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int t = threadIdx.x + k * NT;
+    if (t < n_f) {
+      int i, j;
+      f_pos(t, i, j);
+      fs[(i - r0) * nc + (j - c0)] = fb[k];
+    }
+  }
+  if (me < nr) store_row(me, tr, ir, wr);
+  if (me < nc) store_col(me, tc, ic, wc);
+  // the rest of larger tiles
+  if (!PROLONG) {
+#pragma unroll 4
+    for (int t = threadIdx.x + KB * NT; t < n_u; t += NT) {
+      int i, j;
+      V v = mkv<R>(0, 0);
+      if (u_pos(t, i, j)) v = u[(size_t)i * nb + j];
+      sh[t] = v;
+    }
+  }
+#pragma unroll 4
+  for (int t = threadIdx.x + KB * NT; t < n_f; t += NT) {
+    int i, j;
+    f_pos(t, i, j);
+    fs[(i - r0) * nc + (j - c0)] = f[(size_t)i * nb + j];
+  }
+  for (int rr = me + NT; rr < nr; rr += NT) {
+    R tr2[5], w2[2] = {0, 0};
+    int ix2[2] = {0, 0};
+    row_tables(rr, tr2);
+    if (PROLONG) row_prolong(rr, ix2, w2);
+    store_row(rr, tr2, ix2, w2);
+  }
+  for (int cc = me + NT; cc < nc; cc += NT) {
+    R tc2[4], w2[2] = {0, 0};
+    int ix2[2] = {0, 0};
+    col_tables(cc, tc2);
+    if (PROLONG) col_prolong(cc, ix2, w2);
+    store_col(cc, tc2, ix2, w2);
+  }
   if constexpr (PROLONG) {
-    int* pix = reinterpret_cast<int*>(c4 + nc);          // a0, a1 per row; b0, b1 per column
-    R* pwt = reinterpret_cast<R*>(pix + 2 * (nr + nc));  // the matching weights
-    const int par = m & 1;
-    for (int rr = threadIdx.x; rr < nr; rr += blockDim.x) {
-      const int i = min(max(r0 + rr, 0), na - 1);
-      pix[rr] = gbl(L.pa_i0)[i];
-      pix[nr + rr] = gbl(L.pa_i1)[i];
-      pwt[rr] = (R)gbl(L.pa_w0)[i];
-      pwt[nr + rr] = (R)gbl(L.pa_w1)[i];
-    }
-    for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
-      const int j = min(max(c0 + cc, 0), nb - 1);
-      pix[2 * nr + cc] = gbl(L.pb_i0)[par * nb + j];
-      pix[2 * nr + nc + cc] = gbl(L.pb_i1)[par * nb + j];
-      pwt[2 * nr + cc] = (R)gbl(L.pb_w0)[par * nb + j];
-      pwt[2 * nr + nc + cc] = (R)gbl(L.pb_w1)[par * nb + j];
-    }
+    // u tile plus the interpolated coarse correction, from the staged tables
     __syncthreads();
     const int cnb = J.C.nb;
     const auto uc = gbl(static_cast<const V*>(J.uc) + (size_t)slot * J.C.na * cnb);
 #pragma unroll 4
-    for (int t = threadIdx.x; t < nr * nc; t += blockDim.x) {
+    for (int t = threadIdx.x; t < n_u; t += NT) {
       const int rr = t / nc, cc = t - rr * nc;
-      const int i = r0 + rr, j = c0 + cc;
+      int i, j;
       V v = mkv<R>(0, 0);
-      if (cc < ncu && i >= 0 && i < na && j >= 0 && j < nb) {
+      if (u_pos(t, i, j)) {
         const int a0 = pix[rr], a1 = pix[nr + rr], b0 = pix[2 * nr + cc], b1 = pix[2 * nr + nc + cc];
         const R wa0 = pwt[rr], wa1 = pwt[nr + rr], wb0 = pwt[2 * nr + cc], wb1 = pwt[2 * nr + nc + cc];
         // same operations in the same order as coarse_corr + add (k_prolong),
@@ -196,47 +326,6 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
       }
       sh[t] = v;
     }
-  } else {
-#pragma unroll 4
-    for (int t = threadIdx.x; t < nr * nc; t += blockDim.x) {
-      const int rr = t / nc, cc = t - rr * nc;
-      const int i = r0 + rr, j = c0 + cc;
-      V v = mkv<R>(0, 0);
-      if (cc < ncu && i >= 0 && i < na && j >= 0 && j < nb) v = u[(size_t)i * nb + j];
-      sh[t] = v;
-    }
-  }
-  if (EXACT) {
-  } else if (DIR == 1) {
-#pragma unroll 4
-    for (int t = threadIdx.x; t < (fend - fbeg) * nb; t += blockDim.x) {
-      const int i = fbeg + t / nb, j = t % nb;
-      fs[(i - r0) * nc + (j - c0)] = f[(size_t)i * nb + j];
-    }
-  } else {
-    const int w = fend - fbeg;
-#pragma unroll 4
-    for (int t = threadIdx.x; t < na * w; t += blockDim.x) {
-      const int i = t / w, j = fbeg + t % w;
-      fs[(i - r0) * nc + (j - c0)] = f[(size_t)i * nb + j];
-    }
-  }
-  for (int rr = threadIdx.x; rr < nr; rr += blockDim.x) {
-    const int i = r0 + rr;
-    const bool in = i >= 0 && i < na;
-    t0[rr] = in ? (R)gbl(L.ua)[i] : (R)0;
-    t1[rr] = in ? (R)gbl(L.da)[i] : (R)0;
-    t2[rr] = in ? (R)gbl(L.Rr)[i] : (R)0;
-    t3[rr] = in ? (R)gbl(L.Ca)[(size_t)m * na + i] : (R)1;
-    t4[rr] = in ? (R)gbl(L.wb)[(size_t)m * na + i] : (R)0;
-  }
-  for (int cc = threadIdx.x; cc < nc; cc += blockDim.x) {
-    const int j = c0 + cc;
-    const bool in = j >= 0 && j < nb;
-    c1[cc] = in ? (R)gbl(L.ub)[j] : (R)0;
-    c2[cc] = in ? (R)gbl(L.db)[j] : (R)0;
-    c3[cc] = in ? (R)gbl(L.Cb)[(size_t)m * nb + j] : (R)0;
-    c4[cc] = in ? (R)gbl(L.wr)[(size_t)m * nb + j] : (R)0;
   }
   __syncthreads();
   const LineView<R> view{sh, nc, -r0, -c0, fs, nc, -r0, -c0, t0, t1, t2, t3, t4, -r0, c1, c2, c3, c4, -c0};
