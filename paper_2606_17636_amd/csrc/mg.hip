@@ -33,6 +33,7 @@
 namespace {
 
 constexpr int kThreads = 256;
+constexpr unsigned kXcds = 8;  // accelerator complex dies of the device, each with its own L2
 
 // Residual f - L u at (i, j) of one plane, reading u from global memory (R).
 template <typename R>
@@ -109,11 +110,20 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
   using V = typename Vec<R>::T;
   extern __shared__ char smem[];
   V* sh = reinterpret_cast<V*>(smem);
-  const int p = blockIdx.y;
+  // XCD-aware block order: the hardware deals consecutive blocks round-robin
+  // over the XCDs, so neighbouring tiles of a plane would each fetch their
+  // shared halo lines and partial cache lines into a different L2.  The
+  // blocks are renumbered so that the tiles of a plane are consecutive on one
+  // XCD (a bijection on the grid: XCD x takes ceil or floor of nblk / kXcds
+  // consecutive logical blocks).
+  const unsigned nblk = gridDim.x * gridDim.y, bid = blockIdx.x + gridDim.x * blockIdx.y;
+  const unsigned xcd = bid % kXcds, kk = bid / kXcds, per = nblk / kXcds, rem = nblk % kXcds;
+  const unsigned lid = xcd < rem ? xcd * (per + 1) + kk : rem * (per + 1) + (xcd - rem) * per + kk;
+  const int bx = (int)(lid % gridDim.x), p = (int)(lid / gridDim.x);
   if (bt.count && p >= *bt.count) return;
   const int e = bt.ent[p];
   const LvJob& J = jobs[ent_prob(e)];
-  if (!J.active || (int)blockIdx.x >= J.ntile[DIR]) return;
+  if (!J.active || bx >= J.ntile[DIR]) return;
   const int slot = ent_slot(e);
   const int m = J.mode ? J.mode[slot] : slot;
   const LevelDev L = J.L;
@@ -127,20 +137,20 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
   // tile geometry in (row, col) = (i, j) coordinates
   int r0, nr, c0, nc;  // first global row/col held in LDS and counts (incl. halo/pad)
   if (DIR == 1) {
-    const int i0 = blockIdx.x * tile;
+    const int i0 = bx * tile;
     r0 = i0 - 2; nr = tile + 4;
     c0 = -1; nc = nb + 2;
   } else {
     // row stride odd (one unused column when tile + 4 is even): the lanes
     // walk down the columns
-    const int j0 = blockIdx.x * tile;
+    const int j0 = bx * tile;
     r0 = -1; nr = na + 2;
     c0 = j0 - 2; nc = odd_stride(tile + 4);
   }
   const int ncu = DIR == 0 ? tile + 4 : nc;  // columns holding plane data
   V* fs = sh + nr * nc;  // staged f (SOR variant only)
   // line range of this tile (the coordinate across the lines)
-  const int lbeg = blockIdx.x * tile;                     // first owned line
+  const int lbeg = bx * tile;                             // first owned line
   const int nlines_total = DIR == 1 ? na : nb;
   const int lend = min(lbeg + tile, nlines_total);        // one past the last owned line
   const int npts = DIR == 1 ? nb : na;                    // points per line
