@@ -172,37 +172,57 @@ constexpr int kSepChunk = 8;
 // rounds alike; about 512 (system, segment) pairs, at most 16 segments.
 __host__ __device__ constexpr int sep_seg_max(int nb) { return nb >= 256 ? 1 : (nb >= 16 ? 256 / nb : 16); }
 
+// Row transform of the exact coarse solve on the FP64 matrix cores:
+// x[i][c] <- sum_r M[r][c] x[i][r] for every row i (x complex, M real, both
+// in LDS).  The complex rows split into real rows rho = 2 i + component,
+// which makes the transform a real (2 na x nb) by (nb x nb) product.  A wave
+// owns 16 real rows (8 complex rows) and all columns: one accumulator per
+// 16-column tile, K in steps of 4, one v_mfma_f64_16x16x4 per (tile, step).
+// Operand layout of that instruction: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; element e of its result is D[4 e + l / 16][l % 16].
+// Rows, columns and K beyond the sizes are zero operands and are not
+// written.  The wave has read all of its rows (its own LDS reads complete in
+// order) before it writes them, and no other wave touches them, so the
+// transform runs in place.
+typedef double sep_d4 __attribute__((ext_vector_type(4)));
+constexpr int kSepMaxTiles = 8;  // nb <= 128 (the host builds no tables beyond)
+
 __device__ __forceinline__ void sep_rows(double2* x, int na, int nb, const double* M) {
-  // x[i][c] <- sum_r M[r][c] x[i][r] for every row i.  ng threads share a
-  // row (ng a power of two with 4 ng >= nb, so a row's threads sit in one
-  // wave), thread g computing the columns c = g + ng k, k < 4; the wave reads
-  // the whole row before it writes, so no other wave touches the row.
-  int ng = 1;
-  while (4 * ng < nb) ng *= 2;
-  for (int t = threadIdx.x; t < na * ng; t += blockDim.x) {
-    const int i = t / ng, g = t - i * ng;
-    double2* row = x + i * nb;
-    int c[4];
+  double* X = reinterpret_cast<double*>(x);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  const int lm = lane & 15, lk = lane >> 4;
+  const int nrow = 2 * na, nrb = (nrow + 15) >> 4, nct = (nb + 15) >> 4;
+  for (int rb = wave; rb < nrb; rb += nwave) {  // uniform in the wave
+    const int rho_a = rb * 16 + lm;
+    const bool row_ok = rho_a < nrow;
+    const int abase = (rho_a >> 1) * nb * 2 + (rho_a & 1);
+    sep_d4 acc[kSepMaxTiles];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) c[k] = min(g + ng * k, nb - 1);
-    double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int r = 0; r < nb; ++r) {
-      const double2 v = row[r];
-      const double* mr = M + r * nb;
+    for (int t = 0; t < kSepMaxTiles; ++t) acc[t] = (sep_d4){0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < nb; k0 += 4) {
+      const int r = k0 + lk;
+      const bool k_ok = r < nb;
+      const double av = row_ok && k_ok ? X[abase + 2 * r] : 0.0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const double mv = mr[c[k]];
-        ax[k] = fma(mv, v.x, ax[k]);
-        ay[k] = fma(mv, v.y, ay[k]);
+      for (int t = 0; t < kSepMaxTiles; ++t) {
+        if (t < nct) {
+          const int c = t * 16 + lm;
+          const double bv = k_ok && c < nb ? M[r * nb + c] : 0.0;
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+        }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (g + ng * k < nb) row[g + ng * k] = make_double2(ax[k], ay[k]);
+    for (int t = 0; t < kSepMaxTiles; ++t) {
+      if (t < nct) {
+        const int c = t * 16 + lm;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int rho = rb * 16 + 4 * e + lk;
+          if (rho < nrow && c < nb) X[((rho >> 1) * nb + c) * 2 + (rho & 1)] = acc[t][e];
+        }
+      }
+    }
   }
 }
 
