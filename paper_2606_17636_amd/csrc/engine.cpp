@@ -208,6 +208,7 @@ smg_status Engine::build_jobs(int target, const MGConfig& c, std::vector<LvJob>&
       LdsJob& J = lds[q];
       J.LL = lds_levels(pr, first, prm_.exact, prm_.fp32);
       if (smgk::lds_cycle_bytes(J.LL, prm_.fp32) > lds_cycle_max()) return SMG_EINVAL;
+      smgk::lds_cycle_layout(J.LL, prm_.fp32, J.off);
       J.u = first == 0 && !prm_.fp32 ? (void*)pr.u0[target] : pr.u[first];
       J.f = first == 0 && !prm_.fp32 ? (const void*)pr.f0[target] : pr.f[first];
       J.mode = pr.mode;

@@ -199,6 +199,7 @@ __device__ __forceinline__ void sep_rows(double2* x, int na, int nb, const doubl
     sep_d4 acc[kSepMaxTiles];
 #pragma unroll
     for (int t = 0; t < kSepMaxTiles; ++t) acc[t] = (sep_d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
     for (int k0 = 0; k0 < nb; k0 += 4) {
       const int r = k0 + lk;
       const bool k_ok = r < nb;
@@ -227,9 +228,9 @@ __device__ __forceinline__ void sep_rows(double2* x, int na, int nb, const doubl
 }
 
 __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<double>& T, int m, double2* f,
-                                                 const double* vt, double* fac) {
+                                                 const double* vt, double* fac, bool staged) {
   const int na = L.na, nb = L.nb, nn = na * nb;
-  {
+  if (!staged) {
     const auto gcp = gbl(L.sep_cp + (size_t)m * nn), gid = gbl(L.sep_id + (size_t)m * nn);
 #pragma unroll 4
     for (int t = threadIdx.x; t < nn; t += blockDim.x) {
@@ -390,7 +391,7 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
 // [region A] [scratch] [tables], where region A holds level 0's f while
 // level 0 is smoothed and [coarsest u, f] [levels 1..cl-1: u, f] between
 // the restriction from level 0 and the prolongation to it.
-constexpr int kLayoutSlots = 3 * kMaxLdsLevels + 5;
+constexpr int kLayoutSlots = kLdsLayoutSlots;
 template <typename R>
 __host__ __device__ inline void lds_layout(const LdsLevels& LL, int* o) {
   using V = typename Vec<R>::T;
@@ -470,7 +471,7 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
   // LDS and turned into pointers at each use, so that the pointers stay
   // known as LDS addresses and no per-thread array is indexed dynamically)
   __shared__ int s_off[kLayoutSlots];
-  if (threadIdx.x == 0) lds_layout<R>(LL, s_off);
+  for (int t = threadIdx.x; t < kLayoutSlots; t += blockDim.x) s_off[t] = J.off[t];  // laid out by the host
   __syncthreads();
   // coarsest arrays: f (and, for the SOR fallback, the padded u before it)
   const bool sep = LC.sep_v != nullptr;
@@ -484,13 +485,39 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
   R* cp = reinterpret_cast<R*>(smem + s_off[3 * kMaxLdsLevels + 1]);
   Tab<double> tabC = stage_tab<double>(LC, m, reinterpret_cast<double*>(smem + s_off[2 * kMaxLdsLevels + cl]));
   double* sepV = reinterpret_cast<double*>(smem + s_off[3 * kMaxLdsLevels + 3]);
+  double* sepF = reinterpret_cast<double*>(smem + s_off[3 * kMaxLdsLevels + 4]);
+  // A kernel whose only level is the coarsest stages the Thomas factors and
+  // f together with the eigenvector tables (one round of memory latency);
+  // otherwise the factors share LDS with the finer levels and are staged by
+  // the coarse solve itself.
+  const bool pre = sep && n == 1;
   if (sep) {
-    const int nn = LC.nb * LC.nb;
+    const int nn = LC.nb * LC.nb, nf = pre ? LC.na * LC.nb : 0;
     const auto gv = gbl(LC.sep_v + (size_t)m * nn), gvi = gbl(LC.sep_vi + (size_t)m * nn);
+    const auto gcp = gbl(LC.sep_cp + (size_t)m * LC.na * LC.nb), gid = gbl(LC.sep_id + (size_t)m * LC.na * LC.nb);
+    const size_t off = (size_t)slot * LC.na * LC.nb;
 #pragma unroll 4
-    for (int t = threadIdx.x; t < nn; t += blockDim.x) {
-      sepV[t] = gv[t];
-      sepV[nn + t] = gvi[t];
+    for (int t = threadIdx.x; t < max(nn, nf); t += blockDim.x) {
+      double v0 = 0.0, v1 = 0.0, c0 = 0.0, c1 = 0.0;
+      V fv = mkv<R>(0, 0);
+      if (t < nn) {
+        v0 = gv[t];
+        v1 = gvi[t];
+      }
+      if (t < nf) {
+        c0 = gcp[t];
+        c1 = gid[t];
+        fv = Fg[off + t];
+      }
+      if (t < nn) {
+        sepV[t] = v0;
+        sepV[nn + t] = v1;
+      }
+      if (t < nf) {
+        sepF[t] = c0;
+        sepF[nf + t] = c1;
+        fC[t] = make_double2(fv.x, fv.y);
+      }
     }
   }
   for (int l = 0; l < cl; ++l) (void)stage_tab<R>(LL.L[l], m, reinterpret_cast<R*>(smem + s_off[2 * kMaxLdsLevels + l]));
@@ -513,7 +540,7 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
         const int i = t / nb, j = t - i * nb;
         Fl(0)[i * fs + j] = Fg[off + t];
       }
-    } else {
+    } else if (!pre) {
 #pragma unroll 4
       for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
         const V v = Fg[off + t];
@@ -580,7 +607,7 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
   // factors exist (the solution replaces f in place), otherwise by red-black
   // SOR from zero until the residual 2-norm dropped by rtol (Sec. 3.3)
   if (sep) {
-    coarse_separable(LC, tabC, m, fC, sepV, reinterpret_cast<double*>(smem + s_off[3 * kMaxLdsLevels + 4]));
+    coarse_separable(LC, tabC, m, fC, sepV, sepF, pre);
   } else {
     const LevelDev& L = LC;
     const Tab<double>& T = tabC;
@@ -721,6 +748,11 @@ int lds_cycle_scratch(const LdsLevels& LL, bool exact) {
       scratch = scratch > b ? scratch : b;
     }
   return (int)((scratch + 1) / 2 * 2);  // even: keeps the FP64 tables that follow 8-byte aligned
+}
+
+void lds_cycle_layout(const LdsLevels& LL, bool fp32, int* off) {
+  if (fp32) lds_layout<float>(LL, off);
+  else lds_layout<double>(LL, off);
 }
 
 size_t lds_cycle_bytes(const LdsLevels& LL, bool fp32) {

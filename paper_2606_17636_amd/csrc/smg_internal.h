@@ -180,8 +180,10 @@ struct LvJob {
 };
 
 // One problem's fused coarse end of the V-cycle (mg_lds.hip).
+constexpr int kLdsLayoutSlots = 3 * kMaxLdsLevels + 5;
 struct LdsJob {
   LdsLevels LL;
+  int off[kLdsLayoutSlots];  // LDS byte offsets of the cycle's arrays (smgk::lds_cycle_layout)
   void* u;           // first fused level arrays (R typed; the coarsest is FP64)
   const void* f;
   const int* mode;
@@ -249,6 +251,8 @@ struct SmoothShape { int tile, ntile, scratch; size_t lds; };
 bool smooth_shape(const LevelDev& L, int dir, bool exact, bool fp32, int target_blocks, int planes, SmoothShape* out);
 // fused coarse cycle (mg_lds.hip)
 size_t lds_cycle_bytes(const LdsLevels& LL, bool fp32);
+// The LDS byte offsets of the fused cycle's arrays, as the kernel uses them.
+void lds_cycle_layout(const LdsLevels& LL, bool fp32, int* off);
 // Largest first-level f the aliased layout can restrict through registers.
 bool lds_cycle_alias_ok(const LdsLevels& LL);
 int lds_cycle_scratch(const LdsLevels& LL, bool exact);
