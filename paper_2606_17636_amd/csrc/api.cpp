@@ -129,6 +129,8 @@ struct PlanProf : ProfSink {
   const smg_plan* p = nullptr;
   int mark(hipStream_t st) override;
   void close(int cls, int ev, double bytes, hipStream_t st) override;
+  int launch_events(hipEvent_t* start, hipEvent_t* stop) override;
+  void close_launch(int cls, int id, double bytes) override;
 };
 
 // A captured solve body (both multigrid solves and the boundary steps) for
@@ -483,10 +485,36 @@ static void prof_close(const smg_plan& p, int cls, int ev0, double bytes, hipStr
 
 int PlanProf::mark(hipStream_t st) { return prof_mark(*p, st); }
 
+// two pool events, not recorded here: the launch records them
+static int prof_take(const smg_plan& p) {
+  if (!p.prof_on) return -1;
+  while (p.prof_pool.size() < p.prof_used + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    p.prof_pool.push_back(e);
+  }
+  p.prof_used += 2;
+  return (int)p.prof_used - 2;
+}
+
+int PlanProf::launch_events(hipEvent_t* start, hipEvent_t* stop) {
+  const int id = prof_take(*p);
+  if (id < 0) return -1;
+  *start = p->prof_pool[id];
+  *stop = p->prof_pool[id + 1];
+  return id;
+}
+
 void PlanProf::close(int cls, int ev, double bytes, hipStream_t st) {
   static const int map[] = {K_SMOOTH_RADIAL0, K_SMOOTH_POLAR0, K_SMOOTH_COARSE, K_RESTRICT, K_PROLONG,
                             K_COARSE,         K_NORM,          K_ACCUM,         K_NORM};
   prof_close(*p, map[cls], ev, bytes, st);
+}
+
+void PlanProf::close_launch(int cls, int id, double bytes) {
+  static const int map[] = {K_SMOOTH_RADIAL0, K_SMOOTH_POLAR0, K_SMOOTH_COARSE, K_RESTRICT, K_PROLONG,
+                            K_COARSE,         K_NORM,          K_ACCUM,         K_NORM};
+  if (id >= 0) p->prof_log.push_back({map[cls], id, id + 1, bytes});
 }
 
 // ----------------------------------------------------------------------------

@@ -283,13 +283,19 @@ smg_status Engine::vcycle(int target, int c, const BatchRef& b, hipStream_t st, 
   auto smooth = [&](int d, bool prolong, bool acc) -> hipError_t {
     for (int dir = 0; dir < 2; ++dir) {
       const bool pr = prolong && dir == 0, ac = acc && dir == 1;
-      const int ev = prof_ ? prof_->mark(st) : -1;
+      // profiled: the smoother launch records its own start and stop
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      const int id = prof_ ? prof_->launch_events(&e0, &e1) : -1;
+      const int ev = prof_ && id < 0 ? prof_->mark(st) : -1;
+      if (id >= 0) smgk::next_launch_events(e0, e1);
       hipError_t e = smgk::mg_smooth_dir(dl + (size_t)d * P, hl + (size_t)d * P, P, b, prm_.n_sor, prm_.exact, dir,
                                          f32, st, pr, ac);
+      smgk::next_launch_events(nullptr, nullptr);
       if (e != hipSuccess) return e;
-      if (prof_)
-        prof_->close(d == 0 ? (dir == 0 ? EC_SMOOTH_R0 : EC_SMOOTH_P0) : EC_SMOOTH_C, ev,
-                     ((pr ? 3.25 : 3.0) * vb + (ac ? 32.0 - vb : 0.0)) * cells(d, false), st);
+      const int cls = d == 0 ? (dir == 0 ? EC_SMOOTH_R0 : EC_SMOOTH_P0) : EC_SMOOTH_C;
+      const double bytes = ((pr ? 3.25 : 3.0) * vb + (ac ? 32.0 - vb : 0.0)) * cells(d, false);
+      if (id >= 0) prof_->close_launch(cls, id, bytes);
+      else if (prof_) prof_->close(cls, ev, bytes, st);
     }
     return hipSuccess;
   };
@@ -524,9 +530,13 @@ smg_status Engine::autotune(int target, hipStream_t st, std::string* report) {
   std::vector<MGConfig> best;
   std::string rep;
   const int scratch = kMaxConfigs - 2;
+  // Within a bucket the first candidate (in the order tried: fused range
+  // from the finest feasible level, then fewer blocks) whose time is within
+  // kTuneTie of the fastest is kept, so that near-equal candidates do not
+  // trade places from one process to the next on timing noise.
+  constexpr float kTuneTie = 1.03f;
   for (int cap : caps) {
-    MGConfig bc;
-    float bt = 1e30f;
+    std::vector<std::pair<MGConfig, float>> cand;
     for (int off = 0; off < 3; ++off) {
       bool any_new = false;
       MGConfig c;
@@ -555,7 +565,7 @@ smg_status Engine::autotune(int target, hipStream_t st, std::string* report) {
         smg_status s = vcycle_all(target, cap, scratch, st);
         if (s == SMG_OK) {
           EHIP(hipEventRecord(e0, st));
-          for (int r = 0; r < 3 && s == SMG_OK; ++r) s = vcycle_all(target, cap, scratch, st);
+          for (int r = 0; r < 5 && s == SMG_OK; ++r) s = vcycle_all(target, cap, scratch, st);
           EHIP(hipEventRecord(e1, st));
           EHIP(hipEventSynchronize(e1));
         }
@@ -563,12 +573,20 @@ smg_status Engine::autotune(int target, hipStream_t st, std::string* report) {
         if (s != SMG_OK) return s;
         float ms = 0.f;
         EHIP(hipEventElapsedTime(&ms, e0, e1));
-        ms /= 3.f;
+        ms /= 5.f;
         rep += strprintf("planes %d: fused from +%d, %d blocks: %.1f us\n", cap, off, tb, 1e3 * ms);
-        if (ms < bt) { bt = ms; bc = c; }
+        cand.emplace_back(c, ms);
       }
     }
-    if (bt >= 1e30f) EFAIL(SMG_EINVAL, "autotune: no configuration fits");
+    if (cand.empty()) EFAIL(SMG_EINVAL, "autotune: no configuration fits");
+    float bt = 1e30f;
+    for (const auto& cm : cand) bt = std::min(bt, cm.second);
+    MGConfig bc = cand[0].first;
+    for (const auto& cm : cand)
+      if (cm.second <= kTuneTie * bt) {
+        bc = cm.first;
+        break;
+      }
     rep += strprintf("planes <= %d: fused from level %d (+%d), %d blocks\n", cap, bc.lds_first[0], bc.lds_first[0] - first_min_[0], bc.target_blocks);
     best.push_back(bc);
   }

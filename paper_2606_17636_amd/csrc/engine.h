@@ -47,6 +47,11 @@ struct ProfSink {
   virtual ~ProfSink() = default;
   virtual int mark(hipStream_t st) = 0;
   virtual void close(int cls, int ev, double bytes, hipStream_t st) = 0;
+  // An unrecorded event pair for a launch that records its own start and
+  // stop (the dispatch's timestamps; smgk::next_launch_events): returns an
+  // id for close_launch, or -1 when the sink has none.
+  virtual int launch_events(hipEvent_t* start, hipEvent_t* stop) { (void)start; (void)stop; return -1; }
+  virtual void close_launch(int cls, int id, double bytes) { (void)cls; (void)id; (void)bytes; }
 };
 enum EngineClass { EC_SMOOTH_R0, EC_SMOOTH_P0, EC_SMOOTH_C, EC_RESTRICT, EC_PROLONG, EC_COARSE, EC_NORM, EC_ACCUM, EC_CONV };
 

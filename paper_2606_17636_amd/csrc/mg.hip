@@ -26,6 +26,8 @@
 #include <algorithm>
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "relax_dev.h"
 #include "smg_internal.h"
 #include "vec.h"
@@ -599,6 +601,13 @@ bool smooth_shape(const LevelDev& L, int dir, bool exact, bool fp32, int target_
   return out->lds <= lds_limit();
 }
 
+static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+
+void next_launch_events(hipEvent_t start, hipEvent_t stop) {
+  t_ev_start = start;
+  t_ev_stop = stop;
+}
+
 template <typename R>
 static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, int n_sor,
                                 bool exact, int dir, bool prolong, bool acc, hipStream_t st) {
@@ -637,7 +646,14 @@ static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, 
     if (acc && hj[q].active && !hj[q].acc) return hipErrorInvalidValue;
     if (hj[q].active && (!hj[q].u || !hj[q].u2)) return hipErrorInvalidValue;
   }
-  auto go = [&](auto kern, int nt) { hipLaunchKernelGGL(kern, grid, dim3(nt), lds, st, jobs, b, n_sor); };
+  auto go = [&](auto kern, int nt) {
+    if (t_ev_start) {
+      hipExtLaunchKernelGGL(kern, grid, dim3(nt), lds, st, t_ev_start, t_ev_stop, 0u, jobs, b, n_sor);
+      t_ev_start = t_ev_stop = nullptr;
+    } else {
+      hipLaunchKernelGGL(kern, grid, dim3(nt), lds, st, jobs, b, n_sor);
+    }
+  };
   // radial launch with or without the coarse correction; polar launch
   // storing the lines or adding them to the FP64 iterate
   auto go0 = [&](auto kern_plain, auto kern_prolong, int nt) { prolong ? go(kern_prolong, nt) : go(kern_plain, nt); };

@@ -233,6 +233,10 @@ hipError_t fft_c2r(const double2* modes, double* out, int n_lines, int n_phi, co
                    hipStream_t st);
 // Multigrid (mg.hip).  `jobs` is the device array of one depth's LvJob per
 // problem, `hj` its host mirror (used only to size the grid and LDS).
+// The next smoother launch on this host thread records its start and stop
+// on these events (hipExtLaunchKernelGGL: the dispatch's own timestamps, no
+// event commands around the launch); one launch consumes them.
+void next_launch_events(hipEvent_t start, hipEvent_t stop);
 // With prolong set (radial lines, dir 0, only) the launch first adds the
 // prolonged coarse correction (the job's uc) to u, in place of an
 // mg_prolong launch.  With accumulate set (polar lines, dir 1, FP32 only)
