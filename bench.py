@@ -91,11 +91,13 @@ def cpu_baseline(workload, tol, budget_s):
 
 def _plan(smg, g, form, line_solver, max_cycles=60):
     """The chosen form (mixed precision, scheduled graph replay, autotuned
-    launch shapes) or the plain GPU form (FP64, host reads after every
-    V-cycle, built-in launch shapes, the paper's SOR line smoother)."""
+    launch shapes, smoothing steps chosen at setup: V(1,1) when the finest
+    level is smoothed by whole-grid launches, else V(2,2)) or the plain GPU
+    form (FP64, host reads after every V-cycle, built-in launch shapes, the
+    paper's SOR line smoother, V(2,2))."""
     if form == "chosen":
         return smg.Plan(**g, precision="mixed", launch="graph", autotune=True, line_solver=line_solver,
-                        max_cycles=max_cycles, coarse_cells=COARSE_CELLS)
+                        max_cycles=max_cycles, coarse_cells=COARSE_CELLS, nu_pre=smg.NU_AUTO, nu_post=smg.NU_AUTO)
     return smg.Plan(**g, precision="fp64", launch="dynamic", autotune=False, line_solver="sor", max_cycles=max_cycles)
 
 

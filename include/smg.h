@@ -54,6 +54,11 @@ enum { SMG_RADIAL_UNIFORM = 0, SMG_RADIAL_LOG = 1 };
 enum { SMG_FP64 = 0, SMG_MIXED = 1 };
 enum { SMG_DGF_AUTO = 0, SMG_DGF_AUX = 1, SMG_DGF_EXTENDED = 2 };
 enum { SMG_LINE_SOR = 0, SMG_LINE_EXACT = 1 };
+/* nu_pre = nu_post = SMG_NU_AUTO: smoothing steps chosen by the library at
+ * setup: 1 each way when every problem's finest level is too large for the
+ * fused in-LDS V-cycle (each step there costs two whole-grid launches), 2 when
+ * the whole V-cycle runs in that kernel. */
+enum { SMG_NU_AUTO = -1 };
 
 /* Grid of Sec. 2.1.  Radial faces: uniform, or geometric
  * a_min * (a_max/a_min)^(f/n_a) for SMG_RADIAL_LOG.  b faces are uniform;
@@ -76,8 +81,8 @@ typedef struct {
   int precision;         /* SMG_FP64 [default] | SMG_MIXED (FP32 smoothing
                             and transfers, FP64 residual, coarsest solve and
                             correction accumulation: iterative refinement) */
-  int nu_pre;            /* pre-smoothing steps per level [2] */
-  int nu_post;           /* post-smoothing steps per level [2] */
+  int nu_pre;            /* pre-smoothing steps per level [2]; SMG_NU_AUTO */
+  int nu_post;           /* post-smoothing steps per level [2]; SMG_NU_AUTO */
   int n_sor;             /* SOR passes per line relaxation [2] (Sec. 3.2) */
   int max_cycles;        /* V-cycles per mode and solve [60] */
   int dgf_method;        /* SMG_DGF_AUTO [log radial -> extended domain,

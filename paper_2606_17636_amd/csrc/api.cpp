@@ -260,8 +260,10 @@ static smg_status validate(const smg_grid& g, const smg_opts& o) {
   if (g.radial == SMG_RADIAL_UNIFORM && g.a_min - (g.a_max - g.a_min) / g.n_a <= 0.0)
     return fail(SMG_EINVAL, "uniform radial grid: the inner ghost cell reaches r <= 0");
   if (o.precision != SMG_FP64 && o.precision != SMG_MIXED) return fail(SMG_EINVAL, "precision must be SMG_FP64 or SMG_MIXED");
-  if (o.nu_pre < 0 || o.nu_post < 0 || o.nu_pre + o.nu_post < 1 || o.n_sor < 1 || o.max_cycles < 1)
-    return fail(SMG_EINVAL, "need nu_pre + nu_post >= 1, n_sor >= 1, max_cycles >= 1");
+  const bool nu_auto = o.nu_pre == SMG_NU_AUTO && o.nu_post == SMG_NU_AUTO;
+  if (!nu_auto && (o.nu_pre < 0 || o.nu_post < 0 || o.nu_pre + o.nu_post < 1))
+    return fail(SMG_EINVAL, "need nu_pre + nu_post >= 1 (or both SMG_NU_AUTO)");
+  if (o.n_sor < 1 || o.max_cycles < 1) return fail(SMG_EINVAL, "need n_sor >= 1, max_cycles >= 1");
   if (o.n_pad < 2 || o.n_pad > 24) return fail(SMG_EINVAL, "n_pad must be in [2, 24]");
   if (o.dgf_method < SMG_DGF_AUTO || o.dgf_method > SMG_DGF_EXTENDED) return fail(SMG_EINVAL, "bad dgf_method");
   if (o.line_solver != SMG_LINE_SOR && o.line_solver != SMG_LINE_EXACT) return fail(SMG_EINVAL, "bad line_solver");

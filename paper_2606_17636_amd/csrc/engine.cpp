@@ -98,6 +98,17 @@ smg_status Engine::init(std::vector<MGProblem> probs, int n_targets, const MGPar
     first_min_[q] = fm;
   }
   if (n_total_ > kMaxPlanes) EFAIL(SMG_EINVAL, strprintf("a batch holds at most %d planes", kMaxPlanes));
+  // smoothing steps left to the engine (negative): one each way when every
+  // problem smooths its finest level in whole-grid launches, where a step is
+  // two latency-bound launches and fewer steps with more cycles is faster;
+  // two when the whole V-cycle fits the fused kernel
+  if (prm_.nu_pre < 0 || prm_.nu_post < 0) {
+    bool split = true;
+    for (int q = 0; q < P; ++q)
+      if (first_min_[q] == 0) split = false;
+    if (prm_.nu_pre < 0) prm_.nu_pre = split ? 1 : 2;
+    if (prm_.nu_post < 0) prm_.nu_post = split ? 1 : 2;
+  }
   if (bytes < region_bytes(T_, P, Dmax_, n_total_)) EFAIL(SMG_EWORKSPACE, "engine region too small");
   // carve the region
   char* q0 = region;

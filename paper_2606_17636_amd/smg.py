@@ -19,6 +19,7 @@ UNIFORM, LOG = 0, 1
 FP64, MIXED = 0, 1
 DGF_AUTO, DGF_AUX, DGF_EXTENDED = 0, 1, 2
 LINE_SOR, LINE_EXACT = 0, 1
+NU_AUTO = -1  # nu_pre = nu_post = NU_AUTO: smoothing steps chosen at setup
 LAUNCH_GRAPH, LAUNCH_DYNAMIC = 0, 1
 WARM_PREV = 1
 TIMINGS = 2

@@ -88,3 +88,11 @@ def test_coarsening_depth_matches_oracle(cells):
 def test_coarse_cells_is_validated():
     with pytest.raises(smg.SmgError, match="coarse_cells"):
         smg.grid_from_spec(SPECS[0], n_pad=8, coarse_cells=5)
+
+
+def test_smoothing_steps_auto_is_accepted_and_others_validated():
+    # both fields SMG_NU_AUTO: chosen by the engine at setup
+    smg.grid_from_spec(SPECS[0], n_pad=8, nu_pre=smg.NU_AUTO, nu_post=smg.NU_AUTO)
+    for pre, post in [(smg.NU_AUTO, 2), (-2, -2), (0, -1)]:
+        with pytest.raises(smg.SmgError, match="nu_pre"):
+            smg.grid_from_spec(SPECS[0], n_pad=8, nu_pre=pre, nu_post=post)
