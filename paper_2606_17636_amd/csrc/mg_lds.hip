@@ -169,7 +169,9 @@ __device__ __forceinline__ typename Vec<R>::T resid_lds(const LevelDev& L, const
 constexpr int kSepChunk = 8;
 // Segments per tridiagonal system in the exact coarse solve: a function of
 // the level's width only (not of the block size), so that every launch shape
-// rounds alike; about 512 (system, segment) pairs, at most 16 segments.
+// rounds alike; about 512 (system, segment) pairs, at most 16 segments.  The
+// segment-end scratch (forward and backward) takes 6 sep_seg_max(nb) nb
+// doubles.
 __host__ __device__ constexpr int sep_seg_max(int nb) { return nb >= 256 ? 1 : (nb >= 16 ? 256 / nb : 16); }
 
 // Row transform of the exact coarse solve on the FP64 matrix cores:
@@ -258,123 +260,227 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
   S = (na + len - 1) / len;
   double* pend = fac + 2 * nn;     // [S][nb] coefficient product of a segment
   double* eend = pend + S * nb;    // [S][2 nb] local value at the segment's far end
-  // forward sweep, local part
-  for (int t = threadIdx.x; t < nsys * S; t += blockDim.x) {
-    const int l = t % nsys, sg = t / nsys, q = l >> 1;
-    const int beg = sg * len, end = min(na, beg + len);
-    double y = 0.0, P = 1.0;
-    for (int i0 = beg; i0 < end; i0 += kSepChunk) {
-      double v[kSepChunk], pv[kSepChunk], dv[kSepChunk];
+  double* pendB = eend + S * nsys; // the same for the back substitution
+  double* eendB = pendB + S * nb;
+  constexpr int kSegReg = 8;       // segment rows held in registers
+  constexpr int kSegMax = 16;      // sep_seg_max never exceeds it
+  if (len <= kSegReg && nsys * S <= (int)blockDim.x) {
+    // One (system, segment) per thread, its rows in registers through both
+    // sweeps: load once; forward from a zero carry; barrier; forward carry
+    // and fix, then the back substitution from a zero carry, with no barrier
+    // between them (the backward segment ends go to their own scratch);
+    // barrier; backward carry and fix; store once.  Same operations in the
+    // same order as the general path below.
+    const int t = threadIdx.x;
+    const bool act = t < nsys * S;
+    const int l = act ? t % nsys : 0, sg = act ? t / nsys : 0, q = l >> 1;
+    const int beg = sg * len, cnt = act ? min(na, beg + len) - beg : 0;
+    double y[kSegReg], bf[kSegReg], bb[kSegReg];
+    double yl = 0.0, P = 1.0;
 #pragma unroll
-      for (int k = 0; k < kSepChunk; ++k) {
-        const int i = min(i0 + k, end - 1);
-        v[k] = w[2 * i * nb + l];
-        pv[k] = id[i * nb + q];
-        dv[k] = i > 0 ? T.da[i] : 0.0;
+    for (int k = 0; k < kSegReg; ++k) {
+      const int i = beg + min(k, max(cnt - 1, 0));  // clamped into the segment
+      const double wv = w[2 * i * nb + l], iv = id[i * nb + q];
+      const double dv = i > 0 ? T.da[i] : 0.0;
+      const double cv = i < na - 1 ? cp[i * nb + q] : 0.0;
+      const double a = wv * iv;
+      bf[k] = -dv * iv;
+      bb[k] = -cv;
+      if (k < cnt) {
+        yl = fma(bf[k], yl, a);
+        P *= bf[k];
       }
-#pragma unroll
-      for (int k = 0; k < kSepChunk; ++k) {
-        const double a = v[k] * pv[k], b = -dv[k] * pv[k];
-        if (i0 + k < end) {
-          y = fma(b, y, a);
-          P *= b;
-        }
-        v[k] = y;
-      }
-#pragma unroll
-      for (int k = 0; k < kSepChunk; ++k)
-        if (i0 + k < end) w[2 * (i0 + k) * nb + l] = v[k];
+      y[k] = yl;
     }
-    if (S > 1) {
+    if (act && S > 1) {
       if ((l & 1) == 0) pend[sg * nb + q] = P;
-      eend[sg * nsys + l] = y;
+      eend[sg * nsys + l] = yl;
     }
-  }
-  if (S > 1) {
     __syncthreads();
+    if (act) {
+      if (sg > 0) {
+        double c = 0.0;
+        for (int h = 0; h < kSegMax; h += 8) {  // 8 segment ends per round of loads
+          double pe[8], ee[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int j = min(h + k, S - 1);
+            pe[k] = pend[j * nb + q];
+            ee[k] = eend[j * nsys + l];
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (h + k < sg) c = fma(pe[k], c, ee[k]);
+        }
+        double Pk = 1.0;
+#pragma unroll
+        for (int k = 0; k < kSegReg; ++k) {
+          Pk *= bf[k];
+          y[k] = fma(Pk, c, y[k]);
+        }
+      }
+      double xl = 0.0, Q = 1.0;
+#pragma unroll
+      for (int k = kSegReg - 1; k >= 0; --k) {
+        if (k < cnt) {
+          xl = fma(bb[k], xl, y[k]);
+          Q *= bb[k];
+        }
+        y[k] = xl;
+      }
+      if (S > 1) {
+        if ((l & 1) == 0) pendB[sg * nb + q] = Q;
+        eendB[sg * nsys + l] = xl;
+      }
+    }
+    __syncthreads();
+    if (act) {
+      if (sg < S - 1) {
+        double c = 0.0;
+        for (int h = kSegMax - 8; h >= 0; h -= 8) {
+          double pe[8], ee[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int j = min(h + k, S - 1);
+            pe[k] = pendB[j * nb + q];
+            ee[k] = eendB[j * nsys + l];
+          }
+#pragma unroll
+          for (int k = 7; k >= 0; --k)
+            if (h + k > sg && h + k < S) c = fma(pe[k], c, ee[k]);
+        }
+        double Qk = 1.0;
+#pragma unroll
+        for (int k = kSegReg - 1; k >= 0; --k) {
+          if (k < cnt) {
+            Qk *= bb[k];
+            y[k] = fma(Qk, c, y[k]);
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kSegReg; ++k)
+        if (k < cnt) w[2 * (beg + k) * nb + l] = y[k];
+    }
+  } else {
+    // forward sweep, local part
     for (int t = threadIdx.x; t < nsys * S; t += blockDim.x) {
       const int l = t % nsys, sg = t / nsys, q = l >> 1;
-      if (sg == 0) continue;
-      double c = 0.0;
-      for (int s2 = 0; s2 < sg; ++s2) c = fma(pend[s2 * nb + q], c, eend[s2 * nsys + l]);
       const int beg = sg * len, end = min(na, beg + len);
-      double P = 1.0;
+      double y = 0.0, P = 1.0;
       for (int i0 = beg; i0 < end; i0 += kSepChunk) {
         double v[kSepChunk], pv[kSepChunk], dv[kSepChunk];
-#pragma unroll
+  #pragma unroll
         for (int k = 0; k < kSepChunk; ++k) {
           const int i = min(i0 + k, end - 1);
           v[k] = w[2 * i * nb + l];
           pv[k] = id[i * nb + q];
-          dv[k] = T.da[i];
+          dv[k] = i > 0 ? T.da[i] : 0.0;
         }
-#pragma unroll
+  #pragma unroll
         for (int k = 0; k < kSepChunk; ++k) {
-          P *= -dv[k] * pv[k];
-          v[k] = fma(P, c, v[k]);
+          const double a = v[k] * pv[k], b = -dv[k] * pv[k];
+          if (i0 + k < end) {
+            y = fma(b, y, a);
+            P *= b;
+          }
+          v[k] = y;
         }
-#pragma unroll
+  #pragma unroll
         for (int k = 0; k < kSepChunk; ++k)
           if (i0 + k < end) w[2 * (i0 + k) * nb + l] = v[k];
       }
-    }
-  }
-  __syncthreads();
-  // back substitution, local part
-  for (int t = threadIdx.x; t < nsys * S; t += blockDim.x) {
-    const int l = t % nsys, sg = t / nsys, q = l >> 1;
-    const int beg = sg * len, end = min(na, beg + len);
-    double x = 0.0, Q = 1.0;
-    for (int i1 = end - 1; i1 >= beg; i1 -= kSepChunk) {
-      double v[kSepChunk], cv[kSepChunk];
-#pragma unroll
-      for (int k = 0; k < kSepChunk; ++k) {
-        const int i = max(i1 - k, beg);
-        v[k] = w[2 * i * nb + l];
-        cv[k] = i < na - 1 ? cp[i * nb + q] : 0.0;
+      if (S > 1) {
+        if ((l & 1) == 0) pend[sg * nb + q] = P;
+        eend[sg * nsys + l] = y;
       }
-#pragma unroll
-      for (int k = 0; k < kSepChunk; ++k) {
-        if (i1 - k >= beg) {
-          x = fma(-cv[k], x, v[k]);
-          Q *= -cv[k];
-        }
-        v[k] = x;
-      }
-#pragma unroll
-      for (int k = 0; k < kSepChunk; ++k)
-        if (i1 - k >= beg) w[2 * (i1 - k) * nb + l] = v[k];
     }
     if (S > 1) {
-      if ((l & 1) == 0) pend[sg * nb + q] = Q;
-      eend[sg * nsys + l] = x;
+      __syncthreads();
+      for (int t = threadIdx.x; t < nsys * S; t += blockDim.x) {
+        const int l = t % nsys, sg = t / nsys, q = l >> 1;
+        if (sg == 0) continue;
+        double c = 0.0;
+        for (int s2 = 0; s2 < sg; ++s2) c = fma(pend[s2 * nb + q], c, eend[s2 * nsys + l]);
+        const int beg = sg * len, end = min(na, beg + len);
+        double P = 1.0;
+        for (int i0 = beg; i0 < end; i0 += kSepChunk) {
+          double v[kSepChunk], pv[kSepChunk], dv[kSepChunk];
+  #pragma unroll
+          for (int k = 0; k < kSepChunk; ++k) {
+            const int i = min(i0 + k, end - 1);
+            v[k] = w[2 * i * nb + l];
+            pv[k] = id[i * nb + q];
+            dv[k] = T.da[i];
+          }
+  #pragma unroll
+          for (int k = 0; k < kSepChunk; ++k) {
+            P *= -dv[k] * pv[k];
+            v[k] = fma(P, c, v[k]);
+          }
+  #pragma unroll
+          for (int k = 0; k < kSepChunk; ++k)
+            if (i0 + k < end) w[2 * (i0 + k) * nb + l] = v[k];
+        }
+      }
     }
-  }
-  if (S > 1) {
     __syncthreads();
+    // back substitution, local part
     for (int t = threadIdx.x; t < nsys * S; t += blockDim.x) {
       const int l = t % nsys, sg = t / nsys, q = l >> 1;
-      if (sg == S - 1) continue;
-      double c = 0.0;
-      for (int s2 = S - 1; s2 > sg; --s2) c = fma(pend[s2 * nb + q], c, eend[s2 * nsys + l]);
       const int beg = sg * len, end = min(na, beg + len);
-      double Q = 1.0;
+      double x = 0.0, Q = 1.0;
       for (int i1 = end - 1; i1 >= beg; i1 -= kSepChunk) {
         double v[kSepChunk], cv[kSepChunk];
-#pragma unroll
+  #pragma unroll
         for (int k = 0; k < kSepChunk; ++k) {
           const int i = max(i1 - k, beg);
           v[k] = w[2 * i * nb + l];
-          cv[k] = cp[i * nb + q];
+          cv[k] = i < na - 1 ? cp[i * nb + q] : 0.0;
         }
-#pragma unroll
+  #pragma unroll
         for (int k = 0; k < kSepChunk; ++k) {
-          Q *= -cv[k];
-          v[k] = fma(Q, c, v[k]);
+          if (i1 - k >= beg) {
+            x = fma(-cv[k], x, v[k]);
+            Q *= -cv[k];
+          }
+          v[k] = x;
         }
-#pragma unroll
+  #pragma unroll
         for (int k = 0; k < kSepChunk; ++k)
           if (i1 - k >= beg) w[2 * (i1 - k) * nb + l] = v[k];
+      }
+      if (S > 1) {
+        if ((l & 1) == 0) pend[sg * nb + q] = Q;
+        eend[sg * nsys + l] = x;
+      }
+    }
+    if (S > 1) {
+      __syncthreads();
+      for (int t = threadIdx.x; t < nsys * S; t += blockDim.x) {
+        const int l = t % nsys, sg = t / nsys, q = l >> 1;
+        if (sg == S - 1) continue;
+        double c = 0.0;
+        for (int s2 = S - 1; s2 > sg; --s2) c = fma(pend[s2 * nb + q], c, eend[s2 * nsys + l]);
+        const int beg = sg * len, end = min(na, beg + len);
+        double Q = 1.0;
+        for (int i1 = end - 1; i1 >= beg; i1 -= kSepChunk) {
+          double v[kSepChunk], cv[kSepChunk];
+  #pragma unroll
+          for (int k = 0; k < kSepChunk; ++k) {
+            const int i = max(i1 - k, beg);
+            v[k] = w[2 * i * nb + l];
+            cv[k] = cp[i * nb + q];
+          }
+  #pragma unroll
+          for (int k = 0; k < kSepChunk; ++k) {
+            Q *= -cv[k];
+            v[k] = fma(Q, c, v[k]);
+          }
+  #pragma unroll
+          for (int k = 0; k < kSepChunk; ++k)
+            if (i1 - k >= beg) w[2 * (i1 - k) * nb + l] = v[k];
+        }
       }
     }
   }
@@ -406,7 +512,7 @@ __host__ __device__ inline void lds_layout(const LdsLevels& LL, int* o) {
   // staged Thomas factors of the level, 2 na nb doubles, and the segment-end
   // scratch of the tridiagonal solves
   const int cbf = al((int)sizeof(double2) * ((sep ? 0 : (nac + 2) * (nbc + 2)) + nac * nbc));
-  const int cb = cbf + (sep ? al((int)sizeof(double) * (2 * nac * nbc + 3 * sep_seg_max(nbc) * nbc)) : 0);
+  const int cb = cbf + (sep ? al((int)sizeof(double) * (2 * nac * nbc + 6 * sep_seg_max(nbc) * nbc)) : 0);
   int q = 0;
   if (LL.alias && cl > 0) {
     o[0] = 0;
