@@ -102,13 +102,13 @@ smg_status Engine::init(std::vector<MGProblem> probs, int n_targets, const MGPar
   // problem smooths its finest level in whole-grid launches, where a step is
   // two latency-bound launches and fewer steps with more cycles is faster;
   // two when the whole V-cycle fits the fused kernel
-  if (prm_.nu_pre < 0 || prm_.nu_post < 0) {
-    bool split = true;
-    for (int q = 0; q < P; ++q)
-      if (first_min_[q] == 0) split = false;
-    if (prm_.nu_pre < 0) prm_.nu_pre = split ? 1 : 2;
-    if (prm_.nu_post < 0) prm_.nu_post = split ? 1 : 2;
-  }
+  bool split = true;
+  for (int q = 0; q < P; ++q)
+    if (first_min_[q] == 0) split = false;
+  if (prm_.nu_pre < 0) prm_.nu_pre = split ? 1 : 2;
+  if (prm_.nu_post < 0) prm_.nu_post = split ? 1 : 2;
+  // every configuration then smooths the finest level first (lds_first >= 1)
+  zero_first_ = prm_.fp32 && split && prm_.nu_pre >= 1;
   if (bytes < region_bytes(T_, P, Dmax_, n_total_)) EFAIL(SMG_EWORKSPACE, "engine region too small");
   // carve the region
   char* q0 = region;
@@ -291,20 +291,20 @@ smg_status Engine::vcycle(int target, int c, const BatchRef& b, hipStream_t st, 
   // applies the coarse-grid correction (reads the coarse correction too);
   // with acc set its last launch adds the FP32 correction to the FP64
   // iterate (reads and writes the FP64 iterate instead of storing FP32)
-  auto smooth = [&](int d, bool prolong, bool acc) -> hipError_t {
+  auto smooth = [&](int d, bool prolong, bool acc, bool zero) -> hipError_t {
     for (int dir = 0; dir < 2; ++dir) {
-      const bool pr = prolong && dir == 0, ac = acc && dir == 1;
+      const bool pr = prolong && dir == 0, ac = acc && dir == 1, z = zero && dir == 0;
       // profiled: the smoother launch records its own start and stop
       hipEvent_t e0 = nullptr, e1 = nullptr;
       const int id = prof_ ? prof_->launch_events(&e0, &e1) : -1;
       const int ev = prof_ && id < 0 ? prof_->mark(st) : -1;
       if (id >= 0) smgk::next_launch_events(e0, e1);
       hipError_t e = smgk::mg_smooth_dir(dl + (size_t)d * P, hl + (size_t)d * P, P, b, prm_.n_sor, prm_.exact, dir,
-                                         f32, st, pr, ac);
+                                         f32, st, pr, ac, z);
       smgk::next_launch_events(nullptr, nullptr);
       if (e != hipSuccess) return e;
       const int cls = d == 0 ? (dir == 0 ? EC_SMOOTH_R0 : EC_SMOOTH_P0) : EC_SMOOTH_C;
-      const double bytes = ((pr ? 3.25 : 3.0) * vb + (ac ? 32.0 - vb : 0.0)) * cells(d, false);
+      const double bytes = ((pr ? 3.25 : 3.0) * vb + (ac ? 32.0 - vb : 0.0) - (z ? vb : 0.0)) * cells(d, false);
       if (id >= 0) prof_->close_launch(cls, id, bytes);
       else if (prof_) prof_->close(cls, ev, bytes, st);
     }
@@ -319,7 +319,7 @@ smg_status Engine::vcycle(int target, int c, const BatchRef& b, hipStream_t st, 
   hipError_t e = hipSuccess;
   for (int d = 0; d < D; ++d) {
     for (int k = 0; k < prm_.nu_pre; ++k)
-      if ((e = smooth(d, false, false)) != hipSuccess) return SMG_EHIP;
+      if ((e = smooth(d, false, false, zero_first_ && d == 0 && k == 0)) != hipSuccess) return SMG_EHIP;
     const int ev = prof_ ? prof_->mark(st) : -1;
     if ((e = smgk::mg_restrict(dl + (size_t)d * P, hl + (size_t)d * P, P, b, f32, st)) != hipSuccess) return SMG_EHIP;
     if (prof_) prof_->close(EC_RESTRICT, ev, (2.0 * vb + 0.5 * vb) * cells(d, false), st);
@@ -350,7 +350,8 @@ smg_status Engine::vcycle(int target, int c, const BatchRef& b, hipStream_t st, 
       if (prof_) prof_->close(EC_PROLONG, ev, (2.0 * vb + 0.25 * vb) * cells(d, false), st);
     }
     for (int k = 0; k < prm_.nu_post; ++k)
-      if ((e = smooth(d, fuse && k == 0, acc_last && d == 0 && k == prm_.nu_post - 1)) != hipSuccess) return SMG_EHIP;
+      if ((e = smooth(d, fuse && k == 0, acc_last && d == 0 && k == prm_.nu_post - 1, false)) != hipSuccess)
+        return SMG_EHIP;
   }
   return SMG_OK;
 }
@@ -366,7 +367,7 @@ smg_status Engine::start(int target, double tol, double floor_factor, bool warm,
         return SMG_EHIP;
   BatchRef ball{n_total_, nullptr, d_all_};
   int ev = prof_ ? prof_->mark(st) : -1;
-  if (smgk::mg_norm_partial(dn, hn, P, ball, false, d_partial_, nblk_, st) != hipSuccess) return SMG_EHIP;
+  if (smgk::mg_norm_partial(dn, hn, P, ball, false, d_partial_, nblk_, st, !zero_first_) != hipSuccess) return SMG_EHIP;
   if (smgk::mg_conv_init(dn, d_all_, n_total_, P, d_partial_, nblk_, tol, floor_factor, cs_[target], d_list_[target],
                          d_count_ + target, st) != hipSuccess)
     return SMG_EHIP;
@@ -378,7 +379,7 @@ smg_status Engine::start(int target, double tol, double floor_factor, bool warm,
   fp32_owner_ = target;
   if (warm) {
     BatchRef b{n_total_, d_count_ + target, d_list_[target]};
-    if (smgk::mg_norm_partial(dn, hn, P, b, true, d_partial_, nblk_, st) != hipSuccess) return SMG_EHIP;
+    if (smgk::mg_norm_partial(dn, hn, P, b, true, d_partial_, nblk_, st, !zero_first_) != hipSuccess) return SMG_EHIP;
     if (smgk::mg_converge(dn, n_total_, d_partial_, nblk_, cs_[target], max_cycles_, 0, d_list_[target],
                           d_count_ + target, st) != hipSuccess)
       return SMG_EHIP;
@@ -397,7 +398,7 @@ smg_status Engine::cycle(int target, int cap, hipStream_t st) {
     // the FP32 residual arrays (shared by the targets) hold another solve's
     // residual: recompute this target's for every listed plane
     BatchRef all{n_total_, d_count_ + target, d_list_[target]};
-    if (smgk::mg_norm_partial(dn, hn, P, all, true, d_partial_, nblk_, st) != hipSuccess) return SMG_EHIP;
+    if (smgk::mg_norm_partial(dn, hn, P, all, true, d_partial_, nblk_, st, !zero_first_) != hipSuccess) return SMG_EHIP;
     if (smgk::mg_converge(dn, n_total_, d_partial_, nblk_, cs_[target], max_cycles_, 0, d_list_[target],
                           d_count_ + target, st) != hipSuccess)
       return SMG_EHIP;
@@ -414,7 +415,7 @@ smg_status Engine::cycle(int target, int cap, hipStream_t st) {
     if (prof_) prof_->close(EC_ACCUM, ev, 40.0 * cells, st);
   }
   const int ev = prof_ ? prof_->mark(st) : -1;
-  if (smgk::mg_norm_partial(dn, hn, P, b, true, d_partial_, nblk_, st) != hipSuccess) return SMG_EHIP;
+  if (smgk::mg_norm_partial(dn, hn, P, b, true, d_partial_, nblk_, st, !zero_first_) != hipSuccess) return SMG_EHIP;
   if (prof_) prof_->close(EC_NORM, ev, (prm_.fp32 ? 48.0 : 32.0) * cells, st);
   if (smgk::mg_converge(dn, cap, d_partial_, nblk_, cs_[target], max_cycles_, 1, d_list_[target], d_count_ + target,
                         st) != hipSuccess)

@@ -136,6 +136,9 @@ class Engine {
   int* d_all_ = nullptr;
   std::vector<int*> d_list_;       // per target: planes still cycling
   int* d_count_ = nullptr;         // [T] list lengths
+  // mixed form whose every cycle starts with a finest-level radial launch:
+  // that launch takes e = 0 itself, so the norms need not zero e
+  bool zero_first_ = false;
   double* d_partial_ = nullptr;
   std::vector<ConvState> cs_;      // per target
   NormJob* d_norm_ = nullptr;      // [T][P]

@@ -107,8 +107,14 @@ __host__ __device__ inline size_t smooth_lds_bytes(int dir, int na, int nb, int 
          (prolong ? (nr + nc) * (2 * sizeof(int) + 2 * sizeof(R)) : 0);
 }
 
-template <int DIR, bool EXACT, int PMAX, typename R, int NT, bool PROLONG, bool ACC = false>
+// How a launch obtains u: from the level array, from the level array plus
+// the prolonged coarse correction, or as zero (the mixed form's correction
+// cycle starts from e = 0, so its first launch reads nothing).
+constexpr int kInLoad = 0, kInProlong = 1, kInZero = 2;
+
+template <int DIR, bool EXACT, int PMAX, typename R, int NT, int IN, bool ACC = false>
 __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, BatchRef bt, int n_sor) {
+  constexpr bool PROLONG = IN == kInProlong, ZERO = IN == kInZero;
   using V = typename Vec<R>::T;
   extern __shared__ char smem[];
   V* sh = reinterpret_cast<V*>(smem);
@@ -198,7 +204,7 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
     const int t = threadIdx.x + k * NT;
     int i, j;
     ub[k] = mkv<R>(0, 0);
-    if (!PROLONG && t < n_u && u_pos(t, i, j)) ub[k] = u[(size_t)i * nb + j];
+    if (!PROLONG && !ZERO && t < n_u && u_pos(t, i, j)) ub[k] = u[(size_t)i * nb + j];
   }
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
@@ -289,7 +295,7 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
     for (int t = threadIdx.x + KB * NT; t < n_u; t += NT) {
       int i, j;
       V v = mkv<R>(0, 0);
-      if (u_pos(t, i, j)) v = u[(size_t)i * nb + j];
+      if (!ZERO && u_pos(t, i, j)) v = u[(size_t)i * nb + j];
       sh[t] = v;
     }
   }
@@ -498,9 +504,10 @@ __global__ void __launch_bounds__(kThreads) k_prolong(const LvJob* __restrict__ 
 // Volume-weighted squared defect (FP64): partial sums per (list position,
 // block).  use_u = 0: the defect of the zero guess (f itself).  With the
 // mixed form the FP64 residual is also stored rounded to FP32 (the right-hand
-// side of the next FP32 correction cycle) and the FP32 correction is zeroed.
+// side of the next FP32 correction cycle) and (zero_e) the FP32 correction is
+// zeroed.
 __global__ void __launch_bounds__(kThreads) k_norm_partial(const NormJob* __restrict__ jobs, BatchRef bt, int use_u,
-                                                          double* __restrict__ partial) {
+                                                          double* __restrict__ partial, int zero_e) {
   __shared__ double red[kThreads / 64];
   SMG_ENTRY(jobs, bt);
   const LevelDev L = J.L;
@@ -516,7 +523,7 @@ __global__ void __launch_bounds__(kThreads) k_norm_partial(const NormJob* __rest
     const double2 r = use_u ? resid_at<double>(L, m, U, F, i, j) : (double2)gbl(F)[t];
     if (R32) {
       R32[t] = make_float2((float)r.x, (float)r.y);
-      E32[t] = make_float2(0.f, 0.f);
+      if (zero_e) E32[t] = make_float2(0.f, 0.f);
     }
     acc += (r.x * r.x + r.y * r.y) * (gbl(L.va)[i] * gbl(L.vb)[j]);
   }
@@ -610,7 +617,8 @@ void next_launch_events(hipEvent_t start, hipEvent_t stop) {
 
 template <typename R>
 static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, int n_sor,
-                                bool exact, int dir, bool prolong, bool acc, hipStream_t st) {
+                                bool exact, int dir, int in, bool acc, hipStream_t st) {
+  const bool prolong = in == kInProlong;
   int gx = 0;
   size_t lds = 0;
   for (int q = 0; q < n_prob; ++q) {
@@ -625,7 +633,7 @@ static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, 
     // the tables do not fit beside the widest tile: separate prolongation
     hipError_t e = mg_prolong(jobs, hj, n_prob, b, std::is_same<R, float>::value, st);
     if (e != hipSuccess) return e;
-    return smooth_launch<R>(jobs, hj, n_prob, b, n_sor, exact, dir, false, acc, st);
+    return smooth_launch<R>(jobs, hj, n_prob, b, n_sor, exact, dir, kInLoad, acc, st);
   }
   if (lds > lds_limit()) return hipErrorInvalidConfiguration;
   const dim3 grid(gx, b.cap);
@@ -640,7 +648,7 @@ static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, 
   const bool big = !exact && tmax >= 16 && pmax <= 4;
   // the coarse correction is applied by radial-line launches only, the
   // accumulation into the FP64 iterate by FP32 polar-line launches only
-  if (prolong && dir != 0) return hipErrorInvalidValue;
+  if (in != kInLoad && dir != 0) return hipErrorInvalidValue;
   if (acc && (dir != 1 || !std::is_same<R, float>::value)) return hipErrorInvalidValue;
   for (int q = 0; q < n_prob; ++q) {
     if (acc && hj[q].active && !hj[q].acc) return hipErrorInvalidValue;
@@ -656,37 +664,41 @@ static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, 
   };
   // radial launch with or without the coarse correction; polar launch
   // storing the lines or adding them to the FP64 iterate
-  auto go0 = [&](auto kern_plain, auto kern_prolong, int nt) { prolong ? go(kern_prolong, nt) : go(kern_plain, nt); };
+  auto go0 = [&](auto kern_plain, auto kern_prolong, auto kern_zero, int nt) {
+    in == kInProlong ? go(kern_prolong, nt) : (in == kInZero ? go(kern_zero, nt) : go(kern_plain, nt));
+  };
   auto go1 = [&](auto kern_plain, auto kern_acc, int nt) { acc ? go(kern_acc, nt) : go(kern_plain, nt); };
   if (exact) {
-    if (dir == 0) go0(k_smooth<0, true, 2, R, kThreads, false>, k_smooth<0, true, 2, R, kThreads, true>, kThreads);
-    else go1(k_smooth<1, true, 2, R, kThreads, false>, k_smooth<1, true, 2, R, kThreads, false, true>, kThreads);
+    if (dir == 0) go0(k_smooth<0, true, 2, R, kThreads, kInLoad>, k_smooth<0, true, 2, R, kThreads, kInProlong>, k_smooth<0, true, 2, R, kThreads, kInZero>, kThreads);
+    else go1(k_smooth<1, true, 2, R, kThreads, kInLoad>, k_smooth<1, true, 2, R, kThreads, kInLoad, true>, kThreads);
   } else if (big) {
     if (dir == 0) {
-      if (pmax <= 2) go0(k_smooth<0, false, 2, R, 1024, false>, k_smooth<0, false, 2, R, 1024, true>, 1024);
-      else go0(k_smooth<0, false, 4, R, 1024, false>, k_smooth<0, false, 4, R, 1024, true>, 1024);
+      if (pmax <= 2) go0(k_smooth<0, false, 2, R, 1024, kInLoad>, k_smooth<0, false, 2, R, 1024, kInProlong>, k_smooth<0, false, 2, R, 1024, kInZero>, 1024);
+      else go0(k_smooth<0, false, 4, R, 1024, kInLoad>, k_smooth<0, false, 4, R, 1024, kInProlong>, k_smooth<0, false, 4, R, 1024, kInZero>, 1024);
     } else {
-      if (pmax <= 2) go1(k_smooth<1, false, 2, R, 1024, false>, k_smooth<1, false, 2, R, 1024, false, true>, 1024);
-      else go1(k_smooth<1, false, 4, R, 1024, false>, k_smooth<1, false, 4, R, 1024, false, true>, 1024);
+      if (pmax <= 2) go1(k_smooth<1, false, 2, R, 1024, kInLoad>, k_smooth<1, false, 2, R, 1024, kInLoad, true>, 1024);
+      else go1(k_smooth<1, false, 4, R, 1024, kInLoad>, k_smooth<1, false, 4, R, 1024, kInLoad, true>, 1024);
     }
   } else if (dir == 0) {
-    if (pmax <= 2) go0(k_smooth<0, false, 2, R, kThreads, false>, k_smooth<0, false, 2, R, kThreads, true>, kThreads);
-    else if (pmax <= 4) go0(k_smooth<0, false, 4, R, kThreads, false>, k_smooth<0, false, 4, R, kThreads, true>, kThreads);
-    else if (pmax <= 8) go0(k_smooth<0, false, 8, R, kThreads, false>, k_smooth<0, false, 8, R, kThreads, true>, kThreads);
-    else go0(k_smooth<0, false, 16, R, kThreads, false>, k_smooth<0, false, 16, R, kThreads, true>, kThreads);
+    if (pmax <= 2) go0(k_smooth<0, false, 2, R, kThreads, kInLoad>, k_smooth<0, false, 2, R, kThreads, kInProlong>, k_smooth<0, false, 2, R, kThreads, kInZero>, kThreads);
+    else if (pmax <= 4) go0(k_smooth<0, false, 4, R, kThreads, kInLoad>, k_smooth<0, false, 4, R, kThreads, kInProlong>, k_smooth<0, false, 4, R, kThreads, kInZero>, kThreads);
+    else if (pmax <= 8) go0(k_smooth<0, false, 8, R, kThreads, kInLoad>, k_smooth<0, false, 8, R, kThreads, kInProlong>, k_smooth<0, false, 8, R, kThreads, kInZero>, kThreads);
+    else go0(k_smooth<0, false, 16, R, kThreads, kInLoad>, k_smooth<0, false, 16, R, kThreads, kInProlong>, k_smooth<0, false, 16, R, kThreads, kInZero>, kThreads);
   } else {
-    if (pmax <= 2) go1(k_smooth<1, false, 2, R, kThreads, false>, k_smooth<1, false, 2, R, kThreads, false, true>, kThreads);
-    else if (pmax <= 4) go1(k_smooth<1, false, 4, R, kThreads, false>, k_smooth<1, false, 4, R, kThreads, false, true>, kThreads);
-    else if (pmax <= 8) go1(k_smooth<1, false, 8, R, kThreads, false>, k_smooth<1, false, 8, R, kThreads, false, true>, kThreads);
-    else go1(k_smooth<1, false, 16, R, kThreads, false>, k_smooth<1, false, 16, R, kThreads, false, true>, kThreads);
+    if (pmax <= 2) go1(k_smooth<1, false, 2, R, kThreads, kInLoad>, k_smooth<1, false, 2, R, kThreads, kInLoad, true>, kThreads);
+    else if (pmax <= 4) go1(k_smooth<1, false, 4, R, kThreads, kInLoad>, k_smooth<1, false, 4, R, kThreads, kInLoad, true>, kThreads);
+    else if (pmax <= 8) go1(k_smooth<1, false, 8, R, kThreads, kInLoad>, k_smooth<1, false, 8, R, kThreads, kInLoad, true>, kThreads);
+    else go1(k_smooth<1, false, 16, R, kThreads, kInLoad>, k_smooth<1, false, 16, R, kThreads, kInLoad, true>, kThreads);
   }
   return hipGetLastError();
 }
 
 hipError_t mg_smooth_dir(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, int n_sor, bool exact,
-                         int dir, bool fp32, hipStream_t st, bool prolong, bool accumulate) {
-  return fp32 ? smooth_launch<float>(jobs, hj, n_prob, b, n_sor, exact, dir, prolong, accumulate, st)
-              : smooth_launch<double>(jobs, hj, n_prob, b, n_sor, exact, dir, prolong, accumulate, st);
+                         int dir, bool fp32, hipStream_t st, bool prolong, bool accumulate, bool zero) {
+  const int in = prolong ? kInProlong : (zero ? kInZero : kInLoad);
+  if (prolong && zero) return hipErrorInvalidValue;
+  return fp32 ? smooth_launch<float>(jobs, hj, n_prob, b, n_sor, exact, dir, in, accumulate, st)
+              : smooth_launch<double>(jobs, hj, n_prob, b, n_sor, exact, dir, in, accumulate, st);
 }
 
 // blocks per plane of a per-cell launch: enough for the largest problem
@@ -731,10 +743,11 @@ int norm_blocks(const NormJob* hj, int n_prob) {
 }
 
 hipError_t mg_norm_partial(const NormJob* jobs, const NormJob* hj, int n_prob, const BatchRef& b, bool use_u,
-                           double* partial, int nblk, hipStream_t st) {
+                           double* partial, int nblk, hipStream_t st, bool zero_e) {
   (void)hj; (void)n_prob;
   if (!b.cap) return hipSuccess;
-  hipLaunchKernelGGL(k_norm_partial, dim3(nblk, b.cap), dim3(kThreads), 0, st, jobs, b, use_u ? 1 : 0, partial);
+  hipLaunchKernelGGL(k_norm_partial, dim3(nblk, b.cap), dim3(kThreads), 0, st, jobs, b, use_u ? 1 : 0, partial,
+                     zero_e ? 1 : 0);
   return hipGetLastError();
 }
 

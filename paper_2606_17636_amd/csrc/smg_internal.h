@@ -242,9 +242,11 @@ void next_launch_events(hipEvent_t start, hipEvent_t stop);
 // mg_prolong launch.  With accumulate set (polar lines, dir 1, FP32 only)
 // the relaxed correction of the owned lines is added to the job's FP64
 // iterate (acc) instead of being stored to u, in place of an mg_accumulate
-// launch.
+// launch.  With zero set (radial lines) the launch takes u = 0 instead of
+// reading it (the first launch of a correction cycle that starts from zero).
 hipError_t mg_smooth_dir(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, int n_sor, bool exact,
-                         int dir, bool fp32, hipStream_t st, bool prolong = false, bool accumulate = false);
+                         int dir, bool fp32, hipStream_t st, bool prolong = false, bool accumulate = false,
+                         bool zero = false);
 hipError_t mg_restrict(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, bool fp32, hipStream_t st);
 hipError_t mg_prolong(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, bool fp32, hipStream_t st);
 hipError_t mg_residual(const LvJob* jobs, const LvJob* hj, int n_prob, const BatchRef& b, double2* r, hipStream_t st);
@@ -269,7 +271,7 @@ hipError_t mg_lds_cycle(const LdsJob* jobs, const LdsJob* hj, int n_prob, const 
 // rounded to FP32 and the FP32 correction zeroed.
 int norm_blocks(const NormJob* hj, int n_prob);
 hipError_t mg_norm_partial(const NormJob* jobs, const NormJob* hj, int n_prob, const BatchRef& b, bool use_u,
-                           double* partial, int nblk, hipStream_t st);
+                           double* partial, int nblk, hipStream_t st, bool zero_e = true);
 // Thresholds from the zero-guess defects: thr = tol * max(d0, floor * max
 // over the problem's planes of d0); cyc = 0; the list keeps the planes
 // whose d0 exceeds thr.  The full list of n planes is `all` (n <= 4096).
