@@ -602,8 +602,47 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
     const auto gv = gbl(LC.sep_v + (size_t)m * nn), gvi = gbl(LC.sep_vi + (size_t)m * nn);
     const auto gcp = gbl(LC.sep_cp + (size_t)m * LC.na * LC.nb), gid = gbl(LC.sep_id + (size_t)m * LC.na * LC.nb);
     const size_t off = (size_t)slot * LC.na * LC.nb;
+    // even sizes (the usual case): pairs of entries per 16-byte load (the
+    // tables and planes start on 16-byte boundaries); else one per load
+    const int nn2 = nn / 2, nf2 = nf / 2;
+    const bool pairs = (nn & 1) == 0 && (nf & 1) == 0;
+#pragma unroll 2
+    for (int t = threadIdx.x; pairs && t < max(nn2, nf2); t += blockDim.x) {
+      double2 v0 = make_double2(0.0, 0.0), v1 = v0, c0 = v0, c1 = v0;
+      V fa = mkv<R>(0, 0), fb = fa;
+      if (t < nn2) {
+        v0 = gbl(reinterpret_cast<const double2*>(LC.sep_v + (size_t)m * nn))[t];
+        v1 = gbl(reinterpret_cast<const double2*>(LC.sep_vi + (size_t)m * nn))[t];
+      }
+      if (t < nf2) {
+        c0 = gbl(reinterpret_cast<const double2*>(LC.sep_cp + (size_t)m * LC.na * LC.nb))[t];
+        c1 = gbl(reinterpret_cast<const double2*>(LC.sep_id + (size_t)m * LC.na * LC.nb))[t];
+        if constexpr (sizeof(V) == 8) {
+          const float4 f4 = gbl(reinterpret_cast<const float4*>(static_cast<const V*>(J.f) + off))[t];
+          fa = mkv<R>(f4.x, f4.y);
+          fb = mkv<R>(f4.z, f4.w);
+        } else {
+          fa = Fg[off + 2 * t];
+          fb = Fg[off + 2 * t + 1];
+        }
+      }
+      if (t < nn2) {
+        sepV[2 * t] = v0.x;
+        sepV[2 * t + 1] = v0.y;
+        sepV[nn + 2 * t] = v1.x;
+        sepV[nn + 2 * t + 1] = v1.y;
+      }
+      if (t < nf2) {
+        sepF[2 * t] = c0.x;
+        sepF[2 * t + 1] = c0.y;
+        sepF[nf + 2 * t] = c1.x;
+        sepF[nf + 2 * t + 1] = c1.y;
+        fC[2 * t] = make_double2(fa.x, fa.y);
+        fC[2 * t + 1] = make_double2(fb.x, fb.y);
+      }
+    }
 #pragma unroll 4
-    for (int t = threadIdx.x; t < max(nn, nf); t += blockDim.x) {
+    for (int t = threadIdx.x; !pairs && t < max(nn, nf); t += blockDim.x) {
       double v0 = 0.0, v1 = 0.0, c0 = 0.0, c1 = 0.0;
       V fv = mkv<R>(0, 0);
       if (t < nn) {
