@@ -7,9 +7,9 @@ density from a zero initial guess, to relative residual --tol (default 1e-8)
 on every mode.  The DGF tables, the launch-shape tuning and the plan setup
 are done before the timed region (one-time, as in the paper).  The timed
 form is the chosen one (FP32/FP64 iterative refinement, per-mode cycle
-schedules replayed as HIP graphs, autotuned launch shapes); the plain GPU
-form (FP64, host reads after every V-cycle) is timed next to it.  Prints one
-JSON line.
+schedules replayed as HIP graphs, autotuned launch shapes, smoothing steps
+chosen at setup); the plain GPU form (FP64, host reads after every V-cycle,
+V(2,2)) is timed next to it.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2] [--form chosen|plain]
 """
@@ -399,9 +399,10 @@ def main():
     value = args.steps / dt
     log(f"timed {args.steps} solves in {dt:.3f}s -> {value:.2f} solves/s ({args.form})")
 
-    # per-kernel launch durations: the same solves with every launch
-    # bracketed by HIP events on the solve stream (host loop launches, the
-    # same kernels and launch shapes as the timed replay)
+    # per-kernel launch durations: the same solves again, launched by the
+    # host loop (the same kernels and launch shapes as the timed replay),
+    # with HIP events on the solve stream: smoother launches record their own
+    # start and stop, the other kernels have an event before and after them
     plan.profile_begin()
     _timed(plan, rho, phi, args.steps, args.tol, torch)
     stats = plan.profile_end()

@@ -21,8 +21,12 @@
 // lines on each side across the lines; the first zebra colour is also
 // computed on the inner halo line so the second colour sees the updated
 // neighbours without another pass over memory.  Inside a colour the n_sor
-// even-odd SOR passes of every line run as point updates in LDS, or (exact
-// variant) each line is solved by the Thomas algorithm.
+// even-odd SOR passes of every line run in registers (relax_dev.h), or
+// (exact variant) each line is solved by the Thomas algorithm.  Each level
+// has two iterate arrays: radial-line launches read u and write u2,
+// polar-line launches read u2 and write u, so no block of a launch reads
+// lines another block of it writes.  Blocks are renumbered so that the tiles
+// of a plane run on one XCD and share its L2.
 #include <algorithm>
 #include <type_traits>
 
@@ -84,20 +88,20 @@ __device__ __forceinline__ typename Vec<R>::T coarse_corr(const LevelDev& L, int
 // with one zero column/row of padding at the ends of the lines, f of the
 // lines the block relaxes (owned lines and the inner halo line on each side)
 // in the same layout, and the 1D stencil tables of the tile rounded to R.
-// All global reads are issued before the first barrier; the colours then
-// run out of LDS and registers.  With PROLONG the launch first applies
+// The first batch of global reads is issued before any LDS store; the
+// colours then run out of LDS and registers.  With PROLONG the launch first applies
 // the coarse-grid correction: every u value entering the tile (halo lines
 // included) gets the interpolated coarse correction added, so the owned
 // lines written back carry it and no separate prolongation pass is needed.
 // With ACC (polar lines, FP32 correction of the mixed form) the owned lines
 // are added to the FP64 iterate instead of being stored, which is the
 // correction step of the mixed form done by the V-cycle's last launch.
+// With ZERO (radial lines) the launch takes u = 0 without reading it.
 // ---------------------------------------------------------------------------
 // LDS bytes of a smoother block: u tile, f tile (the SOR variant; the exact
 // variant reads each f value once, from global memory), exact-line scratch
-// and tables.
-// A launch that applies the coarse correction (prolong) also holds the
-// prolongation indices and weights of the tile's rows and columns.
+// and tables.  A launch that applies the coarse correction (prolong) also
+// holds the prolongation indices and weights of the tile's rows and columns.
 template <typename R>
 __host__ __device__ inline size_t smooth_lds_bytes(int dir, int na, int nb, int tile, bool exact, int scratch,
                                                    bool prolong = false) {

@@ -1,8 +1,10 @@
 // The coarse end of the V-cycle in one launch: every level whose plane fits
 // in LDS (from level `first` down to the coarsest) is processed by one block
-// per plane -- pre-smoothing, residual restriction, the coarsest red-black
-// SOR (Sec. 3.3), prolongation and post-smoothing -- without touching global
-// memory between levels.  The arithmetic is that of the per-level kernels in
+// per plane -- pre-smoothing, residual restriction, the coarsest solve,
+// prolongation and post-smoothing -- without touching global memory between
+// levels.  The coarsest level is solved exactly by fast diagonalisation
+// where the host built its tables (row transforms on the FP64 matrix cores,
+// tridiagonal sweeps in segments), else by red-black SOR (Sec. 3.3).  The arithmetic is that of the per-level kernels in
 // mg.hip (same colour order, same transfer weights, same stopping rule of
 // the coarsest solve); only the memory traffic and the launch count differ.
 // Templated on the real type R of the smoothing levels; the coarsest level
