@@ -641,15 +641,20 @@ static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, 
   }
   if (lds > lds_limit()) return hipErrorInvalidConfiguration;
   const dim3 grid(gx, b.cap);
-  int pmax = 2, tmax = 0;  // points per lane of the longest relaxed line; widest tile
+  // Block size: enough waves to relax the first colour's lines (tile / 2
+  // owned lines of one parity and the inner halo line) in one step, 256,
+  // 512 or 1024 threads; 512 and 1024 only for lines of up to 4 points per
+  // lane, where the variant stays within 128 registers.
+  int pmax = 2, waves = 1;
   for (int q = 0; q < n_prob; ++q)
     if (hj[q].active) {
-      pmax = std::max(pmax, relax_points_per_lane(dir == 0 ? hj[q].L.na : hj[q].L.nb));
-      tmax = std::max(tmax, hj[q].tile[dir]);
+      const int npts = dir == 0 ? hj[q].L.na : hj[q].L.nb;
+      const int P = relax_points_per_lane(npts);
+      const int per_wave = 64 / ((npts + P - 1) / P);  // lines a wave relaxes at once
+      pmax = std::max(pmax, P);
+      waves = std::max(waves, (hj[q].tile[dir] / 2 + 1 + per_wave - 1) / per_wave);
     }
-  // wide tiles (more lines per colour than four waves take in one step)
-  // run with 1024 threads where the variant stays within 128 registers
-  const bool big = !exact && tmax >= 16 && pmax <= 4;
+  const int nt = exact || pmax > 4 || waves <= 4 ? 256 : (waves <= 8 ? 512 : 1024);
   // the coarse correction is applied by radial-line launches only, the
   // accumulation into the FP64 iterate by FP32 polar-line launches only
   if (in != kInLoad && dir != 0) return hipErrorInvalidValue;
@@ -675,13 +680,21 @@ static hipError_t smooth_launch(const LvJob* jobs, const LvJob* hj, int n_prob, 
   if (exact) {
     if (dir == 0) go0(k_smooth<0, true, 2, R, kThreads, kInLoad>, k_smooth<0, true, 2, R, kThreads, kInProlong>, k_smooth<0, true, 2, R, kThreads, kInZero>, kThreads);
     else go1(k_smooth<1, true, 2, R, kThreads, kInLoad>, k_smooth<1, true, 2, R, kThreads, kInLoad, true>, kThreads);
-  } else if (big) {
+  } else if (nt == 1024) {
     if (dir == 0) {
       if (pmax <= 2) go0(k_smooth<0, false, 2, R, 1024, kInLoad>, k_smooth<0, false, 2, R, 1024, kInProlong>, k_smooth<0, false, 2, R, 1024, kInZero>, 1024);
       else go0(k_smooth<0, false, 4, R, 1024, kInLoad>, k_smooth<0, false, 4, R, 1024, kInProlong>, k_smooth<0, false, 4, R, 1024, kInZero>, 1024);
     } else {
       if (pmax <= 2) go1(k_smooth<1, false, 2, R, 1024, kInLoad>, k_smooth<1, false, 2, R, 1024, kInLoad, true>, 1024);
       else go1(k_smooth<1, false, 4, R, 1024, kInLoad>, k_smooth<1, false, 4, R, 1024, kInLoad, true>, 1024);
+    }
+  } else if (nt == 512) {
+    if (dir == 0) {
+      if (pmax <= 2) go0(k_smooth<0, false, 2, R, 512, kInLoad>, k_smooth<0, false, 2, R, 512, kInProlong>, k_smooth<0, false, 2, R, 512, kInZero>, 512);
+      else go0(k_smooth<0, false, 4, R, 512, kInLoad>, k_smooth<0, false, 4, R, 512, kInProlong>, k_smooth<0, false, 4, R, 512, kInZero>, 512);
+    } else {
+      if (pmax <= 2) go1(k_smooth<1, false, 2, R, 512, kInLoad>, k_smooth<1, false, 2, R, 512, kInLoad, true>, 512);
+      else go1(k_smooth<1, false, 4, R, 512, kInLoad>, k_smooth<1, false, 4, R, 512, kInLoad, true>, 512);
     }
   } else if (dir == 0) {
     if (pmax <= 2) go0(k_smooth<0, false, 2, R, kThreads, kInLoad>, k_smooth<0, false, 2, R, kThreads, kInProlong>, k_smooth<0, false, 2, R, kThreads, kInZero>, kThreads);
