@@ -559,7 +559,7 @@ smg_status Engine::autotune(int target, hipStream_t st, std::string* report) {
         if (first_min_[q] + off <= (int)P_[q].L.size() - 1) any_new = true;
       }
       if (off > 0 && !any_new) break;
-      for (int tb : {256, 512, 1024, 2048}) {
+      for (int tb : {256, 384, 512, 768, 1024, 2048}) {
         c.target_blocks = tb;
         // stage the candidate in the scratch slot
         std::vector<LvJob> lv;
