@@ -8,9 +8,11 @@
 // A real line of length N is packed as n = N/2 complex values
 // z_k = x_{2k} + i x_{2k+1}; an n-point complex Stockham FFT (radices 4, 2,
 // 3) runs in LDS, and the two interleaved half-length spectra are separated
-// with the post-twiddles e^{-2 pi i m / N}.  A block handles LPB consecutive
-// lines, which are contiguous in the input and give contiguous segments of
-// every output plane.  Twiddles come from a table built on the host in FP64.
+// with the post-twiddles e^{-2 pi i m / N}.  A block handles lpb consecutive
+// lines (a launch parameter), which are contiguous in the input and give
+// contiguous segments of every output plane.  Twiddles come from a table built on the host in FP64.
+#include <algorithm>
+
 #include "smg_internal.h"
 
 namespace {
@@ -99,10 +101,9 @@ __device__ double2* fft_lds(double2* a, double2* b, int n, int lines, const doub
 
 __global__ void __launch_bounds__(kThreads) k_fft_r2c(const double* __restrict__ rho, double2* __restrict__ modes,
                                                      int n_lines, int N, double scale,
-                                                     const double2* __restrict__ tw) {
+                                                     const double2* __restrict__ tw, int lpb) {
   extern __shared__ double2 sh[];
   const int n = N / 2;
-  const int lpb = kPoints / n;
   double2* a = sh;
   double2* b = sh + lpb * n;
   const int line0 = blockIdx.x * lpb;
@@ -128,10 +129,9 @@ __global__ void __launch_bounds__(kThreads) k_fft_r2c(const double* __restrict__
 }
 
 __global__ void __launch_bounds__(kThreads) k_fft_c2r(const double2* __restrict__ modes, double* __restrict__ out,
-                                                     int n_lines, int N, const double2* __restrict__ tw) {
+                                                     int n_lines, int N, const double2* __restrict__ tw, int lpb) {
   extern __shared__ double2 sh[];
   const int n = N / 2;
-  const int lpb = kPoints / n;
   double2* a = sh;
   double2* b = sh + lpb * n;
   const int line0 = blockIdx.x * lpb;
@@ -163,23 +163,31 @@ __global__ void __launch_bounds__(kThreads) k_fft_c2r(const double2* __restrict_
 
 namespace smgk {
 
-static size_t fft_lds_bytes() { return 2 * kPoints * sizeof(double2); }
+// Lines per block: as many as the LDS budget (kPoints complex points, ping
+// and pong) holds, but no more than gives kMinBlocks blocks, so that small
+// transforms still spread over the device.
+constexpr int kMinBlocks = 1024;
+static int fft_lines_per_block(int n_lines, int n) {
+  const int cap = kPoints / n;
+  const int want = std::max(1, n_lines / kMinBlocks);
+  return std::max(1, std::min(cap, want));
+}
 
 hipError_t fft_r2c(const double* rho, double2* modes, int n_lines, int n_phi, double scale,
                    const double2* tw, hipStream_t st) {
-  const int lpb = kPoints / (n_phi / 2);
+  const int n = n_phi / 2, lpb = fft_lines_per_block(n_lines, n);
   const int blocks = (n_lines + lpb - 1) / lpb;
-  hipLaunchKernelGGL(k_fft_r2c, dim3(blocks), dim3(kThreads), fft_lds_bytes(), st, rho, modes, n_lines,
-                     n_phi, scale, tw);
+  hipLaunchKernelGGL(k_fft_r2c, dim3(blocks), dim3(kThreads), 2 * lpb * n * sizeof(double2), st, rho, modes,
+                     n_lines, n_phi, scale, tw, lpb);
   return hipGetLastError();
 }
 
 hipError_t fft_c2r(const double2* modes, double* out, int n_lines, int n_phi, const double2* tw,
                    hipStream_t st) {
-  const int lpb = kPoints / (n_phi / 2);
+  const int n = n_phi / 2, lpb = fft_lines_per_block(n_lines, n);
   const int blocks = (n_lines + lpb - 1) / lpb;
-  hipLaunchKernelGGL(k_fft_c2r, dim3(blocks), dim3(kThreads), fft_lds_bytes(), st, modes, out, n_lines,
-                     n_phi, tw);
+  hipLaunchKernelGGL(k_fft_c2r, dim3(blocks), dim3(kThreads), 2 * lpb * n * sizeof(double2), st, modes, out,
+                     n_lines, n_phi, tw, lpb);
   return hipGetLastError();
 }
 
