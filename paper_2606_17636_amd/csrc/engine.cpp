@@ -117,14 +117,17 @@ smg_status Engine::init(std::vector<MGProblem> probs, int n_targets, const MGPar
   d_list_.assign(T_, nullptr);
   cs_.assign(T_, ConvState{});
   for (int t = 0; t < T_; ++t) d_list_[t] = reinterpret_cast<int*>(take(sizeof(int) * n_total_));
+  // the list lengths and every target's convergence state form one span,
+  // which read_all copies to the host at once
   d_count_ = reinterpret_cast<int*>(take(sizeof(int) * T_));
-  d_partial_ = reinterpret_cast<double*>(take(sizeof(double) * (size_t)n_total_ * kNormBlocks));
   for (int t = 0; t < T_; ++t) {
     cs_[t].d0 = reinterpret_cast<double*>(take(sizeof(double) * n_total_));
     cs_[t].thr = reinterpret_cast<double*>(take(sizeof(double) * n_total_));
     cs_[t].cur = reinterpret_cast<double*>(take(sizeof(double) * n_total_));
     cs_[t].cyc = reinterpret_cast<int*>(take(sizeof(int) * n_total_));
   }
+  state_span_ = (size_t)(reinterpret_cast<char*>(cs_[T_ - 1].cyc + n_total_) - reinterpret_cast<char*>(d_count_));
+  d_partial_ = reinterpret_cast<double*>(take(sizeof(double) * (size_t)n_total_ * kNormBlocks));
   d_norm_ = reinterpret_cast<NormJob*>(take(sizeof(NormJob) * T_ * P));
   d_lv_ = reinterpret_cast<LvJob*>(take(sizeof(LvJob) * (size_t)T_ * kMaxConfigs * Dmax_ * P));
   d_lds_ = reinterpret_cast<LdsJob*>(take(sizeof(LdsJob) * (size_t)T_ * kMaxConfigs * P));
@@ -150,7 +153,7 @@ smg_status Engine::init(std::vector<MGProblem> probs, int n_targets, const MGPar
   if (!h_pin_) EHIP(hipHostMalloc((void**)&h_pin_, sizeof(int) * (kMaxPlanes + 16)));
   if (h_state_) (void)hipHostFree(h_state_);
   h_state_ = nullptr;
-  EHIP(hipHostMalloc((void**)&h_state_, (size_t)T_ * (sizeof(int) + (sizeof(int) + 3 * sizeof(double)) * n_total_)));
+  EHIP(hipHostMalloc((void**)&h_state_, state_span_));
   EHIP(hipMemcpyAsync(d_all_, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice, st));
   EHIP(hipMemcpyAsync(d_norm_, h_norm_.data(), sizeof(NormJob) * h_norm_.size(), hipMemcpyHostToDevice, st));
   // scratch configuration (last slot): every level smoothable, nothing fused;
@@ -479,37 +482,28 @@ smg_status Engine::read_state(int target, hipStream_t st, std::vector<int>& cyc,
 }
 
 smg_status Engine::read_all(hipStream_t st, State* out) {
-  const size_t n = n_total_;
-  char* q = h_state_;
-  int* cnt = reinterpret_cast<int*>(q);
-  q += sizeof(int) * T_;
-  if (hipMemcpyAsync(cnt, d_count_, sizeof(int) * T_, hipMemcpyDeviceToHost, st) != hipSuccess) return SMG_EHIP;
-  std::vector<char*> at(T_);
-  for (int t = 0; t < T_; ++t) {
-    at[t] = q;
-    const ConvState& c = cs_[t];
-    if (hipMemcpyAsync(q, c.cur, sizeof(double) * n, hipMemcpyDeviceToHost, st) != hipSuccess) return SMG_EHIP;
-    q += sizeof(double) * n;
-    if (hipMemcpyAsync(q, c.thr, sizeof(double) * n, hipMemcpyDeviceToHost, st) != hipSuccess) return SMG_EHIP;
-    q += sizeof(double) * n;
-    if (hipMemcpyAsync(q, c.d0, sizeof(double) * n, hipMemcpyDeviceToHost, st) != hipSuccess) return SMG_EHIP;
-    q += sizeof(double) * n;
-    if (hipMemcpyAsync(q, c.cyc, sizeof(int) * n, hipMemcpyDeviceToHost, st) != hipSuccess) return SMG_EHIP;
-    q += sizeof(int) * n;
-  }
+  // one copy of the span [list lengths, every target's state]
+  if (hipMemcpyAsync(h_state_, d_count_, state_span_, hipMemcpyDeviceToHost, st) != hipSuccess) return SMG_EHIP;
   if (hipStreamSynchronize(st) != hipSuccess) return SMG_EHIP;
+  const size_t n = n_total_;
+  const char* base = reinterpret_cast<const char*>(d_count_);
+  auto host = [&](const void* dev) { return h_state_ + (reinterpret_cast<const char*>(dev) - base); };
+  const int* cnt = reinterpret_cast<const int*>(h_state_);
   out->count.assign(cnt, cnt + T_);
   out->cyc.resize(T_);
   out->cur.resize(T_);
   out->thr.resize(T_);
   out->d0.resize(T_);
   for (int t = 0; t < T_; ++t) {
-    const double* d = reinterpret_cast<const double*>(at[t]);
-    out->cur[t].assign(d, d + n);
-    out->thr[t].assign(d + n, d + 2 * n);
-    out->d0[t].assign(d + 2 * n, d + 3 * n);
-    const int* c = reinterpret_cast<const int*>(d + 3 * n);
-    out->cyc[t].assign(c, c + n);
+    const ConvState& c = cs_[t];
+    const double* cur = reinterpret_cast<const double*>(host(c.cur));
+    const double* thr = reinterpret_cast<const double*>(host(c.thr));
+    const double* d0 = reinterpret_cast<const double*>(host(c.d0));
+    const int* cyc = reinterpret_cast<const int*>(host(c.cyc));
+    out->cur[t].assign(cur, cur + n);
+    out->thr[t].assign(thr, thr + n);
+    out->d0[t].assign(d0, d0 + n);
+    out->cyc[t].assign(cyc, cyc + n);
   }
   return SMG_OK;
 }

@@ -150,6 +150,7 @@ class Engine {
   std::vector<LdsJob> h_lds_;
   int* h_pin_ = nullptr;           // pinned count readback
   char* h_state_ = nullptr;        // pinned state readback (read_all)
+  size_t state_span_ = 0;          // bytes from d_count_ to the end of the last target's state
   int nblk_ = 1;
   int max_cycles_ = 60;
   int fp32_owner_ = -1;            // target whose residual the FP32 arrays hold (mixed form)
