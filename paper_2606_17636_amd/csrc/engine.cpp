@@ -364,13 +364,11 @@ smg_status Engine::start(int target, double tol, double floor_factor, bool warm,
   max_cycles_ = max_cycles;
   const NormJob* dn = d_norm_ + (size_t)target * P;
   const NormJob* hn = h_norm_.data() + (size_t)target * P;
-  if (!warm)
-    for (int q = 0; q < P; ++q)
-      if (smgk::fill_zero(P_[q].u0[target], (size_t)P_[q].n * P_[q].L[0].na * P_[q].L[0].nb, st) != hipSuccess)
-        return SMG_EHIP;
+  // a cold start's zero iterate is written by the zero-guess norm below
   BatchRef ball{n_total_, nullptr, d_all_};
   int ev = prof_ ? prof_->mark(st) : -1;
-  if (smgk::mg_norm_partial(dn, hn, P, ball, false, d_partial_, nblk_, st, !zero_first_) != hipSuccess) return SMG_EHIP;
+  if (smgk::mg_norm_partial(dn, hn, P, ball, false, d_partial_, nblk_, st, !zero_first_, !warm) != hipSuccess)
+    return SMG_EHIP;
   if (smgk::mg_conv_init(dn, d_all_, n_total_, P, d_partial_, nblk_, tol, floor_factor, cs_[target], d_list_[target],
                          d_count_ + target, st) != hipSuccess)
     return SMG_EHIP;

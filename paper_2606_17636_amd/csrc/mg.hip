@@ -509,9 +509,10 @@ __global__ void __launch_bounds__(kThreads) k_prolong(const LvJob* __restrict__ 
 // block).  use_u = 0: the defect of the zero guess (f itself).  With the
 // mixed form the FP64 residual is also stored rounded to FP32 (the right-hand
 // side of the next FP32 correction cycle) and (zero_e) the FP32 correction is
-// zeroed.
+// zeroed.  With zero_u (zero guess only) the FP64 iterate is set to zero as
+// well, in place of a separate fill.
 __global__ void __launch_bounds__(kThreads) k_norm_partial(const NormJob* __restrict__ jobs, BatchRef bt, int use_u,
-                                                          double* __restrict__ partial, int zero_e) {
+                                                          double* __restrict__ partial, int zero_e, int zero_u) {
   __shared__ double red[kThreads / 64];
   SMG_ENTRY(jobs, bt);
   const LevelDev L = J.L;
@@ -525,6 +526,7 @@ __global__ void __launch_bounds__(kThreads) k_norm_partial(const NormJob* __rest
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += gridDim.x * blockDim.x) {
     const int i = t / L.nb, j = t - i * L.nb;
     const double2 r = use_u ? resid_at<double>(L, m, U, F, i, j) : (double2)gbl(F)[t];
+    if (zero_u) gbl(J.u + off)[t] = make_double2(0.0, 0.0);  // zero guess: u starts at 0
     if (R32) {
       R32[t] = make_float2((float)r.x, (float)r.y);
       if (zero_e) E32[t] = make_float2(0.f, 0.f);
@@ -760,11 +762,12 @@ int norm_blocks(const NormJob* hj, int n_prob) {
 }
 
 hipError_t mg_norm_partial(const NormJob* jobs, const NormJob* hj, int n_prob, const BatchRef& b, bool use_u,
-                           double* partial, int nblk, hipStream_t st, bool zero_e) {
+                           double* partial, int nblk, hipStream_t st, bool zero_e, bool zero_u) {
   (void)hj; (void)n_prob;
   if (!b.cap) return hipSuccess;
+  if (zero_u && use_u) return hipErrorInvalidValue;  // the defect of a guess it would erase
   hipLaunchKernelGGL(k_norm_partial, dim3(nblk, b.cap), dim3(kThreads), 0, st, jobs, b, use_u ? 1 : 0, partial,
-                     zero_e ? 1 : 0);
+                     zero_e ? 1 : 0, zero_u ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -271,7 +271,7 @@ hipError_t mg_lds_cycle(const LdsJob* jobs, const LdsJob* hj, int n_prob, const 
 // rounded to FP32 and the FP32 correction zeroed.
 int norm_blocks(const NormJob* hj, int n_prob);
 hipError_t mg_norm_partial(const NormJob* jobs, const NormJob* hj, int n_prob, const BatchRef& b, bool use_u,
-                           double* partial, int nblk, hipStream_t st, bool zero_e = true);
+                           double* partial, int nblk, hipStream_t st, bool zero_e = true, bool zero_u = false);
 // Thresholds from the zero-guess defects: thr = tol * max(d0, floor * max
 // over the problem's planes of d0); cyc = 0; the list keeps the planes
 // whose d0 exceeds thr.  The full list of n planes is `all` (n <= 4096).
