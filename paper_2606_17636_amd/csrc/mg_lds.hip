@@ -177,9 +177,11 @@ constexpr int kSepChunk = 8;
 __host__ __device__ constexpr int sep_seg_max(int nb) { return nb >= 256 ? 1 : (nb >= 16 ? 256 / nb : 16); }
 
 // Row transform of the exact coarse solve on the FP64 matrix cores:
-// x[i][c] <- sum_r M[r][c] x[i][r] for every row i (x complex, M real, both
-// in LDS).  The complex rows split into real rows rho = 2 i + component,
-// which makes the transform a real (2 na x nb) by (nb x nb) product.  A wave
+// x[i][c] <- sum_r M[r][c] x[i][r] for every row i (M real, in LDS).  The
+// plane x (LDS, row stride ws doubles) is either complex (QS = 1: the
+// components interleaved, ws = 2 nb), whose rows split into real rows
+// rho = 2 i + component, or one real component (QS = 0), so the transform is
+// a real ((na << QS) x nb) by (nb x nb) product.  A wave
 // owns 16 real rows (8 complex rows) and all columns: one accumulator per
 // 16-column tile, K in steps of 4, one v_mfma_f64_16x16x4 per (tile, step).
 // Operand layout of that instruction: lane l holds A[l % 16][l / 16] and
@@ -191,47 +193,90 @@ __host__ __device__ constexpr int sep_seg_max(int nb) { return nb >= 256 ? 1 : (
 typedef double sep_d4 __attribute__((ext_vector_type(4)));
 constexpr int kSepMaxTiles = 8;  // nb <= 128 (the host builds no tables beyond)
 
-__device__ __forceinline__ void sep_rows(double2* x, int na, int nb, const double* M) {
-  double* X = reinterpret_cast<double*>(x);
+// NB > 0: the width as a compile-time constant, a multiple of 16: the K loop
+// is unrolled whole, so no accumulator is carried around a loop (which would
+// move it between register files at every step), and every operand read is
+// in range with no select (rows beyond the plane read row 0 and feed only
+// outputs that are not written).  NB = 0: any width, runtime K loop,
+// operands beyond the sizes replaced by zero.
+template <int QS, int NCT, int NB>
+__device__ __forceinline__ void sep_rows_t(double* X, int na, int nb_rt, int ws, const double* M) {
+  const int nb = NB ? NB : nb_rt;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   const int lm = lane & 15, lk = lane >> 4;
-  const int nrow = 2 * na, nrb = (nrow + 15) >> 4, nct = (nb + 15) >> 4;
+  const int nrow = na << QS, nrb = (nrow + 15) >> 4;
   for (int rb = wave; rb < nrb; rb += nwave) {  // uniform in the wave
     const int rho_a = rb * 16 + lm;
     const bool row_ok = rho_a < nrow;
-    const int abase = (rho_a >> 1) * nb * 2 + (rho_a & 1);
-    sep_d4 acc[kSepMaxTiles];
+    const int abase = row_ok ? (rho_a >> QS) * ws + (rho_a & QS) : 0;
+    int cc[NCT];
+    bool c_ok[NCT];
 #pragma unroll
-    for (int t = 0; t < kSepMaxTiles; ++t) acc[t] = (sep_d4){0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < NCT; ++t) {
+      const int c = t * 16 + lm;
+      c_ok[t] = c < nb;
+      cc[t] = c_ok[t] ? c : 0;
+    }
+    sep_d4 acc[NCT];
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) acc[t] = (sep_d4){0.0, 0.0, 0.0, 0.0};
+    if constexpr (NB > 0) {
+#pragma unroll
+      for (int k0 = 0; k0 < NB; k0 += 4) {
+        const int r = k0 + lk;
+        const double av = X[abase + (r << QS)];
+#pragma unroll
+        for (int t = 0; t < NCT; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, M[r * NB + t * 16 + lm], acc[t], 0, 0, 0);
+      }
+    } else {
 #pragma unroll 4
-    for (int k0 = 0; k0 < nb; k0 += 4) {
-      const int r = k0 + lk;
-      const bool k_ok = r < nb;
-      const double av = row_ok && k_ok ? X[abase + 2 * r] : 0.0;
+      for (int k0 = 0; k0 < nb; k0 += 4) {
+        const int r = k0 + lk;
+        const bool k_ok = r < nb;
+        const int rr = k_ok ? r : 0;
+        const double ax = X[abase + (rr << QS)];
+        const double av = row_ok && k_ok ? ax : 0.0;
+        double bv[NCT];
 #pragma unroll
-      for (int t = 0; t < kSepMaxTiles; ++t) {
-        if (t < nct) {
-          const int c = t * 16 + lm;
-          const double bv = k_ok && c < nb ? M[r * nb + c] : 0.0;
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+        for (int t = 0; t < NCT; ++t) {
+          const double bx = M[rr * nb + cc[t]];
+          bv[t] = k_ok && c_ok[t] ? bx : 0.0;
         }
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[t], acc[t], 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int t = 0; t < kSepMaxTiles; ++t) {
-      if (t < nct) {
-        const int c = t * 16 + lm;
+    for (int t = 0; t < NCT; ++t) {
+      const int c = t * 16 + lm;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int rho = rb * 16 + 4 * e + lk;
-          if (rho < nrow && c < nb) X[((rho >> 1) * nb + c) * 2 + (rho & 1)] = acc[t][e];
-        }
+      for (int e = 0; e < 4; ++e) {
+        const int rho = rb * 16 + 4 * e + lk;
+        if (rho < nrow && c < nb) X[(rho >> QS) * ws + (c << QS) + (rho & QS)] = acc[t][e];
       }
     }
   }
 }
 
-__device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<double>& T, int m, double2* f,
+// The tile count as a compile-time constant (rounded up to a power of two;
+// the extra tiles multiply zeros), and the usual widths fully unrolled.
+template <int QS>
+__device__ __forceinline__ void sep_rows(double* X, int na, int nb, int ws, const double* M) {
+  const int nct = (nb + 15) >> 4;
+  if (nb == 16) sep_rows_t<QS, 1, 16>(X, na, nb, ws, M);
+  else if (nb == 32) sep_rows_t<QS, 2, 32>(X, na, nb, ws, M);
+  else if (nb == 64) sep_rows_t<QS, 4, 64>(X, na, nb, ws, M);
+  else if (nct <= 1) sep_rows_t<QS, 1, 0>(X, na, nb, ws, M);
+  else if (nct <= 2) sep_rows_t<QS, 2, 0>(X, na, nb, ws, M);
+  else if (nct <= 4) sep_rows_t<QS, 4, 0>(X, na, nb, ws, M);
+  else sep_rows_t<QS, kSepMaxTiles, 0>(X, na, nb, ws, M);
+}
+
+// The exact coarse solve on a plane in LDS, in place: complex interleaved
+// (QS = 1, ws = 2 nb) or one real component with row stride ws (QS = 0).
+template <int QS>
+__device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<double>& T, int m, double* w, int ws,
                                                  const double* vt, double* fac, bool staged) {
   const int na = L.na, nb = L.nb, nn = na * nb;
   if (!staged) {
@@ -242,7 +287,7 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
       fac[nn + t] = gid[t];
     }
   }
-  sep_rows(f, na, nb, vt + nb * nb);
+  sep_rows<QS>(w, na, nb, ws, vt + nb * nb);
   __syncthreads();
   // Tridiagonal solves along a, one per (q, component): the forward sweep
   // y_i = id_i w_i - id_i da_i y_{i-1} and the back substitution
@@ -251,12 +296,11 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
   // a zero carry while it multiplies up the recurrence coefficients, then,
   // after a barrier, takes the true value entering its segment from the
   // segment ends before it and adds carry * (coefficient product) to its
-  // rows.  Lanes run over l = 2 q + component, so row i of every system is
-  // the contiguous run w[2 i nb + l].
+  // rows.  Lanes run over l = (q << QS) + component, so row i of every
+  // system is the contiguous run w[i ws + l].
   const double* cp = fac;
   const double* id = fac + nn;
-  double* w = reinterpret_cast<double*>(f);
-  const int nsys = 2 * nb;
+  const int nsys = nb << QS;
   int S = min(sep_seg_max(nb), na);
   const int len = (na + S - 1) / S;
   S = (na + len - 1) / len;
@@ -275,14 +319,14 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
     // same order as the general path below.
     const int t = threadIdx.x;
     const bool act = t < nsys * S;
-    const int l = act ? t % nsys : 0, sg = act ? t / nsys : 0, q = l >> 1;
+    const int l = act ? t % nsys : 0, sg = act ? t / nsys : 0, q = l >> QS;
     const int beg = sg * len, cnt = act ? min(na, beg + len) - beg : 0;
     double y[kSegReg], bf[kSegReg], bb[kSegReg];
     double yl = 0.0, P = 1.0;
 #pragma unroll
     for (int k = 0; k < kSegReg; ++k) {
       const int i = beg + min(k, max(cnt - 1, 0));  // clamped into the segment
-      const double wv = w[2 * i * nb + l], iv = id[i * nb + q];
+      const double wv = w[i * ws + l], iv = id[i * nb + q];
       const double dv = i > 0 ? T.da[i] : 0.0;
       const double cv = i < na - 1 ? cp[i * nb + q] : 0.0;
       const double a = wv * iv;
@@ -295,7 +339,7 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
       y[k] = yl;
     }
     if (act && S > 1) {
-      if ((l & 1) == 0) pend[sg * nb + q] = P;
+      if ((l & QS) == 0) pend[sg * nb + q] = P;
       eend[sg * nsys + l] = yl;
     }
     __syncthreads();
@@ -331,7 +375,7 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
         y[k] = xl;
       }
       if (S > 1) {
-        if ((l & 1) == 0) pendB[sg * nb + q] = Q;
+        if ((l & QS) == 0) pendB[sg * nb + q] = Q;
         eendB[sg * nsys + l] = xl;
       }
     }
@@ -362,12 +406,12 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
       }
 #pragma unroll
       for (int k = 0; k < kSegReg; ++k)
-        if (k < cnt) w[2 * (beg + k) * nb + l] = y[k];
+        if (k < cnt) w[(beg + k) * ws + l] = y[k];
     }
   } else {
     // forward sweep, local part
     for (int t = threadIdx.x; t < nsys * S; t += blockDim.x) {
-      const int l = t % nsys, sg = t / nsys, q = l >> 1;
+      const int l = t % nsys, sg = t / nsys, q = l >> QS;
       const int beg = sg * len, end = min(na, beg + len);
       double y = 0.0, P = 1.0;
       for (int i0 = beg; i0 < end; i0 += kSepChunk) {
@@ -375,7 +419,7 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
   #pragma unroll
         for (int k = 0; k < kSepChunk; ++k) {
           const int i = min(i0 + k, end - 1);
-          v[k] = w[2 * i * nb + l];
+          v[k] = w[i * ws + l];
           pv[k] = id[i * nb + q];
           dv[k] = i > 0 ? T.da[i] : 0.0;
         }
@@ -390,17 +434,17 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
         }
   #pragma unroll
         for (int k = 0; k < kSepChunk; ++k)
-          if (i0 + k < end) w[2 * (i0 + k) * nb + l] = v[k];
+          if (i0 + k < end) w[(i0 + k) * ws + l] = v[k];
       }
       if (S > 1) {
-        if ((l & 1) == 0) pend[sg * nb + q] = P;
+        if ((l & QS) == 0) pend[sg * nb + q] = P;
         eend[sg * nsys + l] = y;
       }
     }
     if (S > 1) {
       __syncthreads();
       for (int t = threadIdx.x; t < nsys * S; t += blockDim.x) {
-        const int l = t % nsys, sg = t / nsys, q = l >> 1;
+        const int l = t % nsys, sg = t / nsys, q = l >> QS;
         if (sg == 0) continue;
         double c = 0.0;
         for (int s2 = 0; s2 < sg; ++s2) c = fma(pend[s2 * nb + q], c, eend[s2 * nsys + l]);
@@ -411,7 +455,7 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
   #pragma unroll
           for (int k = 0; k < kSepChunk; ++k) {
             const int i = min(i0 + k, end - 1);
-            v[k] = w[2 * i * nb + l];
+            v[k] = w[i * ws + l];
             pv[k] = id[i * nb + q];
             dv[k] = T.da[i];
           }
@@ -422,14 +466,14 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
           }
   #pragma unroll
           for (int k = 0; k < kSepChunk; ++k)
-            if (i0 + k < end) w[2 * (i0 + k) * nb + l] = v[k];
+            if (i0 + k < end) w[(i0 + k) * ws + l] = v[k];
         }
       }
     }
     __syncthreads();
     // back substitution, local part
     for (int t = threadIdx.x; t < nsys * S; t += blockDim.x) {
-      const int l = t % nsys, sg = t / nsys, q = l >> 1;
+      const int l = t % nsys, sg = t / nsys, q = l >> QS;
       const int beg = sg * len, end = min(na, beg + len);
       double x = 0.0, Q = 1.0;
       for (int i1 = end - 1; i1 >= beg; i1 -= kSepChunk) {
@@ -437,7 +481,7 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
   #pragma unroll
         for (int k = 0; k < kSepChunk; ++k) {
           const int i = max(i1 - k, beg);
-          v[k] = w[2 * i * nb + l];
+          v[k] = w[i * ws + l];
           cv[k] = i < na - 1 ? cp[i * nb + q] : 0.0;
         }
   #pragma unroll
@@ -450,17 +494,17 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
         }
   #pragma unroll
         for (int k = 0; k < kSepChunk; ++k)
-          if (i1 - k >= beg) w[2 * (i1 - k) * nb + l] = v[k];
+          if (i1 - k >= beg) w[(i1 - k) * ws + l] = v[k];
       }
       if (S > 1) {
-        if ((l & 1) == 0) pend[sg * nb + q] = Q;
+        if ((l & QS) == 0) pend[sg * nb + q] = Q;
         eend[sg * nsys + l] = x;
       }
     }
     if (S > 1) {
       __syncthreads();
       for (int t = threadIdx.x; t < nsys * S; t += blockDim.x) {
-        const int l = t % nsys, sg = t / nsys, q = l >> 1;
+        const int l = t % nsys, sg = t / nsys, q = l >> QS;
         if (sg == S - 1) continue;
         double c = 0.0;
         for (int s2 = S - 1; s2 > sg; --s2) c = fma(pend[s2 * nb + q], c, eend[s2 * nsys + l]);
@@ -471,7 +515,7 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
   #pragma unroll
           for (int k = 0; k < kSepChunk; ++k) {
             const int i = max(i1 - k, beg);
-            v[k] = w[2 * i * nb + l];
+            v[k] = w[i * ws + l];
             cv[k] = cp[i * nb + q];
           }
   #pragma unroll
@@ -481,13 +525,13 @@ __device__ __forceinline__ void coarse_separable(const LevelDev& L, const Tab<do
           }
   #pragma unroll
           for (int k = 0; k < kSepChunk; ++k)
-            if (i1 - k >= beg) w[2 * (i1 - k) * nb + l] = v[k];
+            if (i1 - k >= beg) w[(i1 - k) * ws + l] = v[k];
         }
       }
     }
   }
   __syncthreads();
-  sep_rows(f, na, nb, vt);
+  sep_rows<QS>(w, na, nb, ws, vt);
   __syncthreads();
 }
 
@@ -754,7 +798,7 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
   // factors exist (the solution replaces f in place), otherwise by red-black
   // SOR from zero until the residual 2-norm dropped by rtol (Sec. 3.3)
   if (sep) {
-    coarse_separable(LC, tabC, m, fC, sepV, sepF, pre);
+    coarse_separable<1>(LC, tabC, m, reinterpret_cast<double*>(fC), 2 * LC.nb, sepV, sepF, pre);
   } else {
     const LevelDev& L = LC;
     const Tab<double>& T = tabC;
@@ -867,6 +911,128 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
   }
 }
 
+// Exact coarsest solve of planes whose only level in the launch is the
+// coarsest, with separable factors: the operator is real, so the real and the
+// imaginary part of a plane are independent problems, and each gets a block
+// of its own (twice the blocks of one per plane, half the work per block).
+// The component sits in LDS as a real plane of row stride split_ws(nb)
+// doubles, 4 more than a multiple of 32, which spreads the 16 rows a matrix
+// core operand reads over the LDS banks.  The arithmetic per element is that
+// of the complex path, so both give the same bits.
+__host__ __device__ inline int split_ws(int nb) { return nb + ((4 - nb % 32) + 32) % 32; }
+
+// LDS layout in doubles: o[0] eigenvector tables (V^T, V^-T), o[1] Thomas
+// factors and segment-end scratch, o[2] the plane, o[3] the 1D tables,
+// o[4] the total.
+__host__ __device__ inline void split_layout(int na, int nb, int* o) {
+  auto al = [](int x) { return (x + 1) & ~1; };
+  const int S = sep_seg_max(nb);
+  o[0] = 0;
+  o[1] = al(2 * nb * nb);
+  o[2] = o[1] + al(2 * na * nb + 4 * S * nb);
+  o[3] = o[2] + al(na * split_ws(nb));
+  o[4] = o[3] + al(5 * na + 4 * nb);
+}
+
+constexpr int kSplitThreads = 256;  // >= nb sep_seg_max(nb) for every nb
+
+template <typename R>
+__global__ void __launch_bounds__(kSplitThreads) k_coarse_split(const LdsJob* __restrict__ jobs, BatchRef bt) {
+  using V = typename Vec<R>::T;
+  extern __shared__ char smem[];
+  const int p = blockIdx.x, comp = blockIdx.y;
+  if (bt.count && p >= *bt.count) return;
+  const int e = bt.ent[p];
+  const LdsJob& J = jobs[ent_prob(e)];
+  const LevelDev& LC = J.LL.L[0];
+  const int slot = ent_slot(e);
+  const int m = J.mode ? J.mode[slot] : slot;
+  const int na = LC.na, nb = LC.nb, nn = na * nb, nv = nb * nb, ws = split_ws(nb);
+  int o[5];
+  split_layout(na, nb, o);
+  double* D = reinterpret_cast<double*>(smem);
+  double* sepV = D + o[0];
+  double* sepF = D + o[1];
+  double* X = D + o[2];
+  const size_t off = (size_t)slot * nn;
+  const V* fv = static_cast<const V*>(J.f) + off;
+  // stage the eigenvector tables, the Thomas factors and this component of
+  // f, all loads in flight together; pairs of entries per 16-byte load when
+  // the sizes are even (tables and planes start on 16-byte boundaries)
+  const bool pairs = (nb & 1) == 0;
+  const int nv2 = nv / 2, nn2 = nn / 2;
+#pragma unroll 2
+  for (int t = threadIdx.x; pairs && t < max(nv2, nn2); t += blockDim.x) {
+    double2 v0 = make_double2(0.0, 0.0), v1 = v0, c0 = v0, c1 = v0;
+    double fa = 0.0, fb = 0.0;
+    if (t < nv2) {
+      v0 = gbl(reinterpret_cast<const double2*>(LC.sep_v + (size_t)m * nv))[t];
+      v1 = gbl(reinterpret_cast<const double2*>(LC.sep_vi + (size_t)m * nv))[t];
+    }
+    if (t < nn2) {
+      c0 = gbl(reinterpret_cast<const double2*>(LC.sep_cp + (size_t)m * nn))[t];
+      c1 = gbl(reinterpret_cast<const double2*>(LC.sep_id + (size_t)m * nn))[t];
+      if constexpr (sizeof(V) == 8) {
+        const float4 f4 = gbl(reinterpret_cast<const float4*>(fv))[t];
+        fa = comp ? f4.y : f4.x;
+        fb = comp ? f4.w : f4.z;
+      } else {
+        const V a = gbl(fv)[2 * t], b = gbl(fv)[2 * t + 1];
+        fa = comp ? a.y : a.x;
+        fb = comp ? b.y : b.x;
+      }
+    }
+    if (t < nv2) {
+      sepV[2 * t] = v0.x;
+      sepV[2 * t + 1] = v0.y;
+      sepV[nv + 2 * t] = v1.x;
+      sepV[nv + 2 * t + 1] = v1.y;
+    }
+    if (t < nn2) {
+      sepF[2 * t] = c0.x;
+      sepF[2 * t + 1] = c0.y;
+      sepF[nn + 2 * t] = c1.x;
+      sepF[nn + 2 * t + 1] = c1.y;
+      const int i = 2 * t / nb, j = 2 * t - i * nb;  // nb even: both cells in row i
+      X[i * ws + j] = fa;
+      X[i * ws + j + 1] = fb;
+    }
+  }
+#pragma unroll 4
+  for (int t = threadIdx.x; !pairs && t < max(nv, nn); t += blockDim.x) {
+    double v0 = 0.0, v1 = 0.0, c0 = 0.0, c1 = 0.0, fa = 0.0;
+    if (t < nv) {
+      v0 = gbl(LC.sep_v + (size_t)m * nv)[t];
+      v1 = gbl(LC.sep_vi + (size_t)m * nv)[t];
+    }
+    if (t < nn) {
+      c0 = gbl(LC.sep_cp + (size_t)m * nn)[t];
+      c1 = gbl(LC.sep_id + (size_t)m * nn)[t];
+      const V a = gbl(fv)[t];
+      fa = comp ? a.y : a.x;
+    }
+    if (t < nv) {
+      sepV[t] = v0;
+      sepV[nv + t] = v1;
+    }
+    if (t < nn) {
+      sepF[t] = c0;
+      sepF[nn + t] = c1;
+      const int i = t / nb;
+      X[i * ws + (t - i * nb)] = fa;
+    }
+  }
+  const Tab<double> T = stage_tab<double>(LC, m, D + o[3]);
+  __syncthreads();
+  coarse_separable<0>(LC, T, m, X, ws, sepV, sepF, true);
+  R* ug = reinterpret_cast<R*>(static_cast<V*>(J.u) + off) + comp;
+#pragma unroll 4
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+    const int i = t / nb;
+    ug[2 * t] = (R)X[i * ws + (t - i * nb)];
+  }
+}
+
 template <typename R>
 size_t cycle_bytes(const LdsLevels& LL) {
   int o[kLayoutSlots];
@@ -916,6 +1082,24 @@ int lds_cycle_threads(const LdsLevels& LL) { return cycle_threads(LL); }
 hipError_t mg_lds_cycle(const LdsJob* jobs, const LdsJob* hj, int n_prob, const BatchRef& b, int nu_pre, int nu_post,
                         int n_sor, bool exact, bool fp32, double rtol, int max_sweeps, hipStream_t st) {
   if (!b.cap) return hipSuccess;
+  // every plane's only level the separable coarsest: one block per component
+  bool split = true;
+  size_t slds = 0;
+  for (int q = 0; q < n_prob && split; ++q) {
+    const LdsLevels& LL = hj[q].LL;
+    split = LL.n == 1 && LL.L[0].sep_v != nullptr && LL.L[0].nb <= 16 * kSepMaxTiles;
+    if (split) {
+      int o[5];
+      split_layout(LL.L[0].na, LL.L[0].nb, o);
+      slds = std::max(slds, sizeof(double) * (size_t)o[4]);
+    }
+  }
+  if (split && slds <= lds_limit() - 1024) {
+    const dim3 grid(b.cap, 2);
+    if (fp32) hipLaunchKernelGGL(k_coarse_split<float>, grid, dim3(kSplitThreads), slds, st, jobs, b);
+    else hipLaunchKernelGGL(k_coarse_split<double>, grid, dim3(kSplitThreads), slds, st, jobs, b);
+    return hipGetLastError();
+  }
   size_t lds = 0;
   int threads = 64;
   for (int q = 0; q < n_prob; ++q) {
