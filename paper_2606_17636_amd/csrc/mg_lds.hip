@@ -11,6 +11,7 @@
 // is always solved in FP64 (the mixed form keeps the coarsest solve in FP64).
 #include <algorithm>
 
+#include "batch_dev.h"
 #include "relax_dev.h"
 #include "smg_internal.h"
 #include "vec.h"
@@ -606,8 +607,9 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
   __shared__ double redbuf[NT / 64];
   Red red{redbuf};
   const int p = blockIdx.x;
-  if (bt.count && p >= *bt.count) return;
-  const int e = bt.ent[p];
+  pin_scalar(jobs);
+  int e;
+  if (!batch_entry(bt, p, e)) return;
   const LdsJob& J = jobs[ent_prob(e)];
   const LdsLevels& LL = J.LL;
   const int slot = ent_slot(e);
@@ -941,12 +943,24 @@ __global__ void __launch_bounds__(kSplitThreads) k_coarse_split(const LdsJob* __
   using V = typename Vec<R>::T;
   extern __shared__ char smem[];
   const int p = blockIdx.x, comp = blockIdx.y;
-  if (bt.count && p >= *bt.count) return;
-  const int e = bt.ent[p];
+  pin_scalar(jobs);
+  int e;
+  if (!batch_entry(bt, p, e)) return;
+  // the job's fields, read in one round before the mode lookup branches
   const LdsJob& J = jobs[ent_prob(e)];
-  const LevelDev& LC = J.LL.L[0];
+  const LevelDev LC = J.LL.L[0];
+  void* const ju = J.u;
+  const void* const jf = J.f;
+  const int* const jmode = J.mode;
+  for (const void* v : {(const void*)jmode, (const void*)ju, jf, (const void*)LC.sep_v, (const void*)LC.sep_vi,
+                        (const void*)LC.sep_cp, (const void*)LC.sep_id, (const void*)LC.ua, (const void*)LC.da,
+                        (const void*)LC.Rr, (const void*)LC.Ca, (const void*)LC.wb, (const void*)LC.ub,
+                        (const void*)LC.db, (const void*)LC.Cb, (const void*)LC.wr})
+    pin_scalar(v);
+  pin_scalar(LC.na);
+  pin_scalar(LC.nb);
   const int slot = ent_slot(e);
-  const int m = J.mode ? J.mode[slot] : slot;
+  const int m = jmode ? jmode[slot] : slot;
   const int na = LC.na, nb = LC.nb, nn = na * nb, nv = nb * nb, ws = split_ws(nb);
   int o[5];
   split_layout(na, nb, o);
@@ -955,7 +969,7 @@ __global__ void __launch_bounds__(kSplitThreads) k_coarse_split(const LdsJob* __
   double* sepF = D + o[1];
   double* X = D + o[2];
   const size_t off = (size_t)slot * nn;
-  const V* fv = static_cast<const V*>(J.f) + off;
+  const V* fv = static_cast<const V*>(jf) + off;
   // stage the eigenvector tables, the Thomas factors and this component of
   // f, all loads in flight together; pairs of entries per 16-byte load when
   // the sizes are even (tables and planes start on 16-byte boundaries)
@@ -1025,7 +1039,7 @@ __global__ void __launch_bounds__(kSplitThreads) k_coarse_split(const LdsJob* __
   const Tab<double> T = stage_tab<double>(LC, m, D + o[3]);
   __syncthreads();
   coarse_separable<0>(LC, T, m, X, ws, sepV, sepF, true);
-  R* ug = reinterpret_cast<R*>(static_cast<V*>(J.u) + off) + comp;
+  R* ug = reinterpret_cast<R*>(static_cast<V*>(ju) + off) + comp;
 #pragma unroll 4
   for (int t = threadIdx.x; t < nn; t += blockDim.x) {
     const int i = t / nb;
