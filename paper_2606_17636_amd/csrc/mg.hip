@@ -32,6 +32,7 @@
 
 #include <hip/hip_ext.h>
 
+#include "batch_dev.h"
 #include "relax_dev.h"
 #include "smg_internal.h"
 #include "vec.h"
@@ -132,14 +133,23 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
   const unsigned xcd = bid % kXcds, kk = bid / kXcds, per = nblk / kXcds, rem = nblk % kXcds;
   const unsigned lid = xcd < rem ? xcd * (per + 1) + kk : rem * (per + 1) + (xcd - rem) * per + kk;
   const int bx = (int)(lid % gridDim.x), p = (int)(lid / gridDim.x);
-  if (bt.count && p >= *bt.count) return;
-  const int e = bt.ent[p];
+  int e;
+  if (!batch_entry(bt, p, e)) return;
+  // the job's fields, read in one round before the exit and the mode lookup
+  // branch on them
   const LvJob& J = jobs[ent_prob(e)];
-  if (!J.active || bx >= J.ntile[DIR]) return;
-  const int slot = ent_slot(e);
-  const int m = J.mode ? J.mode[slot] : slot;
+  const int active = J.active, ntile = J.ntile[DIR];
   const LevelDev L = J.L;
   const int tile = J.tile[DIR], scratch_words = J.scratch[DIR];
+  const int* const jmode = J.mode;
+  for (const void* v : {(const void*)jmode, (const void*)J.u, (const void*)J.u2, (const void*)J.f, (const void*)L.ua,
+                        (const void*)L.da, (const void*)L.Rr, (const void*)L.Ca, (const void*)L.wb, (const void*)L.ub,
+                        (const void*)L.db, (const void*)L.Cb, (const void*)L.wr})
+    pin_scalar(v);
+  for (int v : {active, ntile, tile, scratch_words, L.na, L.nb}) pin_scalar(v);
+  if (!active || bx >= ntile) return;
+  const int slot = ent_slot(e);
+  const int m = jmode ? jmode[slot] : slot;
   const int na = L.na, nb = L.nb;
   // radial lines: u -> u2; polar lines: u2 -> u (a launch never reads what
   // another of its blocks writes)
@@ -433,8 +443,8 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
 // Common prologue of the per-cell kernels: resolve list entry blockIdx.y.
 #define SMG_ENTRY(JOBS, BT)                                  \
   const int p = blockIdx.y;                                  \
-  if ((BT).count && p >= *(BT).count) return;                \
-  const int e = (BT).ent[p];                                 \
+  int e;                                                     \
+  if (!batch_entry((BT), p, e)) return;                      \
   const auto& J = (JOBS)[ent_prob(e)];                       \
   const int slot = ent_slot(e);                              \
   const int m = J.mode ? J.mode[slot] : slot;                \
