@@ -87,22 +87,28 @@ def test_batch_graph_matches_oracle(precision, tol, bound):
 
 
 SPEC_COARSE_ONLY = GridSpec("spherical", "log", 128, 64, 16, 0.05, 5.0, 0.0, math.pi)
+# 256x42 planes coarsened once to 128x21: an odd width (single-entry staging
+# loads) outside the unrolled ones (runtime K loop of the row transform) with
+# segments longer than the register path takes (general tridiagonal sweeps).
+# Cylindrical with square cells, so that two levels converge in a few cycles.
+SPEC_COARSE_ODD = GridSpec("cylindrical", "uniform", 256, 42, 8, 0.2, 2.0, -0.15, 0.15)
 
 
+@pytest.mark.parametrize("spec,coarse", [(SPEC_COARSE_ONLY, 2048), (SPEC_COARSE_ODD, 2688)], ids=["64x32", "128x21"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_component_coarse_solve_matches_complex_path_bitwise(precision):
-    """128x64 planes with a 2048-cell coarsest level: the fused launch holds
-    only the separable coarsest level, which is solved with one block per
-    real and imaginary component.  Batched with a problem that fuses several
-    levels, the same planes take the complex path in one block each.  Both
-    give the same bits, and the result meets the FP64 oracle."""
+def test_component_coarse_solve_matches_complex_path_bitwise(precision, spec, coarse):
+    """Planes whose fused launch holds only the separable coarsest level are
+    solved with one block per real and imaginary component.  Batched with a
+    problem that fuses several levels, the same planes take the complex path
+    in one block each.  Both give the same bits, and the result meets the
+    FP64 oracle."""
     from paper_2606_17636_amd import smg
     kw = dict(precision=precision, launch="dynamic", nu_pre=2, nu_post=2)
-    print(f"[setup] {SPEC_COARSE_ONLY} {kw}", flush=True)
-    coarse_only = smg.grid_from_spec(SPEC_COARSE_ONLY, n_pad=16, coarse_cells=2048, **kw).setup()
+    print(f"[setup] {spec} coarse_cells={coarse} {kw}", flush=True)
+    coarse_only = smg.grid_from_spec(spec, n_pad=16, coarse_cells=coarse, **kw).setup()
     print(f"[setup] {SPECS[1][0]} {kw}", flush=True)
     fused = smg.grid_from_spec(SPECS[1][0], n_pad=SPECS[1][1], **kw).setup()
-    rho_h = _rho(SPEC_COARSE_ONLY, 41)
+    rho_h = _rho(spec, 41)
     rhos = [_dev(rho_h), _dev(_rho(SPECS[1][0], 42))]
     tol = 1e-10 if precision == "fp64" else 1e-8
     single = [coarse_only.solve(rhos[0], tol=tol), fused.solve(rhos[1], tol=tol)]
@@ -111,5 +117,5 @@ def test_component_coarse_solve_matches_complex_path_bitwise(precision):
         assert infos[k]["converged"], k
         assert np.array_equal(infos[k]["cycles1"], single[k][1]["cycles1"]), k
         assert torch.equal(phis[k], single[k][0]), k
-    ref = OraclePlan(SPEC_COARSE_ONLY, n_pad=16).solve(rho_h)
-    assert _l2(SPEC_COARSE_ONLY, phis[0].cpu().numpy(), ref) < (1e-8 if precision == "fp64" else 1e-6)
+    ref = OraclePlan(spec, n_pad=16).solve(rho_h)
+    assert _l2(spec, phis[0].cpu().numpy(), ref) < (1e-8 if precision == "fp64" else 1e-6)
