@@ -358,7 +358,7 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the path would shard "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the path would shard "
               "by Fourier mode across GPUs, which is not built here.", file=sys.stderr)
         sys.exit(2)
 
