@@ -924,8 +924,8 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
 __host__ __device__ inline int split_ws(int nb) { return nb + ((4 - nb % 32) + 32) % 32; }
 
 // LDS layout in doubles: o[0] eigenvector tables (V^T, V^-T), o[1] Thomas
-// factors and segment-end scratch, o[2] the plane, o[3] the 1D tables,
-// o[4] the total.
+// factors and segment-end scratch, o[2] the plane, o[3] the radial table da
+// of the sweeps, o[4] the total.
 __host__ __device__ inline void split_layout(int na, int nb, int* o) {
   auto al = [](int x) { return (x + 1) & ~1; };
   const int S = sep_seg_max(nb);
@@ -933,7 +933,7 @@ __host__ __device__ inline void split_layout(int na, int nb, int* o) {
   o[1] = al(2 * nb * nb);
   o[2] = o[1] + al(2 * na * nb + 4 * S * nb);
   o[3] = o[2] + al(na * split_ws(nb));
-  o[4] = o[3] + al(5 * na + 4 * nb);
+  o[4] = o[3] + al(na);
 }
 
 constexpr int kSplitThreads = 256;  // >= nb sep_seg_max(nb) for every nb
@@ -953,9 +953,7 @@ __global__ void __launch_bounds__(kSplitThreads) k_coarse_split(const LdsJob* __
   const void* const jf = J.f;
   const int* const jmode = J.mode;
   for (const void* v : {(const void*)jmode, (const void*)ju, jf, (const void*)LC.sep_v, (const void*)LC.sep_vi,
-                        (const void*)LC.sep_cp, (const void*)LC.sep_id, (const void*)LC.ua, (const void*)LC.da,
-                        (const void*)LC.Rr, (const void*)LC.Ca, (const void*)LC.wb, (const void*)LC.ub,
-                        (const void*)LC.db, (const void*)LC.Cb, (const void*)LC.wr})
+                        (const void*)LC.sep_cp, (const void*)LC.sep_id, (const void*)LC.da})
     pin_scalar(v);
   pin_scalar(LC.na);
   pin_scalar(LC.nb);
@@ -970,32 +968,20 @@ __global__ void __launch_bounds__(kSplitThreads) k_coarse_split(const LdsJob* __
   double* X = D + o[2];
   const size_t off = (size_t)slot * nn;
   const V* fv = static_cast<const V*>(jf) + off;
-  // stage the eigenvector tables, the Thomas factors and this component of
-  // f, all loads in flight together; pairs of entries per 16-byte load when
-  // the sizes are even (tables and planes start on 16-byte boundaries)
+  // stage the eigenvector tables, the Thomas factors, this component of f
+  // and the sweeps' one 1D table (da), all loads in flight together; pairs
+  // of entries per 16-byte load when the sizes are even (tables and planes
+  // start on 16-byte boundaries)
+  double* const da = D + o[3];
+  double da0 = 0.0;  // da of row threadIdx.x (clamped), loaded with the first batch
   const bool pairs = (nb & 1) == 0;
   const int nv2 = nv / 2, nn2 = nn / 2;
-#pragma unroll 2
-  for (int t = threadIdx.x; pairs && t < max(nv2, nn2); t += blockDim.x) {
-    double2 v0 = make_double2(0.0, 0.0), v1 = v0, c0 = v0, c1 = v0;
-    double fa = 0.0, fb = 0.0;
-    if (t < nv2) {
-      v0 = gbl(reinterpret_cast<const double2*>(LC.sep_v + (size_t)m * nv))[t];
-      v1 = gbl(reinterpret_cast<const double2*>(LC.sep_vi + (size_t)m * nv))[t];
-    }
-    if (t < nn2) {
-      c0 = gbl(reinterpret_cast<const double2*>(LC.sep_cp + (size_t)m * nn))[t];
-      c1 = gbl(reinterpret_cast<const double2*>(LC.sep_id + (size_t)m * nn))[t];
-      if constexpr (sizeof(V) == 8) {
-        const float4 f4 = gbl(reinterpret_cast<const float4*>(fv))[t];
-        fa = comp ? f4.y : f4.x;
-        fb = comp ? f4.w : f4.z;
-      } else {
-        const V a = gbl(fv)[2 * t], b = gbl(fv)[2 * t + 1];
-        fa = comp ? a.y : a.x;
-        fb = comp ? b.y : b.x;
-      }
-    }
+  const auto gv2 = gbl(reinterpret_cast<const double2*>(LC.sep_v + (size_t)m * nv));
+  const auto gvi2 = gbl(reinterpret_cast<const double2*>(LC.sep_vi + (size_t)m * nv));
+  const auto gcp2 = gbl(reinterpret_cast<const double2*>(LC.sep_cp + (size_t)m * nn));
+  const auto gid2 = gbl(reinterpret_cast<const double2*>(LC.sep_id + (size_t)m * nn));
+  // one pair position of every array into LDS (component comp of f)
+  auto put = [&](int t, double2 v0, double2 v1, double2 c0, double2 c1, double fa, double fb) {
     if (t < nv2) {
       sepV[2 * t] = v0.x;
       sepV[2 * t + 1] = v0.y;
@@ -1011,7 +997,55 @@ __global__ void __launch_bounds__(kSplitThreads) k_coarse_split(const LdsJob* __
       X[i * ws + j] = fa;
       X[i * ws + j + 1] = fb;
     }
+  };
+  auto f_pair = [&](int t, double& fa, double& fb) {
+    if constexpr (sizeof(V) == 8) {
+      const float4 f4 = gbl(reinterpret_cast<const float4*>(fv))[t];
+      fa = comp ? f4.y : f4.x;
+      fb = comp ? f4.w : f4.z;
+    } else {
+      const V a = gbl(fv)[2 * t], b = gbl(fv)[2 * t + 1];
+      fa = comp ? a.y : a.x;
+      fb = comp ? b.y : b.x;
+    }
+  };
+  if (pairs) {
+    // the first kStageBatch positions per thread: every load issued before
+    // any store (indices clamped into range, so no load sits behind a
+    // branch), then the stores; larger planes continue in a strided loop
+    constexpr int kStageBatch = 4;
+    double2 v0[kStageBatch], v1[kStageBatch], c0[kStageBatch], c1[kStageBatch];
+    double fa[kStageBatch], fb[kStageBatch];
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k) {
+      const int t = threadIdx.x + k * (int)blockDim.x;
+      const int tv = min(t, nv2 - 1), tn = min(t, nn2 - 1);
+      if (k == 0) da0 = gbl(LC.da)[min((int)threadIdx.x, na - 1)];
+      v0[k] = gv2[tv];
+      v1[k] = gvi2[tv];
+      c0[k] = gcp2[tn];
+      c1[k] = gid2[tn];
+      f_pair(tn, fa[k], fb[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k)
+      put(threadIdx.x + k * (int)blockDim.x, v0[k], v1[k], c0[k], c1[k], fa[k], fb[k]);
+    for (int t = threadIdx.x + kStageBatch * (int)blockDim.x; t < max(nv2, nn2); t += blockDim.x) {
+      double2 a0 = make_double2(0.0, 0.0), a1 = a0, b0 = a0, b1 = a0;
+      double ga = 0.0, gb = 0.0;
+      if (t < nv2) {
+        a0 = gv2[t];
+        a1 = gvi2[t];
+      }
+      if (t < nn2) {
+        b0 = gcp2[t];
+        b1 = gid2[t];
+        f_pair(t, ga, gb);
+      }
+      put(t, a0, a1, b0, b1, ga, gb);
+    }
   }
+  if (!pairs) da0 = gbl(LC.da)[min((int)threadIdx.x, na - 1)];
 #pragma unroll 4
   for (int t = threadIdx.x; !pairs && t < max(nv, nn); t += blockDim.x) {
     double v0 = 0.0, v1 = 0.0, c0 = 0.0, c1 = 0.0, fa = 0.0;
@@ -1036,7 +1070,10 @@ __global__ void __launch_bounds__(kSplitThreads) k_coarse_split(const LdsJob* __
       X[i * ws + (t - i * nb)] = fa;
     }
   }
-  const Tab<double> T = stage_tab<double>(LC, m, D + o[3]);
+  if (threadIdx.x < na) da[threadIdx.x] = da0;
+  for (int i = threadIdx.x + blockDim.x; i < na; i += blockDim.x) da[i] = gbl(LC.da)[i];
+  Tab<double> T{};
+  T.da = da;  // the only table the exact solve reads
   __syncthreads();
   coarse_separable<0>(LC, T, m, X, ws, sepV, sepF, true);
   R* ug = reinterpret_cast<R*>(static_cast<V*>(ju) + off) + comp;
