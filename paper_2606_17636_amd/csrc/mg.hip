@@ -150,6 +150,7 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
   if (!active || bx >= ntile) return;
   const int slot = ent_slot(e);
   const int m = jmode ? jmode[slot] : slot;
+  pin_scalar(m);  // resolved before the loads that index by it are issued
   const int na = L.na, nb = L.nb;
   // radial lines: u -> u2; polar lines: u2 -> u (a launch never reads what
   // another of its blocks writes)
@@ -230,22 +231,32 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
       fb[k] = f[(size_t)i * nb + j];
     }
   }
+  // The table loads are unconditional (indices clamped into the plane) and
+  // rows or columns outside it are masked arithmetically (x * 1 + 0 == x):
+  // a select or a guard on a load becomes a branch that waits for the load
+  // inside it, one round of memory latency per table.
   auto row_tables = [&](int rr, R* tr) {
     const int i = r0 + rr;
-    const bool in = i >= 0 && i < na;
-    tr[0] = in ? (R)gbl(L.ua)[i] : (R)0;
-    tr[1] = in ? (R)gbl(L.da)[i] : (R)0;
-    tr[2] = in ? (R)gbl(L.Rr)[i] : (R)0;
-    tr[3] = in ? (R)gbl(L.Ca)[(size_t)m * na + i] : (R)1;
-    tr[4] = in ? (R)gbl(L.wb)[(size_t)m * na + i] : (R)0;
+    const R in = (i >= 0 && i < na) ? (R)1 : (R)0;
+    const int ic = min(max(i, 0), na - 1);
+    const double a0 = gbl(L.ua)[ic], a1 = gbl(L.da)[ic], a2 = gbl(L.Rr)[ic];
+    const double a3 = gbl(L.Ca)[(size_t)m * na + ic], a4 = gbl(L.wb)[(size_t)m * na + ic];
+    tr[0] = (R)a0 * in;
+    tr[1] = (R)a1 * in;
+    tr[2] = (R)a2 * in;
+    tr[3] = (R)a3 * in + ((R)1 - in);
+    tr[4] = (R)a4 * in;
   };
   auto col_tables = [&](int cc, R* tc) {
     const int j = c0 + cc;
-    const bool in = j >= 0 && j < nb;
-    tc[0] = in ? (R)gbl(L.ub)[j] : (R)0;
-    tc[1] = in ? (R)gbl(L.db)[j] : (R)0;
-    tc[2] = in ? (R)gbl(L.Cb)[(size_t)m * nb + j] : (R)0;
-    tc[3] = in ? (R)gbl(L.wr)[(size_t)m * nb + j] : (R)0;
+    const R in = (j >= 0 && j < nb) ? (R)1 : (R)0;
+    const int jc = min(max(j, 0), nb - 1);
+    const double b0 = gbl(L.ub)[jc], b1 = gbl(L.db)[jc];
+    const double b2 = gbl(L.Cb)[(size_t)m * nb + jc], b3 = gbl(L.wr)[(size_t)m * nb + jc];
+    tc[0] = (R)b0 * in;
+    tc[1] = (R)b1 * in;
+    tc[2] = (R)b2 * in;
+    tc[3] = (R)b3 * in;
   };
   auto row_prolong = [&](int rr, int* ix, R* w) {
     const int i = min(max(r0 + rr, 0), na - 1);
@@ -278,14 +289,12 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
   const int me = threadIdx.x;
   R tr[5], tc[4], wr[2] = {0, 0}, wc[2] = {0, 0};
   int ir[2] = {0, 0}, ic[2] = {0, 0};
-  if (me < nr) {
-    row_tables(me, tr);
-    if (PROLONG) row_prolong(me, ir, wr);
-  }
-  if (me < nc) {
-    col_tables(me, tc);
-    if (PROLONG) col_prolong(me, ic, wc);
-  }
+  // every thread loads (clamped to the last row and column), so no load
+  // sits behind a branch; only the owners store
+  row_tables(min(me, nr - 1), tr);
+  if (PROLONG) row_prolong(min(me, nr - 1), ir, wr);
+  col_tables(min(me, nc - 1), tc);
+  if (PROLONG) col_prolong(min(me, nc - 1), ic, wc);
   // stores of the first batch
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
