@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
     const int t = threadIdx.x + k * NT;
     int i, j;
     ub[k] = mkv<R>(0, 0);
-    if (!PROLONG && !ZERO && t < n_u && u_pos(t, i, j)) ub[k] = u[(size_t)i * nb + j];
+    if (!ZERO && t < n_u && u_pos(t, i, j)) ub[k] = u[(size_t)i * nb + j];
   }
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
@@ -347,8 +347,36 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
     __syncthreads();
     const int cnb = J.C.nb;
     const auto uc = gbl(static_cast<const V*>(J.uc) + (size_t)slot * J.C.na * cnb);
+    // The first batch's positions, whose u is in registers: the coarse
+    // values are read unconditionally (the position clamped into the tile;
+    // the staged indices are in range for every tile row and column) and
+    // cells outside the plane are masked arithmetically, so the reads of
+    // all positions are in flight together.  For a cell in the plane the
+    // operations and their order are those of coarse_corr + add (k_prolong),
+    // so a fused launch rounds exactly like the separate pass.
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int t = min(threadIdx.x + k * NT, n_u - 1);
+      const int rr = t / nc, cc = t - rr * nc;
+      int i, j;
+      const R in = u_pos(t, i, j) ? (R)1 : (R)0;
+      const int a0 = pix[rr], a1 = pix[nr + rr], b0 = pix[2 * nr + cc], b1 = pix[2 * nr + nc + cc];
+      const R wa0 = pwt[rr], wa1 = pwt[nr + rr], wb0 = pwt[2 * nr + cc], wb1 = pwt[2 * nr + nc + cc];
+      V ev = mkv<R>(0, 0);
+      ev = axpy<R>(wa0 * wb0, (V)uc[(size_t)a0 * cnb + b0], ev);
+      ev = axpy<R>(wa0 * wb1, (V)uc[(size_t)a0 * cnb + b1], ev);
+      ev = axpy<R>(wa1 * wb0, (V)uc[(size_t)a1 * cnb + b0], ev);
+      ev = axpy<R>(wa1 * wb1, (V)uc[(size_t)a1 * cnb + b1], ev);
+      ub[k] = mkv<R>((ub[k].x + ev.x) * in, (ub[k].y + ev.y) * in);
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int t = threadIdx.x + k * NT;
+      if (t < n_u) sh[t] = ub[k];
+    }
+    // the rest of larger tiles
 #pragma unroll 4
-    for (int t = threadIdx.x; t < n_u; t += NT) {
+    for (int t = threadIdx.x + KB * NT; t < n_u; t += NT) {
       const int rr = t / nc, cc = t - rr * nc;
       int i, j;
       V v = mkv<R>(0, 0);
