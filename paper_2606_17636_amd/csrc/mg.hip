@@ -312,14 +312,16 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
   }
   if (me < nr) store_row(me, tr, ir, wr);
   if (me < nc) store_col(me, tc, ic, wc);
-  // the rest of larger tiles
+  // the rest of larger tiles (reads clamped into the plane and masked, so
+  // that the unrolled iterations' reads are in flight together)
   if (!PROLONG) {
 #pragma unroll 4
     for (int t = threadIdx.x + KB * NT; t < n_u; t += NT) {
       int i, j;
+      const R in = u_pos(t, i, j) ? (R)1 : (R)0;
       V v = mkv<R>(0, 0);
-      if (!ZERO && u_pos(t, i, j)) v = u[(size_t)i * nb + j];
-      sh[t] = v;
+      if (!ZERO) v = u[(size_t)min(max(i, 0), na - 1) * nb + min(max(j, 0), nb - 1)];
+      sh[t] = mkv<R>(v.x * in, v.y * in);
     }
   }
 #pragma unroll 4
@@ -374,26 +376,21 @@ __global__ void __launch_bounds__(NT) k_smooth(const LvJob* __restrict__ jobs, B
       const int t = threadIdx.x + k * NT;
       if (t < n_u) sh[t] = ub[k];
     }
-    // the rest of larger tiles
+    // the rest of larger tiles, in the same form
 #pragma unroll 4
     for (int t = threadIdx.x + KB * NT; t < n_u; t += NT) {
       const int rr = t / nc, cc = t - rr * nc;
       int i, j;
-      V v = mkv<R>(0, 0);
-      if (u_pos(t, i, j)) {
-        const int a0 = pix[rr], a1 = pix[nr + rr], b0 = pix[2 * nr + cc], b1 = pix[2 * nr + nc + cc];
-        const R wa0 = pwt[rr], wa1 = pwt[nr + rr], wb0 = pwt[2 * nr + cc], wb1 = pwt[2 * nr + nc + cc];
-        // same operations in the same order as coarse_corr + add (k_prolong),
-        // so a fused launch rounds exactly like the separate pass
-        V ev = mkv<R>(0, 0);
-        ev = axpy<R>(wa0 * wb0, (V)uc[(size_t)a0 * cnb + b0], ev);
-        ev = axpy<R>(wa0 * wb1, (V)uc[(size_t)a0 * cnb + b1], ev);
-        ev = axpy<R>(wa1 * wb0, (V)uc[(size_t)a1 * cnb + b0], ev);
-        ev = axpy<R>(wa1 * wb1, (V)uc[(size_t)a1 * cnb + b1], ev);
-        const V w = u[(size_t)i * nb + j];
-        v = mkv<R>(w.x + ev.x, w.y + ev.y);
-      }
-      sh[t] = v;
+      const R in = u_pos(t, i, j) ? (R)1 : (R)0;
+      const int a0 = pix[rr], a1 = pix[nr + rr], b0 = pix[2 * nr + cc], b1 = pix[2 * nr + nc + cc];
+      const R wa0 = pwt[rr], wa1 = pwt[nr + rr], wb0 = pwt[2 * nr + cc], wb1 = pwt[2 * nr + nc + cc];
+      V ev = mkv<R>(0, 0);
+      ev = axpy<R>(wa0 * wb0, (V)uc[(size_t)a0 * cnb + b0], ev);
+      ev = axpy<R>(wa0 * wb1, (V)uc[(size_t)a0 * cnb + b1], ev);
+      ev = axpy<R>(wa1 * wb0, (V)uc[(size_t)a1 * cnb + b0], ev);
+      ev = axpy<R>(wa1 * wb1, (V)uc[(size_t)a1 * cnb + b1], ev);
+      const V w = u[(size_t)min(max(i, 0), na - 1) * nb + min(max(j, 0), nb - 1)];
+      sh[t] = mkv<R>((w.x + ev.x) * in, (w.y + ev.y) * in);
     }
   }
   __syncthreads();
