@@ -399,10 +399,11 @@ def main():
     value = args.steps / dt
     log(f"timed {args.steps} solves in {dt:.3f}s -> {value:.2f} solves/s ({args.form})")
 
-    # per-kernel launch durations: the same solves again, launched by the
-    # host loop (the same kernels and launch shapes as the timed replay),
-    # with HIP events on the solve stream: smoother launches record their own
-    # start and stop, the other kernels have an event before and after them
+    # per-kernel launch durations: the same solves again, the scheduled
+    # launches of the timed replay enqueued from the host instead of the
+    # graph, with HIP events on the solve stream: smoother launches record
+    # their own start and stop, the other kernels have an event before and
+    # after them
     plan.profile_begin()
     _timed(plan, rho, phi, args.steps, args.tol, torch)
     stats = plan.profile_end()

@@ -361,7 +361,11 @@ smg_status smg_dgf_table(smg_plan *plan, int m, double *dgf_host, void *stream);
 
 /* ---- per-launch timing ---------------------------------------------------
  * Between smg_profile_begin and smg_profile_end every kernel launch of
- * smg_solve is bracketed by HIP events on the solve's stream.  End
+ * smg_solve is bracketed by HIP events on the solve's stream.  Once an
+ * earlier solve of the plan gave the per-mode cycle schedule, a profiled
+ * solve enqueues the scheduled launches from the host (the launches a graph
+ * replay makes, without the graph), so the durations are those of the
+ * replayed launches; before that it runs the per-cycle host loop.  End
  * synchronises the device and reports, per kernel class, the number of
  * launches, the summed launch durations (ms) and the summed algorithmic
  * bytes (each launch reads its inputs and writes its outputs once: 48 B per

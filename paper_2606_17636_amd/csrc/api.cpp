@@ -1120,9 +1120,11 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
   const int wk = warm ? 1 : 0;
   // scheduled launches (one host synchronisation per solve) once a previous
   // solve of the same kind gave the per-mode cycle counts; per-cycle host
-  // reads for the first solve, for profiling and with SMG_LAUNCH_DYNAMIC
-  const bool sched = g.launch == SMG_LAUNCH_GRAPH && g.hist_ok[wk] && !profiling;
-  const bool graph = sched && !timings;
+  // reads for the first solve and with SMG_LAUNCH_DYNAMIC.  Component timings
+  // and per-launch profiling enqueue the scheduled launches from the host
+  // instead of replaying the graph (the same launches, with events between)
+  const bool sched = g.launch == SMG_LAUNCH_GRAPH && g.hist_ok[wk];
+  const bool graph = sched && !timings && !profiling;
   if (timings) HIPCHK(hipEventRecord(ev[0], st));
   STCHK(fft_forward_all(g, rho, st));
   if (timings) HIPCHK(hipEventRecord(ev[1], st));
