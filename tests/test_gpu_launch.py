@@ -87,6 +87,32 @@ def test_graph_replay_matches_host_loop_bitwise_split_levels():
         assert torch.equal(phi, ref), f"solve {k}"
 
 
+
+def test_profiled_solve_matches_graph_replay_bitwise():
+    """A profiled solve enqueues the scheduled launches of the graph replay
+    from the host, with events between them: the same kernels, shapes and
+    plane counts, so the same bits as the replay.  The per-class statistics
+    cover the finest-level smoothing with positive durations."""
+    kw = dict(precision="mixed", nu_pre=-1, nu_post=-1, coarse_cells=2048)
+    gra = _plan(SPEC_SPLIT, launch="graph", **kw)
+    rho = _dev(_blobs(SPEC_SPLIT, 7))
+    gra.solve(rho, tol=1e-9)  # host loop: learns the per-mode schedule
+    ref, info = gra.solve(rho, tol=1e-9)  # graph replay
+    gra.profile_begin()
+    phi, info_p = gra.solve(rho, tol=1e-9)
+    stats = gra.profile_end()
+    assert info_p["converged"]
+    assert np.array_equal(info_p["cycles1"], info["cycles1"])
+    assert np.array_equal(info_p["cycles2"], info["cycles2"])
+    assert torch.equal(phi, ref)
+    for cls in ("smooth_radial_lines_l0", "smooth_polar_lines_l0", "lds_coarse_cycle", "defect_norm"):
+        assert stats[cls]["launches"] > 0, cls
+        assert stats[cls]["total_ms"] > 0.0 and stats[cls]["bytes"] > 0.0, cls
+    # and a later replay still gives the same bits
+    phi2, _ = gra.solve(rho, tol=1e-9)
+    assert torch.equal(phi2, ref)
+
+
 def test_schedule_shortfall_is_finished():
     """A schedule learnt on an axisymmetric density (no cycles for m > 0)
     applied to a general one: the modes it starves are finished after the
