@@ -607,7 +607,6 @@ __global__ void __launch_bounds__(NT) k_lds_cycle(const LdsJob* __restrict__ job
   __shared__ double redbuf[NT / 64];
   Red red{redbuf};
   const int p = blockIdx.x;
-  pin_scalar(jobs);
   int e;
   if (!batch_entry(bt, p, e)) return;
   const LdsJob& J = jobs[ent_prob(e)];
@@ -943,7 +942,6 @@ __global__ void __launch_bounds__(kSplitThreads) k_coarse_split(const LdsJob* __
   using V = typename Vec<R>::T;
   extern __shared__ char smem[];
   const int p = blockIdx.x, comp = blockIdx.y;
-  pin_scalar(jobs);
   int e;
   if (!batch_entry(bt, p, e)) return;
   // the job's fields, read in one round before the mode lookup branches
