@@ -203,11 +203,14 @@ def dgf_method(spec):
     return "extended" if spec.radial == LOG else "aux"
 
 
-def _box_rhs(spec, op, m, a_s, b_s, dv_s, src_local):
-    """Right-hand side of L_m Gt = 4 pi G e_s with the box boundary data."""
+def _box_rhs(spec, op, m, a_s, b_s, dv_s, src_local, homogeneous=False):
+    """Right-hand side of L_m Gt = 4 pi G e_s with the box boundary data
+    (none when ``homogeneous``: zero ghosts and zero inner flux)."""
     A, B = op.A, op.B
     rhs = np.zeros((op.n_a, op.n_b))
     rhs[src_local] += FOUR_PI * spec.G
+    if homogeneous:
+        return rhs
     ghosts = {}
     if op.edges["a_lo"] == DIRICHLET:
         ghosts["a_lo"] = dv_s * kernel_mode(spec, m, np.full(op.n_b, A.cent[0]), B.cent[1:-1], a_s, b_s)
@@ -232,10 +235,15 @@ def _box_operator(spec, box, edges):
     return PlaneOperator(spec, A, B, edges)
 
 
-def dgf_tables(spec, n_pad=16, method=None, modes=None):
+def dgf_tables(spec, n_pad=16, method=None, modes=None, homogeneous=False):
     """Gt^m(t <- s) for all ghost pairs, shape (n_modes, n_ghost, n_ghost)
-    (row = field ghost t, column = source ghost s).  Parity unpinned (see
-    module docstring)."""
+    (row = field ghost t, column = source ghost s).  ``homogeneous`` drops
+    the box boundary data (used only to pin the source normalisation: the
+    remaining part is exactly reciprocal, Gt(t <- s) / dV_s = Gt(s <- t) /
+    dV_t, because the finite-volume operator is symmetric in the
+    volume-weighted inner product).  The full tables are only approximately
+    reciprocal (the boundary data of one source seen from another is not
+    symmetric); see the module docstring for what pins them."""
     method = method or dgf_method(spec)
     gh = GhostSet(spec)
     modes = range(spec.n_modes) if modes is None else modes
@@ -243,14 +251,16 @@ def dgf_tables(spec, n_pad=16, method=None, modes=None):
     out = np.zeros((len(modes), gh.n, gh.n))
     if method == "extended":
         box, edges = extended_box(spec, n_pad)
+        i_lo, i_hi, j_lo, j_hi = box
+        if not (np.all((gh.i >= i_lo) & (gh.i <= i_hi)) and np.all((gh.j >= j_lo) & (gh.j <= j_hi))):
+            raise ValueError(f"extended DGF box {box} does not contain every ghost cell (n_pad {n_pad} >= n_a?)")
         op = _box_operator(spec, box, edges)
-        i_lo, _, j_lo, _ = box
         for mi, m in enumerate(modes):
             lu = spla.splu(op.matrix(m).tocsc())
             rhs = np.zeros((op.n_a * op.n_b, gh.n))
             for s in range(gh.n):
                 src = (gh.i[s] - i_lo, gh.j[s] - j_lo)
-                rhs[:, s] = _box_rhs(spec, op, m, gh.a[s], gh.b[s], gh.dv3[s], src).ravel()
+                rhs[:, s] = _box_rhs(spec, op, m, gh.a[s], gh.b[s], gh.dv3[s], src, homogeneous).ravel()
             sol = lu.solve(rhs).reshape(op.n_a, op.n_b, gh.n)
             out[mi] = sol[gh.i - i_lo, gh.j - j_lo, :]
         return out
@@ -260,7 +270,7 @@ def dgf_tables(spec, n_pad=16, method=None, modes=None):
             i_lo, i_hi, j_lo, j_hi = box
             op = _box_operator(spec, box, edges)
             src = (gh.i[s] - i_lo, gh.j[s] - j_lo)
-            rhs = _box_rhs(spec, op, m, gh.a[s], gh.b[s], gh.dv3[s], src)
+            rhs = _box_rhs(spec, op, m, gh.a[s], gh.b[s], gh.dv3[s], src, homogeneous)
             sol = spla.spsolve(op.matrix(m).tocsc(), rhs.ravel()).reshape(op.n_a, op.n_b)
             inside = (gh.i >= i_lo) & (gh.i <= i_hi) & (gh.j >= j_lo) & (gh.j <= j_hi)
             col = np.empty(gh.n)

@@ -433,3 +433,197 @@ def test_exact_line_relaxation_handles_strong_anisotropy():
         rates[ls] = (h.defect_norm(u, f, 0) / d1) ** 0.25
     assert rates["sor"] > 0.8
     assert rates["exact"] < 0.25
+
+
+# -- pins of the gravitational constant, the DGF, the ghost potential, the
+#    transfers and the 2D omega --------------------------------------------------
+def _ghost_xyz(geom, a, b, phi):
+    A, B, P = np.asarray(a)[:, None], np.asarray(b)[:, None], np.asarray(phi)[None, :]
+    if geom == SPH:
+        return A * np.sin(B) * np.cos(P), A * np.sin(B) * np.sin(P), A * np.cos(B) * np.ones_like(P)
+    return A * np.cos(P) * np.ones_like(B), A * np.sin(P) * np.ones_like(B), B * np.ones_like(P)
+
+
+@pytest.mark.parametrize("geom,rad,cen,radius", [
+    (SPH, "log", (1.0, 1.3, 0.4), 0.8),
+    (CYL, "uniform", (1.0, 0.05, 0.4), 0.4),
+])
+def test_gravitational_constant_enters_every_step(geom, rad, cen, radius):
+    """G = 0.5 against the closed form with G explicit (Sec. 6.1.1 form of the
+    smooth sphere, Gauss's law).  G enters the source (4 pi G rho, Eq.
+    poisson_discrete), the screening mass (1/(4 pi G), Eqs. charge_sph/cyl)
+    and the DGF (4 pi G delta and the -G kernel of Eqs. DGF_bc_sph/cyl): a
+    factor dropped or doubled in any one of them breaks Phi(G) = G Phi(1)
+    (the boundary term then scales with another power of G) and moves the
+    result off the closed form by far more than the truncation error."""
+    errs = []
+    for n in (16, 32):
+        spec1 = _spec(geom, rad, n, n // 2, n)
+        spec = GridSpec(*[getattr(spec1, k) for k in ("geometry", "radial", "n_a", "n_b", "n_phi",
+                                                       "a_min", "a_max", "b_min", "b_max")], G=0.5)
+        a, b, p = cell_centres(spec)
+        rho = smooth_sphere(geom, a, b, p, cen, radius)
+        npad = 8 if n == 16 else 16
+        phi_half = OraclePlan(spec, n_pad=npad).solve(rho)
+        phi_one = OraclePlan(spec1, n_pad=npad).solve(rho)
+        assert np.abs(phi_half - 0.5 * phi_one).max() <= 1e-12 * np.abs(phi_one).max()
+        d = analytic.distance(geom, a, b, p, cen)
+        errs.append(_error(spec, phi_half, analytic.smooth_sphere_potential(d, radius, G=0.5)))
+    assert errs[0][0] / errs[1][0] > 3.0, errs
+    assert errs[1][0] < 1e-2, errs
+
+
+@pytest.mark.parametrize("geom,rad", [(SPH, "log"), (CYL, "log"), (CYL, "uniform")])
+def test_dgf_source_part_exactly_reciprocal(geom, rad):
+    """Without the box boundary data the extended-domain table is the
+    volume-weighted inverse of the symmetric finite-volume operator times
+    4 pi G, so Gt(t <- s) / dV_s = Gt(s <- t) / dV_t to rounding (Sec. 4.2,
+    with Gt = G^m dV_s of Eq. Theta_fft).  A wrong source normalisation (2D
+    instead of 3D volume, the field cell's volume instead of the source's)
+    or an unsymmetric coupling breaks it."""
+    spec = _spec(geom, rad, 16, 8, 8)
+    gh = GhostSet(spec)
+    T = dgf_tables(spec, n_pad=8, method="extended", modes=[0, 1, 4], homogeneous=True)
+    S = T / gh.dv3[None, None, :]
+    assert np.abs(S - S.transpose(0, 2, 1)).max() <= 1e-13 * np.abs(S).max()
+    # and the inverse itself: applying the box operator to a column gives
+    # 4 pi G at the source (checked through the ghost rows: positive-definite
+    # sign of the self term of an attractive potential)
+    assert np.all(np.diagonal(T, axis1=1, axis2=2) < 0.0)
+
+
+def test_dgf_reciprocity_improves_under_refinement():
+    """The full tables carry boundary data from the continuous kernel, which
+    is reciprocal itself, so the discrete reciprocity defect falls as the
+    grid is refined (log sphere: about 8x per doubling; log cylinder:
+    about 2x)."""
+    defects = {SPH: [], CYL: []}
+    for n in (16, 32):
+        for geom in (SPH, CYL):
+            spec = _spec(geom, "log", n, n // 2, 8)
+            gh = GhostSet(spec)
+            T = dgf_tables(spec, n_pad=n // 2, method="extended", modes=[0, 2])
+            S = T / gh.dv3[None, None, :]
+            defects[geom].append(np.abs(S - S.transpose(0, 2, 1)).max() / np.abs(S).max())
+    assert defects[SPH][1] < defects[SPH][0] / 4 and defects[SPH][1] < 1e-5, defects
+    assert defects[CYL][1] < defects[CYL][0] / 1.5 and defects[CYL][1] < 1e-2, defects
+
+
+@pytest.mark.parametrize("geom,rad,cen,radius", [
+    (SPH, "uniform", (0.5, 1.3, 0.4), 0.3),
+    (SPH, "log", (1.0, 1.3, 0.4), 0.8),
+    (CYL, "log", (1.0, 0.5, 0.3), 0.8),
+])
+def test_ghost_potential_second_order(geom, rad, cen, radius):
+    """The James boundary potential: -Theta at the ghost-cell centres (back in
+    real space) is the potential of the isolated density there (Sec. 4, step
+    3 sets the second solve's boundary to it), so it converges to the closed
+    form at second order (error / 4 per doubling, Sec. 6.1.3)."""
+    errs = []
+    for n in (32, 64):
+        spec = _spec(geom, rad, n, n // 2, n)
+        a, b, p = cell_centres(spec)
+        rho = smooth_sphere(geom, a, b, p, cen, radius)
+        plan = OraclePlan(spec, n_pad=16)
+        _, parts = plan.solve(rho, return_parts=True)
+        gh = plan.ghosts
+        theta = fourier.inverse(parts["theta"][:, :, None], spec.n_phi)[:, 0, :]   # (n_ghost, n_phi)
+        x, y, z = _ghost_xyz(geom, gh.a, gh.b, p)
+        from workloads.densities import point_cartesian
+        cx, cy, cz = point_cartesian(geom, *cen)
+        d = np.sqrt((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2)
+        ex = analytic.smooth_sphere_potential(d, radius)
+        errs.append(np.abs(-theta - ex).max() / np.abs(ex).max())
+    assert errs[0] / errs[1] > 3.5, errs
+    assert errs[1] < 5e-3, errs
+
+
+def _transfer_x(geom, which, x):
+    return x * x if (which == "a" and geom == SPH) else x
+
+
+@pytest.mark.parametrize("geom,rad", [(SPH, "uniform"), (SPH, "log"), (CYL, "uniform"), (CYL, "log")])
+def test_transfers_reproduce_linear_fields(geom, rad):
+    """Sec. 3.1: restriction and prolongation are bilinear in (r^2, theta)
+    (spherical) or (R, z) (cylindrical).  Restricting a field linear in
+    those coordinates gives its values at the coarse centroids exactly;
+    prolonging one gives its values at the fine centroids exactly.  Where the
+    stencil touches a coarse ghost: at a pole for fields even (m even) or odd
+    (m odd) across it; at a Dirichlet edge for fields that vanish at the
+    finest ghost centre (where the error's boundary condition sits on every
+    level), on the axes whose transfer coordinate is the coordinate itself
+    (theta, R, z).  The coarse ghost factor is set by a straight line in r
+    and the spherical radial transfer is linear in r^2, so on that axis the
+    coarse ghost is checked to lie on the line in r that vanishes at the
+    finest ghost centre."""
+    from oracle.multigrid import prolongation_matrix_1d, restriction_weights_1d
+    if geom == SPH:
+        spec = GridSpec(SPH, rad, 32, 16, 8, *((0.1, 1.0) if rad == "uniform" else (0.05, 5.0)), 0.0, math.pi)
+    else:
+        spec = _spec(geom, rad, 32, 16, 8)
+    h = Hierarchy(spec)
+    fine, coarse = h.levels[0], h.levels[1]
+    rng = np.random.default_rng(4)
+    for which, F, C in (("a", fine.A, coarse.A), ("b", fine.B, coarse.B)):
+        xf = _transfer_x(geom, which, F.cent)
+        xc = _transfer_x(geom, which, C.cent)
+        c0, c1 = rng.standard_normal(2)
+        w = restriction_weights_1d(F, C, geom, which)
+        restricted = w[:, 0] * (c0 + c1 * xf[1:-1:2]) + w[:, 1] * (c0 + c1 * xf[2::2])
+        assert np.abs(restricted - (c0 + c1 * xc[1:-1])).max() <= 1e-13 * (abs(c0) + abs(c1) * np.abs(xc).max())
+        for m in (0, 1):
+            k = coarse.op.kappa
+            e_lo, e_hi = (("a_lo", "a_hi") if which == "a" else ("b_lo", "b_hi"))
+            P = prolongation_matrix_1d(F, C, geom, which, k(e_lo, m), k(e_hi, m))
+            n_f = F.n
+            inner = np.arange(2, n_f - 2)
+            g = c0 + c1 * xc[1:-1]
+            assert np.abs((P @ g)[inner] - (c0 + c1 * xf[1:-1][inner])).max() <= 1e-12 * np.abs(g).max()
+            for edge, rows, x_ghost in ((e_lo, [0, 1], F.cent[0]), (e_hi, [n_f - 2, n_f - 1], F.cent[n_f + 1])):
+                kind = coarse.op.edges[edge]
+                if kind == "pole":
+                    if m % 2:                      # odd across the pole: c1 * theta (or pi - theta)
+                        xp = 0.0 if edge.endswith("lo") else math.pi
+                        g = c1 * (xc[1:-1] - xp)
+                        ex = c1 * (xf[1:-1] - xp)
+                    else:                          # even: constant
+                        g = np.full(C.n, c0)
+                        ex = np.full(n_f, c0)
+                elif which == "a" and geom == SPH:
+                    g = c1 * (C.cent[1:-1] - x_ghost)      # straight line in r through the finest ghost
+                    lo = edge.endswith("lo")
+                    ghost_val = k(edge, m) * (g[0] if lo else g[-1])
+                    cg = C.cent[0] if lo else C.cent[-1]
+                    assert abs(ghost_val - c1 * (cg - x_ghost)) <= 1e-12 * abs(c1) * abs(cg), edge
+                    continue
+                else:                              # Dirichlet: vanishes at the finest ghost centre
+                    xg = _transfer_x(geom, which, np.array([x_ghost]))[0]
+                    g = c1 * (xc[1:-1] - xg)
+                    ex = c1 * (xf[1:-1] - xg)
+                assert np.abs((P @ g)[rows] - ex[rows]).max() <= 1e-12 * np.abs(ex).max(), (edge, m)
+
+
+@pytest.mark.parametrize("shift", [0.0, 37.0])
+def test_omega_2d_exact_for_constant_coefficients(shift):
+    """Appendix A's 2D estimate: for the constant-coefficient 5-point operator
+    (optionally with a constant Helmholtz shift, as the mode term adds) the
+    weighted Rayleigh quotient with the lowest sine mode is the exact Jacobi
+    spectral radius, so omega_2d equals Young's optimum 2 / (1 + sqrt(1 -
+    rho^2)) computed from the eigenvalues of the Jacobi matrix."""
+    from oracle.omega import omega_2d
+    na, nb, hx, hy = 12, 7, 0.3, 0.11
+    xa, xb = hx * np.arange(na + 2), hy * np.arange(nb + 2)
+    ua = np.full(na, 1 / hx**2)
+    ub = np.full((na, nb), 1 / hy**2)
+    diag = np.full((na, nb), -2 / hx**2 - 2 / hy**2 - shift)
+    w = omega_2d(xa, xb, ua, ua.copy(), ub, ub.copy(), diag)
+    n = na * nb
+    J = np.zeros((n, n))
+    idx = np.arange(n).reshape(na, nb)
+    for i in range(na):
+        for j in range(nb):
+            for ii, jj, c in ((i + 1, j, ua[0]), (i - 1, j, ua[0]), (i, j + 1, ub[0, 0]), (i, j - 1, ub[0, 0])):
+                if 0 <= ii < na and 0 <= jj < nb:
+                    J[idx[i, j], idx[ii, jj]] = -c / diag[i, j]
+    rho = np.abs(np.linalg.eigvals(J)).max()
+    assert abs(w - 2.0 / (1.0 + math.sqrt(1.0 - rho * rho))) < 1e-12
