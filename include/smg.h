@@ -147,7 +147,14 @@ typedef struct smg_plan smg_plan;
 
 /* Validate the grid and options and build the host tables (geometry,
  * per-level stencil factors, WKB omegas of Appendix A, transfer weights).
- * *out receives a new plan on success.  No device work. */
+ * *out receives a new plan on success.  No device work.
+ * Besides the field ranges, the grid must coarsen (halving both sides while
+ * both are even, the smaller side stays >= 2 and the coarse inner radial
+ * ghost face stays at r > 0) to a level of at most max(128, coarse_cells)
+ * cells, or to one whose exact solver exists: n_a = c_a 2^k and n_b =
+ * c_b 2^k with small odd c_a, c_b.  SMG_EINVAL otherwise, with the reason
+ * the coarsening stopped in smg_last_error (e.g. 130 x 66 stops at the odd
+ * 65 x 33). */
 smg_status smg_plan_create(const smg_grid *grid, const smg_opts *opts, smg_plan **out);
 
 /* Bytes of device workspace the plan needs (DGF tables, mode planes of every
@@ -252,14 +259,38 @@ smg_status smg_net_backward(smg_net *net, const float *dy_dev, int n, int h, int
 smg_status smg_net_train_step(smg_net *net, const float *samples_dev, int n_samples, const int *idx_host, int n, int h,
                               int w, float lr, void *work_dev, size_t work_bytes, void *stream, float *loss_host);
 
+/* ---- single layers of the network, for layer-level checks ----------------
+ * BF16 arrays are uint16 bit patterns (round to nearest even).  Images are
+ * NHWC: x[n][h][w][c_in], zero outside the image.
+ *
+ * smg_net_conv3: one 3x3 'same' convolution (a layer of the learned-guess
+ * U-Net): y[q][i][j][o] = bf16(act(b[o] + sum_{t,c} W[o][t][c] x[q][i+dy_t][j+dx_t][c]))
+ * with tap t = 3 (dy + 1) + (dx + 1), act = ReLU when relu != 0, b may be
+ * NULL (zero bias); sums in FP32.  W is BF16 [c_out][9][c_in], b FP32
+ * [c_out], y BF16 [n][h][w][c_out].  c_in a multiple of 8 in [8, 64],
+ * c_out = 32 (SMG_EINVAL otherwise).  Enqueued on `stream`.
+ *
+ * smg_net_conv3_wgrad: the parameter gradients of that layer for an output
+ * gradient g[n][h][w][c_out] (BF16): dW[o][t][c] = sum_pixels g[p][o]
+ * x[p + tap t][c], db[o] = sum_pixels g[p][o], both FP32 and overwritten.
+ * work_dev is scratch of smg_net_conv3_wgrad_work_bytes bytes (per-chunk
+ * partial sums; SMG_EWORKSPACE if smaller). */
+smg_status smg_net_conv3(const unsigned short *x_dev, int c_in, const unsigned short *w_dev, const float *b_dev,
+                         unsigned short *y_dev, int c_out, int relu, int n, int h, int w, void *stream);
+size_t smg_net_conv3_wgrad_work_bytes(int c_in, int c_out, int n, int h, int w);
+smg_status smg_net_conv3_wgrad(const unsigned short *g_dev, int c_out, const unsigned short *x_dev, int c_in,
+                               float *dw_dev, float *db_dev, int n, int h, int w, void *work_dev, size_t work_bytes,
+                               void *stream);
+
 /* ---- the learned guess in a plan's solves ---------------------------------
  * Attach a bound network as the initial-guess model of modes 0..m_max
  * (m_max <= 8; n_a and n_b divisible by 2^(levels-1)) using a caller-owned
  * work buffer of smg_plan_net_work_bytes bytes (256-byte aligned).  From
  * then on every solve keeps its right-hand sides of those modes for the next
  * step; a warm-started solve with SMG_NET_GUESS builds the network inputs
- * (per real image: f_t / s_f, (f_t - f_{t-1}) / s_f, u_{t-1} / s_u, m / 4,
- * with s_f, s_u the plane RMS values) before each of its two multigrid
+ * (per real image: f_t / s_f, (f_t - f_{t-1}) / s_d, u_{t-1} / s_u, m / 4,
+ * the two normalised grid coordinates and two zeros, with s_f, s_d, s_u the
+ * plane RMS values of f_t, f_t - f_{t-1} and u_{t-1}) before each of its two multigrid
  * solves and starts every mode from the better of the network's guess and
  * the previous solution (defect norms after one smoothing step of each).
  * A NULL net detaches. */
@@ -277,6 +308,23 @@ int smg_plan_recorded(const smg_plan *plan, void *stream);
 /* Which modes took the network's guess in the last SMG_NET_GUESS solve:
  * used_host[t * (m_max + 1) + m] for solve t = 0 (Psi), 1 (Phi). */
 smg_status smg_plan_net_used(const smg_plan *plan, int *used_host, void *stream);
+/* The learned-guess step of multigrid solve t (0: Psi, 1: Phi) of a
+ * warm-started SMG_NET_GUESS solve, on caller planes, for step-level checks.
+ * Inputs, complex FP64 [m_max+1][n_a][n_b] (modes 0..m_max): f_dev this
+ * step's right-hand side of solve t (for t = 1 with the ghost potential
+ * folded in), fprev_dev the previous step's, uprev_dev the previous step's
+ * solution.  Outputs: guess_dev (same layout) the initial guess each mode
+ * starts from (the network's candidate u_prev + s_o y or u_prev, by the
+ * defect norms after one smoothing step of each); x_dev (may be NULL) the
+ * FP32 network inputs [2 m_max + 1][n_a][n_b][8] (image 0 = Re m=0, 2m-1 =
+ * Re m, 2m = Im m); y_dev (may be NULL) the FP32 network outputs
+ * [2 m_max + 1][n_a][n_b]; used_host (may be NULL) int [m_max+1], 1 where
+ * the network's candidate was taken.  Synchronises.  Overwrites the plan's
+ * solve state, so the next smg_solve starts cold.  SMG_ESTATE without an
+ * attached network. */
+smg_status smg_net_guess_step(smg_plan *plan, int t, const double *f_dev, const double *fprev_dev,
+                              const double *uprev_dev, double *guess_dev, float *x_dev, float *y_dev, int *used_host,
+                              void *stream);
 
 /* ---- geometry query (host, no device work) ------------------------------ */
 /* Cell-centre coordinates: a_host[n_a], b_host[n_b], phi_host[n_phi]

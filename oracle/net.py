@@ -231,3 +231,86 @@ def loss(out, target):
     diff = out - target
     n = diff.size
     return float(np.sum(diff * diff) / n), 2.0 * diff / n
+
+
+# -- the learned guess inside a solve -------------------------------------------
+# The network is this build's addition to the paper's warm start (Sec. 5.1:
+# each multigrid solve starts from the previous time step's solution).  For
+# the low modes 0..m_max the solve may instead start from
+#   cand = u_{t-1} + s_o * net(x),
+# whichever of the two has the smaller volume-weighted defect norm after one
+# smoothing step of each (the multigrid removes the rough part of any error
+# in its first sweep; what is left decides the cycle count).
+def image_mode(k):
+    """Real image k -> (mode m, part): 0 -> (0, real); 2m - 1 -> (m, real);
+    2m -> (m, imaginary)."""
+    m = (k + 1) // 2
+    return m, (1 if (k > 0 and k % 2 == 0) else 0)
+
+
+def _part(z, im):
+    return z.imag if im else z.real
+
+
+def guess_images(f, fprev, uprev, m_max):
+    """Network inputs and scales of modes 0..m_max.
+
+    f, fprev, uprev: complex (>= m_max + 1, n_a, n_b) planes of this step's
+    right-hand side, the previous step's and the previous solution.  Returns
+    x (2 m_max + 1, n_a, n_b, 8) and sc (2 m_max + 1, 4) = (s_f, s_d, s_u,
+    s_o) per image, the RMS values of f, f - fprev and uprev over the plane
+    (1 where zero) and s_o = s_u s_d / s_f."""
+    n_img = 2 * m_max + 1
+    na, nb = f.shape[1], f.shape[2]
+    x = np.zeros((n_img, na, nb, 8))
+    sc = np.zeros((n_img, 4))
+    ci = (np.arange(na) + 0.5) / na - 0.5
+    cj = (np.arange(nb) + 0.5) / nb - 0.5
+    for k in range(n_img):
+        m, im = image_mode(k)
+        fv, fp, uv = _part(f[m], im), _part(fprev[m], im), _part(uprev[m], im)
+        s = [float(np.sqrt(np.mean(v * v))) for v in (fv, fv - fp, uv)]
+        s = [v if v > 0.0 else 1.0 for v in s]
+        sc[k] = (s[0], s[1], s[2], s[2] * s[1] / s[0])
+        x[k, :, :, 0] = fv / s[0]
+        x[k, :, :, 1] = (fv - fp) / s[1]
+        x[k, :, :, 2] = uv / s[2]
+        x[k, :, :, 3] = m / 4.0
+        x[k, :, :, 4] = ci[:, None]
+        x[k, :, :, 5] = cj[None, :]
+    return x, sc
+
+
+def guess_candidate(uprev, y, sc, m_max):
+    """cand = u_{t-1} + s_o y per real image (the imaginary part of m = 0 is
+    kept)."""
+    cand = np.array(uprev[:m_max + 1], dtype=np.complex128)
+    for k in range(2 * m_max + 1):
+        m, im = image_mode(k)
+        if im:
+            cand[m] = cand[m] + 1j * sc[k, 3] * y[k]
+        else:
+            cand[m] = cand[m] + sc[k, 3] * y[k]
+    return cand
+
+
+def guess_judge(level, f, cand, uprev, m_max, n_sor=2, line_solver="sor"):
+    """Per mode m <= m_max: 1 where the candidate's defect norm after one
+    smoothing step (``level``: an oracle.multigrid.MGLevel of the finest
+    grid) is below that of the previous solution.  Returns (used, norm of
+    the candidate, norm of the previous solution)."""
+    used = np.zeros(m_max + 1, dtype=int)
+    nc = np.zeros(m_max + 1)
+    nu = np.zeros(m_max + 1)
+    for m in range(m_max + 1):
+        norms = []
+        for u0 in (cand[m], uprev[m]):
+            u = np.array(u0, dtype=np.complex128)
+            if line_solver == "exact":
+                level.smooth_exact(u, f[m], m)
+            else:
+                level.smooth(u, f[m], m, n_sor)
+            norms.append(float(level.op.norm_v(f[m] - level.apply(u, m))))
+        nc[m], nu[m] = norms
+        used[m] = 1 if norms[0] < norms[1] else 0
+    return used, nc, nu

@@ -223,6 +223,10 @@ struct smg_plan {
   Group grp;                // this plan alone
   std::string tune_report;
   PlanNet pn;
+  // bumped whenever a buffer that captured solve graphs write to changes
+  // (network attach, recording buffer); part of every group graph key, so a
+  // batch holding this plan never replays a graph with the old pointers
+  unsigned gen = 0;
   // per-launch event timing (smg_profile_begin / smg_profile_end)
   struct ProfRec { int cls, ev0, ev1; double bytes; };
   mutable bool prof_on = false;
@@ -305,8 +309,8 @@ extern "C" smg_status smg_plan_create(const smg_grid* grid, const smg_opts* opts
   if (Lc.na * Lc.nb > kMaxCoarseCells && Lc.sep_v.empty())
     return fail(SMG_EINVAL, strprintf("the %dx%d coarsest level has no exact solver", Lc.na, Lc.nb));
   if (Lc.na * Lc.nb > std::max(kMaxCoarseCells, o.coarse_cells))
-    return fail(SMG_EINVAL, strprintf("grid coarsens only to %dx%d (> %d cells): the radial ghost face reaches r <= 0",
-                                      Lc.na, Lc.nb, kMaxCoarseCells));
+    return fail(SMG_EINVAL, strprintf("grid coarsens only to %dx%d (> %d cells): %s", Lc.na, Lc.nb,
+                                      std::max(kMaxCoarseCells, o.coarse_cells), p->H.stop));
   p->gh = make_ghosts(s);
   p->n_g = p->gh.n;
   if (p->n_g > 4096) return fail(SMG_EINVAL, "too many boundary ghost cells (> 4096)");
@@ -1033,8 +1037,10 @@ static smg_status group_graph(Group& g, double tol, bool warm, unsigned flags, c
   std::vector<int> key;
   key.push_back(warm ? 1 : 0);
   key.push_back((int)(flags & SMG_NET_GUESS));
-  for (const smg_plan* p : g.plans)  // the learned-guess steps the body holds
+  for (const smg_plan* p : g.plans) {  // the learned-guess steps the body holds
     key.push_back(p->pn.net ? 1 + 2 * p->pn.prev_ok[0] + 4 * p->pn.prev_ok[1] + 8 * (p->pn.samples != nullptr) : 0);
+    key.push_back((int)p->gen);
+  }
   long long tb;
   std::memcpy(&tb, &tol, sizeof(tb));
   key.push_back((int)(tb & 0xffffffff));
@@ -1252,6 +1258,7 @@ extern "C" size_t smg_plan_net_work_bytes(const smg_plan* p, const smg_net* net,
 extern "C" smg_status smg_plan_attach_net(smg_plan* p, smg_net* net, int m_max, void* work, size_t bytes, void* stream) {
   STCHK(need_ready(p));
   p->grp.drop_graphs();
+  ++p->gen;
   if (!net) {
     p->pn = PlanNet{};
     return SMG_OK;
@@ -1307,6 +1314,7 @@ extern "C" smg_status smg_plan_record(smg_plan* p, float* samples, int capacity,
   STCHK(need_ready(p));
   if (!p->pn.net) return fail(SMG_ESTATE, "no network attached (smg_plan_attach_net)");
   p->grp.drop_graphs();
+  ++p->gen;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int zero = 0;
   HIPCHK(hipMemcpyAsync(p->pn.work + p->pn.o_rec, &zero, sizeof(int), hipMemcpyHostToDevice, st));
@@ -1329,6 +1337,37 @@ extern "C" smg_status smg_plan_net_used(const smg_plan* p, int* used, void* stre
   if (!p || !p->pn.net || !used) return fail(SMG_EINVAL, "no network attached or NULL buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIPCHK(hipMemcpyAsync(used, p->pn.work + p->pn.o_used, sizeof(int) * 2 * (p->pn.m_max + 1), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return SMG_OK;
+}
+
+extern "C" smg_status smg_net_guess_step(smg_plan* p, int t, const double* f, const double* fprev, const double* uprev,
+                                         double* guess, float* x_out, float* y_out, int* used_host, void* stream) {
+  STCHK(need_ready(p));
+  PlanNet& pn = p->pn;
+  if (!pn.net) return fail(SMG_ESTATE, "no network attached (smg_plan_attach_net)");
+  if (t != 0 && t != 1) return fail(SMG_EINVAL, "t must be 0 (Psi) or 1 (Phi)");
+  if (!f || !fprev || !uprev || !guess) return fail(SMG_EINVAL, "f, fprev, uprev and guess must not be NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t np = (size_t)(pn.m_max + 1) * p->spec.n_a * p->spec.n_b;
+  HIPCHK(smgk::copy_planes(const_cast<double2*>(target_f(p, t)), reinterpret_cast<const double2*>(f), np, st));
+  HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_fprev[t]), reinterpret_cast<const double2*>(fprev), np,
+                           st));
+  HIPCHK(smgk::copy_planes(target_u(p, t), reinterpret_cast<const double2*>(uprev), np, st));
+  const bool keep = pn.prev_ok[t];
+  pn.prev_ok[t] = true;
+  const smg_status sb = net_before(p, t, true, true, st);
+  pn.prev_ok[t] = keep;
+  // the plan's solve state now holds these planes: the next solve starts cold
+  p->grp.have_prev = false;
+  STCHK(sb);
+  HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(guess), target_u(p, t), np, st));
+  const size_t img = (size_t)pn.n_img * p->spec.n_a * p->spec.n_b;
+  if (x_out) HIPCHK(hipMemcpyAsync(x_out, pn.work + pn.wl.x32, sizeof(float) * img * 8, hipMemcpyDeviceToDevice, st));
+  if (y_out) HIPCHK(hipMemcpyAsync(y_out, pn.work + pn.wl.y, sizeof(float) * img, hipMemcpyDeviceToDevice, st));
+  if (used_host)
+    HIPCHK(hipMemcpyAsync(used_host, pn.work + pn.o_used + sizeof(int) * t * (pn.m_max + 1), sizeof(int) * (pn.m_max + 1),
+                          hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   return SMG_OK;
 }

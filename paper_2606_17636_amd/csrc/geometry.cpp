@@ -323,9 +323,22 @@ Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, c
   long stride = 1;
   while (true) {
     int ca = sizes.back().first, cb = sizes.back().second;
-    if (ca * cb <= max_coarse && sizes.size() > 1) break;
-    if ((ca % 2) || (cb % 2) || std::min(ca, cb) / 2 < 2) break;
-    if (s.radial_face((double)((a_lo - 1) - 2 * stride)) <= 0.0) break;
+    if (ca * cb <= max_coarse && sizes.size() > 1) {
+      h.stop = "the level is small enough";
+      break;
+    }
+    if ((ca % 2) || (cb % 2)) {
+      h.stop = "a side of the level is odd";
+      break;
+    }
+    if (std::min(ca, cb) / 2 < 2) {
+      h.stop = "halving would leave a side below 2 cells";
+      break;
+    }
+    if (s.radial_face((double)((a_lo - 1) - 2 * stride)) <= 0.0) {
+      h.stop = "the coarse inner radial ghost face would reach r <= 0";
+      break;
+    }
     sizes.push_back({ca / 2, cb / 2});
     stride *= 2;
   }

@@ -358,3 +358,41 @@ extern "C" smg_status smg_net_train_step(smg_net* net, const float* samples, int
   }
   return SMG_OK;
 }
+
+// ---------------------------------------------------------------------------
+// single layers, for layer-level checks
+// ---------------------------------------------------------------------------
+static smg_status layer_shape_ok(int c_in, int c_out, int n, int h, int w) {
+  if (c_in < 8 || c_in % 8 || c_in > 64) return nfail(SMG_EINVAL, "c_in must be a multiple of 8 in [8, 64]");
+  if (c_out != 32) return nfail(SMG_EINVAL, "c_out must be 32");
+  if (n < 1 || h < 1 || w < 1) return nfail(SMG_EINVAL, "image batch must be non-empty");
+  return SMG_OK;
+}
+
+extern "C" smg_status smg_net_conv3(const unsigned short* x, int c_in, const unsigned short* W, const float* b,
+                                    unsigned short* y, int c_out, int relu, int n, int h, int w, void* stream) {
+  NST(layer_shape_ok(c_in, c_out, n, h, w));
+  if (!x || !W || !y) return nfail(SMG_EINVAL, "x, W and y must not be NULL");
+  NCHK(smgn::conv3(x, c_in, c_in, W, b, y, c_out, c_out, nullptr, 0, relu != 0, n, h, w,
+                   static_cast<hipStream_t>(stream)));
+  return SMG_OK;
+}
+
+extern "C" size_t smg_net_conv3_wgrad_work_bytes(int c_in, int c_out, int n, int h, int w) {
+  if (layer_shape_ok(c_in, c_out, n, h, w) != SMG_OK) return 0;
+  const size_t npix = (size_t)n * h * w;
+  return sizeof(float) * ((npix + 1023) / 1024) * (size_t)c_out * 9 * c_in;
+}
+
+extern "C" smg_status smg_net_conv3_wgrad(const unsigned short* g, int c_out, const unsigned short* x, int c_in, float* dW,
+                                          float* db, int n, int h, int w, void* work, size_t work_bytes, void* stream) {
+  NST(layer_shape_ok(c_in, c_out, n, h, w));
+  if (!g || !x || !dW || !db) return nfail(SMG_EINVAL, "g, x, dW and db must not be NULL");
+  const size_t need = smg_net_conv3_wgrad_work_bytes(c_in, c_out, n, h, w);
+  if (!work || work_bytes < need) return nfail(SMG_EWORKSPACE, strprintf("wgrad work buffer of %zu bytes needed", need));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  NCHK(smgn::fill_f32(db, c_out, 0.f, st));
+  NCHK(smgn::wgrad(g, c_out, c_out, x, c_in, c_in, static_cast<float*>(work), work_bytes / sizeof(float), dW, db, n, h, w,
+                   st));
+  return SMG_OK;
+}

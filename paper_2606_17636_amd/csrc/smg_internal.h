@@ -78,6 +78,7 @@ struct Hierarchy {
   Spec spec;
   int M;  // number of mode indices the tables cover
   std::vector<LevelTables> lv;
+  const char* stop = "";  // why coarsening stopped at the last level
 };
 
 // Build a hierarchy for interior cells a in [a_lo, a_lo + na - 1] and b in

@@ -113,6 +113,12 @@ def load():
         "smg_plan_record": ([P, P, ctypes.c_int, P], ctypes.c_int),
         "smg_plan_recorded": ([P, P], ctypes.c_int),
         "smg_plan_net_used": ([P, _PI, P], ctypes.c_int),
+        "smg_net_guess_step": ([P, ctypes.c_int, P, P, P, P, P, P, _PI, P], ctypes.c_int),
+        "smg_net_conv3": ([P, ctypes.c_int, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                           ctypes.c_int, P], ctypes.c_int),
+        "smg_net_conv3_wgrad_work_bytes": ([ctypes.c_int] * 5, ctypes.c_size_t),
+        "smg_net_conv3_wgrad": ([P, ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P,
+                                 ctypes.c_size_t, P], ctypes.c_int),
         "smg_net_create": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(P)], ctypes.c_int),
         "smg_net_destroy": ([P], ctypes.c_int),
         "smg_net_param_count": ([P], ctypes.c_longlong),
@@ -258,6 +264,22 @@ class Plan:
         used = np.zeros(2 * (self.m_max + 1), dtype=np.int32)
         _check(load().smg_plan_net_used(self._h, _iptr(used), _stream()))
         return used.reshape(2, self.m_max + 1)
+
+    def net_guess_step(self, t, f, fprev, uprev):
+        """The learned-guess step of solve t on caller planes (complex128
+        cuda, shape (m_max+1, n_a, n_b)): returns (guess, x, y, used)."""
+        import torch
+        shape = (self.m_max + 1, self.n_a, self.n_b)
+        for a in (f, fprev, uprev):
+            self._c128(a, shape)
+        n_img = 2 * self.m_max + 1
+        guess = torch.empty(shape, dtype=torch.complex128, device=f.device)
+        x = torch.empty((n_img, self.n_a, self.n_b, 8), dtype=torch.float32, device=f.device)
+        y = torch.empty((n_img, self.n_a, self.n_b), dtype=torch.float32, device=f.device)
+        used = np.zeros(self.m_max + 1, dtype=np.int32)
+        _check(load().smg_net_guess_step(self._h, int(t), _ptr(f), _ptr(fprev), _ptr(uprev), _ptr(guess), _ptr(x),
+                                         _ptr(y), _iptr(used), _stream()))
+        return guess, x, y, used
 
     def solve(self, rho, tol=1e-8, warm=False, out=None, timings=False, allow_noconv=False, net=False):
         """Phi for the density rho (cuda float64 [n_a, n_b, n_phi]); returns
@@ -527,6 +549,38 @@ class Net:
         _check(load().smg_net_train_step(self._h, _ptr(samples), n_samples, _iptr(ia), n, h, w, ctypes.c_float(lr), wp,
                                          wb, _stream(), ctypes.byref(loss)))
         return loss.value
+
+
+def conv3_layer(x, w, b=None, relu=True):
+    """One 3x3 convolution layer (smg_net_conv3).  x: int16 cuda tensor of
+    BF16 bit patterns (n, h, w, c_in); w: int16 BF16 bits (32, 9, c_in); b:
+    float32 (32,) or None.  Returns the BF16 bits (n, h, w, 32)."""
+    import torch
+    n, h, wd, cin = x.shape
+    cout = w.shape[0]
+    y = torch.empty((n, h, wd, cout), dtype=torch.int16, device=x.device)
+    _check(load().smg_net_conv3(_ptr(x.contiguous()), cin, _ptr(w.contiguous()), _ptr(b), _ptr(y), cout,
+                                1 if relu else 0, n, h, wd, _stream()))
+    return y
+
+
+def conv3_wgrad(g, x):
+    """Parameter gradients of a 3x3 layer (smg_net_conv3_wgrad): g int16 BF16
+    bits (n, h, w, 32), x int16 BF16 bits (n, h, w, c_in).  Returns (dW
+    float32 (32, 9, c_in), db float32 (32,))."""
+    import torch
+    n, h, wd, cout = g.shape
+    cin = x.shape[3]
+    lib = load()
+    nb = int(lib.smg_net_conv3_wgrad_work_bytes(cin, cout, n, h, wd))
+    if nb == 0:
+        raise ValueError("invalid layer shape")
+    work = torch.empty(nb // 4 + 64, dtype=torch.float32, device=g.device)
+    dw = torch.empty((cout, 9, cin), dtype=torch.float32, device=g.device)
+    db = torch.empty(cout, dtype=torch.float32, device=g.device)
+    _check(lib.smg_net_conv3_wgrad(_ptr(g.contiguous()), cout, _ptr(x.contiguous()), cin, _ptr(dw), _ptr(db), n, h, wd,
+                                   _ptr(work), ctypes.c_size_t(work.numel() * 4), _stream()))
+    return dw, db
 
 
 def grid_from_spec(spec, **opts):

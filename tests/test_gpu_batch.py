@@ -119,3 +119,36 @@ def test_component_coarse_solve_matches_complex_path_bitwise(precision, spec, co
         assert torch.equal(phis[k], single[k][0]), k
     ref = OraclePlan(spec, n_pad=16).solve(rho_h)
     assert _l2(spec, phis[0].cpu().numpy(), ref) < (1e-8 if precision == "fp64" else 1e-6)
+
+
+def test_batch_graphs_follow_a_new_recording_buffer():
+    """A batch member that records training samples and then points recording
+    at a new buffer: the batch's captured solve graphs must write the new
+    buffer, never the old one (which stays allocated and untouched)."""
+    from paper_2606_17636_amd import learn, smg
+    from workloads.netinit import init_params
+    plans = _plans(precision="mixed")[1:3]
+    net = smg.Net()
+    net.set_params(init_params(4))
+    plans[0].attach_net(net, 2)
+    batch = smg.Batch(plans).setup()
+    rhos = [_dev(_rho(spec, 60 + q)) for q, (spec, _) in enumerate(SPECS[1:3])]
+    cap = 64
+    old = learn.sample_buffer(plans[0], cap)
+    old.zero_()
+    plans[0].record(old, cap)
+    for k in range(4):                       # cold, then warm solves (graphs captured and replayed)
+        batch.solve([r * (1.0 + 0.01 * k) for r in rhos], warm=k > 0, info=False)
+    torch.cuda.synchronize()
+    n_old = plans[0].recorded()
+    assert n_old > 0
+    snapshot = old.clone()
+    new = learn.sample_buffer(plans[0], cap)
+    new.zero_()
+    plans[0].record(new, cap)
+    for k in range(3):
+        batch.solve([r * (1.05 + 0.01 * k) for r in rhos], warm=True, info=False)
+    torch.cuda.synchronize()
+    assert plans[0].recorded() > 0
+    assert torch.equal(old, snapshot), "a replayed graph wrote the old recording buffer"
+    assert bool(new.abs().sum() > 0), "the new recording buffer received nothing"

@@ -82,3 +82,75 @@ def test_rounded_forward_is_close_to_exact():
     a, _ = net.forward(p, x, rounding=True)
     b, _ = net.forward(p, x, rounding=False)
     assert np.linalg.norm(a - b) < 0.05 * np.linalg.norm(b)
+
+
+# -- the learned guess's input assembly, candidate and judge --------------------
+def _planes(rng, M, na, nb):
+    return rng.standard_normal((M, na, nb)) + 1j * rng.standard_normal((M, na, nb))
+
+
+def test_guess_images_layout_and_scaling():
+    """Image k is the real (k odd, k = 0) or imaginary (k even > 0) part of
+    mode (k + 1) // 2; channels 0-2 have unit RMS; the inputs do not change
+    when f, f_prev and u_prev are scaled; the change channel is
+    (f - f_prev) / RMS(f - f_prev)."""
+    rng = np.random.default_rng(40)
+    M, na, nb, m_max = 5, 12, 10, 3
+    f, fp, up = _planes(rng, M, na, nb), _planes(rng, M, na, nb), _planes(rng, M, na, nb)
+    x, sc = net.guess_images(f, fp, up, m_max)
+    assert x.shape == (2 * m_max + 1, na, nb, 8) and sc.shape == (2 * m_max + 1, 4)
+    for k in range(2 * m_max + 1):
+        m = (k + 1) // 2
+        part = (lambda z: z.imag) if (k > 0 and k % 2 == 0) else (lambda z: z.real)
+        d = part(f[m]) - part(fp[m])
+        assert np.allclose(x[k, :, :, 0] * sc[k, 0], part(f[m]), rtol=1e-14, atol=0)
+        assert np.allclose(x[k, :, :, 1], d / math.sqrt(np.mean(d * d)), rtol=1e-13, atol=0)
+        assert np.allclose(x[k, :, :, 2] * sc[k, 2], part(up[m]), rtol=1e-14, atol=0)
+        assert np.allclose(np.sqrt(np.mean(x[k, :, :, :3] ** 2, axis=(0, 1))), 1.0, rtol=1e-13)
+        assert np.all(x[k, :, :, 3] == m / 4.0)
+        assert abs(sc[k, 3] - sc[k, 2] * sc[k, 1] / sc[k, 0]) <= 1e-15 * sc[k, 3]
+    assert np.allclose(x[0, :, 0, 4], (np.arange(na) + 0.5) / na - 0.5)
+    assert np.allclose(x[0, 0, :, 5], (np.arange(nb) + 0.5) / nb - 0.5)
+    assert np.all(x[..., 6:] == 0.0)
+    x2, _ = net.guess_images(3.5 * f, 3.5 * fp, -2.0 * up, m_max)
+    assert np.allclose(x2[..., :2], x[..., :2], rtol=1e-13) and np.allclose(x2[..., 2], -x[..., 2], rtol=1e-13)
+    # a zero plane keeps scale 1 (no division by zero)
+    f0 = f.copy(); f0[1] = 0.0
+    _, sc0 = net.guess_images(f0, f0, up, m_max)
+    assert sc0[1, 0] == 1.0 and sc0[2, 1] == 1.0
+
+
+def test_guess_candidate_inverts_the_target():
+    """The training target is (u_t - u_{t-1}) / s_o per real image, so the
+    candidate built from a perfect prediction is u_t (the imaginary part of
+    m = 0 comes from u_{t-1})."""
+    rng = np.random.default_rng(41)
+    M, na, nb, m_max = 6, 8, 6, 4
+    f, fp, up, ut = (_planes(rng, M, na, nb) for _ in range(4))
+    up[0] = up[0].real + 1j * ut[0].imag
+    _, sc = net.guess_images(f, fp, up, m_max)
+    y = np.stack([((ut[m] - up[m]).imag if (k > 0 and k % 2 == 0) else (ut[m] - up[m]).real) / sc[k, 3]
+                  for k, m in ((k, (k + 1) // 2) for k in range(2 * m_max + 1))])
+    cand = net.guess_candidate(up, y, sc, m_max)
+    assert np.allclose(cand, ut[:m_max + 1], rtol=0, atol=1e-13 * np.abs(ut).max())
+
+
+def test_guess_judge_prefers_the_better_start():
+    """The judge picks the exact solution over a perturbed one in both
+    directions, and keeps the previous solution on a tie."""
+    from oracle.geometry import GridSpec
+    from oracle.multigrid import MGLevel
+    from oracle.solve import OraclePlan
+    spec = GridSpec("spherical", "log", 16, 8, 8, 0.05, 5.0, 0.0, math.pi)
+    rng = np.random.default_rng(42)
+    f = _planes(rng, spec.n_modes, 16, 8)
+    u = OraclePlan(spec, dgf=np.zeros((spec.n_modes, 1, 1))).solve_modes(f)
+    lev = MGLevel(spec, 0)
+    bad = u + 0.3 * np.abs(u).max() * np.cos(np.arange(8))[None, None, :]
+    m_max = 2
+    cand = np.stack([u[0], bad[1], u[2]])
+    prev = np.stack([bad[0], u[1], u[2]])
+    for ls in ("sor", "exact"):
+        used, nc, nu = net.guess_judge(lev, f, cand, prev, m_max, line_solver=ls)
+        assert list(used) == [1, 0, 0], (ls, nc, nu)
+        assert nc[2] == nu[2]
