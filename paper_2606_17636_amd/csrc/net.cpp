@@ -71,8 +71,8 @@ NetWork NetDef::work_layout(int n, int H, int W) const {
     w.g32b[l] = take(bf * np * ch);
     w.g64[l] = l < levels - 1 ? take(bf * np * 2 * ch) : 0;
   }
-  const size_t chunks = (np0 + 1023) / 1024;
-  w.part_floats = chunks * (size_t)ch * 9 * 2 * ch;
+  // the largest layer's weight-gradient partials (the 2 ch -> ch decoder input layer)
+  w.part_floats = std::max(smgn::wgrad_partials((int)np0, ch, 2 * ch), smgn::wgrad_partials((int)np0, ch, in_ch));
   w.part = take(sizeof(float) * w.part_floats);
   w.bytes = off;
   return w;
@@ -380,8 +380,7 @@ extern "C" smg_status smg_net_conv3(const unsigned short* x, int c_in, const uns
 
 extern "C" size_t smg_net_conv3_wgrad_work_bytes(int c_in, int c_out, int n, int h, int w) {
   if (layer_shape_ok(c_in, c_out, n, h, w) != SMG_OK) return 0;
-  const size_t npix = (size_t)n * h * w;
-  return sizeof(float) * ((npix + 1023) / 1024) * (size_t)c_out * 9 * c_in;
+  return sizeof(float) * smgn::wgrad_partials(n * h * w, c_out, c_in);
 }
 
 extern "C" smg_status smg_net_conv3_wgrad(const unsigned short* g, int c_out, const unsigned short* x, int c_in, float* dW,

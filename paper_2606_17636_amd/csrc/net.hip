@@ -33,90 +33,174 @@ __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float
 // 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
 __device__ __forceinline__ int mfma_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
-// out[n, y, x, o] = act(b[o] + sum_{t, c} W[o, t, c] in[n, y + dy_t, x + dx_t, c]),
-// optionally multiplied by (mask > 0).  Grid (ceil(W/32), H, N * cout/32),
-// one wave per block.  cin % 4 == 0, cout % 32 == 0; channel strides and
-// base pointers select sub-ranges of wider (concatenated) arrays.
-__global__ void __launch_bounds__(64) k_conv3(const unsigned short* __restrict__ in, int ics, int cin,
-                                             const unsigned short* __restrict__ Wt, const float* __restrict__ bias,
-                                             unsigned short* __restrict__ out, int ocs, int cout,
-                                             const unsigned short* __restrict__ mask, int mcs, int relu, int H, int Wd) {
-  const int lane = threadIdx.x;
-  const int x0 = blockIdx.x * 32, y = blockIdx.y;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// gfx950 matrix core: D (32 x 32, FP32) += A (32 x 16) B (16 x 32), BF16
+// operands; lane l supplies A[l % 32][8 (l / 32) .. + 7] and
+// B[8 (l / 32) .. + 7][l % 32]; D as in mfma_row.
+__device__ __forceinline__ f32x16 mma16(uint4 a, uint4 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0,
+                                                 0);
+}
+
+// 3x3 convolution as a GEMM on LDS-staged tiles:
+//   out[n, y, x, o] = act(b[o] + sum_{t, c} W[o, t, c] in[n, y + dy_t, x + dx_t, c]),
+// optionally multiplied by (mask > 0).  A block of 4 waves computes an
+// output tile of TH = 4 R rows x 32 pixels x 32 output channels: its input
+// tile (TH + 2 rows x 34 pixels x CIN channels, zero outside the image) and
+// the 32 x 9 CIN weights are staged in LDS once with 16-byte loads, so the
+// 9 taps reuse them; each wave owns R rows and steps K = 9 CIN in slices of
+// 16 (one 16-byte LDS read per operand per lane: 8 channels of one tap).
+// Grid (ceil(W / 32), ceil(H / TH), N * cout / 32).  Channel strides and
+// base pointers select sub-ranges of wider (concatenated) arrays; ics and
+// the base must keep 16-byte alignment (ics % 8 == 0).
+template <int CIN, int R>
+__global__ void __launch_bounds__(256) k_conv3(const unsigned short* __restrict__ in, int ics,
+                                               const unsigned short* __restrict__ Wt, const float* __restrict__ bias,
+                                               unsigned short* __restrict__ out, int ocs, int cout,
+                                               const unsigned short* __restrict__ mask, int mcs, int relu, int H,
+                                               int Wd) {
+  constexpr int TH = 4 * R, TW = 32, K = 9 * CIN, KS = (K + 15) / 16;
+  constexpr int PS = CIN + 8;       // LDS elements per staged pixel (padding spreads the lanes over banks)
+  constexpr int WS = 16 * KS + 8;   // LDS elements per staged weight row
+  constexpr int C8 = CIN / 8;
+  extern __shared__ uint4 smem_conv[];
+  unsigned short* xs = reinterpret_cast<unsigned short*>(smem_conv);   // (TH + 2) * (TW + 2) * PS
+  unsigned short* ws = xs + (TH + 2) * (TW + 2) * PS;                  // 32 * WS
   const int ntile = cout >> 5;
   const int n = blockIdx.z / ntile, ct = blockIdx.z - n * ntile;
+  const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 32 * (K / 8); e += 256) {
+    const int j = e / (K / 8), q = e - j * (K / 8);
+    *reinterpret_cast<uint4*>(ws + j * WS + 8 * q) =
+        *reinterpret_cast<const uint4*>(Wt + (size_t)(ct * 32 + j) * K + 8 * q);
+  }
+  if (16 * KS > K)
+    for (int j = tid; j < 32; j += 256) *reinterpret_cast<uint4*>(ws + j * WS + K) = make_uint4(0, 0, 0, 0);
+  for (int e = tid; e < (TH + 2) * (TW + 2) * C8; e += 256) {
+    const int q = e % C8, pix = e / C8;
+    const int row = pix / (TW + 2), col = pix - row * (TW + 2);
+    const int yy = y0 - 1 + row, xx = x0 - 1 + col;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (yy >= 0 && yy < H && xx >= 0 && xx < Wd)
+      v = *reinterpret_cast<const uint4*>(in + ((size_t)(n * H + yy) * Wd + xx) * ics + 8 * q);
+    *reinterpret_cast<uint4*>(xs + pix * PS + 8 * q) = v;
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
   const int i = lane & 31, kg = lane >> 5;
-  const int px = x0 + i;
-  const int K = 9 * cin;
-  const unsigned short* wrow = Wt + (size_t)(ct * 32 + i) * K;
-  f32x16 acc;
-  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-  for (int k0 = 0; k0 < K; k0 += 8) {
-    const int k = k0 + 4 * kg;
-    bf16x4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
-    if (k < K) {
-      const int tap = k / cin, c = k - tap * cin;
-      const int yy = y + tap / 3 - 1, xx = px + tap % 3 - 1;
-      if (yy >= 0 && yy < H && xx >= 0 && xx < Wd)
-        a = *reinterpret_cast<const bf16x4*>(in + ((size_t)(n * H + yy) * Wd + xx) * ics + c);
-      b = *reinterpret_cast<const bf16x4*>(wrow + k);
+  f32x16 acc[R];
+  for (int r = 0; r < R; ++r)
+    for (int q = 0; q < 16; ++q) acc[r][q] = 0.f;
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int k0 = 16 * s + 8 * kg;        // this lane's 8 k: one tap, 8 channels
+    const int tap = k0 / CIN, c = k0 - tap * CIN;
+    const int dy = tap / 3, dx = tap - 3 * dy;
+    const uint4 b = *reinterpret_cast<const uint4*>(ws + i * WS + k0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      uint4 a = make_uint4(0, 0, 0, 0);
+      if (tap < 9) a = *reinterpret_cast<const uint4*>(xs + ((wave * R + r + dy) * (TW + 2) + i + dx) * PS + c);
+      acc[r] = mma16(a, b, acc[r]);
     }
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
   }
   const int co = ct * 32 + i;
   const float bv = bias ? bias[co] : 0.f;
-  for (int r = 0; r < 16; ++r) {
-    const int xo = x0 + mfma_row(r, lane);
-    if (xo >= Wd) continue;
-    float v = acc[r] + bv;
-    if (relu) v = fmaxf(v, 0.f);
-    const size_t pix = (size_t)(n * H + y) * Wd + xo;
-    if (mask && !(bf2f(mask[pix * mcs + co]) > 0.f)) v = 0.f;
-    out[pix * ocs + co] = f2bf(v);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int y = y0 + wave * R + r;
+    if (y >= H) continue;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int xo = x0 + mfma_row(q, lane);
+      if (xo >= Wd) continue;
+      float v = acc[r][q] + bv;
+      if (relu) v = fmaxf(v, 0.f);
+      const size_t pix = (size_t)(n * H + y) * Wd + xo;
+      if (mask && !(bf2f(mask[pix * mcs + co]) > 0.f)) v = 0.f;
+      out[pix * ocs + co] = f2bf(v);
+    }
   }
 }
 
-// Weight gradient partials: part[chunk][o][k] = sum over the chunk's pixels
-// of g[p, o] * im2col(x)[p, k].  Grid (ceil(K/32), cout/32, chunks), one
-// wave per block; pixels are enumerated over (n, y, x).
-__global__ void __launch_bounds__(64) k_wgrad(const unsigned short* __restrict__ g, int gcs, int cout,
-                                             const unsigned short* __restrict__ x, int xcs, int cin,
-                                             float* __restrict__ part, int npix, int chunk, int H, int Wd) {
-  const int lane = threadIdx.x;
+// Weight-gradient partials of a 3x3 convolution:
+//   part[chunk][o][k] = sum over the chunk's pixels p of g[p, o] im2col(x)[p, k],
+// k = t CIN + c.  A block of 4 waves takes its chunk 64 pixels at a time
+// (pixels enumerated over (n, y, x)): it stages g transposed ([o][pixel])
+// and the im2col slice of the 64 pixels transposed ([k][pixel], zero outside
+// the image) in LDS, then each wave accumulates its 32 x 32 blocks of dW
+// (columns of k) over the pixels with one 16-byte LDS read per operand per
+// lane.  Grid (chunks); chunk is a multiple of 64.
+template <int CIN>
+__global__ void __launch_bounds__(256) k_wgrad(const unsigned short* __restrict__ g, int gcs,
+                                               const unsigned short* __restrict__ x, int xcs,
+                                               float* __restrict__ part, int npix, int chunk, int H, int Wd) {
+  constexpr int K = 9 * CIN, KT = (K + 31) / 32;   // column tiles of 32
+  constexpr int NT = (KT + 3) / 4;                 // column tiles per wave
+  constexpr int P = 64, PP = P + 8;                // pixels per step, LDS row stride
+  constexpr int C8 = CIN / 8;
+  extern __shared__ uint4 smem_wgrad[];
+  unsigned short* gs = reinterpret_cast<unsigned short*>(smem_wgrad);  // 32 * PP
+  unsigned short* cs = gs + 32 * PP;                                   // 32 * KT * PP
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int i = lane & 31, kg = lane >> 5;
-  const int K = 9 * cin;
-  const int kcol = blockIdx.x * 32 + i;  // this lane's B column (k)
-  const int o = blockIdx.y * 32 + i;     // this lane's A row (output channel)
-  int tap = 0, c = 0;
-  const bool kin = kcol < K;
-  if (kin) { tap = kcol / cin; c = kcol - tap * cin; }
-  const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-  const int p0 = blockIdx.z * chunk, p1 = min(p0 + chunk, npix);
   const int HW = H * Wd;
-  f32x16 acc;
-  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-  for (int pb = p0; pb < p1; pb += 8) {
-    bf16x4 a, b;
-    for (int v = 0; v < 4; ++v) {
-      const int p = pb + 4 * kg + v;
-      unsigned short av = 0, bv = 0;
-      if (p < p1) {
-        av = g[(size_t)p * gcs + o];
-        if (kin) {
-          const int n = p / HW, rem = p - n * HW, yy = rem / Wd + dy, xx = rem % Wd + dx;
-          if (yy >= 0 && yy < H && xx >= 0 && xx < Wd) bv = x[((size_t)(n * H + yy) * Wd + xx) * xcs + c];
+  f32x16 acc[NT];
+  for (int u = 0; u < NT; ++u)
+    for (int q = 0; q < 16; ++q) acc[u][q] = 0.f;
+  // columns beyond K stay zero
+  for (int e = tid; e < (32 * KT - K) * PP; e += 256) cs[K * PP + e] = 0;
+  const int p_begin = blockIdx.x * chunk, p_end = min(p_begin + chunk, npix);
+  for (int p0 = p_begin; p0 < p_end; p0 += P) {
+    __syncthreads();
+    // g: 64 pixels x 32 channels, 16-byte loads, stored transposed
+    for (int e = tid; e < P * 4; e += 256) {
+      const int pl = e >> 2, q = e & 3, p = p0 + pl;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (p < p_end) v = *reinterpret_cast<const uint4*>(g + (size_t)p * gcs + 8 * q);
+      const unsigned short* h = reinterpret_cast<const unsigned short*>(&v);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) gs[(8 * q + u) * PP + pl] = h[u];
+    }
+    // im2col: pixel x tap, CIN channels each, stored transposed
+    for (int e = tid; e < P * 9 * C8; e += 256) {
+      const int q = e % C8, rest = e / C8, t = rest % 9, pl = rest / 9, p = p0 + pl;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (p < p_end) {
+        const int nimg = p / HW, rem = p - nimg * HW, y = rem / Wd, xx = rem - y * Wd;
+        const int yy = y + t / 3 - 1, xs_ = xx + t % 3 - 1;
+        if (yy >= 0 && yy < H && xs_ >= 0 && xs_ < Wd)
+          v = *reinterpret_cast<const uint4*>(x + ((size_t)(nimg * H + yy) * Wd + xs_) * xcs + 8 * q);
+      }
+      const unsigned short* h = reinterpret_cast<const unsigned short*>(&v);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) cs[(t * CIN + 8 * q + u) * PP + pl] = h[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < P / 16; ++s) {
+      const int pk = 16 * s + 8 * kg;
+      const uint4 a = *reinterpret_cast<const uint4*>(gs + i * PP + pk);
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const int tcol = wave + 4 * u;
+        if (tcol < KT) {
+          const uint4 b = *reinterpret_cast<const uint4*>(cs + (tcol * 32 + i) * PP + pk);
+          acc[u] = mma16(a, b, acc[u]);
         }
       }
-      a[v] = (short)av;
-      b[v] = (short)bv;
     }
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
   }
-  // D[row = o local][col = k local]: lane holds column i (k), rows from mfma_row
-  const size_t base = (size_t)blockIdx.z * cout * K;
-  for (int r = 0; r < 16; ++r) {
-    const int orow = blockIdx.y * 32 + mfma_row(r, lane);
-    if (kin) part[base + (size_t)orow * K + kcol] = acc[r];
+  // D[row = o][col = k]: lane holds column i of its tile, rows from mfma_row
+  float* base = part + (size_t)blockIdx.x * 32 * K;
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    const int kc = (wave + 4 * u) * 32 + i;
+    if (wave + 4 * u >= KT || kc >= K) continue;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) base[(size_t)mfma_row(q, lane) * K + kc] = acc[u][q];
   }
 }
 
@@ -322,28 +406,57 @@ unsigned grid1(size_t n, unsigned block = 256) {
 
 namespace smgn {
 
+template <int CIN, int R>
+static void launch_conv3(const unsigned short* in, int ics, const unsigned short* W, const float* bias,
+                         unsigned short* out, int ocs, int cout, const unsigned short* mask, int mcs, bool relu, int N,
+                         int H, int Wd, hipStream_t st) {
+  constexpr int KS = (9 * CIN + 15) / 16;
+  constexpr size_t lds = sizeof(unsigned short) * ((4 * R + 2) * 34 * (CIN + 8) + 32 * (16 * KS + 8));
+  dim3 grid((Wd + 31) / 32, (H + 4 * R - 1) / (4 * R), N * (cout / 32));
+  hipLaunchKernelGGL((k_conv3<CIN, R>), grid, dim3(256), lds, st, in, ics, W, bias, out, ocs, cout, mask, mcs,
+                     relu ? 1 : 0, H, Wd);
+}
+
 hipError_t conv3(const unsigned short* in, int ics, int cin, const unsigned short* W, const float* bias,
                  unsigned short* out, int ocs, int cout, const unsigned short* mask, int mcs, bool relu, int N, int H,
                  int Wd, hipStream_t st) {
-  if (cin % 4 || cout % 32 || ics % 4) return hipErrorInvalidValue;
-  dim3 grid((Wd + 31) / 32, H, N * (cout / 32));
-  hipLaunchKernelGGL(k_conv3, grid, dim3(64), 0, st, in, ics, cin, W, bias, out, ocs, cout, mask, mcs, relu ? 1 : 0, H,
-                     Wd);
+  if (cout % 32 || ics % 8 || (reinterpret_cast<uintptr_t>(in) & 15)) return hipErrorInvalidValue;
+  switch (cin) {
+    case 8: launch_conv3<8, 2>(in, ics, W, bias, out, ocs, cout, mask, mcs, relu, N, H, Wd, st); break;
+    case 32: launch_conv3<32, 2>(in, ics, W, bias, out, ocs, cout, mask, mcs, relu, N, H, Wd, st); break;
+    case 64: launch_conv3<64, 1>(in, ics, W, bias, out, ocs, cout, mask, mcs, relu, N, H, Wd, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
+}
+
+int wgrad_chunk(int npix, int cout, int cin) {
+  const size_t K = 9 * (size_t)cin;
+  int chunk = 1024;
+  while ((size_t)((npix + chunk - 1) / chunk) * cout * K > kWgradMaxPartials) chunk *= 2;
+  return chunk;
+}
+
+size_t wgrad_partials(int npix, int cout, int cin) {
+  const int chunk = wgrad_chunk(npix, cout, cin);
+  return (size_t)((npix + chunk - 1) / chunk) * cout * 9 * cin;
 }
 
 hipError_t wgrad(const unsigned short* g, int gcs, int cout, const unsigned short* x, int xcs, int cin, float* part,
                  size_t part_floats, float* dW, float* db, int N, int H, int Wd, hipStream_t st) {
-  if (cout % 32) return hipErrorInvalidValue;
+  if (cout != 32 || gcs % 8 || xcs % 8) return hipErrorInvalidValue;
   const int npix = N * H * Wd, K = 9 * cin;
-  int chunk = 1024;
-  int nchunk = (npix + chunk - 1) / chunk;
-  while ((size_t)nchunk * cout * K > part_floats) {
-    chunk *= 2;
-    nchunk = (npix + chunk - 1) / chunk;
+  const int chunk = wgrad_chunk(npix, cout, cin);
+  const int nchunk = (npix + chunk - 1) / chunk;
+  if ((size_t)nchunk * cout * K > part_floats) return hipErrorInvalidValue;
+  // LDS: g (32 rows) and the im2col slice (32 KT rows), 72 elements each
+  const size_t lds = sizeof(unsigned short) * 72 * (32 + 32 * ((K + 31) / 32));
+  switch (cin) {
+    case 8: hipLaunchKernelGGL(k_wgrad<8>, dim3(nchunk), dim3(256), lds, st, g, gcs, x, xcs, part, npix, chunk, H, Wd); break;
+    case 32: hipLaunchKernelGGL(k_wgrad<32>, dim3(nchunk), dim3(256), lds, st, g, gcs, x, xcs, part, npix, chunk, H, Wd); break;
+    case 64: hipLaunchKernelGGL(k_wgrad<64>, dim3(nchunk), dim3(256), lds, st, g, gcs, x, xcs, part, npix, chunk, H, Wd); break;
+    default: return hipErrorInvalidValue;
   }
-  dim3 grid((K + 31) / 32, cout / 32, nchunk);
-  hipLaunchKernelGGL(k_wgrad, grid, dim3(64), 0, st, g, gcs, cout, x, xcs, cin, part, npix, chunk, H, Wd);
   const int len = cout * K;
   hipLaunchKernelGGL(k_reduce_chunks, dim3((len + 255) / 256), dim3(256), 0, st, part, nchunk, len, dW);
   const int bchunk = 2048;

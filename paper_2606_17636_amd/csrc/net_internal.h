@@ -7,6 +7,12 @@
 #include <cmath>
 
 namespace smgn {
+// Upper bound on the weight-gradient partial sums (floats): the pixel chunk
+// of smgn::wgrad grows until the per-chunk partials fit (8 MiB).
+constexpr size_t kWgradMaxPartials = (size_t)2 << 20;
+// pixel chunk and partial-sum floats of smgn::wgrad for a layer
+int wgrad_chunk(int npix, int cout, int cin);
+size_t wgrad_partials(int npix, int cout, int cin);
 // 3x3 convolution (MFMA): see k_conv3 in net.hip for the layout.
 hipError_t conv3(const unsigned short* in, int ics, int cin, const unsigned short* W, const float* bias,
                  unsigned short* out, int ocs, int cout, const unsigned short* mask, int mcs, bool relu, int N, int H,
