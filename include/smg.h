@@ -281,6 +281,18 @@ size_t smg_net_conv3_wgrad_work_bytes(int c_in, int c_out, int n, int h, int w);
 smg_status smg_net_conv3_wgrad(const unsigned short *g_dev, int c_out, const unsigned short *x_dev, int c_in,
                                float *dw_dev, float *db_dev, int n, int h, int w, void *work_dev, size_t work_bytes,
                                void *stream);
+/* smg_net_conv3_wgrad for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results (dW bit for bit; db up to the
+ * order of its FP32 atomic additions), with the per-chunk partial sums in
+ * a static 8 MiB device array instead of a work buffer.  Calls no
+ * allocating routine.  Each GPU holds its own array from the first call on
+ * it until the process ends; every call on that GPU shares it, so calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  SMG_EINVAL beyond n*h*w = 2^28 pixels (the
+ * pixel chunks grow so that the partial sums of any layer fit the array). */
+smg_status smg_net_conv3_wgrad_noalloc(const unsigned short *g_dev, int c_out, const unsigned short *x_dev, int c_in,
+                                       float *dw_dev, float *db_dev, int n, int h, int w, void *stream);
 
 /* ---- the learned guess in a plan's solves ---------------------------------
  * Attach a bound network as the initial-guess model of modes 0..m_max

@@ -6,6 +6,7 @@
 
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -393,5 +394,58 @@ extern "C" smg_status smg_net_conv3_wgrad(const unsigned short* g, int c_out, co
   NCHK(smgn::fill_f32(db, c_out, 0.f, st));
   NCHK(smgn::wgrad(g, c_out, c_out, x, c_in, c_in, static_cast<float*>(work), work_bytes / sizeof(float), dW, db, n, h, w,
                    st));
+  return SMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient without allocation: the partial sums live in a static
+// device array (one per GPU, held until the process ends)
+// ---------------------------------------------------------------------------
+namespace {
+
+static __device__ __align__(256) float scratch[smgn::kWgradMaxPartials];
+
+constexpr int kMaxDevices = 64;
+// most pixels a call accepts: keeps every pixel index of the kernels in int range
+constexpr long long kNoAllocMaxPixels = 1LL << 28;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array (looked up once per device,
+// with that device current).
+smg_status scratch_of_current_device(float** out) {
+  int dev = 0;
+  NCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return nfail(SMG_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return nfail(SMG_EHIP, strprintf("hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e)));
+    g_scratch_ptr[dev] = static_cast<float*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return SMG_OK;
+}
+
+}  // namespace
+
+extern "C" smg_status smg_net_conv3_wgrad_noalloc(const unsigned short* g, int c_out, const unsigned short* x, int c_in,
+                                                  float* dW, float* db, int n, int h, int w, void* stream) {
+  NST(layer_shape_ok(c_in, c_out, n, h, w));
+  if (!g || !x || !dW || !db) return nfail(SMG_EINVAL, "g, x, dW and db must not be NULL");
+  if ((long long)n * h * w > kNoAllocMaxPixels)
+    return nfail(SMG_EINVAL, strprintf("n*h*w = %lld pixels exceeds the no-allocation limit of %lld",
+                                       (long long)n * h * w, kNoAllocMaxPixels));
+  const size_t need = smgn::wgrad_partials(n * h * w, c_out, c_in);
+  if (need > smgn::kWgradMaxPartials)
+    return nfail(SMG_EINVAL, strprintf("partial sums of %zu floats exceed the %zu-float scratch", need,
+                                       smgn::kWgradMaxPartials));
+  float* part = nullptr;
+  NST(scratch_of_current_device(&part));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  NCHK(smgn::fill_f32(db, c_out, 0.f, st));
+  NCHK(smgn::wgrad(g, c_out, c_out, x, c_in, c_in, part, smgn::kWgradMaxPartials, dW, db, n, h, w, st));
   return SMG_OK;
 }

@@ -119,6 +119,8 @@ def load():
         "smg_net_conv3_wgrad_work_bytes": ([ctypes.c_int] * 5, ctypes.c_size_t),
         "smg_net_conv3_wgrad": ([P, ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P,
                                  ctypes.c_size_t, P], ctypes.c_int),
+        "smg_net_conv3_wgrad_noalloc": ([P, ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, P], ctypes.c_int),
         "smg_net_create": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(P)], ctypes.c_int),
         "smg_net_destroy": ([P], ctypes.c_int),
         "smg_net_param_count": ([P], ctypes.c_longlong),
@@ -580,6 +582,20 @@ def conv3_wgrad(g, x):
     db = torch.empty(cout, dtype=torch.float32, device=g.device)
     _check(lib.smg_net_conv3_wgrad(_ptr(g.contiguous()), cout, _ptr(x.contiguous()), cin, _ptr(dw), _ptr(db), n, h, wd,
                                    _ptr(work), ctypes.c_size_t(work.numel() * 4), _stream()))
+    return dw, db
+
+
+def conv3_wgrad_noalloc(g, x, dw=None, db=None):
+    """conv3_wgrad through the entry point that allocates nothing (its
+    partial sums live in the library's static device array); dw and db may
+    be given (float32 (32, 9, c_in) and (32,))."""
+    import torch
+    n, h, wd, cout = g.shape
+    cin = x.shape[3]
+    dw = dw if dw is not None else torch.empty((cout, 9, cin), dtype=torch.float32, device=g.device)
+    db = db if db is not None else torch.empty(cout, dtype=torch.float32, device=g.device)
+    _check(load().smg_net_conv3_wgrad_noalloc(_ptr(g.contiguous()), cout, _ptr(x.contiguous()), cin, _ptr(dw),
+                                              _ptr(db), n, h, wd, _stream()))
     return dw, db
 
 
