@@ -115,7 +115,16 @@ typedef struct {
                             paper leaves the depth open, Sec. 3.3); that level
                             is solved exactly by fast diagonalisation
                             [0: 128] */
+  int coarse_solver;     /* SMG_COARSE_EXACT [default]: the coarsest level
+                            solved exactly by fast diagonalisation (falls
+                            back to red-black SOR where the factors fail
+                            their check); SMG_COARSE_SOR: red-black point
+                            SOR with the 2D omega of Appendix A, from zero
+                            until the residual drops by 1e-10 (Sec. 3.3; the
+                            coarsest level must then have <= 1024 cells) */
 } smg_opts;
+
+enum { SMG_COARSE_EXACT = 0, SMG_COARSE_SOR = 1 };
 
 enum { SMG_LAUNCH_GRAPH = 0, SMG_LAUNCH_DYNAMIC = 1 };
 
@@ -301,8 +310,10 @@ smg_status smg_net_conv3_wgrad_noalloc(const unsigned short *g_dev, int c_out, c
  * then on every solve keeps its right-hand sides of those modes for the next
  * step; a warm-started solve with SMG_NET_GUESS builds the network inputs
  * (per real image: f_t / s_f, (f_t - f_{t-1}) / s_d, u_{t-1} / s_u, m / 4,
- * the two normalised grid coordinates and two zeros, with s_f, s_d, s_u the
- * plane RMS values of f_t, f_t - f_{t-1} and u_{t-1}) before each of its two multigrid
+ * the two normalised grid coordinates, (u_{t-1} - u_{t-2}) / s_o (zero
+ * until two warm steps have run) and a zero, with s_f, s_d, s_u the plane
+ * RMS values of f_t, f_t - f_{t-1} and u_{t-1} and s_o = s_u s_d / s_f,
+ * the scale of the output (u_t - u_{t-1}) / s_o) before each of its two multigrid
  * solves and starts every mode from the better of the network's guess and
  * the previous solution (defect norms after one smoothing step of each).
  * A NULL net detaches. */
@@ -325,7 +336,8 @@ smg_status smg_plan_net_used(const smg_plan *plan, int *used_host, void *stream)
  * Inputs, complex FP64 [m_max+1][n_a][n_b] (modes 0..m_max): f_dev this
  * step's right-hand side of solve t (for t = 1 with the ghost potential
  * folded in), fprev_dev the previous step's, uprev_dev the previous step's
- * solution.  Outputs: guess_dev (same layout) the initial guess each mode
+ * solution, uprev2_dev (may be NULL) the solution of the step before.
+ * Outputs: guess_dev (same layout) the initial guess each mode
  * starts from (the network's candidate u_prev + s_o y or u_prev, by the
  * defect norms after one smoothing step of each); x_dev (may be NULL) the
  * FP32 network inputs [2 m_max + 1][n_a][n_b][8] (image 0 = Re m=0, 2m-1 =
@@ -335,8 +347,8 @@ smg_status smg_plan_net_used(const smg_plan *plan, int *used_host, void *stream)
  * solve state, so the next smg_solve starts cold.  SMG_ESTATE without an
  * attached network. */
 smg_status smg_net_guess_step(smg_plan *plan, int t, const double *f_dev, const double *fprev_dev,
-                              const double *uprev_dev, double *guess_dev, float *x_dev, float *y_dev, int *used_host,
-                              void *stream);
+                              const double *uprev_dev, const double *uprev2_dev, double *guess_dev, float *x_dev,
+                              float *y_dev, int *used_host, void *stream);
 
 /* ---- geometry query (host, no device work) ------------------------------ */
 /* Cell-centre coordinates: a_host[n_a], b_host[n_b], phi_host[n_phi]

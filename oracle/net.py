@@ -8,7 +8,9 @@ real plane (the real or imaginary part of a mode) with eight channels,
   2: u_{t-1} / s_u          (the previous step's solution)
   3: m / 4                  (the azimuthal index),
   4, 5: (i + 1/2) / n_a - 1/2, (j + 1/2) / n_b - 1/2  (the position on the grid),
-  6, 7: zero,
+  6: (u_{t-1} - u_{t-2}) / s_o  (the previous step's change; zero when there
+     is no solution two steps back),
+  7: zero,
 and the output is (u_t - u_{t-1}) / s_o, so that the guess is
 u_{t-1} + s_o * net(x).  s_f, s_d and s_u are the per-plane RMS values of
 f_t, f_t - f_{t-1} and u_{t-1}, and s_o = s_u s_d / s_f.  The output
@@ -252,11 +254,12 @@ def _part(z, im):
     return z.imag if im else z.real
 
 
-def guess_images(f, fprev, uprev, m_max):
+def guess_images(f, fprev, uprev, m_max, uprev2=None):
     """Network inputs and scales of modes 0..m_max.
 
     f, fprev, uprev: complex (>= m_max + 1, n_a, n_b) planes of this step's
-    right-hand side, the previous step's and the previous solution.  Returns
+    right-hand side, the previous step's and the previous solution; uprev2
+    (optional) the solution of the step before that.  Returns
     x (2 m_max + 1, n_a, n_b, 8) and sc (2 m_max + 1, 4) = (s_f, s_d, s_u,
     s_o) per image, the RMS values of f, f - fprev and uprev over the plane
     (1 where zero) and s_o = s_u s_d / s_f."""
@@ -278,6 +281,8 @@ def guess_images(f, fprev, uprev, m_max):
         x[k, :, :, 3] = m / 4.0
         x[k, :, :, 4] = ci[:, None]
         x[k, :, :, 5] = cj[None, :]
+        if uprev2 is not None:
+            x[k, :, :, 6] = (uv - _part(uprev2[m], im)) / sc[k, 3]
     return x, sc
 
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -184,11 +185,15 @@ struct PlanNet {
   int m_max = 0, n_img = 0, nblk = 1;
   char* work = nullptr;
   NetWork wl{};
-  size_t o_fprev[2] = {0, 0}, o_uprev = 0, o_cand = 0, o_cs = 0, o_us = 0, o_u2 = 0, o_sc = 0, o_part = 0, o_used = 0,
-         o_jobs = 0, o_lv = 0, o_list = 0, o_rec = 0, bytes = 0;
+  size_t o_fprev[2] = {0, 0}, o_uprev[2] = {0, 0}, o_uprev2[2] = {0, 0}, o_cand = 0, o_cs = 0, o_us = 0, o_u2 = 0,
+         o_sc = 0, o_part = 0, o_used = 0, o_jobs = 0, o_lv = 0, o_list = 0, o_rec = 0, bytes = 0;
   std::vector<NormJob> hjobs;  // [target][smoothed candidate, smoothed previous solution]
   std::vector<LvJob> hlv;      // [target][the same two arrays]: one smoothing step
   bool prev_ok[2] = {false, false};
+  // o_uprev[t] holds the solution one step back (set by the last guess
+  // step of target t), so the next one can move it two steps back
+  bool have_u[2] = {false, false};
+  bool prev2_ok[2] = {false, false};   // the current guess step has u two steps back
   float* samples = nullptr;
   int capacity = 0;
 };
@@ -273,6 +278,8 @@ static smg_status validate(const smg_grid& g, const smg_opts& o) {
   if (o.line_solver != SMG_LINE_SOR && o.line_solver != SMG_LINE_EXACT) return fail(SMG_EINVAL, "bad line_solver");
   if (o.coarse_cells != 0 && (o.coarse_cells < 16 || o.coarse_cells > 8192))
     return fail(SMG_EINVAL, "coarse_cells must be 0 or in [16, 8192]");
+  if (o.coarse_solver != SMG_COARSE_EXACT && o.coarse_solver != SMG_COARSE_SOR)
+    return fail(SMG_EINVAL, "coarse_solver must be SMG_COARSE_EXACT or SMG_COARSE_SOR");
   return SMG_OK;
 }
 
@@ -304,7 +311,8 @@ extern "C" smg_status smg_plan_create(const smg_grid* grid, const smg_opts* opts
                  s.pole_hi() ? EDGE_POLE : EDGE_DIRICHLET};
   std::vector<int> modes(p->M);
   for (int m = 0; m < p->M; ++m) modes[m] = m;
-  p->H = build_hierarchy(s, 1, s.n_a, 1, s.n_b, edge, modes, true, o.coarse_cells);
+  p->H = build_hierarchy(s, 1, s.n_a, 1, s.n_b, edge, modes, true, o.coarse_cells,
+                         o.coarse_solver == SMG_COARSE_EXACT);
   const LevelTables& Lc = p->H.lv.back();
   if (Lc.na * Lc.nb > kMaxCoarseCells && Lc.sep_v.empty())
     return fail(SMG_EINVAL, strprintf("the %dx%d coarsest level has no exact solver", Lc.na, Lc.nb));
@@ -949,13 +957,17 @@ static smg_status net_before(smg_plan* p, int t, bool warm, bool guess, hipStrea
   if (!pn.net || !warm || !pn.prev_ok[t]) return SMG_OK;
   const int plane = p->spec.n_a * p->spec.n_b;
   const size_t np = (size_t)(pn.m_max + 1) * plane;
-  double2* uprev = reinterpret_cast<double2*>(pn.work + pn.o_uprev);
+  double2* uprev = reinterpret_cast<double2*>(pn.work + pn.o_uprev[t]);
+  double2* uprev2 = reinterpret_cast<double2*>(pn.work + pn.o_uprev2[t]);
   double* sc = reinterpret_cast<double*>(pn.work + pn.o_sc);
   const double2* fprev = reinterpret_cast<const double2*>(pn.work + pn.o_fprev[t]);
+  // the host decided before the body (group_solve) whether uprev still holds
+  // the solution of the step before the previous one
+  if (pn.prev2_ok[t]) HIPCHK(smgk::copy_planes(uprev2, uprev, np, st));
   HIPCHK(smgk::copy_planes(uprev, target_u(p, t), np, st));
   HIPCHK(smgg::scales(target_f(p, t), fprev, uprev, plane, pn.n_img, sc, st));
-  HIPCHK(smgg::assemble(target_f(p, t), fprev, uprev, sc, p->spec.n_a, p->spec.n_b, pn.n_img,
-                        reinterpret_cast<float*>(pn.work + pn.wl.x32), st));
+  HIPCHK(smgg::assemble(target_f(p, t), fprev, uprev, pn.prev2_ok[t] ? uprev2 : nullptr, sc, p->spec.n_a, p->spec.n_b,
+                        pn.n_img, reinterpret_cast<float*>(pn.work + pn.wl.x32), st));
   if (!guess) return SMG_OK;
   STCHK(pn.net->def.forward(pn.work, pn.wl, st));
   double2* cand = reinterpret_cast<double2*>(pn.work + pn.o_cand);
@@ -989,7 +1001,7 @@ static smg_status net_after(smg_plan* p, int t, bool warm, hipStream_t st) {
   const int plane = p->spec.n_a * p->spec.n_b;
   if (warm && pn.prev_ok[t] && pn.samples)
     HIPCHK(smgg::record(reinterpret_cast<const float*>(pn.work + pn.wl.x32), target_u(p, t),
-                        reinterpret_cast<const double2*>(pn.work + pn.o_uprev),
+                        reinterpret_cast<const double2*>(pn.work + pn.o_uprev[t]),
                         reinterpret_cast<const double*>(pn.work + pn.o_sc), plane, pn.n_img,
                         reinterpret_cast<int*>(pn.work + pn.o_rec), pn.capacity, pn.samples, st));
   HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_fprev[t]), target_f(p, t),
@@ -1038,7 +1050,9 @@ static smg_status group_graph(Group& g, double tol, bool warm, unsigned flags, c
   key.push_back(warm ? 1 : 0);
   key.push_back((int)(flags & SMG_NET_GUESS));
   for (const smg_plan* p : g.plans) {  // the learned-guess steps the body holds
-    key.push_back(p->pn.net ? 1 + 2 * p->pn.prev_ok[0] + 4 * p->pn.prev_ok[1] + 8 * (p->pn.samples != nullptr) : 0);
+    key.push_back(p->pn.net ? 1 + 2 * p->pn.prev_ok[0] + 4 * p->pn.prev_ok[1] + 8 * (p->pn.samples != nullptr) +
+                                  16 * p->pn.prev2_ok[0] + 32 * p->pn.prev2_ok[1]
+                            : 0);
     key.push_back((int)p->gen);
   }
   long long tb;
@@ -1124,6 +1138,18 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
   } guard{ev, timings};
   const bool warm = (flags & SMG_WARM_PREV) && g.have_prev;
   const int wk = warm ? 1 : 0;
+  // learned-guess bookkeeping, decided on the host (a replayed graph runs
+  // none of the body's host code): a guess step of target t runs when the
+  // solve is warm and the previous right-hand side is kept; it sees the
+  // solution two steps back when the previous solve ran one as well
+  std::vector<std::array<bool, 2>> guess_step(P, std::array<bool, 2>{false, false});
+  for (int q = 0; q < P; ++q) {
+    PlanNet& pn = g.plans[q]->pn;
+    for (int t = 0; t < 2; ++t) {
+      guess_step[q][t] = pn.net && warm && pn.prev_ok[t];
+      pn.prev2_ok[t] = guess_step[q][t] && pn.have_u[t];
+    }
+  }
   // scheduled launches (one host synchronisation per solve) once a previous
   // solve of the same kind gave the per-mode cycle counts; per-cycle host
   // reads for the first solve and with SMG_LAUNCH_DYNAMIC.  Component timings
@@ -1149,6 +1175,8 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
   STCHK(fft_inverse_all(g, phi, st));
   if (timings) HIPCHK(hipEventRecord(ev[5], st));
   g.have_prev = true;
+  for (int q = 0; q < P; ++q)
+    for (int t = 0; t < 2; ++t) g.plans[q]->pn.have_u[t] = guess_step[q][t];
   // per-mode state of both solves (one synchronisation); modes that needed
   // more cycles than the schedule gave them are finished here and the
   // inverse transforms are repeated
@@ -1229,7 +1257,10 @@ static smg_status net_layout(const smg_plan* p, const smg_net* net, int m_max, P
   auto take = [&](size_t b) { size_t o = off; off = align_up(off + b); return o; };
   pn.o_fprev[0] = take(sizeof(double2) * np);
   pn.o_fprev[1] = take(sizeof(double2) * np);
-  pn.o_uprev = take(sizeof(double2) * np);
+  for (int t = 0; t < 2; ++t) {
+    pn.o_uprev[t] = take(sizeof(double2) * np);
+    pn.o_uprev2[t] = take(sizeof(double2) * np);
+  }
   pn.o_cand = take(sizeof(double2) * np);
   pn.o_cs = take(sizeof(double2) * np);
   pn.o_us = take(sizeof(double2) * np);
@@ -1342,7 +1373,8 @@ extern "C" smg_status smg_plan_net_used(const smg_plan* p, int* used, void* stre
 }
 
 extern "C" smg_status smg_net_guess_step(smg_plan* p, int t, const double* f, const double* fprev, const double* uprev,
-                                         double* guess, float* x_out, float* y_out, int* used_host, void* stream) {
+                                         const double* uprev2, double* guess, float* x_out, float* y_out, int* used_host,
+                                         void* stream) {
   STCHK(need_ready(p));
   PlanNet& pn = p->pn;
   if (!pn.net) return fail(SMG_ESTATE, "no network attached (smg_plan_attach_net)");
@@ -1354,10 +1386,17 @@ extern "C" smg_status smg_net_guess_step(smg_plan* p, int t, const double* f, co
   HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_fprev[t]), reinterpret_cast<const double2*>(fprev), np,
                            st));
   HIPCHK(smgk::copy_planes(target_u(p, t), reinterpret_cast<const double2*>(uprev), np, st));
+  // net_before moves o_uprev (the solution one step back) two steps back
+  if (uprev2)
+    HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_uprev[t]), reinterpret_cast<const double2*>(uprev2),
+                             np, st));
   const bool keep = pn.prev_ok[t];
   pn.prev_ok[t] = true;
+  pn.prev2_ok[t] = uprev2 != nullptr;
   const smg_status sb = net_before(p, t, true, true, st);
   pn.prev_ok[t] = keep;
+  pn.prev2_ok[t] = false;
+  pn.have_u[0] = pn.have_u[1] = false;
   // the plan's solve state now holds these planes: the next solve starts cold
   p->grp.have_prev = false;
   STCHK(sb);

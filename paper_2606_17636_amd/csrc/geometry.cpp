@@ -309,7 +309,7 @@ static double transfer_coord(const Spec& s, char which, double x) {
 }
 
 Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, const int edge[4],
-                          const std::vector<int>& modes, bool main_grid, int max_coarse) {
+                          const std::vector<int>& modes, bool main_grid, int max_coarse, bool exact_coarse) {
   Hierarchy h;
   h.spec = s;
   h.M = (int)modes.size();
@@ -444,7 +444,7 @@ Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, c
     for (int j = 0; j < n2; ++j) T.vb[j] = B.vol[j + 1] / sb;
   }
   // exact solve of the coarsest level by fast diagonalisation
-  {
+  if (exact_coarse) {
     LevelTables& T = h.lv[L - 1];
     separable_factors(T, h.M);
   }

@@ -9,8 +9,9 @@ namespace smgg {
 // f_t - f_prev, of u_prev, and s_u s_d / s_f (the output scale)
 hipError_t scales(const double2* f, const double2* fprev, const double2* uprev, int plane, int n_img, double* sc,
                   hipStream_t st);
-hipError_t assemble(const double2* f, const double2* fprev, const double2* uprev, const double* sc, int na, int nb,
-                    int n_img, float* x, hipStream_t st);
+// uprev2: the solution two steps back (channel 6 = (uprev - uprev2) / s_o), or null
+hipError_t assemble(const double2* f, const double2* fprev, const double2* uprev, const double2* uprev2, const double* sc,
+                    int na, int nb, int n_img, float* x, hipStream_t st);
 hipError_t candidate(const double2* uprev, const float* y, const double* sc, int plane, int m_max, double2* cand,
                      hipStream_t st);
 hipError_t select(const double* pc, const double* pu, int nblk, const double2* cand, double2* u, int plane, int m_max,

@@ -53,11 +53,14 @@ __global__ void k_scales(const double2* __restrict__ f, const double2* __restric
 }
 
 // x[k][i][j][0..7] = (f_t / s_f, (f_t - f_prev) / s_d, u_prev / s_u, m / 4,
-//                     (i + 1/2) / n_a - 1/2, (j + 1/2) / n_b - 1/2, 0, 0)
-// (the last channels tell the convolutions where on the grid they are)
+//                     (i + 1/2) / n_a - 1/2, (j + 1/2) / n_b - 1/2,
+//                     (u_prev - u_prev2) / s_o, 0)
+// (channels 4, 5 tell the convolutions where on the grid they are;
+// channel 6, the previous step's change of the solution, is zero when
+// uprev2 is null: no solution two steps back)
 __global__ void k_assemble(const double2* __restrict__ f, const double2* __restrict__ fprev,
-                           const double2* __restrict__ uprev, const double* __restrict__ sc, int na, int nb, int n_img,
-                           float* __restrict__ x) {
+                           const double2* __restrict__ uprev, const double2* __restrict__ uprev2,
+                           const double* __restrict__ sc, int na, int nb, int n_img, float* __restrict__ x) {
   const int plane = na * nb;
   const size_t total = (size_t)n_img * plane;
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
@@ -67,11 +70,12 @@ __global__ void k_assemble(const double2* __restrict__ f, const double2* __restr
     const double fv = part_of(f[(size_t)m * plane + q], im);
     const double fp = part_of(fprev[(size_t)m * plane + q], im);
     const double uv = part_of(uprev[(size_t)m * plane + q], im);
-    const double sf = sc[4 * k], sd = sc[4 * k + 1], su = sc[4 * k + 2];
+    const double sf = sc[4 * k], sd = sc[4 * k + 1], su = sc[4 * k + 2], so = sc[4 * k + 3];
+    const double dv = uprev2 ? (uv - part_of(uprev2[(size_t)m * plane + q], im)) / so : 0.0;
     const int i = q / nb, j = q - i * nb;
     float4* xo = reinterpret_cast<float4*>(x) + 2 * t;
     xo[0] = make_float4((float)(fv / sf), (float)((fv - fp) / sd), (float)(uv / su), 0.25f * (float)m);
-    xo[1] = make_float4((i + 0.5f) / na - 0.5f, (j + 0.5f) / nb - 0.5f, 0.f, 0.f);
+    xo[1] = make_float4((i + 0.5f) / na - 0.5f, (j + 0.5f) / nb - 0.5f, (float)dv, 0.f);
   }
 }
 
@@ -148,10 +152,10 @@ hipError_t scales(const double2* f, const double2* fprev, const double2* uprev, 
   return hipGetLastError();
 }
 
-hipError_t assemble(const double2* f, const double2* fprev, const double2* uprev, const double* sc, int na, int nb,
-                    int n_img, float* x, hipStream_t st) {
-  hipLaunchKernelGGL(k_assemble, dim3(grid1((size_t)n_img * na * nb)), dim3(256), 0, st, f, fprev, uprev, sc, na, nb, n_img,
-                     x);
+hipError_t assemble(const double2* f, const double2* fprev, const double2* uprev, const double2* uprev2, const double* sc,
+                    int na, int nb, int n_img, float* x, hipStream_t st) {
+  hipLaunchKernelGGL(k_assemble, dim3(grid1((size_t)n_img * na * nb)), dim3(256), 0, st, f, fprev, uprev, uprev2, sc, na,
+                     nb, n_img, x);
   return hipGetLastError();
 }
 

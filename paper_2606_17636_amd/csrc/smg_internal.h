@@ -88,8 +88,11 @@ struct Hierarchy {
 void separable_factors(LevelTables& T, int M);
 // max_coarse: coarsening stops at the first level with at most this many
 // cells (after at least one halving); 0 takes kMaxDirect.
+// exact_coarse: build the fast-diagonalisation factors of the coarsest
+// level (otherwise it is solved by red-black SOR).
 Hierarchy build_hierarchy(const Spec& s, long a_lo, int na, long b_lo, int nb, const int edge[4],
-                          const std::vector<int>& modes, bool main_grid, int max_coarse = 0);
+                          const std::vector<int>& modes, bool main_grid, int max_coarse = 0,
+                          bool exact_coarse = true);
 
 // Coarsest levels up to this many cells are solved with a precomputed
 // inverse instead of red-black SOR.

@@ -21,6 +21,7 @@ DGF_AUTO, DGF_AUX, DGF_EXTENDED = 0, 1, 2
 LINE_SOR, LINE_EXACT = 0, 1
 NU_AUTO = -1  # nu_pre = nu_post = NU_AUTO: smoothing steps chosen at setup
 LAUNCH_GRAPH, LAUNCH_DYNAMIC = 0, 1
+COARSE_EXACT, COARSE_SOR = 0, 1
 WARM_PREV = 1
 TIMINGS = 2
 NET_GUESS = 4
@@ -44,7 +45,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
                 ("n_sor", ctypes.c_int), ("max_cycles", ctypes.c_int), ("dgf_method", ctypes.c_int),
                 ("n_pad", ctypes.c_int), ("dgf_tol", ctypes.c_double), ("line_solver", ctypes.c_int),
-                ("launch", ctypes.c_int), ("autotune", ctypes.c_int), ("coarse_cells", ctypes.c_int)]
+                ("launch", ctypes.c_int), ("autotune", ctypes.c_int), ("coarse_cells", ctypes.c_int),
+                ("coarse_solver", ctypes.c_int)]
 
 
 _PI = ctypes.POINTER(ctypes.c_int)
@@ -113,7 +115,7 @@ def load():
         "smg_plan_record": ([P, P, ctypes.c_int, P], ctypes.c_int),
         "smg_plan_recorded": ([P, P], ctypes.c_int),
         "smg_plan_net_used": ([P, _PI, P], ctypes.c_int),
-        "smg_net_guess_step": ([P, ctypes.c_int, P, P, P, P, P, P, _PI, P], ctypes.c_int),
+        "smg_net_guess_step": ([P, ctypes.c_int, P, P, P, P, P, P, P, _PI, P], ctypes.c_int),
         "smg_net_conv3": ([P, ctypes.c_int, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                            ctypes.c_int, P], ctypes.c_int),
         "smg_net_conv3_wgrad_work_bytes": ([ctypes.c_int] * 5, ctypes.c_size_t),
@@ -172,7 +174,7 @@ class Plan:
 
     def __init__(self, geometry, radial, n_a, n_b, n_phi, a_min, a_max, b_min, b_max, G=1.0, precision=FP64,
                  nu_pre=2, nu_post=2, n_sor=2, max_cycles=60, dgf_method=DGF_AUTO, n_pad=16, dgf_tol=1e-13,
-                 line_solver=LINE_SOR, launch=LAUNCH_GRAPH, autotune=False, coarse_cells=0):
+                 line_solver=LINE_SOR, launch=LAUNCH_GRAPH, autotune=False, coarse_cells=0, coarse_solver=COARSE_EXACT):
         lib = load()
         geo = {"spherical": SPHERICAL, "cylindrical": CYLINDRICAL}.get(geometry, geometry)
         rad = {"uniform": UNIFORM, "log": LOG}.get(radial, radial)
@@ -180,8 +182,9 @@ class Plan:
         self.grid = Grid(geo, rad, n_a, n_b, n_phi, a_min, a_max, b_min, b_max, G)
         ls = {"sor": LINE_SOR, "exact": LINE_EXACT}.get(line_solver, line_solver)
         lc = {"graph": LAUNCH_GRAPH, "dynamic": LAUNCH_DYNAMIC}.get(launch, launch)
+        cs = {"exact": COARSE_EXACT, "sor": COARSE_SOR}.get(coarse_solver, coarse_solver)
         self.opts = Opts(prec, nu_pre, nu_post, n_sor, max_cycles, dgf_method, n_pad, dgf_tol, ls, lc,
-                         1 if autotune else 0, coarse_cells)
+                         1 if autotune else 0, coarse_cells, cs)
         self.line_solver = ls
         self._h = ctypes.c_void_p()
         _check(lib.smg_plan_create(ctypes.byref(self.grid), ctypes.byref(self.opts), ctypes.byref(self._h)))
@@ -267,20 +270,20 @@ class Plan:
         _check(load().smg_plan_net_used(self._h, _iptr(used), _stream()))
         return used.reshape(2, self.m_max + 1)
 
-    def net_guess_step(self, t, f, fprev, uprev):
+    def net_guess_step(self, t, f, fprev, uprev, uprev2=None):
         """The learned-guess step of solve t on caller planes (complex128
         cuda, shape (m_max+1, n_a, n_b)): returns (guess, x, y, used)."""
         import torch
         shape = (self.m_max + 1, self.n_a, self.n_b)
-        for a in (f, fprev, uprev):
+        for a in (f, fprev, uprev) + ((uprev2,) if uprev2 is not None else ()):
             self._c128(a, shape)
         n_img = 2 * self.m_max + 1
         guess = torch.empty(shape, dtype=torch.complex128, device=f.device)
         x = torch.empty((n_img, self.n_a, self.n_b, 8), dtype=torch.float32, device=f.device)
         y = torch.empty((n_img, self.n_a, self.n_b), dtype=torch.float32, device=f.device)
         used = np.zeros(self.m_max + 1, dtype=np.int32)
-        _check(load().smg_net_guess_step(self._h, int(t), _ptr(f), _ptr(fprev), _ptr(uprev), _ptr(guess), _ptr(x),
-                                         _ptr(y), _iptr(used), _stream()))
+        _check(load().smg_net_guess_step(self._h, int(t), _ptr(f), _ptr(fprev), _ptr(uprev), _ptr(uprev2), _ptr(guess),
+                                         _ptr(x), _ptr(y), _iptr(used), _stream()))
         return guess, x, y, used
 
     def solve(self, rho, tol=1e-8, warm=False, out=None, timings=False, allow_noconv=False, net=False):

@@ -51,9 +51,11 @@ def _setup():
         dt = 0.5 * (2 * math.pi / SPEC.n_phi) / (blobs[0].min() ** -1.5)
         f0 = op.source_modes(keplerian_snapshot(a, b, p, blobs, 0.0))
         f1 = op.source_modes(keplerian_snapshot(a, b, p, blobs, dt))
+        fm = op.source_modes(keplerian_snapshot(a, b, p, blobs, -dt))
         u0 = op.solve_modes(f0)
         u1 = op.solve_modes(f1)
-        _cache.update(p=plan, net=net, op=op, f0=f0, f1=f1, u0=u0, u1=u1)
+        um = op.solve_modes(fm)
+        _cache.update(p=plan, net=net, op=op, f0=f0, f1=f1, u0=u0, u1=u1, um=um)
     return _cache
 
 
@@ -65,12 +67,13 @@ def test_guess_inputs_and_network_output_match_oracle():
     c = _setup()
     params = init_params(21, zero_output=False)
     c["net"].set_params(params)
-    for t in (0, 1):
-        print(f"[case] inputs and output, t={t}", flush=True)
-        guess, x, y, used = c["p"].net_guess_step(t, _dev(c["f1"]), _dev(c["f0"]), _dev(c["u0"]))
+    for t, u2 in ((0, None), (1, c["um"])):
+        print(f"[case] inputs and output, t={t}, two steps back: {u2 is not None}", flush=True)
+        guess, x, y, used = c["p"].net_guess_step(t, _dev(c["f1"]), _dev(c["f0"]), _dev(c["u0"]),
+                                                  None if u2 is None else _dev(u2))
         x = x.cpu().numpy().astype(np.float64)
         y = y.cpu().numpy().astype(np.float64)
-        xo, sc = onet.guess_images(c["f1"], c["f0"], c["u0"], M_MAX)
+        xo, sc = onet.guess_images(c["f1"], c["f0"], c["u0"], M_MAX, uprev2=u2)
         err = np.abs(x - xo)
         bound = 2.0**-23 * np.abs(xo) + 2.0**-126      # one FP32 rounding; FP32 underflow
         bad = np.argwhere(err > bound)

@@ -197,6 +197,23 @@ def test_full_solve_fp64(key):
     assert info["converged"]
 
 
+@pytest.mark.parametrize("key", ["sph-uni", "sph-log", "cyl-uni"])
+def test_full_solve_sor_coarsest_fp64(key):
+    """The plain method of the paper on the GPU: FP64, V(2,2), SOR line
+    smoother and the coarsest level solved by red-black point SOR with the
+    2D omega (Sec. 3.3) instead of fast diagonalisation; same bar as the
+    other FP64 solves."""
+    from paper_2606_17636_amd import smg
+    spec, npad = SPECS[key]
+    _, _, op = _plans(key)
+    print(f"[setup] {key} coarse_solver=sor", flush=True)
+    gp = smg.grid_from_spec(spec, n_pad=npad, precision="fp64", launch="dynamic", coarse_solver="sor").setup()
+    rho = _density(spec, 12)
+    phi, info = gp.solve(_dev(rho), tol=1e-12)
+    assert info["converged"]
+    assert _l2(spec, phi.cpu().numpy(), op.solve(rho)) < 1e-10
+
+
 def test_zero_density_gives_zero():
     spec, gp, op = _plans("sph-uni")
     phi, info = gp.solve(torch.zeros((spec.n_a, spec.n_b, spec.n_phi), dtype=torch.float64, device="cuda"), tol=1e-8)

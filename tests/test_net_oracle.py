@@ -112,6 +112,14 @@ def test_guess_images_layout_and_scaling():
     assert np.allclose(x[0, :, 0, 4], (np.arange(na) + 0.5) / na - 0.5)
     assert np.allclose(x[0, 0, :, 5], (np.arange(nb) + 0.5) / nb - 0.5)
     assert np.all(x[..., 6:] == 0.0)
+    # channel 6: the previous change of the solution in units of the output scale
+    u2 = _planes(rng, M, na, nb)
+    x6, sc6 = net.guess_images(f, fp, up, m_max, uprev2=u2)
+    assert np.array_equal(x6[..., :6], x[..., :6]) and np.all(x6[..., 7] == 0.0)
+    for k in range(2 * m_max + 1):
+        m = (k + 1) // 2
+        part = (lambda z: z.imag) if (k > 0 and k % 2 == 0) else (lambda z: z.real)
+        assert np.allclose(x6[k, :, :, 6] * sc6[k, 3], part(up[m]) - part(u2[m]), rtol=1e-13, atol=0)
     x2, _ = net.guess_images(3.5 * f, 3.5 * fp, -2.0 * up, m_max)
     assert np.allclose(x2[..., :2], x[..., :2], rtol=1e-13) and np.allclose(x2[..., 2], -x[..., 2], rtol=1e-13)
     # a zero plane keeps scale 1 (no division by zero)
