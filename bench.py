@@ -406,12 +406,12 @@ def bench_trajectory(args, smg, configs, torch, pool):
     # training on method-generated trajectories (setup)
     t0 = time.perf_counter()
     seeds = list(range(50, 50 + args.train_traj))
-    cap = len(seeds) * (n_train_snap - 1) * learn.samples_per_step(m_max)
+    cap = len(seeds) * (n_train_snap - 2) * learn.samples_per_step(m_max)
     buf = learn.sample_buffer(plan, cap)
     n, _ = learn.record_trajectories(plan, [traj(s, n_train_snap) for s in seeds], args.tol, buf, cap)
     log(f"recorded {n} samples from {len(seeds)} trajectories in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    losses = learn.train(net, buf, n, g["n_a"], g["n_b"], steps=args.train_steps, batch=16, lr=1e-3, seed=1,
+    losses = learn.train(net, buf, n, g["n_a"], g["n_b"], steps=args.train_steps, batch=16, lr=args.train_lr, seed=1,
                          log_every=max(1, args.train_steps // 4), log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
@@ -612,6 +612,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="CPU seconds of oracle work in the sample")
     ap.add_argument("--train-traj", type=int, default=8, help="c5: training trajectories")
     ap.add_argument("--train-steps", type=int, default=2000, help="c5: Adam steps")
+    ap.add_argument("--train-lr", type=float, default=1e-3, help="c5: peak Adam learning rate (cosine decay)")
     ap.add_argument("--part", default="solve", choices=["solve", "accel"],
                     help="accel: time the face acceleration of the solved potential instead of the solve")
     ap.add_argument("--copy-calibration", action="store_true",

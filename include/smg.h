@@ -220,10 +220,13 @@ smg_status smg_batch_destroy(smg_batch *batch);
 /* ---- the learned initial guess --------------------------------------------
  * A U-Net on real mode planes (one image per real or imaginary part of a
  * low-m mode), 8 input channels (f_t / s_f, (f_t - f_{t-1}) / s_d,
- * u_{t-1} / s_u, m / 4, (i + 1/2) / n_a - 1/2, (j + 1/2) / n_b - 1/2, 0, 0;
- * s_f, s_d, s_u the plane RMS of f_t, f_t - f_{t-1} and u_{t-1}) and one
- * output channel, the change (u_t - u_{t-1}) / s_o of
- * the plane since the previous time step, s_o = s_u s_d / s_f.  At each
+ * u_{t-1} / s_u, m / 4, (i + 1/2) / n_a - 1/2, (j + 1/2) / n_b - 1/2,
+ * and this part of (u_{t-1} - u_{t-2}) / s_o and of -i (u_{t-1} - u_{t-2})
+ * / s_o (the other part, signed as a small rotation of the mode changes
+ * it); s_f, s_d, s_u the plane RMS of f_t,
+ * f_t - f_{t-1} and u_{t-1}, s_o the RMS of u_{t-1} - u_{t-2}) and one
+ * output channel, the correction (u_t - 2 u_{t-1} + u_{t-2}) / s_o to the
+ * linear extrapolation of the last two solutions.  At each
  * of `levels` resolutions two 3x3 convolutions with ReLU (32 channels),
  * 2x2 average pooling down, nearest upsampling and concatenation with the
  * encoder output up, a 1x1 output layer.  Weights and activations are BF16,
@@ -310,20 +313,26 @@ smg_status smg_net_conv3_wgrad_noalloc(const unsigned short *g_dev, int c_out, c
  * then on every solve keeps its right-hand sides of those modes for the next
  * step; a warm-started solve with SMG_NET_GUESS builds the network inputs
  * (per real image: f_t / s_f, (f_t - f_{t-1}) / s_d, u_{t-1} / s_u, m / 4,
- * the two normalised grid coordinates, (u_{t-1} - u_{t-2}) / s_o (zero
- * until two warm steps have run) and a zero, with s_f, s_d, s_u the plane
- * RMS values of f_t, f_t - f_{t-1} and u_{t-1} and s_o = s_u s_d / s_f,
- * the scale of the output (u_t - u_{t-1}) / s_o) before each of its two multigrid
- * solves and starts every mode from the better of the network's guess and
- * the previous solution (defect norms after one smoothing step of each).
+ * the two normalised grid coordinates, this part of (u_{t-1} - u_{t-2}) /
+ * s_o and of -i (u_{t-1} - u_{t-2}) / s_o, with s_f, s_d, s_u the plane RMS
+ * values of f_t, f_t - f_{t-1} and u_{t-1}, and s_o, the scale of the
+ * output, the RMS of u_{t-1} - u_{t-2}; before two warm steps have run,
+ * and for a static plane (last change below 1e-6 of its RMS), channels 6
+ * and 7 are zero) before each of its two multigrid solves and
+ * starts every mode from the better (defect norms after one smoothing step
+ * of each) of the previous solution and the candidate u_{t-1} + (u_{t-1} -
+ * u_{t-2}) + s_o y: the linear extrapolation plus the network's correction
+ * y (without u_{t-2}: u_{t-1} + s_o y).
  * A NULL net detaches. */
 size_t smg_plan_net_work_bytes(const smg_plan *plan, const smg_net *net, int m_max);
 smg_status smg_plan_attach_net(smg_plan *plan, smg_net *net, int m_max, void *work_dev, size_t work_bytes,
                                void *stream);
-/* Record training samples: every later warm-started solve appends, for each
- * of its two multigrid solves and each real image of modes 0..m_max, the
- * sample (network input [n_a][n_b][8], target (u_t - u_{t-1}) / s_o
- * [n_a][n_b], FP32) to samples_dev while fewer than `capacity` are stored
+/* Record training samples: every later warm-started solve that has the
+ * solutions of the two previous steps (from the third solve of a sequence
+ * on) appends, for each of its two multigrid solves and each real image of
+ * modes 0..m_max, the sample (network input [n_a][n_b][8], target
+ * (u_t - 2 u_{t-1} + u_{t-2}) / s_o [n_a][n_b] -- the correction to the
+ * linear extrapolation, FP32) to samples_dev while fewer than `capacity` are stored
  * (the layout smg_net_train_step reads).  Resets the count; capacity 0 stops
  * recording.  smg_plan_recorded returns the count (synchronises). */
 smg_status smg_plan_record(smg_plan *plan, float *samples_dev, int capacity, void *stream);

@@ -8,12 +8,17 @@ real plane (the real or imaginary part of a mode) with eight channels,
   2: u_{t-1} / s_u          (the previous step's solution)
   3: m / 4                  (the azimuthal index),
   4, 5: (i + 1/2) / n_a - 1/2, (j + 1/2) / n_b - 1/2  (the position on the grid),
-  6: (u_{t-1} - u_{t-2}) / s_o  (the previous step's change; zero when there
-     is no solution two steps back),
-  7: zero,
+  6: (u_{t-1} - u_{t-2}) / s_o  (this part of the previous step's change,
+     of unit RMS since s_o is then its RMS),
+  7: the same part of -i (u_{t-1} - u_{t-2}) / s_o  (the other part, with
+     the sign a rotation of the mode gives: a rotation by a small angle a
+     changes the mode by a times -i m u; zero for m = 0),
+  channels 6 and 7 are zero when there is no solution two steps back or the
+  plane is static,
 and the output is (u_t - u_{t-1}) / s_o, so that the guess is
 u_{t-1} + s_o * net(x).  s_f, s_d and s_u are the per-plane RMS values of
-f_t, f_t - f_{t-1} and u_{t-1}, and s_o = s_u s_d / s_f.  The output
+f_t, f_t - f_{t-1} and u_{t-1}; s_o is the RMS of u_{t-1} - u_{t-2} when
+that exists, else s_u s_d / s_f.  The output
 layer starts at zero: the untrained network reproduces the previous-step
 warm start exactly.
 
@@ -45,6 +50,9 @@ import numpy as np
 LEVELS = 4
 CH = 32
 IN_CH = 8
+# a plane whose last change is below this fraction of its RMS is static (its
+# change is the solver's own error): no extrapolation, correction or target
+STATIC = 1e-6
 
 
 def layer_shapes(levels=LEVELS, ch=CH, in_ch=IN_CH):
@@ -239,10 +247,14 @@ def loss(out, target):
 # The network is this build's addition to the paper's warm start (Sec. 5.1:
 # each multigrid solve starts from the previous time step's solution).  For
 # the low modes 0..m_max the solve may instead start from
-#   cand = u_{t-1} + s_o * net(x),
-# whichever of the two has the smaller volume-weighted defect norm after one
+#   cand = u_{t-1} + (u_{t-1} - u_{t-2}) + s_o * net(x)
+# (the linear extrapolation of the last two solutions plus the network's
+# correction; without u_{t-2}, u_{t-1} + s_o * net(x)), whichever of cand
+# and u_{t-1} has the smaller volume-weighted defect norm after one
 # smoothing step of each (the multigrid removes the rough part of any error
-# in its first sweep; what is left decides the cycle count).
+# in its first sweep; what is left decides the cycle count).  The network
+# is trained on the correction the candidate needs,
+# (u_t - u_{t-1} - (u_{t-1} - u_{t-2})) / s_o.
 def image_mode(k):
     """Real image k -> (mode m, part): 0 -> (0, real); 2m - 1 -> (m, real);
     2m -> (m, imaginary)."""
@@ -262,7 +274,9 @@ def guess_images(f, fprev, uprev, m_max, uprev2=None):
     (optional) the solution of the step before that.  Returns
     x (2 m_max + 1, n_a, n_b, 8) and sc (2 m_max + 1, 4) = (s_f, s_d, s_u,
     s_o) per image, the RMS values of f, f - fprev and uprev over the plane
-    (1 where zero) and s_o = s_u s_d / s_f."""
+    (1 where zero) and the output scale s_o: the RMS of uprev - uprev2 when
+    uprev2 is given (the size of the last change; 0 marks a static plane,
+    one whose change is below STATIC of its RMS), else s_u s_d / s_f."""
     n_img = 2 * m_max + 1
     na, nb = f.shape[1], f.shape[2]
     x = np.zeros((n_img, na, nb, 8))
@@ -274,22 +288,37 @@ def guess_images(f, fprev, uprev, m_max, uprev2=None):
         fv, fp, uv = _part(f[m], im), _part(fprev[m], im), _part(uprev[m], im)
         s = [float(np.sqrt(np.mean(v * v))) for v in (fv, fv - fp, uv)]
         s = [v if v > 0.0 else 1.0 for v in s]
-        sc[k] = (s[0], s[1], s[2], s[2] * s[1] / s[0])
+        so = s[2] * s[1] / s[0]
+        if uprev2 is not None:
+            e = uv - _part(uprev2[m], im)
+            so = float(np.sqrt(np.mean(e * e)))
+            so = so if so > STATIC * s[2] else 0.0      # static plane: marked by s_o = 0
+        sc[k] = (s[0], s[1], s[2], so)
         x[k, :, :, 0] = fv / s[0]
         x[k, :, :, 1] = (fv - fp) / s[1]
         x[k, :, :, 2] = uv / s[2]
         x[k, :, :, 3] = m / 4.0
         x[k, :, :, 4] = ci[:, None]
         x[k, :, :, 5] = cj[None, :]
-        if uprev2 is not None:
-            x[k, :, :, 6] = (uv - _part(uprev2[m], im)) / sc[k, 3]
+        if uprev2 is not None and sc[k, 3] > 0.0:
+            d = (uprev[m] - uprev2[m]) / sc[k, 3]
+            x[k, :, :, 6] = _part(d, im)
+            if m > 0:
+                x[k, :, :, 7] = _part(-1j * d, im)
     return x, sc
 
 
-def guess_candidate(uprev, y, sc, m_max):
-    """cand = u_{t-1} + s_o y per real image (the imaginary part of m = 0 is
-    kept)."""
+def guess_candidate(uprev, y, sc, m_max, uprev2=None):
+    """cand = u_{t-1} + (u_{t-1} - u_{t-2}) + s_o y per real image (no
+    extrapolation without uprev2; the imaginary part of m = 0 is only
+    extrapolated)."""
     cand = np.array(uprev[:m_max + 1], dtype=np.complex128)
+    if uprev2 is not None:
+        for m in range(m_max + 1):
+            kr = 0 if m == 0 else 2 * m - 1
+            ki = kr if m == 0 else 2 * m            # m = 0: the imaginary part follows the real image
+            d = cand[m] - np.asarray(uprev2[m], dtype=np.complex128)
+            cand[m] = cand[m] + (d.real if sc[kr, 3] > 0.0 else 0.0) + 1j * (d.imag if sc[ki, 3] > 0.0 else 0.0)
     for k in range(2 * m_max + 1):
         m, im = image_mode(k)
         if im:
@@ -297,6 +326,19 @@ def guess_candidate(uprev, y, sc, m_max):
         else:
             cand[m] = cand[m] + sc[k, 3] * y[k]
     return cand
+
+
+def guess_target(u, uprev, sc, m_max, uprev2=None):
+    """The training target of each real image: the correction the candidate
+    needs to become u_t, (u_t - u_{t-1} - (u_{t-1} - u_{t-2})) / s_o."""
+    out = np.zeros((2 * m_max + 1,) + u.shape[1:])
+    for k in range(2 * m_max + 1):
+        m, im = image_mode(k)
+        d = _part(u[m], im) - _part(uprev[m], im)
+        if uprev2 is not None:
+            d = d - (_part(uprev[m], im) - _part(uprev2[m], im))
+        out[k] = d / sc[k, 3] if sc[k, 3] > 0.0 else 0.0
+    return out
 
 
 def guess_judge(level, f, cand, uprev, m_max, n_sor=2, line_solver="sor"):

@@ -186,7 +186,7 @@ struct PlanNet {
   char* work = nullptr;
   NetWork wl{};
   size_t o_fprev[2] = {0, 0}, o_uprev[2] = {0, 0}, o_uprev2[2] = {0, 0}, o_cand = 0, o_cs = 0, o_us = 0, o_u2 = 0,
-         o_sc = 0, o_part = 0, o_used = 0, o_jobs = 0, o_lv = 0, o_list = 0, o_rec = 0, bytes = 0;
+         o_sc = 0, o_part = 0, o_used = 0, o_jobs = 0, o_lv = 0, o_list = 0, o_rec = 0, o_rec0 = 0, bytes = 0;
   std::vector<NormJob> hjobs;  // [target][smoothed candidate, smoothed previous solution]
   std::vector<LvJob> hlv;      // [target][the same two arrays]: one smoothing step
   bool prev_ok[2] = {false, false};
@@ -926,12 +926,16 @@ static smg_status james_steps(smg_plan* p, const double2* psi, const double2* f,
 
 // Per-cycle plane counts of a solve from the per-mode cycle counts of the
 // previous one: cycle k runs on the modes that needed more than k cycles.
+// Every mode is given one cycle more than it needed last time: a mode
+// that converged early drops out of the device list (its blocks return at
+// once), while one cycle too few would send the whole solve back to the
+// host loop.
 static std::vector<int> schedule_of(const std::vector<int>& cyc) {
   int mx = 0;
   for (int c : cyc) mx = std::max(mx, c);
-  std::vector<int> caps(mx, 0);
+  std::vector<int> caps(mx + 1, 0);
   for (int c : cyc)
-    for (int k = 0; k < c; ++k) caps[k] += 1;
+    for (int k = 0; k < c + 1; ++k) caps[k] += 1;
   return caps;
 }
 
@@ -949,9 +953,10 @@ static const double2* target_f(const smg_plan* p, int t) { return p->dptr(t == 0
 static double2* target_u(const smg_plan* p, int t) { return p->dptr(t == 0 ? p->w_psi : p->w_phi); }
 
 // Before solve t of a warm start: the network inputs of modes 0..m_max;
-// with `guess`, the candidate u_prev + s_o net(x) replaces the previous
-// step's solution in every mode where, after one smoothing step of each,
-// its defect norm is the smaller one.
+// with `guess`, the candidate (the linear extrapolation of the last two
+// solutions plus s_o net(x)) replaces the previous step's solution in every
+// mode where, after one smoothing step of each, its defect norm is the
+// smaller one.
 static smg_status net_before(smg_plan* p, int t, bool warm, bool guess, hipStream_t st) {
   PlanNet& pn = p->pn;
   if (!pn.net || !warm || !pn.prev_ok[t]) return SMG_OK;
@@ -965,13 +970,14 @@ static smg_status net_before(smg_plan* p, int t, bool warm, bool guess, hipStrea
   // the solution of the step before the previous one
   if (pn.prev2_ok[t]) HIPCHK(smgk::copy_planes(uprev2, uprev, np, st));
   HIPCHK(smgk::copy_planes(uprev, target_u(p, t), np, st));
-  HIPCHK(smgg::scales(target_f(p, t), fprev, uprev, plane, pn.n_img, sc, st));
+  HIPCHK(smgg::scales(target_f(p, t), fprev, uprev, pn.prev2_ok[t] ? uprev2 : nullptr, plane, pn.n_img, sc, st));
   HIPCHK(smgg::assemble(target_f(p, t), fprev, uprev, pn.prev2_ok[t] ? uprev2 : nullptr, sc, p->spec.n_a, p->spec.n_b,
                         pn.n_img, reinterpret_cast<float*>(pn.work + pn.wl.x32), st));
   if (!guess) return SMG_OK;
   STCHK(pn.net->def.forward(pn.work, pn.wl, st));
   double2* cand = reinterpret_cast<double2*>(pn.work + pn.o_cand);
-  HIPCHK(smgg::candidate(uprev, reinterpret_cast<const float*>(pn.work + pn.wl.y), sc, plane, pn.m_max, cand, st));
+  HIPCHK(smgg::candidate(uprev, pn.prev2_ok[t] ? uprev2 : nullptr, reinterpret_cast<const float*>(pn.work + pn.wl.y), sc,
+                         plane, pn.m_max, cand, st));
   // judge: defect norms after one smoothing step of each candidate (the
   // smoothing removes the rough part of an error, which the multigrid
   // removes in its first sweep anyway; what is left decides the cycles)
@@ -993,15 +999,19 @@ static smg_status net_before(smg_plan* p, int t, bool warm, bool guess, hipStrea
   return SMG_OK;
 }
 
-// After solve t: a training sample per image when recording, and this
-// step's right-hand side kept for the next step's inputs.
+// After solve t: a training sample per image when recording (from the
+// third step of a sequence on), and this step's right-hand side kept for
+// the next step's inputs.
 static smg_status net_after(smg_plan* p, int t, bool warm, hipStream_t st) {
   PlanNet& pn = p->pn;
   if (!pn.net) return SMG_OK;
   const int plane = p->spec.n_a * p->spec.n_b;
-  if (warm && pn.prev_ok[t] && pn.samples)
+  // samples only where the candidate extrapolates (two solutions back
+  // exist): the network learns one kind of correction
+  if (warm && pn.prev_ok[t] && pn.prev2_ok[t] && pn.samples)
     HIPCHK(smgg::record(reinterpret_cast<const float*>(pn.work + pn.wl.x32), target_u(p, t),
                         reinterpret_cast<const double2*>(pn.work + pn.o_uprev[t]),
+                        pn.prev2_ok[t] ? reinterpret_cast<const double2*>(pn.work + pn.o_uprev2[t]) : nullptr,
                         reinterpret_cast<const double*>(pn.work + pn.o_sc), plane, pn.n_img,
                         reinterpret_cast<int*>(pn.work + pn.o_rec), pn.capacity, pn.samples, st));
   HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_fprev[t]), target_f(p, t),
@@ -1020,6 +1030,9 @@ static smg_status group_body(Group& g, double tol, bool warm, unsigned flags, co
                              const std::vector<int>* sched1, hipStream_t st, hipEvent_t* ev) {
   Engine& e = *g.eng;
   const bool guess = (flags & SMG_NET_GUESS) != 0;
+  for (smg_plan* p : g.plans)  // samples of a solve the host has to finish are withdrawn (group_solve)
+    if (p->pn.net && p->pn.samples)
+      HIPCHK(hipMemcpyAsync(p->pn.work + p->pn.o_rec0, p->pn.work + p->pn.o_rec, sizeof(int), hipMemcpyDeviceToDevice, st));
   for (smg_plan* p : g.plans) STCHK(net_before(p, 0, warm, guess, st));
   STCHK(e.start(0, tol, kFloor, warm, g.max_cycles, st));
   if (sched0) {
@@ -1184,6 +1197,11 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
   Engine::State es;
   STCHK(e.read_all(st, &es));
   if (es.count[0] > 0 || es.count[1] > 0) {
+    // the training samples recorded in the body came from unfinished solves
+    for (smg_plan* p : g.plans)
+      if (p->pn.net && p->pn.samples)
+        HIPCHK(hipMemcpyAsync(p->pn.work + p->pn.o_rec, p->pn.work + p->pn.o_rec0, sizeof(int), hipMemcpyDeviceToDevice,
+                              st));
     if (es.count[0] > 0) {
       STCHK(e.finish_dynamic(0, st, nullptr));
       STCHK(james_all(g, st));
@@ -1275,6 +1293,7 @@ static smg_status net_layout(const smg_plan* p, const smg_net* net, int m_max, P
   pn.o_lv = take(sizeof(LvJob) * 4);
   pn.o_list = take(sizeof(int) * (m_max + 1));
   pn.o_rec = take(sizeof(int));
+  pn.o_rec0 = take(sizeof(int));   // the count when the current solve started
   pn.bytes = off;
   return SMG_OK;
 }

@@ -6,16 +6,18 @@
 namespace smgg {
 // images: 0 = re(m=0); 2m-1 = re(m), 2m = im(m) for m = 1..m_max (n_img = 2 m_max + 1)
 // sc[4 k + (0, 1, 2, 3)] = (s_f, s_d, s_u, s_o) per image: RMS of f_t, of
-// f_t - f_prev, of u_prev, and s_u s_d / s_f (the output scale)
-hipError_t scales(const double2* f, const double2* fprev, const double2* uprev, int plane, int n_img, double* sc,
-                  hipStream_t st);
+// f_t - f_prev, of u_prev, and the output scale s_o: the RMS of
+// u_prev - u_prev2 (uprev2 given) or s_u s_d / s_f
+hipError_t scales(const double2* f, const double2* fprev, const double2* uprev, const double2* uprev2, int plane, int n_img,
+                  double* sc, hipStream_t st);
 // uprev2: the solution two steps back (channel 6 = (uprev - uprev2) / s_o), or null
 hipError_t assemble(const double2* f, const double2* fprev, const double2* uprev, const double2* uprev2, const double* sc,
                     int na, int nb, int n_img, float* x, hipStream_t st);
-hipError_t candidate(const double2* uprev, const float* y, const double* sc, int plane, int m_max, double2* cand,
-                     hipStream_t st);
+// cand = uprev + (uprev - uprev2 if uprev2) + s_o y
+hipError_t candidate(const double2* uprev, const double2* uprev2, const float* y, const double* sc, int plane, int m_max,
+                     double2* cand, hipStream_t st);
 hipError_t select(const double* pc, const double* pu, int nblk, const double2* cand, double2* u, int plane, int m_max,
                   int* used, hipStream_t st);
-hipError_t record(const float* x, const double2* u, const double2* uprev, const double* sc, int plane, int n_img,
-                  int* count, int capacity, float* samples, hipStream_t st);
+hipError_t record(const float* x, const double2* u, const double2* uprev, const double2* uprev2, const double* sc,
+                  int plane, int n_img, int* count, int capacity, float* samples, hipStream_t st);
 }  // namespace smgg

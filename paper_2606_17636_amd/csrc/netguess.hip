@@ -1,11 +1,14 @@
 // The learned guess inside a solve: network inputs from the mode planes of
 // modes 0..m_max (one image per real or imaginary part), the candidate
-// u_prev + s_u * net(x), the choice per mode between it and the previous
+// (linear extrapolation of the last two solutions + s_o * net(x)), the choice per mode between it and the previous
 // step's solution by their defect norms, training-sample recording, and the
 // bookkeeping of the previous step's right-hand side.
 #include "netguess.h"
 
 namespace {
+
+// relative size of the last change below which a plane counts as static
+constexpr double kStatic = 1e-6;
 
 __device__ __forceinline__ double part_of(double2 v, int im) { return im ? v.y : v.x; }
 
@@ -16,48 +19,61 @@ __device__ __forceinline__ void image_mode(int k, int* m, int* im) {
 }
 
 // per image: RMS of f_t, of f_t - f_prev and of u_prev, and the output
-// scale: sc = (s_f, s_d, s_u, s_o) with s_o = s_u s_d / s_f (the size the
-// change of u takes when it follows the change of f); 1 where zero
+// scale: sc = (s_f, s_d, s_u, s_o) with s_o the RMS of u_prev - u_prev2
+// (the size of the last change of u) when u_prev2 is given, else
+// s_u s_d / s_f (the size the change of u takes when it follows the change
+// of f); 1 where zero
 __global__ void k_scales(const double2* __restrict__ f, const double2* __restrict__ fprev,
-                         const double2* __restrict__ uprev, int plane, double* __restrict__ sc) {
-  __shared__ double red[3][256];
+                         const double2* __restrict__ uprev, const double2* __restrict__ uprev2, int plane,
+                         double* __restrict__ sc) {
+  __shared__ double red[4][256];
   int m, im;
   image_mode(blockIdx.x, &m, &im);
-  double a = 0.0, b = 0.0, c = 0.0;
+  double a = 0.0, b = 0.0, c = 0.0, e = 0.0;
   for (int t = threadIdx.x; t < plane; t += blockDim.x) {
     const double fv = part_of(f[(size_t)m * plane + t], im), uv = part_of(uprev[(size_t)m * plane + t], im);
     const double dv = fv - part_of(fprev[(size_t)m * plane + t], im);
     a += fv * fv;
     b += dv * dv;
     c += uv * uv;
+    if (uprev2) {
+      const double ev = uv - part_of(uprev2[(size_t)m * plane + t], im);
+      e += ev * ev;
+    }
   }
   red[0][threadIdx.x] = a;
   red[1][threadIdx.x] = b;
   red[2][threadIdx.x] = c;
+  red[3][threadIdx.x] = e;
   __syncthreads();
   for (int o = blockDim.x / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o)
-      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
+      for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     double sf = sqrt(red[0][0] / plane), sd = sqrt(red[1][0] / plane), su = sqrt(red[2][0] / plane);
+    const double se = sqrt(red[3][0] / plane);
     sf = sf > 0.0 ? sf : 1.0;
     sd = sd > 0.0 ? sd : 1.0;
     su = su > 0.0 ? su : 1.0;
     sc[4 * blockIdx.x] = sf;
     sc[4 * blockIdx.x + 1] = sd;
     sc[4 * blockIdx.x + 2] = su;
-    sc[4 * blockIdx.x + 3] = su * sd / sf;
+    // a plane whose last change is at the level of the solve's own error
+    // (below 1e-6 of the plane) is static: s_o = 0 marks it (no
+    // extrapolation, no correction, no change channel, zero target)
+    sc[4 * blockIdx.x + 3] = uprev2 ? (se > kStatic * su ? se : 0.0) : su * sd / sf;
   }
 }
 
 // x[k][i][j][0..7] = (f_t / s_f, (f_t - f_prev) / s_d, u_prev / s_u, m / 4,
 //                     (i + 1/2) / n_a - 1/2, (j + 1/2) / n_b - 1/2,
-//                     (u_prev - u_prev2) / s_o, 0)
+//                     this part of (u_prev - u_prev2) / s_o,
+//                     this part of -i (u_prev - u_prev2) / s_o)
 // (channels 4, 5 tell the convolutions where on the grid they are;
-// channel 6, the previous step's change of the solution, is zero when
-// uprev2 is null: no solution two steps back)
+// channels 6, 7, the previous step's change of the solution, are zero when
+// uprev2 is null or the plane is static)
 __global__ void k_assemble(const double2* __restrict__ f, const double2* __restrict__ fprev,
                            const double2* __restrict__ uprev, const double2* __restrict__ uprev2,
                            const double* __restrict__ sc, int na, int nb, int n_img, float* __restrict__ x) {
@@ -71,25 +87,45 @@ __global__ void k_assemble(const double2* __restrict__ f, const double2* __restr
     const double fp = part_of(fprev[(size_t)m * plane + q], im);
     const double uv = part_of(uprev[(size_t)m * plane + q], im);
     const double sf = sc[4 * k], sd = sc[4 * k + 1], su = sc[4 * k + 2], so = sc[4 * k + 3];
-    const double dv = uprev2 ? (uv - part_of(uprev2[(size_t)m * plane + q], im)) / so : 0.0;
+    // the last change of u and of the partner part, as the corresponding
+    // part of -i (u_prev - u_prev2): a rotation of the mode by a small
+    // angle changes each part by that angle times it (zero for m = 0)
+    double dv = 0.0, dr = 0.0;
+    if (uprev2 && so > 0.0) {
+      const double2 d2 = uprev[(size_t)m * plane + q], w2 = uprev2[(size_t)m * plane + q];
+      const double re = d2.x - w2.x, imv = d2.y - w2.y;
+      dv = (im ? imv : re) / so;
+      dr = m > 0 ? (im ? -re : imv) / so : 0.0;
+    }
     const int i = q / nb, j = q - i * nb;
     float4* xo = reinterpret_cast<float4*>(x) + 2 * t;
     xo[0] = make_float4((float)(fv / sf), (float)((fv - fp) / sd), (float)(uv / su), 0.25f * (float)m);
-    xo[1] = make_float4((i + 0.5f) / na - 0.5f, (j + 0.5f) / nb - 0.5f, (float)dv, 0.f);
+    xo[1] = make_float4((i + 0.5f) / na - 0.5f, (j + 0.5f) / nb - 0.5f, (float)dv, (float)dr);
   }
 }
 
-// cand = u_prev + s_o * y, both parts of modes 0..m_max (m = 0 keeps its
-// imaginary part)
-__global__ void k_candidate(const double2* __restrict__ uprev, const float* __restrict__ y, const double* __restrict__ sc,
-                            int plane, int m_max, double2* __restrict__ cand) {
+// cand = u_prev + (u_prev - u_prev2) + s_o * y: the linear extrapolation
+// of the last two solutions (u_prev alone when there is no u_prev2) plus
+// the network's correction, both parts of modes 0..m_max (m = 0 has no
+// imaginary image: its imaginary part is only extrapolated)
+__global__ void k_candidate(const double2* __restrict__ uprev, const double2* __restrict__ uprev2,
+                            const float* __restrict__ y, const double* __restrict__ sc, int plane, int m_max,
+                            double2* __restrict__ cand) {
   const size_t total = (size_t)(m_max + 1) * plane;
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
     const int m = (int)(t / plane), q = (int)(t - (size_t)m * plane);
     double2 v = uprev[t];
     const int kr = m == 0 ? 0 : 2 * m - 1;
-    v.x += sc[4 * kr + 3] * (double)y[(size_t)kr * plane + q];
-    if (m > 0) v.y += sc[4 * (2 * m) + 3] * (double)y[(size_t)(2 * m) * plane + q];
+    // static parts (s_o = 0) keep u_prev; the imaginary part of m = 0 has no
+    // image and follows the real part's kind
+    const double sr = sc[4 * kr + 3], si = m > 0 ? sc[4 * (2 * m) + 3] : sr;
+    if (uprev2) {
+      const double2 w = uprev2[t];
+      if (sr > 0.0) v.x += v.x - w.x;
+      if (si > 0.0) v.y += v.y - w.y;
+    }
+    v.x += sr * (double)y[(size_t)kr * plane + q];
+    if (m > 0) v.y += si * (double)y[(size_t)(2 * m) * plane + q];
     cand[t] = v;
   }
 }
@@ -113,11 +149,12 @@ __global__ void k_select(const double* __restrict__ pc, const double* __restrict
   for (int t = threadIdx.x; t < plane; t += blockDim.x) u[(size_t)m * plane + t] = cand[(size_t)m * plane + t];
 }
 
-// training samples: (x, (u_t - u_prev) / s_o) per image at list position
-// *count + k while below capacity
+// training samples: (x, (u_t - u_prev - (u_prev - u_prev2)) / s_o) per
+// image (the correction the candidate needs; without u_prev2 the change
+// u_t - u_prev) at list position *count + k while below capacity
 __global__ void k_record(const float* __restrict__ x, const double2* __restrict__ u, const double2* __restrict__ uprev,
-                         const double* __restrict__ sc, int plane, int n_img, const int* __restrict__ count, int capacity,
-                         float* __restrict__ samples) {
+                         const double2* __restrict__ uprev2, const double* __restrict__ sc, int plane, int n_img,
+                         const int* __restrict__ count, int capacity, float* __restrict__ samples) {
   const int base = *count;
   const size_t total = (size_t)n_img * plane;
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
@@ -128,8 +165,10 @@ __global__ void k_record(const float* __restrict__ x, const double2* __restrict_
     float* s = samples + (size_t)(base + k) * plane * 9;
     reinterpret_cast<float4*>(s)[2 * q] = reinterpret_cast<const float4*>(x)[2 * t];
     reinterpret_cast<float4*>(s)[2 * q + 1] = reinterpret_cast<const float4*>(x)[2 * t + 1];
-    const double d = part_of(u[(size_t)m * plane + q], im) - part_of(uprev[(size_t)m * plane + q], im);
-    s[(size_t)plane * 8 + q] = (float)(d / sc[4 * k + 3]);
+    const double up = part_of(uprev[(size_t)m * plane + q], im), so = sc[4 * k + 3];
+    double d = part_of(u[(size_t)m * plane + q], im) - up;
+    if (uprev2) d -= up - part_of(uprev2[(size_t)m * plane + q], im);
+    s[(size_t)plane * 8 + q] = so > 0.0 ? (float)(d / so) : 0.f;
   }
 }
 
@@ -146,9 +185,9 @@ unsigned grid1(size_t n) {
 
 namespace smgg {
 
-hipError_t scales(const double2* f, const double2* fprev, const double2* uprev, int plane, int n_img, double* sc,
-                  hipStream_t st) {
-  hipLaunchKernelGGL(k_scales, dim3(n_img), dim3(256), 0, st, f, fprev, uprev, plane, sc);
+hipError_t scales(const double2* f, const double2* fprev, const double2* uprev, const double2* uprev2, int plane, int n_img,
+                  double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_scales, dim3(n_img), dim3(256), 0, st, f, fprev, uprev, uprev2, plane, sc);
   return hipGetLastError();
 }
 
@@ -159,10 +198,10 @@ hipError_t assemble(const double2* f, const double2* fprev, const double2* uprev
   return hipGetLastError();
 }
 
-hipError_t candidate(const double2* uprev, const float* y, const double* sc, int plane, int m_max, double2* cand,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_candidate, dim3(grid1((size_t)(m_max + 1) * plane)), dim3(256), 0, st, uprev, y, sc, plane, m_max,
-                     cand);
+hipError_t candidate(const double2* uprev, const double2* uprev2, const float* y, const double* sc, int plane, int m_max,
+                     double2* cand, hipStream_t st) {
+  hipLaunchKernelGGL(k_candidate, dim3(grid1((size_t)(m_max + 1) * plane)), dim3(256), 0, st, uprev, uprev2, y, sc, plane,
+                     m_max, cand);
   return hipGetLastError();
 }
 
@@ -172,10 +211,10 @@ hipError_t select(const double* pc, const double* pu, int nblk, const double2* c
   return hipGetLastError();
 }
 
-hipError_t record(const float* x, const double2* u, const double2* uprev, const double* sc, int plane, int n_img,
-                  int* count, int capacity, float* samples, hipStream_t st) {
-  hipLaunchKernelGGL(k_record, dim3(grid1((size_t)n_img * plane)), dim3(256), 0, st, x, u, uprev, sc, plane, n_img, count,
-                     capacity, samples);
+hipError_t record(const float* x, const double2* u, const double2* uprev, const double2* uprev2, const double* sc,
+                  int plane, int n_img, int* count, int capacity, float* samples, hipStream_t st) {
+  hipLaunchKernelGGL(k_record, dim3(grid1((size_t)n_img * plane)), dim3(256), 0, st, x, u, uprev, uprev2, sc, plane, n_img,
+                     count, capacity, samples);
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, count, n_img, capacity);
   return hipGetLastError();
 }

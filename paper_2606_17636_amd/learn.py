@@ -15,7 +15,8 @@ from . import smg
 
 
 def samples_per_step(m_max):
-    """Samples one warm-started solve records: 2 multigrid solves x (2 m_max + 1) real images."""
+    """Samples one warm-started solve records (from the third solve of a
+    sequence on): 2 multigrid solves x (2 m_max + 1) real images."""
     return 2 * (2 * m_max + 1)
 
 

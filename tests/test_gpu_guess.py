@@ -99,25 +99,39 @@ def test_guess_candidate_and_judge_match_oracle():
     bias = 0.5
     c["net"].set_params(_constant_output_params(bias))
     lev = MGLevel(SPEC, 0)
+    rng = np.random.default_rng(24)
     for t, (f, fp, ut) in enumerate(((c["f1"], c["f0"], c["u1"]), (c["f1"] * 0.7, c["f0"] * 0.7, c["u1"] * 0.7))):
         # previous solutions: the exact solution of f for modes 1 and 3; for
-        # modes 0, 2, 4 the exact solution minus the constant the candidate
-        # adds back (fixed point of uprev = u - s_o(uprev) * bias), so the
-        # candidate is the better start there and the worse one elsewhere
+        # modes 0, 2, 4 the exact solution minus what the candidate adds back,
+        # so the candidate is the better start there and the worse one
+        # elsewhere.  t = 0: no solution two steps back, the candidate adds
+        # s_o(uprev) * bias (a fixed point in uprev); t = 1: uprev2 = uprev -
+        # delta, the candidate adds delta + RMS(delta) * bias
         up = np.array(ut[:M_MAX + 1])
-        for _ in range(30):
-            _, sc = onet.guess_images(f, fp, up, M_MAX)
+        up2 = None
+        if t == 1:
+            delta = 1e-3 * np.abs(ut).max() * (rng.standard_normal(up.shape) + 1j * rng.standard_normal(up.shape))
+            delta[0] = delta[0].real
+            rms = lambda v: float(np.sqrt(np.mean(v * v)))
             for m in (0, 2, 4):
-                kr = 0 if m == 0 else 2 * m - 1
-                shift = sc[kr, 3] * bias + (1j * sc[2 * m, 3] * bias if m else 1j * 0.0)
-                up[m] = ut[m] - shift
-                if m == 0:
-                    up[0] = up[0].real + 1j * ut[0].imag
+                up[m] = ut[m] - delta[m] - bias * rms(delta[m].real)
+                if m:
+                    up[m] -= 1j * bias * rms(delta[m].imag)
+            up2 = up - delta
+        else:
+            for _ in range(30):
+                _, sc = onet.guess_images(f, fp, up, M_MAX)
+                for m in (0, 2, 4):
+                    kr = 0 if m == 0 else 2 * m - 1
+                    shift = sc[kr, 3] * bias + (1j * sc[2 * m, 3] * bias if m else 1j * 0.0)
+                    up[m] = ut[m] - shift
+                    if m == 0:
+                        up[0] = up[0].real + 1j * ut[0].imag
         print(f"[case] candidate and judge, t={t}", flush=True)
-        guess, _, y, used = c["p"].net_guess_step(t, _dev(f), _dev(fp), _dev(up))
+        guess, _, y, used = c["p"].net_guess_step(t, _dev(f), _dev(fp), _dev(up), None if up2 is None else _dev(up2))
         assert np.all(y.cpu().numpy() == np.float32(bias))
-        _, sc = onet.guess_images(f, fp, up, M_MAX)
-        cand = onet.guess_candidate(up, np.full((2 * M_MAX + 1,) + up.shape[1:], bias), sc, M_MAX)
+        _, sc = onet.guess_images(f, fp, up, M_MAX, uprev2=up2)
+        cand = onet.guess_candidate(up, np.full((2 * M_MAX + 1,) + up.shape[1:], bias), sc, M_MAX, uprev2=up2)
         uo, nc, nu = onet.guess_judge(lev, f, cand, up, M_MAX)
         margin = np.abs(nc - nu) / np.maximum(nc, nu)
         print("oracle judge", list(uo), "margins", margin, "gpu", list(used), flush=True)
@@ -129,6 +143,32 @@ def test_guess_candidate_and_judge_match_oracle():
                 assert np.abs(g[m] - cand[m]).max() <= 1e-12 * np.abs(cand[m]).max(), m
             else:
                 assert np.array_equal(g[m], up[m]), m
+
+
+def test_untrained_network_extrapolates():
+    """With a zero output layer the candidate is the linear extrapolation of
+    the last two solutions, 2 u_{t-1} - u_{t-2}: on a smooth trajectory it is
+    the better start for the modes that change (m >= 1 here; m = 0 of the
+    orbiting blobs does not change, so the previous solution is exact and
+    kept), and the step returns it to FP64 rounding."""
+    c = _setup()
+    c["net"].set_params(init_params(23, zero_output=True))
+    lev = MGLevel(SPEC, 0)
+    print("[case] untrained network, extrapolation", flush=True)
+    guess, _, y, used = c["p"].net_guess_step(0, _dev(c["f1"]), _dev(c["f0"]), _dev(c["u0"]), _dev(c["um"]))
+    assert np.all(y.cpu().numpy() == 0.0)
+    _, sc = onet.guess_images(c["f1"], c["f0"], c["u0"], M_MAX, uprev2=c["um"])
+    cand = onet.guess_candidate(c["u0"], np.zeros((2 * M_MAX + 1,) + c["u0"].shape[1:]), sc, M_MAX, uprev2=c["um"])
+    uo, nc, nu = onet.guess_judge(lev, c["f1"], cand, c["u0"][:M_MAX + 1], M_MAX)
+    margin = np.abs(nc - nu) / np.maximum(nc, nu)
+    print("oracle judge", list(uo), "margins", margin, "gpu", list(used), flush=True)
+    g = guess.cpu().numpy()
+    for m in range(M_MAX + 1):
+        if margin[m] > 1e-6:
+            assert used[m] == uo[m], m
+        ref = cand[m] if used[m] else c["u0"][m]
+        assert np.abs(g[m] - ref).max() <= 1e-13 * np.abs(ref).max(), m
+    assert list(uo[1:]) == [1] * M_MAX
 
 
 def test_trained_trajectory_matches_oracle():
@@ -152,7 +192,7 @@ def test_trained_trajectory_matches_oracle():
     print(f"[setup] trajectory {spec}", flush=True)
     rec = smg.grid_from_spec(spec, precision="fp64").setup().attach_net(net, M_MAX)
     steps = 16
-    cap = 3 * (steps - 1) * learn.samples_per_step(M_MAX)
+    cap = 3 * (steps - 2) * learn.samples_per_step(M_MAX)
     buf = learn.sample_buffer(rec, cap)
     n, _ = learn.record_trajectories(rec, [traj(s, steps) for s in (50, 51, 52)], 1e-10, buf, cap)
     learn.train(net, buf, n, spec.n_a, spec.n_b, steps=300, batch=16, lr=1e-3, seed=3)

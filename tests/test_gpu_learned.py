@@ -48,7 +48,12 @@ def _l2(x, ref):
     return math.sqrt(np.sum((x - ref) ** 2 * w) / np.sum(ref**2 * w))
 
 
-def test_untrained_net_equals_previous_step_guess():
+def test_untrained_net_first_step_equals_previous_step_guess():
+    """Before a solution two steps back exists, the untrained network's
+    candidate (zero output layer, no extrapolation) is exactly the previous
+    step's solution, so the first warm solve equals the plain warm start
+    bit for bit; later warm solves start from the extrapolation where the
+    judge takes it and meet the same tolerance."""
     from paper_2606_17636_amd import smg
     net = smg.Net()
     net.set_params(init_params(1))
@@ -57,8 +62,12 @@ def test_untrained_net_equals_previous_step_guess():
     for k, rho in enumerate(_traj(5, 5)):
         pa, ia = a.solve(rho, tol=1e-9, warm=k > 0, net=True)
         pb, ib = b.solve(rho, tol=1e-9, warm=k > 0)
-        assert np.array_equal(ia["cycles1"], ib["cycles1"]), k
-        assert torch.equal(pa, pb), k
+        assert ia["converged"] and ib["converged"], k
+        if k <= 1:
+            assert np.array_equal(ia["cycles1"], ib["cycles1"]), k
+            assert torch.equal(pa, pb), k
+        else:
+            assert _l2(pa.cpu().numpy(), pb.cpu().numpy()) < 1e-7, k
 
 
 def test_trained_net_saves_low_mode_cycles():
@@ -67,7 +76,7 @@ def test_trained_net_saves_low_mode_cycles():
     net.set_params(init_params(2))
     rec = _plan(precision="fp64").attach_net(net, M_MAX)
     steps = 24
-    cap = 4 * (steps - 1) * learn.samples_per_step(M_MAX)
+    cap = 4 * (steps - 2) * learn.samples_per_step(M_MAX)
     buf = learn.sample_buffer(rec, cap)
     n, _ = learn.record_trajectories(rec, [_traj(s, steps) for s in (50, 51, 52, 53)], 1e-10, buf, cap)
     print("samples", n, flush=True)

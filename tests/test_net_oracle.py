@@ -108,18 +108,26 @@ def test_guess_images_layout_and_scaling():
         assert np.allclose(x[k, :, :, 2] * sc[k, 2], part(up[m]), rtol=1e-14, atol=0)
         assert np.allclose(np.sqrt(np.mean(x[k, :, :, :3] ** 2, axis=(0, 1))), 1.0, rtol=1e-13)
         assert np.all(x[k, :, :, 3] == m / 4.0)
-        assert abs(sc[k, 3] - sc[k, 2] * sc[k, 1] / sc[k, 0]) <= 1e-15 * sc[k, 3]
+        assert abs(sc[k, 3] - sc[k, 2] * sc[k, 1] / sc[k, 0]) <= 1e-15 * sc[k, 3]   # no u_{t-2}
     assert np.allclose(x[0, :, 0, 4], (np.arange(na) + 0.5) / na - 0.5)
     assert np.allclose(x[0, 0, :, 5], (np.arange(nb) + 0.5) / nb - 0.5)
     assert np.all(x[..., 6:] == 0.0)
     # channel 6: the previous change of the solution in units of the output scale
     u2 = _planes(rng, M, na, nb)
     x6, sc6 = net.guess_images(f, fp, up, m_max, uprev2=u2)
-    assert np.array_equal(x6[..., :6], x[..., :6]) and np.all(x6[..., 7] == 0.0)
+    assert np.array_equal(x6[..., :6], x[..., :6]) and np.all(x6[0, :, :, 7] == 0.0)
+    assert np.array_equal(sc6[:, :3], sc[:, :3])
     for k in range(2 * m_max + 1):
         m = (k + 1) // 2
         part = (lambda z: z.imag) if (k > 0 and k % 2 == 0) else (lambda z: z.real)
-        assert np.allclose(x6[k, :, :, 6] * sc6[k, 3], part(up[m]) - part(u2[m]), rtol=1e-13, atol=0)
+        e = part(up[m]) - part(u2[m])
+        assert abs(sc6[k, 3] - math.sqrt(np.mean(e * e))) <= 1e-14 * sc6[k, 3]
+        assert np.allclose(x6[k, :, :, 6] * sc6[k, 3], e, rtol=1e-13, atol=0)
+        assert abs(math.sqrt(np.mean(x6[k, :, :, 6] ** 2)) - 1.0) < 1e-13
+        if m > 0:   # channel 7: the other part, as a rotation generator -i d: (Im d, -Re d)
+            other = (up[m] - u2[m]).real if part(1j) != 0 else (up[m] - u2[m]).imag
+            sign = -1.0 if part(1j) != 0 else 1.0
+            assert np.allclose(x6[k, :, :, 7] * sc6[k, 3], sign * other, rtol=1e-13, atol=0)
     x2, _ = net.guess_images(3.5 * f, 3.5 * fp, -2.0 * up, m_max)
     assert np.allclose(x2[..., :2], x[..., :2], rtol=1e-13) and np.allclose(x2[..., 2], -x[..., 2], rtol=1e-13)
     # a zero plane keeps scale 1 (no division by zero)
@@ -129,18 +137,24 @@ def test_guess_images_layout_and_scaling():
 
 
 def test_guess_candidate_inverts_the_target():
-    """The training target is (u_t - u_{t-1}) / s_o per real image, so the
-    candidate built from a perfect prediction is u_t (the imaginary part of
-    m = 0 comes from u_{t-1})."""
+    """The training target is the correction the candidate needs, so the
+    candidate built from a perfect prediction is u_t -- with the
+    extrapolation from u_{t-2} and without it (the imaginary part of m = 0
+    is only extrapolated); a zero prediction gives the extrapolation
+    2 u_{t-1} - u_{t-2} itself."""
     rng = np.random.default_rng(41)
     M, na, nb, m_max = 6, 8, 6, 4
-    f, fp, up, ut = (_planes(rng, M, na, nb) for _ in range(4))
-    up[0] = up[0].real + 1j * ut[0].imag
-    _, sc = net.guess_images(f, fp, up, m_max)
-    y = np.stack([((ut[m] - up[m]).imag if (k > 0 and k % 2 == 0) else (ut[m] - up[m]).real) / sc[k, 3]
-                  for k, m in ((k, (k + 1) // 2) for k in range(2 * m_max + 1))])
-    cand = net.guess_candidate(up, y, sc, m_max)
-    assert np.allclose(cand, ut[:m_max + 1], rtol=0, atol=1e-13 * np.abs(ut).max())
+    f, fp, up, ut, u2 = (_planes(rng, M, na, nb) for _ in range(5))
+    for prev2 in (None, u2):
+        upk = up.copy()
+        ext = upk if prev2 is None else 2 * upk - prev2
+        upk[0] = upk[0].real + 1j * (ut[0].imag if prev2 is None else 0.5 * (ut[0].imag + prev2[0].imag))
+        _, sc = net.guess_images(f, fp, upk, m_max, uprev2=prev2)
+        y = net.guess_target(ut, upk, sc, m_max, uprev2=prev2)
+        cand = net.guess_candidate(upk, y, sc, m_max, uprev2=prev2)
+        assert np.allclose(cand, ut[:m_max + 1], rtol=0, atol=1e-13 * np.abs(ut).max())
+    zero = net.guess_candidate(up, np.zeros((2 * m_max + 1, na, nb)), sc, m_max, uprev2=u2)
+    assert np.allclose(zero, (2 * up - u2)[:m_max + 1], rtol=0, atol=1e-14 * np.abs(up).max())
 
 
 def test_guess_judge_prefers_the_better_start():
@@ -162,3 +176,19 @@ def test_guess_judge_prefers_the_better_start():
         used, nc, nu = net.guess_judge(lev, f, cand, prev, m_max, line_solver=ls)
         assert list(used) == [1, 0, 0], (ls, nc, nu)
         assert nc[2] == nu[2]
+
+
+def test_static_plane_is_left_alone():
+    """A plane whose last change is below STATIC of its size (the solver's
+    own error, e.g. the axisymmetric mode of rigidly orbiting blobs) is
+    static: s_o = 0, no change channel, no extrapolation, no correction and
+    a zero training target."""
+    rng = np.random.default_rng(43)
+    M, na, nb, m_max = 3, 8, 6, 2
+    f, fp, up, ut = (_planes(rng, M, na, nb) for _ in range(4))
+    u2 = up + 1e-9 * _planes(rng, M, na, nb)               # a change far below 1e-6 of the plane
+    x, sc = net.guess_images(f, fp, up, m_max, uprev2=u2)
+    assert np.all(sc[:, 3] == 0.0) and np.all(x[..., 6:] == 0.0)
+    y = rng.standard_normal((2 * m_max + 1, na, nb))
+    assert np.array_equal(net.guess_candidate(up, y, sc, m_max, uprev2=u2), up[:m_max + 1])
+    assert np.all(net.guess_target(ut, up, sc, m_max, uprev2=u2) == 0.0)
