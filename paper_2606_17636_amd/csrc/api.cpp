@@ -186,7 +186,7 @@ struct PlanNet {
   char* work = nullptr;
   NetWork wl{};
   size_t o_fprev[2] = {0, 0}, o_uprev[2] = {0, 0}, o_uprev2[2] = {0, 0}, o_cand = 0, o_cs = 0, o_us = 0, o_u2 = 0,
-         o_sc = 0, o_part = 0, o_used = 0, o_jobs = 0, o_lv = 0, o_list = 0, o_rec = 0, o_rec0 = 0, bytes = 0;
+         o_sc = 0, o_part = 0, o_used = 0, o_jobs = 0, o_lv = 0, o_list = 0, o_rec = 0, o_rec0 = 0, o_scpart = 0, bytes = 0;
   std::vector<NormJob> hjobs;  // [target][smoothed candidate, smoothed previous solution]
   std::vector<LvJob> hlv;      // [target][the same two arrays]: one smoothing step
   bool prev_ok[2] = {false, false};
@@ -970,11 +970,12 @@ static smg_status net_before(smg_plan* p, int t, bool warm, bool guess, hipStrea
   // the solution of the step before the previous one
   if (pn.prev2_ok[t]) HIPCHK(smgk::copy_planes(uprev2, uprev, np, st));
   HIPCHK(smgk::copy_planes(uprev, target_u(p, t), np, st));
-  HIPCHK(smgg::scales(target_f(p, t), fprev, uprev, pn.prev2_ok[t] ? uprev2 : nullptr, plane, pn.n_img, sc, st));
+  HIPCHK(smgg::scales(target_f(p, t), fprev, uprev, pn.prev2_ok[t] ? uprev2 : nullptr, plane, pn.n_img,
+                      reinterpret_cast<double*>(pn.work + pn.o_scpart), sc, st));
   HIPCHK(smgg::assemble(target_f(p, t), fprev, uprev, pn.prev2_ok[t] ? uprev2 : nullptr, sc, p->spec.n_a, p->spec.n_b,
                         pn.n_img, reinterpret_cast<float*>(pn.work + pn.wl.x32), st));
   if (!guess) return SMG_OK;
-  STCHK(pn.net->def.forward(pn.work, pn.wl, st));
+  STCHK(pn.net->def.forward(pn.work, pn.wl, st, false));
   double2* cand = reinterpret_cast<double2*>(pn.work + pn.o_cand);
   HIPCHK(smgg::candidate(uprev, pn.prev2_ok[t] ? uprev2 : nullptr, reinterpret_cast<const float*>(pn.work + pn.wl.y), sc,
                          plane, pn.m_max, cand, st));
@@ -1284,6 +1285,7 @@ static smg_status net_layout(const smg_plan* p, const smg_net* net, int m_max, P
   pn.o_us = take(sizeof(double2) * np);
   pn.o_u2 = take(sizeof(double2) * np);  // the smoother's second array (steps run one after another)
   pn.o_sc = take(sizeof(double) * 4 * pn.n_img);
+  pn.o_scpart = take(sizeof(double) * smgg::scales_partial_doubles(pn.n_img));
   NormJob hj{};
   hj.L = p->levels.empty() ? LevelDev{} : p->levels[0];
   pn.nblk = smgk::norm_blocks(&hj, 1);

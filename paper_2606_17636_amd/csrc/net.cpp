@@ -124,42 +124,51 @@ void NetDef::bind(char* s) {
 // ---------------------------------------------------------------------------
 // forward / backward
 // ---------------------------------------------------------------------------
-smg_status NetDef::forward(char* base, const NetWork& w, hipStream_t st) const {
+smg_status NetDef::forward(char* base, const NetWork& w, hipStream_t st, bool train) const {
   auto B = [&](size_t off) { return reinterpret_cast<unsigned short*>(base + off); };
   const int n = w.n;
   const size_t np0 = (size_t)n * w.H * w.W;
   NCHK(smgn::to_bf16(reinterpret_cast<const float*>(base + w.x32), B(w.xb), np0 * in_ch, st));
+  const NetLayer& LO = layers.back();
+  float* y = reinterpret_cast<float*>(base + w.y);
   int k = 0;
   for (int l = 0; l < levels; ++l) {
     const int H = w.H >> l, W = w.W >> l;
+    // level l > 0 reads the pooled copy its level above wrote with its output
     const unsigned short* in = l == 0 ? B(w.xb) : B(w.h[l]);
     const int ics = l == 0 ? in_ch : ch, cin = l == 0 ? in_ch : ch;
-    if (l > 0) {
-      // pool the previous encoder output (held in the skip half of its concat buffer)
-      NCHK(smgn::pool(B(w.cat[l - 1]) + ch, 2 * ch, B(w.h[l]), ch, ch, n, H * 2, W * 2, st));
-    }
     const NetLayer& L0 = layers[k];
     NCHK(smgn::conv3(in, ics, cin, pb + L0.w_off, p + L0.b_off, B(w.a[l]), ch, ch, nullptr, 0, true, n, H, W, st));
     const NetLayer& L1 = layers[k + 1];
-    unsigned short* e = l < levels - 1 ? B(w.cat[l]) + ch : B(w.ebot);
-    const int ecs = l < levels - 1 ? 2 * ch : ch;
-    NCHK(smgn::conv3(B(w.a[l]), ch, ch, pb + L1.w_off, p + L1.b_off, e, ecs, ch, nullptr, 0, true, n, H, W, st));
+    const bool last = l == levels - 1;
+    smgn::ConvIn I{B(w.a[l]), nullptr, ch, ch, pb + L1.w_off, p + L1.b_off};
+    smgn::ConvOut O{last ? B(w.ebot) : B(w.cat[l]) + ch, last ? ch : 2 * ch, ch, nullptr, 0, true,
+                    last ? nullptr : B(w.h[l + 1]), ch, nullptr, nullptr, nullptr};
+    if (levels == 1) { O.w1 = pb + LO.w_off; O.b1 = p + LO.b_off; O.y1 = y; }
+    NCHK(smgn::conv3x(I, O, n, H, W, st));
     k += 2;
   }
   const unsigned short* dprev = B(w.ebot);
   for (int l = levels - 2; l >= 0; --l) {
     const int H = w.H >> l, W = w.W >> l;
-    NCHK(smgn::up(dprev, ch, B(w.cat[l]), 2 * ch, ch, n, H / 2, W / 2, st));
+    // the concatenation [upsampled level below, encoder output]: materialised
+    // for training (the weight gradient reads it), read in place otherwise
+    if (train) NCHK(smgn::up(dprev, ch, B(w.cat[l]), 2 * ch, ch, n, H / 2, W / 2, st));
     const NetLayer& LA = layers[k];
-    NCHK(smgn::conv3(B(w.cat[l]), 2 * ch, 2 * ch, pb + LA.w_off, p + LA.b_off, B(w.ad[l]), ch, ch, nullptr, 0, true, n, H,
-                     W, st));
+    smgn::ConvIn IA{B(w.cat[l]), train ? nullptr : dprev, 2 * ch, 2 * ch, pb + LA.w_off, p + LA.b_off};
+    smgn::ConvOut OA{B(w.ad[l]), ch, ch, nullptr, 0, true, nullptr, 0, nullptr, nullptr, nullptr};
+    NCHK(smgn::conv3x(IA, OA, n, H, W, st));
     const NetLayer& LB = layers[k + 1];
-    NCHK(smgn::conv3(B(w.ad[l]), ch, ch, pb + LB.w_off, p + LB.b_off, B(w.d[l]), ch, ch, nullptr, 0, true, n, H, W, st));
+    smgn::ConvIn IB{B(w.ad[l]), nullptr, ch, ch, pb + LB.w_off, p + LB.b_off};
+    // the top level also computes the 1x1 output layer; its own output is
+    // only needed by the backward pass
+    smgn::ConvOut OB{(train || l > 0) ? B(w.d[l]) : nullptr, ch, ch, nullptr, 0, true, nullptr, 0, nullptr, nullptr,
+                     nullptr};
+    if (l == 0) { OB.w1 = pb + LO.w_off; OB.b1 = p + LO.b_off; OB.y1 = y; }
+    NCHK(smgn::conv3x(IB, OB, n, H, W, st));
     dprev = B(w.d[l]);
     k += 2;
   }
-  const NetLayer& LO = layers[k];
-  NCHK(smgn::out_layer(dprev, ch, ch, pb + LO.w_off, p + LO.b_off, reinterpret_cast<float*>(base + w.y), (int)np0, st));
   return SMG_OK;
 }
 
@@ -313,7 +322,8 @@ extern "C" smg_status smg_net_forward(smg_net* net, const float* x, float* y, in
   char* base = static_cast<char*>(work);
   const size_t np0 = (size_t)n * h * w;
   NCHK(hipMemcpyAsync(base + wl.x32, x, sizeof(float) * np0 * net->def.in_ch, hipMemcpyDeviceToDevice, st));
-  NST(net->def.forward(base, wl, st));
+  // the forward the backward pass follows (it keeps every activation)
+  NST(net->def.forward(base, wl, st, true));
   if (y) NCHK(hipMemcpyAsync(y, base + wl.y, sizeof(float) * np0, hipMemcpyDeviceToDevice, st));
   return SMG_OK;
 }
@@ -345,7 +355,7 @@ extern "C" smg_status smg_net_train_step(smg_net* net, const float* samples, int
     NCHK(hipMemcpyAsync(base + wl.tgt + sizeof(float) * img * q, s + img * net->def.in_ch, sizeof(float) * img,
                         hipMemcpyDeviceToDevice, st));
   }
-  NST(net->def.forward(base, wl, st));
+  NST(net->def.forward(base, wl, st, true));
   NCHK(smgn::fill_f32(net->def.loss, 1, 0.f, st));
   NCHK(smgn::mse(reinterpret_cast<float*>(base + wl.y), reinterpret_cast<float*>(base + wl.tgt),
                  reinterpret_cast<float*>(base + wl.gy), (int)(img * n), net->def.loss, st));

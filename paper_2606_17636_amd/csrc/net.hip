@@ -51,41 +51,83 @@ __device__ __forceinline__ f32x16 mma16(uint4 a, uint4 b, f32x16 c) {
 // the 32 x 9 CIN weights are staged in LDS once with 16-byte loads, so the
 // 9 taps reuse them; each wave owns R rows and steps K = 9 CIN in slices of
 // 16 (one 16-byte LDS read per operand per lane: 8 channels of one tap).
-// Grid (ceil(W / 32), ceil(H / TH), N * cout / 32).  Channel strides and
-// base pointers select sub-ranges of wider (concatenated) arrays; ics and
-// the base must keep 16-byte alignment (ics % 8 == 0).
+// Every thread issues all of its staging loads (addresses clamped into the
+// arrays, values outside the image zeroed afterwards) before its first LDS
+// store, so a block waits for one round of memory latency.
+// Fused forms (ConvArgs): the decoder's concatenated input read straight
+// from the level below (channels 0..31 upsampled from `lo`) and the skip
+// half; the 2x2 average pooling of the output (the next level's input) and
+// the 1x1 output layer computed from the tile's BF16 outputs in the same
+// order as their own kernels (so the bits do not depend on the fusion).
+// Grid (ceil(W / 32), ceil(H / TH), N * cout / 32).
+struct ConvArgs {
+  const unsigned short* in;  // input, ics elements per pixel (16-byte aligned)
+  const unsigned short* lo;  // concatenated form: channels 0..31 from this (H/2 x W/2, 32 per pixel), or null
+  const unsigned short* W;   // [cout][9][CIN]
+  const float* bias;         // [cout] or null
+  unsigned short* out;       // output, ocs per pixel, or null
+  const unsigned short* mask;
+  unsigned short* pooled;    // 2x2 average of the output (H/2 x W/2, pcs per pixel), or null
+  const unsigned short* w1;  // 1x1 output layer weights [32] and bias, or null
+  const float* b1;
+  float* y1;                 // its output [N][H][W]
+  int ics, ocs, mcs, pcs, cout, relu, H, Wd;
+};
+
 template <int CIN, int R>
-__global__ void __launch_bounds__(256) k_conv3(const unsigned short* __restrict__ in, int ics,
-                                               const unsigned short* __restrict__ Wt, const float* __restrict__ bias,
-                                               unsigned short* __restrict__ out, int ocs, int cout,
-                                               const unsigned short* __restrict__ mask, int mcs, int relu, int H,
-                                               int Wd) {
+__global__ void __launch_bounds__(256) k_conv3(const ConvArgs A) {
   constexpr int TH = 4 * R, TW = 32, K = 9 * CIN, KS = (K + 15) / 16;
   constexpr int PS = CIN + 8;       // LDS elements per staged pixel (padding spreads the lanes over banks)
   constexpr int WS = 16 * KS + 8;   // LDS elements per staged weight row
   constexpr int C8 = CIN / 8;
+  constexpr int NX = (TH + 2) * (TW + 2) * C8, NXT = (NX + 255) / 256;
+  constexpr int NW = 32 * (K / 8), NWT = (NW + 255) / 256;
   extern __shared__ uint4 smem_conv[];
   unsigned short* xs = reinterpret_cast<unsigned short*>(smem_conv);   // (TH + 2) * (TW + 2) * PS
   unsigned short* ws = xs + (TH + 2) * (TW + 2) * PS;                  // 32 * WS
-  const int ntile = cout >> 5;
+  const int H = A.H, Wd = A.Wd;
+  const int ntile = A.cout >> 5;
   const int n = blockIdx.z / ntile, ct = blockIdx.z - n * ntile;
   const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
   const int tid = threadIdx.x;
-  for (int e = tid; e < 32 * (K / 8); e += 256) {
+  uint4 wv[NWT], xv[NXT];
+  unsigned inside = 0;
+#pragma unroll
+  for (int r = 0; r < NWT; ++r) {
+    const int e = min(tid + 256 * r, NW - 1);
     const int j = e / (K / 8), q = e - j * (K / 8);
-    *reinterpret_cast<uint4*>(ws + j * WS + 8 * q) =
-        *reinterpret_cast<const uint4*>(Wt + (size_t)(ct * 32 + j) * K + 8 * q);
+    wv[r] = *reinterpret_cast<const uint4*>(A.W + (size_t)(ct * 32 + j) * K + 8 * q);
   }
-  if (16 * KS > K)
-    for (int j = tid; j < 32; j += 256) *reinterpret_cast<uint4*>(ws + j * WS + K) = make_uint4(0, 0, 0, 0);
-  for (int e = tid; e < (TH + 2) * (TW + 2) * C8; e += 256) {
+#pragma unroll
+  for (int r = 0; r < NXT; ++r) {
+    const int e = min(tid + 256 * r, NX - 1);
     const int q = e % C8, pix = e / C8;
     const int row = pix / (TW + 2), col = pix - row * (TW + 2);
     const int yy = y0 - 1 + row, xx = x0 - 1 + col;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (yy >= 0 && yy < H && xx >= 0 && xx < Wd)
-      v = *reinterpret_cast<const uint4*>(in + ((size_t)(n * H + yy) * Wd + xx) * ics + 8 * q);
-    *reinterpret_cast<uint4*>(xs + pix * PS + 8 * q) = v;
+    if (yy >= 0 && yy < H && xx >= 0 && xx < Wd) inside |= 1u << r;
+    const int yc = min(max(yy, 0), H - 1), xc = min(max(xx, 0), Wd - 1);
+    const unsigned short* src =
+        (A.lo && q < 4) ? A.lo + ((size_t)(n * (H >> 1) + (yc >> 1)) * (Wd >> 1) + (xc >> 1)) * 32 + 8 * q
+                        : A.in + ((size_t)(n * H + yc) * Wd + xc) * A.ics + 8 * q;
+    xv[r] = *reinterpret_cast<const uint4*>(src);
+  }
+#pragma unroll
+  for (int r = 0; r < NWT; ++r) {
+    const int e = tid + 256 * r;
+    if (e < NW) {
+      const int j = e / (K / 8), q = e - j * (K / 8);
+      *reinterpret_cast<uint4*>(ws + j * WS + 8 * q) = wv[r];
+    }
+  }
+  if (16 * KS > K)
+    for (int j = tid; j < 32; j += 256) *reinterpret_cast<uint4*>(ws + j * WS + K) = make_uint4(0, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < NXT; ++r) {
+    const int e = tid + 256 * r;
+    if (e < NX) {
+      const int q = e % C8, pix = e / C8;
+      *reinterpret_cast<uint4*>(xs + pix * PS + 8 * q) = ((inside >> r) & 1u) ? xv[r] : make_uint4(0, 0, 0, 0);
+    }
   }
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63;
@@ -107,22 +149,49 @@ __global__ void __launch_bounds__(256) k_conv3(const unsigned short* __restrict_
     }
   }
   const int co = ct * 32 + i;
-  const float bv = bias ? bias[co] : 0.f;
+  const float bv = A.bias ? A.bias[co] : 0.f;
+  const bool post = A.pooled || A.w1;
+  unsigned short* os = xs;   // TH x TW x 32 BF16 outputs for the fused pooling / output layer
+  if (post) __syncthreads();  // every wave is done reading the staged tiles
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int y = y0 + wave * R + r;
-    if (y >= H) continue;
+    const int yl = wave * R + r, y = y0 + yl;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int xo = x0 + mfma_row(q, lane);
-      if (xo >= Wd) continue;
+      const int xl = mfma_row(q, lane), xo = x0 + xl;
       float v = acc[r][q] + bv;
-      if (relu) v = fmaxf(v, 0.f);
-      const size_t pix = (size_t)(n * H + y) * Wd + xo;
-      if (mask && !(bf2f(mask[pix * mcs + co]) > 0.f)) v = 0.f;
-      out[pix * ocs + co] = f2bf(v);
+      if (A.relu) v = fmaxf(v, 0.f);
+      const bool in_img = y < H && xo < Wd;
+      const size_t pix = (size_t)(n * H + min(y, H - 1)) * Wd + min(xo, Wd - 1);
+      if (A.mask && in_img && !(bf2f(A.mask[pix * A.mcs + co]) > 0.f)) v = 0.f;
+      const unsigned short h = f2bf(v);
+      if (A.out && in_img) A.out[pix * A.ocs + co] = h;
+      if (post) os[(yl * TW + xl) * 32 + i] = h;
     }
   }
+  if (!post) return;
+  __syncthreads();
+  if (A.pooled) {
+    const int Hp = H >> 1, Wp = Wd >> 1;
+    for (int e = tid; e < (TH / 2) * (TW / 2) * 32; e += 256) {
+      const int c = e & 31, pp = e >> 5, py = pp / (TW / 2), px = pp - py * (TW / 2);
+      const int yo = (y0 >> 1) + py, xo = (x0 >> 1) + px;
+      if (yo >= Hp || xo >= Wp) continue;
+      float sum = 0.f;
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) sum += bf2f(os[((2 * py + a) * TW + 2 * px + b) * 32 + c]);
+      A.pooled[((size_t)(n * Hp + yo) * Wp + xo) * A.pcs + c] = f2bf(0.25f * sum);
+    }
+  }
+  if (A.w1)
+    for (int pl = tid; pl < TH * TW; pl += 256) {
+      const int yl = pl / TW, xl = pl - yl * TW, y = y0 + yl, xo = x0 + xl;
+      if (y < H && xo < Wd) {
+        float sum = 0.f;
+        for (int c = 0; c < 32; ++c) sum = fmaf(bf2f(A.w1[c]), bf2f(os[(yl * TW + xl) * 32 + c]), sum);
+        A.y1[(size_t)(n * H + y) * Wd + xo] = sum + A.b1[0];
+      }
+    }
 }
 
 // Weight-gradient partials of a 3x3 convolution:
@@ -407,27 +476,39 @@ unsigned grid1(size_t n, unsigned block = 256) {
 namespace smgn {
 
 template <int CIN, int R>
-static void launch_conv3(const unsigned short* in, int ics, const unsigned short* W, const float* bias,
-                         unsigned short* out, int ocs, int cout, const unsigned short* mask, int mcs, bool relu, int N,
-                         int H, int Wd, hipStream_t st) {
+static void launch_conv3(const ConvArgs& A, int N, hipStream_t st) {
   constexpr int KS = (9 * CIN + 15) / 16;
   constexpr size_t lds = sizeof(unsigned short) * ((4 * R + 2) * 34 * (CIN + 8) + 32 * (16 * KS + 8));
-  dim3 grid((Wd + 31) / 32, (H + 4 * R - 1) / (4 * R), N * (cout / 32));
-  hipLaunchKernelGGL((k_conv3<CIN, R>), grid, dim3(256), lds, st, in, ics, W, bias, out, ocs, cout, mask, mcs,
-                     relu ? 1 : 0, H, Wd);
+  static_assert(lds >= sizeof(unsigned short) * 4 * R * 32 * 32, "the fused post-operations reuse the staging LDS");
+  dim3 grid((A.Wd + 31) / 32, (A.H + 4 * R - 1) / (4 * R), N * (A.cout / 32));
+  hipLaunchKernelGGL((k_conv3<CIN, R>), grid, dim3(256), lds, st, A);
+}
+
+hipError_t conv3x(const ConvIn& I, const ConvOut& O, int N, int H, int Wd, hipStream_t st) {
+  ConvArgs A{};
+  A.in = I.in; A.lo = I.lo; A.W = I.W; A.bias = I.bias; A.ics = I.ics;
+  A.out = O.out; A.ocs = O.ocs; A.cout = O.cout; A.mask = O.mask; A.mcs = O.mcs; A.relu = O.relu ? 1 : 0;
+  A.pooled = O.pooled; A.pcs = O.pcs; A.w1 = O.w1; A.b1 = O.b1; A.y1 = O.y1;
+  A.H = H; A.Wd = Wd;
+  const bool post = O.pooled || O.w1;
+  if (O.cout % 32 || I.ics % 8 || (reinterpret_cast<uintptr_t>(I.in) & 15)) return hipErrorInvalidValue;
+  if (I.lo && (I.cin != 64 || (H & 1) || (Wd & 1) || (reinterpret_cast<uintptr_t>(I.lo) & 15))) return hipErrorInvalidValue;
+  if (post && (O.cout != 32 || I.cin == 64 || (O.pooled && ((H & 1) || (Wd & 1))))) return hipErrorInvalidValue;
+  switch (I.cin) {
+    case 8: launch_conv3<8, 2>(A, N, st); break;
+    case 32: launch_conv3<32, 2>(A, N, st); break;
+    case 64: launch_conv3<64, 1>(A, N, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t conv3(const unsigned short* in, int ics, int cin, const unsigned short* W, const float* bias,
                  unsigned short* out, int ocs, int cout, const unsigned short* mask, int mcs, bool relu, int N, int H,
                  int Wd, hipStream_t st) {
-  if (cout % 32 || ics % 8 || (reinterpret_cast<uintptr_t>(in) & 15)) return hipErrorInvalidValue;
-  switch (cin) {
-    case 8: launch_conv3<8, 2>(in, ics, W, bias, out, ocs, cout, mask, mcs, relu, N, H, Wd, st); break;
-    case 32: launch_conv3<32, 2>(in, ics, W, bias, out, ocs, cout, mask, mcs, relu, N, H, Wd, st); break;
-    case 64: launch_conv3<64, 1>(in, ics, W, bias, out, ocs, cout, mask, mcs, relu, N, H, Wd, st); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  ConvIn I{in, nullptr, ics, cin, W, bias};
+  ConvOut O{out, ocs, cout, mask, mcs, relu, nullptr, 0, nullptr, nullptr, nullptr};
+  return conv3x(I, O, N, H, Wd, st);
 }
 
 int wgrad_chunk(int npix, int cout, int cin) {

@@ -13,6 +13,29 @@ constexpr size_t kWgradMaxPartials = (size_t)2 << 20;
 // pixel chunk and partial-sum floats of smgn::wgrad for a layer
 int wgrad_chunk(int npix, int cout, int cin);
 size_t wgrad_partials(int npix, int cout, int cin);
+// 3x3 convolution with fused forms (see k_conv3 in net.hip): the input
+// (optionally the decoder's concatenation, channels 0..31 upsampled from
+// `lo`), the output and the optional pooled copy / 1x1 output layer.
+struct ConvIn {
+  const unsigned short* in;  // ics elements per pixel (the skip half at channel 32 when lo is set)
+  const unsigned short* lo;  // or null
+  int ics, cin;
+  const unsigned short* W;
+  const float* bias;
+};
+struct ConvOut {
+  unsigned short* out;  // or null
+  int ocs, cout;
+  const unsigned short* mask;
+  int mcs;
+  bool relu;
+  unsigned short* pooled;  // or null
+  int pcs;
+  const unsigned short* w1;  // or null
+  const float* b1;
+  float* y1;
+};
+hipError_t conv3x(const ConvIn& in, const ConvOut& out, int N, int H, int Wd, hipStream_t st);
 // 3x3 convolution (MFMA): see k_conv3 in net.hip for the layout.
 hipError_t conv3(const unsigned short* in, int ics, int cin, const unsigned short* W, const float* bias,
                  unsigned short* out, int ocs, int cout, const unsigned short* mask, int mcs, bool relu, int N, int H,

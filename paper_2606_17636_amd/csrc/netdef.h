@@ -41,8 +41,10 @@ struct NetDef {
   size_t state_bytes() const;
   void bind(char* state);
   NetWork work_layout(int n, int H, int W) const;
-  // forward: x32 (FP32 NHWC) -> y; backward: gy -> g (overwritten)
-  smg_status forward(char* work, const NetWork& w, hipStream_t st) const;
+  // forward: x32 (FP32 NHWC) -> y (train: keep every activation the
+  // backward pass reads; otherwise the concatenations are read in place and
+  // the top decoder output is not stored); backward: gy -> g (overwritten)
+  smg_status forward(char* work, const NetWork& w, hipStream_t st, bool train) const;
   smg_status backward(char* work, const NetWork& w, hipStream_t st) const;
 };
 

@@ -8,8 +8,10 @@ namespace smgg {
 // sc[4 k + (0, 1, 2, 3)] = (s_f, s_d, s_u, s_o) per image: RMS of f_t, of
 // f_t - f_prev, of u_prev, and the output scale s_o: the RMS of
 // u_prev - u_prev2 (uprev2 given) or s_u s_d / s_f
+// part: scratch of scales_partial_doubles(n_img) doubles
+size_t scales_partial_doubles(int n_img);
 hipError_t scales(const double2* f, const double2* fprev, const double2* uprev, const double2* uprev2, int plane, int n_img,
-                  double* sc, hipStream_t st);
+                  double* part, double* sc, hipStream_t st);
 // uprev2: the solution two steps back (channel 6 = (uprev - uprev2) / s_o), or null
 hipError_t assemble(const double2* f, const double2* fprev, const double2* uprev, const double2* uprev2, const double* sc,
                     int na, int nb, int n_img, float* x, hipStream_t st);

@@ -5,6 +5,8 @@
 // bookkeeping of the previous step's right-hand side.
 #include "netguess.h"
 
+#include <algorithm>
+
 namespace {
 
 // relative size of the last change below which a plane counts as static
@@ -18,19 +20,23 @@ __device__ __forceinline__ void image_mode(int k, int* m, int* im) {
   *im = (k > 0 && (k & 1) == 0) ? 1 : 0;
 }
 
-// per image: RMS of f_t, of f_t - f_prev and of u_prev, and the output
+// Per image: RMS of f_t, of f_t - f_prev and of u_prev, and the output
 // scale: sc = (s_f, s_d, s_u, s_o) with s_o the RMS of u_prev - u_prev2
 // (the size of the last change of u) when u_prev2 is given, else
 // s_u s_d / s_f (the size the change of u takes when it follows the change
-// of f); 1 where zero
-__global__ void k_scales(const double2* __restrict__ f, const double2* __restrict__ fprev,
-                         const double2* __restrict__ uprev, const double2* __restrict__ uprev2, int plane,
-                         double* __restrict__ sc) {
+// of f); 1 where zero.  Two passes: kScaleBlocks blocks per image write
+// partial sums of squares (part[image][block][4]), one block per image then
+// adds them in block order.
+constexpr int kScaleBlocks = 32;
+
+__global__ void k_scales_partial(const double2* __restrict__ f, const double2* __restrict__ fprev,
+                                 const double2* __restrict__ uprev, const double2* __restrict__ uprev2, int plane,
+                                 double* __restrict__ part) {
   __shared__ double red[4][256];
   int m, im;
-  image_mode(blockIdx.x, &m, &im);
+  image_mode(blockIdx.y, &m, &im);
   double a = 0.0, b = 0.0, c = 0.0, e = 0.0;
-  for (int t = threadIdx.x; t < plane; t += blockDim.x) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < plane; t += gridDim.x * blockDim.x) {
     const double fv = part_of(f[(size_t)m * plane + t], im), uv = part_of(uprev[(size_t)m * plane + t], im);
     const double dv = fv - part_of(fprev[(size_t)m * plane + t], im);
     a += fv * fv;
@@ -51,20 +57,26 @@ __global__ void k_scales(const double2* __restrict__ f, const double2* __restric
       for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    double sf = sqrt(red[0][0] / plane), sd = sqrt(red[1][0] / plane), su = sqrt(red[2][0] / plane);
-    const double se = sqrt(red[3][0] / plane);
-    sf = sf > 0.0 ? sf : 1.0;
-    sd = sd > 0.0 ? sd : 1.0;
-    su = su > 0.0 ? su : 1.0;
-    sc[4 * blockIdx.x] = sf;
-    sc[4 * blockIdx.x + 1] = sd;
-    sc[4 * blockIdx.x + 2] = su;
-    // a plane whose last change is at the level of the solve's own error
-    // (below 1e-6 of the plane) is static: s_o = 0 marks it (no
-    // extrapolation, no correction, no change channel, zero target)
-    sc[4 * blockIdx.x + 3] = uprev2 ? (se > kStatic * su ? se : 0.0) : su * sd / sf;
-  }
+  if (threadIdx.x < 4) part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_scales_final(const double* __restrict__ part, int nblk, int plane, int have2, double* __restrict__ sc) {
+  if (threadIdx.x != 0) return;
+  double r[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < nblk; ++k)
+    for (int q = 0; q < 4; ++q) r[q] += part[((size_t)blockIdx.x * nblk + k) * 4 + q];
+  double sf = sqrt(r[0] / plane), sd = sqrt(r[1] / plane), su = sqrt(r[2] / plane);
+  const double se = sqrt(r[3] / plane);
+  sf = sf > 0.0 ? sf : 1.0;
+  sd = sd > 0.0 ? sd : 1.0;
+  su = su > 0.0 ? su : 1.0;
+  sc[4 * blockIdx.x] = sf;
+  sc[4 * blockIdx.x + 1] = sd;
+  sc[4 * blockIdx.x + 2] = su;
+  // a plane whose last change is at the level of the solve's own error
+  // (below 1e-6 of the plane) is static: s_o = 0 marks it (no
+  // extrapolation, no correction, no change channels, zero target)
+  sc[4 * blockIdx.x + 3] = have2 ? (se > kStatic * su ? se : 0.0) : su * sd / sf;
 }
 
 // x[k][i][j][0..7] = (f_t / s_f, (f_t - f_prev) / s_d, u_prev / s_u, m / 4,
@@ -130,11 +142,14 @@ __global__ void k_candidate(const double2* __restrict__ uprev, const double2* __
   }
 }
 
-// per mode: keep the candidate where its defect norm is the smaller one
+// per mode: keep the candidate where its defect norm is the smaller one.
+// Grid (blocks per plane, m_max + 1): every block sums its mode's partial
+// norms (nblk each) and copies its slice of the plane when the candidate
+// wins; block 0 of the mode records the choice.
 __global__ void k_select(const double* __restrict__ pc, const double* __restrict__ pu, int nblk,
                          const double2* __restrict__ cand, double2* __restrict__ u, int plane, int* __restrict__ used) {
   __shared__ int take;
-  const int m = blockIdx.x;
+  const int m = blockIdx.y;
   if (threadIdx.x == 0) {
     double a = 0.0, b = 0.0;
     for (int k = 0; k < nblk; ++k) {
@@ -142,11 +157,12 @@ __global__ void k_select(const double* __restrict__ pc, const double* __restrict
       b += pu[(size_t)m * nblk + k];
     }
     take = a < b ? 1 : 0;
-    used[m] = take;
+    if (blockIdx.x == 0) used[m] = take;
   }
   __syncthreads();
   if (!take) return;
-  for (int t = threadIdx.x; t < plane; t += blockDim.x) u[(size_t)m * plane + t] = cand[(size_t)m * plane + t];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < plane; t += gridDim.x * blockDim.x)
+    u[(size_t)m * plane + t] = cand[(size_t)m * plane + t];
 }
 
 // training samples: (x, (u_t - u_prev - (u_prev - u_prev2)) / s_o) per
@@ -185,9 +201,12 @@ unsigned grid1(size_t n) {
 
 namespace smgg {
 
+size_t scales_partial_doubles(int n_img) { return (size_t)n_img * kScaleBlocks * 4; }
+
 hipError_t scales(const double2* f, const double2* fprev, const double2* uprev, const double2* uprev2, int plane, int n_img,
-                  double* sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_scales, dim3(n_img), dim3(256), 0, st, f, fprev, uprev, uprev2, plane, sc);
+                  double* part, double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_scales_partial, dim3(kScaleBlocks, n_img), dim3(256), 0, st, f, fprev, uprev, uprev2, plane, part);
+  hipLaunchKernelGGL(k_scales_final, dim3(n_img), dim3(64), 0, st, part, kScaleBlocks, plane, uprev2 ? 1 : 0, sc);
   return hipGetLastError();
 }
 
@@ -207,7 +226,8 @@ hipError_t candidate(const double2* uprev, const double2* uprev2, const float* y
 
 hipError_t select(const double* pc, const double* pu, int nblk, const double2* cand, double2* u, int plane, int m_max,
                   int* used, hipStream_t st) {
-  hipLaunchKernelGGL(k_select, dim3(m_max + 1), dim3(256), 0, st, pc, pu, nblk, cand, u, plane, used);
+  const int per = std::max(1, std::min(64, (plane + 1023) / 1024));
+  hipLaunchKernelGGL(k_select, dim3(per, m_max + 1), dim3(256), 0, st, pc, pu, nblk, cand, u, plane, used);
   return hipGetLastError();
 }
 
