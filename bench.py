@@ -410,11 +410,13 @@ def bench_trajectory(args, smg, configs, torch, pool):
     buf = learn.sample_buffer(plan, cap)
     n, _ = learn.record_trajectories(plan, [traj(s, n_train_snap) for s in seeds], args.tol, buf, cap)
     log(f"recorded {n} samples from {len(seeds)} trajectories in {time.perf_counter() - t0:.1f}s")
+    eval_before = learn.evaluate(net, buf, n, g["n_a"], g["n_b"])
     t0 = time.perf_counter()
     losses = learn.train(net, buf, n, g["n_a"], g["n_b"], steps=args.train_steps, batch=16, lr=args.train_lr, seed=1,
                          log_every=max(1, args.train_steps // 4), log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    eval_after = learn.evaluate(net, buf, n, g["n_a"], g["n_b"])
     del buf
     torch.cuda.empty_cache()
 
@@ -483,8 +485,8 @@ def bench_trajectory(args, smg, configs, torch, pool):
                    "line_solver": args.line_solver,
                    "step": "one warm-started solve of the next snapshot",
                    "train": {"trajectories": len(seeds), "samples": n, "steps": args.train_steps,
-                             "loss_first": round(float(np.mean(losses[:10])), 4),
-                             "loss_last": round(float(np.mean(losses[-20:])), 4), "seconds": round(t_train, 1)},
+                             "loss_fixed_64_samples": [float("%.4g" % eval_before), float("%.4g" % eval_after)],
+                             "seconds": round(t_train, 1)},
                    "low_mode_v_cycles_per_step": {"zero_guess": round(float(np.mean(zero)), 2),
                                                   "previous_step": round(float(np.mean(cyc_prev)), 2),
                                                   "network": round(float(np.mean(cyc_net)), 2)},

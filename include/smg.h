@@ -317,7 +317,7 @@ smg_status smg_net_conv3_wgrad_noalloc(const unsigned short *g_dev, int c_out, c
  * s_o and of -i (u_{t-1} - u_{t-2}) / s_o, with s_f, s_d, s_u the plane RMS
  * values of f_t, f_t - f_{t-1} and u_{t-1}, and s_o, the scale of the
  * output, the RMS of u_{t-1} - u_{t-2}; before two warm steps have run,
- * and for a static plane (last change below 1e-6 of its RMS), channels 6
+ * and for a static plane (last change below 1e-4 of its RMS), channels 6
  * and 7 are zero) before each of its two multigrid solves and
  * starts every mode from the better (defect norms after one smoothing step
  * of each) of the previous solution and the candidate u_{t-1} + (u_{t-1} -

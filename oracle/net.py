@@ -50,9 +50,10 @@ import numpy as np
 LEVELS = 4
 CH = 32
 IN_CH = 8
-# a plane whose last change is below this fraction of its RMS is static (its
-# change is the solver's own error): no extrapolation, correction or target
-STATIC = 1e-6
+# a plane whose last change is below this fraction of its RMS is static (the
+# previous solution is already a better start than a guess needs to be): no
+# extrapolation, correction or target
+STATIC = 1e-4
 
 
 def layer_shapes(levels=LEVELS, ch=CH, in_ch=IN_CH):

@@ -155,6 +155,8 @@ struct Group {
   // per-mode cycle counts of the last solve, per initial-guess kind (0 zero,
   // 1 warm) and target: the schedule of the next solve of that kind
   std::vector<int> hist[2][2];
+  std::vector<int> hist_prev[2][2];  // the counts of the solve of that kind before the last one
+  int margin[2] = {0, 0};            // extra cycles per mode: 1 after a solve of the kind ran short
   bool hist_ok[2] = {false, false};
   std::vector<GraphEnt> graphs;
   unsigned long long clock = 0;
@@ -167,6 +169,8 @@ struct Group {
   void reset() {
     have_prev = false;
     hist_ok[0] = hist_ok[1] = false;
+    for (auto& h : hist_prev)
+      for (auto& v : h) v.clear();
     drop_graphs();
   }
   Group() = default;
@@ -926,16 +930,22 @@ static smg_status james_steps(smg_plan* p, const double2* psi, const double2* f,
 
 // Per-cycle plane counts of a solve from the per-mode cycle counts of the
 // previous one: cycle k runs on the modes that needed more than k cycles.
-// Every mode is given one cycle more than it needed last time: a mode
-// that converged early drops out of the device list (its blocks return at
-// once), while one cycle too few would send the whole solve back to the
-// host loop.
-static std::vector<int> schedule_of(const std::vector<int>& cyc) {
+// Every mode is given as many cycles as it needed in the more demanding of
+// the last two solves of the kind (a sequence whose counts alternate, a
+// time series of warm starts, is covered; a repeated solve is scheduled
+// exactly), plus `margin` after a solve that ran short.  A mode that
+// converges early drops out of the device list (its blocks return at once);
+// one cycle too few sends the whole solve back to the host loop.
+static std::vector<int> schedule_of(const std::vector<int>& cyc, const std::vector<int>& prev, int margin) {
+  std::vector<int> need(cyc);
+  if (prev.size() == cyc.size())
+    for (size_t k = 0; k < need.size(); ++k) need[k] = std::max(need[k], prev[k]);
+  for (int& c : need) c += margin;
   int mx = 0;
-  for (int c : cyc) mx = std::max(mx, c);
-  std::vector<int> caps(mx + 1, 0);
-  for (int c : cyc)
-    for (int k = 0; k < c + 1; ++k) caps[k] += 1;
+  for (int c : need) mx = std::max(mx, c);
+  std::vector<int> caps(mx, 0);
+  for (int c : need)
+    for (int k = 0; k < c; ++k) caps[k] += 1;
   return caps;
 }
 
@@ -1176,8 +1186,8 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
   if (timings) HIPCHK(hipEventRecord(ev[1], st));
   std::vector<int> s0, s1;
   if (sched) {
-    s0 = schedule_of(g.hist[wk][0]);
-    s1 = schedule_of(g.hist[wk][1]);
+    s0 = schedule_of(g.hist[wk][0], g.hist_prev[wk][0], g.margin[wk]);
+    s1 = schedule_of(g.hist[wk][1], g.hist_prev[wk][1], g.margin[wk]);
   }
   if (graph) {
     hipGraphExec_t exec = nullptr;
@@ -1197,6 +1207,7 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
   Engine& e = *g.eng;
   Engine::State es;
   STCHK(e.read_all(st, &es));
+  if (sched) g.margin[wk] = (es.count[0] > 0 || es.count[1] > 0) ? 1 : 0;
   if (es.count[0] > 0 || es.count[1] > 0) {
     // the training samples recorded in the body came from unfinished solves
     for (smg_plan* p : g.plans)
@@ -1219,8 +1230,10 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
       if (!(es.cur[t][k] <= es.thr[t][k])) converged = false;
   if (converged && g.launch == SMG_LAUNCH_GRAPH) {
     // a mode that took more cycles than scheduled keeps its new count
-    g.hist[wk][0] = es.cyc[0];
-    g.hist[wk][1] = es.cyc[1];
+    for (int t = 0; t < 2; ++t) {
+      g.hist_prev[wk][t] = g.hist[wk][t];
+      g.hist[wk][t] = es.cyc[t];
+    }
     g.hist_ok[wk] = true;
   }
   if (infos) {

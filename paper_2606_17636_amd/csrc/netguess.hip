@@ -10,7 +10,9 @@
 namespace {
 
 // relative size of the last change below which a plane counts as static
-constexpr double kStatic = 1e-6;
+// (a change that small leaves the previous solution a better start than
+// any guess needs to be)
+constexpr double kStatic = 1e-4;
 
 __device__ __forceinline__ double part_of(double2 v, int im) { return im ? v.y : v.x; }
 

@@ -55,9 +55,22 @@ def train(net, samples, n_samples, h, w, steps=1000, batch=16, lr=1e-3, seed=0, 
     return losses
 
 
+def evaluate(net, samples, n_samples, h, w, count=64, batch=16):
+    """Mean training loss over the first `count` samples (fixed batches),
+    through the library's training step at learning rate 0; resets the Adam
+    moments afterwards (the parameters are unchanged)."""
+    count = min(count, n_samples)
+    total, k = 0.0, 0
+    for q in range(0, count - batch + 1, batch):
+        total += net.train_step(samples, np.arange(q, q + batch), h, w, 0.0)
+        k += 1
+    net.set_params(net.params())
+    return total / max(k, 1)
+
+
 def low_mode_cycles(info, m_max):
     """V-cycles of modes 0..m_max in both multigrid solves of one step."""
     return int(info["cycles1"][: m_max + 1].sum() + info["cycles2"][: m_max + 1].sum())
 
 
-__all__ = ["samples_per_step", "sample_buffer", "record_trajectories", "train", "low_mode_cycles", "smg"]
+__all__ = ["samples_per_step", "sample_buffer", "record_trajectories", "train", "evaluate", "low_mode_cycles", "smg"]

@@ -80,10 +80,14 @@ def test_trained_net_saves_low_mode_cycles():
     buf = learn.sample_buffer(rec, cap)
     n, _ = learn.record_trajectories(rec, [_traj(s, steps) for s in (50, 51, 52, 53)], 1e-10, buf, cap)
     print("samples", n, flush=True)
-    assert n == cap
-    losses = learn.train(net, buf, n, SPEC.n_a, SPEC.n_b, steps=400, batch=16, lr=1e-3, seed=3)
-    print("loss", np.mean(losses[:10]), "->", np.mean(losses[-20:]), flush=True)
-    assert np.mean(losses[-20:]) < 0.5 * np.mean(losses[:10])
+    # a solve that needs more cycles than its schedule gave is finished on the
+    # host and its samples withdrawn; most are kept
+    assert 0.75 * cap <= n <= cap
+    before = learn.evaluate(net, buf, n, SPEC.n_a, SPEC.n_b)
+    learn.train(net, buf, n, SPEC.n_a, SPEC.n_b, steps=600, batch=16, lr=1e-3, seed=3)
+    after = learn.evaluate(net, buf, n, SPEC.n_a, SPEC.n_b)
+    print("loss on a fixed set of 64 samples", before, "->", after, flush=True)
+    assert after < 0.5 * before
 
     with_net = _plan(precision="mixed").attach_net(net, M_MAX)
     plain = _plan(precision="mixed")
