@@ -425,11 +425,15 @@ def bench_trajectory(args, smg, configs, torch, pool):
     phi = torch.empty_like(rhos[0])
     taken = [0]
 
-    def run(pl, use_net, with_info=False, profile=False):
+    def run(pl, use_net, with_info=False, profile=False, mark=False):
         """Cold solve of snapshot 0, then snapshots 1..K warm; returns the time
-        of the warm solves and their low-mode cycles."""
+        of the warm solves and their low-mode cycles.  With mark set, a short
+        spin kernel runs just before and just after the warm solves (outside
+        the timed span), so that a kernel trace can pick out their launches."""
         pl.solve_nosync(rhos[0], phi, tol=args.tol)
         cyc = []
+        if mark:
+            torch.cuda._sleep(64)
         torch.cuda.synchronize()
         if profile:
             pl.profile_begin()
@@ -446,16 +450,18 @@ def bench_trajectory(args, smg, configs, torch, pool):
         torch.cuda.synchronize()
         el = time.perf_counter() - t
         stats = pl.profile_end() if profile else None
+        if mark:
+            torch.cuda._sleep(64)
         return el, cyc, stats
 
     _, cyc_net, _ = run(plan, True, with_info=True)
     _, cyc_prev, _ = run(plan, False, with_info=True)
     for _ in range(max(args.warmup, 1)):
         run(plan, True)
-    dt_net, _, _ = run(plan, True)
+    dt_net, _, _ = run(plan, True, mark=True)
     phi_last = phi.cpu().numpy()
     log(f"timed {K} warm solves with the learned guess: {K / dt_net:.2f} solves/s")
-    _, _, stats = run(plan, True, profile=True)
+    _, _, stats = run(plan, True, profile=True, mark=True)
     roof, kern = _roofline(stats, "c5", K)
     for _ in range(max(args.warmup, 1)):
         run(plan, False)

@@ -476,11 +476,12 @@ extern "C" smg_status smg_plan_shape(const smg_plan* p, int* n_levels, int* n_gh
 // per-launch timing
 // ----------------------------------------------------------------------------
 enum KernelClass {
-  K_FFT_R2C, K_FFT_C2R, K_SMOOTH_RADIAL0, K_SMOOTH_POLAR0, K_SMOOTH_COARSE, K_RESTRICT, K_PROLONG, K_COARSE,
-  K_NORM, K_SCREEN, K_CONV, K_APPLY, K_ACCUM, K_COUNT
+  K_FFT_R2C, K_FFT_C2R, K_SMOOTH_RADIAL0, K_SMOOTH_POLAR0, K_SMOOTH_RADIAL_C, K_SMOOTH_POLAR_C, K_RESTRICT,
+  K_PROLONG, K_COARSE, K_NORM, K_SCREEN, K_CONV, K_APPLY, K_ACCUM, K_COUNT
 };
 static const char* kKernelNames[K_COUNT] = {
-  "fft_r2c", "fft_c2r", "smooth_radial_lines_l0", "smooth_polar_lines_l0", "smooth_coarser_levels",
+  "fft_r2c", "fft_c2r", "smooth_radial_lines_l0", "smooth_polar_lines_l0", "smooth_radial_lines_coarser",
+  "smooth_polar_lines_coarser",
   "residual_restrict", "prolong_add", "lds_coarse_cycle", "defect_norm", "james_screen", "james_conv", "james_apply",
   "accumulate_fp64"};
 
@@ -524,14 +525,14 @@ int PlanProf::launch_events(hipEvent_t* start, hipEvent_t* stop) {
 }
 
 void PlanProf::close(int cls, int ev, double bytes, hipStream_t st) {
-  static const int map[] = {K_SMOOTH_RADIAL0, K_SMOOTH_POLAR0, K_SMOOTH_COARSE, K_RESTRICT, K_PROLONG,
-                            K_COARSE,         K_NORM,          K_ACCUM,         K_NORM};
+  static const int map[] = {K_SMOOTH_RADIAL0, K_SMOOTH_POLAR0, K_SMOOTH_RADIAL_C, K_SMOOTH_POLAR_C, K_RESTRICT,
+                            K_PROLONG,        K_COARSE,        K_NORM,            K_ACCUM,           K_NORM};
   prof_close(*p, map[cls], ev, bytes, st);
 }
 
 void PlanProf::close_launch(int cls, int id, double bytes) {
-  static const int map[] = {K_SMOOTH_RADIAL0, K_SMOOTH_POLAR0, K_SMOOTH_COARSE, K_RESTRICT, K_PROLONG,
-                            K_COARSE,         K_NORM,          K_ACCUM,         K_NORM};
+  static const int map[] = {K_SMOOTH_RADIAL0, K_SMOOTH_POLAR0, K_SMOOTH_RADIAL_C, K_SMOOTH_POLAR_C, K_RESTRICT,
+                            K_PROLONG,        K_COARSE,        K_NORM,            K_ACCUM,           K_NORM};
   if (id >= 0) p->prof_log.push_back({map[cls], id, id + 1, bytes});
 }
 

@@ -306,7 +306,7 @@ smg_status Engine::vcycle(int target, int c, const BatchRef& b, hipStream_t st, 
                                          f32, st, pr, ac, z);
       smgk::next_launch_events(nullptr, nullptr);
       if (e != hipSuccess) return e;
-      const int cls = d == 0 ? (dir == 0 ? EC_SMOOTH_R0 : EC_SMOOTH_P0) : EC_SMOOTH_C;
+      const int cls = d == 0 ? (dir == 0 ? EC_SMOOTH_R0 : EC_SMOOTH_P0) : (dir == 0 ? EC_SMOOTH_RC : EC_SMOOTH_PC);
       const double bytes = ((pr ? 3.25 : 3.0) * vb + (ac ? 32.0 - vb : 0.0) - (z ? vb : 0.0)) * cells(d, false);
       if (id >= 0) prof_->close_launch(cls, id, bytes);
       else if (prof_) prof_->close(cls, ev, bytes, st);

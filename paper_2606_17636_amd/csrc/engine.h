@@ -53,7 +53,9 @@ struct ProfSink {
   virtual int launch_events(hipEvent_t* start, hipEvent_t* stop) { (void)start; (void)stop; return -1; }
   virtual void close_launch(int cls, int id, double bytes) { (void)cls; (void)id; (void)bytes; }
 };
-enum EngineClass { EC_SMOOTH_R0, EC_SMOOTH_P0, EC_SMOOTH_C, EC_RESTRICT, EC_PROLONG, EC_COARSE, EC_NORM, EC_ACCUM, EC_CONV };
+enum EngineClass {
+  EC_SMOOTH_R0, EC_SMOOTH_P0, EC_SMOOTH_RC, EC_SMOOTH_PC, EC_RESTRICT, EC_PROLONG, EC_COARSE, EC_NORM, EC_ACCUM, EC_CONV
+};
 
 class Engine {
  public:

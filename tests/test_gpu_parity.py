@@ -214,6 +214,28 @@ def test_full_solve_sor_coarsest_fp64(key):
     assert _l2(spec, phi.cpu().numpy(), op.solve(rho)) < 1e-10
 
 
+@pytest.mark.parametrize("key", ["sph-log", "cyl-uni"])
+def test_full_solve_gravitational_constant(key):
+    """G enters the source 4 pi G rho, the screening mass 1/(4 pi G) and the
+    boundary sums -G (Sec. 2.2, Sec. 4.2): a solve at G = 0.5 matches the
+    oracle at G = 0.5 (whose G factors are pinned by the closed forms) and is
+    half the GPU's own solve at G = 1 to rounding."""
+    import dataclasses
+    from paper_2606_17636_amd import smg
+    spec1, npad = SPECS[key]
+    spec = dataclasses.replace(spec1, G=0.5)
+    print(f"[setup] {key} G=0.5", flush=True)
+    gp = smg.grid_from_spec(spec, n_pad=npad).setup()
+    _, gp1, _ = _plans(key)
+    rho = _density(spec, 14)
+    phi, info = gp.solve(_dev(rho), tol=1e-12)
+    phi1, _ = gp1.solve(_dev(rho), tol=1e-12)
+    assert info["converged"]
+    ref = OraclePlan(spec, n_pad=npad).solve(rho)
+    assert _l2(spec, phi.cpu().numpy(), ref) < 1e-10
+    assert _l2(spec, phi.cpu().numpy(), 0.5 * phi1.cpu().numpy()) < 1e-10
+
+
 def test_zero_density_gives_zero():
     spec, gp, op = _plans("sph-uni")
     phi, info = gp.solve(torch.zeros((spec.n_a, spec.n_b, spec.n_phi), dtype=torch.float64, device="cuda"), tol=1e-8)
