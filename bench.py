@@ -110,8 +110,11 @@ def _oracle_worker(conn, grid, modes):
 
 class OraclePool:
     """The FP64 oracle solving one grid's modes in `cores` processes (modes
-    dealt round-robin).  Started before the GPU is touched, so its setup
-    (LU factors, DGF tables: untimed, as on the GPU) overlaps the GPU's."""
+    dealt round-robin).  Started before torch is imported, so its setup
+    (LU factors, DGF tables: untimed, as on the GPU) overlaps that import;
+    the GPU work waits for it (`ready`) before its own setup, so that no
+    host core is busy with the oracle while the autotuner or the timed
+    solves run."""
 
     def __init__(self, grid, cores):
         import multiprocessing as mp
@@ -391,6 +394,8 @@ def bench_trajectory(args, smg, configs, torch, pool):
     K = args.steps
     log(f"workload c5: {configs.DESCRIPTION['c5']}; {K} timed snapshots")
     dt = configs.keplerian_dt()
+    if pool is not None:
+        pool.ready()
     t0 = time.perf_counter()
     plan = _plan(smg, g, "chosen", args.line_solver).setup("cuda:0")
     a, b, ph, dv = plan.geometry()
@@ -536,6 +541,8 @@ def bench_cold(args, smg, configs, torch, pool):
     g = configs.GRIDS[wl]
     log(f"workload {args.workload}: {desc}")
     plan = _plan(smg, g, args.form, args.line_solver)
+    if pool is not None:
+        pool.ready()
     t0 = time.perf_counter()
     plan.setup("cuda:0")
     torch.cuda.synchronize()

@@ -1,16 +1,14 @@
 // Kernels of the learned initial guess: a U-Net on real mode planes with
 // BF16 weights and activations and FP32 accumulation on the matrix cores
-// (v_mfma_f32_32x32x8_bf16), its backward pass and an Adam update.
+// (v_mfma_f32_32x32x16_bf16 of gfx950), its backward pass and an Adam update.
 //
 // Activations are NHWC (pixel-major, channels contiguous) BF16 arrays; a
 // 3x3 weight tensor is [c_out][9][c_in] with tap t = 3 (dy + 1) + (dx + 1)
 // reading input pixel (y + dy, x + dx), zero outside the image.  A 3x3
 // convolution is a GEMM with M = pixels, N = output channels and
-// K = 9 c_in (k = t c_in + c): one wave computes 32 pixels of one image row
-// times 32 output channels, each lane feeding four consecutive k of its
-// pixel (one tap, four channels: one 8-byte load) and four of its output
-// channel's weights.  The weight gradient is the GEMM with M = output
-// channels, N = k, K = pixels, reduced over pixel chunks.
+// K = 9 c_in (k = t c_in + c), computed on LDS-staged tiles (k_conv3).  The
+// weight gradient is the GEMM with M = output channels, N = k, K = pixels,
+// reduced over pixel chunks (k_wgrad, k_reduce_chunks).
 #include <hip/hip_runtime.h>
 
 #include "net_internal.h"
