@@ -524,6 +524,8 @@ smg_status Engine::finish_dynamic(int target, hipStream_t st, int* cycles_run) {
 smg_status Engine::autotune(int target, hipStream_t st, std::string* report) {
   std::string* err = report;
   const int P = (int)P_.size();
+  // plane-count buckets; a launch takes the configuration of the first
+  // bucket that holds its planes
   std::vector<int> caps;
   for (int c : {2, 8, 32}) if (c < n_total_) caps.push_back(c);
   caps.push_back(n_total_);
@@ -539,7 +541,17 @@ smg_status Engine::autotune(int target, hipStream_t st, std::string* report) {
   // kTuneTie of the fastest is kept, so that near-equal candidates do not
   // trade places from one process to the next on timing noise.
   constexpr float kTuneTie = 1.03f;
-  for (int cap : caps) {
+  for (size_t ci = 0; ci < caps.size(); ++ci) {
+    const int cap = caps[ci];
+    // a bucket serves every launch of (lo, cap] planes: candidates are timed
+    // at its top, middle and bottom plane counts, since a shape that fills
+    // the device exactly at the top can leave a partly filled last round of
+    // blocks below it
+    const int lo = ci > 0 ? caps[ci - 1] : 0;
+    std::vector<int> counts{cap};
+    const int mid = lo + (cap - lo + 1) / 2;
+    if (mid > lo && mid < cap) counts.push_back(mid);
+    if (lo + 1 < cap && lo + 1 != mid) counts.push_back(lo + 1);
     std::vector<std::pair<MGConfig, float>> cand;
     for (int off = 0; off < 3; ++off) {
       bool any_new = false;
@@ -551,7 +563,7 @@ smg_status Engine::autotune(int target, hipStream_t st, std::string* report) {
         if (first_min_[q] + off <= (int)P_[q].L.size() - 1) any_new = true;
       }
       if (off > 0 && !any_new) break;
-      for (int tb : {256, 384, 512, 768, 1024, 2048}) {
+      for (int tb : {256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096}) {
         c.target_blocks = tb;
         // stage the candidate in the scratch slot
         std::vector<LvJob> lv;
@@ -567,18 +579,19 @@ smg_status Engine::autotune(int target, hipStream_t st, std::string* report) {
         if ((int)cfg_.size() <= scratch) cfg_.resize(scratch + 1, c);
         cfg_[scratch] = c;
         smg_status s = vcycle_all(target, cap, scratch, st);
-        if (s == SMG_OK) {
+        float ms = 0.f;
+        for (size_t k = 0; k < counts.size() && s == SMG_OK; ++k) {
           EHIP(hipEventRecord(e0, st));
-          for (int r = 0; r < 5 && s == SMG_OK; ++r) s = vcycle_all(target, cap, scratch, st);
+          for (int r = 0; r < 5 && s == SMG_OK; ++r) s = vcycle_all(target, counts[k], scratch, st);
           EHIP(hipEventRecord(e1, st));
           EHIP(hipEventSynchronize(e1));
+          float t = 0.f;
+          EHIP(hipEventElapsedTime(&t, e0, e1));
+          ms += t / 5.f;
         }
         cfg_[scratch] = keep;
         if (s != SMG_OK) return s;
-        float ms = 0.f;
-        EHIP(hipEventElapsedTime(&ms, e0, e1));
-        ms /= 5.f;
-        rep += strprintf("planes %d: fused from +%d, %d blocks: %.1f us\n", cap, off, tb, 1e3 * ms);
+        rep += strprintf("planes %d..%d: fused from +%d, %d blocks: %.1f us\n", lo + 1, cap, off, tb, 1e3 * ms);
         cand.emplace_back(c, ms);
       }
     }
