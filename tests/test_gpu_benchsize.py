@@ -20,8 +20,8 @@ import pytest
 
 from oracle import fourier
 from oracle.geometry import GridSpec, cell_centres, cell_volumes_3d
-from oracle.james import boundary_ghost_values, dgf_tables, screening_mass
 from oracle.solve import OraclePlan
+from tests.oracle_modes import oracle_modes
 from workloads import configs
 
 torch = pytest.importorskip("torch")
@@ -63,31 +63,12 @@ def test_c2_bench_configuration_matches_oracle(precision, tol, bound):
         assert err < bound, (k, err)
 
 
-def _oracle_modes(spec, rho, modes):
-    """Phi^m of the sampled modes through the seven steps, with DGF tables of
-    those modes only (every mode is independent after the forward FFT)."""
-    op = OraclePlan(spec, dgf=np.zeros((spec.n_modes, 1, 1)))
-    f = op.source_modes(rho)
-    gh = op.ghosts
-    out = {}
-    for m in modes:
-        print(f"[oracle] mode {m}", flush=True)
-        psi = op.lu(m).solve(f[m].real.ravel().copy()) + 1j * op.lu(m).solve(f[m].imag.ravel().copy())
-        psi = psi.reshape(spec.n_a, spec.n_b)
-        sigma = screening_mass(spec, gh, psi[None])[0]
-        theta = dgf_tables(spec, modes=[m])[0] @ sigma
-        f2 = f[m] + op.op.dirichlet_rhs(boundary_ghost_values(spec, gh, -theta))
-        phi = op.lu(m).solve(f2.real.ravel().copy()) + 1j * op.lu(m).solve(f2.imag.ravel().copy())
-        out[m] = phi.reshape(spec.n_a, spec.n_b)
-    return out
-
-
 def test_c5_snapshot_sampled_modes_match_oracle():
     spec = GridSpec(**configs.GRIDS["c5"])
     a, b, p = cell_centres(spec)
     rho = configs.density("c5", a, b, p)
     modes = [0, 1, 2, 64, 128]
-    ref = _oracle_modes(spec, rho, modes)
+    ref = oracle_modes(spec, rho, modes)
     plan = _chosen(spec, "mixed")
     rd = torch.from_numpy(rho).cuda()
     for k in range(2):
