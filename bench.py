@@ -6,16 +6,18 @@ form): the orbiting-blob trajectory on the 256x128x256 logarithmic sphere.
 One step = one full solve (azimuthal FFT -> multigrid solve 1 -> screening
 mass + DGF convolution -> multigrid solve 2 -> inverse FFT) of the next
 snapshot's density to relative residual --tol (1e-8) on every mode, warm
-started from the previous step, modes 0..4 starting from the learned guess
-where the judge takes it.  The chosen form: FP32/FP64 iterative refinement,
+started from the previous steps: modes 0..4 from the learned guess where the
+judge takes it, the other modes from the linear extrapolation of their last
+two solutions.  The chosen form: FP32/FP64 iterative refinement,
 per-mode cycle schedules replayed as HIP graphs, autotuned launch shapes,
 smoothing steps chosen at setup, learned initial guess.  The network is
 trained at setup on 8 method-generated trajectories (seeds 50-57); the DGF
 tables, tuning and training are one-time setup, outside the timed region,
 as the DGF is in the paper.  --steps K times snapshots 1..K (snapshot 0 is
 the cold start of the trajectory), after --warmup W untimed passes over the
-same snapshots.  Reported next to it: the same trajectory with the previous
-step's solution as the guess (no network), the plain GPU form (FP64, host
+same snapshots.  Reported next to it: the same trajectory with the
+extrapolated guess for every mode (no network) and with the previous step's
+solution as the guess (no network, no extrapolation), the plain GPU form (FP64, host
 reads after every V-cycle, red-black SOR coarsest solve, V(2,2), no graph),
 cold solves of the 128x64x128 sphere and of one 256x128x256 snapshot, the
 per-launch roofline of the dominant kernel class, the error of a timed
@@ -208,16 +210,18 @@ def cpu_baseline_from_pool(pool, rhos, budget_cpu_s, label):
     return base, results
 
 
-def _plan(smg, g, form, line_solver, max_cycles=60):
+def _plan(smg, g, form, line_solver, max_cycles=60, extrapolate=False):
     """The chosen form (mixed precision, scheduled graph replay, autotuned
     launch shapes, smoothing steps chosen at setup: V(1,1) when the finest
     level is smoothed by whole-grid launches, else V(2,2)) or the plain GPU
     form (FP64, host reads after every V-cycle, built-in launch shapes, the
     paper's SOR line smoother, V(2,2), red-black SOR on the 128-cell
-    coarsest level)."""
+    coarsest level).  extrapolate: the plan keeps two previous solutions for
+    the extrapolated warm start."""
     if form == "chosen":
         return smg.Plan(**g, precision="mixed", launch="graph", autotune=True, line_solver=line_solver,
-                        max_cycles=max_cycles, coarse_cells=COARSE_CELLS, nu_pre=smg.NU_AUTO, nu_post=smg.NU_AUTO)
+                        max_cycles=max_cycles, coarse_cells=COARSE_CELLS, nu_pre=smg.NU_AUTO, nu_post=smg.NU_AUTO,
+                        warm_extrapolate=extrapolate)
     return smg.Plan(**g, precision="fp64", launch="dynamic", autotune=False, line_solver="sor", max_cycles=max_cycles,
                     coarse_solver="sor")
 
@@ -397,7 +401,7 @@ def bench_trajectory(args, smg, configs, torch, pool):
     if pool is not None:
         pool.ready()
     t0 = time.perf_counter()
-    plan = _plan(smg, g, "chosen", args.line_solver).setup("cuda:0")
+    plan = _plan(smg, g, "chosen", args.line_solver, extrapolate=True).setup("cuda:0")
     a, b, ph, dv = plan.geometry()
     net = smg.Net()
     net.set_params(init_params(0))
@@ -430,11 +434,15 @@ def bench_trajectory(args, smg, configs, torch, pool):
     phi = torch.empty_like(rhos[0])
     taken = [0]
 
-    def run(pl, use_net, with_info=False, profile=False, mark=False):
+    # initial-guess forms of the warm solves: (network for modes 0..m_max, extrapolation of the other modes)
+    LEARNED, EXTRAP, PREVIOUS = (True, True), (False, True), (False, False)
+
+    def run(pl, form, with_info=False, profile=False, mark=False):
         """Cold solve of snapshot 0, then snapshots 1..K warm; returns the time
         of the warm solves and their low-mode cycles.  With mark set, a short
         spin kernel runs just before and just after the warm solves (outside
         the timed span), so that a kernel trace can pick out their launches."""
+        use_net, ext = form
         pl.solve_nosync(rhos[0], phi, tol=args.tol)
         cyc = []
         if mark:
@@ -445,13 +453,14 @@ def bench_trajectory(args, smg, configs, torch, pool):
         t = time.perf_counter()
         for k in range(1, K + 1):
             if with_info:
-                _, info = pl.solve(rhos[k], tol=args.tol, warm=True, out=phi, net=use_net)
+                _, info = pl.solve(rhos[k], tol=args.tol, warm=True, out=phi, net=use_net, extrapolate=ext)
                 if k >= 2:
-                    cyc.append(learn.low_mode_cycles(info, m_max))
+                    cyc.append((learn.low_mode_cycles(info, m_max), int(info["cycles1"].max()),
+                                int(info["cycles2"].max()), info["total_cycles"]))
                     if use_net:
                         taken[0] += int(pl.net_used().sum())
             else:
-                pl.solve_nosync(rhos[k], phi, tol=args.tol, warm=True, net=use_net)
+                pl.solve_nosync(rhos[k], phi, tol=args.tol, warm=True, net=use_net, extrapolate=ext)
         torch.cuda.synchronize()
         el = time.perf_counter() - t
         stats = pl.profile_end() if profile else None
@@ -459,23 +468,33 @@ def bench_trajectory(args, smg, configs, torch, pool):
             torch.cuda._sleep(64)
         return el, cyc, stats
 
-    _, cyc_net, _ = run(plan, True, with_info=True)
-    _, cyc_prev, _ = run(plan, False, with_info=True)
+    _, cyc_net, _ = run(plan, LEARNED, with_info=True)
+    _, cyc_ext, _ = run(plan, EXTRAP, with_info=True)
+    _, cyc_prev, _ = run(plan, PREVIOUS, with_info=True)
     for _ in range(max(args.warmup, 1)):
-        run(plan, True)
-    dt_net, _, _ = run(plan, True, mark=True)
+        run(plan, LEARNED)
+    dt_net, _, _ = run(plan, LEARNED, mark=True)
     phi_last = phi.cpu().numpy()
     log(f"timed {K} warm solves with the learned guess: {K / dt_net:.2f} solves/s")
-    _, _, stats = run(plan, True, profile=True, mark=True)
+    _, _, stats = run(plan, LEARNED, profile=True, mark=True)
     roof, kern = _roofline(stats, "c5", K)
     for _ in range(max(args.warmup, 1)):
-        run(plan, False)
-    dt_prev, _, _ = run(plan, False)
+        run(plan, EXTRAP)
+    dt_ext, _, _ = run(plan, EXTRAP)
+    log(f"extrapolated guess: {K / dt_ext:.2f} solves/s")
+    for _ in range(max(args.warmup, 1)):
+        run(plan, PREVIOUS)
+    dt_prev, _, _ = run(plan, PREVIOUS)
     log(f"previous-step guess: {K / dt_prev:.2f} solves/s")
     zero = []
     for r in rhos[:4]:
         _, info = plan.solve(r, tol=args.tol, out=phi)
         zero.append(learn.low_mode_cycles(info, m_max))
+
+    def cycles(c):
+        c = np.asarray(c, dtype=float)
+        return dict(low_modes=round(float(c[:, 0].mean()), 2), slowest_mode_solve1=round(float(c[:, 1].mean()), 2),
+                    slowest_mode_solve2=round(float(c[:, 2].mean()), 2), all_modes=round(float(c[:, 3].mean()), 1))
     out = {
         "metric": "Poisson solves/s at rel. residual 1e-8",
         "value": round(K / dt_net, 3),
@@ -492,25 +511,28 @@ def bench_trajectory(args, smg, configs, torch, pool):
         "config": {"workload": f"c5 trajectory: {configs.DESCRIPTION['c5']}, snapshots 1..{K} warm-started",
                    "tol": args.tol,
                    "form": "chosen: mixed precision, graph-replayed per-mode schedules, autotuned launch shapes, "
-                           f"learned guess of modes 0..{m_max}",
+                           f"learned guess of modes 0..{m_max}, the other modes extrapolated from their last two "
+                           "solutions",
                    "line_solver": args.line_solver,
                    "step": "one warm-started solve of the next snapshot",
                    "train": {"trajectories": len(seeds), "samples": n, "steps": args.train_steps,
                              "loss_fixed_64_samples": [float("%.4g" % eval_before), float("%.4g" % eval_after)],
                              "seconds": round(t_train, 1)},
-                   "low_mode_v_cycles_per_step": {"zero_guess": round(float(np.mean(zero)), 2),
-                                                  "previous_step": round(float(np.mean(cyc_prev)), 2),
-                                                  "network": round(float(np.mean(cyc_net)), 2)},
+                   "low_mode_v_cycles_per_step": {"zero_guess": round(float(np.mean(zero)), 2)},
+                   "v_cycles_per_step": {"learned": cycles(cyc_net), "extrapolated": cycles(cyc_ext),
+                                         "previous_step": cycles(cyc_prev)},
                    "network_guess_taken": f"{taken[0]} of {2 * (m_max + 1) * max(K - 1, 0)} mode solves"},
         "roofline": roof,
         "kernels_per_step": kern,
+        "extrapolated_guess": dict(value=round(K / dt_ext, 3), unit="solves/s", ms_per_step=round(1e3 * dt_ext / K, 3),
+                                   form="chosen form without the network, every mode extrapolated"),
         "previous_step_guess": dict(value=round(K / dt_prev, 3), unit="solves/s", ms_per_step=round(1e3 * dt_prev / K, 3),
-                                    form="chosen form without the network"),
+                                    form="chosen form without the network and the extrapolation"),
     }
     if not args.no_plain:
         pl = _plan(smg, g, "plain", args.line_solver).setup("cuda:0")
-        run(pl, False)
-        dtp, _, _ = run(pl, False)
+        run(pl, PREVIOUS)
+        dtp, _, _ = run(pl, PREVIOUS)
         out["plain_gpu"] = dict(value=round(K / dtp, 3), unit="solves/s", ms_per_step=round(1e3 * dtp / K, 3),
                                 form="FP64, previous-step warm start, host reads after every V-cycle, built-in "
                                      "launch shapes, SOR lines, V(2,2), red-black SOR coarsest level, no network")

@@ -108,8 +108,10 @@ typedef struct {
                             unconverged modes after every V-cycle (no graph). */
   int autotune;          /* 1: at setup, time V-cycles under candidate launch
                             shapes (where the in-LDS coarse cycle starts,
-                            smoother blocks per launch) for 2, 8, 32 and all
-                            planes, and keep the fastest [0: built-in rule] */
+                            smoother blocks per launch) for the plane-count
+                            buckets up to 2, 8, 32 and all planes, each at
+                            its top, middle and bottom count, and keep the
+                            fastest [0: built-in rule] */
   int coarse_cells;      /* coarsening stops at the first level with at most
                             this many cells, after at least one halving (the
                             paper leaves the depth open, Sec. 3.3); that level
@@ -122,6 +124,10 @@ typedef struct {
                             SOR with the 2D omega of Appendix A, from zero
                             until the residual drops by 1e-10 (Sec. 3.3; the
                             coarsest level must then have <= 1024 cells) */
+  int warm_extrapolate;  /* 1: keep the solutions of the two previous solves
+                            so that warm solves can start from their linear
+                            extrapolation (flag SMG_WARM_EXTRAP); costs two
+                            more sets of FP64 mode planes of workspace [0] */
 } smg_opts;
 
 enum { SMG_COARSE_EXACT = 0, SMG_COARSE_SOR = 1 };
@@ -146,11 +152,27 @@ typedef struct {
                                otherwise from zero                         */
 #define SMG_TIMINGS     2u  /* fill the component times of smg_info        */
 #define SMG_NET_GUESS   4u  /* with SMG_WARM_PREV and an attached network:
-                               modes 0..m_max start from the network's
-                               prediction wherever, after one smoothing step
-                               of each, its defect norm is below that of the
-                               previous step's solution (the multigrid then
-                               runs to the same tolerance)                 */
+                               in the potential's multigrid solve (solve 2,
+                               Phi^m) modes 0..m_max start from the
+                               network's prediction wherever, after one
+                               smoothing step of each, its defect norm is
+                               below that of the extrapolation of the last
+                               two solutions (the previous solution before
+                               two exist), else from that extrapolation;
+                               solve 1 (Psi^m) starts them like the other
+                               modes.  The multigrid runs to the same
+                               tolerance either way.                       */
+#define SMG_WARM_EXTRAP 8u  /* with SMG_WARM_PREV on a plan created with
+                               opts.warm_extrapolate: each multigrid solve
+                               starts its modes from 2 u_{t-1} - u_{t-2},
+                               the linear extrapolation of its last two
+                               solutions (with SMG_NET_GUESS, the modes
+                               above m_max; the network's candidate already
+                               extrapolates), once two warm-startable
+                               solutions exist (a solve without this flag
+                               leaves one); otherwise from u_{t-1}.  Only the
+                               cycle count depends on the guess.  SMG_EINVAL
+                               on a plan without opts.warm_extrapolate.    */
 
 typedef struct smg_plan smg_plan;
 
@@ -318,11 +340,13 @@ smg_status smg_net_conv3_wgrad_noalloc(const unsigned short *g_dev, int c_out, c
  * values of f_t, f_t - f_{t-1} and u_{t-1}, and s_o, the scale of the
  * output, the RMS of u_{t-1} - u_{t-2}; before two warm steps have run,
  * and for a static plane (last change below 1e-4 of its RMS), channels 6
- * and 7 are zero) before each of its two multigrid solves and
+ * and 7 are zero) before the potential's multigrid solve (solve 2) and
  * starts every mode from the better (defect norms after one smoothing step
- * of each) of the previous solution and the candidate u_{t-1} + (u_{t-1} -
- * u_{t-2}) + s_o y: the linear extrapolation plus the network's correction
- * y (without u_{t-2}: u_{t-1} + s_o y).
+ * of each) of the baseline u_{t-1} + (u_{t-1} - u_{t-2}), the linear
+ * extrapolation (u_{t-1} before u_{t-2} exists, and on a static part), and
+ * the candidate baseline + s_o y, the network's correction y added.  The
+ * inputs of solve 1 are built as well (they are recorded as training
+ * samples), but its modes take no network guess.
  * A NULL net detaches. */
 size_t smg_plan_net_work_bytes(const smg_plan *plan, const smg_net *net, int m_max);
 smg_status smg_plan_attach_net(smg_plan *plan, smg_net *net, int m_max, void *work_dev, size_t work_bytes,
@@ -338,7 +362,7 @@ smg_status smg_plan_attach_net(smg_plan *plan, smg_net *net, int m_max, void *wo
 smg_status smg_plan_record(smg_plan *plan, float *samples_dev, int capacity, void *stream);
 int smg_plan_recorded(const smg_plan *plan, void *stream);
 /* Which modes took the network's guess in the last SMG_NET_GUESS solve:
- * used_host[t * (m_max + 1) + m] for solve t = 0 (Psi), 1 (Phi). */
+ * used_host[t * (m_max + 1) + m] for solve t = 0 (Psi: always 0), 1 (Phi). */
 smg_status smg_plan_net_used(const smg_plan *plan, int *used_host, void *stream);
 /* The learned-guess step of multigrid solve t (0: Psi, 1: Phi) of a
  * warm-started SMG_NET_GUESS solve, on caller planes, for step-level checks.

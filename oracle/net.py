@@ -329,6 +329,13 @@ def guess_candidate(uprev, y, sc, m_max, uprev2=None):
     return cand
 
 
+def guess_base(uprev, sc, m_max, uprev2=None):
+    """The start the judge weighs the candidate against: the candidate
+    without the network's correction, u_{t-1} + (u_{t-1} - u_{t-2}) on the
+    parts that change (u_{t-1} without uprev2 or on static parts)."""
+    return guess_candidate(uprev, np.zeros((2 * m_max + 1,) + np.shape(uprev)[1:]), sc, m_max, uprev2=uprev2)
+
+
 def guess_target(u, uprev, sc, m_max, uprev2=None):
     """The training target of each real image: the correction the candidate
     needs to become u_t, (u_t - u_{t-1} - (u_{t-1} - u_{t-2})) / s_o."""
@@ -345,8 +352,9 @@ def guess_target(u, uprev, sc, m_max, uprev2=None):
 def guess_judge(level, f, cand, uprev, m_max, n_sor=2, line_solver="sor"):
     """Per mode m <= m_max: 1 where the candidate's defect norm after one
     smoothing step (``level``: an oracle.multigrid.MGLevel of the finest
-    grid) is below that of the previous solution.  Returns (used, norm of
-    the candidate, norm of the previous solution)."""
+    grid) is below that of the other start ``uprev`` (in a solve: the
+    baseline of guess_base).  Returns (used, norm of the candidate, norm of
+    the other start)."""
     used = np.zeros(m_max + 1, dtype=int)
     nc = np.zeros(m_max + 1)
     nu = np.zeros(m_max + 1)

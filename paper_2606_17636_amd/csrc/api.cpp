@@ -232,6 +232,14 @@ struct smg_plan {
   Group grp;                // this plan alone
   std::string tune_report;
   PlanNet pn;
+  // extrapolated warm start (opts.warm_extrapolate): the solution before the
+  // last one per target, how many solutions of the target the plan holds
+  // in a form a warm solve can use (0, 1, or 2: w_psi/w_phi and w_xprev),
+  // and this solve's step (0 none, 1 keep u as the previous solution,
+  // 2 extrapolate), decided on the host before the body
+  size_t w_xprev[2] = {0, 0};
+  int xhave[2] = {0, 0};
+  int xstep[2] = {0, 0};
   // bumped whenever a buffer that captured solve graphs write to changes
   // (network attach, recording buffer); part of every group graph key, so a
   // batch holding this plan never replays a graph with the old pointers
@@ -284,6 +292,7 @@ static smg_status validate(const smg_grid& g, const smg_opts& o) {
     return fail(SMG_EINVAL, "coarse_cells must be 0 or in [16, 8192]");
   if (o.coarse_solver != SMG_COARSE_EXACT && o.coarse_solver != SMG_COARSE_SOR)
     return fail(SMG_EINVAL, "coarse_solver must be SMG_COARSE_EXACT or SMG_COARSE_SOR");
+  if (o.warm_extrapolate != 0 && o.warm_extrapolate != 1) return fail(SMG_EINVAL, "warm_extrapolate must be 0 or 1");
   return SMG_OK;
 }
 
@@ -406,6 +415,8 @@ extern "C" smg_status smg_plan_create(const smg_grid* grid, const smg_opts* opts
   p->w_phi = take(sizeof(double2) * M * plane);
   p->w_f = take(sizeof(double2) * M * plane);
   p->w_f2 = take(sizeof(double2) * M * plane);
+  if (p->opts.warm_extrapolate)
+    for (int t = 0; t < 2; ++t) p->w_xprev[t] = take(sizeof(double2) * M * plane);
   p->w_sigma = take(sizeof(double2) * (size_t)M * p->n_g);
   p->w_theta = take(sizeof(double2) * (size_t)M * p->n_g);
   p->w_gpot = take(sizeof(double) * (size_t)p->n_g * s.n_phi);
@@ -867,6 +878,7 @@ extern "C" smg_status smg_plan_setup(smg_plan* p, void* workspace, size_t bytes,
   p->ws = static_cast<char*>(workspace);
   p->ready = false;
   p->grp.reset();
+  p->xhave[0] = p->xhave[1] = 0;
   HIPCHK(hipMemcpyAsync(p->ws + p->w_blob, p->blob.bytes.data(), p->blob.bytes.size(), hipMemcpyHostToDevice, st));
   p->levels.clear();
   for (size_t l = 0; l < p->H.lv.size(); ++l)
@@ -988,13 +1000,15 @@ static smg_status net_before(smg_plan* p, int t, bool warm, bool guess, hipStrea
   if (!guess) return SMG_OK;
   STCHK(pn.net->def.forward(pn.work, pn.wl, st, false));
   double2* cand = reinterpret_cast<double2*>(pn.work + pn.o_cand);
+  // the candidate and the baseline it is judged against (the linear
+  // extrapolation, or the previous solution before two exist), the latter
+  // straight into the judge's second buffer
   HIPCHK(smgg::candidate(uprev, pn.prev2_ok[t] ? uprev2 : nullptr, reinterpret_cast<const float*>(pn.work + pn.wl.y), sc,
-                         plane, pn.m_max, cand, st));
-  // judge: defect norms after one smoothing step of each candidate (the
+                         plane, pn.m_max, cand, reinterpret_cast<double2*>(pn.work + pn.o_us), st));
+  // judge: defect norms after one smoothing step of each start (the
   // smoothing removes the rough part of an error, which the multigrid
   // removes in its first sweep anyway; what is left decides the cycles)
   HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_cs), cand, np, st));
-  HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_us), uprev, np, st));
   BatchRef b{pn.m_max + 1, nullptr, reinterpret_cast<const int*>(pn.work + pn.o_list)};
   const LvJob* dl = reinterpret_cast<const LvJob*>(pn.work + pn.o_lv) + 2 * t;
   const bool exact = p->opts.line_solver == SMG_LINE_EXACT;
@@ -1006,7 +1020,7 @@ static smg_status net_before(smg_plan* p, int t, bool warm, bool guess, hipStrea
   double* pu = pc + (size_t)(pn.m_max + 1) * pn.nblk;
   HIPCHK(smgk::mg_norm_partial(dj, &pn.hjobs[2 * t], 1, b, true, pc, pn.nblk, st));
   HIPCHK(smgk::mg_norm_partial(dj + 1, &pn.hjobs[2 * t + 1], 1, b, true, pu, pn.nblk, st));
-  HIPCHK(smgg::select(pc, pu, pn.nblk, cand, target_u(p, t), plane, pn.m_max,
+  HIPCHK(smgg::select(pc, pu, pn.nblk, cand, uprev, pn.prev2_ok[t] ? uprev2 : nullptr, sc, target_u(p, t), plane, pn.m_max,
                       reinterpret_cast<int*>(pn.work + pn.o_used) + t * (pn.m_max + 1), st));
   return SMG_OK;
 }
@@ -1038,6 +1052,24 @@ static smg_status net_after(smg_plan* p, int t, bool warm, hipStream_t st) {
 // enqueued up front (no host synchronisation); otherwise each solve reads
 // its list length after every cycle.  ev (optional) records 3 component
 // boundaries.
+// Extrapolated warm start of target t (decided on the host: p->xstep[t]):
+// the last solution is kept as the one before, and every mode the learned
+// guess does not handle in this solve starts from 2 u_{t-1} - u_{t-2}.
+// Runs after net_before, which has read modes 0..m_max of u_{t-1} (and,
+// with the guess, replaced them by the chosen candidate: for those modes
+// the kept solution is net_before's copy of u_{t-1}).
+static smg_status warm_extrapolate(smg_plan* p, int t, bool warm, bool guess, hipStream_t st) {
+  if (!warm || p->xstep[t] == 0) return SMG_OK;
+  const size_t plane = (size_t)p->spec.n_a * p->spec.n_b, n = (size_t)p->M * plane;
+  const PlanNet& pn = p->pn;
+  const bool net = guess && pn.net && pn.prev_ok[t];
+  const size_t nlow = net ? (size_t)(pn.m_max + 1) * plane : 0;
+  double2* prev = p->dptr(p->w_xprev[t]);
+  HIPCHK(smgg::extrapolate(target_u(p, t), prev, n, p->xstep[t] == 1 ? n : nlow, st));
+  if (net) HIPCHK(smgk::copy_planes(prev, reinterpret_cast<const double2*>(pn.work + pn.o_uprev[t]), nlow, st));
+  return SMG_OK;
+}
+
 static smg_status group_body(Group& g, double tol, bool warm, unsigned flags, const std::vector<int>* sched0,
                              const std::vector<int>* sched1, hipStream_t st, hipEvent_t* ev) {
   Engine& e = *g.eng;
@@ -1045,7 +1077,10 @@ static smg_status group_body(Group& g, double tol, bool warm, unsigned flags, co
   for (smg_plan* p : g.plans)  // samples of a solve the host has to finish are withdrawn (group_solve)
     if (p->pn.net && p->pn.samples)
       HIPCHK(hipMemcpyAsync(p->pn.work + p->pn.o_rec0, p->pn.work + p->pn.o_rec, sizeof(int), hipMemcpyDeviceToDevice, st));
-  for (smg_plan* p : g.plans) STCHK(net_before(p, 0, warm, guess, st));
+  // the network guesses the potential's solve (solve 2) only; solve 1 (Psi,
+  // zero ghosts) keeps the network's bookkeeping and starts like the other modes
+  for (smg_plan* p : g.plans) STCHK(net_before(p, 0, warm, false, st));
+  for (smg_plan* p : g.plans) STCHK(warm_extrapolate(p, 0, warm, false, st));
   STCHK(e.start(0, tol, kFloor, warm, g.max_cycles, st));
   if (sched0) {
     for (int cap : *sched0) STCHK(e.cycle(0, cap, st));
@@ -1057,6 +1092,7 @@ static smg_status group_body(Group& g, double tol, bool warm, unsigned flags, co
   STCHK(james_all(g, st));
   if (ev) HIPCHK(hipEventRecord(ev[1], st));
   for (smg_plan* p : g.plans) STCHK(net_before(p, 1, warm, guess, st));
+  for (smg_plan* p : g.plans) STCHK(warm_extrapolate(p, 1, warm, guess, st));
   STCHK(e.start(1, tol, kFloor, warm, g.max_cycles, st));
   if (sched1) {
     for (int cap : *sched1) STCHK(e.cycle(1, cap, st));
@@ -1079,6 +1115,7 @@ static smg_status group_graph(Group& g, double tol, bool warm, unsigned flags, c
                                   16 * p->pn.prev2_ok[0] + 32 * p->pn.prev2_ok[1]
                             : 0);
     key.push_back((int)p->gen);
+    key.push_back(p->xstep[0] + 3 * p->xstep[1]);
   }
   long long tb;
   std::memcpy(&tb, &tol, sizeof(tb));
@@ -1163,6 +1200,12 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
   } guard{ev, timings};
   const bool warm = (flags & SMG_WARM_PREV) && g.have_prev;
   const int wk = warm ? 1 : 0;
+  const bool extrap = (flags & SMG_WARM_EXTRAP) != 0;
+  for (smg_plan* p : g.plans) {
+    if (extrap && !p->opts.warm_extrapolate)
+      return fail(SMG_EINVAL, "SMG_WARM_EXTRAP needs a plan created with opts.warm_extrapolate");
+    for (int t = 0; t < 2; ++t) p->xstep[t] = extrap && warm ? std::min(p->xhave[t], 2) : 0;
+  }
   // learned-guess bookkeeping, decided on the host (a replayed graph runs
   // none of the body's host code): a guess step of target t runs when the
   // solve is warm and the previous right-hand side is kept; it sees the
@@ -1200,6 +1243,8 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
   STCHK(fft_inverse_all(g, phi, st));
   if (timings) HIPCHK(hipEventRecord(ev[5], st));
   g.have_prev = true;
+  for (smg_plan* p : g.plans)
+    for (int t = 0; t < 2; ++t) p->xhave[t] = p->xstep[t] > 0 ? 2 : 1;
   for (int q = 0; q < P; ++q)
     for (int t = 0; t < 2; ++t) g.plans[q]->pn.have_u[t] = guess_step[q][t];
   // per-mode state of both solves (one synchronisation); modes that needed
@@ -1434,6 +1479,7 @@ extern "C" smg_status smg_net_guess_step(smg_plan* p, int t, const double* f, co
   pn.have_u[0] = pn.have_u[1] = false;
   // the plan's solve state now holds these planes: the next solve starts cold
   p->grp.have_prev = false;
+  p->xhave[0] = p->xhave[1] = 0;
   STCHK(sb);
   HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(guess), target_u(p, t), np, st));
   const size_t img = (size_t)pn.n_img * p->spec.n_a * p->spec.n_b;
@@ -1564,6 +1610,7 @@ static smg_status stage_in(smg_plan* p, const double* f, const double* u, hipStr
   if (f) HIPCHK(smgk::copy_planes(p->dptr(p->w_f), reinterpret_cast<const double2*>(f), n, st));
   if (u) HIPCHK(smgk::copy_planes(p->dptr(p->w_psi), reinterpret_cast<const double2*>(u), n, st));
   p->grp.have_prev = false;
+  p->xhave[0] = p->xhave[1] = 0;
   return SMG_OK;
 }
 

@@ -15,11 +15,14 @@ hipError_t scales(const double2* f, const double2* fprev, const double2* uprev, 
 // uprev2: the solution two steps back (channel 6 = (uprev - uprev2) / s_o), or null
 hipError_t assemble(const double2* f, const double2* fprev, const double2* uprev, const double2* uprev2, const double* sc,
                     int na, int nb, int n_img, float* x, hipStream_t st);
-// cand = uprev + (uprev - uprev2 if uprev2) + s_o y
+// base = uprev + (uprev - uprev2 if uprev2; not on static parts), cand = base + s_o y
 hipError_t candidate(const double2* uprev, const double2* uprev2, const float* y, const double* sc, int plane, int m_max,
-                     double2* cand, hipStream_t st);
-hipError_t select(const double* pc, const double* pu, int nblk, const double2* cand, double2* u, int plane, int m_max,
-                  int* used, hipStream_t st);
+                     double2* cand, double2* base, hipStream_t st);
+// per mode: u = cand where pc's norm is below pu's, else base (recomputed)
+hipError_t select(const double* pc, const double* pu, int nblk, const double2* cand, const double2* uprev,
+                  const double2* uprev2, const double* sc, double2* u, int plane, int m_max, int* used, hipStream_t st);
 hipError_t record(const float* x, const double2* u, const double2* uprev, const double2* uprev2, const double* sc,
                   int plane, int n_img, int* count, int capacity, float* samples, hipStream_t st);
+// warm start from two solutions (n values): prev <- u; u <- 2 u - prev from value lo on
+hipError_t extrapolate(double2* u, double2* prev, size_t n, size_t lo, hipStream_t st);
 }  // namespace smgg

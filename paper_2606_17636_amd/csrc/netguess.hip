@@ -1,8 +1,10 @@
 // The learned guess inside a solve: network inputs from the mode planes of
 // modes 0..m_max (one image per real or imaginary part), the candidate
-// (linear extrapolation of the last two solutions + s_o * net(x)), the choice per mode between it and the previous
-// step's solution by their defect norms, training-sample recording, and the
-// bookkeeping of the previous step's right-hand side.
+// (linear extrapolation of the last two solutions + s_o * net(x)), the choice per mode between it and the
+// extrapolation alone (the previous step's solution before two exist) by their defect norms, training-sample
+// recording, and the
+// bookkeeping of the previous step's right-hand side.  Also the extrapolated
+// warm start of the modes the network does not handle.
 #include "netguess.h"
 
 #include <algorithm>
@@ -118,38 +120,52 @@ __global__ void k_assemble(const double2* __restrict__ f, const double2* __restr
   }
 }
 
-// cand = u_prev + (u_prev - u_prev2) + s_o * y: the linear extrapolation
-// of the last two solutions (u_prev alone when there is no u_prev2) plus
-// the network's correction, both parts of modes 0..m_max (m = 0 has no
-// imaginary image: its imaginary part is only extrapolated)
+// The baseline of value t (mode m = t / plane): u_prev + (u_prev -
+// u_prev2), the linear extrapolation of the last two solutions (u_prev alone
+// when there is no u_prev2, or where the part is static: s_o = 0; the
+// imaginary part of m = 0 has no image and follows the real part's kind)
+__device__ __forceinline__ double2 guess_base(const double2* __restrict__ uprev, const double2* __restrict__ uprev2,
+                                              const double* __restrict__ sc, int m, size_t t, double& sr, double& si) {
+  double2 v = uprev[t];
+  const int kr = m == 0 ? 0 : 2 * m - 1;
+  sr = sc[4 * kr + 3];
+  si = m > 0 ? sc[4 * (2 * m) + 3] : sr;
+  if (uprev2) {
+    const double2 w = uprev2[t];
+    if (sr > 0.0) v.x += v.x - w.x;
+    if (si > 0.0) v.y += v.y - w.y;
+  }
+  return v;
+}
+
+// cand = base + s_o * y (the network's correction), both parts of modes
+// 0..m_max (m = 0 has no imaginary image: its imaginary part is only
+// extrapolated); base = the baseline alone, the judge's other start
 __global__ void k_candidate(const double2* __restrict__ uprev, const double2* __restrict__ uprev2,
                             const float* __restrict__ y, const double* __restrict__ sc, int plane, int m_max,
-                            double2* __restrict__ cand) {
+                            double2* __restrict__ cand, double2* __restrict__ base) {
   const size_t total = (size_t)(m_max + 1) * plane;
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
     const int m = (int)(t / plane), q = (int)(t - (size_t)m * plane);
-    double2 v = uprev[t];
+    double sr, si;
+    double2 v = guess_base(uprev, uprev2, sc, m, t, sr, si);
+    base[t] = v;
     const int kr = m == 0 ? 0 : 2 * m - 1;
-    // static parts (s_o = 0) keep u_prev; the imaginary part of m = 0 has no
-    // image and follows the real part's kind
-    const double sr = sc[4 * kr + 3], si = m > 0 ? sc[4 * (2 * m) + 3] : sr;
-    if (uprev2) {
-      const double2 w = uprev2[t];
-      if (sr > 0.0) v.x += v.x - w.x;
-      if (si > 0.0) v.y += v.y - w.y;
-    }
     v.x += sr * (double)y[(size_t)kr * plane + q];
     if (m > 0) v.y += si * (double)y[(size_t)(2 * m) * plane + q];
     cand[t] = v;
   }
 }
 
-// per mode: keep the candidate where its defect norm is the smaller one.
-// Grid (blocks per plane, m_max + 1): every block sums its mode's partial
-// norms (nblk each) and copies its slice of the plane when the candidate
-// wins; block 0 of the mode records the choice.
+// per mode: the candidate where its defect norm is the smaller one, else
+// the baseline (recomputed, with the arithmetic of k_candidate).  Grid
+// (blocks per plane, m_max + 1): every block sums its mode's partial norms
+// (nblk each) and writes its slice of the plane; block 0 of the mode records
+// the choice.
 __global__ void k_select(const double* __restrict__ pc, const double* __restrict__ pu, int nblk,
-                         const double2* __restrict__ cand, double2* __restrict__ u, int plane, int* __restrict__ used) {
+                         const double2* __restrict__ cand, const double2* __restrict__ uprev,
+                         const double2* __restrict__ uprev2, const double* __restrict__ sc, double2* __restrict__ u,
+                         int plane, int* __restrict__ used) {
   __shared__ int take;
   const int m = blockIdx.y;
   if (threadIdx.x == 0) {
@@ -162,9 +178,11 @@ __global__ void k_select(const double* __restrict__ pc, const double* __restrict
     if (blockIdx.x == 0) used[m] = take;
   }
   __syncthreads();
-  if (!take) return;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < plane; t += gridDim.x * blockDim.x)
-    u[(size_t)m * plane + t] = cand[(size_t)m * plane + t];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < plane; t += gridDim.x * blockDim.x) {
+    const size_t k = (size_t)m * plane + t;
+    double sr, si;
+    u[k] = take ? cand[k] : guess_base(uprev, uprev2, sc, m, k, sr, si);
+  }
 }
 
 // training samples: (x, (u_t - u_prev - (u_prev - u_prev2)) / s_o) per
@@ -194,6 +212,16 @@ __global__ void k_advance(int* count, int n, int capacity) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *count = min(*count + n, capacity);
 }
 
+// prev <- u everywhere and, from value lo on, u <- 2 u - prev: the linear
+// extrapolation of the last two solutions (one FP64 rounding per value)
+__global__ void k_extrapolate(double2* __restrict__ u, double2* __restrict__ prev, size_t n, size_t lo) {
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const double2 x = u[t], q = prev[t];
+    if (t >= lo) u[t] = make_double2(2.0 * x.x - q.x, 2.0 * x.y - q.y);
+    prev[t] = x;
+  }
+}
+
 unsigned grid1(size_t n) {
   size_t g = (n + 255) / 256;
   return (unsigned)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
@@ -220,16 +248,17 @@ hipError_t assemble(const double2* f, const double2* fprev, const double2* uprev
 }
 
 hipError_t candidate(const double2* uprev, const double2* uprev2, const float* y, const double* sc, int plane, int m_max,
-                     double2* cand, hipStream_t st) {
+                     double2* cand, double2* base, hipStream_t st) {
   hipLaunchKernelGGL(k_candidate, dim3(grid1((size_t)(m_max + 1) * plane)), dim3(256), 0, st, uprev, uprev2, y, sc, plane,
-                     m_max, cand);
+                     m_max, cand, base);
   return hipGetLastError();
 }
 
-hipError_t select(const double* pc, const double* pu, int nblk, const double2* cand, double2* u, int plane, int m_max,
-                  int* used, hipStream_t st) {
+hipError_t select(const double* pc, const double* pu, int nblk, const double2* cand, const double2* uprev,
+                  const double2* uprev2, const double* sc, double2* u, int plane, int m_max, int* used, hipStream_t st) {
   const int per = std::max(1, std::min(64, (plane + 1023) / 1024));
-  hipLaunchKernelGGL(k_select, dim3(per, m_max + 1), dim3(256), 0, st, pc, pu, nblk, cand, u, plane, used);
+  hipLaunchKernelGGL(k_select, dim3(per, m_max + 1), dim3(256), 0, st, pc, pu, nblk, cand, uprev, uprev2, sc, u, plane,
+                     used);
   return hipGetLastError();
 }
 
@@ -238,6 +267,12 @@ hipError_t record(const float* x, const double2* u, const double2* uprev, const 
   hipLaunchKernelGGL(k_record, dim3(grid1((size_t)n_img * plane)), dim3(256), 0, st, x, u, uprev, uprev2, sc, plane, n_img,
                      count, capacity, samples);
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, count, n_img, capacity);
+  return hipGetLastError();
+}
+
+hipError_t extrapolate(double2* u, double2* prev, size_t n, size_t lo, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_extrapolate, dim3(grid1(n)), dim3(256), 0, st, u, prev, n, lo);
   return hipGetLastError();
 }
 

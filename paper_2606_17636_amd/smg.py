@@ -25,6 +25,7 @@ COARSE_EXACT, COARSE_SOR = 0, 1
 WARM_PREV = 1
 TIMINGS = 2
 NET_GUESS = 4
+WARM_EXTRAP = 8
 
 STATUS = {0: "SMG_OK", -1: "SMG_EINVAL", -2: "SMG_ENOCONV", -3: "SMG_EHIP", -4: "SMG_EWORKSPACE", -5: "SMG_ESTATE"}
 
@@ -46,7 +47,7 @@ class Opts(ctypes.Structure):
                 ("n_sor", ctypes.c_int), ("max_cycles", ctypes.c_int), ("dgf_method", ctypes.c_int),
                 ("n_pad", ctypes.c_int), ("dgf_tol", ctypes.c_double), ("line_solver", ctypes.c_int),
                 ("launch", ctypes.c_int), ("autotune", ctypes.c_int), ("coarse_cells", ctypes.c_int),
-                ("coarse_solver", ctypes.c_int)]
+                ("coarse_solver", ctypes.c_int), ("warm_extrapolate", ctypes.c_int)]
 
 
 _PI = ctypes.POINTER(ctypes.c_int)
@@ -174,7 +175,8 @@ class Plan:
 
     def __init__(self, geometry, radial, n_a, n_b, n_phi, a_min, a_max, b_min, b_max, G=1.0, precision=FP64,
                  nu_pre=2, nu_post=2, n_sor=2, max_cycles=60, dgf_method=DGF_AUTO, n_pad=16, dgf_tol=1e-13,
-                 line_solver=LINE_SOR, launch=LAUNCH_GRAPH, autotune=False, coarse_cells=0, coarse_solver=COARSE_EXACT):
+                 line_solver=LINE_SOR, launch=LAUNCH_GRAPH, autotune=False, coarse_cells=0, coarse_solver=COARSE_EXACT,
+                 warm_extrapolate=False):
         lib = load()
         geo = {"spherical": SPHERICAL, "cylindrical": CYLINDRICAL}.get(geometry, geometry)
         rad = {"uniform": UNIFORM, "log": LOG}.get(radial, radial)
@@ -184,7 +186,7 @@ class Plan:
         lc = {"graph": LAUNCH_GRAPH, "dynamic": LAUNCH_DYNAMIC}.get(launch, launch)
         cs = {"exact": COARSE_EXACT, "sor": COARSE_SOR}.get(coarse_solver, coarse_solver)
         self.opts = Opts(prec, nu_pre, nu_post, n_sor, max_cycles, dgf_method, n_pad, dgf_tol, ls, lc,
-                         1 if autotune else 0, coarse_cells, cs)
+                         1 if autotune else 0, coarse_cells, cs, 1 if warm_extrapolate else 0)
         self.line_solver = ls
         self._h = ctypes.c_void_p()
         _check(lib.smg_plan_create(ctypes.byref(self.grid), ctypes.byref(self.opts), ctypes.byref(self._h)))
@@ -286,9 +288,12 @@ class Plan:
                                          _ptr(x), _ptr(y), _iptr(used), _stream()))
         return guess, x, y, used
 
-    def solve(self, rho, tol=1e-8, warm=False, out=None, timings=False, allow_noconv=False, net=False):
+    def solve(self, rho, tol=1e-8, warm=False, out=None, timings=False, allow_noconv=False, net=False,
+              extrapolate=False):
         """Phi for the density rho (cuda float64 [n_a, n_b, n_phi]); returns
-        (phi, info dict)."""
+        (phi, info dict).  extrapolate: warm start from the linear
+        extrapolation of the last two solutions (plan made with
+        warm_extrapolate=True)."""
         import torch
         shape = (self.n_a, self.n_b, self.n_phi)
         self._f64(rho, shape)
@@ -300,7 +305,8 @@ class Plan:
         r1 = np.zeros(M)
         r2 = np.zeros(M)
         info = Info(M, _iptr(c1), _iptr(c2), _dptr(r1), _dptr(r2), 0, 0, 0, 0, 0, 0, 0)
-        flags = (WARM_PREV if warm else 0) | (TIMINGS if timings else 0) | (NET_GUESS if net else 0)
+        flags = ((WARM_PREV if warm else 0) | (TIMINGS if timings else 0) | (NET_GUESS if net else 0) |
+                 (WARM_EXTRAP if extrapolate else 0))
         st = load().smg_solve(self._h, _ptr(rho), _ptr(phi), ctypes.c_double(tol), ctypes.c_uint(flags), _stream(),
                               ctypes.byref(info))
         _check(st, ok=(0, -2) if allow_noconv else (0,))
@@ -311,10 +317,11 @@ class Plan:
                      ms_ifft=info.ms_ifft)
         return phi, d
 
-    def solve_nosync(self, rho, phi, tol=1e-8, warm=False, net=False):
+    def solve_nosync(self, rho, phi, tol=1e-8, warm=False, net=False, extrapolate=False):
         """smg_solve without the info report (for timing loops)."""
-        _check(load().smg_solve(self._h, _ptr(rho), _ptr(phi), ctypes.c_double(tol),
-                                ctypes.c_uint((WARM_PREV if warm else 0) | (NET_GUESS if net else 0)), _stream(), None))
+        flags = (WARM_PREV if warm else 0) | (NET_GUESS if net else 0) | (WARM_EXTRAP if extrapolate else 0)
+        _check(load().smg_solve(self._h, _ptr(rho), _ptr(phi), ctypes.c_double(tol), ctypes.c_uint(flags), _stream(),
+                                None))
 
     # -- steps ----------------------------------------------------------------
     def mode_shape(self):
@@ -439,7 +446,7 @@ class Batch:
     def tune_report(self):
         return load().smg_batch_tune_report(self._h).decode()
 
-    def solve(self, rhos, tol=1e-8, warm=False, outs=None, timings=False, info=True):
+    def solve(self, rhos, tol=1e-8, warm=False, outs=None, timings=False, info=True, extrapolate=False):
         """phi for every plan's density; returns (phis, infos or None)."""
         import torch
         n = len(self.plans)
@@ -450,7 +457,7 @@ class Batch:
             p._f64(o, shape)
         rp = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
         op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
-        flags = (WARM_PREV if warm else 0) | (TIMINGS if timings else 0)
+        flags = (WARM_PREV if warm else 0) | (TIMINGS if timings else 0) | (WARM_EXTRAP if extrapolate else 0)
         infos = None
         keep = []
         if info:

@@ -1,0 +1,146 @@
+"""The extrapolated warm start (opts.warm_extrapolate, flag SMG_WARM_EXTRAP):
+each multigrid solve starts from 2 u_{t-1} - u_{t-2}, the linear
+extrapolation of its last two solutions, instead of u_{t-1}.
+
+* A density that changes linearly in time has solutions that change
+  linearly (the whole solve, boundary treatment included, is linear in the
+  density), so the extrapolated guess is the next solution up to the
+  tolerance of the last two: every mode then needs at most two V-cycles,
+  where the previous solution as the guess needs several; the potential
+  meets the oracle's.
+* Graph replay gives the host loop's bits and cycle counts on a Keplerian
+  trajectory, and a batch gives each plan's own bits (same launch
+  configuration, fixed smoothing steps).
+* Beside the learned guess (modes 0..4), the other modes are extrapolated,
+  and the kept solutions stay right when the forms alternate.
+* The flag needs the option (SMG_EINVAL otherwise)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.geometry import GridSpec, cell_centres, cell_volumes_3d
+from oracle.solve import OraclePlan
+from workloads import configs
+from workloads.densities import draw_blobs, gaussian_blobs, keplerian_snapshot_device
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SPEC = GridSpec("spherical", "log", 64, 32, 64, 0.05, 5.0, 0.0, math.pi)
+SPEC2 = GridSpec("cylindrical", "uniform", 48, 24, 32, 0.2, 2.0, -0.5, 0.5)
+
+
+def _plan(spec=SPEC, **kw):
+    from paper_2606_17636_amd import smg
+    kw.setdefault("precision", "mixed")
+    kw.setdefault("nu_pre", smg.NU_AUTO)
+    kw.setdefault("nu_post", smg.NU_AUTO)
+    print(f"[setup] {spec} {kw}", flush=True)
+    return smg.grid_from_spec(spec, coarse_cells=2048, **kw).setup()
+
+
+def _blobs(spec, seed):
+    a, b, p = cell_centres(spec)
+    rng = np.random.default_rng(seed)
+    cen, w, amp = draw_blobs(rng, spec.geometry, spec.radial, spec.a_min, spec.a_max, spec.b_min, spec.b_max, 4)
+    return gaussian_blobs(spec.geometry, a, b, p, cen, np.asarray(w) * (spec.a_max - spec.a_min), amp)
+
+
+def _traj(spec, steps, seed=5):
+    a, b, p = cell_centres(spec)
+    blobs = configs.c5_blobs(seed)
+    dt = 0.5 * (2 * math.pi / spec.n_phi) / (blobs[0].min() ** -1.5)
+    return [keplerian_snapshot_device(a, b, p, blobs, k * dt) for k in range(steps)]
+
+
+def _l2(spec, x, ref):
+    w = cell_volumes_3d(spec)[:, :, None]
+    return math.sqrt(np.sum((x - ref) ** 2 * w) / np.sum(ref**2 * w))
+
+
+def test_linear_in_time_density_is_extrapolated():
+    r0, r1 = _blobs(SPEC, 71), _blobs(SPEC, 72)
+    rhos = [r0 + 0.05 * k * (r1 - r0) for k in range(6)]
+    ext = _plan(launch="graph", autotune=True, warm_extrapolate=True)
+    prev = _plan(launch="graph", autotune=True)
+    for k, rho in enumerate(rhos):
+        rd = torch.from_numpy(rho).cuda()
+        pe, ie = ext.solve(rd, tol=1e-8, warm=k > 0, extrapolate=True)
+        pp, ip = prev.solve(rd, tol=1e-8, warm=k > 0)
+        assert ie["converged"] and ip["converged"], k
+        me = max(ie["cycles1"].max(), ie["cycles2"].max())
+        mp = max(ip["cycles1"].max(), ip["cycles2"].max())
+        print(f"step {k}: slowest mode, extrapolated {me}, previous {mp}", flush=True)
+        if k >= 2:
+            assert me <= 2, (k, me)
+            assert mp >= 4, (k, mp)
+        assert _l2(SPEC, pe.cpu().numpy(), pp.cpu().numpy()) < 1e-6, k
+    ref = OraclePlan(SPEC).solve(rhos[-1])
+    assert _l2(SPEC, pe.cpu().numpy(), ref) < 1e-6
+
+
+def test_extrapolation_beside_the_learned_guess():
+    """A plan with an untrained network (zero output layer: its candidate is
+    the extrapolation itself), alternating solves with the learned guess of
+    modes 0..4 plus the extrapolation of the others, and solves with the
+    extrapolation of every mode: on the linear-in-time density every mode
+    needs at most two V-cycles from the third step on in both forms, so the
+    low modes' kept solution is u_{t-1} also after a step in which the
+    network's candidate replaced it."""
+    from paper_2606_17636_amd import smg
+    from workloads.netinit import init_params
+    r0, r1 = _blobs(SPEC, 71), _blobs(SPEC, 72)
+    rhos = [r0 + 0.05 * k * (r1 - r0) for k in range(8)]
+    plan = _plan(launch="graph", warm_extrapolate=True)
+    net = smg.Net()
+    net.set_params(init_params(4))
+    plan.attach_net(net, 4)
+    for k, rho in enumerate(rhos):
+        learned = k % 2 == 1
+        phi, info = plan.solve(torch.from_numpy(rho).cuda(), tol=1e-8, warm=k > 0, net=learned, extrapolate=True)
+        assert info["converged"], k
+        slow = max(info["cycles1"].max(), info["cycles2"].max())
+        print(f"step {k} ({'learned' if learned else 'extrapolated'}): slowest mode {slow}", flush=True)
+        if k >= 2:
+            assert slow <= 2, (k, slow)
+    ref = OraclePlan(SPEC).solve(rhos[-1])
+    assert _l2(SPEC, phi.cpu().numpy(), ref) < 1e-6
+
+
+def test_extrapolated_graph_replay_matches_host_loop():
+    graph = _plan(launch="graph", warm_extrapolate=True)
+    loop = _plan(launch="dynamic", warm_extrapolate=True)
+    for k, rd in enumerate(_traj(SPEC, 8)):
+        pg, ig = graph.solve(rd, tol=1e-8, warm=k > 0, extrapolate=True)
+        pl, il = loop.solve(rd, tol=1e-8, warm=k > 0, extrapolate=True)
+        assert ig["converged"] and il["converged"], k
+        assert np.array_equal(ig["cycles1"], il["cycles1"]) and np.array_equal(ig["cycles2"], il["cycles2"]), k
+        assert torch.equal(pg, pl), k
+
+
+def test_extrapolated_batch_matches_single_plans():
+    from paper_2606_17636_amd import smg
+    specs = [SPEC, SPEC2]
+    kw = dict(launch="dynamic", precision="fp64", nu_pre=2, nu_post=2, warm_extrapolate=True)
+    singles = [_plan(s, **kw) for s in specs]
+    members = [_plan(s, **kw) for s in specs]
+    batch = smg.Batch(members).setup()
+    trajs = [_traj(s, 6, seed=5 + q) for q, s in enumerate(specs)]
+    for k in range(6):
+        rhos = [t[k] for t in trajs]
+        ones = [p.solve(r, tol=1e-8, warm=k > 0, extrapolate=True) for p, r in zip(singles, rhos)]
+        phis, infos = batch.solve(rhos, tol=1e-8, warm=k > 0, extrapolate=True)
+        for q in range(2):
+            assert infos[q]["converged"], (k, q)
+            assert np.array_equal(infos[q]["cycles1"], ones[q][1]["cycles1"]), (k, q)
+            assert torch.equal(phis[q], ones[q][0]), (k, q)
+
+
+def test_extrapolate_needs_the_option():
+    from paper_2606_17636_amd import smg
+    p = _plan(launch="dynamic")
+    rd = _traj(SPEC, 1)[0]
+    p.solve(rd, tol=1e-8)
+    with pytest.raises(smg.SmgError, match="warm_extrapolate"):
+        p.solve(rd, tol=1e-8, warm=True, extrapolate=True)

@@ -155,6 +155,11 @@ def test_guess_candidate_inverts_the_target():
         assert np.allclose(cand, ut[:m_max + 1], rtol=0, atol=1e-13 * np.abs(ut).max())
     zero = net.guess_candidate(up, np.zeros((2 * m_max + 1, na, nb)), sc, m_max, uprev2=u2)
     assert np.allclose(zero, (2 * up - u2)[:m_max + 1], rtol=0, atol=1e-14 * np.abs(up).max())
+    # the judge's baseline is that zero-correction candidate: the
+    # extrapolation, or u_{t-1} before a second solution exists
+    assert np.array_equal(net.guess_base(up, sc, m_max, uprev2=u2), zero)
+    _, sc1 = net.guess_images(f, fp, up, m_max)
+    assert np.array_equal(net.guess_base(up, sc1, m_max), up[:m_max + 1])
 
 
 def test_guess_judge_prefers_the_better_start():
