@@ -521,7 +521,8 @@ def bench_trajectory(args, smg, configs, torch, pool):
                    "low_mode_v_cycles_per_step": {"zero_guess": round(float(np.mean(zero)), 2)},
                    "v_cycles_per_step": {"learned": cycles(cyc_net), "extrapolated": cycles(cyc_ext),
                                          "previous_step": cycles(cyc_prev)},
-                   "network_guess_taken": f"{taken[0]} of {2 * (m_max + 1) * max(K - 1, 0)} mode solves"},
+                   "network_guess_taken": f"{taken[0]} of {(m_max + 1) * max(K - 1, 0)} judged mode solves "
+                                          "(modes 0..4 of the potential's solve)"},
         "roofline": roof,
         "kernels_per_step": kern,
         "extrapolated_guess": dict(value=round(K / dt_ext, 3), unit="solves/s", ms_per_step=round(1e3 * dt_ext / K, 3),
