@@ -6,9 +6,9 @@ form): the orbiting-blob trajectory on the 256x128x256 logarithmic sphere.
 One step = one full solve (azimuthal FFT -> multigrid solve 1 -> screening
 mass + DGF convolution -> multigrid solve 2 -> inverse FFT) of the next
 snapshot's density to relative residual --tol (1e-8) on every mode, warm
-started from the previous steps: modes 0..4 from the learned guess where the
-judge takes it, the other modes from the linear extrapolation of their last
-two solutions.  The chosen form: FP32/FP64 iterative refinement,
+started from the previous steps: every mode from the cubic extrapolation of
+its last four solutions, and modes 0..4 of the potential's solve from the
+learned guess where the judge finds it better.  The chosen form: FP32/FP64 iterative refinement,
 per-mode cycle schedules replayed as HIP graphs, autotuned launch shapes,
 smoothing steps chosen at setup, learned initial guess.  The network is
 trained at setup on 8 method-generated trajectories (seeds 50-57); the DGF
@@ -41,6 +41,9 @@ HBM_PEAK_GBS = 8000.0
 # chosen form: coarsening stops at a level of at most this many cells, solved
 # exactly by fast diagonalisation (the plain form keeps the 128-cell default)
 COARSE_CELLS = 2048
+# chosen form, warm solves: order of the extrapolated start (the polynomial
+# through the last EXTRAP_ORDER + 1 solutions)
+EXTRAP_ORDER = 3
 
 
 def measured_traffic(workload, kernel_class):
@@ -221,7 +224,7 @@ def _plan(smg, g, form, line_solver, max_cycles=60, extrapolate=False):
     if form == "chosen":
         return smg.Plan(**g, precision="mixed", launch="graph", autotune=True, line_solver=line_solver,
                         max_cycles=max_cycles, coarse_cells=COARSE_CELLS, nu_pre=smg.NU_AUTO, nu_post=smg.NU_AUTO,
-                        warm_extrapolate=extrapolate)
+                        warm_extrapolate=EXTRAP_ORDER if extrapolate else 0)
     return smg.Plan(**g, precision="fp64", launch="dynamic", autotune=False, line_solver="sor", max_cycles=max_cycles,
                     coarse_solver="sor")
 
@@ -511,8 +514,8 @@ def bench_trajectory(args, smg, configs, torch, pool):
         "config": {"workload": f"c5 trajectory: {configs.DESCRIPTION['c5']}, snapshots 1..{K} warm-started",
                    "tol": args.tol,
                    "form": "chosen: mixed precision, graph-replayed per-mode schedules, autotuned launch shapes, "
-                           f"learned guess of modes 0..{m_max}, the other modes extrapolated from their last two "
-                           "solutions",
+                           f"every mode started from the cubic extrapolation of its last {EXTRAP_ORDER + 1} "
+                           f"solutions, learned guess of modes 0..{m_max} in the potential's solve",
                    "line_solver": args.line_solver,
                    "step": "one warm-started solve of the next snapshot",
                    "train": {"trajectories": len(seeds), "samples": n, "steps": args.train_steps,

@@ -124,10 +124,15 @@ typedef struct {
                             SOR with the 2D omega of Appendix A, from zero
                             until the residual drops by 1e-10 (Sec. 3.3; the
                             coarsest level must then have <= 1024 cells) */
-  int warm_extrapolate;  /* 1: keep the solutions of the two previous solves
-                            so that warm solves can start from their linear
-                            extrapolation (flag SMG_WARM_EXTRAP); costs two
-                            more sets of FP64 mode planes of workspace [0] */
+  int warm_extrapolate;  /* order of the extrapolated warm start (flag
+                            SMG_WARM_EXTRAP), 0 to 3: the plan keeps that
+                            many solutions before the last one and warm
+                            solves start from the polynomial through them
+                            (1: 2 u_{t-1} - u_{t-2}; 2: 3 u_{t-1} -
+                            3 u_{t-2} + u_{t-3}; 3: 4 u_{t-1} - 6 u_{t-2} +
+                            4 u_{t-3} - u_{t-4}); each order costs two more
+                            sets of FP64 mode planes of workspace (one per
+                            multigrid solve) [0: none] */
 } smg_opts;
 
 enum { SMG_COARSE_EXACT = 0, SMG_COARSE_SOR = 1 };
@@ -156,21 +161,24 @@ typedef struct {
                                Phi^m) modes 0..m_max start from the
                                network's prediction wherever, after one
                                smoothing step of each, its defect norm is
-                               below that of the extrapolation of the last
-                               two solutions (the previous solution before
-                               two exist), else from that extrapolation;
+                               below that of the start they would take
+                               otherwise (the extrapolated warm start with
+                               SMG_WARM_EXTRAP, else the linear
+                               extrapolation of the last two solutions, or
+                               the previous solution before two exist);
                                solve 1 (Psi^m) starts them like the other
                                modes.  The multigrid runs to the same
                                tolerance either way.                       */
 #define SMG_WARM_EXTRAP 8u  /* with SMG_WARM_PREV on a plan created with
                                opts.warm_extrapolate: each multigrid solve
-                               starts its modes from 2 u_{t-1} - u_{t-2},
-                               the linear extrapolation of its last two
-                               solutions (with SMG_NET_GUESS, the modes
-                               above m_max; the network's candidate already
-                               extrapolates), once two warm-startable
-                               solutions exist (a solve without this flag
-                               leaves one); otherwise from u_{t-1}.  Only the
+                               starts its modes from the polynomial
+                               extrapolation of its last solutions, of the
+                               plan's order or lower while fewer exist
+                               (with SMG_NET_GUESS the network's candidate
+                               then competes with this start for modes
+                               0..m_max); a solve without this flag
+                               leaves one usable solution, from which the
+                               next starts as u_{t-1}.  Only the
                                cycle count depends on the guess.  SMG_EINVAL
                                on a plan without opts.warm_extrapolate.    */
 
@@ -342,11 +350,13 @@ smg_status smg_net_conv3_wgrad_noalloc(const unsigned short *g_dev, int c_out, c
  * and for a static plane (last change below 1e-4 of its RMS), channels 6
  * and 7 are zero) before the potential's multigrid solve (solve 2) and
  * starts every mode from the better (defect norms after one smoothing step
- * of each) of the baseline u_{t-1} + (u_{t-1} - u_{t-2}), the linear
- * extrapolation (u_{t-1} before u_{t-2} exists, and on a static part), and
- * the candidate baseline + s_o y, the network's correction y added.  The
- * inputs of solve 1 are built as well (they are recorded as training
- * samples), but its modes take no network guess.
+ * of each) of the candidate, the baseline u_{t-1} + (u_{t-1} - u_{t-2}) (the
+ * linear extrapolation; u_{t-1} before u_{t-2} exists, and on a static
+ * part) plus s_o y, the network's correction y, and the start the mode
+ * would take otherwise: the plan's extrapolated warm start where
+ * SMG_WARM_EXTRAP applies one, else that baseline.  The inputs of solve 1
+ * are built as well (they are recorded as training samples), but its modes
+ * take no network guess.
  * A NULL net detaches. */
 size_t smg_plan_net_work_bytes(const smg_plan *plan, const smg_net *net, int m_max);
 smg_status smg_plan_attach_net(smg_plan *plan, smg_net *net, int m_max, void *work_dev, size_t work_bytes,

@@ -232,12 +232,12 @@ struct smg_plan {
   Group grp;                // this plan alone
   std::string tune_report;
   PlanNet pn;
-  // extrapolated warm start (opts.warm_extrapolate): the solution before the
-  // last one per target, how many solutions of the target the plan holds
-  // in a form a warm solve can use (0, 1, or 2: w_psi/w_phi and w_xprev),
-  // and this solve's step (0 none, 1 keep u as the previous solution,
-  // 2 extrapolate), decided on the host before the body
-  size_t w_xprev[2] = {0, 0};
+  // extrapolated warm start (opts.warm_extrapolate = order): the solutions
+  // before the last one per target (order of them), how many solutions of
+  // the target the plan holds in a form a warm solve can use (0 .. order + 1:
+  // w_psi/w_phi and w_xprev), and how many this solve extrapolates from (0:
+  // no step, 1: only shift the history), decided on the host before the body
+  size_t w_xprev[2][3] = {{0, 0, 0}, {0, 0, 0}};
   int xhave[2] = {0, 0};
   int xstep[2] = {0, 0};
   // bumped whenever a buffer that captured solve graphs write to changes
@@ -292,7 +292,7 @@ static smg_status validate(const smg_grid& g, const smg_opts& o) {
     return fail(SMG_EINVAL, "coarse_cells must be 0 or in [16, 8192]");
   if (o.coarse_solver != SMG_COARSE_EXACT && o.coarse_solver != SMG_COARSE_SOR)
     return fail(SMG_EINVAL, "coarse_solver must be SMG_COARSE_EXACT or SMG_COARSE_SOR");
-  if (o.warm_extrapolate != 0 && o.warm_extrapolate != 1) return fail(SMG_EINVAL, "warm_extrapolate must be 0 or 1");
+  if (o.warm_extrapolate < 0 || o.warm_extrapolate > 3) return fail(SMG_EINVAL, "warm_extrapolate must be 0 to 3");
   return SMG_OK;
 }
 
@@ -415,8 +415,8 @@ extern "C" smg_status smg_plan_create(const smg_grid* grid, const smg_opts* opts
   p->w_phi = take(sizeof(double2) * M * plane);
   p->w_f = take(sizeof(double2) * M * plane);
   p->w_f2 = take(sizeof(double2) * M * plane);
-  if (p->opts.warm_extrapolate)
-    for (int t = 0; t < 2; ++t) p->w_xprev[t] = take(sizeof(double2) * M * plane);
+  for (int k = 0; k < p->opts.warm_extrapolate; ++k)
+    for (int t = 0; t < 2; ++t) p->w_xprev[t][k] = take(sizeof(double2) * M * plane);
   p->w_sigma = take(sizeof(double2) * (size_t)M * p->n_g);
   p->w_theta = take(sizeof(double2) * (size_t)M * p->n_g);
   p->w_gpot = take(sizeof(double) * (size_t)p->n_g * s.n_phi);
@@ -999,15 +999,33 @@ static smg_status net_before(smg_plan* p, int t, bool warm, bool guess, hipStrea
                         pn.n_img, reinterpret_cast<float*>(pn.work + pn.wl.x32), st));
   if (!guess) return SMG_OK;
   STCHK(pn.net->def.forward(pn.work, pn.wl, st, false));
-  double2* cand = reinterpret_cast<double2*>(pn.work + pn.o_cand);
   // the candidate and the baseline it is judged against (the linear
   // extrapolation, or the previous solution before two exist), the latter
   // straight into the judge's second buffer
   HIPCHK(smgg::candidate(uprev, pn.prev2_ok[t] ? uprev2 : nullptr, reinterpret_cast<const float*>(pn.work + pn.wl.y), sc,
-                         plane, pn.m_max, cand, reinterpret_cast<double2*>(pn.work + pn.o_us), st));
-  // judge: defect norms after one smoothing step of each start (the
-  // smoothing removes the rough part of an error, which the multigrid
-  // removes in its first sweep anyway; what is left decides the cycles)
+                         plane, pn.m_max, reinterpret_cast<double2*>(pn.work + pn.o_cand),
+                         reinterpret_cast<double2*>(pn.work + pn.o_us), st));
+  return SMG_OK;
+}
+
+// Second phase of the learned guess of solve t: the judge.  The candidate
+// and the other start each get one smoothing step and the one with the
+// smaller defect norm is kept.  The other start is the baseline of
+// net_before, or, where the plan's extrapolated warm start has already
+// written u (base_in_u), u itself: the candidate then has to beat the
+// plan's own start.  (The smoothing removes the rough part of an error,
+// which the multigrid removes in its first sweep anyway; what is left
+// decides the cycles.)
+static smg_status net_judge(smg_plan* p, int t, bool warm, bool guess, bool base_in_u, hipStream_t st) {
+  PlanNet& pn = p->pn;
+  if (!pn.net || !warm || !pn.prev_ok[t] || !guess) return SMG_OK;
+  const int plane = p->spec.n_a * p->spec.n_b;
+  const size_t np = (size_t)(pn.m_max + 1) * plane;
+  const double2* uprev = reinterpret_cast<const double2*>(pn.work + pn.o_uprev[t]);
+  const double2* uprev2 = reinterpret_cast<const double2*>(pn.work + pn.o_uprev2[t]);
+  const double* sc = reinterpret_cast<const double*>(pn.work + pn.o_sc);
+  const double2* cand = reinterpret_cast<const double2*>(pn.work + pn.o_cand);
+  if (base_in_u) HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_us), target_u(p, t), np, st));
   HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_cs), cand, np, st));
   BatchRef b{pn.m_max + 1, nullptr, reinterpret_cast<const int*>(pn.work + pn.o_list)};
   const LvJob* dl = reinterpret_cast<const LvJob*>(pn.work + pn.o_lv) + 2 * t;
@@ -1020,8 +1038,9 @@ static smg_status net_before(smg_plan* p, int t, bool warm, bool guess, hipStrea
   double* pu = pc + (size_t)(pn.m_max + 1) * pn.nblk;
   HIPCHK(smgk::mg_norm_partial(dj, &pn.hjobs[2 * t], 1, b, true, pc, pn.nblk, st));
   HIPCHK(smgk::mg_norm_partial(dj + 1, &pn.hjobs[2 * t + 1], 1, b, true, pu, pn.nblk, st));
-  HIPCHK(smgg::select(pc, pu, pn.nblk, cand, uprev, pn.prev2_ok[t] ? uprev2 : nullptr, sc, target_u(p, t), plane, pn.m_max,
-                      reinterpret_cast<int*>(pn.work + pn.o_used) + t * (pn.m_max + 1), st));
+  HIPCHK(smgg::select(pc, pu, pn.nblk, cand, base_in_u ? nullptr : uprev, pn.prev2_ok[t] ? uprev2 : nullptr, sc,
+                      target_u(p, t), plane, pn.m_max, reinterpret_cast<int*>(pn.work + pn.o_used) + t * (pn.m_max + 1),
+                      st));
   return SMG_OK;
 }
 
@@ -1052,21 +1071,20 @@ static smg_status net_after(smg_plan* p, int t, bool warm, hipStream_t st) {
 // enqueued up front (no host synchronisation); otherwise each solve reads
 // its list length after every cycle.  ev (optional) records 3 component
 // boundaries.
-// Extrapolated warm start of target t (decided on the host: p->xstep[t]):
-// the last solution is kept as the one before, and every mode the learned
-// guess does not handle in this solve starts from 2 u_{t-1} - u_{t-2}.
-// Runs after net_before, which has read modes 0..m_max of u_{t-1} (and,
-// with the guess, replaced them by the chosen candidate: for those modes
-// the kept solution is net_before's copy of u_{t-1}).
-static smg_status warm_extrapolate(smg_plan* p, int t, bool warm, bool guess, hipStream_t st) {
+// Extrapolated warm start of target t (decided on the host: p->xstep[t]
+// solutions to extrapolate from): every mode starts from the polynomial
+// extrapolation of its last solutions (order 1: 2 u_{t-1} - u_{t-2};
+// 2: 3 u_{t-1} - 3 u_{t-2} + u_{t-3}; 3: 4 u_{t-1} - 6 u_{t-2} + 4 u_{t-3} -
+// u_{t-4}), and the kept history shifts.  Runs between the two phases of the
+// learned guess: after net_before has read u_{t-1}, before the judge, which
+// then weighs the network's candidate against this start.
+static smg_status warm_extrapolate(smg_plan* p, int t, bool warm, hipStream_t st) {
   if (!warm || p->xstep[t] == 0) return SMG_OK;
   const size_t plane = (size_t)p->spec.n_a * p->spec.n_b, n = (size_t)p->M * plane;
-  const PlanNet& pn = p->pn;
-  const bool net = guess && pn.net && pn.prev_ok[t];
-  const size_t nlow = net ? (size_t)(pn.m_max + 1) * plane : 0;
-  double2* prev = p->dptr(p->w_xprev[t]);
-  HIPCHK(smgg::extrapolate(target_u(p, t), prev, n, p->xstep[t] == 1 ? n : nlow, st));
-  if (net) HIPCHK(smgk::copy_planes(prev, reinterpret_cast<const double2*>(pn.work + pn.o_uprev[t]), nlow, st));
+  const int kept = p->opts.warm_extrapolate;
+  double2* hist[3] = {nullptr, nullptr, nullptr};
+  for (int j = 0; j < kept; ++j) hist[j] = p->dptr(p->w_xprev[t][j]);
+  HIPCHK(smgg::extrapolate(target_u(p, t), hist, kept, n, 0, p->xstep[t], st));
   return SMG_OK;
 }
 
@@ -1080,7 +1098,7 @@ static smg_status group_body(Group& g, double tol, bool warm, unsigned flags, co
   // the network guesses the potential's solve (solve 2) only; solve 1 (Psi,
   // zero ghosts) keeps the network's bookkeeping and starts like the other modes
   for (smg_plan* p : g.plans) STCHK(net_before(p, 0, warm, false, st));
-  for (smg_plan* p : g.plans) STCHK(warm_extrapolate(p, 0, warm, false, st));
+  for (smg_plan* p : g.plans) STCHK(warm_extrapolate(p, 0, warm, st));
   STCHK(e.start(0, tol, kFloor, warm, g.max_cycles, st));
   if (sched0) {
     for (int cap : *sched0) STCHK(e.cycle(0, cap, st));
@@ -1092,7 +1110,8 @@ static smg_status group_body(Group& g, double tol, bool warm, unsigned flags, co
   STCHK(james_all(g, st));
   if (ev) HIPCHK(hipEventRecord(ev[1], st));
   for (smg_plan* p : g.plans) STCHK(net_before(p, 1, warm, guess, st));
-  for (smg_plan* p : g.plans) STCHK(warm_extrapolate(p, 1, warm, guess, st));
+  for (smg_plan* p : g.plans) STCHK(warm_extrapolate(p, 1, warm, st));
+  for (smg_plan* p : g.plans) STCHK(net_judge(p, 1, warm, guess, p->xstep[1] >= 2, st));
   STCHK(e.start(1, tol, kFloor, warm, g.max_cycles, st));
   if (sched1) {
     for (int cap : *sched1) STCHK(e.cycle(1, cap, st));
@@ -1115,7 +1134,7 @@ static smg_status group_graph(Group& g, double tol, bool warm, unsigned flags, c
                                   16 * p->pn.prev2_ok[0] + 32 * p->pn.prev2_ok[1]
                             : 0);
     key.push_back((int)p->gen);
-    key.push_back(p->xstep[0] + 3 * p->xstep[1]);
+    key.push_back(p->xstep[0] + 4 * p->xstep[1]);
   }
   long long tb;
   std::memcpy(&tb, &tol, sizeof(tb));
@@ -1204,7 +1223,7 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
   for (smg_plan* p : g.plans) {
     if (extrap && !p->opts.warm_extrapolate)
       return fail(SMG_EINVAL, "SMG_WARM_EXTRAP needs a plan created with opts.warm_extrapolate");
-    for (int t = 0; t < 2; ++t) p->xstep[t] = extrap && warm ? std::min(p->xhave[t], 2) : 0;
+    for (int t = 0; t < 2; ++t) p->xstep[t] = extrap && warm ? std::min(p->xhave[t], p->opts.warm_extrapolate + 1) : 0;
   }
   // learned-guess bookkeeping, decided on the host (a replayed graph runs
   // none of the body's host code): a guess step of target t runs when the
@@ -1244,7 +1263,7 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
   if (timings) HIPCHK(hipEventRecord(ev[5], st));
   g.have_prev = true;
   for (smg_plan* p : g.plans)
-    for (int t = 0; t < 2; ++t) p->xhave[t] = p->xstep[t] > 0 ? 2 : 1;
+    for (int t = 0; t < 2; ++t) p->xhave[t] = p->xstep[t] > 0 ? std::min(p->xstep[t] + 1, p->opts.warm_extrapolate + 1) : 1;
   for (int q = 0; q < P; ++q)
     for (int t = 0; t < 2; ++t) g.plans[q]->pn.have_u[t] = guess_step[q][t];
   // per-mode state of both solves (one synchronisation); modes that needed
@@ -1473,7 +1492,8 @@ extern "C" smg_status smg_net_guess_step(smg_plan* p, int t, const double* f, co
   const bool keep = pn.prev_ok[t];
   pn.prev_ok[t] = true;
   pn.prev2_ok[t] = uprev2 != nullptr;
-  const smg_status sb = net_before(p, t, true, true, st);
+  smg_status sb = net_before(p, t, true, true, st);
+  if (sb == SMG_OK) sb = net_judge(p, t, true, true, false, st);
   pn.prev_ok[t] = keep;
   pn.prev2_ok[t] = false;
   pn.have_u[0] = pn.have_u[1] = false;

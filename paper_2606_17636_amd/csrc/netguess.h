@@ -18,11 +18,13 @@ hipError_t assemble(const double2* f, const double2* fprev, const double2* uprev
 // base = uprev + (uprev - uprev2 if uprev2; not on static parts), cand = base + s_o y
 hipError_t candidate(const double2* uprev, const double2* uprev2, const float* y, const double* sc, int plane, int m_max,
                      double2* cand, double2* base, hipStream_t st);
-// per mode: u = cand where pc's norm is below pu's, else base (recomputed)
+// per mode: u = cand where pc's norm is below pu's, else base (recomputed; u left as it is with uprev null)
 hipError_t select(const double* pc, const double* pu, int nblk, const double2* cand, const double2* uprev,
                   const double2* uprev2, const double* sc, double2* u, int plane, int m_max, int* used, hipStream_t st);
 hipError_t record(const float* x, const double2* u, const double2* uprev, const double2* uprev2, const double* sc,
                   int plane, int n_img, int* count, int capacity, float* samples, hipStream_t st);
-// warm start from two solutions (n values): prev <- u; u <- 2 u - prev from value lo on
-hipError_t extrapolate(double2* u, double2* prev, size_t n, size_t lo, hipStream_t st);
+// warm start from the last k solutions (n values; hist[0..kept-1] the kept older ones, newest
+// first; k <= kept + 1): from value lo on, u <- the polynomial extrapolation through them
+// (2 u - h0, 3 u - 3 h0 + h1, 4 u - 6 h0 + 4 h1 - h2); then the history shifts, h0 <- u's old value
+hipError_t extrapolate(double2* u, double2* const* hist, int kept, size_t n, size_t lo, int k, hipStream_t st);
 }  // namespace smgg

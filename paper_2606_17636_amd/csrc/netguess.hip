@@ -158,10 +158,10 @@ __global__ void k_candidate(const double2* __restrict__ uprev, const double2* __
 }
 
 // per mode: the candidate where its defect norm is the smaller one, else
-// the baseline (recomputed, with the arithmetic of k_candidate).  Grid
-// (blocks per plane, m_max + 1): every block sums its mode's partial norms
-// (nblk each) and writes its slice of the plane; block 0 of the mode records
-// the choice.
+// the baseline (recomputed, with the arithmetic of k_candidate), or, with no
+// uprev, u as it is (the other start was u itself).  Grid (blocks per plane,
+// m_max + 1): every block sums its mode's partial norms (nblk each) and
+// writes its slice of the plane; block 0 of the mode records the choice.
 __global__ void k_select(const double* __restrict__ pc, const double* __restrict__ pu, int nblk,
                          const double2* __restrict__ cand, const double2* __restrict__ uprev,
                          const double2* __restrict__ uprev2, const double* __restrict__ sc, double2* __restrict__ u,
@@ -178,6 +178,7 @@ __global__ void k_select(const double* __restrict__ pc, const double* __restrict
     if (blockIdx.x == 0) used[m] = take;
   }
   __syncthreads();
+  if (!take && !uprev) return;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < plane; t += gridDim.x * blockDim.x) {
     const size_t k = (size_t)m * plane + t;
     double sr, si;
@@ -212,13 +213,35 @@ __global__ void k_advance(int* count, int n, int capacity) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *count = min(*count + n, capacity);
 }
 
-// prev <- u everywhere and, from value lo on, u <- 2 u - prev: the linear
-// extrapolation of the last two solutions (one FP64 rounding per value)
-__global__ void k_extrapolate(double2* __restrict__ u, double2* __restrict__ prev, size_t n, size_t lo) {
+// Warm start from the last k solutions, u (the latest) and the kept ones
+// h[0], h[1], h[2] (older in turn; h[j] null beyond those kept): from value
+// lo on, u <- the value at the next step of the polynomial through them
+// (k = 2: 2 u - h0; k = 3: 3 u - 3 h0 + h1; k = 4: 4 u - 6 h0 + 4 h1 - h2;
+// k = 1: u unchanged); then the history shifts by one, h0 <- u's old value.
+struct History {
+  double2* h[3];
+};
+
+__global__ void k_extrapolate(double2* __restrict__ u, History hs, size_t n, size_t lo, int k) {
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-    const double2 x = u[t], q = prev[t];
-    if (t >= lo) u[t] = make_double2(2.0 * x.x - q.x, 2.0 * x.y - q.y);
-    prev[t] = x;
+    const double2 x = u[t];
+    double2 q[3] = {};
+    for (int j = 0; j < 3; ++j)
+      if (hs.h[j]) q[j] = hs.h[j][t];
+    if (t >= lo && k >= 2) {
+      double2 v;
+      if (k == 2) {
+        v = make_double2(2.0 * x.x - q[0].x, 2.0 * x.y - q[0].y);
+      } else if (k == 3) {
+        v = make_double2(3.0 * (x.x - q[0].x) + q[1].x, 3.0 * (x.y - q[0].y) + q[1].y);
+      } else {
+        v = make_double2(4.0 * (x.x + q[1].x) - 6.0 * q[0].x - q[2].x, 4.0 * (x.y + q[1].y) - 6.0 * q[0].y - q[2].y);
+      }
+      u[t] = v;
+    }
+    for (int j = 2; j > 0; --j)
+      if (hs.h[j]) hs.h[j][t] = q[j - 1];
+    hs.h[0][t] = x;
   }
 }
 
@@ -270,9 +293,12 @@ hipError_t record(const float* x, const double2* u, const double2* uprev, const 
   return hipGetLastError();
 }
 
-hipError_t extrapolate(double2* u, double2* prev, size_t n, size_t lo, hipStream_t st) {
+hipError_t extrapolate(double2* u, double2* const* hist, int kept, size_t n, size_t lo, int k, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_extrapolate, dim3(grid1(n)), dim3(256), 0, st, u, prev, n, lo);
+  if (kept < 1 || kept > 3 || k < 1 || k > kept + 1) return hipErrorInvalidValue;
+  History hs{{nullptr, nullptr, nullptr}};
+  for (int j = 0; j < kept; ++j) hs.h[j] = hist[j];
+  hipLaunchKernelGGL(k_extrapolate, dim3(grid1(n)), dim3(256), 0, st, u, hs, n, lo, k);
   return hipGetLastError();
 }
 

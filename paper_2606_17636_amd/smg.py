@@ -186,7 +186,7 @@ class Plan:
         lc = {"graph": LAUNCH_GRAPH, "dynamic": LAUNCH_DYNAMIC}.get(launch, launch)
         cs = {"exact": COARSE_EXACT, "sor": COARSE_SOR}.get(coarse_solver, coarse_solver)
         self.opts = Opts(prec, nu_pre, nu_post, n_sor, max_cycles, dgf_method, n_pad, dgf_tol, ls, lc,
-                         1 if autotune else 0, coarse_cells, cs, 1 if warm_extrapolate else 0)
+                         1 if autotune else 0, coarse_cells, cs, int(warm_extrapolate))
         self.line_solver = ls
         self._h = ctypes.c_void_p()
         _check(lib.smg_plan_create(ctypes.byref(self.grid), ctypes.byref(self.opts), ctypes.byref(self._h)))

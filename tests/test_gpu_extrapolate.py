@@ -1,13 +1,14 @@
-"""The extrapolated warm start (opts.warm_extrapolate, flag SMG_WARM_EXTRAP):
-each multigrid solve starts from 2 u_{t-1} - u_{t-2}, the linear
-extrapolation of its last two solutions, instead of u_{t-1}.
+"""The extrapolated warm start (opts.warm_extrapolate = order q, flag
+SMG_WARM_EXTRAP): each multigrid solve starts from the polynomial of degree
+q through its last q + 1 solutions, evaluated at the next step (q = 1:
+2 u_{t-1} - u_{t-2}), instead of u_{t-1}.
 
-* A density that changes linearly in time has solutions that change
-  linearly (the whole solve, boundary treatment included, is linear in the
-  density), so the extrapolated guess is the next solution up to the
-  tolerance of the last two: every mode then needs at most two V-cycles,
-  where the previous solution as the guess needs several; the potential
-  meets the oracle's.
+* A density that changes in time as a polynomial of degree q has solutions
+  that do too (the whole solve, boundary treatment included, is linear in
+  the density), so the extrapolation of order q is the next solution up to
+  the tolerance of the last ones: every mode then needs at most two
+  V-cycles, where the order below (or the previous solution) needs several;
+  the potential meets the oracle's.
 * Graph replay gives the host loop's bits and cycle counts on a Keplerian
   trajectory, and a batch gives each plan's own bits (same launch
   configuration, fixed smoothing steps).
@@ -81,18 +82,19 @@ def test_linear_in_time_density_is_extrapolated():
 
 
 def test_extrapolation_beside_the_learned_guess():
-    """A plan with an untrained network (zero output layer: its candidate is
-    the extrapolation itself), alternating solves with the learned guess of
-    modes 0..4 plus the extrapolation of the others, and solves with the
-    extrapolation of every mode: on the linear-in-time density every mode
-    needs at most two V-cycles from the third step on in both forms, so the
-    low modes' kept solution is u_{t-1} also after a step in which the
-    network's candidate replaced it."""
+    """A plan of order 3 with an untrained network (zero output layer: its
+    candidate is the linear extrapolation), alternating solves with the
+    learned guess (the candidate judged against the plan's extrapolated
+    start for modes 0..4 of the potential's solve) and solves without it:
+    on the linear-in-time density every mode needs at most two V-cycles from
+    the third step on in both forms, so the kept history of the low modes
+    stays right after a step in which the network's candidate could have
+    replaced their start."""
     from paper_2606_17636_amd import smg
     from workloads.netinit import init_params
     r0, r1 = _blobs(SPEC, 71), _blobs(SPEC, 72)
     rhos = [r0 + 0.05 * k * (r1 - r0) for k in range(8)]
-    plan = _plan(launch="graph", warm_extrapolate=True)
+    plan = _plan(launch="graph", warm_extrapolate=3)
     net = smg.Net()
     net.set_params(init_params(4))
     plan.attach_net(net, 4)
@@ -108,9 +110,33 @@ def test_extrapolation_beside_the_learned_guess():
     assert _l2(SPEC, phi.cpu().numpy(), ref) < 1e-6
 
 
-def test_extrapolated_graph_replay_matches_host_loop():
-    graph = _plan(launch="graph", warm_extrapolate=True)
-    loop = _plan(launch="dynamic", warm_extrapolate=True)
+@pytest.mark.parametrize("order", [2, 3])
+def test_polynomial_in_time_density_is_extrapolated_to_its_order(order):
+    """Degree-`order` density sequence: the plan of that order needs at most
+    two V-cycles per mode once order + 1 earlier solutions exist; the plan
+    one order lower (whose polynomial misses the top term) needs more."""
+    r0, r1 = _blobs(SPEC, 73), _blobs(SPEC, 74)
+    rhos = [r0 + 0.02 * (k**order) * (r1 - r0) for k in range(order + 4)]
+    hi = _plan(launch="graph", warm_extrapolate=order)
+    lo = _plan(launch="graph", warm_extrapolate=order - 1)
+    for k, rho in enumerate(rhos):
+        rd = torch.from_numpy(rho).cuda()
+        ph, ih = hi.solve(rd, tol=1e-8, warm=k > 0, extrapolate=True)
+        pl, il = lo.solve(rd, tol=1e-8, warm=k > 0, extrapolate=True)
+        assert ih["converged"] and il["converged"], k
+        mh = max(ih["cycles1"].max(), ih["cycles2"].max())
+        ml = max(il["cycles1"].max(), il["cycles2"].max())
+        print(f"order {order}, step {k}: slowest mode {mh}, order {order - 1}: {ml}", flush=True)
+        if k >= order + 1:
+            assert mh <= 2, (k, mh)
+            assert ml >= 4, (k, ml)
+        assert _l2(SPEC, ph.cpu().numpy(), pl.cpu().numpy()) < 1e-6, k
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_extrapolated_graph_replay_matches_host_loop(order):
+    graph = _plan(launch="graph", warm_extrapolate=order)
+    loop = _plan(launch="dynamic", warm_extrapolate=order)
     for k, rd in enumerate(_traj(SPEC, 8)):
         pg, ig = graph.solve(rd, tol=1e-8, warm=k > 0, extrapolate=True)
         pl, il = loop.solve(rd, tol=1e-8, warm=k > 0, extrapolate=True)
@@ -122,12 +148,12 @@ def test_extrapolated_graph_replay_matches_host_loop():
 def test_extrapolated_batch_matches_single_plans():
     from paper_2606_17636_amd import smg
     specs = [SPEC, SPEC2]
-    kw = dict(launch="dynamic", precision="fp64", nu_pre=2, nu_post=2, warm_extrapolate=True)
+    kw = dict(launch="dynamic", precision="fp64", nu_pre=2, nu_post=2, warm_extrapolate=3)
     singles = [_plan(s, **kw) for s in specs]
     members = [_plan(s, **kw) for s in specs]
     batch = smg.Batch(members).setup()
-    trajs = [_traj(s, 6, seed=5 + q) for q, s in enumerate(specs)]
-    for k in range(6):
+    trajs = [_traj(s, 7, seed=5 + q) for q, s in enumerate(specs)]
+    for k in range(7):
         rhos = [t[k] for t in trajs]
         ones = [p.solve(r, tol=1e-8, warm=k > 0, extrapolate=True) for p, r in zip(singles, rhos)]
         phis, infos = batch.solve(rhos, tol=1e-8, warm=k > 0, extrapolate=True)
