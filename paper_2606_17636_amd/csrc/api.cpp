@@ -141,7 +141,7 @@ struct GraphEnt {
   hipGraphExec_t exec = nullptr;
   unsigned long long used = 0;
 };
-constexpr int kMaxGraphs = 8;
+constexpr int kMaxGraphs = 64;
 }  // namespace
 
 // Plans whose multigrid solves share one engine (a plan alone, or a batch):
@@ -240,6 +240,11 @@ struct smg_plan {
   size_t w_xprev[2][3] = {{0, 0, 0}, {0, 0, 0}};
   int xhave[2] = {0, 0};
   int xstep[2] = {0, 0};
+  // the kept solutions live in a ring of slots: xorder[t][j] is the slot of
+  // the j-th newest; a solve writes u_{t-1} into the oldest position's slot,
+  // which then becomes the newest (no data moves); back to identity whenever
+  // the history is empty again
+  int xorder[2][3] = {{0, 1, 2}, {0, 1, 2}};
   // bumped whenever a buffer that captured solve graphs write to changes
   // (network attach, recording buffer); part of every group graph key, so a
   // batch holding this plan never replays a graph with the old pointers
@@ -1075,7 +1080,9 @@ static smg_status net_after(smg_plan* p, int t, bool warm, hipStream_t st) {
 // solutions to extrapolate from): every mode starts from the polynomial
 // extrapolation of its last solutions (order 1: 2 u_{t-1} - u_{t-2};
 // 2: 3 u_{t-1} - 3 u_{t-2} + u_{t-3}; 3: 4 u_{t-1} - 6 u_{t-2} + 4 u_{t-3} -
-// u_{t-4}), and the kept history shifts.  Runs between the two phases of the
+// u_{t-4}), and the kept history advances (the kernel writes u_{t-1} into
+// the oldest position's slot; group_solve rotates the slot order after the
+// solve).  Runs between the two phases of the
 // learned guess: after net_before has read u_{t-1}, before the judge, which
 // then weighs the network's candidate against this start.
 static smg_status warm_extrapolate(smg_plan* p, int t, bool warm, hipStream_t st) {
@@ -1083,7 +1090,7 @@ static smg_status warm_extrapolate(smg_plan* p, int t, bool warm, hipStream_t st
   const size_t plane = (size_t)p->spec.n_a * p->spec.n_b, n = (size_t)p->M * plane;
   const int kept = p->opts.warm_extrapolate;
   double2* hist[3] = {nullptr, nullptr, nullptr};
-  for (int j = 0; j < kept; ++j) hist[j] = p->dptr(p->w_xprev[t][j]);
+  for (int j = 0; j < kept; ++j) hist[j] = p->dptr(p->w_xprev[t][p->xorder[t][j]]);
   HIPCHK(smgg::extrapolate(target_u(p, t), hist, kept, n, 0, p->xstep[t], st));
   return SMG_OK;
 }
@@ -1134,7 +1141,7 @@ static smg_status group_graph(Group& g, double tol, bool warm, unsigned flags, c
                                   16 * p->pn.prev2_ok[0] + 32 * p->pn.prev2_ok[1]
                             : 0);
     key.push_back((int)p->gen);
-    key.push_back(p->xstep[0] + 4 * p->xstep[1]);
+    key.push_back(p->xstep[0] + 4 * p->xstep[1] + 16 * p->xorder[0][0] + 64 * p->xorder[1][0]);
   }
   long long tb;
   std::memcpy(&tb, &tol, sizeof(tb));
@@ -1223,7 +1230,11 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
   for (smg_plan* p : g.plans) {
     if (extrap && !p->opts.warm_extrapolate)
       return fail(SMG_EINVAL, "SMG_WARM_EXTRAP needs a plan created with opts.warm_extrapolate");
-    for (int t = 0; t < 2; ++t) p->xstep[t] = extrap && warm ? std::min(p->xhave[t], p->opts.warm_extrapolate + 1) : 0;
+    for (int t = 0; t < 2; ++t) {
+      p->xstep[t] = extrap && warm ? std::min(p->xhave[t], p->opts.warm_extrapolate + 1) : 0;
+      if (p->xhave[t] <= 1)  // nothing kept yet: start the ring over (the same graphs for every sequence)
+        for (int j = 0; j < 3; ++j) p->xorder[t][j] = j;
+    }
   }
   // learned-guess bookkeeping, decided on the host (a replayed graph runs
   // none of the body's host code): a guess step of target t runs when the
@@ -1263,7 +1274,15 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
   if (timings) HIPCHK(hipEventRecord(ev[5], st));
   g.have_prev = true;
   for (smg_plan* p : g.plans)
-    for (int t = 0; t < 2; ++t) p->xhave[t] = p->xstep[t] > 0 ? std::min(p->xstep[t] + 1, p->opts.warm_extrapolate + 1) : 1;
+    for (int t = 0; t < 2; ++t) {
+      p->xhave[t] = p->xstep[t] > 0 ? std::min(p->xstep[t] + 1, p->opts.warm_extrapolate + 1) : 1;
+      const int kept = p->opts.warm_extrapolate;
+      if (p->xstep[t] > 0 && kept > 1) {  // the oldest position's slot now holds the newest solution
+        const int s0 = p->xorder[t][kept - 1];
+        for (int j = kept - 1; j > 0; --j) p->xorder[t][j] = p->xorder[t][j - 1];
+        p->xorder[t][0] = s0;
+      }
+    }
   for (int q = 0; q < P; ++q)
     for (int t = 0; t < 2; ++t) g.plans[q]->pn.have_u[t] = guess_step[q][t];
   // per-mode state of both solves (one synchronisation); modes that needed

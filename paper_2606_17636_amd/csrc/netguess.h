@@ -25,6 +25,7 @@ hipError_t record(const float* x, const double2* u, const double2* uprev, const 
                   int plane, int n_img, int* count, int capacity, float* samples, hipStream_t st);
 // warm start from the last k solutions (n values; hist[0..kept-1] the kept older ones, newest
 // first; k <= kept + 1): from value lo on, u <- the polynomial extrapolation through them
-// (2 u - h0, 3 u - 3 h0 + h1, 4 u - 6 h0 + 4 h1 - h2); then the history shifts, h0 <- u's old value
+// (2 u - h0, 3 u - 3 h0 + h1, 4 u - 6 h0 + 4 h1 - h2); u's old value goes into hist[kept - 1]
+// (the caller's ring of slots then makes that slot the newest)
 hipError_t extrapolate(double2* u, double2* const* hist, int kept, size_t n, size_t lo, int k, hipStream_t st);
 }  // namespace smgg

@@ -214,20 +214,20 @@ __global__ void k_advance(int* count, int n, int capacity) {
 }
 
 // Warm start from the last k solutions, u (the latest) and the kept ones
-// h[0], h[1], h[2] (older in turn; h[j] null beyond those kept): from value
-// lo on, u <- the value at the next step of the polynomial through them
-// (k = 2: 2 u - h0; k = 3: 3 u - 3 h0 + h1; k = 4: 4 u - 6 h0 + 4 h1 - h2;
-// k = 1: u unchanged); then the history shifts by one, h0 <- u's old value.
+// h[0], h[1], h[2] (older in turn; `kept` of them): from value lo on, u <-
+// the value at the next step of the polynomial through them (k = 2:
+// 2 u - h0; k = 3: 3 u - 3 h0 + h1; k = 4: 4 u - 6 h0 + 4 h1 - h2; k = 1: u
+// unchanged); u's old value goes into h[kept - 1], the oldest position,
+// whose slot the caller then makes the newest (a ring: nothing else moves).
 struct History {
   double2* h[3];
 };
 
-__global__ void k_extrapolate(double2* __restrict__ u, History hs, size_t n, size_t lo, int k) {
+__global__ void k_extrapolate(double2* __restrict__ u, History hs, int kept, size_t n, size_t lo, int k) {
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
     const double2 x = u[t];
     double2 q[3] = {};
-    for (int j = 0; j < 3; ++j)
-      if (hs.h[j]) q[j] = hs.h[j][t];
+    for (int j = 0; j < k - 1; ++j) q[j] = hs.h[j][t];
     if (t >= lo && k >= 2) {
       double2 v;
       if (k == 2) {
@@ -239,9 +239,7 @@ __global__ void k_extrapolate(double2* __restrict__ u, History hs, size_t n, siz
       }
       u[t] = v;
     }
-    for (int j = 2; j > 0; --j)
-      if (hs.h[j]) hs.h[j][t] = q[j - 1];
-    hs.h[0][t] = x;
+    hs.h[kept - 1][t] = x;
   }
 }
 
@@ -298,7 +296,7 @@ hipError_t extrapolate(double2* u, double2* const* hist, int kept, size_t n, siz
   if (kept < 1 || kept > 3 || k < 1 || k > kept + 1) return hipErrorInvalidValue;
   History hs{{nullptr, nullptr, nullptr}};
   for (int j = 0; j < kept; ++j) hs.h[j] = hist[j];
-  hipLaunchKernelGGL(k_extrapolate, dim3(grid1(n)), dim3(256), 0, st, u, hs, n, lo, k);
+  hipLaunchKernelGGL(k_extrapolate, dim3(grid1(n)), dim3(256), 0, st, u, hs, kept, n, lo, k);
   return hipGetLastError();
 }
 
