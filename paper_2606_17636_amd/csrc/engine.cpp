@@ -364,10 +364,12 @@ smg_status Engine::start(int target, double tol, double floor_factor, bool warm,
   max_cycles_ = max_cycles;
   const NormJob* dn = d_norm_ + (size_t)target * P;
   const NormJob* hn = h_norm_.data() + (size_t)target * P;
-  // a cold start's zero iterate is written by the zero-guess norm below
+  // a cold start's zero iterate is written by the zero-guess norm below; a
+  // warm start needs only the norm of f from it (its own defect pass below
+  // writes the FP32 residual and clears the correction)
   BatchRef ball{n_total_, nullptr, d_all_};
   int ev = prof_ ? prof_->mark(st) : -1;
-  if (smgk::mg_norm_partial(dn, hn, P, ball, false, d_partial_, nblk_, st, !zero_first_, !warm) != hipSuccess)
+  if (smgk::mg_norm_partial(dn, hn, P, ball, false, d_partial_, nblk_, st, !zero_first_, !warm, warm) != hipSuccess)
     return SMG_EHIP;
   if (smgk::mg_conv_init(dn, d_all_, n_total_, P, d_partial_, nblk_, tol, floor_factor, cs_[target], d_list_[target],
                          d_count_ + target, st) != hipSuccess)
@@ -375,7 +377,7 @@ smg_status Engine::start(int target, double tol, double floor_factor, bool warm,
   if (prof_) {
     double s = 0.0;
     for (int q = 0; q < P; ++q) s += (double)P_[q].n * P_[q].L[0].na * P_[q].L[0].nb;
-    prof_->close(EC_NORM, ev, (prm_.fp32 ? 32.0 : 16.0) * s, st);
+    prof_->close(EC_NORM, ev, (prm_.fp32 && !warm ? 32.0 : 16.0) * s, st);
   }
   fp32_owner_ = target;
   if (warm) {

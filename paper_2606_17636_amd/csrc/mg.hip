@@ -553,17 +553,19 @@ __global__ void __launch_bounds__(kThreads) k_prolong(const LvJob* __restrict__ 
 // block).  use_u = 0: the defect of the zero guess (f itself).  With the
 // mixed form the FP64 residual is also stored rounded to FP32 (the right-hand
 // side of the next FP32 correction cycle) and (zero_e) the FP32 correction is
-// zeroed.  With zero_u (zero guess only) the FP64 iterate is set to zero as
-// well, in place of a separate fill.
+// zeroed; with norm_only neither (the zero-guess norm of a warm start, whose
+// own defect pass writes them next).  With zero_u (zero guess only) the FP64
+// iterate is set to zero as well, in place of a separate fill.
 __global__ void __launch_bounds__(kThreads) k_norm_partial(const NormJob* __restrict__ jobs, BatchRef bt, int use_u,
-                                                          double* __restrict__ partial, int zero_e, int zero_u) {
+                                                          double* __restrict__ partial, int zero_e, int zero_u,
+                                                          int norm_only) {
   __shared__ double red[kThreads / 64];
   SMG_ENTRY(jobs, bt);
   const LevelDev L = J.L;
   const size_t off = (size_t)slot * L.na * L.nb;
   const double2* U = J.u + off;
   const double2* F = J.f + off;
-  const auto R32 = gbl(J.r32 ? J.r32 + off : nullptr);
+  const auto R32 = gbl(J.r32 && !norm_only ? J.r32 + off : nullptr);
   const auto E32 = gbl(J.e32 ? J.e32 + off : nullptr);
   const int cells = L.na * L.nb;
   double acc = 0.0;
@@ -806,12 +808,12 @@ int norm_blocks(const NormJob* hj, int n_prob) {
 }
 
 hipError_t mg_norm_partial(const NormJob* jobs, const NormJob* hj, int n_prob, const BatchRef& b, bool use_u,
-                           double* partial, int nblk, hipStream_t st, bool zero_e, bool zero_u) {
+                           double* partial, int nblk, hipStream_t st, bool zero_e, bool zero_u, bool norm_only) {
   (void)hj; (void)n_prob;
   if (!b.cap) return hipSuccess;
   if (zero_u && use_u) return hipErrorInvalidValue;  // the defect of a guess it would erase
   hipLaunchKernelGGL(k_norm_partial, dim3(nblk, b.cap), dim3(kThreads), 0, st, jobs, b, use_u ? 1 : 0, partial,
-                     zero_e ? 1 : 0, zero_u ? 1 : 0);
+                     zero_e ? 1 : 0, zero_u ? 1 : 0, norm_only ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -272,10 +272,11 @@ hipError_t mg_lds_cycle(const LdsJob* jobs, const LdsJob* hj, int n_prob, const 
 // Norms and convergence (sched.hip).  mg_norm_partial: volume-weighted
 // squared defect per (list position, block); use_u = 0 takes the zero guess
 // (defect = f).  With the mixed form the FP64 residual is also stored
-// rounded to FP32 and the FP32 correction zeroed.
+// rounded to FP32 and the FP32 correction zeroed, unless norm_only.
 int norm_blocks(const NormJob* hj, int n_prob);
 hipError_t mg_norm_partial(const NormJob* jobs, const NormJob* hj, int n_prob, const BatchRef& b, bool use_u,
-                           double* partial, int nblk, hipStream_t st, bool zero_e = true, bool zero_u = false);
+                           double* partial, int nblk, hipStream_t st, bool zero_e = true, bool zero_u = false,
+                           bool norm_only = false);
 // Thresholds from the zero-guess defects: thr = tol * max(d0, floor * max
 // over the problem's planes of d0); cyc = 0; the list keeps the planes
 // whose d0 exceeds thr.  The full list of n planes is `all` (n <= 4096).
