@@ -97,7 +97,9 @@ typedef struct {
                             lines (their radial cells reach aspect ratios
                             of 1e3 and more). */
   int launch;            /* SMG_LAUNCH_GRAPH [default]: after the first solve
-                            of a kind (zero or warm start) every V-cycle of a
+                            of a kind (zero guess; warm start, told apart by
+                            the number of solutions its extrapolation uses
+                            and by the learned guess) every V-cycle of a
                             solve is scheduled from the previous solve's
                             per-mode cycle counts, the whole body (both
                             multigrid solves and the boundary steps) replays

@@ -152,12 +152,16 @@ struct Group {
   int launch = SMG_LAUNCH_GRAPH;
   int max_cycles = 60;
   bool have_prev = false;
-  // per-mode cycle counts of the last solve, per initial-guess kind (0 zero,
-  // 1 warm) and target: the schedule of the next solve of that kind
-  std::vector<int> hist[2][2];
-  std::vector<int> hist_prev[2][2];  // the counts of the solve of that kind before the last one
-  int margin[2] = {0, 0};            // extra cycles per mode: 1 after a solve of the kind ran short
-  bool hist_ok[2] = {false, false};
+  // per-mode cycle counts of the last solve, per initial-guess kind and
+  // target: the schedule of the next solve of that kind.  Kinds: 0 zero
+  // guess; warm starts 1 + x + 5 g, with x the solutions the extrapolation
+  // uses (0: none, 1: the previous one .. 4: cubic) and g = 1 with the
+  // learned guess -- each start needs its own number of cycles
+  static constexpr int kKinds = 11;
+  std::vector<int> hist[kKinds][2];
+  std::vector<int> hist_prev[kKinds][2];  // the counts of the solve of that kind before the last one
+  int margin[kKinds] = {};                // extra cycles per mode: 1 after a solve of the kind ran short
+  bool hist_ok[kKinds] = {};
   std::vector<GraphEnt> graphs;
   unsigned long long clock = 0;
   hipStream_t cap_stream = nullptr;  // private stream the solve graphs are captured on
@@ -168,7 +172,7 @@ struct Group {
   }
   void reset() {
     have_prev = false;
-    hist_ok[0] = hist_ok[1] = false;
+    for (bool& b : hist_ok) b = false;
     for (auto& h : hist_prev)
       for (auto& v : h) v.clear();
     drop_graphs();
@@ -1225,17 +1229,19 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
     ~EvGuard() { if (on) for (int k = 0; k < 6; ++k) (void)hipEventDestroy(e[k]); }
   } guard{ev, timings};
   const bool warm = (flags & SMG_WARM_PREV) && g.have_prev;
-  const int wk = warm ? 1 : 0;
   const bool extrap = (flags & SMG_WARM_EXTRAP) != 0;
+  int xs = 0;  // solutions the extrapolated starts use (the most over the plans)
   for (smg_plan* p : g.plans) {
     if (extrap && !p->opts.warm_extrapolate)
       return fail(SMG_EINVAL, "SMG_WARM_EXTRAP needs a plan created with opts.warm_extrapolate");
     for (int t = 0; t < 2; ++t) {
       p->xstep[t] = extrap && warm ? std::min(p->xhave[t], p->opts.warm_extrapolate + 1) : 0;
+      xs = std::max(xs, p->xstep[t]);
       if (p->xhave[t] <= 1)  // nothing kept yet: start the ring over (the same graphs for every sequence)
         for (int j = 0; j < 3; ++j) p->xorder[t][j] = j;
     }
   }
+  const int wk = warm ? 1 + xs + ((flags & SMG_NET_GUESS) ? 5 : 0) : 0;
   // learned-guess bookkeeping, decided on the host (a replayed graph runs
   // none of the body's host code): a guess step of target t runs when the
   // solve is warm and the previous right-hand side is kept; it sees the
