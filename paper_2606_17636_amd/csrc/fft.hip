@@ -18,7 +18,7 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kPoints = 2048;  // complex points staged per block (ping-pong)
+constexpr int kPoints = 1024;  // complex points staged per block (ping-pong)
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
