@@ -992,6 +992,8 @@ static double2* target_u(const smg_plan* p, int t) { return p->dptr(t == 0 ? p->
 static smg_status net_before(smg_plan* p, int t, bool warm, bool guess, hipStream_t st) {
   PlanNet& pn = p->pn;
   if (!pn.net || !warm || !pn.prev_ok[t]) return SMG_OK;
+  // the inputs serve the network's guess or a recorded sample, nothing else
+  if (!guess && !pn.samples) return SMG_OK;
   const int plane = p->spec.n_a * p->spec.n_b;
   const size_t np = (size_t)(pn.m_max + 1) * plane;
   double2* uprev = reinterpret_cast<double2*>(pn.work + pn.o_uprev[t]);
@@ -1243,14 +1245,17 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
   }
   const int wk = warm ? 1 + xs + ((flags & SMG_NET_GUESS) ? 5 : 0) : 0;
   // learned-guess bookkeeping, decided on the host (a replayed graph runs
-  // none of the body's host code): a guess step of target t runs when the
-  // solve is warm and the previous right-hand side is kept; it sees the
+  // none of the body's host code): a guess step of target t (the network's
+  // inputs, and its candidate where it guesses) runs when the solve is warm,
+  // the previous right-hand side is kept and the network guesses this
+  // target (the potential's solve) or samples are recorded; it sees the
   // solution two steps back when the previous solve ran one as well
   std::vector<std::array<bool, 2>> guess_step(P, std::array<bool, 2>{false, false});
   for (int q = 0; q < P; ++q) {
     PlanNet& pn = g.plans[q]->pn;
     for (int t = 0; t < 2; ++t) {
-      guess_step[q][t] = pn.net && warm && pn.prev_ok[t];
+      const bool inputs = pn.samples != nullptr || (t == 1 && (flags & SMG_NET_GUESS));
+      guess_step[q][t] = pn.net && warm && pn.prev_ok[t] && inputs;
       pn.prev2_ok[t] = guess_step[q][t] && pn.have_u[t];
     }
   }
