@@ -223,24 +223,34 @@ struct History {
   double2* h[3];
 };
 
-__global__ void k_extrapolate(double2* __restrict__ u, History hs, int kept, size_t n, size_t lo, int k) {
-  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-    const double2 x = u[t];
-    double2 q[3] = {};
-    for (int j = 0; j < k - 1; ++j) q[j] = hs.h[j][t];
-    if (t >= lo && k >= 2) {
-      double2 v;
-      if (k == 2) {
-        v = make_double2(2.0 * x.x - q[0].x, 2.0 * x.y - q[0].y);
-      } else if (k == 3) {
-        v = make_double2(3.0 * (x.x - q[0].x) + q[1].x, 3.0 * (x.y - q[0].y) + q[1].y);
-      } else {
-        v = make_double2(4.0 * (x.x + q[1].x) - 6.0 * q[0].x - q[2].x, 4.0 * (x.y + q[1].y) - 6.0 * q[0].y - q[2].y);
-      }
-      u[t] = v;
+// One value per thread (the pass is a stream over HBM: four plane sets read,
+// two written); the kept solutions are read and written with non-temporal
+// hints, since the next use of each is a step away, while u stays cached
+// for the defect pass that follows.
+typedef double cd2 __attribute__((ext_vector_type(2)));
+template <int K>
+__global__ void __launch_bounds__(256) k_extrapolate(double2* __restrict__ u, History hs, int kept, size_t n, size_t lo) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double2 x = u[t];
+  cd2 q[3] = {};
+#pragma unroll
+  for (int j = 0; j < K - 1; ++j) q[j] = __builtin_nontemporal_load(reinterpret_cast<const cd2*>(hs.h[j]) + t);
+  if (K >= 2 && t >= lo) {
+    double2 v;
+    if (K == 2) {
+      v = make_double2(2.0 * x.x - q[0].x, 2.0 * x.y - q[0].y);
+    } else if (K == 3) {
+      v = make_double2(3.0 * (x.x - q[0].x) + q[1].x, 3.0 * (x.y - q[0].y) + q[1].y);
+    } else {
+      v = make_double2(4.0 * (x.x + q[1].x) - 6.0 * q[0].x - q[2].x, 4.0 * (x.y + q[1].y) - 6.0 * q[0].y - q[2].y);
     }
-    hs.h[kept - 1][t] = x;
+    u[t] = v;
   }
+  cd2 keep;
+  keep.x = x.x;
+  keep.y = x.y;
+  __builtin_nontemporal_store(keep, reinterpret_cast<cd2*>(hs.h[kept - 1]) + t);
 }
 
 unsigned grid1(size_t n) {
@@ -293,10 +303,16 @@ hipError_t record(const float* x, const double2* u, const double2* uprev, const 
 
 hipError_t extrapolate(double2* u, double2* const* hist, int kept, size_t n, size_t lo, int k, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  if (kept < 1 || kept > 3 || k < 1 || k > kept + 1) return hipErrorInvalidValue;
+  if (kept < 1 || kept > 3 || k < 1 || k > kept + 1 || (n + 255) / 256 > 0x7fffffffu) return hipErrorInvalidValue;
   History hs{{nullptr, nullptr, nullptr}};
   for (int j = 0; j < kept; ++j) hs.h[j] = hist[j];
-  hipLaunchKernelGGL(k_extrapolate, dim3(grid1(n)), dim3(256), 0, st, u, hs, kept, n, lo, k);
+  const dim3 grid((unsigned)((n + 255) / 256));
+  switch (k) {
+    case 1: hipLaunchKernelGGL(k_extrapolate<1>, grid, dim3(256), 0, st, u, hs, kept, n, lo); break;
+    case 2: hipLaunchKernelGGL(k_extrapolate<2>, grid, dim3(256), 0, st, u, hs, kept, n, lo); break;
+    case 3: hipLaunchKernelGGL(k_extrapolate<3>, grid, dim3(256), 0, st, u, hs, kept, n, lo); break;
+    default: hipLaunchKernelGGL(k_extrapolate<4>, grid, dim3(256), 0, st, u, hs, kept, n, lo); break;
+  }
   return hipGetLastError();
 }
 
