@@ -927,8 +927,10 @@ static smg_status need_ready(const smg_plan* p) {
   return SMG_OK;
 }
 
+// f2_holds_f: f2 already holds f (the forward FFT wrote both), so only the
+// boundary cells are completed.
 static smg_status james_steps(smg_plan* p, const double2* psi, const double2* f, double2* sigma, double2* theta,
-                              double2* f2, hipStream_t st) {
+                              double2* f2, hipStream_t st, bool f2_holds_f = false) {
   const Spec& s = p->spec;
   const int plane = s.n_a * s.n_b;
   const char* base = p->ws + p->w_blob;
@@ -940,7 +942,7 @@ static smg_status james_steps(smg_plan* p, const double2* psi, const double2* f,
   ev = prof_mark(*p, st);
   HIPCHK(smgk::james_conv(reinterpret_cast<const double*>(p->ws + p->w_dgf), sigma, theta, p->n_g, p->M, st));
   prof_close(*p, K_CONV, ev, M * ng * ng * 8.0 + M * ng * 32.0, st);
-  if (f2 != f) HIPCHK(smgk::copy_planes(f2, f, (size_t)p->M * plane, st));
+  if (f2 != f && !f2_holds_f) HIPCHK(smgk::copy_planes(f2, f, (size_t)p->M * plane, st));
   ev = prof_mark(*p, st);
   HIPCHK(smgk::james_apply(reinterpret_cast<const int*>(base + p->o_apc), reinterpret_cast<const int*>(base + p->o_apg0),
                            reinterpret_cast<const int*>(base + p->o_apg1), reinterpret_cast<const double*>(base + p->o_apc0),
@@ -971,10 +973,12 @@ static std::vector<int> schedule_of(const std::vector<int>& cyc, const std::vect
   return caps;
 }
 
-static smg_status james_all(Group& g, hipStream_t st) {
+// f2_holds_f: every plan's solve-2 right-hand side still holds the
+// transformed density (written by fft_forward_all, not completed since).
+static smg_status james_all(Group& g, hipStream_t st, bool f2_holds_f) {
   for (smg_plan* p : g.plans) {
     STCHK(james_steps(p, p->dptr(p->w_psi), p->dptr(p->w_f), p->dptr(p->w_sigma), p->dptr(p->w_theta),
-                      p->dptr(p->w_f2), st));
+                      p->dptr(p->w_f2), st, f2_holds_f));
     p->have_theta = true;
   }
   return SMG_OK;
@@ -1120,7 +1124,7 @@ static smg_status group_body(Group& g, double tol, bool warm, unsigned flags, co
   }
   for (smg_plan* p : g.plans) STCHK(net_after(p, 0, warm, st));
   if (ev) HIPCHK(hipEventRecord(ev[0], st));
-  STCHK(james_all(g, st));
+  STCHK(james_all(g, st, true));
   if (ev) HIPCHK(hipEventRecord(ev[1], st));
   for (smg_plan* p : g.plans) STCHK(net_before(p, 1, warm, guess, st));
   for (smg_plan* p : g.plans) STCHK(warm_extrapolate(p, 1, warm, st));
@@ -1196,8 +1200,10 @@ static smg_status fft_forward_all(Group& g, const double* const* rho, hipStream_
     const int lines = s.n_a * s.n_b;
     const double2* tw = reinterpret_cast<const double2*>(p->ws + p->w_blob + p->o_tw);
     int pe = prof_mark(*p, st);
-    HIPCHK(smgk::fft_r2c(rho[q], p->dptr(p->w_f), lines, s.n_phi, 4.0 * kPi * s.G / s.n_phi, tw, st));
-    prof_close(*p, K_FFT_R2C, pe, (double)lines * (8.0 * s.n_phi + 16.0 * p->M), st);
+    // the solve-2 right-hand side starts as the same modes (the James steps
+    // then complete its boundary cells in place)
+    HIPCHK(smgk::fft_r2c(rho[q], p->dptr(p->w_f), lines, s.n_phi, 4.0 * kPi * s.G / s.n_phi, tw, st, p->dptr(p->w_f2)));
+    prof_close(*p, K_FFT_R2C, pe, (double)lines * (8.0 * s.n_phi + 32.0 * p->M), st);
   }
   return SMG_OK;
 }
@@ -1311,7 +1317,7 @@ static smg_status group_solve(Group& g, const double* const* rho, double* const*
                               st));
     if (es.count[0] > 0) {
       STCHK(e.finish_dynamic(0, st, nullptr));
-      STCHK(james_all(g, st));
+      STCHK(james_all(g, st, false));
       // Phi^m holds the result for the old boundary data: a good guess
       STCHK(e.start(1, tol, kFloor, true, g.max_cycles, st));
     }

@@ -2,7 +2,7 @@
 //
 // Forward: modes[m][line] = scale * sum_k rho[line][k] e^{-2 pi i m k / N},
 // m = 0..N/2, line = i*n_b + j (so mode m's output is the contiguous plane
-// [n_a][n_b]).  Inverse: out[line][k] = sum_{m=0}^{N-1} X_m e^{+2 pi i m k/N}
+// [n_a][n_b]), optionally written to a second array as well.  Inverse: out[line][k] = sum_{m=0}^{N-1} X_m e^{+2 pi i m k/N}
 // with Hermitian completion.
 //
 // A real line of length N is packed as n = N/2 complex values
@@ -100,7 +100,7 @@ __device__ double2* fft_lds(double2* a, double2* b, int n, int lines, const doub
 }
 
 __global__ void __launch_bounds__(kThreads) k_fft_r2c(const double* __restrict__ rho, double2* __restrict__ modes,
-                                                     int n_lines, int N, double scale,
+                                                     double2* __restrict__ modes2, int n_lines, int N, double scale,
                                                      const double2* __restrict__ tw, int lpb) {
   extern __shared__ double2 sh[];
   const int n = N / 2;
@@ -124,7 +124,9 @@ __global__ void __launch_bounds__(kThreads) k_fft_r2c(const double* __restrict__
     double2 dd = csub(zm, zc);
     double2 O = make_double2(0.5 * dd.y, -0.5 * dd.x);  // -i/2 (Z_m - conj Z_{n-m})
     double2 X = cadd(E, cmul(post[m], O));
-    modes[(size_t)m * n_lines + line0 + line] = make_double2(scale * X.x, scale * X.y);
+    const double2 v = make_double2(scale * X.x, scale * X.y);
+    modes[(size_t)m * n_lines + line0 + line] = v;
+    if (modes2) modes2[(size_t)m * n_lines + line0 + line] = v;
   }
 }
 
@@ -174,10 +176,10 @@ static int fft_lines_per_block(int n_lines, int n) {
 }
 
 hipError_t fft_r2c(const double* rho, double2* modes, int n_lines, int n_phi, double scale,
-                   const double2* tw, hipStream_t st) {
+                   const double2* tw, hipStream_t st, double2* modes2) {
   const int n = n_phi / 2, lpb = fft_lines_per_block(n_lines, n);
   const int blocks = (n_lines + lpb - 1) / lpb;
-  hipLaunchKernelGGL(k_fft_r2c, dim3(blocks), dim3(kThreads), 2 * lpb * n * sizeof(double2), st, rho, modes,
+  hipLaunchKernelGGL(k_fft_r2c, dim3(blocks), dim3(kThreads), 2 * lpb * n * sizeof(double2), st, rho, modes, modes2,
                      n_lines, n_phi, scale, tw, lpb);
   return hipGetLastError();
 }

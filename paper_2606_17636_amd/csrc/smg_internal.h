@@ -231,8 +231,10 @@ namespace smgk {
 // Face acceleration (accel.hip)
 hipError_t accel(const AccelArgs& a, hipStream_t st);
 // FFT (fft.hip)
+// modes2 (optional): a second array given the same values (the plan's
+// solve-2 right-hand side, which the James steps then complete in place).
 hipError_t fft_r2c(const double* rho, double2* modes, int n_lines, int n_phi, double scale,
-                   const double2* tw, hipStream_t st);
+                   const double2* tw, hipStream_t st, double2* modes2 = nullptr);
 hipError_t fft_c2r(const double2* modes, double* out, int n_lines, int n_phi, const double2* tw,
                    hipStream_t st);
 // Multigrid (mg.hip).  `jobs` is the device array of one depth's LvJob per
