@@ -19,6 +19,12 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kPoints = 1024;  // complex points staged per block (ping-pong)
+// Values a thread moves per round of the staging and output loops: every
+// global load of a round is issued, unconditionally from an index clamped
+// into the array, before the first of them is used, so a round costs one
+// memory latency (a loop with a runtime trip count would wait for each load
+// in turn).
+constexpr int kItems = kPoints / kThreads;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -109,24 +115,42 @@ __global__ void __launch_bounds__(kThreads) k_fft_r2c(const double* __restrict__
   const int line0 = blockIdx.x * lpb;
   const int lines = min(lpb, n_lines - line0);
   const double2* src = reinterpret_cast<const double2*>(rho + (size_t)line0 * N);
-  for (int t = threadIdx.x; t < lines * n; t += blockDim.x) a[t] = src[t];
+  for (int t0 = 0; t0 < lines * n; t0 += kItems * kThreads) {
+    // clamped stores too (a thread past the end rewrites the last value with
+    // itself), so that no load is sunk into a conditional store's branch
+    double2 v[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) v[r] = src[min(t0 + (int)threadIdx.x + r * kThreads, lines * n - 1)];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) a[min(t0 + (int)threadIdx.x + r * kThreads, lines * n - 1)] = v[r];
+  }
   __syncthreads();
   double2* z = fft_lds(a, b, n, lines, tw);
   // separate the even/odd half spectra: X_m = E_m + e^{-2 pi i m/N} O_m
   const double2* post = tw + n;
   const int total = lines * (n + 1);
-  for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int m = t / lines, line = t - m * lines;
-    const double2* Z = z + line * n;
-    double2 zm = Z[m % n];
-    double2 zc = cconj(Z[(n - m) % n]);
-    double2 E = make_double2(0.5 * (zm.x + zc.x), 0.5 * (zm.y + zc.y));
-    double2 dd = csub(zm, zc);
-    double2 O = make_double2(0.5 * dd.y, -0.5 * dd.x);  // -i/2 (Z_m - conj Z_{n-m})
-    double2 X = cadd(E, cmul(post[m], O));
-    const double2 v = make_double2(scale * X.x, scale * X.y);
-    modes[(size_t)m * n_lines + line0 + line] = v;
-    if (modes2) modes2[(size_t)m * n_lines + line0 + line] = v;
+  constexpr int kOut = kItems + 1;  // lines * (n + 1) <= kPoints + lines
+  for (int t0 = 0; t0 < total; t0 += kOut * kThreads) {
+    double2 pw[kOut];
+#pragma unroll
+    for (int r = 0; r < kOut; ++r) pw[r] = post[min(t0 + (int)threadIdx.x + r * kThreads, total - 1) / lines];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < kOut; ++r) {
+      const int t = t0 + threadIdx.x + r * kThreads;
+      if (t >= total) continue;
+      const int m = t / lines, line = t - m * lines;
+      const double2* Z = z + line * n;
+      double2 zm = Z[m % n];
+      double2 zc = cconj(Z[(n - m) % n]);
+      double2 E = make_double2(0.5 * (zm.x + zc.x), 0.5 * (zm.y + zc.y));
+      double2 dd = csub(zm, zc);
+      double2 O = make_double2(0.5 * dd.y, -0.5 * dd.x);  // -i/2 (Z_m - conj Z_{n-m})
+      double2 X = cadd(E, cmul(pw[r], O));
+      const double2 v = make_double2(scale * X.x, scale * X.y);
+      modes[(size_t)m * n_lines + line0 + line] = v;
+      if (modes2) modes2[(size_t)m * n_lines + line0 + line] = v;
+    }
   }
 }
 
@@ -142,18 +166,30 @@ __global__ void __launch_bounds__(kThreads) k_fft_c2r(const double2* __restrict_
   // Z_m = (X_m + conj X_{n-m}) + i w^m (X_m - conj X_{n-m}), w = e^{+2 pi i/N};
   // stored conjugated so that a forward FFT gives conj of the inverse sum.
   const int total = lines * n;
-  for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int m = t / lines, line = t - m * lines;
-    double2 xm = modes[(size_t)m * n_lines + line0 + line];
-    double2 xr = modes[(size_t)(n - m) * n_lines + line0 + line];
-    if (m == 0) { xm.y = 0.0; xr.y = 0.0; }  // m = 0 and m = N/2 are real
-    double2 xc = cconj(xr);
-    double2 S = cadd(xm, xc);
-    double2 D = csub(xm, xc);
-    double2 wm = cconj(post[m]);               // e^{+2 pi i m/N}
-    double2 iwD = cmul(make_double2(-wm.y, wm.x), D);  // i w^m D
-    double2 Z = cadd(S, iwD);
-    a[line * n + m] = cconj(Z);
+  for (int t0 = 0; t0 < total; t0 += kItems * kThreads) {
+    double2 xm[kItems], xr[kItems], pw[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const int t = min(t0 + (int)threadIdx.x + r * kThreads, total - 1);
+      const int m = t / lines, line = t - m * lines;
+      xm[r] = modes[(size_t)m * n_lines + line0 + line];
+      xr[r] = modes[(size_t)(n - m) * n_lines + line0 + line];
+      pw[r] = post[m];
+    }
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const int t = t0 + threadIdx.x + r * kThreads;
+      if (t >= total) continue;
+      const int m = t / lines, line = t - m * lines;
+      if (m == 0) { xm[r].y = 0.0; xr[r].y = 0.0; }  // m = 0 and m = N/2 are real
+      double2 xc = cconj(xr[r]);
+      double2 S = cadd(xm[r], xc);
+      double2 D = csub(xm[r], xc);
+      double2 wm = cconj(pw[r]);                 // e^{+2 pi i m/N}
+      double2 iwD = cmul(make_double2(-wm.y, wm.x), D);  // i w^m D
+      double2 Z = cadd(S, iwD);
+      a[line * n + m] = cconj(Z);
+    }
   }
   __syncthreads();
   double2* z = fft_lds(a, b, n, lines, tw);
