@@ -25,9 +25,16 @@ __global__ void k_screen(const int* __restrict__ adj, const double* __restrict__
   }
 }
 
-// Theta = Gt sigma per mode: one wavefront per output row, lanes stride the
-// row (coalesced 512-byte reads of the FP64 table), sigma staged in LDS.
+// Theta = Gt sigma per mode: each wavefront takes kRowsPerWave output rows,
+// lanes stride the rows (coalesced 512-byte reads of the FP64 table), sigma
+// staged in LDS.  A round loads kColRounds values of every row of the wave
+// (clamped indices, all issued before the first is used), so a row costs one
+// memory latency per 64 kColRounds columns; each lane still sums its columns
+// in ascending order.
 constexpr int kRowsPerBlock = 16;
+constexpr int kRowsPerWave = kRowsPerBlock / (kThreads / 64);
+constexpr int kColRounds = 4;
+
 __global__ void __launch_bounds__(kThreads) k_conv(const double* __restrict__ dgf, const double2* __restrict__ sigma,
                                                   double2* __restrict__ theta, int n_g) {
   extern __shared__ double2 sg[];
@@ -37,22 +44,37 @@ __global__ void __launch_bounds__(kThreads) k_conv(const double* __restrict__ dg
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double* G = dgf + (size_t)m * n_g * n_g;
-  for (int r = wave; r < kRowsPerBlock; r += kThreads / 64) {
-    const int row = blockIdx.x * kRowsPerBlock + r;
-    if (row >= n_g) break;
-    const double* g = G + (size_t)row * n_g;
-    double ax = 0.0, ay = 0.0;
-    for (int c = lane; c < n_g; c += 64) {
-      const double w = g[c];
-      const double2 v = sg[c];
-      ax = fma(w, v.x, ax);
-      ay = fma(w, v.y, ay);
+  const int row0 = blockIdx.x * kRowsPerBlock + wave * kRowsPerWave;
+  double ax[kRowsPerWave], ay[kRowsPerWave];
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r) ax[r] = ay[r] = 0.0;
+  for (int c0 = 0; c0 < n_g; c0 += 64 * kColRounds) {
+    double w[kRowsPerWave][kColRounds];
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r)
+#pragma unroll
+      for (int k = 0; k < kColRounds; ++k)
+        w[r][k] = G[(size_t)min(row0 + r, n_g - 1) * n_g + min(c0 + lane + 64 * k, n_g - 1)];
+#pragma unroll
+    for (int k = 0; k < kColRounds; ++k) {
+      const int c = c0 + lane + 64 * k;
+      const double2 v = sg[min(c, n_g - 1)];
+#pragma unroll
+      for (int r = 0; r < kRowsPerWave; ++r) {
+        const double wk = c < n_g ? w[r][k] : 0.0;
+        ax[r] = fma(wk, v.x, ax[r]);
+        ay[r] = fma(wk, v.y, ay[r]);
+      }
     }
+  }
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r) {
+    double x = ax[r], y = ay[r];
     for (int o = 32; o > 0; o >>= 1) {
-      ax += __shfl_xor(ax, o);
-      ay += __shfl_xor(ay, o);
+      x += __shfl_xor(x, o);
+      y += __shfl_xor(y, o);
     }
-    if (lane == 0) theta[(size_t)m * n_g + row] = make_double2(ax, ay);
+    if (lane == 0 && row0 + r < n_g) theta[(size_t)m * n_g + row0 + r] = make_double2(x, y);
   }
 }
 
