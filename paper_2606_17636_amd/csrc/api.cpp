@@ -194,7 +194,7 @@ struct PlanNet {
   char* work = nullptr;
   NetWork wl{};
   size_t o_fprev[2] = {0, 0}, o_uprev[2] = {0, 0}, o_uprev2[2] = {0, 0}, o_cand = 0, o_cs = 0, o_us = 0, o_u2 = 0,
-         o_sc = 0, o_part = 0, o_used = 0, o_jobs = 0, o_lv = 0, o_list = 0, o_rec = 0, o_rec0 = 0, o_scpart = 0, bytes = 0;
+         o_u2b = 0, o_sc = 0, o_part = 0, o_used = 0, o_jobs = 0, o_lv = 0, o_list = 0, o_rec = 0, o_rec0 = 0, o_scpart = 0, bytes = 0;
   std::vector<NormJob> hjobs;  // [target][smoothed candidate, smoothed previous solution]
   std::vector<LvJob> hlv;      // [target][the same two arrays]: one smoothing step
   bool prev_ok[2] = {false, false};
@@ -1042,17 +1042,18 @@ static smg_status net_judge(smg_plan* p, int t, bool warm, bool guess, bool base
   const double2* cand = reinterpret_cast<const double2*>(pn.work + pn.o_cand);
   if (base_in_u) HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_us), target_u(p, t), np, st));
   HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_cs), cand, np, st));
-  BatchRef b{pn.m_max + 1, nullptr, reinterpret_cast<const int*>(pn.work + pn.o_list)};
+  // both starts as the two problems of one launch per step: list position
+  // q (m_max + 1) + m is start q's mode m, so the norm partials of the
+  // candidate come first, then those of the other start
+  BatchRef b{2 * (pn.m_max + 1), nullptr, reinterpret_cast<const int*>(pn.work + pn.o_list)};
   const LvJob* dl = reinterpret_cast<const LvJob*>(pn.work + pn.o_lv) + 2 * t;
   const bool exact = p->opts.line_solver == SMG_LINE_EXACT;
-  for (int k = 0; k < 2; ++k)
-    for (int dir = 0; dir < 2; ++dir)
-      HIPCHK(smgk::mg_smooth_dir(dl + k, &pn.hlv[2 * t + k], 1, b, p->opts.n_sor, exact, dir, false, st));
+  for (int dir = 0; dir < 2; ++dir)
+    HIPCHK(smgk::mg_smooth_dir(dl, &pn.hlv[2 * t], 2, b, p->opts.n_sor, exact, dir, false, st));
   const NormJob* dj = reinterpret_cast<const NormJob*>(pn.work + pn.o_jobs) + 2 * t;
   double* pc = reinterpret_cast<double*>(pn.work + pn.o_part);
   double* pu = pc + (size_t)(pn.m_max + 1) * pn.nblk;
-  HIPCHK(smgk::mg_norm_partial(dj, &pn.hjobs[2 * t], 1, b, true, pc, pn.nblk, st));
-  HIPCHK(smgk::mg_norm_partial(dj + 1, &pn.hjobs[2 * t + 1], 1, b, true, pu, pn.nblk, st));
+  HIPCHK(smgk::mg_norm_partial(dj, &pn.hjobs[2 * t], 2, b, true, pc, pn.nblk, st));
   HIPCHK(smgg::select(pc, pu, pn.nblk, cand, base_in_u ? nullptr : uprev, pn.prev2_ok[t] ? uprev2 : nullptr, sc,
                       target_u(p, t), plane, pn.m_max, reinterpret_cast<int*>(pn.work + pn.o_used) + t * (pn.m_max + 1),
                       st));
@@ -1397,7 +1398,9 @@ static smg_status net_layout(const smg_plan* p, const smg_net* net, int m_max, P
   pn.o_cand = take(sizeof(double2) * np);
   pn.o_cs = take(sizeof(double2) * np);
   pn.o_us = take(sizeof(double2) * np);
-  pn.o_u2 = take(sizeof(double2) * np);  // the smoother's second array (steps run one after another)
+  // the smoother's second arrays of the two judged starts (smoothed in one launch)
+  pn.o_u2 = take(sizeof(double2) * np);
+  pn.o_u2b = take(sizeof(double2) * np);
   pn.o_sc = take(sizeof(double) * 4 * pn.n_img);
   pn.o_scpart = take(sizeof(double) * smgg::scales_partial_doubles(pn.n_img));
   NormJob hj{};
@@ -1407,7 +1410,7 @@ static smg_status net_layout(const smg_plan* p, const smg_net* net, int m_max, P
   pn.o_used = take(sizeof(int) * 2 * (m_max + 1));
   pn.o_jobs = take(sizeof(NormJob) * 4);
   pn.o_lv = take(sizeof(LvJob) * 4);
-  pn.o_list = take(sizeof(int) * (m_max + 1));
+  pn.o_list = take(sizeof(int) * 2 * (m_max + 1));  // both starts' planes
   pn.o_rec = take(sizeof(int));
   pn.o_rec0 = take(sizeof(int));   // the count when the current solve started
   pn.bytes = off;
@@ -1440,6 +1443,7 @@ extern "C" smg_status smg_plan_attach_net(smg_plan* p, smg_net* net, int m_max, 
   const bool exact = p->opts.line_solver == SMG_LINE_EXACT;
   for (int t = 0; t < 2; ++t) {
     for (size_t arr : {pn.o_cs, pn.o_us}) {
+      const size_t u2 = arr == pn.o_cs ? pn.o_u2 : pn.o_u2b;
       NormJob c{};
       c.L = p->levels[0];
       c.u = reinterpret_cast<double2*>(pn.work + arr);
@@ -1449,7 +1453,7 @@ extern "C" smg_status smg_plan_attach_net(smg_plan* p, smg_net* net, int m_max, 
       J.L = p->levels[0];
       J.C = p->levels[0];
       J.u = c.u;
-      J.u2 = pn.work + pn.o_u2;
+      J.u2 = pn.work + u2;
       J.f = const_cast<double2*>(c.f);
       J.active = 1;
       for (int dir = 0; dir < 2; ++dir) {
@@ -1463,8 +1467,13 @@ extern "C" smg_status smg_plan_attach_net(smg_plan* p, smg_net* net, int m_max, 
       pn.hlv.push_back(J);
     }
   }
-  std::vector<int> list(m_max + 1);
-  for (int m = 0; m <= m_max; ++m) list[m] = ent_make(0, m);
+  // the judge's launches cover both starts: problem 0 the candidate, 1 the
+  // other start, modes 0..m_max of each
+  std::vector<int> list(2 * (m_max + 1));
+  for (int m = 0; m <= m_max; ++m) {
+    list[m] = ent_make(0, m);
+    list[m_max + 1 + m] = ent_make(1, m);
+  }
   std::vector<int> zeros(2 * (m_max + 1) + 1, 0);
   HIPCHK(hipMemcpyAsync(pn.work + pn.o_jobs, pn.hjobs.data(), sizeof(NormJob) * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(pn.work + pn.o_lv, pn.hlv.data(), sizeof(LvJob) * 4, hipMemcpyHostToDevice, st));
