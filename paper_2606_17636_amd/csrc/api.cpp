@@ -1014,12 +1014,13 @@ static smg_status net_before(smg_plan* p, int t, bool warm, bool guess, hipStrea
                         pn.n_img, reinterpret_cast<float*>(pn.work + pn.wl.x32), st));
   if (!guess) return SMG_OK;
   STCHK(pn.net->def.forward(pn.work, pn.wl, st, false));
-  // the candidate and the baseline it is judged against (the linear
-  // extrapolation, or the previous solution before two exist), the latter
-  // straight into the judge's second buffer
+  // the candidate (also into the copy the judge smooths) and the baseline
+  // it is judged against (the linear extrapolation, or the previous solution
+  // before two exist), the latter straight into the judge's second buffer
   HIPCHK(smgg::candidate(uprev, pn.prev2_ok[t] ? uprev2 : nullptr, reinterpret_cast<const float*>(pn.work + pn.wl.y), sc,
                          plane, pn.m_max, reinterpret_cast<double2*>(pn.work + pn.o_cand),
-                         reinterpret_cast<double2*>(pn.work + pn.o_us), st));
+                         reinterpret_cast<double2*>(pn.work + pn.o_us), st,
+                         reinterpret_cast<double2*>(pn.work + pn.o_cs)));
   return SMG_OK;
 }
 
@@ -1041,7 +1042,6 @@ static smg_status net_judge(smg_plan* p, int t, bool warm, bool guess, bool base
   const double* sc = reinterpret_cast<const double*>(pn.work + pn.o_sc);
   const double2* cand = reinterpret_cast<const double2*>(pn.work + pn.o_cand);
   if (base_in_u) HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_us), target_u(p, t), np, st));
-  HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_cs), cand, np, st));
   // both starts as the two problems of one launch per step: list position
   // q (m_max + 1) + m is start q's mode m, so the norm partials of the
   // candidate come first, then those of the other start

@@ -16,8 +16,9 @@ hipError_t scales(const double2* f, const double2* fprev, const double2* uprev, 
 hipError_t assemble(const double2* f, const double2* fprev, const double2* uprev, const double2* uprev2, const double* sc,
                     int na, int nb, int n_img, float* x, hipStream_t st);
 // base = uprev + (uprev - uprev2 if uprev2; not on static parts), cand = base + s_o y
+// (also into cand2 when given: the copy the judge smooths)
 hipError_t candidate(const double2* uprev, const double2* uprev2, const float* y, const double* sc, int plane, int m_max,
-                     double2* cand, double2* base, hipStream_t st);
+                     double2* cand, double2* base, hipStream_t st, double2* cand2 = nullptr);
 // per mode: u = cand where pc's norm is below pu's, else base (recomputed; u left as it is with uprev null)
 hipError_t select(const double* pc, const double* pu, int nblk, const double2* cand, const double2* uprev,
                   const double2* uprev2, const double* sc, double2* u, int plane, int m_max, int* used, hipStream_t st);

@@ -143,7 +143,7 @@ __device__ __forceinline__ double2 guess_base(const double2* __restrict__ uprev,
 // extrapolated); base = the baseline alone, the judge's other start
 __global__ void k_candidate(const double2* __restrict__ uprev, const double2* __restrict__ uprev2,
                             const float* __restrict__ y, const double* __restrict__ sc, int plane, int m_max,
-                            double2* __restrict__ cand, double2* __restrict__ base) {
+                            double2* __restrict__ cand, double2* __restrict__ base, double2* __restrict__ cand2) {
   const size_t total = (size_t)(m_max + 1) * plane;
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
     const int m = (int)(t / plane), q = (int)(t - (size_t)m * plane);
@@ -154,6 +154,7 @@ __global__ void k_candidate(const double2* __restrict__ uprev, const double2* __
     v.x += sr * (double)y[(size_t)kr * plane + q];
     if (m > 0) v.y += si * (double)y[(size_t)(2 * m) * plane + q];
     cand[t] = v;
+    if (cand2) cand2[t] = v;
   }
 }
 
@@ -279,9 +280,9 @@ hipError_t assemble(const double2* f, const double2* fprev, const double2* uprev
 }
 
 hipError_t candidate(const double2* uprev, const double2* uprev2, const float* y, const double* sc, int plane, int m_max,
-                     double2* cand, double2* base, hipStream_t st) {
+                     double2* cand, double2* base, hipStream_t st, double2* cand2) {
   hipLaunchKernelGGL(k_candidate, dim3(grid1((size_t)(m_max + 1) * plane)), dim3(256), 0, st, uprev, uprev2, y, sc, plane,
-                     m_max, cand, base);
+                     m_max, cand, base, cand2);
   return hipGetLastError();
 }
 
