@@ -499,30 +499,77 @@ __global__ void __launch_bounds__(kThreads) k_residual(const LvJob* __restrict__
 }
 
 // Coarse right-hand side = bilinear restriction of the fine residual; the
-// coarse correction starts from zero.
+// coarse correction starts from zero.  A thread reads everything its coarse
+// cell needs (the 2 x 2 fine cells' stencils of u, f, the row and column
+// tables and the restriction weights) before it computes, so one round of
+// memory latency covers them; the residuals are those of resid_at, with the
+// same operations in the same order.
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_restrict(const LvJob* __restrict__ jobs, BatchRef bt) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4)))
+k_restrict(const LvJob* __restrict__ jobs, BatchRef bt) {
   using V = typename Vec<R>::T;
   SMG_ENTRY(jobs, bt);
   if (!J.active) return;
   const LevelDev L = J.L, C = J.C;
   const size_t off = (size_t)slot * L.na * L.nb;
   const size_t offc = (size_t)slot * C.na * C.nb;
-  const V* U = static_cast<const V*>(J.u) + off;
-  const V* F = static_cast<const V*>(J.f) + off;
+  const auto U = gbl(static_cast<const V*>(J.u) + off);
+  const auto F = gbl(static_cast<const V*>(J.f) + off);
   const auto FC = gbl(static_cast<V*>(J.fc) + offc);
   const auto UC = gbl(static_cast<V*>(J.uc) + offc);
+  const int na = L.na, nb = L.nb;
   const int cells = C.na * C.nb;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cells; t += gridDim.x * blockDim.x) {
     const int I = t / C.nb, Jc = t - I * C.nb;
+    R wa[2], wb[2], Rr[2], ca[2], ua[2], da[2], cb[2], ub[2], db[2];
+    V uc[2][2], uip[2][2], uim[2][2], ujp[2][2], ujm[2][2], fv[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int i = 2 * I + a;
+      wa[a] = (R)gbl(L.rwa)[i];
+      Rr[a] = (R)gbl(L.Rr)[i];
+      ca[a] = (R)gbl(L.Ca)[(size_t)m * na + i];
+      ua[a] = (R)gbl(L.ua)[i];
+      da[a] = (R)gbl(L.da)[i];
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int j = 2 * Jc + b;
+      wb[b] = (R)gbl(L.rwb)[j];
+      cb[b] = (R)gbl(L.Cb)[(size_t)m * nb + j];
+      ub[b] = (R)gbl(L.ub)[j];
+      db[b] = (R)gbl(L.db)[j];
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int i = 2 * I + a;
+      const int ip = min(i + 1, na - 1), im = max(i - 1, 0);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int j = 2 * Jc + b;
+        const int jp = min(j + 1, nb - 1), jm = max(j - 1, 0);
+        const size_t row = (size_t)i * nb;
+        uc[a][b] = U[row + j];
+        uip[a][b] = U[(size_t)ip * nb + j];
+        uim[a][b] = U[(size_t)im * nb + j];
+        ujp[a][b] = U[row + jp];
+        ujm[a][b] = U[row + jm];
+        fv[a][b] = F[row + j];
+      }
+    }
     V acc = mkv<R>(0, 0);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      const R wa = (R)gbl(L.rwa)[2 * I + a];
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const R w = wa * (R)gbl(L.rwb)[2 * Jc + b];
-        const V r = resid_at<R>(L, m, U, F, 2 * I + a, 2 * Jc + b);
+        const R w = wa[a] * wb[b];
+        const R c = ca[a] + Rr[a] * cb[b];
+        V s = mkv<R>(c * uc[a][b].x, c * uc[a][b].y);
+        s = axpy<R>(ua[a], uip[a][b], s);
+        s = axpy<R>(da[a], uim[a][b], s);
+        s = axpy<R>(Rr[a] * ub[b], ujp[a][b], s);
+        s = axpy<R>(Rr[a] * db[b], ujm[a][b], s);
+        const V r = mkv<R>(fv[a][b].x - s.x, fv[a][b].y - s.y);
         acc = axpy<R>(w, r, acc);
       }
     }
