@@ -35,7 +35,9 @@ __device__ int block_scan(int v, int* wsum, int* total) {
 __device__ double sum_partial(const double* partial, int p, int nblk) {
   const auto pp = gbl(partial + (size_t)p * nblk);
   double s = 0.0;
-#pragma unroll 8
+  // 32 partials per round of loads (64 blocks per plane: two rounds), summed
+  // in order
+#pragma unroll 32
   for (int b = 0; b < nblk; ++b) s += pp[b];
   return sqrt(s);
 }
@@ -103,23 +105,37 @@ __global__ void __launch_bounds__(kConvThreads) k_converge(const NormJob* __rest
   int total;
   const int n = *count;  // every thread reads it before the block writes it
   norms_to_lds(partial, min(n, cap), nblk, s_nrm);
-  int e[kPerThread];
+  // the thread's list entries, their planes' state and thresholds, each
+  // kind read for all of the thread's entries at once (indices clamped to a
+  // valid entry; what lies beyond the list is not used)
+  int e[kPerThread], g[kPerThread], c[kPerThread];
+  double thr[kPerThread];
   bool kk[kPerThread];
+  const int last = max(n - 1, 0);
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) e[k] = list[min((int)threadIdx.x * kPerThread + k, last)];
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) g[k] = jobs[ent_prob(e[k])].base + ent_slot(e[k]);
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    c[k] = gbl(cs.cyc)[g[k]];
+    thr[k] = gbl(cs.thr)[g[k]];
+  }
   int keep = 0;
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
     const int p = threadIdx.x * kPerThread + k;
-    e[k] = -1;
     kk[k] = false;
-    if (p >= n) continue;
-    e[k] = list[p];
+    if (p >= n) {
+      e[k] = -1;
+      continue;
+    }
     if (p < cap) {
-      const int g = jobs[ent_prob(e[k])].base + ent_slot(e[k]);
       const double nrm = s_nrm[p];
-      gbl(cs.cur)[g] = nrm;
-      const int c = gbl(cs.cyc)[g] + count_cycle;
-      gbl(cs.cyc)[g] = c;
-      kk[k] = !(nrm <= gbl(cs.thr)[g]) && c < max_cycles;
+      gbl(cs.cur)[g[k]] = nrm;
+      const int cn = c[k] + count_cycle;
+      gbl(cs.cyc)[g[k]] = cn;
+      kk[k] = !(nrm <= thr[k]) && cn < max_cycles;
     } else {
       kk[k] = true;  // not cycled this time
     }
