@@ -1075,6 +1075,12 @@ static smg_status net_after(smg_plan* p, int t, bool warm, hipStream_t st) {
                         pn.prev2_ok[t] ? reinterpret_cast<const double2*>(pn.work + pn.o_uprev2[t]) : nullptr,
                         reinterpret_cast<const double*>(pn.work + pn.o_sc), plane, pn.n_img,
                         reinterpret_cast<int*>(pn.work + pn.o_rec), pn.capacity, pn.samples, st));
+  // solve 1's inputs are built only while samples are recorded, so its
+  // right-hand side is kept only then
+  if (t == 0 && !pn.samples) {
+    pn.prev_ok[0] = false;
+    return SMG_OK;
+  }
   HIPCHK(smgk::copy_planes(reinterpret_cast<double2*>(pn.work + pn.o_fprev[t]), target_f(p, t),
                            (size_t)(pn.m_max + 1) * plane, st));
   pn.prev_ok[t] = true;

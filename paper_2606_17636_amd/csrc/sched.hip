@@ -59,16 +59,23 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_init(const NormJob* __res
   int total;
   for (int q = threadIdx.x; q < n_prob; q += blockDim.x) dmax[q] = 0ull;
   norms_to_lds(partial, n, nblk, s_nrm);
+  // the thread's entries, then their plane indices, each read for all of
+  // its entries at once (indices clamped to a valid entry)
   int e[kPerThread], g[kPerThread];
   double d[kPerThread];
+  const int last = max(n - 1, 0);
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) e[k] = all[min((int)threadIdx.x * kPerThread + k, last)];
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) g[k] = jobs[ent_prob(e[k])].base + ent_slot(e[k]);
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
     const int p = threadIdx.x * kPerThread + k;
-    e[k] = -1;
-    if (p >= n) continue;
-    e[k] = all[p];
+    if (p >= n) {
+      e[k] = -1;
+      continue;
+    }
     const int q = ent_prob(e[k]);
-    g[k] = jobs[q].base + ent_slot(e[k]);
     d[k] = s_nrm[p];
     gbl(cs.d0)[g[k]] = d[k];
     gbl(cs.cur)[g[k]] = d[k];
