@@ -2,8 +2,9 @@
 //
 // Forward: modes[m][line] = scale * sum_k rho[line][k] e^{-2 pi i m k / N},
 // m = 0..N/2, line = i*n_b + j (so mode m's output is the contiguous plane
-// [n_a][n_b]), optionally written to a second array as well.  Inverse: out[line][k] = sum_{m=0}^{N-1} X_m e^{+2 pi i m k/N}
-// with Hermitian completion.
+// [n_a][n_b]), optionally written to a second array as well.  Inverse:
+// out[line][k] = sum_{m=0}^{N-1} X_m e^{+2 pi i m k/N} with Hermitian
+// completion.
 //
 // A real line of length N is packed as n = N/2 complex values
 // z_k = x_{2k} + i x_{2k+1}; an n-point complex Stockham FFT (radices 4, 2,
@@ -134,7 +135,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_r2c(const double* __restrict__
     double2 pw[kOut];
 #pragma unroll
     for (int r = 0; r < kOut; ++r) pw[r] = post[min(t0 + (int)threadIdx.x + r * kThreads, total - 1) / lines];
-    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_sched_barrier(0);  // the twiddle loads stay ahead of the arithmetic
 #pragma unroll
     for (int r = 0; r < kOut; ++r) {
       const int t = t0 + threadIdx.x + r * kThreads;

@@ -224,13 +224,14 @@ struct History {
   double2* h[3];
 };
 
-// One value per thread (the pass is a stream over HBM: four plane sets read,
+// One value per thread (the pass is a stream over HBM: up to four plane sets read,
 // two written); the kept solutions are read and written with non-temporal
 // hints, since the next use of each is a step away, while u stays cached
 // for the defect pass that follows.
 typedef double cd2 __attribute__((ext_vector_type(2)));
 template <int K>
-__global__ void __launch_bounds__(256) k_extrapolate(double2* __restrict__ u, History hs, int kept, size_t n, size_t lo) {
+__global__ void __launch_bounds__(256) k_extrapolate(double2* __restrict__ u, History hs, int kept, size_t n,
+                                                     size_t lo) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const double2 x = u[t];
