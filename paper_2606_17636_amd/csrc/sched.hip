@@ -113,14 +113,21 @@ __global__ void __launch_bounds__(kConvThreads) k_converge(const NormJob* __rest
   const int n = *count;  // every thread reads it before the block writes it
   norms_to_lds(partial, min(n, cap), nblk, s_nrm);
   // the thread's list entries, their planes' state and thresholds, each
-  // kind read for all of the thread's entries at once (indices clamped to a
-  // valid entry; what lies beyond the list is not used)
+  // kind read for all of the thread's entries at once: a position past the
+  // list's end reads a position inside the buffer (clamped) and then takes
+  // entry 0 (problem 0, slot 0) in its place, since the buffer need not hold
+  // an entry there, so every index below is valid; nothing read for such a
+  // position is used
   int e[kPerThread], g[kPerThread], c[kPerThread];
   double thr[kPerThread];
   bool kk[kPerThread];
   const int last = max(n - 1, 0);
 #pragma unroll
-  for (int k = 0; k < kPerThread; ++k) e[k] = list[min((int)threadIdx.x * kPerThread + k, last)];
+  for (int k = 0; k < kPerThread; ++k) {
+    const int p = (int)threadIdx.x * kPerThread + k;
+    const int v = list[min(p, last)];
+    e[k] = p < n ? v : 0;
+  }
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) g[k] = jobs[ent_prob(e[k])].base + ent_slot(e[k]);
 #pragma unroll
