@@ -8,17 +8,19 @@ mass + DGF convolution -> multigrid solve 2 -> inverse FFT) of the next
 snapshot's density to relative residual --tol (1e-8) on every mode, warm
 started from the previous steps: every mode from the cubic extrapolation of
 its last four solutions, and modes 0..4 of the potential's solve from the
-learned guess where the judge finds it better.  The chosen form: FP32/FP64 iterative refinement,
-per-mode cycle schedules replayed as HIP graphs, autotuned launch shapes,
-smoothing steps chosen at setup, learned initial guess.  The network is
+learned guess where the judge finds it better.  The chosen form: FP32/FP64
+iterative refinement, per-mode cycle schedules replayed as HIP graphs,
+autotuned launch shapes, smoothing steps chosen at setup, learned initial
+guess.  The network is
 trained at setup on 8 method-generated trajectories (seeds 50-57); the DGF
 tables, tuning and training are one-time setup, outside the timed region,
 as the DGF is in the paper.  --steps K times snapshots 1..K (snapshot 0 is
 the cold start of the trajectory), after --warmup W untimed passes over the
 same snapshots.  Reported next to it: the same trajectory with the
 extrapolated guess for every mode (no network) and with the previous step's
-solution as the guess (no network, no extrapolation), the plain GPU form (FP64, host
-reads after every V-cycle, red-black SOR coarsest solve, V(2,2), no graph),
+solution as the guess (no network, no extrapolation), the plain GPU form
+(FP64, host reads after every V-cycle, red-black SOR coarsest solve, V(2,2),
+no graph),
 cold solves of the 128x64x128 sphere and of one 256x128x256 snapshot, the
 per-launch roofline of the dominant kernel class, the error of a timed
 result against the FP64 oracle and the oracle's own throughput on the
