@@ -342,8 +342,9 @@ smg_status smg_net_conv3_wgrad_noalloc(const unsigned short *g_dev, int c_out, c
  * Attach a bound network as the initial-guess model of modes 0..m_max
  * (m_max <= 8; n_a and n_b divisible by 2^(levels-1)) using a caller-owned
  * work buffer of smg_plan_net_work_bytes bytes (256-byte aligned).  From
- * then on every solve keeps its right-hand sides of those modes for the next
- * step; a warm-started solve with SMG_NET_GUESS builds the network inputs
+ * then on every solve keeps the potential's right-hand side of those modes
+ * for the next step (that of solve 1 too while samples are recorded); a
+ * warm-started solve with SMG_NET_GUESS builds the network inputs
  * (per real image: f_t / s_f, (f_t - f_{t-1}) / s_d, u_{t-1} / s_u, m / 4,
  * the two normalised grid coordinates, this part of (u_{t-1} - u_{t-2}) /
  * s_o and of -i (u_{t-1} - u_{t-2}) / s_o, with s_f, s_d, s_u the plane RMS
@@ -356,16 +357,18 @@ smg_status smg_net_conv3_wgrad_noalloc(const unsigned short *g_dev, int c_out, c
  * linear extrapolation; u_{t-1} before u_{t-2} exists, and on a static
  * part) plus s_o y, the network's correction y, and the start the mode
  * would take otherwise: the plan's extrapolated warm start where
- * SMG_WARM_EXTRAP applies one, else that baseline.  The inputs of solve 1
- * are built as well (they are recorded as training samples), but its modes
- * take no network guess.
+ * SMG_WARM_EXTRAP applies one, else that baseline.  While samples are
+ * recorded (smg_plan_record), the inputs are built for both solves (as
+ * training samples; without SMG_NET_GUESS too), but the modes of solve 1
+ * take no network guess; otherwise a solve builds inputs only for the
+ * network's guess.
  * A NULL net detaches. */
 size_t smg_plan_net_work_bytes(const smg_plan *plan, const smg_net *net, int m_max);
 smg_status smg_plan_attach_net(smg_plan *plan, smg_net *net, int m_max, void *work_dev, size_t work_bytes,
                                void *stream);
 /* Record training samples: every later warm-started solve that has the
  * solutions of the two previous steps (from the third solve of a sequence
- * on) appends, for each of its two multigrid solves and each real image of
+ * on; for solve 1, counted from the first solve recorded) appends, for each of its two multigrid solves and each real image of
  * modes 0..m_max, the sample (network input [n_a][n_b][8], target
  * (u_t - 2 u_{t-1} + u_{t-2}) / s_o [n_a][n_b] -- the correction to the
  * linear extrapolation, FP32) to samples_dev while fewer than `capacity` are stored
